@@ -1,0 +1,223 @@
+"""CPU oracle of the block-forest finite-volume update.
+
+TEST INFRASTRUCTURE ONLY: tests/, the smoke check and bench.py's CPU-baseline
+leg may import it; the product package never does.  It wraps liborc.so
+(oracle/orc.c, plain C in binary64) and exposes the same operations as the
+HIP library's C-ABI on host arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("block_nx", ctypes.c_int32 * 3),
+        ("nghost", ctypes.c_int32),
+        ("base_blocks", ctypes.c_int32 * 3),
+        ("max_level", ctypes.c_int32),
+        ("physics", ctypes.c_int32),
+        ("flux", ctypes.c_int32),
+        ("limiter", ctypes.c_int32),
+        ("rk_stages", ctypes.c_int32),
+        ("bc", (ctypes.c_int32 * 2) * 3),
+        ("pad_", ctypes.c_int32),
+        ("xmin", ctypes.c_double * 3),
+        ("xmax", ctypes.c_double * 3),
+        ("gamma", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("lohner_tol", ctypes.c_double),
+        ("lohner_coarsen_frac", ctypes.c_double),
+        ("lohner_eps", ctypes.c_double),
+        ("lohner_w_rho", ctypes.c_double),
+        ("lohner_w_p", ctypes.c_double),
+        ("glm_cr", ctypes.c_double),
+    ]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        P = ctypes.c_void_p
+        L.orc_forest_create.argtypes = [ctypes.POINTER(_Config), ctypes.c_int64, P, P, ctypes.POINTER(P)]
+        L.orc_forest_destroy.argtypes = [P]
+        L.orc_nvar.argtypes = [P]
+        L.orc_set_state.argtypes = [P, P, ctypes.c_int64]
+        L.orc_get_state.argtypes = [P, P, ctypes.c_int64]
+        L.orc_max_dt.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+        L.orc_glm_ch.argtypes = [P]
+        L.orc_glm_ch.restype = ctypes.c_double
+        L.orc_advance.argtypes = [P, ctypes.c_double]
+        L.orc_flag_blocks.argtypes = [P, P, P]
+        L.orc_padded_block.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64]
+        L.orc_face_kinds.argtypes = [P, ctypes.c_int64, P]
+        L.orc_lohner_cells.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64]
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
+        L.orc_get_threads.restype = ctypes.c_int
+        L.orc_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"oracle error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise OracleError(rc, lib().orc_last_error().decode())
+
+
+def make_config(s) -> _Config:
+    c = _Config()
+    c.ndim = s.ndim
+    for d in range(3):
+        c.block_nx[d] = s.block_nx[d]
+        c.base_blocks[d] = s.base_blocks[d]
+        c.xmin[d] = s.xmin[d]
+        c.xmax[d] = s.xmax[d]
+        c.bc[d][0] = s.bc
+        c.bc[d][1] = s.bc
+    c.nghost = s.nghost
+    c.max_level = s.max_level
+    c.physics = s.physics
+    c.flux = s.flux
+    c.limiter = s.limiter
+    c.rk_stages = s.rk_stages
+    c.gamma = s.gamma
+    c.cfl = s.cfl
+    c.lohner_tol = s.lohner_tol
+    c.lohner_coarsen_frac = s.lohner_coarsen_frac
+    c.lohner_eps = s.lohner_eps
+    c.lohner_w_rho = s.lohner_w_rho
+    c.lohner_w_p = s.lohner_w_p
+    c.glm_cr = s.glm_cr
+    return c
+
+
+def set_threads(n: int):
+    lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
+
+
+class OracleForest:
+    """The oracle's forest: the same operations as the HIP library on host arrays."""
+
+    def __init__(self, forest, config=None):
+        self.forest = forest
+        self.scheme = forest.scheme
+        cfg = config if config is not None else make_config(forest.scheme)
+        self._h = ctypes.c_void_p()
+        lev = np.ascontiguousarray(forest.level, dtype=np.int32)
+        ijk = np.ascontiguousarray(forest.ijk, dtype=np.int32)
+        _check(lib().orc_forest_create(ctypes.byref(cfg), forest.n, lev.ctypes.data, ijk.ctypes.data,
+                                       ctypes.byref(self._h)))
+        self.nvar = lib().orc_nvar(self._h)
+        self.shape = forest.state_shape()
+
+    def close(self):
+        if self._h:
+            lib().orc_forest_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, U: np.ndarray):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        if U.shape != self.shape:
+            raise ValueError(f"state shape {U.shape} != {self.shape}")
+        _check(lib().orc_set_state(self._h, U.ctypes.data, U.size))
+
+    def get_state(self) -> np.ndarray:
+        U = np.empty(self.shape, dtype=np.float64)
+        _check(lib().orc_get_state(self._h, U.ctypes.data, U.size))
+        return U
+
+    def max_dt(self) -> float:
+        dt = ctypes.c_double()
+        _check(lib().orc_max_dt(self._h, ctypes.byref(dt)))
+        return dt.value
+
+    @property
+    def glm_ch(self) -> float:
+        return float(lib().orc_glm_ch(self._h))
+
+    def advance(self, dt: float):
+        _check(lib().orc_advance(self._h, float(dt)))
+
+    def flag_blocks(self, with_emax: bool = False):
+        flags = np.empty(self.forest.n, dtype=np.int8)
+        emax = np.empty(self.forest.n, dtype=np.float64)
+        _check(lib().orc_flag_blocks(self._h, flags.ctypes.data, emax.ctypes.data))
+        return (flags, emax) if with_emax else flags
+
+    def padded_block(self, leaf: int) -> np.ndarray:
+        s = self.scheme
+        px = [s.block_nx[d] + 2 * s.nghost if d < s.ndim else 1 for d in range(3)]
+        out = np.empty((self.nvar, px[2], px[1], px[0]), dtype=np.float64)
+        _check(lib().orc_padded_block(self._h, int(leaf), out.ctypes.data, out.size))
+        return out
+
+    def lohner_cells(self, leaf: int) -> np.ndarray:
+        s = self.scheme
+        out = np.empty([s.block_nx[d] for d in reversed(range(s.ndim))], dtype=np.float64)
+        _check(lib().orc_lohner_cells(self._h, int(leaf), out.ctypes.data, out.size))
+        return out
+
+    def face_kinds(self, leaf: int) -> np.ndarray:
+        k = np.empty(2 * self.scheme.ndim, dtype=np.int32)
+        _check(lib().orc_face_kinds(self._h, int(leaf), k.ctypes.data))
+        return k
+
+
+def run(forest, U0: np.ndarray, *, t_end: float | None = None, steps: int | None = None,
+        dts=None):
+    """Drive the oracle: free Courant steps to t_end, a fixed step count, or a
+    given dt sequence (lockstep runs).  Returns (state, list of dt used)."""
+    o = OracleForest(forest)
+    o.set_state(U0)
+    used = []
+    if dts is not None:
+        for dt in dts:
+            o.max_dt()
+            o.advance(dt)
+            used.append(dt)
+    else:
+        t = 0.0
+        n = 0
+        while True:
+            if steps is not None and n >= steps:
+                break
+            dt = o.max_dt()
+            if t_end is not None:
+                if t >= t_end:
+                    break
+                dt = min(dt, t_end - t)
+            o.advance(dt)
+            used.append(dt)
+            t += dt
+            n += 1
+    U = o.get_state()
+    o.close()
+    return U, used

@@ -1,0 +1,90 @@
+/* orc.h -- CPU oracle for the block-forest conservative finite-volume update.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the CPU-baseline
+ * leg of bench.py may load this library.  The product path (the HIP library)
+ * never links, loads or calls it, and the two share no source, header, table
+ * or helper.
+ *
+ * What it computes follows MPI-AMRVAC (Keppens et al., arXiv 2004.03275):
+ *   conservation law dU/dt + div F(U) = 0 (Sec. 1.1, Eq. (eq)), HD variables
+ *   (rho, rho v, E) with E = rho v^2/2 + p/(gamma-1) (Sec. 1.1); primitive
+ *   conversion and signal speeds (Sec. 1.2, phys_to_primitive, phys_get_cmax,
+ *   phys_get_cbounds); TVDLF / HLL / HLLC approximate Riemann fluxes (Sec. 1.2,
+ *   Sec. 2.4); block quadtree/octree with refinement ratio 2 and the Loehner
+ *   refine/coarsen rule (Sec. 1.3); three-step / SSP Runge-Kutta (Sec. 2.1,
+ *   2.3.2, 2.4); Courant-limited time step (Sec. 2.1).  The paper prints none
+ *   of the scheme formulas; where it is silent the reading used is stated at
+ *   the function that implements it.
+ *
+ * All arithmetic is IEEE binary64 with round-to-nearest, built with
+ * -ffp-contract=off and without fast-math, so every expression is evaluated
+ * exactly in the order written.
+ *
+ * State layout (host memory, caller owned, copied in/out):
+ *   U[var][leaf][z][y][x], interior cells only, leaves in the caller's order.
+ * Error codes: 0 ok, -1 invalid argument, -2 unbalanced / non-covering forest,
+ *   -3 non-physical state (rho <= 0, p <= 0 or NaN), -4 out of memory.
+ */
+#ifndef ORC_H
+#define ORC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_forest orc_forest;
+
+/* Field order is part of the contract: 20 int32 then 11 double. */
+typedef struct {
+  int32_t ndim;            /* 1, 2 or 3 */
+  int32_t block_nx[3];     /* interior cells per block and dimension (1 if unused) */
+  int32_t nghost;          /* ghost layers; must be 2 */
+  int32_t base_blocks[3];  /* level-1 blocks per dimension */
+  int32_t max_level;       /* refine_max_level of Sec. 1.3 (1 = pure decomposition) */
+  int32_t physics;         /* 0 = Euler (HD), 1 = ideal MHD with GLM cleaning */
+  int32_t flux;            /* 0 = TVDLF, 1 = HLL, 2 = HLLC */
+  int32_t limiter;         /* 0 = minmod, 1 = van Leer */
+  int32_t rk_stages;       /* 2 = SSP-RK2, 3 = SSP-RK3 */
+  int32_t bc[3][2];        /* per dimension, low/high side: 0 periodic, 1 zero gradient */
+  int32_t pad_;
+  double xmin[3], xmax[3]; /* xprobmin/xprobmax of Sec. 1.3 */
+  double gamma, cfl;
+  double lohner_tol, lohner_coarsen_frac, lohner_eps, lohner_w_rho, lohner_w_p;
+  double glm_cr;
+} orc_config;
+
+int orc_forest_create(const orc_config* cfg, int64_t nleaves,
+                      const int32_t* leaf_level, const int32_t* leaf_ijk,
+                      orc_forest** out);
+int orc_forest_destroy(orc_forest* f);
+int orc_nvar(const orc_forest* f);
+int orc_set_state(orc_forest* f, const double* U, int64_t n_doubles);
+int orc_get_state(const orc_forest* f, double* U, int64_t n_doubles);
+/* Courant time step of the current state; also validates positivity and, for
+ * MHD, records the GLM cleaning speed used by the next advance calls. */
+int orc_max_dt(orc_forest* f, double* dt_out);
+/* GLM cleaning speed recorded by the last orc_max_dt (0 if none). */
+double orc_glm_ch(const orc_forest* f);
+/* One full SSP Runge-Kutta step of size dt. */
+int orc_advance(orc_forest* f, double dt);
+/* Loehner refine (+1) / keep (0) / coarsen (-1) flags, one per leaf; emax_out
+ * (optional, may be NULL) receives the per-leaf max of the weighted estimator. */
+int orc_flag_blocks(orc_forest* f, int8_t* flags_out, double* emax_out);
+/* Test hook: the ghost-filled block of leaf `leaf` for the current state,
+ * layout [var][pz][py][px] with px = nx + 2*nghost on active dimensions.
+ * Edge and corner ghost cells are never filled and hold NaN. */
+int orc_padded_block(orc_forest* f, int64_t leaf, double* out, int64_t n_doubles);
+/* Test hook: neighbour kind per face of a leaf: 0 same level, 1 coarser,
+ * 2 finer, 3 physical boundary. faces = 2*ndim entries (-x,+x,-y,+y,-z,+z). */
+int orc_face_kinds(const orc_forest* f, int64_t leaf, int32_t* kinds);
+/* Test hook: per-cell weighted Loehner estimator of one leaf, [cell]. */
+int orc_lohner_cells(orc_forest* f, int64_t leaf, double* out, int64_t n_doubles);
+void orc_set_threads(int n);
+int orc_get_threads(void);
+const char* orc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
