@@ -1,0 +1,155 @@
+/* amrv.h -- C-ABI of the MI355X block-forest finite-volume library (libamrv.so).
+ *
+ * The library advances the conservative finite-volume discretisation of
+ *   dU/dt + div F(U) = 0                       (arXiv 2004.03275, Sec. 1.1, Eq. (eq))
+ * on a quadtree/octree forest of fixed-size blocks with refinement ratio 2
+ * (Sec. 1.3): ghost-cell fill (same-level copy, fine-to-coarse restriction,
+ * coarse-to-fine prolongation), limited MUSCL reconstruction in primitive
+ * variables (Sec. 1.2 phys_to_primitive), TVDLF / HLL / HLLC fluxes (Sec. 1.2,
+ * Sec. 2.4), coarse-fine flux replacement for conservation (Sec. 1.1), SSP
+ * Runge-Kutta stages (Sec. 2.1-2.4), the Courant time step (Sec. 2.1,
+ * phys_get_cmax) and the Loehner refine/coarsen flags (Sec. 1.3).  Ideal MHD
+ * uses HLL with mixed GLM divergence cleaning.
+ *
+ * Every operation runs in hand-written HIP kernels for gfx950 in binary64.
+ *
+ * Conventions for every entry point:
+ *  - Return 0 on success or a negative AMRV_E* code; amrv_last_error() gives a
+ *    thread-local message.  No entry point aborts the process.
+ *  - Host arrays passed in are owned by the caller and copied; the library
+ *    keeps no pointer to them after the call returns.
+ *  - Device memory: the caller allocates ONE device workspace of
+ *    amrv_workspace_bytes() bytes (e.g. a torch uint8 tensor) and keeps it
+ *    alive until amrv_forest_destroy; the library allocates no device memory
+ *    of its own.  The HIP stream is borrowed; all work is enqueued on it.
+ *  - State layout: conserved binary64 U[var][leaf][z][y][x], interior cells
+ *    only, leaves in the caller's order.  Hydrodynamics: var = (rho, m_x,
+ *    [m_y, m_z,] E); MHD: (rho, m.., E, B.., psi).
+ */
+#ifndef AMRV_H
+#define AMRV_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AMRV_OK 0
+#define AMRV_EINVAL (-1)        /* bad config, argument, size or dt */
+#define AMRV_EUNBALANCED (-2)   /* leaves overlap, leave gaps or break 2:1 balance */
+#define AMRV_ENONPHYSICAL (-3)  /* rho <= 0, p <= 0 or NaN in the state */
+#define AMRV_ENOMEM (-4)        /* workspace too small */
+#define AMRV_EDEVICE (-5)       /* HIP runtime error */
+#define AMRV_ENOTSUP (-6)       /* configuration valid but not supported by the kernels */
+
+#define AMRV_EULER 0
+#define AMRV_MHD_GLM 1
+#define AMRV_TVDLF 0
+#define AMRV_HLL 1
+#define AMRV_HLLC 2
+#define AMRV_MINMOD 0
+#define AMRV_VANLEER 1
+#define AMRV_BC_PERIODIC 0
+#define AMRV_BC_ZERO_GRADIENT 1
+
+/* schedules of the stage update (amrv_set_schedule) */
+#define AMRV_SCHED_PER_BLOCK 0    /* one kernel launch per leaf per stage */
+#define AMRV_SCHED_GRID 1         /* one launch per stage, one workgroup per leaf */
+#define AMRV_SCHED_PERSISTENT 2   /* one launch per stage, persistent workgroups */
+
+/* flag modes (amrv_flag_blocks) */
+#define AMRV_FLAG_LOHNER 0
+
+typedef struct amrv_forest amrv_forest;
+
+/* Problem description (par-file keys of Sec. 1.3: block size, base domain
+ * size in blocks, refine_max_level, xprobmin/xprobmax; Courant number of
+ * Sec. 2.1; scheme choice of Sec. 1.3; Loehner tolerances of Sec. 1.3).
+ * Field order is part of the ABI: 20 int32 followed by 14 double. */
+typedef struct {
+  int32_t ndim;            /* 1, 2 or 3 */
+  int32_t block_nx[3];     /* cells per block; 1D: any even nx >= 4; 2D/3D: 16 */
+  int32_t nghost;          /* must be 2 */
+  int32_t base_blocks[3];  /* level-1 blocks per dimension */
+  int32_t max_level;       /* 1 = pure domain decomposition */
+  int32_t physics;         /* AMRV_EULER or AMRV_MHD_GLM */
+  int32_t flux;            /* AMRV_TVDLF, AMRV_HLL, AMRV_HLLC (HLLC: Euler only) */
+  int32_t limiter;         /* AMRV_MINMOD or AMRV_VANLEER */
+  int32_t rk_stages;       /* 2 (SSP-RK2) or 3 (SSP-RK3) */
+  int32_t bc[3][2];        /* AMRV_BC_*, same value on both sides of a dimension */
+  int32_t pad_;
+  double xmin[3], xmax[3];
+  double gamma, cfl;
+  double lohner_tol;           /* refine if the block max estimator exceeds it */
+  double lohner_coarsen_frac;  /* coarsen if the block max is below frac*tol */
+  double lohner_eps;           /* noise filter of the estimator */
+  double lohner_w_rho, lohner_w_p;
+  double glm_cr;               /* GLM damping length c_r */
+} amrv_config;
+
+/* Device bytes the forest needs for this leaf list (three state copies,
+ * neighbour tables, ghost and flux slabs of coarse-fine faces, scratch).
+ * Returns 0 and sets the error message on an invalid config or forest. */
+size_t amrv_workspace_bytes(const amrv_config* cfg, int64_t nleaves, const int32_t* leaf_level,
+                            const int32_t* leaf_ijk);
+
+/* Validate the leaf list (levels 1..max_level, block coordinates at that
+ * level in leaf_ijk[3*i..3*i+2], cover without overlap, 2:1 balance across
+ * faces, edges and corners), build neighbour and coarse-fine tables and bind
+ * the workspace.  hip_stream is a hipStream_t (NULL = default stream). */
+int amrv_forest_create(const amrv_config* cfg, int64_t nleaves, const int32_t* leaf_level,
+                       const int32_t* leaf_ijk, void* d_workspace, size_t ws_bytes,
+                       void* hip_stream, amrv_forest** out);
+int amrv_forest_destroy(amrv_forest* f);
+
+int amrv_nvar(const amrv_forest* f);
+int64_t amrv_state_doubles(const amrv_forest* f);
+
+/* Copy the state in/out.  on_device = 0: U is host memory (the call
+ * synchronises the stream); 1: U is device memory (asynchronous). */
+int amrv_set_state(amrv_forest* f, const double* U, int64_t n_doubles, int32_t on_device);
+int amrv_get_state(amrv_forest* f, double* U, int64_t n_doubles, int32_t on_device);
+
+/* Courant time step dt = cfl / max_cells sum_d (|v_d| + c_d)/dx_d of the
+ * current state (Sec. 2.1; c = sound speed, or fast speed for MHD).
+ * Synchronises; returns AMRV_ENONPHYSICAL if any cell has rho <= 0, p <= 0 or
+ * NaN.  For MHD it also records the GLM speed c_h = max |v_d| + c_f,d used by
+ * the following amrv_advance calls. */
+int amrv_max_dt(amrv_forest* f, double* dt_out);
+/* GLM cleaning speed recorded by the last amrv_max_dt (0 before any). */
+double amrv_glm_ch(const amrv_forest* f);
+
+/* One full SSP Runge-Kutta step of size dt (Sec. 2.1-2.4), asynchronous on
+ * the forest's stream.  dt must be positive and finite (else AMRV_EINVAL).
+ * A non-physical result is reported by the next amrv_max_dt. */
+int amrv_advance(amrv_forest* f, double dt);
+
+/* Loehner flags (Sec. 1.3), one int8 per leaf into host memory: +1 refine
+ * (level < max_level and block max estimator > tol), -1 coarsen (level > 1
+ * and max < frac * tol), else 0.  emax_out (host, may be NULL) receives each
+ * leaf's max estimator.  Synchronises. */
+int amrv_flag_blocks(amrv_forest* f, int32_t mode, int8_t* flags_out, double* emax_out);
+
+/* Select the schedule of the stage update (AMRV_SCHED_*).  xcd_remap != 0
+ * maps consecutive leaves to the same XCD; persistent_wgs is the persistent
+ * grid size (0 = 2 per compute unit).  The default is AMRV_SCHED_GRID with
+ * the remap on, or the result of amrv_autotune. */
+int amrv_set_schedule(amrv_forest* f, int32_t sched, int32_t xcd_remap, int32_t persistent_wgs);
+int amrv_get_schedule(const amrv_forest* f, int32_t* sched, int32_t* xcd_remap, int32_t* persistent_wgs);
+
+/* Time the candidate schedules on the current state (first-stage kernel,
+ * state unchanged) and keep the fastest.  Synchronises. */
+int amrv_autotune(amrv_forest* f, int32_t reps);
+
+/* Capture one advance step in a HIP graph and replay it on later
+ * amrv_advance calls (enable != 0), or launch kernels directly (0). */
+int amrv_use_graph(amrv_forest* f, int32_t enable);
+
+int amrv_synchronize(amrv_forest* f);
+const char* amrv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,136 @@
+"""ctypes binding of libamrv.so (the C-ABI in include/amrv.h).
+
+Argument marshalling only: every step of the update runs in the library's HIP
+kernels.  Loading fails loudly if the library is missing; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libamrv.so")
+
+OK = 0
+EINVAL = -1
+EUNBALANCED = -2
+ENONPHYSICAL = -3
+ENOMEM = -4
+EDEVICE = -5
+ENOTSUP = -6
+
+SCHED_PER_BLOCK = 0
+SCHED_GRID = 1
+SCHED_PERSISTENT = 2
+
+FLAG_LOHNER = 0
+
+
+class Config(ctypes.Structure):
+    """amrv_config: 20 int32 followed by 14 double."""
+
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("block_nx", ctypes.c_int32 * 3),
+        ("nghost", ctypes.c_int32),
+        ("base_blocks", ctypes.c_int32 * 3),
+        ("max_level", ctypes.c_int32),
+        ("physics", ctypes.c_int32),
+        ("flux", ctypes.c_int32),
+        ("limiter", ctypes.c_int32),
+        ("rk_stages", ctypes.c_int32),
+        ("bc", (ctypes.c_int32 * 2) * 3),
+        ("pad_", ctypes.c_int32),
+        ("xmin", ctypes.c_double * 3),
+        ("xmax", ctypes.c_double * 3),
+        ("gamma", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("lohner_tol", ctypes.c_double),
+        ("lohner_coarsen_frac", ctypes.c_double),
+        ("lohner_eps", ctypes.c_double),
+        ("lohner_w_rho", ctypes.c_double),
+        ("lohner_w_p", ctypes.c_double),
+        ("glm_cr", ctypes.c_double),
+    ]
+
+
+class AmrvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"amrv error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+# exported symbols and their signatures (also checked by the CPU test suite)
+P = ctypes.c_void_p
+SIGNATURES = {
+    "amrv_workspace_bytes": ([ctypes.POINTER(Config), ctypes.c_int64, P, P], ctypes.c_size_t),
+    "amrv_forest_create": ([ctypes.POINTER(Config), ctypes.c_int64, P, P, P, ctypes.c_size_t, P,
+                            ctypes.POINTER(P)], ctypes.c_int),
+    "amrv_forest_destroy": ([P], ctypes.c_int),
+    "amrv_nvar": ([P], ctypes.c_int),
+    "amrv_state_doubles": ([P], ctypes.c_int64),
+    "amrv_set_state": ([P, P, ctypes.c_int64, ctypes.c_int32], ctypes.c_int),
+    "amrv_get_state": ([P, P, ctypes.c_int64, ctypes.c_int32], ctypes.c_int),
+    "amrv_max_dt": ([P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "amrv_glm_ch": ([P], ctypes.c_double),
+    "amrv_advance": ([P, ctypes.c_double], ctypes.c_int),
+    "amrv_flag_blocks": ([P, ctypes.c_int32, P, P], ctypes.c_int),
+    "amrv_set_schedule": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+    "amrv_get_schedule": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                           ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "amrv_autotune": ([P, ctypes.c_int32], ctypes.c_int),
+    "amrv_use_graph": ([P, ctypes.c_int32], ctypes.c_int),
+    "amrv_synchronize": ([P], ctypes.c_int),
+    "amrv_last_error": ([], ctypes.c_char_p),
+}
+
+
+def lib():
+    """Load libamrv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() (hipcc, gfx950) first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def check(rc: int):
+    if rc != OK:
+        raise AmrvError(rc, lib().amrv_last_error().decode())
+
+
+def make_config(s) -> Config:
+    """Config from a workloads.Scheme (or any object with the same fields)."""
+    c = Config()
+    c.ndim = s.ndim
+    for d in range(3):
+        c.block_nx[d] = s.block_nx[d]
+        c.base_blocks[d] = s.base_blocks[d]
+        c.xmin[d] = s.xmin[d]
+        c.xmax[d] = s.xmax[d]
+        c.bc[d][0] = s.bc
+        c.bc[d][1] = s.bc
+    c.nghost = s.nghost
+    c.max_level = s.max_level
+    c.physics = s.physics
+    c.flux = s.flux
+    c.limiter = s.limiter
+    c.rk_stages = s.rk_stages
+    c.gamma = s.gamma
+    c.cfl = s.cfl
+    c.lohner_tol = s.lohner_tol
+    c.lohner_coarsen_frac = s.lohner_coarsen_frac
+    c.lohner_eps = s.lohner_eps
+    c.lohner_w_rho = s.lohner_w_rho
+    c.lohner_w_p = s.lohner_w_p
+    c.glm_cr = s.glm_cr
+    return c

@@ -1,0 +1,528 @@
+// api.cpp -- the C-ABI of libamrv (declared in include/amrv.h): workspace
+// layout, stage scheduling (per-block launches, one grid launch, or persistent
+// workgroups on an atomic leaf queue), HIP-graph replay of a whole step, the
+// schedule autotuner, and the synchronising queries (max_dt, flag_blocks).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/amrv.h"
+#include "forest.hpp"
+#include "internal.hpp"
+
+using namespace amrv;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(AMRV_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr)                             \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+  } while (0)
+
+constexpr size_t ALIGN = 256;
+
+struct Layout {
+  size_t off_U[3], off_G, off_FF, off_lvl, off_ijk, off_nbr, off_slot, off_kind, off_fslot, off_sleaf, off_sface,
+      off_rlist, off_plist, off_pp, off_lp, off_red, off_cnt, off_emax, off_flags, total;
+};
+
+Layout plan(const Tables& t) {
+  Layout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += (bytes + ALIGN - 1) / ALIGN * ALIGN;
+    return at;
+  };
+  const size_t state = sizeof(double) * (size_t)t.nvar * (size_t)t.n * (size_t)t.ncell;
+  for (int i = 0; i < 3; i++) L.off_U[i] = take(state);
+  L.off_G = take(sizeof(double) * (size_t)std::max(1, t.nslot) * t.nvar * 2 * t.T);
+  L.off_FF = take(sizeof(double) * (size_t)std::max(1, t.nslot) * t.nvar * t.T);
+  L.off_lvl = take(sizeof(int32_t) * t.n);
+  L.off_ijk = take(sizeof(int32_t) * 3 * t.n);
+  L.off_nbr = take(sizeof(int32_t) * 6 * t.n);
+  L.off_slot = take(sizeof(int32_t) * 6 * t.n);
+  L.off_kind = take(sizeof(int8_t) * 6 * t.n);
+  L.off_fslot = take(sizeof(int32_t) * 4 * std::max(1, t.nslot));
+  L.off_sleaf = take(sizeof(int32_t) * std::max(1, t.nslot));
+  L.off_sface = take(sizeof(int32_t) * std::max(1, t.nslot));
+  L.off_rlist = take(sizeof(int32_t) * std::max<size_t>(1, t.rlist.size()));
+  L.off_plist = take(sizeof(int32_t) * std::max<size_t>(1, t.plist.size()));
+  L.off_pp = take(sizeof(double) * PP_COUNT);
+  L.off_lp = take(sizeof(double) * LP_COUNT);
+  L.off_red = take(sizeof(unsigned long long) * 4);
+  L.off_cnt = take(sizeof(unsigned) * 16);
+  L.off_emax = take(sizeof(double) * t.n);
+  L.off_flags = take(sizeof(int8_t) * t.n);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+struct amrv_forest {
+  amrv_config cfg{};
+  Tables tab;
+  Layout lay{};
+  Geo geo{};
+  LaunchCfg lc{};
+  hipStream_t st = nullptr;
+  char* ws = nullptr;
+  double* U[3] = {nullptr, nullptr, nullptr};
+  double* pp = nullptr;
+  double* lp = nullptr;
+  unsigned long long* red = nullptr;
+  unsigned* cnt = nullptr;
+  double* emax = nullptr;
+  int8_t* flags = nullptr;
+  int32_t* rlist = nullptr;
+  int32_t* plist = nullptr;
+  int sched = AMRV_SCHED_GRID, xcd = 1, pwgs = 0, ncu = 256;
+  double ch = 0.0;
+  bool graph_on = false, graph_valid = false;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+};
+
+namespace {
+
+int set_scalars(amrv_forest* f, int at, const std::vector<double>& v) {
+  HIPCHK(launch_set_scalars(f->pp + at, v.data(), (int)v.size(), f->st));
+  return AMRV_OK;
+}
+
+Sched make_sched(const amrv_forest* f, int mode, int leaf0) {
+  Sched s{};
+  s.mode = mode;
+  s.xcd_remap = f->xcd;
+  s.leaf0 = leaf0;
+  s.per_xcd = (int)((f->tab.n + 7) / 8);
+  s.counter = f->cnt;
+  return s;
+}
+
+int stage_grid(const amrv_forest* f, int mode) {
+  const Tables& t = f->tab;
+  if (t.nd == 1) {
+    const int nch = (t.nx + 255) / 256;
+    return mode == AMRV_SCHED_PER_BLOCK ? nch : (int)(t.n * nch);
+  }
+  if (mode == AMRV_SCHED_PER_BLOCK) return 1;
+  if (mode == AMRV_SCHED_PERSISTENT) return f->pwgs > 0 ? f->pwgs : 2 * f->ncu;
+  return f->xcd ? 8 * (int)((t.n + 7) / 8) : (int)t.n;
+}
+
+// enqueue the coarse-fine pre-pass on state U
+int enqueue_ghosts(amrv_forest* f, const double* U, bool fluxes) {
+  const int nr = (int)f->tab.rlist.size(), np = (int)f->tab.plist.size();
+  if (nr) HIPCHK(launch_restrict(f->geo, f->lc, U, f->rlist, nr, f->st));
+  if (np) HIPCHK(launch_prolong(f->geo, f->lc, U, f->plist, np, f->st));
+  if (np && fluxes) HIPCHK(launch_fineflux(f->geo, f->lc, U, f->pp, f->plist, np, f->st));
+  return AMRV_OK;
+}
+
+int enqueue_stage_update(amrv_forest* f, const StageArgs& a, int mode) {
+  const Tables& t = f->tab;
+  int m = mode;
+  if (t.nd == 1 && m == AMRV_SCHED_PERSISTENT) m = AMRV_SCHED_GRID;
+  if (m == AMRV_SCHED_PER_BLOCK) {
+    const int grid = stage_grid(f, m);
+    for (int64_t b = 0; b < t.n; b++) {
+      Sched s = make_sched(f, 0, (int)b);
+      HIPCHK(launch_stage(f->geo, f->lc, a, f->pp, s, grid, f->st));
+    }
+    return AMRV_OK;
+  }
+  Sched s = make_sched(f, m == AMRV_SCHED_PERSISTENT ? 2 : 1, 0);
+  if (t.nd == 1) s.xcd_remap = 0;
+  if (m == AMRV_SCHED_PERSISTENT) s.counter = f->cnt + a.stage;
+  HIPCHK(launch_stage(f->geo, f->lc, a, f->pp, s, stage_grid(f, m), f->st));
+  return AMRV_OK;
+}
+
+// one full SSP step on the forest's stream; dt and the damping factor are
+// read from the device parameter block
+int enqueue_step(amrv_forest* f) {
+  const int S = f->cfg.rk_stages;
+  if (f->sched == AMRV_SCHED_PERSISTENT && f->tab.nd > 1) HIPCHK(launch_reset_u32(f->cnt, 16, f->st));
+  for (int s = 1; s <= S; s++) {
+    const double* in = s == 1 ? f->U[0] : (s == 2 ? f->U[1] : f->U[2]);
+    double* out = s == S ? f->U[0] : (s == 1 ? f->U[1] : f->U[2]);
+    int rc = enqueue_ghosts(f, in, true);
+    if (rc) return rc;
+    StageArgs a{};
+    a.Uin = in;
+    a.Un = f->U[0];
+    a.Uout = out;
+    a.dtp = f->pp + PP_DT;
+    a.stage = s;
+    a.rk = S;
+    rc = enqueue_stage_update(f, a, f->sched);
+    if (rc) return rc;
+  }
+  if (f->cfg.physics == AMRV_MHD_GLM) {
+    const int ip = 2 + 2 * f->tab.nd;
+    double* psi = f->U[0] + (size_t)ip * f->tab.n * f->tab.ncell;
+    HIPCHK(launch_scale_var(psi, f->pp + PP_DAMP, (long long)f->tab.n * f->tab.ncell, f->st));
+  }
+  return AMRV_OK;
+}
+
+void drop_graph(amrv_forest* f) {
+  if (f->gexec) hipGraphExecDestroy(f->gexec);
+  if (f->graph) hipGraphDestroy(f->graph);
+  f->gexec = nullptr;
+  f->graph = nullptr;
+  f->graph_valid = false;
+}
+
+int capture_graph(amrv_forest* f) {
+  drop_graph(f);
+  HIPCHK(hipStreamBeginCapture(f->st, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue_step(f);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(f->st, &g);
+  if (rc) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  f->graph = g;
+  HIPCHK(hipGraphInstantiate(&f->gexec, g, nullptr, nullptr, 0));
+  f->graph_valid = true;
+  return AMRV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* amrv_last_error(void) { return g_err.c_str(); }
+
+size_t amrv_workspace_bytes(const amrv_config* cfg, int64_t n, const int32_t* lev, const int32_t* ijk) {
+  if (!cfg) {
+    g_err = "null config";
+    return 0;
+  }
+  Tables t;
+  const int rc = build_tables(*cfg, n, lev, ijk, t);
+  if (rc) {
+    g_err = t.err;
+    return 0;
+  }
+  return plan(t).total;
+}
+
+int amrv_forest_create(const amrv_config* cfg, int64_t n, const int32_t* lev, const int32_t* ijk, void* d_ws,
+                       size_t ws_bytes, void* stream, amrv_forest** out) {
+  if (!cfg || !out) return fail(AMRV_EINVAL, "null argument");
+  *out = nullptr;
+  amrv_forest* f = new amrv_forest();
+  f->cfg = *cfg;
+  int rc = build_tables(*cfg, n, lev, ijk, f->tab);
+  if (rc) {
+    std::string m = f->tab.err;
+    delete f;
+    return fail(rc, m);
+  }
+  f->lay = plan(f->tab);
+  if (!d_ws) {
+    delete f;
+    return fail(AMRV_EINVAL, "null workspace");
+  }
+  if (ws_bytes < f->lay.total) {
+    delete f;
+    return fail(AMRV_ENOMEM, "workspace too small: need " + std::to_string(f->lay.total) + " bytes");
+  }
+  if (((uintptr_t)d_ws) % ALIGN) {
+    delete f;
+    return fail(AMRV_EINVAL, "workspace must be 256-byte aligned");
+  }
+  f->st = (hipStream_t)stream;
+  f->ws = (char*)d_ws;
+  const Tables& t = f->tab;
+  const Layout& L = f->lay;
+  for (int i = 0; i < 3; i++) f->U[i] = (double*)(f->ws + L.off_U[i]);
+  f->pp = (double*)(f->ws + L.off_pp);
+  f->lp = (double*)(f->ws + L.off_lp);
+  f->red = (unsigned long long*)(f->ws + L.off_red);
+  f->cnt = (unsigned*)(f->ws + L.off_cnt);
+  f->emax = (double*)(f->ws + L.off_emax);
+  f->flags = (int8_t*)(f->ws + L.off_flags);
+  f->rlist = (int32_t*)(f->ws + L.off_rlist);
+  f->plist = (int32_t*)(f->ws + L.off_plist);
+
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&f->ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) {
+    delete f;
+    return hip_fail(e, "device query");
+  }
+
+  Geo& g = f->geo;
+  g.n = (int)t.n;
+  g.ndim = t.nd;
+  g.nx = t.nx;
+  g.ncell = t.ncell;
+  g.T = t.T;
+  g.nslot = t.nslot;
+  g.nvar = t.nvar;
+  g.lvl = (const int32_t*)(f->ws + L.off_lvl);
+  g.ijk = (const int32_t*)(f->ws + L.off_ijk);
+  g.nbr = (const int32_t*)(f->ws + L.off_nbr);
+  g.slot = (const int32_t*)(f->ws + L.off_slot);
+  g.kind = (const int8_t*)(f->ws + L.off_kind);
+  g.fslot = (const int32_t*)(f->ws + L.off_fslot);
+  g.sleaf = (const int32_t*)(f->ws + L.off_sleaf);
+  g.sface = (const int32_t*)(f->ws + L.off_sface);
+  g.G = (double*)(f->ws + L.off_G);
+  g.FF = (double*)(f->ws + L.off_FF);
+  for (int l = 0; l < MAXLEV; l++)
+    for (int d = 0; d < 3; d++) {
+      g.rdx[l][d] = 0.0;
+      if (d < t.nd && l >= 1 && l <= cfg->max_level) {
+        const double cells = (double)(((int64_t)cfg->base_blocks[d] << (l - 1)) * cfg->block_nx[d]);
+        const double dx = (cfg->xmax[d] - cfg->xmin[d]) / cells;
+        g.rdx[l][d] = 1.0 / dx;
+      }
+    }
+  f->lc.ndim = t.nd;
+  f->lc.mhd = cfg->physics == AMRV_MHD_GLM;
+  f->lc.flux = cfg->flux;
+  f->lc.lim = cfg->limiter;
+
+  auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+    if (!bytes) return hipSuccess;
+    return hipMemcpyAsync(f->ws + off, src, bytes, hipMemcpyHostToDevice, f->st);
+  };
+  const size_t nsl = (size_t)t.nslot;
+  double pp[PP_COUNT] = {0};
+  pp[PP_GAMMA] = cfg->gamma;
+  pp[PP_GM1] = cfg->gamma - 1.0;
+  pp[PP_IGM1] = 1.0 / (cfg->gamma - 1.0);
+  double lp[LP_COUNT] = {0};
+  lp[LP_EPS] = cfg->lohner_eps;
+  lp[LP_WRHO] = cfg->lohner_w_rho;
+  lp[LP_WP] = cfg->lohner_w_p;
+  lp[LP_TOL] = cfg->lohner_tol;
+  lp[LP_CTOL] = cfg->lohner_coarsen_frac * cfg->lohner_tol;
+  hipError_t es[] = {up(L.off_lvl, t.lvl.data(), 4 * t.n),
+                     up(L.off_ijk, t.ijk.data(), 12 * t.n),
+                     up(L.off_nbr, t.nbr.data(), 24 * t.n),
+                     up(L.off_slot, t.slot.data(), 24 * t.n),
+                     up(L.off_kind, t.kind.data(), 6 * t.n),
+                     up(L.off_fslot, t.fslot.data(), 16 * nsl),
+                     up(L.off_sleaf, t.sleaf.data(), 4 * nsl),
+                     up(L.off_sface, t.sface.data(), 4 * nsl),
+                     up(L.off_rlist, t.rlist.data(), 4 * t.rlist.size()),
+                     up(L.off_plist, t.plist.data(), 4 * t.plist.size()),
+                     up(L.off_pp, pp, sizeof pp),
+                     up(L.off_lp, lp, sizeof lp),
+                     hipStreamSynchronize(f->st)};
+  for (hipError_t x : es)
+    if (x != hipSuccess) {
+      delete f;
+      return hip_fail(x, "table upload");
+    }
+  *out = f;
+  return AMRV_OK;
+}
+
+int amrv_forest_destroy(amrv_forest* f) {
+  if (!f) return AMRV_OK;
+  if (f->st || true) hipStreamSynchronize(f->st);
+  drop_graph(f);
+  delete f;
+  return AMRV_OK;
+}
+
+int amrv_nvar(const amrv_forest* f) { return f ? f->tab.nvar : 0; }
+
+int64_t amrv_state_doubles(const amrv_forest* f) {
+  return f ? (int64_t)f->tab.nvar * f->tab.n * f->tab.ncell : 0;
+}
+
+int amrv_set_state(amrv_forest* f, const double* U, int64_t nd, int32_t on_device) {
+  if (!f || !U) return fail(AMRV_EINVAL, "null argument");
+  if (nd != amrv_state_doubles(f)) return fail(AMRV_EINVAL, "state size mismatch");
+  HIPCHK(hipMemcpyAsync(f->U[0], U, sizeof(double) * nd, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                        f->st));
+  if (!on_device) HIPCHK(hipStreamSynchronize(f->st));
+  return AMRV_OK;
+}
+
+int amrv_get_state(amrv_forest* f, double* U, int64_t nd, int32_t on_device) {
+  if (!f || !U) return fail(AMRV_EINVAL, "null argument");
+  if (nd != amrv_state_doubles(f)) return fail(AMRV_EINVAL, "state size mismatch");
+  HIPCHK(hipMemcpyAsync(U, f->U[0], sizeof(double) * nd, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                        f->st));
+  if (!on_device) HIPCHK(hipStreamSynchronize(f->st));
+  return AMRV_OK;
+}
+
+int amrv_max_dt(amrv_forest* f, double* dt_out) {
+  if (!f || !dt_out) return fail(AMRV_EINVAL, "null argument");
+  HIPCHK(launch_reset_u32((unsigned*)f->red, 8, f->st));
+  HIPCHK(launch_cfl(f->geo, f->lc, f->U[0], f->pp, f->red, f->st));
+  unsigned long long h[4] = {0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(h, f->red, sizeof h, hipMemcpyDeviceToHost, f->st));
+  HIPCHK(hipStreamSynchronize(f->st));
+  if (h[2]) return fail(AMRV_ENONPHYSICAL, "non-physical state (rho <= 0, p <= 0 or NaN)");
+  double smax, cmax;
+  std::memcpy(&smax, &h[0], 8);
+  std::memcpy(&cmax, &h[1], 8);
+  if (!(smax > 0.0)) return fail(AMRV_ENONPHYSICAL, "zero signal speed");
+  f->ch = cmax;
+  int rc = set_scalars(f, PP_CH, {cmax});
+  if (rc) return rc;
+  *dt_out = f->cfg.cfl / smax;
+  return AMRV_OK;
+}
+
+double amrv_glm_ch(const amrv_forest* f) { return f ? f->ch : 0.0; }
+
+int amrv_advance(amrv_forest* f, double dt) {
+  if (!f) return fail(AMRV_EINVAL, "null forest");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(AMRV_EINVAL, "dt must be positive and finite");
+  if (f->cfg.physics == AMRV_MHD_GLM && !(f->ch > 0.0)) return fail(AMRV_EINVAL, "MHD needs amrv_max_dt first");
+  const double damp = f->cfg.physics == AMRV_MHD_GLM ? std::exp(-(dt * f->ch) / f->cfg.glm_cr) : 1.0;
+  int rc = set_scalars(f, PP_DT, {dt, damp});
+  if (rc) return rc;
+  if (f->graph_on) {
+    if (!f->graph_valid) {
+      rc = capture_graph(f);
+      if (rc) return rc;
+    }
+    HIPCHK(hipGraphLaunch(f->gexec, f->st));
+    return AMRV_OK;
+  }
+  return enqueue_step(f);
+}
+
+int amrv_flag_blocks(amrv_forest* f, int32_t mode, int8_t* flags_out, double* emax_out) {
+  if (!f || !flags_out) return fail(AMRV_EINVAL, "null argument");
+  if (mode != AMRV_FLAG_LOHNER) return fail(AMRV_EINVAL, "unknown flag mode");
+  int rc = enqueue_ghosts(f, f->U[0], false);
+  if (rc) return rc;
+  HIPCHK(launch_lohner(f->geo, f->lc, f->U[0], f->pp, f->lp, f->cfg.max_level, f->emax, f->flags, f->st));
+  HIPCHK(hipMemcpyAsync(flags_out, f->flags, f->tab.n, hipMemcpyDeviceToHost, f->st));
+  if (emax_out) HIPCHK(hipMemcpyAsync(emax_out, f->emax, sizeof(double) * f->tab.n, hipMemcpyDeviceToHost, f->st));
+  HIPCHK(hipStreamSynchronize(f->st));
+  return AMRV_OK;
+}
+
+int amrv_set_schedule(amrv_forest* f, int32_t sched, int32_t xcd_remap, int32_t pwgs) {
+  if (!f) return fail(AMRV_EINVAL, "null forest");
+  if (sched < AMRV_SCHED_PER_BLOCK || sched > AMRV_SCHED_PERSISTENT) return fail(AMRV_EINVAL, "unknown schedule");
+  if (pwgs < 0 || pwgs > 1 << 20) return fail(AMRV_EINVAL, "bad persistent grid size");
+  f->sched = sched;
+  f->xcd = xcd_remap ? 1 : 0;
+  f->pwgs = pwgs;
+  drop_graph(f);
+  return AMRV_OK;
+}
+
+int amrv_get_schedule(const amrv_forest* f, int32_t* sched, int32_t* xcd, int32_t* pwgs) {
+  if (!f || !sched || !xcd || !pwgs) return fail(AMRV_EINVAL, "null argument");
+  *sched = f->sched;
+  *xcd = f->xcd;
+  *pwgs = f->pwgs;
+  return AMRV_OK;
+}
+
+int amrv_autotune(amrv_forest* f, int32_t reps) {
+  if (!f) return fail(AMRV_EINVAL, "null forest");
+  if (reps < 1) reps = 3;
+  struct Cand {
+    int sched, xcd, pwgs;
+  };
+  std::vector<Cand> cands = {{AMRV_SCHED_GRID, 0, 0}, {AMRV_SCHED_GRID, 1, 0}};
+  if (f->tab.nd > 1)
+    for (int k : {1, 2, 3, 4, 6}) cands.push_back({AMRV_SCHED_PERSISTENT, 0, k * f->ncu});
+  const int s0 = f->sched, x0 = f->xcd, p0 = f->pwgs;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  // time the first-stage pass U^n -> U^(1) with dt = 0: the state is untouched
+  int rc = set_scalars(f, PP_DT, {0.0, 1.0});
+  double best = 1e300;
+  Cand bc = {s0, x0, p0};
+  for (const Cand& c : cands) {
+    if (rc) break;
+    f->sched = c.sched;
+    f->xcd = c.xcd;
+    f->pwgs = c.pwgs;
+    StageArgs a{};
+    a.Uin = f->U[0];
+    a.Un = f->U[0];
+    a.Uout = f->U[1];
+    a.dtp = f->pp + PP_DT;
+    a.stage = 1;
+    a.rk = f->cfg.rk_stages;
+    std::vector<float> ts;
+    for (int r = 0; r < reps + 1 && !rc; r++) {
+      if (c.sched == AMRV_SCHED_PERSISTENT) {
+        hipError_t e = launch_reset_u32(f->cnt, 16, f->st);
+        if (e != hipSuccess) rc = hip_fail(e, "reset");
+      }
+      hipEventRecord(e0, f->st);
+      if (!rc) rc = enqueue_stage_update(f, a, c.sched);
+      hipEventRecord(e1, f->st);
+      hipEventSynchronize(e1);
+      float ms = 0;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (r) ts.push_back(ms);
+    }
+    if (rc) break;
+    std::sort(ts.begin(), ts.end());
+    const double med = ts[ts.size() / 2];
+    if (med < best) {
+      best = med;
+      bc = c;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  f->sched = bc.sched;
+  f->xcd = bc.xcd;
+  f->pwgs = bc.pwgs;
+  drop_graph(f);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(f->st));
+  return AMRV_OK;
+}
+
+int amrv_use_graph(amrv_forest* f, int32_t enable) {
+  if (!f) return fail(AMRV_EINVAL, "null forest");
+  if (enable && f->st == nullptr) return fail(AMRV_EINVAL, "graph capture needs a non-default stream");
+  if (enable && f->sched == AMRV_SCHED_PER_BLOCK) return fail(AMRV_EINVAL, "graphs replay the batched schedules only");
+  f->graph_on = enable != 0;
+  drop_graph(f);
+  return AMRV_OK;
+}
+
+int amrv_synchronize(amrv_forest* f) {
+  if (!f) return fail(AMRV_EINVAL, "null forest");
+  HIPCHK(hipStreamSynchronize(f->st));
+  return AMRV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// internal.hpp -- device tables and kernel launch interface of libamrv.
+//
+// Data layout in HBM (all inside the caller's workspace):
+//   state   U[var][leaf][z][y][x]           binary64, interior cells only (3 copies:
+//                                           U^n, U^(1), U^(2) of the SSP stages)
+//   tables  per leaf: level, block coords, per face: neighbour kind / index /
+//           coarse-fine slot (int32 / int8)
+//   slabs   G[slot][var][layer][t]          ghost cells of coarse-fine faces only
+//                                           (restricted on the coarse side,
+//                                           prolonged on the fine side)
+//           FF[slot][var][t]                fine-side face fluxes of coarse-fine faces
+//   where t = a2 * NB + a1 indexes the face's transverse cells (a1 along the
+//   lower-numbered transverse axis).  Same-level and boundary ghosts are never
+//   stored: kernels read them from the neighbour's (or own) interior.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace amrv {
+
+enum { NB_SAME = 0, NB_COARSER = 1, NB_FINER = 2, NB_BND = 3 };
+constexpr int MAXLEV = 16;
+
+struct Geo {
+  int n;          // leaves
+  int ndim;
+  int nx;         // cells per block per dimension (16 in 2D/3D; 1D: any even >= 4)
+  int ncell;      // cells per block
+  int T;          // transverse cells per face slab
+  int nslot;      // coarse-fine face slots
+  int nvar;
+  const int32_t* lvl;    // [n]
+  const int32_t* ijk;    // [n][3]
+  const int32_t* nbr;    // [n][6] same-level or coarser neighbour, own index at a boundary
+  const int8_t* kind;    // [n][6] NB_*
+  const int32_t* slot;   // [n][6] coarse-fine slot or -1
+  const int32_t* fslot;  // [nslot][4] FINER slots: the fine leaves' slots, transverse order
+  const int32_t* sleaf;  // [nslot] leaf owning the slot
+  const int32_t* sface;  // [nslot] face of the slot
+  double* G;             // [nslot][nvar][2][T]
+  double* FF;            // [nslot][nvar][T]
+  double rdx[MAXLEV][3]; // 1/dx per level and dimension
+};
+
+struct Sched {
+  int mode;            // 0 per-block launch, 1 grid, 2 persistent
+  int xcd_remap;       // map consecutive leaves onto one XCD
+  int leaf0;           // per-block mode: the leaf
+  int per_xcd;         // ceil(n / 8) for the remap
+  unsigned* counter;   // persistent work counter (reset before each stage)
+};
+
+struct StageArgs {
+  const double* Uin;   // stage input U^(s-1)
+  const double* Un;    // step initial state U^n
+  double* Uout;        // stage output
+  const double* dtp;   // device-resident dt
+  int stage;           // 1..rk
+  int rk;              // 2 or 3
+};
+
+struct Kernels;  // forward
+
+// launchers (kernels.hip)
+struct LaunchCfg {
+  int ndim, mhd, flux, lim;
+};
+
+hipError_t launch_restrict(const Geo& g, const LaunchCfg& c, const double* U, const int32_t* list, int nlist,
+                           hipStream_t st);
+hipError_t launch_prolong(const Geo& g, const LaunchCfg& c, const double* U, const int32_t* list, int nlist,
+                          hipStream_t st);
+hipError_t launch_fineflux(const Geo& g, const LaunchCfg& c, const double* U, const double* physp,
+                           const int32_t* list, int nlist, hipStream_t st);
+hipError_t launch_stage(const Geo& g, const LaunchCfg& c, const StageArgs& a, const double* physp, const Sched& s,
+                        int grid, hipStream_t st);
+hipError_t launch_cfl(const Geo& g, const LaunchCfg& c, const double* U, const double* physp,
+                      unsigned long long* red, hipStream_t st);
+hipError_t launch_lohner(const Geo& g, const LaunchCfg& c, const double* U, const double* physp,
+                         const double* lohp, int max_level, double* emax, int8_t* flags, hipStream_t st);
+hipError_t launch_set_scalars(double* dst, const double* src_host_vals, int n, hipStream_t st);
+hipError_t launch_reset_u32(unsigned* p, int n, hipStream_t st);
+hipError_t launch_scale_var(double* U, const double* facp, long long count, hipStream_t st);
+
+// device parameter block (written once per forest, plus dt / ch per step)
+// layout: [0] gamma [1] gm1 [2] igm1 [3] ch [4] dt [5] glm damping factor
+constexpr int PP_GAMMA = 0, PP_GM1 = 1, PP_IGM1 = 2, PP_CH = 3, PP_DT = 4, PP_DAMP = 5, PP_COUNT = 8;
+// Loehner parameters: [0] eps [1] w_rho [2] w_p [3] tol [4] coarsen tol
+constexpr int LP_EPS = 0, LP_WRHO = 1, LP_WP = 2, LP_TOL = 3, LP_CTOL = 4, LP_COUNT = 8;
+
+}  // namespace amrv

@@ -1,0 +1,931 @@
+// kernels.hip -- gfx950 kernels of the block-forest finite-volume update.
+//
+// One SSP Runge-Kutta stage (arXiv 2004.03275, Sec. 2.1-2.4) on a forest of
+// 16^d blocks (Sec. 1.3) is:
+//   k_restrict   coarse-side ghost slabs of coarse-fine faces: mean of the
+//                2^d finer cells (pairwise sum, times 2^-d)
+//   k_prolong    fine-side ghost slabs: coarse value plus a quarter of its
+//                minmod slope per dimension
+//   k_fineflux   fine-side face fluxes of coarse-fine faces (the coarse side
+//                replaces its own flux by their mean: conservation)
+//   k_stage      per leaf: primitive variables, MUSCL states, Riemann fluxes,
+//                flux divergence and the SSP combination.  Same-level and
+//                boundary ghosts are gathered straight from the neighbour's
+//                interior, so only coarse-fine faces touch the slabs above.
+// plus k_cfl (Courant reduction, Sec. 2.1) and k_lohner (Sec. 1.3 flags).
+//
+// The stencil work is FP64 VALU and HBM traffic: there is no matrix-core
+// contraction here.  The 2D/3D stage kernel streams a 16^3 block through a
+// 16x16 workgroup plane by plane: z-direction data stays in registers, the
+// x/y planes of primitive values, face states and fluxes in LDS.
+#include <float.h>
+
+#include <type_traits>
+
+#include "internal.hpp"
+#include "physics.hpp"
+
+namespace amrv {
+
+constexpr int NB = 16;   // block edge in 2D/3D
+constexpr int WGS = 256; // workgroup size
+
+__device__ __forceinline__ size_t uidx(const Geo& g, int v, int leaf, int cell) {
+  return ((size_t)v * g.n + leaf) * g.ncell + cell;
+}
+
+__device__ __forceinline__ int cell_index(const Geo& g, int x, int y, int z) { return x + g.nx * (y + g.nx * z); }
+
+// conserved values of ghost cell (layer, a1, a2) across face f of `leaf`
+template <int NV>
+__device__ __forceinline__ void ghost_cons(const Geo& g, const double* __restrict__ U, int leaf, int f, int layer,
+                                           int a1, int a2, double* u) {
+  const int kind = g.kind[leaf * 6 + f];
+  const int d = f >> 1, hi = f & 1;
+  if (kind == NB_SAME || kind == NB_BND) {
+    const int src = g.nbr[leaf * 6 + f];
+    const int along = (kind == NB_SAME) ? (hi ? layer : g.nx - 1 - layer) : (hi ? g.nx - 1 : 0);
+    int c[3] = {0, 0, 0};
+    c[d] = along;
+    if (g.ndim > 1) c[d == 0 ? 1 : 0] = a1;
+    if (g.ndim > 2) c[d == 2 ? 1 : 2] = a2;
+    const int cell = cell_index(g, c[0], c[1], c[2]);
+#pragma unroll
+    for (int v = 0; v < NV; v++) u[v] = U[uidx(g, v, src, cell)];
+  } else {
+    const int s = g.slot[leaf * 6 + f];
+    const size_t base = (size_t)s * NV * 2 * g.T + (size_t)layer * g.T + a2 * g.nx + a1;
+#pragma unroll
+    for (int v = 0; v < NV; v++) u[v] = g.G[base + (size_t)v * 2 * g.T];
+  }
+}
+
+// conserved values of a cell of `leaf` given in local coordinates; at most one
+// coordinate may lie in the two face-ghost layers
+template <int NV, int ND>
+__device__ __forceinline__ void fetch_cons(const Geo& g, const double* __restrict__ U, int leaf, int x, int y, int z,
+                                           double* u) {
+  int c[3] = {x, y, z};
+  int f = -1, layer = 0;
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    if (c[d] < 0) {
+      f = 2 * d;
+      layer = -1 - c[d];
+    } else if (c[d] >= g.nx) {
+      f = 2 * d + 1;
+      layer = c[d] - g.nx;
+    }
+  }
+  if (f < 0) {
+    const int cell = cell_index(g, x, y, z);
+#pragma unroll
+    for (int v = 0; v < NV; v++) u[v] = U[uidx(g, v, leaf, cell)];
+    return;
+  }
+  const int d = f >> 1;
+  const int a1 = ND > 1 ? c[d == 0 ? 1 : 0] : 0;
+  const int a2 = ND > 2 ? c[d == 2 ? 1 : 2] : 0;
+  ghost_cons<NV>(g, U, leaf, f, layer, a1, a2, u);
+}
+
+// face flux of a coarse-fine face taken from the fine-side flux slabs: the
+// fine leaf's own value, or on the coarse side the mean of the 2^(d-1) fine
+// fluxes covering the coarse face
+template <int NV, int ND>
+__device__ __forceinline__ void cf_flux(const Geo& g, int leaf, int f, int kind, int a1, int a2, double* F) {
+  const int s = g.slot[leaf * 6 + f];
+  if (kind == NB_COARSER) {
+    const size_t base = (size_t)s * NV * g.T + a2 * g.nx + a1;
+#pragma unroll
+    for (int v = 0; v < NV; v++) F[v] = g.FF[base + (size_t)v * g.T];
+    return;
+  }
+  if constexpr (ND == 1) {
+    const int fs = g.fslot[s * 4];
+#pragma unroll
+    for (int v = 0; v < NV; v++) F[v] = g.FF[(size_t)fs * NV + v];
+  } else if constexpr (ND == 2) {
+    const int fs = g.fslot[s * 4 + (a1 >= NB / 2)];
+    const size_t base = (size_t)fs * NV * g.T;
+    const int t0 = (2 * a1) & (NB - 1), t1 = (2 * a1 + 1) & (NB - 1);
+#pragma unroll
+    for (int v = 0; v < NV; v++) F[v] = (g.FF[base + (size_t)v * g.T + t0] + g.FF[base + (size_t)v * g.T + t1]) * 0.5;
+  } else {
+    const int fs = g.fslot[s * 4 + (a1 >= NB / 2) + 2 * (a2 >= NB / 2)];
+    const size_t base = (size_t)fs * NV * g.T;
+    const int x0 = (2 * a1) & (NB - 1), x1 = (2 * a1 + 1) & (NB - 1);
+    const int y0 = (2 * a2) & (NB - 1), y1 = (2 * a2 + 1) & (NB - 1);
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+      const double* p = g.FF + base + (size_t)v * g.T;
+      F[v] = ((p[y0 * NB + x0] + p[y0 * NB + x1]) + (p[y1 * NB + x0] + p[y1 * NB + x1])) * 0.25;
+    }
+  }
+}
+
+__device__ __forceinline__ PhysParams load_phys(const double* __restrict__ pp) {
+  PhysParams P;
+  P.gamma = pp[PP_GAMMA];
+  P.gm1 = pp[PP_GM1];
+  P.igm1 = pp[PP_IGM1];
+  P.ch = pp[PP_CH];
+  return P;
+}
+
+template <int ND, bool MHD, int FLUX>
+__device__ __forceinline__ void riemann_dir(int d, double* vl, double* vr, double* F, const PhysParams& P) {
+  if (d == 0) {
+    riemann<ND, MHD, FLUX, 0>(vl, vr, F, P);
+  } else if constexpr (ND > 1) {
+    if (d == 1) {
+      riemann<ND, MHD, FLUX, (ND > 1 ? 1 : 0)>(vl, vr, F, P);
+    } else if constexpr (ND > 2) {
+      riemann<ND, MHD, FLUX, (ND > 2 ? 2 : 0)>(vl, vr, F, P);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// ghost slabs of coarse-fine faces
+// ---------------------------------------------------------------------------
+
+template <int ND, int NV>
+__global__ void __launch_bounds__(WGS) k_restrict(Geo g, const double* __restrict__ U, const int32_t* __restrict__ list,
+                                                  int nlist) {
+  const long long i = (long long)blockIdx.x * WGS + threadIdx.x;
+  const long long per = 2LL * g.T;
+  if (i >= nlist * per) return;
+  const int slot = list[i / per];
+  const int rem = (int)(i % per);
+  const int layer = rem / g.T, t = rem % g.T;
+  const int a1 = ND > 1 ? t % g.nx : 0, a2 = ND > 2 ? t / g.nx : 0;
+  const int f = g.sface[slot];
+  const int d = f >> 1, hi = f & 1;
+  const int half = g.nx >> 1;
+  const int q = (ND > 1 ? (a1 >= half) : 0) + (ND > 2 ? 2 * (a2 >= half) : 0);
+  const int fine = g.sleaf[g.fslot[slot * 4 + q]];
+  double acc[8][NV];
+#pragma unroll
+  for (int o = 0; o < (1 << ND); o++) {
+    int c[3] = {0, 0, 0};
+#pragma unroll
+    for (int e = 0; e < ND; e++) {
+      const int oe = (o >> e) & 1;
+      if (e == d)
+        c[e] = hi ? 2 * layer + oe : g.nx - 2 - 2 * layer + oe;
+      else
+        c[e] = (2 * ((e == (d == 0 ? 1 : 0)) ? a1 : a2) + oe) % g.nx;
+    }
+    const int cell = cell_index(g, c[0], c[1], c[2]);
+#pragma unroll
+    for (int v = 0; v < NV; v++) acc[o][v] = U[uidx(g, v, fine, cell)];
+  }
+  const size_t base = (size_t)slot * NV * 2 * g.T + (size_t)layer * g.T + t;
+#pragma unroll
+  for (int v = 0; v < NV; v++) {
+    double r;
+    if constexpr (ND == 1)
+      r = (acc[0][v] + acc[1][v]) * 0.5;
+    else if constexpr (ND == 2)
+      r = ((acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v])) * 0.25;
+    else
+      r = (((acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v])) + ((acc[4][v] + acc[5][v]) + (acc[6][v] + acc[7][v]))) *
+          0.125;
+    g.G[base + (size_t)v * 2 * g.T] = r;
+  }
+}
+
+template <int ND, int NV>
+__global__ void __launch_bounds__(WGS) k_prolong(Geo g, const double* __restrict__ U, const int32_t* __restrict__ list,
+                                                 int nlist) {
+  const long long i = (long long)blockIdx.x * WGS + threadIdx.x;
+  const long long per = 2LL * g.T;
+  if (i >= nlist * per) return;
+  const int slot = list[i / per];
+  const int rem = (int)(i % per);
+  const int layer = rem / g.T, t = rem % g.T;
+  const int a1 = ND > 1 ? t % g.nx : 0, a2 = ND > 2 ? t / g.nx : 0;
+  const int fine = g.sleaf[slot];
+  const int f = g.sface[slot];
+  const int d = f >> 1, hi = f & 1;
+  const int C = g.nbr[fine * 6 + f];
+  int cc[3] = {0, 0, 0}, par[3] = {0, 0, 0};
+#pragma unroll
+  for (int e = 0; e < ND; e++) {
+    int loc;
+    if (e == d)
+      loc = hi ? g.nx + layer : -1 - layer;
+    else
+      loc = (e == (d == 0 ? 1 : 0)) ? a1 : a2;
+    const long long gl = (long long)g.ijk[fine * 3 + e] * g.nx + loc;  // fine global coordinate
+    const long long gc = gl >> 1;                                       // coarse global (floor)
+    cc[e] = (int)(((gc % g.nx) + g.nx) % g.nx);
+    par[e] = (int)(gl & 1);
+  }
+  double u0[NV];
+  fetch_cons<NV, ND>(g, U, C, cc[0], cc[1], cc[2], u0);
+  double res[NV];
+#pragma unroll
+  for (int v = 0; v < NV; v++) res[v] = u0[v];
+#pragma unroll
+  for (int e = 0; e < ND; e++) {
+    double um[NV], up[NV];
+    int lo[3] = {cc[0], cc[1], cc[2]}, hi3[3] = {cc[0], cc[1], cc[2]};
+    lo[e] -= 1;
+    hi3[e] += 1;
+    fetch_cons<NV, ND>(g, U, C, lo[0], lo[1], lo[2], um);
+    fetch_cons<NV, ND>(g, U, C, hi3[0], hi3[1], hi3[2], up);
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+      const double tq = 0.25 * minmod(u0[v] - um[v], up[v] - u0[v]);
+      res[v] = par[e] ? res[v] + tq : res[v] - tq;
+    }
+  }
+  const size_t base = (size_t)slot * NV * 2 * g.T + (size_t)layer * g.T + t;
+#pragma unroll
+  for (int v = 0; v < NV; v++) g.G[base + (size_t)v * 2 * g.T] = res[v];
+}
+
+// fine-side flux of each coarse-fine face (list of COARSER slots)
+template <int ND, bool MHD, int FLUX, int LIM>
+__global__ void __launch_bounds__(WGS) k_fineflux(Geo g, const double* __restrict__ U, const double* __restrict__ pp,
+                                                  const int32_t* __restrict__ list, int nlist) {
+  using S = Sys<ND, MHD>;
+  constexpr int NV = S::NV;
+  const long long i = (long long)blockIdx.x * WGS + threadIdx.x;
+  if (i >= (long long)nlist * g.T) return;
+  const PhysParams P = load_phys(pp);
+  const int slot = list[i / g.T];
+  const int t = (int)(i % g.T);
+  const int a1 = ND > 1 ? t % g.nx : 0, a2 = ND > 2 ? t / g.nx : 0;
+  const int leaf = g.sleaf[slot];
+  const int f = g.sface[slot];
+  const int d = f >> 1, hi = f & 1;
+  const int m = hi ? g.nx : 0;  // face between cells m-1 and m along d
+  double V[4][NV];
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    int c[3] = {0, 0, 0};
+    c[d] = m - 2 + j;
+    if (ND > 1) c[d == 0 ? 1 : 0] = a1;
+    if (ND > 2) c[d == 2 ? 1 : 2] = a2;
+    double u[NV];
+    fetch_cons<NV, ND>(g, U, leaf, c[0], c[1], c[2], u);
+    cons2prim<ND, MHD>(u, V[j], P);
+  }
+  double lo[NV], vl[NV], vr[NV], hi_[NV], F[NV];
+  muscl<NV, LIM>(V[0], V[1], V[2], lo, vl);
+  muscl<NV, LIM>(V[1], V[2], V[3], vr, hi_);
+  riemann_dir<ND, MHD, FLUX>(d, vl, vr, F, P);
+  const size_t base = (size_t)slot * NV * g.T + t;
+#pragma unroll
+  for (int v = 0; v < NV; v++) g.FF[base + (size_t)v * g.T] = F[v];
+}
+
+// ---------------------------------------------------------------------------
+// stage update, 2D / 3D: one 16x16 workgroup per leaf, streaming z-planes
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int pick_leaf(const Sched& sc, int b) {
+  if (sc.mode == 0) return sc.leaf0;
+  if (sc.xcd_remap) return (b & 7) * sc.per_xcd + (b >> 3);
+  return b;
+}
+
+template <int ND, bool MHD>
+__device__ __forceinline__ void own_prim(const Geo& g, const double* __restrict__ U, int leaf, int x, int y, int z,
+                                         double* v, const PhysParams& P) {
+  constexpr int NV = Sys<ND, MHD>::NV;
+  double u[NV];
+  fetch_cons<NV, ND>(g, U, leaf, x, y, z, u);
+  cons2prim<ND, MHD>(u, v, P);
+}
+
+template <int NV>
+__device__ __forceinline__ double combine(int stage, int rk, double un, double tmp) {
+  if (stage == 1) return tmp;
+  if (rk == 2) return 0.5 * un + 0.5 * tmp;
+  if (stage == 2) return 0.75 * un + 0.25 * tmp;
+  return (1.0 / 3.0) * un + (2.0 / 3.0) * tmp;
+}
+
+template <int ND, bool MHD, int FLUX, int LIM>
+__global__ void __launch_bounds__(WGS) k_stage_tile(Geo g, StageArgs a, const double* __restrict__ pp, Sched sc) {
+  using S = Sys<ND, MHD>;
+  constexpr int NV = S::NV;
+  constexpr int PW = NB + 4;
+  constexpr int NZ = ND == 3 ? NB : 1;
+  __shared__ double sP[NV][PW * PW];  // primitive plane incl. x/y ghost ring, (y+2)*PW + x+2
+  __shared__ double sL[NV][NB * 18];  // upper-face states per row, cell index + 1
+  __shared__ double sR[NV][NB * 18];  // lower-face states
+  __shared__ double sF[NV][NB * 17];  // face fluxes per row
+  __shared__ int sLeaf;
+
+  const PhysParams P = load_phys(pp);
+  const double dt = pp[PP_DT];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+
+  for (int iter = 0;; iter++) {
+    int leaf;
+    if (sc.mode == 2) {
+      if (tid == 0) sLeaf = (int)atomicAdd(sc.counter, 1u);
+      __syncthreads();
+      leaf = sLeaf;
+      __syncthreads();
+    } else {
+      if (iter) break;
+      leaf = pick_leaf(sc, blockIdx.x);
+    }
+    if (leaf >= g.n) break;
+
+    const int lvl = g.lvl[leaf];
+    const double rdx = g.rdx[lvl][0], rdy = g.rdx[lvl][1], rdz = ND == 3 ? g.rdx[lvl][2] : 0.0;
+    int kinds[2 * ND];
+#pragma unroll
+    for (int f = 0; f < 2 * ND; f++) kinds[f] = g.kind[leaf * 6 + f];
+
+    // ring cell handled by this thread (tid < 128)
+    int rx = 0, ry = 0, rface = 0, rlayer = 0, ra1 = 0;
+    if (tid < 64) {
+      const int c = tid >> 4;
+      ry = tid & 15;
+      rx = c < 2 ? c - 2 : 14 + c;
+      rface = rx < 0 ? 0 : 1;
+      rlayer = rx < 0 ? -1 - rx : rx - NB;
+      ra1 = ry;
+    } else if (tid < 128) {
+      const int u = tid - 64, c = u >> 4;
+      rx = u & 15;
+      ry = c < 2 ? c - 2 : 14 + c;
+      rface = ry < 0 ? 2 : 3;
+      rlayer = ry < 0 ? -1 - ry : ry - NB;
+      ra1 = rx;
+    }
+
+    double q0[NV], q1[NV], VLz[NV], Flo[NV];
+    if constexpr (ND == 3) {
+      double vm2[NV], vm1[NV], lo[NV], hi[NV], vlm1[NV];
+      own_prim<ND, MHD>(g, a.Uin, leaf, tx, ty, -2, vm2, P);
+      own_prim<ND, MHD>(g, a.Uin, leaf, tx, ty, -1, vm1, P);
+      own_prim<ND, MHD>(g, a.Uin, leaf, tx, ty, 0, q0, P);
+      own_prim<ND, MHD>(g, a.Uin, leaf, tx, ty, 1, q1, P);
+      muscl<NV, LIM>(vm2, vm1, q0, lo, vlm1);
+      muscl<NV, LIM>(vm1, q0, q1, lo, hi);
+      if (kinds[4] == NB_SAME || kinds[4] == NB_BND) {
+        riemann<ND, MHD, FLUX, (ND == 3 ? 2 : 0)>(vlm1, lo, Flo, P);
+      } else {
+        cf_flux<NV, ND>(g, leaf, 4, kinds[4], tx, ty, Flo);
+      }
+#pragma unroll
+      for (int v = 0; v < NV; v++) VLz[v] = hi[v];
+    }
+
+    for (int k = 0; k < NZ; k++) {
+      double Fhi[NV], VLn[NV];
+      if constexpr (ND == 3) {
+        double q2[NV], VRn[NV];
+        own_prim<ND, MHD>(g, a.Uin, leaf, tx, ty, k + 2, q2, P);
+        muscl<NV, LIM>(q0, q1, q2, VRn, VLn);
+        if (k == NB - 1 && !(kinds[5] == NB_SAME || kinds[5] == NB_BND)) {
+          cf_flux<NV, ND>(g, leaf, 5, kinds[5], tx, ty, Fhi);
+        } else {
+          double vl[NV];
+#pragma unroll
+          for (int v = 0; v < NV; v++) vl[v] = VLz[v];
+          riemann<ND, MHD, FLUX, (ND == 3 ? 2 : 0)>(vl, VRn, Fhi, P);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+          sP[v][(ty + 2) * PW + tx + 2] = q0[v];
+          q0[v] = q1[v];
+          q1[v] = q2[v];
+        }
+      } else {
+        double own[NV];
+        own_prim<ND, MHD>(g, a.Uin, leaf, tx, ty, 0, own, P);
+#pragma unroll
+        for (int v = 0; v < NV; v++) sP[v][(ty + 2) * PW + tx + 2] = own[v];
+      }
+      if (tid < 128) {
+        double u[NV], w[NV];
+        ghost_cons<NV>(g, a.Uin, leaf, rface, rlayer, ra1, k, u);
+        cons2prim<ND, MHD>(u, w, P);
+#pragma unroll
+        for (int v = 0; v < NV; v++) sP[v][(ry + 2) * PW + rx + 2] = w[v];
+      }
+      __syncthreads();
+
+      // ---- x direction: rows are y
+      for (int t = tid; t < NB * 18; t += WGS) {
+        const int r = t / 18, c = t % 18 - 1;
+        const int b = (r + 2) * PW + c + 2;
+        double vm[NV], v0[NV], vp[NV], lo[NV], hi[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+          vm[v] = sP[v][b - 1];
+          v0[v] = sP[v][b];
+          vp[v] = sP[v][b + 1];
+        }
+        muscl<NV, LIM>(vm, v0, vp, lo, hi);
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+          sL[v][r * 18 + c + 1] = hi[v];
+          sR[v][r * 18 + c + 1] = lo[v];
+        }
+      }
+      __syncthreads();
+      for (int t = tid; t < NB * 17; t += WGS) {
+        const int r = t / 17, m = t % 17;
+        double F[NV];
+        const int bf = m == 0 ? 0 : (m == NB ? 1 : -1);
+        if (bf >= 0 && !(kinds[bf] == NB_SAME || kinds[bf] == NB_BND)) {
+          cf_flux<NV, ND>(g, leaf, bf, kinds[bf], r, k, F);
+        } else {
+          double vl[NV], vr[NV];
+#pragma unroll
+          for (int v = 0; v < NV; v++) {
+            vl[v] = sL[v][r * 18 + m];
+            vr[v] = sR[v][r * 18 + m + 1];
+          }
+          riemann<ND, MHD, FLUX, 0>(vl, vr, F, P);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; v++) sF[v][r * 17 + m] = F[v];
+      }
+      __syncthreads();
+      double acc[NV];
+#pragma unroll
+      for (int v = 0; v < NV; v++) acc[v] = (sF[v][ty * 17 + tx + 1] - sF[v][ty * 17 + tx]) * rdx;
+
+      // ---- y direction: rows are x
+      for (int t = tid; t < NB * 18; t += WGS) {
+        const int r = t / 18, c = t % 18 - 1;
+        const int b = (c + 2) * PW + r + 2;
+        double vm[NV], v0[NV], vp[NV], lo[NV], hi[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+          vm[v] = sP[v][b - PW];
+          v0[v] = sP[v][b];
+          vp[v] = sP[v][b + PW];
+        }
+        muscl<NV, LIM>(vm, v0, vp, lo, hi);
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+          sL[v][r * 18 + c + 1] = hi[v];
+          sR[v][r * 18 + c + 1] = lo[v];
+        }
+      }
+      __syncthreads();
+      for (int t = tid; t < NB * 17; t += WGS) {
+        const int r = t / 17, m = t % 17;
+        double F[NV];
+        const int bf = m == 0 ? 2 : (m == NB ? 3 : -1);
+        if (bf >= 0 && !(kinds[bf] == NB_SAME || kinds[bf] == NB_BND)) {
+          cf_flux<NV, ND>(g, leaf, bf, kinds[bf], r, k, F);
+        } else {
+          double vl[NV], vr[NV];
+#pragma unroll
+          for (int v = 0; v < NV; v++) {
+            vl[v] = sL[v][r * 18 + m];
+            vr[v] = sR[v][r * 18 + m + 1];
+          }
+          riemann<ND, MHD, FLUX, 1>(vl, vr, F, P);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; v++) sF[v][r * 17 + m] = F[v];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < NV; v++) acc[v] = acc[v] + (sF[v][tx * 17 + ty + 1] - sF[v][tx * 17 + ty]) * rdy;
+      if constexpr (ND == 3) {
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+          acc[v] = acc[v] + (Fhi[v] - Flo[v]) * rdz;
+          Flo[v] = Fhi[v];
+          VLz[v] = VLn[v];
+        }
+      }
+      const int cell = tx + NB * (ty + NB * k);
+#pragma unroll
+      for (int v = 0; v < NV; v++) {
+        const size_t id = uidx(g, v, leaf, cell);
+        const double tmp = a.Uin[id] - dt * acc[v];
+        const double un = a.stage == 1 ? 0.0 : a.Un[id];
+        a.Uout[id] = combine<NV>(a.stage, a.rk, un, tmp);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stage update, 1D: a leaf of nx cells in chunks of 256, one workgroup each
+// ---------------------------------------------------------------------------
+
+template <bool MHD, int FLUX, int LIM>
+__global__ void __launch_bounds__(WGS) k_stage_line(Geo g, StageArgs a, const double* __restrict__ pp, Sched sc) {
+  using S = Sys<1, MHD>;
+  constexpr int NV = S::NV;
+  constexpr int CH = WGS;
+  __shared__ double sP[NV][CH + 4];
+  __shared__ double sL[NV][CH + 2];
+  __shared__ double sR[NV][CH + 2];
+  __shared__ double sF[NV][CH + 1];
+  const PhysParams P = load_phys(pp);
+  const double dt = pp[PP_DT];
+  const int tid = threadIdx.x;
+  const int nch = (g.nx + CH - 1) / CH;
+  const int leaf = sc.mode == 0 ? sc.leaf0 : (int)(blockIdx.x / nch);
+  const int c0 = (int)(blockIdx.x % nch) * CH;
+  if (leaf >= g.n) return;
+  const int lvl = g.lvl[leaf];
+  const double rdx = g.rdx[lvl][0];
+  const int kind0 = g.kind[leaf * 6 + 0], kind1 = g.kind[leaf * 6 + 1];
+
+  for (int t = tid; t < CH + 4; t += WGS) {
+    const int x = c0 - 2 + t;
+    if (x > g.nx + 1) continue;
+    double u[NV], w[NV];
+    fetch_cons<NV, 1>(g, a.Uin, leaf, x, 0, 0, u);
+    cons2prim<1, MHD>(u, w, P);
+#pragma unroll
+    for (int v = 0; v < NV; v++) sP[v][t] = w[v];
+  }
+  __syncthreads();
+  for (int t = tid; t < CH + 2; t += WGS) {
+    const int x = c0 - 1 + t;
+    if (x > g.nx) continue;
+    double vm[NV], v0[NV], vp[NV], lo[NV], hi[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+      vm[v] = sP[v][t];
+      v0[v] = sP[v][t + 1];
+      vp[v] = sP[v][t + 2];
+    }
+    muscl<NV, LIM>(vm, v0, vp, lo, hi);
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+      sL[v][t] = hi[v];
+      sR[v][t] = lo[v];
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < CH + 1; t += WGS) {
+    const int m = c0 + t;
+    if (m > g.nx) continue;
+    double F[NV];
+    if (m == 0 && !(kind0 == NB_SAME || kind0 == NB_BND)) {
+      cf_flux<NV, 1>(g, leaf, 0, kind0, 0, 0, F);
+    } else if (m == g.nx && !(kind1 == NB_SAME || kind1 == NB_BND)) {
+      cf_flux<NV, 1>(g, leaf, 1, kind1, 0, 0, F);
+    } else {
+      double vl[NV], vr[NV];
+#pragma unroll
+      for (int v = 0; v < NV; v++) {
+        vl[v] = sL[v][t];
+        vr[v] = sR[v][t + 1];
+      }
+      riemann<1, MHD, FLUX, 0>(vl, vr, F, P);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; v++) sF[v][t] = F[v];
+  }
+  __syncthreads();
+  const int x = c0 + tid;
+  if (x < g.nx) {
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+      const double acc = (sF[v][tid + 1] - sF[v][tid]) * rdx;
+      const size_t id = uidx(g, v, leaf, x);
+      const double tmp = a.Uin[id] - dt * acc;
+      const double un = a.stage == 1 ? 0.0 : a.Un[id];
+      a.Uout[id] = combine<NV>(a.stage, a.rk, un, tmp);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Courant reduction and validation (Sec. 2.1)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long y = __shfl_xor(x, o, 64);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+// red[0] = bits of max_cells sum_d (|v_d|+c_d)/dx_d, red[1] = bits of the max
+// signal speed (GLM c_h), red[2] = non-physical flag.  Non-negative doubles
+// order like their bit patterns, so integer atomics give the exact maximum.
+template <int ND, bool MHD>
+__global__ void __launch_bounds__(WGS) k_cfl(Geo g, const double* __restrict__ U, const double* __restrict__ pp,
+                                             unsigned long long* red) {
+  constexpr int NV = Sys<ND, MHD>::NV;
+  const PhysParams P = load_phys(pp);
+  const long long total = (long long)g.n * g.ncell;
+  unsigned long long smax = 0, cmax = 0;
+  int bad = 0;
+  for (long long i = (long long)blockIdx.x * WGS + threadIdx.x; i < total; i += (long long)gridDim.x * WGS) {
+    const int leaf = (int)(i / g.ncell), cell = (int)(i % g.ncell);
+    double u[NV], v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; k++) u[k] = U[uidx(g, k, leaf, cell)];
+    cons2prim<ND, MHD>(u, v, P);
+    if (!(v[0] > 0.0) || !(v[Sys<ND, MHD>::IE] > 0.0)) {
+      bad = 1;
+      continue;
+    }
+    const int lvl = g.lvl[leaf];
+    double s = 0.0, cm = 0.0;
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+      const double w = fabs(v[1 + d]) + wave_speed_dir<ND, MHD>(v, d, P);
+      const double tq = w * g.rdx[lvl][d];
+      s = d == 0 ? tq : s + tq;
+      cm = w > cm ? w : cm;
+    }
+    const unsigned long long sb = (unsigned long long)__double_as_longlong(s);
+    const unsigned long long cb = (unsigned long long)__double_as_longlong(cm);
+    smax = sb > smax ? sb : smax;
+    cmax = cb > cmax ? cb : cmax;
+  }
+  smax = wave_max_u64(smax);
+  cmax = wave_max_u64(cmax);
+  bad = __any(bad);
+  if ((threadIdx.x & 63) == 0) {
+    if (smax) atomicMax(&red[0], smax);
+    if (cmax) atomicMax(&red[1], cmax);
+    if (bad) atomicOr(&red[2], 1ull);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Loehner flags (Sec. 1.3): one workgroup per leaf
+// ---------------------------------------------------------------------------
+
+template <int ND, bool MHD>
+__device__ __forceinline__ void rho_p(const Geo& g, const double* __restrict__ U, int leaf, int x, int y, int z,
+                                      const PhysParams& P, double& rho, double& p) {
+  constexpr int NV = Sys<ND, MHD>::NV;
+  double u[NV], v[NV];
+  fetch_cons<NV, ND>(g, U, leaf, x, y, z, u);
+  cons2prim<ND, MHD>(u, v, P);
+  rho = v[0];
+  p = v[Sys<ND, MHD>::IE];
+}
+
+template <int ND, bool MHD>
+__global__ void __launch_bounds__(WGS) k_lohner(Geo g, const double* __restrict__ U, const double* __restrict__ pp,
+                                                const double* __restrict__ lp, int max_level, double* emax_out,
+                                                int8_t* flags) {
+  __shared__ double red[WGS / 64];
+  const int leaf = blockIdx.x;
+  const PhysParams P = load_phys(pp);
+  const double eps = lp[LP_EPS], wr = lp[LP_WRHO], wp = lp[LP_WP];
+  double m = 0.0;
+  for (int cell = threadIdx.x; cell < g.ncell; cell += WGS) {
+    const int x = cell % g.nx;
+    const int y = ND > 1 ? (cell / g.nx) % g.nx : 0;
+    const int z = ND > 2 ? cell / (g.nx * g.nx) : 0;
+    double r0, p0;
+    rho_p<ND, MHD>(g, U, leaf, x, y, z, P, r0, p0);
+    double nr = 0.0, dr = 0.0, np = 0.0, dp = 0.0;
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+      int lo[3] = {x, y, z}, hi[3] = {x, y, z};
+      lo[d] -= 1;
+      hi[d] += 1;
+      double rm, pm, rp, pq;
+      rho_p<ND, MHD>(g, U, leaf, lo[0], lo[1], lo[2], P, rm, pm);
+      rho_p<ND, MHD>(g, U, leaf, hi[0], hi[1], hi[2], P, rp, pq);
+      const double d2r = rp - 2.0 * r0 + rm;
+      const double ddr = fabs(rp - r0) + fabs(r0 - rm) + eps * (fabs(rp) + 2.0 * fabs(r0) + fabs(rm));
+      const double d2p = pq - 2.0 * p0 + pm;
+      const double ddp = fabs(pq - p0) + fabs(p0 - pm) + eps * (fabs(pq) + 2.0 * fabs(p0) + fabs(pm));
+      nr = d == 0 ? d2r * d2r : nr + d2r * d2r;
+      dr = d == 0 ? ddr * ddr : dr + ddr * ddr;
+      np = d == 0 ? d2p * d2p : np + d2p * d2p;
+      dp = d == 0 ? ddp * ddp : dp + ddp * ddp;
+    }
+    const double er = dr > 0.0 ? sqrt(nr / dr) : 0.0;
+    const double ep = dp > 0.0 ? sqrt(np / dp) : 0.0;
+    const double e = wr * er + wp * ep;
+    if (e > m) m = e;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double y = __shfl_xor(m, o, 64);
+    m = y > m ? y : m;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mm = red[0];
+    for (int w = 1; w < WGS / 64; w++) mm = red[w] > mm ? red[w] : mm;
+    const int l = g.lvl[leaf];
+    int8_t fl = 0;
+    if (l < max_level && mm > lp[LP_TOL])
+      fl = 1;
+    else if (l > 1 && mm < lp[LP_CTOL])
+      fl = -1;
+    flags[leaf] = fl;
+    emax_out[leaf] = mm;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+__global__ void k_set_scalars(double* dst, double a0, double a1, double a2, double a3, int n) {
+  const int i = threadIdx.x;
+  const double v = i == 0 ? a0 : (i == 1 ? a1 : (i == 2 ? a2 : a3));
+  if (i < n) dst[i] = v;
+}
+
+__global__ void k_reset_u32(unsigned* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+__global__ void k_scale(double* U, const double* __restrict__ facp, long long count) {
+  const double fac = *facp;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+    U[i] = U[i] * fac;
+}
+
+// ---------------------------------------------------------------------------
+// launchers: dispatch runtime configuration onto template instances
+// ---------------------------------------------------------------------------
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// call fn(IC<ndim>, IC<mhd>, IC<flux>, IC<limiter>) for the runtime
+// configuration; MHD has no HLLC instance
+template <class Fn>
+static void dispatch(const LaunchCfg& c, Fn&& fn) {
+  auto lim = [&](auto nd, auto mhd, auto fl) {
+    if (c.lim == LIM_MINMOD)
+      fn(nd, mhd, fl, IC<LIM_MINMOD>{});
+    else
+      fn(nd, mhd, fl, IC<LIM_VANLEER>{});
+  };
+  auto flx = [&](auto nd, auto mhd) {
+    if (c.flux == FLX_TVDLF)
+      lim(nd, mhd, IC<FLX_TVDLF>{});
+    else if (c.flux == FLX_HLL || decltype(mhd)::value)
+      lim(nd, mhd, IC<FLX_HLL>{});
+    else
+      lim(nd, mhd, IC<(decltype(mhd)::value ? FLX_HLL : FLX_HLLC)>{});
+  };
+  auto phys = [&](auto nd) {
+    if (c.mhd)
+      flx(nd, IC<1>{});
+    else
+      flx(nd, IC<0>{});
+  };
+  if (c.ndim == 1)
+    phys(IC<1>{});
+  else if (c.ndim == 2)
+    phys(IC<2>{});
+  else
+    phys(IC<3>{});
+}
+
+static inline unsigned blocks_for(long long work) { return (unsigned)((work + WGS - 1) / WGS); }
+
+hipError_t launch_restrict(const Geo& g, const LaunchCfg& c, const double* U, const int32_t* list, int nlist,
+                           hipStream_t st) {
+  if (nlist <= 0) return hipSuccess;
+  const unsigned nb = blocks_for((long long)nlist * 2 * g.T);
+#define BODY_R                                                                                 \
+  if (c.mhd) {                                                                                 \
+    hipLaunchKernelGGL((k_restrict<ND, Sys<ND, true>::NV>), dim3(nb), dim3(WGS), 0, st, g, U, list, nlist); \
+  } else {                                                                                     \
+    hipLaunchKernelGGL((k_restrict<ND, Sys<ND, false>::NV>), dim3(nb), dim3(WGS), 0, st, g, U, list, nlist); \
+  }
+  if (c.ndim == 1) {
+    constexpr int ND = 1;
+    BODY_R
+  } else if (c.ndim == 2) {
+    constexpr int ND = 2;
+    BODY_R
+  } else {
+    constexpr int ND = 3;
+    BODY_R
+  }
+#undef BODY_R
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong(const Geo& g, const LaunchCfg& c, const double* U, const int32_t* list, int nlist,
+                          hipStream_t st) {
+  if (nlist <= 0) return hipSuccess;
+  const unsigned nb = blocks_for((long long)nlist * 2 * g.T);
+#define BODY_P                                                                                \
+  if (c.mhd) {                                                                                \
+    hipLaunchKernelGGL((k_prolong<ND, Sys<ND, true>::NV>), dim3(nb), dim3(WGS), 0, st, g, U, list, nlist); \
+  } else {                                                                                    \
+    hipLaunchKernelGGL((k_prolong<ND, Sys<ND, false>::NV>), dim3(nb), dim3(WGS), 0, st, g, U, list, nlist); \
+  }
+  if (c.ndim == 1) {
+    constexpr int ND = 1;
+    BODY_P
+  } else if (c.ndim == 2) {
+    constexpr int ND = 2;
+    BODY_P
+  } else {
+    constexpr int ND = 3;
+    BODY_P
+  }
+#undef BODY_P
+  return hipGetLastError();
+}
+
+hipError_t launch_fineflux(const Geo& g, const LaunchCfg& c, const double* U, const double* physp,
+                           const int32_t* list, int nlist, hipStream_t st) {
+  if (nlist <= 0) return hipSuccess;
+  const unsigned nb = blocks_for((long long)nlist * g.T);
+  dispatch(c, [&](auto nd, auto mhd, auto fl, auto lm) {
+    constexpr int ND = decltype(nd)::value, FL = decltype(fl)::value, LM = decltype(lm)::value;
+    constexpr bool MHD = decltype(mhd)::value != 0;
+    hipLaunchKernelGGL((k_fineflux<ND, MHD, FL, LM>), dim3(nb), dim3(WGS), 0, st, g, U, physp, list, nlist);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_stage(const Geo& g, const LaunchCfg& c, const StageArgs& a, const double* physp, const Sched& s,
+                        int grid, hipStream_t st) {
+  dispatch(c, [&](auto nd, auto mhd, auto fl, auto lm) {
+    constexpr int ND = decltype(nd)::value, FL = decltype(fl)::value, LM = decltype(lm)::value;
+    constexpr bool MHD = decltype(mhd)::value != 0;
+    if constexpr (ND == 1)
+      hipLaunchKernelGGL((k_stage_line<MHD, FL, LM>), dim3(grid), dim3(WGS), 0, st, g, a, physp, s);
+    else
+      hipLaunchKernelGGL((k_stage_tile<ND, MHD, FL, LM>), dim3(grid), dim3(WGS), 0, st, g, a, physp, s);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_cfl(const Geo& g, const LaunchCfg& c, const double* U, const double* physp,
+                      unsigned long long* red, hipStream_t st) {
+  const long long total = (long long)g.n * g.ncell;
+  long long nb = (total + WGS - 1) / WGS;
+  if (nb > 4096) nb = 4096;
+#define BODY_C(ND)                                                                                            \
+  if (c.mhd)                                                                                                  \
+    hipLaunchKernelGGL((k_cfl<ND, true>), dim3((unsigned)nb), dim3(WGS), 0, st, g, U, physp, red);             \
+  else                                                                                                        \
+    hipLaunchKernelGGL((k_cfl<ND, false>), dim3((unsigned)nb), dim3(WGS), 0, st, g, U, physp, red);
+  if (c.ndim == 1) {
+    BODY_C(1)
+  } else if (c.ndim == 2) {
+    BODY_C(2)
+  } else {
+    BODY_C(3)
+  }
+#undef BODY_C
+  return hipGetLastError();
+}
+
+hipError_t launch_lohner(const Geo& g, const LaunchCfg& c, const double* U, const double* physp, const double* lohp,
+                         int max_level, double* emax, int8_t* flags, hipStream_t st) {
+#define BODY_L(ND)                                                                                                \
+  if (c.mhd)                                                                                                      \
+    hipLaunchKernelGGL((k_lohner<ND, true>), dim3(g.n), dim3(WGS), 0, st, g, U, physp, lohp, max_level, emax, flags); \
+  else                                                                                                            \
+    hipLaunchKernelGGL((k_lohner<ND, false>), dim3(g.n), dim3(WGS), 0, st, g, U, physp, lohp, max_level, emax, flags);
+  if (c.ndim == 1) {
+    BODY_L(1)
+  } else if (c.ndim == 2) {
+    BODY_L(2)
+  } else {
+    BODY_L(3)
+  }
+#undef BODY_L
+  return hipGetLastError();
+}
+
+hipError_t launch_set_scalars(double* dst, const double* vals, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, st, dst, vals[0], n > 1 ? vals[1] : 0.0,
+                     n > 2 ? vals[2] : 0.0, n > 3 ? vals[3] : 0.0, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_u32(unsigned* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_u32, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_var(double* U, const double* facp, long long count, hipStream_t st) {
+  long long nb = (count + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  hipLaunchKernelGGL(k_scale, dim3((unsigned)nb), dim3(256), 0, st, U, facp, count);
+  return hipGetLastError();
+}
+
+}  // namespace amrv

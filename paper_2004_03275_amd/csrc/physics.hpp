@@ -1,0 +1,272 @@
+// physics.hpp -- device-side physics of the finite-volume update (gfx950, binary64).
+//
+// Hydrodynamics: U = (rho, rho v, E), E = rho v^2/2 + p/(gamma-1)
+// (arXiv 2004.03275, Sec. 1.1); primitive V = (rho, v, p) (Sec. 1.2,
+// phys_to_primitive / phys_to_conserved).  Ideal MHD (mu0 = 1) adds B and the
+// GLM scalar psi.  Fluxes: TVDLF (Rusanov), HLL, HLLC (Sec. 1.2, Sec. 2.4),
+// all with the textbook formulas; the expression order below is fixed so that
+// every result is reproducible bit for bit (built with -ffp-contract=off).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace amrv {
+
+enum { FLX_TVDLF = 0, FLX_HLL = 1, FLX_HLLC = 2 };
+enum { LIM_MINMOD = 0, LIM_VANLEER = 1 };
+
+struct PhysParams {
+  double gamma;
+  double gm1;   // gamma - 1
+  double igm1;  // 1 / (gamma - 1)
+  double ch;    // GLM cleaning speed (MHD)
+};
+
+template <int ND, bool MHD>
+struct Sys {
+  static constexpr int NV = MHD ? 3 + 2 * ND : 2 + ND;
+  static constexpr int IE = 1 + ND;   // energy / pressure
+  static constexpr int IB = 2 + ND;   // first magnetic component
+  static constexpr int IP = 2 + 2 * ND;  // psi
+};
+
+__device__ __forceinline__ double dmin(double a, double b) { return a < b ? a : b; }
+__device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
+
+// conserved -> primitive: 1/rho once, v = m * (1/rho),
+// p = (gamma-1) * ((E - (0.5*m.m)*(1/rho)) [- 0.5*B.B])
+template <int ND, bool MHD>
+__device__ __forceinline__ void cons2prim(const double* u, double* v, const PhysParams& P) {
+  using S = Sys<ND, MHD>;
+  const double rho = u[0];
+  const double inv = 1.0 / rho;
+  double mm = u[1] * u[1];
+  v[0] = rho;
+  v[1] = u[1] * inv;
+#pragma unroll
+  for (int d = 1; d < ND; d++) {
+    v[1 + d] = u[1 + d] * inv;
+    mm = mm + u[1 + d] * u[1 + d];
+  }
+  if constexpr (!MHD) {
+    v[S::IE] = P.gm1 * (u[S::IE] - 0.5 * mm * inv);
+  } else {
+    double bb = u[S::IB] * u[S::IB];
+    v[S::IB] = u[S::IB];
+#pragma unroll
+    for (int d = 1; d < ND; d++) {
+      bb = bb + u[S::IB + d] * u[S::IB + d];
+      v[S::IB + d] = u[S::IB + d];
+    }
+    v[S::IE] = P.gm1 * (u[S::IE] - 0.5 * mm * inv - 0.5 * bb);
+    v[S::IP] = u[S::IP];
+  }
+}
+
+// primitive -> conserved: m = rho v, E = p*(1/(gamma-1)) + (0.5*rho)*v.v [+ 0.5*B.B]
+template <int ND, bool MHD>
+__device__ __forceinline__ void prim2cons(const double* v, double* u, const PhysParams& P) {
+  using S = Sys<ND, MHD>;
+  const double rho = v[0];
+  double vv = v[1] * v[1];
+  u[0] = rho;
+  u[1] = rho * v[1];
+#pragma unroll
+  for (int d = 1; d < ND; d++) {
+    u[1 + d] = rho * v[1 + d];
+    vv = vv + v[1 + d] * v[1 + d];
+  }
+  if constexpr (!MHD) {
+    u[S::IE] = v[S::IE] * P.igm1 + 0.5 * rho * vv;
+  } else {
+    double bb = v[S::IB] * v[S::IB];
+    u[S::IB] = v[S::IB];
+#pragma unroll
+    for (int d = 1; d < ND; d++) {
+      bb = bb + v[S::IB + d] * v[S::IB + d];
+      u[S::IB + d] = v[S::IB + d];
+    }
+    u[S::IE] = v[S::IE] * P.igm1 + 0.5 * rho * vv + 0.5 * bb;
+    u[S::IP] = v[S::IP];
+  }
+}
+
+// physical flux normal to direction n (compile-time)
+template <int ND, bool MHD, int N>
+__device__ __forceinline__ void phys_flux(const double* v, const double* u, double* F) {
+  using S = Sys<ND, MHD>;
+  const double vn = v[1 + N];
+  const double p = v[S::IE];
+  F[0] = u[1 + N];
+  if constexpr (!MHD) {
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+      F[1 + d] = u[1 + d] * vn;
+      if (d == N) F[1 + d] = F[1 + d] + p;
+    }
+    F[S::IE] = (u[S::IE] + p) * vn;
+  } else {
+    const double* B = v + S::IB;
+    double bb = B[0] * B[0];
+    double vB = v[1] * B[0];
+#pragma unroll
+    for (int d = 1; d < ND; d++) {
+      bb = bb + B[d] * B[d];
+      vB = vB + v[1 + d] * B[d];
+    }
+    const double pt = p + 0.5 * bb;
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+      F[1 + d] = u[1 + d] * vn - B[d] * B[N];
+      if (d == N) F[1 + d] = F[1 + d] + pt;
+    }
+    F[S::IE] = (u[S::IE] + pt) * vn - B[N] * vB;
+#pragma unroll
+    for (int d = 0; d < ND; d++) F[S::IB + d] = (d == N) ? 0.0 : B[d] * vn - B[N] * v[1 + d];
+    F[S::IP] = 0.0;
+  }
+}
+
+// signal speed: sound speed sqrt((gamma*p)/rho), or the MHD fast speed along N
+template <int ND, bool MHD, int N>
+__device__ __forceinline__ double wave_speed(const double* v, const PhysParams& P) {
+  using S = Sys<ND, MHD>;
+  if constexpr (!MHD) {
+    return sqrt(P.gamma * v[S::IE] / v[0]);
+  } else {
+    const double irho = 1.0 / v[0];
+    double bb = v[S::IB] * v[S::IB];
+#pragma unroll
+    for (int d = 1; d < ND; d++) bb = bb + v[S::IB + d] * v[S::IB + d];
+    const double a2 = P.gamma * v[S::IE] * irho;
+    const double b2 = bb * irho;
+    const double bn2 = v[S::IB + N] * v[S::IB + N] * irho;
+    const double s = a2 + b2;
+    double disc = s * s - 4.0 * a2 * bn2;
+    if (!(disc > 0.0)) disc = 0.0;
+    return sqrt(0.5 * (s + sqrt(disc)));
+  }
+}
+
+// runtime-direction wrapper
+template <int ND, bool MHD>
+__device__ __forceinline__ double wave_speed_dir(const double* v, int n, const PhysParams& P) {
+  if (n == 0) return wave_speed<ND, MHD, 0>(v, P);
+  if constexpr (ND > 1) {
+    if (n == 1) return wave_speed<ND, MHD, (ND > 1 ? 1 : 0)>(v, P);
+  }
+  if constexpr (ND > 2) return wave_speed<ND, MHD, (ND > 2 ? 2 : 0)>(v, P);
+  return 0.0;
+}
+
+template <int LIM>
+__device__ __forceinline__ double limiter(double a, double b) {
+  if (a * b <= 0.0) return 0.0;
+  if constexpr (LIM == LIM_MINMOD) {
+    return fabs(a) < fabs(b) ? a : b;
+  } else {
+    return 2.0 * a * b / (a + b);
+  }
+}
+
+__device__ __forceinline__ double minmod(double a, double b) {
+  if (a * b <= 0.0) return 0.0;
+  return fabs(a) < fabs(b) ? a : b;
+}
+
+// Approximate Riemann flux normal to N from left/right primitive face states.
+// vl/vr are modified only for MHD (normal field replaced by the GLM value).
+template <int ND, bool MHD, int FLUX, int N>
+__device__ __forceinline__ void riemann(double* vl, double* vr, double* F, const PhysParams& P) {
+  using S = Sys<ND, MHD>;
+  constexpr int NV = S::NV;
+  double bns = 0.0, psis = 0.0;
+  if constexpr (MHD) {
+    constexpr int ib = S::IB + N, ip = S::IP;
+    bns = 0.5 * (vl[ib] + vr[ib]) - 0.5 * (vr[ip] - vl[ip]) / P.ch;
+    psis = 0.5 * (vl[ip] + vr[ip]) - 0.5 * P.ch * (vr[ib] - vl[ib]);
+    vl[ib] = bns;
+    vr[ib] = bns;
+  }
+  double ul[NV], ur[NV], fl[NV], fr[NV];
+  prim2cons<ND, MHD>(vl, ul, P);
+  prim2cons<ND, MHD>(vr, ur, P);
+  phys_flux<ND, MHD, N>(vl, ul, fl);
+  phys_flux<ND, MHD, N>(vr, ur, fr);
+  const double cl = wave_speed<ND, MHD, N>(vl, P);
+  const double cr = wave_speed<ND, MHD, N>(vr, P);
+  const double unl = vl[1 + N], unr = vr[1 + N];
+  if constexpr (FLUX == FLX_TVDLF) {
+    const double cmax = dmax(fabs(unl) + cl, fabs(unr) + cr);
+#pragma unroll
+    for (int k = 0; k < NV; k++) F[k] = 0.5 * ((fl[k] + fr[k]) - cmax * (ur[k] - ul[k]));
+  } else if constexpr (FLUX == FLX_HLL) {
+    const double sl = dmin(unl - cl, unr - cr);
+    const double sr = dmax(unl + cl, unr + cr);
+    if (sl >= 0.0) {
+#pragma unroll
+      for (int k = 0; k < NV; k++) F[k] = fl[k];
+    } else if (sr <= 0.0) {
+#pragma unroll
+      for (int k = 0; k < NV; k++) F[k] = fr[k];
+    } else {
+      const double ids = 1.0 / (sr - sl);
+#pragma unroll
+      for (int k = 0; k < NV; k++) F[k] = ((sr * fl[k] - sl * fr[k]) + (sl * sr) * (ur[k] - ul[k])) * ids;
+    }
+  } else {  // HLLC (hydrodynamics)
+    static_assert(!MHD, "HLLC is implemented for hydrodynamics only");
+    constexpr int ie = S::IE;
+    const double sl = dmin(unl - cl, unr - cr);
+    const double sr = dmax(unl + cl, unr + cr);
+    const double pl = vl[ie], pr = vr[ie];
+    const double rl = vl[0] * (sl - unl);
+    const double rr = vr[0] * (sr - unr);
+    const double sm = ((pr - pl) + unl * rl - unr * rr) / (rl - rr);
+    if (sl >= 0.0) {
+#pragma unroll
+      for (int k = 0; k < NV; k++) F[k] = fl[k];
+    } else if (sm >= 0.0 || sr > 0.0) {
+      const bool left = sm >= 0.0;
+      const double sk = left ? sl : sr;
+      const double rk = left ? rl : rr;
+      const double rhok = left ? vl[0] : vr[0];
+      const double unk = left ? unl : unr;
+      const double pk = left ? pl : pr;
+      const double coef = rk / (sk - sm);
+      double us[NV];
+      us[0] = coef;
+#pragma unroll
+      for (int d = 0; d < ND; d++) us[1 + d] = (d == N) ? coef * sm : coef * (left ? vl[1 + d] : vr[1 + d]);
+      const double Ek = left ? ul[ie] : ur[ie];
+      us[ie] = coef * (Ek / rhok + (sm - unk) * (sm + pk / rk));
+#pragma unroll
+      for (int k = 0; k < NV; k++) {
+        const double fk = left ? fl[k] : fr[k];
+        const double uk = left ? ul[k] : ur[k];
+        F[k] = fk + sk * (us[k] - uk);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < NV; k++) F[k] = fr[k];
+    }
+  }
+  if constexpr (MHD) {
+    F[S::IB + N] = psis;
+    F[S::IP] = P.ch * P.ch * bns;
+  }
+}
+
+// limited face states of a cell from its two neighbours along one direction:
+// hi = v0 + 0.5*phi (value at the cell's upper face), lo = v0 - 0.5*phi
+template <int NV, int LIM>
+__device__ __forceinline__ void muscl(const double* vm, const double* v0, const double* vp, double* lo, double* hi) {
+#pragma unroll
+  for (int k = 0; k < NV; k++) {
+    const double s = limiter<LIM>(v0[k] - vm[k], vp[k] - v0[k]);
+    hi[k] = v0[k] + 0.5 * s;
+    lo[k] = v0[k] - 0.5 * s;
+  }
+}
+
+}  // namespace amrv

@@ -1,0 +1,155 @@
+"""Python face of libamrv: a block forest whose state lives in HBM.
+
+PyTorch supplies the device workspace (one uint8 tensor) and the stream; every
+operation is a call through the C-ABI into the HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+
+class GpuForest:
+    """A forest on one GPU.  ``forest`` is a workloads.Forest (leaf list and
+    scheme); ``stream`` a torch.cuda.Stream (a new one by default)."""
+
+    def __init__(self, forest, device: str | torch.device = "cuda:0", stream: torch.cuda.Stream | None = None,
+                 config: N.Config | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("GpuForest needs a ROCm GPU (torch.cuda.is_available() is False)")
+        L = N.lib()
+        self.forest = forest
+        self.scheme = forest.scheme
+        self.device = torch.device(device)
+        self.cfg = config if config is not None else N.make_config(forest.scheme)
+        self._lev = np.ascontiguousarray(forest.level, dtype=np.int32)
+        self._ijk = np.ascontiguousarray(forest.ijk, dtype=np.int32)
+        nbytes = L.amrv_workspace_bytes(ctypes.byref(self.cfg), forest.n, self._lev.ctypes.data,
+                                        self._ijk.ctypes.data)
+        if nbytes == 0:
+            raise N.AmrvError(N.EINVAL, L.amrv_last_error().decode())
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+            self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self._h = ctypes.c_void_p()
+        N.check(L.amrv_forest_create(ctypes.byref(self.cfg), forest.n, self._lev.ctypes.data, self._ijk.ctypes.data,
+                                     ctypes.c_void_p(self.workspace.data_ptr()), int(nbytes),
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._h)))
+        self.nvar = L.amrv_nvar(self._h)
+        self.shape = forest.state_shape()
+        self.n_doubles = int(L.amrv_state_doubles(self._h))
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            N.lib().amrv_forest_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- state --------------------------------------------------------------
+    def set_state(self, U):
+        if isinstance(U, torch.Tensor) and U.is_cuda:
+            t = U.contiguous()
+            if t.dtype != torch.float64 or t.numel() != self.n_doubles:
+                raise ValueError("device state must be float64 with the forest's size")
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+            N.check(N.lib().amrv_set_state(self._h, ctypes.c_void_p(t.data_ptr()), self.n_doubles, 1))
+            self.synchronize()
+            return
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        if U.shape != tuple(self.shape):
+            raise ValueError(f"state shape {U.shape} != {tuple(self.shape)}")
+        N.check(N.lib().amrv_set_state(self._h, U.ctypes.data, U.size, 0))
+
+    def get_state(self) -> np.ndarray:
+        U = np.empty(self.shape, dtype=np.float64)
+        N.check(N.lib().amrv_get_state(self._h, U.ctypes.data, U.size, 0))
+        return U
+
+    def state_tensor(self) -> torch.Tensor:
+        """A device copy of the current state (float64, shape of the state)."""
+        t = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        N.check(N.lib().amrv_get_state(self._h, ctypes.c_void_p(t.data_ptr()), self.n_doubles, 1))
+        self.synchronize()
+        return t
+
+    # -- the method ---------------------------------------------------------
+    def max_dt(self) -> float:
+        dt = ctypes.c_double()
+        N.check(N.lib().amrv_max_dt(self._h, ctypes.byref(dt)))
+        return dt.value
+
+    @property
+    def glm_ch(self) -> float:
+        return float(N.lib().amrv_glm_ch(self._h))
+
+    def advance(self, dt: float):
+        N.check(N.lib().amrv_advance(self._h, float(dt)))
+
+    def flag_blocks(self, with_emax: bool = False, mode: int = N.FLAG_LOHNER):
+        flags = np.empty(self.forest.n, dtype=np.int8)
+        emax = np.empty(self.forest.n, dtype=np.float64)
+        N.check(N.lib().amrv_flag_blocks(self._h, int(mode), flags.ctypes.data, emax.ctypes.data))
+        return (flags, emax) if with_emax else flags
+
+    # -- scheduling ---------------------------------------------------------
+    def set_schedule(self, sched: int, xcd_remap: int = 1, persistent_wgs: int = 0):
+        N.check(N.lib().amrv_set_schedule(self._h, int(sched), int(xcd_remap), int(persistent_wgs)))
+
+    def get_schedule(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        N.check(N.lib().amrv_get_schedule(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def autotune(self, reps: int = 3):
+        N.check(N.lib().amrv_autotune(self._h, int(reps)))
+        return self.get_schedule()
+
+    def use_graph(self, enable: bool = True):
+        N.check(N.lib().amrv_use_graph(self._h, 1 if enable else 0))
+
+    def synchronize(self):
+        N.check(N.lib().amrv_synchronize(self._h))
+
+
+def run(forest, U0, *, t_end=None, steps=None, dts=None, schedule=None, graph=False, device="cuda:0"):
+    """Drive the GPU forest like oracle.run: free Courant steps to t_end, a
+    fixed step count, or a given dt sequence.  Returns (state, dts used)."""
+    g = GpuForest(forest, device=device)
+    if schedule is not None:
+        g.set_schedule(*schedule)
+    if graph:
+        g.use_graph(True)
+    g.set_state(U0)
+    used = []
+    if dts is not None:
+        for dt in dts:
+            g.max_dt()
+            g.advance(dt)
+            used.append(dt)
+    else:
+        t, n = 0.0, 0
+        while True:
+            if steps is not None and n >= steps:
+                break
+            dt = g.max_dt()
+            if t_end is not None:
+                if t >= t_end:
+                    break
+                dt = min(dt, t_end - t)
+            g.advance(dt)
+            used.append(dt)
+            t += dt
+            n += 1
+    U = g.get_state()
+    g.close()
+    return U, used
