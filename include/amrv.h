@@ -146,6 +146,16 @@ int amrv_autotune(amrv_forest* f, int32_t reps);
  * amrv_advance calls (enable != 0), or launch kernels directly (0). */
 int amrv_use_graph(amrv_forest* f, int32_t enable);
 
+/* Stage-kernel timing: with enable != 0, every batched stage-update launch
+ * is bracketed by HIP events on the forest's stream (graph replay is
+ * bypassed while enabled).  amrv_profile_read synchronises and returns the
+ * summed event time of those launches (ms), their count, and their
+ * algorithmic HBM bytes: per launch, the interior state read and written
+ * (2 passes in the first stage, 3 in later ones, nvar * 8 bytes per cell
+ * and pass).  Reading resets the counters. */
+int amrv_profile(amrv_forest* f, int32_t enable);
+int amrv_profile_read(amrv_forest* f, double* ms_total, int64_t* launches, double* bytes);
+
 int amrv_synchronize(amrv_forest* f);
 const char* amrv_last_error(void);
 

@@ -83,6 +83,9 @@ SIGNATURES = {
                            ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "amrv_autotune": ([P, ctypes.c_int32], ctypes.c_int),
     "amrv_use_graph": ([P, ctypes.c_int32], ctypes.c_int),
+    "amrv_profile": ([P, ctypes.c_int32], ctypes.c_int),
+    "amrv_profile_read": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                           ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "amrv_synchronize": ([P], ctypes.c_int),
     "amrv_last_error": ([], ctypes.c_char_p),
 }

@@ -99,6 +99,10 @@ struct amrv_forest {
   bool graph_on = false, graph_valid = false;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;  // recorded pairs
+  std::vector<hipEvent_t> ev_free;
+  double prof_bytes = 0.0;
 };
 
 namespace {
@@ -153,7 +157,25 @@ int enqueue_stage_update(amrv_forest* f, const StageArgs& a, int mode) {
   Sched s = make_sched(f, m == AMRV_SCHED_PERSISTENT ? 2 : 1, 0);
   if (t.nd == 1) s.xcd_remap = 0;
   if (m == AMRV_SCHED_PERSISTENT) s.counter = f->cnt + a.stage;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (f->prof) {
+    for (hipEvent_t* e : {&e0, &e1}) {
+      if (!f->ev_free.empty()) {
+        *e = f->ev_free.back();
+        f->ev_free.pop_back();
+      } else {
+        HIPCHK(hipEventCreate(e));
+      }
+    }
+    HIPCHK(hipEventRecord(e0, f->st));
+  }
   HIPCHK(launch_stage(f->geo, f->lc, a, f->pp, s, stage_grid(f, m), f->st));
+  if (f->prof) {
+    HIPCHK(hipEventRecord(e1, f->st));
+    f->ev.emplace_back(e0, e1);
+    const double passes = a.stage == 1 ? 2.0 : 3.0;
+    f->prof_bytes += passes * 8.0 * (double)t.nvar * (double)t.n * (double)t.ncell;
+  }
   return AMRV_OK;
 }
 
@@ -186,8 +208,8 @@ int enqueue_step(amrv_forest* f) {
 }
 
 void drop_graph(amrv_forest* f) {
-  if (f->gexec) hipGraphExecDestroy(f->gexec);
-  if (f->graph) hipGraphDestroy(f->graph);
+  if (f->gexec) (void)hipGraphExecDestroy(f->gexec);
+  if (f->graph) (void)hipGraphDestroy(f->graph);
   f->gexec = nullptr;
   f->graph = nullptr;
   f->graph_valid = false;
@@ -200,7 +222,7 @@ int capture_graph(amrv_forest* f) {
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(f->st, &g);
   if (rc) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return rc;
   }
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -348,7 +370,6 @@ int amrv_forest_create(const amrv_config* cfg, int64_t n, const int32_t* lev, co
 
 int amrv_forest_destroy(amrv_forest* f) {
   if (!f) return AMRV_OK;
-  if (f->st || true) hipStreamSynchronize(f->st);
   drop_graph(f);
   delete f;
   return AMRV_OK;
@@ -406,7 +427,7 @@ int amrv_advance(amrv_forest* f, double dt) {
   const double damp = f->cfg.physics == AMRV_MHD_GLM ? std::exp(-(dt * f->ch) / f->cfg.glm_cr) : 1.0;
   int rc = set_scalars(f, PP_DT, {dt, damp});
   if (rc) return rc;
-  if (f->graph_on) {
+  if (f->graph_on && !f->prof) {
     if (!f->graph_valid) {
       rc = capture_graph(f);
       if (rc) return rc;
@@ -483,12 +504,12 @@ int amrv_autotune(amrv_forest* f, int32_t reps) {
         hipError_t e = launch_reset_u32(f->cnt, 16, f->st);
         if (e != hipSuccess) rc = hip_fail(e, "reset");
       }
-      hipEventRecord(e0, f->st);
+      (void)hipEventRecord(e0, f->st);
       if (!rc) rc = enqueue_stage_update(f, a, c.sched);
-      hipEventRecord(e1, f->st);
-      hipEventSynchronize(e1);
+      (void)hipEventRecord(e1, f->st);
+      (void)hipEventSynchronize(e1);
       float ms = 0;
-      hipEventElapsedTime(&ms, e0, e1);
+      (void)hipEventElapsedTime(&ms, e0, e1);
       if (r) ts.push_back(ms);
     }
     if (rc) break;
@@ -499,8 +520,8 @@ int amrv_autotune(amrv_forest* f, int32_t reps) {
       bc = c;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   f->sched = bc.sched;
   f->xcd = bc.xcd;
   f->pwgs = bc.pwgs;
@@ -516,6 +537,31 @@ int amrv_use_graph(amrv_forest* f, int32_t enable) {
   if (enable && f->sched == AMRV_SCHED_PER_BLOCK) return fail(AMRV_EINVAL, "graphs replay the batched schedules only");
   f->graph_on = enable != 0;
   drop_graph(f);
+  return AMRV_OK;
+}
+
+int amrv_profile(amrv_forest* f, int32_t enable) {
+  if (!f) return fail(AMRV_EINVAL, "null forest");
+  f->prof = enable != 0;
+  return AMRV_OK;
+}
+
+int amrv_profile_read(amrv_forest* f, double* ms_total, int64_t* launches, double* bytes) {
+  if (!f || !ms_total || !launches || !bytes) return fail(AMRV_EINVAL, "null argument");
+  HIPCHK(hipStreamSynchronize(f->st));
+  double tot = 0.0;
+  for (auto& pr : f->ev) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+    tot += ms;
+    f->ev_free.push_back(pr.first);
+    f->ev_free.push_back(pr.second);
+  }
+  *ms_total = tot;
+  *launches = (int64_t)f->ev.size();
+  *bytes = f->prof_bytes;
+  f->ev.clear();
+  f->prof_bytes = 0.0;
   return AMRV_OK;
 }
 

@@ -117,6 +117,15 @@ class GpuForest:
     def use_graph(self, enable: bool = True):
         N.check(N.lib().amrv_use_graph(self._h, 1 if enable else 0))
 
+    def profile(self, enable: bool = True):
+        N.check(N.lib().amrv_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(summed stage-kernel ms, launches, algorithmic bytes) since the last read."""
+        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        N.check(N.lib().amrv_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
+        return ms.value, n.value, b.value
+
     def synchronize(self):
         N.check(N.lib().amrv_synchronize(self._h))
 
