@@ -310,21 +310,60 @@ __device__ __forceinline__ double combine(int stage, int rk, double un, double t
   return (1.0 / 3.0) * un + (2.0 / 3.0) * tmp;
 }
 
+template <int NV>
+__device__ __forceinline__ void load_strided(const double* __restrict__ p, size_t vs, double* u) {
+#pragma unroll
+  for (int v = 0; v < NV; v++) u[v] = p[v * vs];
+}
+
+// Stage update of 16^2 / 16^3 leaves.  One 256-thread workgroup owns a leaf;
+// thread (tx, ty) owns the z-column of cells (tx, ty, *).  Per z-plane:
+//   (1) z direction in registers: slope of cell k+1, flux of face k+1/2;
+//   (2) the plane's primitive values (plus the 2-cell x/y ghost ring) to LDS;
+//   (3) limited slopes of all cells of the plane along x and y (LDS);
+//   (4) x and y face fluxes from the slopes (LDS);
+//   (5) flux divergence, summed x, y, z, and the SSP combination.
+// Global loads are issued one phase or one plane ahead of their use, so the
+// memory latency overlaps the FP64 work of the current plane.
 template <int ND, bool MHD, int FLUX, int LIM>
 __global__ void __launch_bounds__(WGS) k_stage_tile(Geo g, StageArgs a, const double* __restrict__ pp, Sched sc) {
   using S = Sys<ND, MHD>;
   constexpr int NV = S::NV;
   constexpr int PW = NB + 4;
   constexpr int NZ = ND == 3 ? NB : 1;
+  constexpr int NSX = NB * 18;  // x slopes: 16 rows x cells -1..16, [row][cell+1]
+  constexpr int NFX = NB * 17;  // x faces: 16 rows x faces 0..16, [row][face]
   __shared__ double sP[NV][PW * PW];  // primitive plane incl. x/y ghost ring, (y+2)*PW + x+2
-  __shared__ double sL[NV][NB * 18];  // upper-face states per row, cell index + 1
-  __shared__ double sR[NV][NB * 18];  // lower-face states
-  __shared__ double sF[NV][NB * 17];  // face fluxes per row
+  __shared__ double sSx[NV][NSX];
+  __shared__ double sSy[NV][NSX];     // y slopes, [cell+1][column]
+  __shared__ double sFx[NV][NFX];
+  __shared__ double sFy[NV][NFX];     // y faces, [face][column]
   __shared__ int sLeaf;
 
   const PhysParams P = load_phys(pp);
   const double dt = pp[PP_DT];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const size_t vs = (size_t)g.n * g.ncell;  // variable stride of the state
+
+  // ring cell of this thread (tid < 128): x ring then y ring
+  int rx = 0, ry = 0, rface = 0, rlayer = 0, ra1 = 0;
+  if (tid < 64) {
+    const int c = tid >> 4;
+    ry = tid & 15;
+    rx = c < 2 ? c - 2 : 14 + c;
+    rface = rx < 0 ? 0 : 1;
+    rlayer = rx < 0 ? -1 - rx : rx - NB;
+    ra1 = ry;
+  } else if (tid < 128) {
+    const int u = tid - 64, c = u >> 4;
+    rx = u & 15;
+    ry = c < 2 ? c - 2 : 14 + c;
+    rface = ry < 0 ? 2 : 3;
+    rlayer = ry < 0 ? -1 - ry : ry - NB;
+    ra1 = rx;
+  }
+  const bool ring = tid < 128;
+  const int rdst = (ry + 2) * PW + rx + 2;
 
   for (int iter = 0;; iter++) {
     int leaf;
@@ -345,33 +384,64 @@ __global__ void __launch_bounds__(WGS) k_stage_tile(Geo g, StageArgs a, const do
 #pragma unroll
     for (int f = 0; f < 2 * ND; f++) kinds[f] = g.kind[leaf * 6 + f];
 
-    // ring cell handled by this thread (tid < 128)
-    int rx = 0, ry = 0, rface = 0, rlayer = 0, ra1 = 0;
-    if (tid < 64) {
-      const int c = tid >> 4;
-      ry = tid & 15;
-      rx = c < 2 ? c - 2 : 14 + c;
-      rface = rx < 0 ? 0 : 1;
-      rlayer = rx < 0 ? -1 - rx : rx - NB;
-      ra1 = ry;
-    } else if (tid < 128) {
-      const int u = tid - 64, c = u >> 4;
-      rx = u & 15;
-      ry = c < 2 ? c - 2 : 14 + c;
-      rface = ry < 0 ? 2 : 3;
-      rlayer = ry < 0 ? -1 - ry : ry - NB;
-      ra1 = rx;
+    const size_t col = (size_t)leaf * g.ncell + tx + NB * ty;
+    const double* own = a.Uin + col;   // var 0 of cell (tx, ty, 0); plane stride NB*NB
+    const double* ownn = a.Un + col;
+    double* out = a.Uout + col;
+
+    // source of this thread's ring cell: var 0 at plane 0, plane and var strides
+    const double* rptr = a.Uin;
+    int rks = 0;
+    size_t rvs = vs;
+    if (ring) {
+      const int kd = kinds[rface];
+      const int d = rface >> 1, hi = rface & 1;
+      if (kd == NB_SAME || kd == NB_BND) {
+        const int src = g.nbr[leaf * 6 + rface];
+        const int along = kd == NB_SAME ? (hi ? rlayer : NB - 1 - rlayer) : (hi ? NB - 1 : 0);
+        const int cell0 = d == 0 ? along + NB * ra1 : ra1 + NB * along;
+        rptr = a.Uin + (size_t)src * g.ncell + cell0;
+        rks = NB * NB;
+        rvs = vs;
+      } else {
+        const int sl = g.slot[leaf * 6 + rface];
+        rptr = g.G + (size_t)sl * NV * 2 * g.T + (size_t)rlayer * g.T + ra1;
+        rks = NB;
+        rvs = 2 * (size_t)g.T;
+      }
     }
 
-    double q0[NV], q1[NV], VLz[NV], Flo[NV];
+    // +z face source of this thread's column (ghost planes 16, 17)
+    const double* zptr = a.Uin;
+    int zls = 0;
+    size_t zvs = vs;
     if constexpr (ND == 3) {
-      double vm2[NV], vm1[NV], lo[NV], hi[NV], vlm1[NV];
+      const int kd = kinds[5];
+      if (kd == NB_SAME) {
+        zptr = a.Uin + (size_t)g.nbr[leaf * 6 + 5] * g.ncell + tx + NB * ty;
+        zls = NB * NB;
+      } else if (kd == NB_BND) {
+        zptr = own + (NB - 1) * NB * NB;
+        zls = 0;
+      } else {
+        zptr = g.G + (size_t)g.slot[leaf * 6 + 5] * NV * 2 * g.T + tx + NB * ty;
+        zls = g.T;
+        zvs = 2 * (size_t)g.T;
+      }
+    }
+
+    double V0[NV], V1[NV], C2[NV], VLz[NV], Flo[NV], Cr[NV];
+    if constexpr (ND == 3) {
+      double vm2[NV], vm1[NV], c[NV], lo[NV], hi[NV], vlm1[NV];
       own_prim<ND, MHD>(g, a.Uin, leaf, tx, ty, -2, vm2, P);
       own_prim<ND, MHD>(g, a.Uin, leaf, tx, ty, -1, vm1, P);
-      own_prim<ND, MHD>(g, a.Uin, leaf, tx, ty, 0, q0, P);
-      own_prim<ND, MHD>(g, a.Uin, leaf, tx, ty, 1, q1, P);
-      muscl<NV, LIM>(vm2, vm1, q0, lo, vlm1);
-      muscl<NV, LIM>(vm1, q0, q1, lo, hi);
+      load_strided<NV>(own, vs, c);
+      cons2prim<ND, MHD>(c, V0, P);
+      load_strided<NV>(own + NB * NB, vs, c);
+      cons2prim<ND, MHD>(c, V1, P);
+      load_strided<NV>(own + 2 * NB * NB, vs, C2);
+      muscl<NV, LIM>(vm2, vm1, V0, lo, vlm1);
+      muscl<NV, LIM>(vm1, V0, V1, lo, hi);
       if (kinds[4] == NB_SAME || kinds[4] == NB_BND) {
         riemann<ND, MHD, FLUX, (ND == 3 ? 2 : 0)>(vlm1, lo, Flo, P);
       } else {
@@ -379,140 +449,137 @@ __global__ void __launch_bounds__(WGS) k_stage_tile(Geo g, StageArgs a, const do
       }
 #pragma unroll
       for (int v = 0; v < NV; v++) VLz[v] = hi[v];
+    } else {
+      double c[NV];
+      load_strided<NV>(own, vs, c);
+      cons2prim<ND, MHD>(c, V0, P);
     }
+    if (ring) load_strided<NV>(rptr, rvs, Cr);
 
     for (int k = 0; k < NZ; k++) {
-      double Fhi[NV], VLn[NV];
+      double zd[NV];
       if constexpr (ND == 3) {
-        double q2[NV], VRn[NV];
-        own_prim<ND, MHD>(g, a.Uin, leaf, tx, ty, k + 2, q2, P);
-        muscl<NV, LIM>(q0, q1, q2, VRn, VLn);
+        // (1) z direction: prefetched plane k+2, slope of cell k+1, face k+1/2
+        double V2[NV], VR1[NV], VL1[NV], Fhi[NV];
+        cons2prim<ND, MHD>(C2, V2, P);
+        const int pn = k + 3;
+        if (pn < NB)
+          load_strided<NV>(own + pn * NB * NB, vs, C2);
+        else if (pn < NB + 2)
+          load_strided<NV>(zptr + (pn - NB) * zls, zvs, C2);
+        muscl<NV, LIM>(V0, V1, V2, VR1, VL1);
         if (k == NB - 1 && !(kinds[5] == NB_SAME || kinds[5] == NB_BND)) {
           cf_flux<NV, ND>(g, leaf, 5, kinds[5], tx, ty, Fhi);
         } else {
-          double vl[NV];
-#pragma unroll
-          for (int v = 0; v < NV; v++) vl[v] = VLz[v];
-          riemann<ND, MHD, FLUX, (ND == 3 ? 2 : 0)>(vl, VRn, Fhi, P);
+          riemann<ND, MHD, FLUX, (ND == 3 ? 2 : 0)>(VLz, VR1, Fhi, P);
         }
 #pragma unroll
         for (int v = 0; v < NV; v++) {
-          sP[v][(ty + 2) * PW + tx + 2] = q0[v];
-          q0[v] = q1[v];
-          q1[v] = q2[v];
+          zd[v] = (Fhi[v] - Flo[v]) * rdz;
+          Flo[v] = Fhi[v];
+          VLz[v] = VL1[v];
+        }
+        // (2) plane k to LDS; V1, V2 move down the queue
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+          sP[v][(ty + 2) * PW + tx + 2] = V0[v];
+          V0[v] = V1[v];
+          V1[v] = V2[v];
         }
       } else {
-        double own[NV];
-        own_prim<ND, MHD>(g, a.Uin, leaf, tx, ty, 0, own, P);
 #pragma unroll
-        for (int v = 0; v < NV; v++) sP[v][(ty + 2) * PW + tx + 2] = own[v];
+        for (int v = 0; v < NV; v++) sP[v][(ty + 2) * PW + tx + 2] = V0[v];
       }
-      if (tid < 128) {
-        double u[NV], w[NV];
-        ghost_cons<NV>(g, a.Uin, leaf, rface, rlayer, ra1, k, u);
-        cons2prim<ND, MHD>(u, w, P);
+      if (ring) {
+        double w[NV];
+        cons2prim<ND, MHD>(Cr, w, P);
 #pragma unroll
-        for (int v = 0; v < NV; v++) sP[v][(ry + 2) * PW + rx + 2] = w[v];
+        for (int v = 0; v < NV; v++) sP[v][rdst] = w[v];
+        if (k + 1 < NZ) load_strided<NV>(rptr + (k + 1) * rks, rvs, Cr);
+      }
+      // operands of this plane's update, consumed after the flux phase
+      double Ui[NV], Uo[NV];
+      load_strided<NV>(own + k * NB * NB, vs, Ui);
+      if (a.stage > 1) load_strided<NV>(ownn + k * NB * NB, vs, Uo);
+      __syncthreads();
+
+      // (3) slopes along x (rows y) and y (columns x)
+      for (int t = tid; t < 2 * NSX; t += WGS) {
+        const bool yd = t >= NSX;
+        const int u = yd ? t - NSX : t;
+        int b, st;
+        if (!yd) {
+          const int r = u / 18, c = u % 18 - 1;
+          b = (r + 2) * PW + c + 2;
+          st = 1;
+        } else {
+          const int c = u / NB - 1, r = u % NB;
+          b = (c + 2) * PW + r + 2;
+          st = PW;
+        }
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+          const double vm = sP[v][b - st], v0 = sP[v][b], vp = sP[v][b + st];
+          const double sl = limiter<LIM>(v0 - vm, vp - v0);
+          if (!yd)
+            sSx[v][u] = sl;
+          else
+            sSy[v][u] = sl;
+        }
       }
       __syncthreads();
 
-      // ---- x direction: rows are y
-      for (int t = tid; t < NB * 18; t += WGS) {
-        const int r = t / 18, c = t % 18 - 1;
-        const int b = (r + 2) * PW + c + 2;
-        double vm[NV], v0[NV], vp[NV], lo[NV], hi[NV];
-#pragma unroll
-        for (int v = 0; v < NV; v++) {
-          vm[v] = sP[v][b - 1];
-          v0[v] = sP[v][b];
-          vp[v] = sP[v][b + 1];
-        }
-        muscl<NV, LIM>(vm, v0, vp, lo, hi);
-#pragma unroll
-        for (int v = 0; v < NV; v++) {
-          sL[v][r * 18 + c + 1] = hi[v];
-          sR[v][r * 18 + c + 1] = lo[v];
-        }
-      }
-      __syncthreads();
-      for (int t = tid; t < NB * 17; t += WGS) {
-        const int r = t / 17, m = t % 17;
+      // (4) face fluxes along x and y
+      for (int t = tid; t < 2 * NFX; t += WGS) {
+        const bool yd = t >= NFX;
+        const int u = yd ? t - NFX : t;
         double F[NV];
-        const int bf = m == 0 ? 0 : (m == NB ? 1 : -1);
-        if (bf >= 0 && !(kinds[bf] == NB_SAME || kinds[bf] == NB_BND)) {
-          cf_flux<NV, ND>(g, leaf, bf, kinds[bf], r, k, F);
-        } else {
-          double vl[NV], vr[NV];
+        if (!yd) {
+          const int r = u / 17, m = u % 17;
+          const int bf = m == 0 ? 0 : (m == NB ? 1 : -1);
+          if (bf >= 0 && !(kinds[bf] == NB_SAME || kinds[bf] == NB_BND)) {
+            cf_flux<NV, ND>(g, leaf, bf, kinds[bf], r, k, F);
+          } else {
+            double vl[NV], vr[NV];
+            const int bl = (r + 2) * PW + m + 1;
 #pragma unroll
-          for (int v = 0; v < NV; v++) {
-            vl[v] = sL[v][r * 18 + m];
-            vr[v] = sR[v][r * 18 + m + 1];
+            for (int v = 0; v < NV; v++) {
+              vl[v] = sP[v][bl] + 0.5 * sSx[v][r * 18 + m];
+              vr[v] = sP[v][bl + 1] - 0.5 * sSx[v][r * 18 + m + 1];
+            }
+            riemann<ND, MHD, FLUX, 0>(vl, vr, F, P);
           }
-          riemann<ND, MHD, FLUX, 0>(vl, vr, F, P);
-        }
 #pragma unroll
-        for (int v = 0; v < NV; v++) sF[v][r * 17 + m] = F[v];
+          for (int v = 0; v < NV; v++) sFx[v][u] = F[v];
+        } else {
+          const int m = u / NB, r = u % NB;
+          const int bf = m == 0 ? 2 : (m == NB ? 3 : -1);
+          if (bf >= 0 && !(kinds[bf] == NB_SAME || kinds[bf] == NB_BND)) {
+            cf_flux<NV, ND>(g, leaf, bf, kinds[bf], r, k, F);
+          } else {
+            double vl[NV], vr[NV];
+            const int bl = (m + 1) * PW + r + 2;
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+              vl[v] = sP[v][bl] + 0.5 * sSy[v][m * NB + r];
+              vr[v] = sP[v][bl + PW] - 0.5 * sSy[v][(m + 1) * NB + r];
+            }
+            riemann<ND, MHD, FLUX, 1>(vl, vr, F, P);
+          }
+#pragma unroll
+          for (int v = 0; v < NV; v++) sFy[v][u] = F[v];
+        }
       }
       __syncthreads();
-      double acc[NV];
-#pragma unroll
-      for (int v = 0; v < NV; v++) acc[v] = (sF[v][ty * 17 + tx + 1] - sF[v][ty * 17 + tx]) * rdx;
 
-      // ---- y direction: rows are x
-      for (int t = tid; t < NB * 18; t += WGS) {
-        const int r = t / 18, c = t % 18 - 1;
-        const int b = (c + 2) * PW + r + 2;
-        double vm[NV], v0[NV], vp[NV], lo[NV], hi[NV];
-#pragma unroll
-        for (int v = 0; v < NV; v++) {
-          vm[v] = sP[v][b - PW];
-          v0[v] = sP[v][b];
-          vp[v] = sP[v][b + PW];
-        }
-        muscl<NV, LIM>(vm, v0, vp, lo, hi);
-#pragma unroll
-        for (int v = 0; v < NV; v++) {
-          sL[v][r * 18 + c + 1] = hi[v];
-          sR[v][r * 18 + c + 1] = lo[v];
-        }
-      }
-      __syncthreads();
-      for (int t = tid; t < NB * 17; t += WGS) {
-        const int r = t / 17, m = t % 17;
-        double F[NV];
-        const int bf = m == 0 ? 2 : (m == NB ? 3 : -1);
-        if (bf >= 0 && !(kinds[bf] == NB_SAME || kinds[bf] == NB_BND)) {
-          cf_flux<NV, ND>(g, leaf, bf, kinds[bf], r, k, F);
-        } else {
-          double vl[NV], vr[NV];
-#pragma unroll
-          for (int v = 0; v < NV; v++) {
-            vl[v] = sL[v][r * 18 + m];
-            vr[v] = sR[v][r * 18 + m + 1];
-          }
-          riemann<ND, MHD, FLUX, 1>(vl, vr, F, P);
-        }
-#pragma unroll
-        for (int v = 0; v < NV; v++) sF[v][r * 17 + m] = F[v];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int v = 0; v < NV; v++) acc[v] = acc[v] + (sF[v][tx * 17 + ty + 1] - sF[v][tx * 17 + ty]) * rdy;
-      if constexpr (ND == 3) {
-#pragma unroll
-        for (int v = 0; v < NV; v++) {
-          acc[v] = acc[v] + (Fhi[v] - Flo[v]) * rdz;
-          Flo[v] = Fhi[v];
-          VLz[v] = VLn[v];
-        }
-      }
-      const int cell = tx + NB * (ty + NB * k);
+      // (5) divergence (x, then y, then z) and the SSP combination
 #pragma unroll
       for (int v = 0; v < NV; v++) {
-        const size_t id = uidx(g, v, leaf, cell);
-        const double tmp = a.Uin[id] - dt * acc[v];
-        const double un = a.stage == 1 ? 0.0 : a.Un[id];
-        a.Uout[id] = combine<NV>(a.stage, a.rk, un, tmp);
+        double acc = (sFx[v][ty * 17 + tx + 1] - sFx[v][ty * 17 + tx]) * rdx;
+        acc = acc + (sFy[v][(ty + 1) * NB + tx] - sFy[v][ty * NB + tx]) * rdy;
+        if constexpr (ND == 3) acc = acc + zd[v];
+        const double tmp = Ui[v] - dt * acc;
+        out[v * vs + (size_t)k * NB * NB] = combine<NV>(a.stage, a.rk, a.stage > 1 ? Uo[v] : 0.0, tmp);
       }
     }
   }

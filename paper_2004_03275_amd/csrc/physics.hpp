@@ -174,86 +174,99 @@ __device__ __forceinline__ double minmod(double a, double b) {
   return fabs(a) < fabs(b) ? a : b;
 }
 
+// HLLC flux (hydrodynamics) normal to N.  Every branch needs the conserved
+// state and physical flux of one side only (F_L and F*_L use the left state,
+// F*_R and F_R the right one), so the side is chosen first from the wave
+// speeds and only its state and flux are formed.  The arithmetic of each
+// quantity is the textbook one in a fixed order.
+template <int ND, int N>
+__device__ __forceinline__ void hllc_flux(const double* vl, const double* vr, double* F, const PhysParams& P) {
+  using S = Sys<ND, false>;
+  constexpr int NV = S::NV, ie = S::IE;
+  const double cl = wave_speed<ND, false, N>(vl, P);
+  const double cr = wave_speed<ND, false, N>(vr, P);
+  const double unl = vl[1 + N], unr = vr[1 + N];
+  const double sl = dmin(unl - cl, unr - cr);
+  const double sr = dmax(unl + cl, unr + cr);
+  const double pl = vl[ie], pr = vr[ie];
+  const double rl = vl[0] * (sl - unl);
+  const double rr = vr[0] * (sr - unr);
+  const double sm = ((pr - pl) + unl * rl - unr * rr) / (rl - rr);
+  const bool left = sl >= 0.0 || sm >= 0.0;
+  const bool star = !(sl >= 0.0) && (sm >= 0.0 || sr > 0.0);
+  double vk[NV];
+#pragma unroll
+  for (int k = 0; k < NV; k++) vk[k] = left ? vl[k] : vr[k];
+  double uk[NV], fk[NV];
+  prim2cons<ND, false>(vk, uk, P);
+  phys_flux<ND, false, N>(vk, uk, fk);
+  if (star) {
+    const double sk = left ? sl : sr;
+    const double rk = left ? rl : rr;
+    const double coef = rk / (sk - sm);
+    double us[NV];
+    us[0] = coef;
+#pragma unroll
+    for (int d = 0; d < ND; d++) us[1 + d] = (d == N) ? coef * sm : coef * vk[1 + d];
+    us[ie] = coef * (uk[ie] / vk[0] + (sm - vk[1 + N]) * (sm + vk[ie] / rk));
+#pragma unroll
+    for (int k = 0; k < NV; k++) F[k] = fk[k] + sk * (us[k] - uk[k]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < NV; k++) F[k] = fk[k];
+  }
+}
+
 // Approximate Riemann flux normal to N from left/right primitive face states.
 // vl/vr are modified only for MHD (normal field replaced by the GLM value).
 template <int ND, bool MHD, int FLUX, int N>
 __device__ __forceinline__ void riemann(double* vl, double* vr, double* F, const PhysParams& P) {
   using S = Sys<ND, MHD>;
   constexpr int NV = S::NV;
-  double bns = 0.0, psis = 0.0;
-  if constexpr (MHD) {
-    constexpr int ib = S::IB + N, ip = S::IP;
-    bns = 0.5 * (vl[ib] + vr[ib]) - 0.5 * (vr[ip] - vl[ip]) / P.ch;
-    psis = 0.5 * (vl[ip] + vr[ip]) - 0.5 * P.ch * (vr[ib] - vl[ib]);
-    vl[ib] = bns;
-    vr[ib] = bns;
-  }
-  double ul[NV], ur[NV], fl[NV], fr[NV];
-  prim2cons<ND, MHD>(vl, ul, P);
-  prim2cons<ND, MHD>(vr, ur, P);
-  phys_flux<ND, MHD, N>(vl, ul, fl);
-  phys_flux<ND, MHD, N>(vr, ur, fr);
-  const double cl = wave_speed<ND, MHD, N>(vl, P);
-  const double cr = wave_speed<ND, MHD, N>(vr, P);
-  const double unl = vl[1 + N], unr = vr[1 + N];
-  if constexpr (FLUX == FLX_TVDLF) {
-    const double cmax = dmax(fabs(unl) + cl, fabs(unr) + cr);
-#pragma unroll
-    for (int k = 0; k < NV; k++) F[k] = 0.5 * ((fl[k] + fr[k]) - cmax * (ur[k] - ul[k]));
-  } else if constexpr (FLUX == FLX_HLL) {
-    const double sl = dmin(unl - cl, unr - cr);
-    const double sr = dmax(unl + cl, unr + cr);
-    if (sl >= 0.0) {
-#pragma unroll
-      for (int k = 0; k < NV; k++) F[k] = fl[k];
-    } else if (sr <= 0.0) {
-#pragma unroll
-      for (int k = 0; k < NV; k++) F[k] = fr[k];
-    } else {
-      const double ids = 1.0 / (sr - sl);
-#pragma unroll
-      for (int k = 0; k < NV; k++) F[k] = ((sr * fl[k] - sl * fr[k]) + (sl * sr) * (ur[k] - ul[k])) * ids;
-    }
-  } else {  // HLLC (hydrodynamics)
+  if constexpr (FLUX == FLX_HLLC) {
     static_assert(!MHD, "HLLC is implemented for hydrodynamics only");
-    constexpr int ie = S::IE;
-    const double sl = dmin(unl - cl, unr - cr);
-    const double sr = dmax(unl + cl, unr + cr);
-    const double pl = vl[ie], pr = vr[ie];
-    const double rl = vl[0] * (sl - unl);
-    const double rr = vr[0] * (sr - unr);
-    const double sm = ((pr - pl) + unl * rl - unr * rr) / (rl - rr);
-    if (sl >= 0.0) {
-#pragma unroll
-      for (int k = 0; k < NV; k++) F[k] = fl[k];
-    } else if (sm >= 0.0 || sr > 0.0) {
-      const bool left = sm >= 0.0;
-      const double sk = left ? sl : sr;
-      const double rk = left ? rl : rr;
-      const double rhok = left ? vl[0] : vr[0];
-      const double unk = left ? unl : unr;
-      const double pk = left ? pl : pr;
-      const double coef = rk / (sk - sm);
-      double us[NV];
-      us[0] = coef;
-#pragma unroll
-      for (int d = 0; d < ND; d++) us[1 + d] = (d == N) ? coef * sm : coef * (left ? vl[1 + d] : vr[1 + d]);
-      const double Ek = left ? ul[ie] : ur[ie];
-      us[ie] = coef * (Ek / rhok + (sm - unk) * (sm + pk / rk));
-#pragma unroll
-      for (int k = 0; k < NV; k++) {
-        const double fk = left ? fl[k] : fr[k];
-        const double uk = left ? ul[k] : ur[k];
-        F[k] = fk + sk * (us[k] - uk);
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < NV; k++) F[k] = fr[k];
+    hllc_flux<ND, N>(vl, vr, F, P);
+    return;
+  } else {
+    double bns = 0.0, psis = 0.0;
+    if constexpr (MHD) {
+      constexpr int ib = S::IB + N, ip = S::IP;
+      bns = 0.5 * (vl[ib] + vr[ib]) - 0.5 * (vr[ip] - vl[ip]) / P.ch;
+      psis = 0.5 * (vl[ip] + vr[ip]) - 0.5 * P.ch * (vr[ib] - vl[ib]);
+      vl[ib] = bns;
+      vr[ib] = bns;
     }
-  }
-  if constexpr (MHD) {
-    F[S::IB + N] = psis;
-    F[S::IP] = P.ch * P.ch * bns;
+    double ul[NV], ur[NV], fl[NV], fr[NV];
+    prim2cons<ND, MHD>(vl, ul, P);
+    prim2cons<ND, MHD>(vr, ur, P);
+    phys_flux<ND, MHD, N>(vl, ul, fl);
+    phys_flux<ND, MHD, N>(vr, ur, fr);
+    const double cl = wave_speed<ND, MHD, N>(vl, P);
+    const double cr = wave_speed<ND, MHD, N>(vr, P);
+    const double unl = vl[1 + N], unr = vr[1 + N];
+    if constexpr (FLUX == FLX_TVDLF) {
+      const double cmax = dmax(fabs(unl) + cl, fabs(unr) + cr);
+#pragma unroll
+      for (int k = 0; k < NV; k++) F[k] = 0.5 * ((fl[k] + fr[k]) - cmax * (ur[k] - ul[k]));
+    } else {
+      const double sl = dmin(unl - cl, unr - cr);
+      const double sr = dmax(unl + cl, unr + cr);
+      if (sl >= 0.0) {
+#pragma unroll
+        for (int k = 0; k < NV; k++) F[k] = fl[k];
+      } else if (sr <= 0.0) {
+#pragma unroll
+        for (int k = 0; k < NV; k++) F[k] = fr[k];
+      } else {
+        const double ids = 1.0 / (sr - sl);
+#pragma unroll
+        for (int k = 0; k < NV; k++) F[k] = ((sr * fl[k] - sl * fr[k]) + (sl * sr) * (ur[k] - ul[k])) * ids;
+      }
+    }
+    if constexpr (MHD) {
+      F[S::IB + N] = psis;
+      F[S::IP] = P.ch * P.ch * bns;
+    }
   }
 }
 
