@@ -62,6 +62,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay each step as a HIP graph")
+    ap.add_argument("--schedule", default=None,
+                    help="fixed schedule instead of autotuning: grid, grid-noremap or persistent:<workgroups>")
+    ap.add_argument("--variant", type=int, default=None, help="force the stage-kernel variant (0 or 1)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -116,12 +121,36 @@ def main():
         del G1, R1
         g.set_state(U0)
 
+    if args.copy_calibration_mib > 0:
+        nel = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration_mib} MiB read + written")
+        del src, dst
+
     sched = None
-    if not args.no_autotune:
+    if args.schedule:
+        if args.schedule == "grid":
+            g.set_schedule(N.SCHED_GRID, 1, 0)
+        elif args.schedule == "grid-noremap":
+            g.set_schedule(N.SCHED_GRID, 0, 0)
+        elif args.schedule.startswith("persistent"):
+            wgs = int(args.schedule.split(":")[1]) if ":" in args.schedule else 0
+            g.set_schedule(N.SCHED_PERSISTENT, 0, wgs)
+        else:
+            raise SystemExit(f"unknown schedule {args.schedule}")
+        sched = (*g.get_schedule(), g.get_variant())
+    elif not args.no_autotune:
         sched = g.autotune(3)
         log(f"autotuned schedule {sched}")
     else:
-        sched = g.get_schedule()
+        sched = (*g.get_schedule(), g.get_variant())
+    if args.variant is not None:
+        g.set_variant(args.variant)
+        sched = (*sched[:3], args.variant)
     if args.graph:
         g.use_graph(True)
 
@@ -196,7 +225,8 @@ def main():
             "gamma": s.gamma,
             "cfl": s.cfl,
             "flag_every": args.flag_every,
-            "schedule": {"mode": names[sched[0]], "xcd_remap": sched[1], "persistent_wgs": sched[2]},
+            "schedule": {"mode": names[sched[0]], "xcd_remap": sched[1], "persistent_wgs": sched[2],
+                         "stage_kernel_variant": ["combined_xy", "split_xy"][sched[3]]},
             "graph": bool(args.graph),
         },
         "roofline": {

@@ -138,8 +138,15 @@ int amrv_flag_blocks(amrv_forest* f, int32_t mode, int8_t* flags_out, double* em
 int amrv_set_schedule(amrv_forest* f, int32_t sched, int32_t xcd_remap, int32_t persistent_wgs);
 int amrv_get_schedule(const amrv_forest* f, int32_t* sched, int32_t* xcd_remap, int32_t* persistent_wgs);
 
-/* Time the candidate schedules on the current state (first-stage kernel,
- * state unchanged) and keep the fastest.  Synchronises. */
+/* Stage-kernel variant for 2D/3D leaves: 0 = x and y share the slope and
+ * flux phases (fewer barriers, more LDS), 1 = x then y through one set of
+ * LDS arrays (less LDS, more workgroups per compute unit).  Both give
+ * identical results. */
+int amrv_set_variant(amrv_forest* f, int32_t variant);
+int amrv_get_variant(const amrv_forest* f, int32_t* variant);
+
+/* Time the candidate schedules and kernel variants on the current state
+ * (first-stage kernel, state unchanged) and keep the fastest.  Synchronises. */
 int amrv_autotune(amrv_forest* f, int32_t reps);
 
 /* Capture one advance step in a HIP graph and replay it on later

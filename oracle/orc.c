@@ -328,11 +328,17 @@ static void riemann(const orc_forest* f, const double* vl_in, const double* vr_i
       const double* fk = left ? fl : fr;
       double sk = left ? sl : sr;
       double rk = left ? rl : rr; /* rho_K (S_K - u_K) */
-      double coef = rk / (sk - sm);
+      double unk = vk[1 + n], pk = vk[ie];
+      /* star state U*_K = rho_K (S_K - u_K)/(S_K - S_M) (1, S_M, v_t, .) with
+       * the energy in the star-pressure form p* = p_K + rho_K (S_K - u_K)(S_M - u_K),
+       * E* = ((S_K - u_K) E_K - p_K u_K + p* S_M) / (S_K - S_M) */
+      double inv = 1.0 / (sk - sm);
+      double coef = rk * inv;
+      double ps = pk + rk * (sm - unk);
       double us[NVMAX];
       us[0] = coef;
       for (int d = 0; d < f->nd; d++) us[1 + d] = (d == n) ? coef * sm : coef * vk[1 + d];
-      us[ie] = coef * (uk[ie] / vk[0] + (sm - vk[1 + n]) * (sm + vk[ie] / rk));
+      us[ie] = ((sk - unk) * uk[ie] - pk * unk + ps * sm) * inv;
       for (int k = 0; k < nv; k++) F[k] = fk[k] + sk * (us[k] - uk[k]);
     } else {
       for (int k = 0; k < nv; k++) F[k] = fr[k];

@@ -81,6 +81,8 @@ SIGNATURES = {
     "amrv_set_schedule": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "amrv_get_schedule": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "amrv_set_variant": ([P, ctypes.c_int32], ctypes.c_int),
+    "amrv_get_variant": ([P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "amrv_autotune": ([P, ctypes.c_int32], ctypes.c_int),
     "amrv_use_graph": ([P, ctypes.c_int32], ctypes.c_int),
     "amrv_profile": ([P, ctypes.c_int32], ctypes.c_int),

@@ -330,6 +330,7 @@ int amrv_forest_create(const amrv_config* cfg, int64_t n, const int32_t* lev, co
   f->lc.mhd = cfg->physics == AMRV_MHD_GLM;
   f->lc.flux = cfg->flux;
   f->lc.lim = cfg->limiter;
+  f->lc.variant = 0;
 
   auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
     if (!bytes) return hipSuccess;
@@ -469,28 +470,47 @@ int amrv_get_schedule(const amrv_forest* f, int32_t* sched, int32_t* xcd, int32_
   return AMRV_OK;
 }
 
+int amrv_set_variant(amrv_forest* f, int32_t variant) {
+  if (!f) return fail(AMRV_EINVAL, "null forest");
+  if (variant < 0 || variant > 1) return fail(AMRV_EINVAL, "unknown stage-kernel variant");
+  f->lc.variant = variant;
+  drop_graph(f);
+  return AMRV_OK;
+}
+
+int amrv_get_variant(const amrv_forest* f, int32_t* variant) {
+  if (!f || !variant) return fail(AMRV_EINVAL, "null argument");
+  *variant = f->lc.variant;
+  return AMRV_OK;
+}
+
 int amrv_autotune(amrv_forest* f, int32_t reps) {
   if (!f) return fail(AMRV_EINVAL, "null forest");
   if (reps < 1) reps = 3;
   struct Cand {
-    int sched, xcd, pwgs;
+    int sched, xcd, pwgs, var;
   };
-  std::vector<Cand> cands = {{AMRV_SCHED_GRID, 0, 0}, {AMRV_SCHED_GRID, 1, 0}};
-  if (f->tab.nd > 1)
-    for (int k : {1, 2, 3, 4, 6}) cands.push_back({AMRV_SCHED_PERSISTENT, 0, k * f->ncu});
-  const int s0 = f->sched, x0 = f->xcd, p0 = f->pwgs;
+  std::vector<Cand> cands;
+  for (int var : f->tab.nd > 1 ? std::vector<int>{0, 1} : std::vector<int>{0}) {
+    cands.push_back({AMRV_SCHED_GRID, 0, 0, var});
+    cands.push_back({AMRV_SCHED_GRID, 1, 0, var});
+    if (f->tab.nd > 1)
+      for (int k : {1, 2, 3, 4}) cands.push_back({AMRV_SCHED_PERSISTENT, 0, k * f->ncu, var});
+  }
+  const int s0 = f->sched, x0 = f->xcd, p0 = f->pwgs, v0 = f->lc.variant;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   // time the first-stage pass U^n -> U^(1) with dt = 0: the state is untouched
   int rc = set_scalars(f, PP_DT, {0.0, 1.0});
   double best = 1e300;
-  Cand bc = {s0, x0, p0};
+  Cand bc = {s0, x0, p0, v0};
   for (const Cand& c : cands) {
     if (rc) break;
     f->sched = c.sched;
     f->xcd = c.xcd;
     f->pwgs = c.pwgs;
+    f->lc.variant = c.var;
     StageArgs a{};
     a.Uin = f->U[0];
     a.Un = f->U[0];
@@ -525,6 +545,7 @@ int amrv_autotune(amrv_forest* f, int32_t reps) {
   f->sched = bc.sched;
   f->xcd = bc.xcd;
   f->pwgs = bc.pwgs;
+  f->lc.variant = bc.var;
   drop_graph(f);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(f->st));

@@ -64,6 +64,7 @@ struct Kernels;  // forward
 // launchers (kernels.hip)
 struct LaunchCfg {
   int ndim, mhd, flux, lim;
+  int variant;  // stage kernel: 0 combined x/y phases, 1 split x then y
 };
 
 hipError_t launch_restrict(const Geo& g, const LaunchCfg& c, const double* U, const int32_t* list, int nlist,

@@ -201,14 +201,20 @@ __device__ __forceinline__ void hllc_flux(const double* vl, const double* vr, do
   prim2cons<ND, false>(vk, uk, P);
   phys_flux<ND, false, N>(vk, uk, fk);
   if (star) {
+    // star state rho_K (S_K - u_K)/(S_K - S_M) (1, S_M, v_t, .); energy in the
+    // star-pressure form E* = ((S_K - u_K) E_K - p_K u_K + p* S_M)/(S_K - S_M),
+    // p* = p_K + rho_K (S_K - u_K)(S_M - u_K): one reciprocal serves both
     const double sk = left ? sl : sr;
     const double rk = left ? rl : rr;
-    const double coef = rk / (sk - sm);
+    const double unk = vk[1 + N], pk = vk[ie];
+    const double inv = 1.0 / (sk - sm);
+    const double coef = rk * inv;
+    const double ps = pk + rk * (sm - unk);
     double us[NV];
     us[0] = coef;
 #pragma unroll
     for (int d = 0; d < ND; d++) us[1 + d] = (d == N) ? coef * sm : coef * vk[1 + d];
-    us[ie] = coef * (uk[ie] / vk[0] + (sm - vk[1 + N]) * (sm + vk[ie] / rk));
+    us[ie] = ((sk - unk) * uk[ie] - pk * unk + ps * sm) * inv;
 #pragma unroll
     for (int k = 0; k < NV; k++) F[k] = fk[k] + sk * (us[k] - uk[k]);
   } else {

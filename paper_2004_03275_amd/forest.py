@@ -110,9 +110,19 @@ class GpuForest:
         N.check(N.lib().amrv_get_schedule(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
 
+    def set_variant(self, variant: int):
+        N.check(N.lib().amrv_set_variant(self._h, int(variant)))
+
+    def get_variant(self) -> int:
+        v = ctypes.c_int32()
+        N.check(N.lib().amrv_get_variant(self._h, ctypes.byref(v)))
+        return v.value
+
     def autotune(self, reps: int = 3):
+        """Pick the fastest schedule and stage-kernel variant; returns
+        (schedule, xcd_remap, persistent_wgs, variant)."""
         N.check(N.lib().amrv_autotune(self._h, int(reps)))
-        return self.get_schedule()
+        return (*self.get_schedule(), self.get_variant())
 
     def use_graph(self, enable: bool = True):
         N.check(N.lib().amrv_use_graph(self._h, 1 if enable else 0))
@@ -130,12 +140,15 @@ class GpuForest:
         N.check(N.lib().amrv_synchronize(self._h))
 
 
-def run(forest, U0, *, t_end=None, steps=None, dts=None, schedule=None, graph=False, device="cuda:0"):
+def run(forest, U0, *, t_end=None, steps=None, dts=None, schedule=None, graph=False, device="cuda:0",
+        variant=None):
     """Drive the GPU forest like oracle.run: free Courant steps to t_end, a
     fixed step count, or a given dt sequence.  Returns (state, dts used)."""
     g = GpuForest(forest, device=device)
     if schedule is not None:
         g.set_schedule(*schedule)
+    if variant is not None:
+        g.set_variant(variant)
     if graph:
         g.use_graph(True)
     g.set_state(U0)

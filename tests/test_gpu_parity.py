@@ -166,9 +166,10 @@ def test_schedules_and_graph_are_bitwise_equal():
     f, U = _blast_small()
     dts = [1e-4, 1.2e-4]
     outs = []
-    for sched, graph in [((0, 0, 0), False), ((1, 0, 0), False), ((1, 1, 0), False), ((2, 0, 64), False),
-                         ((1, 1, 0), True), ((2, 0, 0), True)]:
-        G, _ = F.run(f, U, dts=dts, schedule=sched, graph=graph)
+    for sched, graph, var in [((0, 0, 0), False, 0), ((1, 0, 0), False, 0), ((1, 1, 0), False, 1),
+                              ((2, 0, 64), False, 1), ((1, 1, 0), True, 0), ((2, 0, 0), True, 1),
+                              ((0, 0, 0), False, 1)]:
+        G, _ = F.run(f, U, dts=dts, schedule=sched, graph=graph, variant=var)
         outs.append(G)
     for G in outs[1:]:
         assert np.array_equal(G, outs[0])
