@@ -59,7 +59,9 @@ extern "C" {
 #define AMRV_SCHED_PERSISTENT 2   /* one launch per stage, persistent workgroups */
 
 /* flag modes (amrv_flag_blocks) */
-#define AMRV_FLAG_LOHNER 0
+#define AMRV_FLAG_LOHNER 0        /* Loehner estimator (Sec. 1.3) */
+#define AMRV_FLAG_MLP 1           /* learned flagger: +1 where its logit > 0, else 0 */
+#define AMRV_FLAG_MLP_FALLBACK 2  /* learned flagger, Loehner where |logit| < margin */
 
 typedef struct amrv_forest amrv_forest;
 
@@ -125,11 +127,51 @@ double amrv_glm_ch(const amrv_forest* f);
  * A non-physical result is reported by the next amrv_max_dt. */
 int amrv_advance(amrv_forest* f, double dt);
 
-/* Loehner flags (Sec. 1.3), one int8 per leaf into host memory: +1 refine
- * (level < max_level and block max estimator > tol), -1 coarsen (level > 1
- * and max < frac * tol), else 0.  emax_out (host, may be NULL) receives each
- * leaf's max estimator.  Synchronises. */
+/* Refinement flags, one int8 per leaf into host memory.
+ * AMRV_FLAG_LOHNER (Sec. 1.3): +1 refine (level < max_level and block max
+ * estimator > tol), -1 coarsen (level > 1 and max < frac * tol), else 0;
+ * emax_out (host, may be NULL) receives each leaf's max estimator.
+ * AMRV_FLAG_MLP: +1 where the learned flagger's logit is > 0 (and level <
+ * max_level), else 0; emax_out receives the logits.  Needs
+ * amrv_mlp_set_weights.  AMRV_FLAG_MLP_FALLBACK: as AMRV_FLAG_MLP, but leaves
+ * with |logit| < margin (amrv_mlp_set_margin) get the Loehner flag, and
+ * emax_out the Loehner maximum for them.  Synchronises. */
 int amrv_flag_blocks(amrv_forest* f, int32_t mode, int8_t* flags_out, double* emax_out);
+
+/* ---- learned refinement flagger (a 128-64-64-1 perceptron, bfloat16 MFMA
+ * products with binary32 accumulation; not part of the paper, which flags
+ * with the Loehner estimator of Sec. 1.3) ----
+ * Parameters: 12,481 binary32 values, W1 [64][128], b1 [64], W2 [64][64],
+ * b2 [64], w3 [64], b3.  Features of a leaf: the means of rho and p over 64
+ * sub-blocks (4^3 cells in 3D, 2^2 in 2D), each divided by the leaf's mean of
+ * them minus one, as bfloat16 bit patterns [128] (rho first). */
+#define AMRV_MLP_NPARAM 12481
+#define AMRV_MLP_NIN 128
+int amrv_mlp_set_weights(amrv_forest* f, const float* w_host, int64_t n);
+int amrv_mlp_set_margin(amrv_forest* f, float margin);
+/* Features of the current state, [nleaves][128] bfloat16 bits; out is host
+ * (on_device = 0, synchronises) or device memory. */
+int amrv_mlp_features(amrv_forest* f, uint16_t* out, int32_t on_device);
+
+typedef struct {
+  float lr, beta1, beta2, eps;  /* Adam (binary32) */
+  float pos_weight;             /* weight of positive samples in the loss */
+  int32_t t0;                   /* Adam steps already taken */
+} amrv_train_cfg;
+/* Device scratch bytes of amrv_mlp_train for batch size `batch`. */
+size_t amrv_mlp_train_workspace_bytes(int32_t batch);
+/* nbatch optimisation steps on device data, all pointers device memory:
+ * X [n][128] bfloat16 features, y [n] labels (0 or 1), order [n] sample
+ * order (batch b uses order[b*batch .. b*batch+batch-1]; the caller draws the
+ * permutation), w [12,481] binary32 master weights updated in place, m and v
+ * [12,481] Adam moments.  Steps first_batch .. first_batch+nbatch-1; a last
+ * partial batch is padded with zero-weight rows.  loss (may be NULL):
+ * per-batch mean loss, indexed by batch number.  grad (may be NULL): the last
+ * step's gradient.  batch must be a positive multiple of 32 <= 4096.
+ * Asynchronous on the stream. */
+int amrv_mlp_train(const uint16_t* X, const float* y, const int32_t* order, int64_t n, int32_t batch,
+                   int32_t first_batch, int32_t nbatch, float* w, float* m, float* v, const amrv_train_cfg* cfg,
+                   void* d_workspace, size_t ws_bytes, void* hip_stream, float* loss, float* grad);
 
 /* Select the schedule of the stage update (AMRV_SCHED_*).  xcd_remap != 0
  * maps consecutive leaves to the same XCD; persistent_wgs is the persistent

@@ -25,6 +25,10 @@ SCHED_GRID = 1
 SCHED_PERSISTENT = 2
 
 FLAG_LOHNER = 0
+FLAG_MLP = 1
+FLAG_MLP_FALLBACK = 2
+MLP_NPARAM = 12481
+MLP_NIN = 128
 
 
 class Config(ctypes.Structure):
@@ -55,6 +59,11 @@ class Config(ctypes.Structure):
     ]
 
 
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("pos_weight", ctypes.c_float), ("t0", ctypes.c_int32)]
+
+
 class AmrvError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"amrv error {code}: {msg}")
@@ -78,6 +87,12 @@ SIGNATURES = {
     "amrv_glm_ch": ([P], ctypes.c_double),
     "amrv_advance": ([P, ctypes.c_double], ctypes.c_int),
     "amrv_flag_blocks": ([P, ctypes.c_int32, P, P], ctypes.c_int),
+    "amrv_mlp_set_weights": ([P, P, ctypes.c_int64], ctypes.c_int),
+    "amrv_mlp_set_margin": ([P, ctypes.c_float], ctypes.c_int),
+    "amrv_mlp_features": ([P, P, ctypes.c_int32], ctypes.c_int),
+    "amrv_mlp_train_workspace_bytes": ([ctypes.c_int32], ctypes.c_size_t),
+    "amrv_mlp_train": ([P, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P,
+                        ctypes.POINTER(TrainCfg), P, ctypes.c_size_t, P, P, P], ctypes.c_int),
     "amrv_set_schedule": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "amrv_get_schedule": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),

@@ -14,6 +14,7 @@
 #include "../../include/amrv.h"
 #include "forest.hpp"
 #include "internal.hpp"
+#include "mlp.hpp"
 
 using namespace amrv;
 
@@ -40,7 +41,8 @@ constexpr size_t ALIGN = 256;
 
 struct Layout {
   size_t off_U[3], off_G, off_FF, off_lvl, off_ijk, off_nbr, off_slot, off_kind, off_fslot, off_sleaf, off_sface,
-      off_rlist, off_plist, off_pp, off_lp, off_red, off_cnt, off_emax, off_flags, total;
+      off_rlist, off_plist, off_pp, off_lp, off_red, off_cnt, off_emax, off_flags, off_mw, off_mwb, off_mx, off_mz,
+      off_munc, total;
 };
 
 Layout plan(const Tables& t) {
@@ -71,6 +73,11 @@ Layout plan(const Tables& t) {
   L.off_cnt = take(sizeof(unsigned) * 16);
   L.off_emax = take(sizeof(double) * t.n);
   L.off_flags = take(sizeof(int8_t) * t.n);
+  L.off_mw = take(sizeof(float) * MLP_NPARAM);
+  L.off_mwb = take(sizeof(uint16_t) * MLP_WB_COUNT);
+  L.off_mx = take(sizeof(uint16_t) * MLP_NIN * t.n);
+  L.off_mz = take(sizeof(float) * t.n);
+  L.off_munc = take(sizeof(int8_t) * t.n);
   L.total = o;
   return L;
 }
@@ -103,6 +110,8 @@ struct amrv_forest {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;  // recorded pairs
   std::vector<hipEvent_t> ev_free;
   double prof_bytes = 0.0;
+  bool have_mlp = false;
+  float margin = 2.0f;
 };
 
 namespace {
@@ -441,13 +450,87 @@ int amrv_advance(amrv_forest* f, double dt) {
 
 int amrv_flag_blocks(amrv_forest* f, int32_t mode, int8_t* flags_out, double* emax_out) {
   if (!f || !flags_out) return fail(AMRV_EINVAL, "null argument");
-  if (mode != AMRV_FLAG_LOHNER) return fail(AMRV_EINVAL, "unknown flag mode");
-  int rc = enqueue_ghosts(f, f->U[0], false);
-  if (rc) return rc;
-  HIPCHK(launch_lohner(f->geo, f->lc, f->U[0], f->pp, f->lp, f->cfg.max_level, f->emax, f->flags, f->st));
-  HIPCHK(hipMemcpyAsync(flags_out, f->flags, f->tab.n, hipMemcpyDeviceToHost, f->st));
-  if (emax_out) HIPCHK(hipMemcpyAsync(emax_out, f->emax, sizeof(double) * f->tab.n, hipMemcpyDeviceToHost, f->st));
+  if (mode != AMRV_FLAG_LOHNER && mode != AMRV_FLAG_MLP && mode != AMRV_FLAG_MLP_FALLBACK)
+    return fail(AMRV_EINVAL, "unknown flag mode");
+  const int n = (int)f->tab.n;
+  const int8_t* only = nullptr;
+  if (mode != AMRV_FLAG_LOHNER) {
+    if (!f->have_mlp) return fail(AMRV_EINVAL, "flag mode needs amrv_mlp_set_weights");
+    if (f->tab.nd < 2) return fail(AMRV_ENOTSUP, "the learned flagger is defined for 2D and 3D leaves");
+    uint16_t* X = (uint16_t*)(f->ws + f->lay.off_mx);
+    float* z = (float*)(f->ws + f->lay.off_mz);
+    int8_t* unc = (int8_t*)(f->ws + f->lay.off_munc);
+    HIPCHK(launch_mlp_features(f->geo, f->lc, f->U[0], f->pp, X, f->st));
+    HIPCHK(launch_mlp_infer(X, n, (const uint16_t*)(f->ws + f->lay.off_mwb), (const float*)(f->ws + f->lay.off_mw), z,
+                            f->st));
+    HIPCHK(launch_mlp_flags(z, f->geo.lvl, n, f->cfg.max_level, f->margin, f->flags,
+                            mode == AMRV_FLAG_MLP_FALLBACK ? unc : nullptr, f->emax, f->st));
+    if (mode == AMRV_FLAG_MLP_FALLBACK) only = unc;
+  }
+  if (mode != AMRV_FLAG_MLP) {
+    int rc = enqueue_ghosts(f, f->U[0], false);
+    if (rc) return rc;
+    HIPCHK(launch_lohner(f->geo, f->lc, f->U[0], f->pp, f->lp, f->cfg.max_level, f->emax, f->flags, only, f->st));
+  }
+  HIPCHK(hipMemcpyAsync(flags_out, f->flags, n, hipMemcpyDeviceToHost, f->st));
+  if (emax_out) HIPCHK(hipMemcpyAsync(emax_out, f->emax, sizeof(double) * n, hipMemcpyDeviceToHost, f->st));
   HIPCHK(hipStreamSynchronize(f->st));
+  return AMRV_OK;
+}
+
+int amrv_mlp_set_weights(amrv_forest* f, const float* w, int64_t n) {
+  if (!f || !w) return fail(AMRV_EINVAL, "null argument");
+  if (n != MLP_NPARAM) return fail(AMRV_EINVAL, "expected 12481 parameters");
+  float* dw = (float*)(f->ws + f->lay.off_mw);
+  HIPCHK(hipMemcpyAsync(dw, w, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, f->st));
+  HIPCHK(launch_mlp_prep(dw, (uint16_t*)(f->ws + f->lay.off_mwb), f->st));
+  HIPCHK(hipStreamSynchronize(f->st));
+  f->have_mlp = true;
+  return AMRV_OK;
+}
+
+int amrv_mlp_set_margin(amrv_forest* f, float margin) {
+  if (!f) return fail(AMRV_EINVAL, "null forest");
+  if (!(margin >= 0.0f)) return fail(AMRV_EINVAL, "margin must be >= 0");
+  f->margin = margin;
+  return AMRV_OK;
+}
+
+int amrv_mlp_features(amrv_forest* f, uint16_t* out, int32_t on_device) {
+  if (!f || !out) return fail(AMRV_EINVAL, "null argument");
+  if (f->tab.nd < 2) return fail(AMRV_ENOTSUP, "features are defined for 2D and 3D leaves");
+  uint16_t* X = (uint16_t*)(f->ws + f->lay.off_mx);
+  HIPCHK(launch_mlp_features(f->geo, f->lc, f->U[0], f->pp, X, f->st));
+  const size_t bytes = sizeof(uint16_t) * MLP_NIN * (size_t)f->tab.n;
+  HIPCHK(hipMemcpyAsync(out, X, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, f->st));
+  if (!on_device) HIPCHK(hipStreamSynchronize(f->st));
+  return AMRV_OK;
+}
+
+size_t amrv_mlp_train_workspace_bytes(int32_t batch) {
+  if (batch <= 0 || batch % 32 || batch > 4096) {
+    g_err = "batch must be a positive multiple of 32 <= 4096";
+    return 0;
+  }
+  return mlp_train_scratch_bytes(batch);
+}
+
+int amrv_mlp_train(const uint16_t* X, const float* y, const int32_t* order, int64_t n, int32_t batch,
+                   int32_t first_batch, int32_t nbatch, float* w, float* m, float* v, const amrv_train_cfg* cfg,
+                   void* ws, size_t ws_bytes, void* stream, float* loss, float* grad) {
+  if (!X || !y || !order || !w || !m || !v || !cfg || !ws) return fail(AMRV_EINVAL, "null argument");
+  if (n <= 0 || n > (1 << 30)) return fail(AMRV_EINVAL, "bad sample count");
+  if (batch <= 0 || batch % 32 || batch > 4096) return fail(AMRV_EINVAL, "batch must be a positive multiple of 32 <= 4096");
+  const int64_t nb_total = (n + batch - 1) / batch;
+  if (first_batch < 0 || nbatch < 0 || first_batch + nbatch > nb_total) return fail(AMRV_EINVAL, "batch range outside the data");
+  if (ws_bytes < mlp_train_scratch_bytes(batch)) return fail(AMRV_ENOMEM, "training workspace too small");
+  if (((uintptr_t)ws) % 256) return fail(AMRV_EINVAL, "workspace must be 256-byte aligned");
+  if (!(cfg->lr >= 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) || !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) ||
+      !(cfg->eps > 0.0f) || !(cfg->pos_weight > 0.0f) || cfg->t0 < 0)
+    return fail(AMRV_EINVAL, "bad training hyper-parameters");
+  TrainHyper hp{cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, cfg->pos_weight};
+  HIPCHK(launch_mlp_train(X, y, order, (int)n, batch, first_batch, nbatch, w, m, v, hp, cfg->t0, ws, loss, grad,
+                          (hipStream_t)stream));
   return AMRV_OK;
 }
 

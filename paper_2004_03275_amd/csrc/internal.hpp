@@ -78,7 +78,8 @@ hipError_t launch_stage(const Geo& g, const LaunchCfg& c, const StageArgs& a, co
 hipError_t launch_cfl(const Geo& g, const LaunchCfg& c, const double* U, const double* physp,
                       unsigned long long* red, hipStream_t st);
 hipError_t launch_lohner(const Geo& g, const LaunchCfg& c, const double* U, const double* physp,
-                         const double* lohp, int max_level, double* emax, int8_t* flags, hipStream_t st);
+                         const double* lohp, int max_level, double* emax, int8_t* flags, const int8_t* only,
+                         hipStream_t st);
 hipError_t launch_set_scalars(double* dst, const double* src_host_vals, int n, hipStream_t st);
 hipError_t launch_reset_u32(unsigned* p, int n, hipStream_t st);
 hipError_t launch_scale_var(double* U, const double* facp, long long count, hipStream_t st);

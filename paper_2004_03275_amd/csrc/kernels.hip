@@ -781,9 +781,10 @@ __device__ __forceinline__ void rho_p(const Geo& g, const double* __restrict__ U
 template <int ND, bool MHD>
 __global__ void __launch_bounds__(WGS) k_lohner(Geo g, const double* __restrict__ U, const double* __restrict__ pp,
                                                 const double* __restrict__ lp, int max_level, double* emax_out,
-                                                int8_t* flags) {
+                                                int8_t* flags, const int8_t* __restrict__ only) {
   __shared__ double red[WGS / 64];
   const int leaf = blockIdx.x;
+  if (only && !only[leaf]) return;
   const PhysParams P = load_phys(pp);
   const double eps = lp[LP_EPS], wr = lp[LP_WRHO], wp = lp[LP_WP];
   double m = 0.0;
@@ -996,12 +997,14 @@ hipError_t launch_cfl(const Geo& g, const LaunchCfg& c, const double* U, const d
 }
 
 hipError_t launch_lohner(const Geo& g, const LaunchCfg& c, const double* U, const double* physp, const double* lohp,
-                         int max_level, double* emax, int8_t* flags, hipStream_t st) {
-#define BODY_L(ND)                                                                                                \
-  if (c.mhd)                                                                                                      \
-    hipLaunchKernelGGL((k_lohner<ND, true>), dim3(g.n), dim3(WGS), 0, st, g, U, physp, lohp, max_level, emax, flags); \
-  else                                                                                                            \
-    hipLaunchKernelGGL((k_lohner<ND, false>), dim3(g.n), dim3(WGS), 0, st, g, U, physp, lohp, max_level, emax, flags);
+                         int max_level, double* emax, int8_t* flags, const int8_t* only, hipStream_t st) {
+#define BODY_L(ND)                                                                                                   \
+  if (c.mhd)                                                                                                         \
+    hipLaunchKernelGGL((k_lohner<ND, true>), dim3(g.n), dim3(WGS), 0, st, g, U, physp, lohp, max_level, emax, flags, \
+                       only);                                                                                        \
+  else                                                                                                               \
+    hipLaunchKernelGGL((k_lohner<ND, false>), dim3(g.n), dim3(WGS), 0, st, g, U, physp, lohp, max_level, emax, flags, \
+                       only);
   if (c.ndim == 1) {
     BODY_L(1)
   } else if (c.ndim == 2) {

@@ -1,0 +1,41 @@
+// mlp.hpp -- parameter layout and launchers of the learned flagger (mlp.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.hpp"
+
+namespace amrv {
+
+// binary32 master parameter vector: W1 [64][128], b1 [64], W2 [64][64], b2 [64], w3 [64], b3
+constexpr int MLP_NIN = 128, MLP_NH = 64;
+constexpr int MLP_W1 = 0;
+constexpr int MLP_B1 = MLP_W1 + MLP_NH * MLP_NIN;
+constexpr int MLP_W2 = MLP_B1 + MLP_NH;
+constexpr int MLP_B2 = MLP_W2 + MLP_NH * MLP_NH;
+constexpr int MLP_W3 = MLP_B2 + MLP_NH;
+constexpr int MLP_B3 = MLP_W3 + MLP_NH;
+constexpr int MLP_NPARAM = MLP_B3 + 1;  // 12,481
+// bfloat16 operand copies: W1b [64][128], W2b [64][64], W2bT [64][64], w3b [64]
+constexpr int MLP_WB_W1 = 0;
+constexpr int MLP_WB_W2 = MLP_WB_W1 + MLP_NH * MLP_NIN;
+constexpr int MLP_WB_W2T = MLP_WB_W2 + MLP_NH * MLP_NH;
+constexpr int MLP_WB_W3 = MLP_WB_W2T + MLP_NH * MLP_NH;
+constexpr int MLP_WB_COUNT = MLP_WB_W3 + MLP_NH;
+
+struct TrainHyper {
+  float lr, beta1, beta2, eps, pos_weight;
+};
+
+hipError_t launch_mlp_features(const Geo& g, const LaunchCfg& c, const double* U, const double* physp, uint16_t* X,
+                               hipStream_t st);
+hipError_t launch_mlp_prep(const float* w, uint16_t* wb, hipStream_t st);
+hipError_t launch_mlp_infer(const uint16_t* X, int n, const uint16_t* wb, const float* w, float* z, hipStream_t st);
+hipError_t launch_mlp_flags(const float* z, const int32_t* lvl, int n, int max_level, float margin, int8_t* flags,
+                            int8_t* uncertain, double* zout, hipStream_t st);
+size_t mlp_train_scratch_bytes(int B);
+hipError_t launch_mlp_train(const uint16_t* X, const float* Y, const int32_t* order, int n, int B, int first_batch,
+                            int nbatch, float* w, float* am, float* av, const TrainHyper& hp, int t0, void* ws,
+                            float* loss_out, float* grad_out, hipStream_t st);
+
+}  // namespace amrv

@@ -96,10 +96,35 @@ class GpuForest:
         N.check(N.lib().amrv_advance(self._h, float(dt)))
 
     def flag_blocks(self, with_emax: bool = False, mode: int = N.FLAG_LOHNER):
+        """Refinement flags (+1/0/-1).  with_emax also returns, per leaf, the
+        Loehner maximum (LOHNER mode) or the learned flagger's logit (MLP
+        modes; Loehner maximum on the fallback leaves)."""
         flags = np.empty(self.forest.n, dtype=np.int8)
         emax = np.empty(self.forest.n, dtype=np.float64)
         N.check(N.lib().amrv_flag_blocks(self._h, int(mode), flags.ctypes.data, emax.ctypes.data))
         return (flags, emax) if with_emax else flags
+
+    # -- learned flagger ----------------------------------------------------
+    def mlp_set_weights(self, w: np.ndarray):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        if w.size != N.MLP_NPARAM:
+            raise ValueError(f"expected {N.MLP_NPARAM} parameters")
+        N.check(N.lib().amrv_mlp_set_weights(self._h, w.ctypes.data, w.size))
+
+    def mlp_set_margin(self, margin: float):
+        N.check(N.lib().amrv_mlp_set_margin(self._h, float(margin)))
+
+    def mlp_features(self, device: bool = False):
+        """[n, 128] bfloat16 bit patterns of the current state (numpy uint16,
+        or a device int16 tensor with the same bits if device=True)."""
+        if device:
+            t = torch.empty((self.forest.n, N.MLP_NIN), dtype=torch.int16, device=self.device)
+            N.check(N.lib().amrv_mlp_features(self._h, ctypes.c_void_p(t.data_ptr()), 1))
+            self.synchronize()
+            return t
+        X = np.empty((self.forest.n, N.MLP_NIN), dtype=np.uint16)
+        N.check(N.lib().amrv_mlp_features(self._h, X.ctypes.data, 0))
+        return X
 
     # -- scheduling ---------------------------------------------------------
     def set_schedule(self, sched: int, xcd_remap: int = 1, persistent_wgs: int = 0):

@@ -1,0 +1,141 @@
+"""The learned flagger's HIP kernels against the CPU reference (oracle/mlp.py).
+
+* features: bit for bit (binary64 sums in the same order);
+* inference logits: bfloat16 MFMA products with binary32 accumulation against
+  the reference's identical rounding points; accumulation order differs, so
+  |dz| <= 2e-3 (|z| + 1);
+* one training step's gradient (lr = 0): relative L2 error <= 2e-2 against the
+  rounding-emulating reference (rounding of bfloat16 operands can flip);
+* training lowers the loss; MLP flags follow the logits.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from paper_2004_03275_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _blast_small():
+    s = W.blast_scheme(base=2, max_level=3)
+    f = W.blast_forest(s, radius=0.2, buffer_cells=2.0)
+    return W.blast(s, radius=0.2, forest=f)
+
+
+def test_features_bitwise():
+    from paper_2004_03275_amd.forest import GpuForest
+
+    for name, (f, U) in {"blast": _blast_small(), "kh": W.kh(4)}.items():
+        g = GpuForest(f)
+        g.set_state(U)
+        g.advance(g.max_dt())
+        Ug = g.get_state()
+        Xg = g.mlp_features()
+        Xo = M.features(Ug, f.scheme.ndim, f.scheme.gamma)
+        print(f"[mlp] features {name}: {Xg.shape}, differing {int(np.sum(Xg != Xo))}", flush=True)
+        assert np.array_equal(Xg, Xo), name
+
+
+def test_inference_logits_and_flags():
+    from paper_2004_03275_amd import _native as N
+    from paper_2004_03275_amd.forest import GpuForest
+
+    f, U = _blast_small()
+    g = GpuForest(f)
+    g.set_state(U)
+    w = W.mlp_init(11)
+    g.mlp_set_weights(w)
+    X = g.mlp_features()
+    flags, z = g.flag_blocks(with_emax=True, mode=N.FLAG_MLP)
+    zr, _ = M.forward_bf16(w, X)
+    err = np.abs(z - zr) / (np.abs(zr) + 1.0)
+    print(f"[mlp] logits max rel err {err.max():.2e}", flush=True)
+    assert err.max() <= 2e-3
+    expect = ((z > 0) & (f.level < f.scheme.max_level)).astype(np.int8)
+    assert np.array_equal(flags, expect)
+
+
+def test_fallback_uses_lohner_on_uncertain_leaves():
+    from paper_2004_03275_amd import _native as N
+    from paper_2004_03275_amd.forest import GpuForest
+
+    f, U = _blast_small()
+    g = GpuForest(f)
+    g.set_state(U)
+    g.mlp_set_weights(W.mlp_init(11))
+    fl = g.flag_blocks()
+    fm, z = g.flag_blocks(with_emax=True, mode=N.FLAG_MLP)
+    g.mlp_set_margin(1e30)  # every leaf uncertain: pure Loehner
+    assert np.array_equal(g.flag_blocks(mode=N.FLAG_MLP_FALLBACK), fl)
+    g.mlp_set_margin(0.0)  # none uncertain: pure MLP
+    assert np.array_equal(g.flag_blocks(mode=N.FLAG_MLP_FALLBACK), fm)
+
+
+def _train_call(X, y, w0, batch, lr, nbatch=1, order=None):
+    import torch
+
+    from paper_2004_03275_amd import _native as N
+
+    dev = torch.device("cuda:0")
+    n = X.shape[0]
+    Xd = torch.from_numpy(X.view(np.int16)).to(dev)
+    yd = torch.from_numpy(y.astype(np.float32)).to(dev)
+    od = torch.from_numpy((np.arange(n) if order is None else order).astype(np.int32)).to(dev)
+    w = torch.from_numpy(w0.copy()).to(dev)
+    m = torch.zeros_like(w)
+    v = torch.zeros_like(w)
+    nb = N.lib().amrv_mlp_train_workspace_bytes(batch)
+    ws = torch.empty(int(nb), dtype=torch.uint8, device=dev)
+    loss = torch.zeros((n + batch - 1) // batch, dtype=torch.float32, device=dev)
+    grad = torch.zeros_like(w)
+    cfg = N.TrainCfg(lr, 0.9, 0.999, 1e-8, 2.0, 0)
+    torch.cuda.synchronize()
+    N.check(N.lib().amrv_mlp_train(ctypes.c_void_p(Xd.data_ptr()), ctypes.c_void_p(yd.data_ptr()),
+                                   ctypes.c_void_p(od.data_ptr()), n, batch, 0, nbatch, ctypes.c_void_p(w.data_ptr()),
+                                   ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), ctypes.byref(cfg),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), None, ctypes.c_void_p(loss.data_ptr()),
+                                   ctypes.c_void_p(grad.data_ptr())))
+    torch.cuda.synchronize()
+    return w.cpu().numpy(), grad.cpu().numpy(), loss.cpu().numpy()
+
+
+@pytest.mark.parametrize("n", [256, 200])
+def test_training_step_gradient_matches_reference(n):
+    X, y = W.mlp_random_features(21, n)
+    w0 = W.mlp_init(4)
+    w1, g, loss = _train_call(X, y, w0, 256, 0.0)
+    gr, lr = M.grad_bf16(w0, X, y, 2.0)
+    rel = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    print(f"[mlp] n={n} grad rel err {rel:.2e}, loss {loss[0]:.5f} vs {lr:.5f}", flush=True)
+    assert rel <= 2e-2
+    assert abs(loss[0] - lr) <= 1e-4 * max(1.0, lr)
+    assert np.array_equal(w1, w0)  # lr = 0 leaves the weights
+
+
+def test_one_adam_step_matches_reference():
+    X, y = W.mlp_random_features(22, 256)
+    w0 = W.mlp_init(4)
+    w1, g, _ = _train_call(X, y, w0, 256, 1e-3)
+    ref, _, _ = M.adam(w0, g, np.zeros_like(w0), np.zeros_like(w0), 1, lr=1e-3)
+    assert np.allclose(w1, ref, rtol=0, atol=2e-6)
+
+
+def test_training_reduces_loss():
+    X, y = W.mlp_random_features(23, 4096)
+    # a learnable rule: label = first feature > 0
+    xv = M.bf16_value(X)
+    y = (xv[:, 0] + 0.5 * xv[:, 1] > 0).astype(np.float32)
+    w0 = W.mlp_init(5)
+    losses = []
+    w = w0
+    import torch
+
+    from paper_2004_03275_amd.mlp import Trainer
+
+    tr = Trainer(X, y, batch=512, seed=5, lr=3e-3, pos_weight=1.0)
+    hist = tr.fit(8)
+    print(f"[mlp] losses {['%.3f' % h for h in hist]}", flush=True)
+    assert hist[-1] < 0.5 * hist[0]
