@@ -197,6 +197,39 @@ def main():
                      "ms_per_step": pel / args.per_block_steps * 1e3, "batched_over_per_block": mcups / pb}
         log(f"per-block: {pb:.1f} MCUPS ({mcups / pb:.1f}x slower)")
 
+    # learned flagger against Loehner on the evolved state (config 5 on this forest)
+    flagger = None
+    if s.ndim > 1:
+        from paper_2004_03275_amd import mlp as MLP
+
+        try:
+            wts = MLP.trained_weights()
+        except (OSError, ValueError):
+            wts = None
+        if wts is not None:
+            g.set_schedule(*sched[:3])
+            g.mlp_set_weights(wts)
+            g.mlp_set_margin(2.0)
+            fl, emax = g.flag_blocks(with_emax=True)
+            fm, z = g.flag_blocks(with_emax=True, mode=N.FLAG_MLP)
+            ff = g.flag_blocks(mode=N.FLAG_MLP_FALLBACK)
+
+            def tflag(mode, reps=5):
+                g.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    g.flag_blocks(mode=mode)
+                return (time.perf_counter() - t0) / reps * 1e3
+
+            tl, tm, tf = tflag(N.FLAG_LOHNER), tflag(N.FLAG_MLP), tflag(N.FLAG_MLP_FALLBACK)
+            flagger = {"lohner_ms": tl, "mlp_ms": tm, "mlp_fallback_ms": tf,
+                       "flag_disagreement": float(np.mean((fm == 1) != (fl == 1))),
+                       "fallback_flag_disagreement": float(np.mean((ff == 1) != (fl == 1))),
+                       "fallback_fraction": float(np.mean(np.abs(z) < 2.0)),
+                       "refine_flags_lohner": int(np.sum(fl == 1))}
+            log(f"flagger: Loehner {tl:.2f} ms, MLP {tm:.2f} ms, fallback {tf:.2f} ms; "
+                f"disagreement {flagger['flag_disagreement']:.4f} (fallback {flagger['fallback_flag_disagreement']:.4f})")
+
     names = {0: "per_block", 1: "grid", 2: "persistent"}
     bytes_per_cell_step = (2 + 3 * (s.rk_stages - 1)) * s.nvar * 8
     out = {
@@ -244,6 +277,7 @@ def main():
         "cpu_baseline": cpu,
         "per_block": per_block,
         "parity": parity,
+        "learned_flagger": flagger,
     }
     print(json.dumps(out), flush=True)
 

@@ -129,25 +129,109 @@ class Trainer:
 
 def evaluate(w: np.ndarray, seeds, tol=0.1, base=8, max_level=3, steps=(0, 6, 12, 20, 30), margin=None,
              device="cuda:0"):
-    """Disagreement of the learned refine decision with Loehner's on held-out
-    jittered blasts: fraction of leaves where [logit > 0] != [Loehner max > tol]
-    (and, with a margin, of the fallback flags against the Loehner flags)."""
-    tot = dis = dis_fb = unc = 0
+    """Agreement of the learned flagger with Loehner on held-out jittered
+    blasts.  flag_disagreement: fraction of leaves whose refine flag (+1)
+    differs between AMRV_FLAG_MLP and AMRV_FLAG_LOHNER (the flags that drive
+    refinement; neither refines a finest-level leaf).  label_disagreement:
+    [logit > 0] against [Loehner max > tol] on every leaf, finest level
+    included.  With a margin, the same for AMRV_FLAG_MLP_FALLBACK and the
+    fraction of leaves that fell back to Loehner."""
+    tot = dis_flag = dis_label = dis_fb = unc = 0
     for sd in seeds:
         f, U = W.jittered_blast(sd, base=base, max_level=max_level)
         for _, g in snapshots(f, U, steps, device):
             g.mlp_set_weights(w)
             fl, emax = g.flag_blocks(with_emax=True)
             fm, z = g.flag_blocks(with_emax=True, mode=N.FLAG_MLP)
-            dis += int(np.sum((z > 0) != (emax > tol)))
+            dis_flag += int(np.sum((fm == 1) != (fl == 1)))
+            dis_label += int(np.sum((z > 0) != (emax > tol)))
             tot += f.n
             if margin is not None:
                 g.mlp_set_margin(margin)
                 ff = g.flag_blocks(mode=N.FLAG_MLP_FALLBACK)
-                # the fallback agrees with Loehner's refine decision where used
                 dis_fb += int(np.sum((ff == 1) != (fl == 1)))
                 unc += int(np.sum(np.abs(z) < margin))
-    out = {"leaves": tot, "disagreement": dis / tot}
+    out = {"leaves": tot, "flag_disagreement": dis_flag / tot, "label_disagreement": dis_label / tot}
     if margin is not None:
-        out.update({"fallback_disagreement": dis_fb / tot, "fallback_fraction": unc / tot, "margin": margin})
+        out.update({"fallback_flag_disagreement": dis_fb / tot, "fallback_fraction": unc / tot, "margin": margin})
     return out
+
+
+DATA_WEIGHTS = __import__("os").path.join(__import__("os").path.dirname(__file__), "data", "flagger_weights.npy")
+
+
+def trained_weights() -> np.ndarray:
+    """The flagger weights trained by `python -m paper_2004_03275_amd.mlp --save`
+    (binary32, 12,481 values)."""
+    w = np.load(DATA_WEIGHTS, allow_pickle=False)
+    if w.shape != (N.MLP_NPARAM,) or w.dtype != np.float32:
+        raise ValueError("unexpected flagger weight file")
+    return w
+
+
+def _seeds(spec: str):
+    out = []
+    for part in spec.split(","):
+        if "-" in part:
+            a, b = part.split("-")
+            out.extend(range(int(a), int(b) + 1))
+        elif part:
+            out.append(int(part))
+    return out
+
+
+def main(argv=None):
+    import argparse
+    import json
+    import sys
+
+    ap = argparse.ArgumentParser(description="train the learned refinement flagger on solver data")
+    ap.add_argument("--blast-seeds", default="1-24")
+    ap.add_argument("--kh-seeds", default="1-8")
+    ap.add_argument("--test-seeds", default="101-103")
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--margin", type=float, default=2.0)
+    ap.add_argument("--tol", type=float, default=0.1)
+    ap.add_argument("--out", default=None, help="write the weights and the training record (.npz)")
+    ap.add_argument("--save", action="store_true", help="store the weights as the package's trained flagger")
+    args = ap.parse_args(argv)
+
+    def log(m):
+        print(f"[flagger] {m}", file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    X1, e1, l1 = blast_dataset(_seeds(args.blast_seeds))
+    log(f"blast data: {len(e1)} leaves ({time.perf_counter() - t0:.1f} s)")
+    X2, e2, l2 = kh_dataset(_seeds(args.kh_seeds))
+    log(f"kh data: {len(e2)} leaves ({time.perf_counter() - t0:.1f} s)")
+    X = np.concatenate([X1, X2])
+    y = (np.concatenate([e1, e2]) > args.tol).astype(np.float32)
+    log(f"dataset: {len(y)} samples, {int(y.sum())} refine labels")
+    tr = Trainer(X, y, batch=args.batch, seed=args.seed, lr=args.lr)
+    t1 = time.perf_counter()
+    hist = tr.fit(args.epochs, log)
+    train_s = time.perf_counter() - t1
+    w = tr.weights()
+    res = evaluate(w, _seeds(args.test_seeds), tol=args.tol, margin=args.margin)
+    rec = {"samples": int(len(y)), "positives": int(y.sum()), "epochs": args.epochs, "batch": args.batch,
+           "lr": args.lr, "train_seconds": train_s, "final_loss": hist[-1], "pos_weight": tr.pos_weight,
+           "steps": tr.t, "samples_per_s": len(y) * args.epochs / train_s, **res}
+    log(json.dumps(rec))
+    if args.out:
+        np.savez(args.out, weights=w, loss=np.array(hist), record=json.dumps(rec))
+    if args.save:
+        import os
+
+        os.makedirs(os.path.dirname(DATA_WEIGHTS), exist_ok=True)
+        np.save(DATA_WEIGHTS, w)
+        with open(os.path.join(os.path.dirname(DATA_WEIGHTS), "flagger_record.json"), "w") as fh:
+            fh.write(json.dumps(rec, indent=1) + "\n")
+    print(json.dumps(rec), flush=True)
+    return rec
+
+
+if __name__ == "__main__":
+    main()

@@ -139,3 +139,54 @@ def test_training_reduces_loss():
     hist = tr.fit(8)
     print(f"[mlp] losses {['%.3f' % h for h in hist]}", flush=True)
     assert hist[-1] < 0.5 * hist[0]
+
+
+def test_trained_flagger_within_one_percent_of_lohner():
+    """The committed weights (trained on the GPU by amrv_mlp_train on
+    solver-generated, Loehner-labelled blocks, seeds 1-24 blast + 1-8 KH) on
+    held-out blast seeds 101-103: refine flags differ from Loehner's on at
+    most 1% of leaves; with the fallback margin, on fewer still."""
+    from paper_2004_03275_amd import mlp
+
+    res = mlp.evaluate(mlp.trained_weights(), [101, 102, 103], margin=2.0)
+    print(f"[mlp] held-out: {res}", flush=True)
+    assert res["flag_disagreement"] <= 0.01
+    assert res["fallback_flag_disagreement"] <= res["flag_disagreement"]
+    assert res["fallback_fraction"] < 0.05
+
+
+def test_learned_flagger_gain_over_lohner():
+    """What the network buys: flagging a 3D AMR forest with the MLP (features
+    + inference) against the Loehner estimator (ghost slabs + second
+    differences), same flags on >= 99% of leaves."""
+    import time
+
+    from paper_2004_03275_amd import _native as N
+    from paper_2004_03275_amd import mlp
+    from paper_2004_03275_amd.forest import GpuForest
+
+    s = W.blast_scheme(base=8, max_level=4)
+    f = W.blast_forest(s, radius=0.1, buffer_cells=4.0)
+    _, U = W.blast(s, radius=0.1, forest=f)
+    g = GpuForest(f)
+    g.set_state(U)
+    for _ in range(5):
+        g.advance(g.max_dt())
+    g.mlp_set_weights(mlp.trained_weights())
+    fl = g.flag_blocks()
+    fm = g.flag_blocks(mode=N.FLAG_MLP)
+
+    def timed(mode, reps=5):
+        g.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.flag_blocks(mode=mode)
+        return (time.perf_counter() - t0) / reps
+
+    tl = timed(N.FLAG_LOHNER)
+    tm = timed(N.FLAG_MLP)
+    dis = float(np.mean((fm == 1) != (fl == 1)))
+    print(f"[mlp] {f.n} leaves: Loehner {tl * 1e3:.2f} ms, MLP {tm * 1e3:.2f} ms ({tl / tm:.1f}x), "
+          f"flag disagreement {dis:.4f}", flush=True)
+    assert dis <= 0.01
+    assert tm < tl
