@@ -1,0 +1,93 @@
+"""Parity at the workloads' full sizes, in the bench's launch configuration
+(autotuned schedule), GPU against the oracle.
+
+* KH: 256 leaves of 16^2, 1000 SSP-RK3 steps with each side's own Courant
+  dt, compared every 100 steps;
+* Orszag-Tang: 1024 leaves of 16^2, MHD + GLM, to t = 0.5, compared every
+  200 steps and at the end;
+* 3D AMR blast: 19,384 leaves of 16^3 on 4 levels, 2 steps, then identical
+  Loehner flags.
+The bar is relative L1 <= 1e-10 per variable; the runs are in fact equal
+bit for bit.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_03275_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _pair(f, U, tune=True):
+    from paper_2004_03275_amd.forest import GpuForest
+
+    g = GpuForest(f)
+    g.set_state(U)
+    if tune:
+        g.autotune(2)
+    o = oracle.OracleForest(f)
+    o.set_state(U)
+    return g, o
+
+
+def _check(name, g, o, f, step):
+    G = g.get_state()
+    R = o.get_state()
+    e = W.relative_l1(G, R, f).max()
+    print(f"[full] {name} step {step}: rel L1 {e:.3e}, bitwise {np.array_equal(G, R)}", flush=True)
+    assert e <= TOL, (name, step, e)
+
+
+def test_kh_full_1000_steps():
+    f, U = W.kh(16)
+    g, o = _pair(f, U)
+    t0 = time.time()
+    for step in range(1, 1001):
+        dg, do = g.max_dt(), o.max_dt()
+        assert dg == do, (step, dg, do)
+        g.advance(dg)
+        o.advance(do)
+        if step % 100 == 0:
+            _check("kh", g, o, f, step)
+    print(f"[full] kh done in {time.time() - t0:.1f} s", flush=True)
+
+
+def test_orszag_tang_full_to_t05():
+    f, U = W.orszag_tang(32)
+    g, o = _pair(f, U)
+    t, step = 0.0, 0
+    t0 = time.time()
+    while t < 0.5:
+        dg, do = g.max_dt(), o.max_dt()
+        assert dg == do and g.glm_ch == o.glm_ch, (step, dg, do)
+        dt = min(dg, 0.5 - t)
+        g.advance(dt)
+        o.advance(dt)
+        t += dt
+        step += 1
+        if step % 200 == 0:
+            _check("ot", g, o, f, step)
+    _check("ot", g, o, f, step)
+    print(f"[full] ot: {step} steps to t = 0.5 in {time.time() - t0:.1f} s", flush=True)
+
+
+def test_blast_full_size_two_steps_and_flags():
+    f, U = W.blast(W.blast_scheme())
+    g, o = _pair(f, U)
+    for step in (1, 2):
+        dg, do = g.max_dt(), o.max_dt()
+        assert dg == do
+        g.advance(dg)
+        o.advance(do)
+        _check("blast", g, o, f, step)
+    fg, eg = g.flag_blocks(with_emax=True)
+    fo, eo = o.flag_blocks(with_emax=True)
+    print(f"[full] blast flags: refine {int(np.sum(fo == 1))}, keep {int(np.sum(fo == 0))}, "
+          f"coarsen {int(np.sum(fo == -1))}; identical {np.array_equal(fg, fo)}", flush=True)
+    assert np.array_equal(fg, fo)
+    assert np.array_equal(eg, eo)
