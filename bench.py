@@ -65,6 +65,9 @@ def main():
     ap.add_argument("--schedule", default=None,
                     help="fixed schedule instead of autotuning: grid, grid-noremap or persistent:<workgroups>")
     ap.add_argument("--variant", type=int, default=None, help="force the stage-kernel variant (0 or 1)")
+    ap.add_argument("--tune-reps", type=int, default=5)
+    ap.add_argument("--host-dt", action="store_true",
+                    help="time steps as amrv_max_dt + amrv_advance (host-side dt) instead of amrv_advance_cfl")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -144,8 +147,8 @@ def main():
             raise SystemExit(f"unknown schedule {args.schedule}")
         sched = (*g.get_schedule(), g.get_variant())
     elif not args.no_autotune:
-        sched = g.autotune(3)
-        log(f"autotuned schedule {sched}")
+        sched = g.autotune(args.tune_reps)
+        log(f"autotuned schedule {sched}\n" + g.autotune_report())
     else:
         sched = (*g.get_schedule(), g.get_variant())
     if args.variant is not None:
@@ -154,28 +157,56 @@ def main():
     if args.graph:
         g.use_graph(True)
 
-    def step(i):
+    def host_step(i):
         dt = g.max_dt()
         g.advance(dt)
         if args.flag_every and (i + 1) % args.flag_every == 0:
             g.flag_blocks()
 
-    for i in range(args.warmup):
-        step(i)
+    def device_steps(k, t):
+        # k steps with device-computed dt, Loehner flags every flag_every steps
+        done = 0
+        while done < k:
+            m = k - done
+            if args.flag_every:
+                m = min(m, args.flag_every - (done % args.flag_every))
+            t, _ = g.advance_cfl(m, float("inf"), t)
+            done += m
+            if args.flag_every and done % args.flag_every == 0:
+                g.flag_blocks()
+        return t
+
+    t_sim = 0.0
+    if args.host_dt:
+        for i in range(args.warmup):
+            host_step(i)
+    else:
+        t_sim = device_steps(args.warmup, t_sim)
     g.synchronize()
     torch.cuda.synchronize()
 
-    g.profile(True)
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(i)
+    if args.host_dt:
+        for i in range(args.steps):
+            host_step(i)
+    else:
+        t_sim = device_steps(args.steps, t_sim)
     g.synchronize()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    kms, launches, kbytes = g.profile_read()
-    g.profile(False)
     mcups = cells * args.steps / el / 1e6
     ms_step = el / args.steps * 1e3
+
+    # stage-kernel roofline: HIP events around each stage launch (separate pass)
+    g.profile(True)
+    nprof = max(1, min(args.steps, 6))
+    if args.host_dt:
+        for i in range(nprof):
+            host_step(i)
+    else:
+        t_sim = device_steps(nprof, t_sim)
+    kms, launches, kbytes = g.profile_read()
+    g.profile(False)
     avg_ms = kms / max(launches, 1)
     achieved = (kbytes / max(launches, 1)) / (avg_ms / 1e3) / 1e9 if launches else 0.0
     log(f"batched: {mcups:.1f} MCUPS, {ms_step:.3f} ms/step; stage kernel {avg_ms:.3f} ms/launch, "
@@ -260,7 +291,8 @@ def main():
             "flag_every": args.flag_every,
             "schedule": {"mode": names[sched[0]], "xcd_remap": sched[1], "persistent_wgs": sched[2],
                          "stage_kernel_variant": ["combined_xy", "split_xy"][sched[3]]},
-            "graph": bool(args.graph),
+            "graph": bool(args.graph) or not args.host_dt,
+            "time_step": "host (amrv_max_dt + amrv_advance)" if args.host_dt else "device (amrv_advance_cfl)",
         },
         "roofline": {
             "bound": "hbm",

@@ -127,6 +127,19 @@ double amrv_glm_ch(const amrv_forest* f);
  * A non-physical result is reported by the next amrv_max_dt. */
 int amrv_advance(amrv_forest* f, double dt);
 
+/* nsteps full SSP-RK steps whose time steps are computed on the device:
+ * each step takes dt = min(cfl / max_cells sum_d (|v_d| + c_d)/dx_d, t_end - t)
+ * from the Courant reduction of the state it starts from (the last stage of
+ * each step folds the reduction of its result into the same pass), so the
+ * host does not synchronise between steps; the steps replay one captured
+ * HIP graph.  *t (host) is the time before and after; a step starting at or
+ * after t_end does nothing.  *taken (may be NULL) counts the steps with
+ * dt > 0.  Synchronises at the end; AMRV_ENONPHYSICAL if a step met a
+ * non-physical state (the steps after it do nothing).  The same arithmetic
+ * as amrv_max_dt + amrv_advance, except that the MHD damping factor is
+ * evaluated on the device. */
+int amrv_advance_cfl(amrv_forest* f, int32_t nsteps, double t_end, double* t, int32_t* taken);
+
 /* Refinement flags, one int8 per leaf into host memory.
  * AMRV_FLAG_LOHNER (Sec. 1.3): +1 refine (level < max_level and block max
  * estimator > tol), -1 coarsen (level > 1 and max < frac * tol), else 0;
@@ -190,6 +203,9 @@ int amrv_get_variant(const amrv_forest* f, int32_t* variant);
 /* Time the candidate schedules and kernel variants on the current state
  * (first-stage kernel, state unchanged) and keep the fastest.  Synchronises. */
 int amrv_autotune(amrv_forest* f, int32_t reps);
+/* Text table of the last amrv_autotune: one line per candidate with its
+ * median first-stage kernel time.  Valid until the next call on f. */
+const char* amrv_autotune_report(const amrv_forest* f);
 
 /* Capture one advance step in a HIP graph and replay it on later
  * amrv_advance calls (enable != 0), or launch kernels directly (0). */

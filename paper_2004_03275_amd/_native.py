@@ -87,6 +87,8 @@ SIGNATURES = {
     "amrv_glm_ch": ([P], ctypes.c_double),
     "amrv_advance": ([P, ctypes.c_double], ctypes.c_int),
     "amrv_flag_blocks": ([P, ctypes.c_int32, P, P], ctypes.c_int),
+    "amrv_advance_cfl": ([P, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                          ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "amrv_mlp_set_weights": ([P, P, ctypes.c_int64], ctypes.c_int),
     "amrv_mlp_set_margin": ([P, ctypes.c_float], ctypes.c_int),
     "amrv_mlp_features": ([P, P, ctypes.c_int32], ctypes.c_int),
@@ -99,6 +101,7 @@ SIGNATURES = {
     "amrv_set_variant": ([P, ctypes.c_int32], ctypes.c_int),
     "amrv_get_variant": ([P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "amrv_autotune": ([P, ctypes.c_int32], ctypes.c_int),
+    "amrv_autotune_report": ([P], ctypes.c_char_p),
     "amrv_use_graph": ([P, ctypes.c_int32], ctypes.c_int),
     "amrv_profile": ([P, ctypes.c_int32], ctypes.c_int),
     "amrv_profile_read": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),

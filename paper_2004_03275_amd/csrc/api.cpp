@@ -106,12 +106,16 @@ struct amrv_forest {
   bool graph_on = false, graph_valid = false;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
+  hipGraphExec_t dexec = nullptr;  // device-timed step
+  hipGraph_t dgraph = nullptr;
+  double dt_tend = 0.0;            // t_end baked into the captured device-timed step
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;  // recorded pairs
   std::vector<hipEvent_t> ev_free;
   double prof_bytes = 0.0;
   bool have_mlp = false;
   float margin = 2.0f;
+  std::string tune_report;  // the last autotune's timing table
 };
 
 namespace {
@@ -189,8 +193,9 @@ int enqueue_stage_update(amrv_forest* f, const StageArgs& a, int mode) {
 }
 
 // one full SSP step on the forest's stream; dt and the damping factor are
-// read from the device parameter block
-int enqueue_step(amrv_forest* f) {
+// read from the device parameter block.  fold != null: the last stage folds
+// the Courant reduction of the new state into it.
+int enqueue_step(amrv_forest* f, unsigned long long* fold = nullptr) {
   const int S = f->cfg.rk_stages;
   if (f->sched == AMRV_SCHED_PERSISTENT && f->tab.nd > 1) HIPCHK(launch_reset_u32(f->cnt, 16, f->st));
   for (int s = 1; s <= S; s++) {
@@ -205,6 +210,7 @@ int enqueue_step(amrv_forest* f) {
     a.dtp = f->pp + PP_DT;
     a.stage = s;
     a.rk = S;
+    a.cflred = s == S ? fold : nullptr;
     rc = enqueue_stage_update(f, a, f->sched);
     if (rc) return rc;
   }
@@ -219,9 +225,20 @@ int enqueue_step(amrv_forest* f) {
 void drop_graph(amrv_forest* f) {
   if (f->gexec) (void)hipGraphExecDestroy(f->gexec);
   if (f->graph) (void)hipGraphDestroy(f->graph);
+  if (f->dexec) (void)hipGraphExecDestroy(f->dexec);
+  if (f->dgraph) (void)hipGraphDestroy(f->dgraph);
   f->gexec = nullptr;
   f->graph = nullptr;
+  f->dexec = nullptr;
+  f->dgraph = nullptr;
   f->graph_valid = false;
+}
+
+// a device-timed step: dt from the previous fold, then the step with a fold
+int enqueue_device_step(amrv_forest* f, double t_end) {
+  HIPCHK(launch_dt_update(f->red, f->pp, f->pp + PP_T, f->cnt + CNT_ERR, f->cfg.cfl, t_end, f->cfg.glm_cr,
+                          f->cfg.physics == AMRV_MHD_GLM, f->st));
+  return enqueue_step(f, f->red);
 }
 
 int capture_graph(amrv_forest* f) {
@@ -448,6 +465,60 @@ int amrv_advance(amrv_forest* f, double dt) {
   return enqueue_step(f);
 }
 
+int amrv_advance_cfl(amrv_forest* f, int32_t nsteps, double t_end, double* t, int32_t* taken) {
+  if (!f || !t) return fail(AMRV_EINVAL, "null argument");
+  if (nsteps < 0) return fail(AMRV_EINVAL, "nsteps must be >= 0");
+  if (!std::isfinite(*t) || std::isnan(t_end)) return fail(AMRV_EINVAL, "bad time");
+  // initial fold: the Courant reduction of the current state
+  HIPCHK(launch_reset_u32((unsigned*)f->red, 8, f->st));
+  HIPCHK(launch_reset_u32(f->cnt + CNT_ERR, 2, f->st));
+  int rc = set_scalars(f, PP_T, {*t});
+  if (rc) return rc;
+  HIPCHK(launch_cfl(f->geo, f->lc, f->U[0], f->pp, f->red, f->st));
+  const bool graph = f->st != nullptr && f->sched != AMRV_SCHED_PER_BLOCK && !f->prof;
+  if (graph && (!f->dexec || f->dt_tend != t_end)) {
+    if (f->dexec) (void)hipGraphExecDestroy(f->dexec);
+    if (f->dgraph) (void)hipGraphDestroy(f->dgraph);
+    f->dexec = nullptr;
+    f->dgraph = nullptr;
+    HIPCHK(hipStreamBeginCapture(f->st, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_device_step(f, t_end);
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(f->st, &gr);
+    if (rc) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    f->dgraph = gr;
+    HIPCHK(hipGraphInstantiate(&f->dexec, gr, nullptr, nullptr, 0));
+    f->dt_tend = t_end;
+  }
+  for (int i = 0; i < nsteps; i++) {
+    if (graph) {
+      HIPCHK(hipGraphLaunch(f->dexec, f->st));
+    } else {
+      rc = enqueue_device_step(f, t_end);
+      if (rc) return rc;
+    }
+  }
+  double th = 0.0;
+  unsigned cw[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(&th, f->pp + PP_T, sizeof th, hipMemcpyDeviceToHost, f->st));
+  HIPCHK(hipMemcpyAsync(cw, f->cnt + CNT_ERR, sizeof cw, hipMemcpyDeviceToHost, f->st));
+  HIPCHK(hipStreamSynchronize(f->st));
+  *t = th;
+  if (taken) *taken = (int32_t)cw[1];
+  // the GLM speed of the latest fold (the next amrv_advance needs it)
+  if (f->cfg.physics == AMRV_MHD_GLM) {
+    double ch = 0.0;
+    HIPCHK(hipMemcpy(&ch, f->pp + PP_CH, sizeof ch, hipMemcpyDeviceToHost));
+    f->ch = ch;
+  }
+  if (cw[0]) return fail(AMRV_ENONPHYSICAL, "non-physical state during a device-timed run");
+  return AMRV_OK;
+}
+
 int amrv_flag_blocks(amrv_forest* f, int32_t mode, int8_t* flags_out, double* emax_out) {
   if (!f || !flags_out) return fail(AMRV_EINVAL, "null argument");
   if (mode != AMRV_FLAG_LOHNER && mode != AMRV_FLAG_MLP && mode != AMRV_FLAG_MLP_FALLBACK)
@@ -584,9 +655,11 @@ int amrv_autotune(amrv_forest* f, int32_t reps) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  // time the first-stage pass U^n -> U^(1) with dt = 0: the state is untouched
-  int rc = set_scalars(f, PP_DT, {0.0, 1.0});
+  // time the first-stage pass U^n -> U^(1): it writes only the stage buffer,
+  // so the state is untouched (dt must be > 0: dt = 0 marks a finished run)
+  int rc = set_scalars(f, PP_DT, {1.0e-12, 1.0});
   double best = 1e300;
+  std::string report;
   Cand bc = {s0, x0, p0, v0};
   for (const Cand& c : cands) {
     if (rc) break;
@@ -618,6 +691,10 @@ int amrv_autotune(amrv_forest* f, int32_t reps) {
     if (rc) break;
     std::sort(ts.begin(), ts.end());
     const double med = ts[ts.size() / 2];
+    char line[160];
+    snprintf(line, sizeof line, "sched=%d xcd=%d wgs=%d variant=%d: median %.4f ms (min %.4f)\n", c.sched, c.xcd,
+             c.pwgs, c.var, med, (double)ts.front());
+    report += line;
     if (med < best) {
       best = med;
       bc = c;
@@ -629,11 +706,14 @@ int amrv_autotune(amrv_forest* f, int32_t reps) {
   f->xcd = bc.xcd;
   f->pwgs = bc.pwgs;
   f->lc.variant = bc.var;
+  f->tune_report = report;
   drop_graph(f);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(f->st));
   return AMRV_OK;
 }
+
+const char* amrv_autotune_report(const amrv_forest* f) { return f ? f->tune_report.c_str() : ""; }
 
 int amrv_use_graph(amrv_forest* f, int32_t enable) {
   if (!f) return fail(AMRV_EINVAL, "null forest");

@@ -57,6 +57,7 @@ struct StageArgs {
   const double* dtp;   // device-resident dt
   int stage;           // 1..rk
   int rk;              // 2 or 3
+  unsigned long long* cflred;  // last stage: fold the Courant reduction of the new state here (or null)
 };
 
 struct Kernels;  // forward
@@ -83,10 +84,17 @@ hipError_t launch_lohner(const Geo& g, const LaunchCfg& c, const double* U, cons
 hipError_t launch_set_scalars(double* dst, const double* src_host_vals, int n, hipStream_t st);
 hipError_t launch_reset_u32(unsigned* p, int n, hipStream_t st);
 hipError_t launch_scale_var(double* U, const double* facp, long long count, hipStream_t st);
+// device-side time step from a Courant reduction: dt = min(cfl / smax, t_end - t),
+// t += dt, c_h and the GLM damping factor into the parameter block, then the
+// reduction words are cleared for the next fold
+hipError_t launch_dt_update(unsigned long long* red, double* pp, double* t, unsigned* err, double cfl, double t_end,
+                            double glm_cr, int mhd, hipStream_t st);
+// persistent counters: [1..3] stage work queues, [8] non-physical flag, [9] steps taken
+constexpr int CNT_ERR = 8, CNT_TAKEN = 9;
 
 // device parameter block (written once per forest, plus dt / ch per step)
 // layout: [0] gamma [1] gm1 [2] igm1 [3] ch [4] dt [5] glm damping factor
-constexpr int PP_GAMMA = 0, PP_GM1 = 1, PP_IGM1 = 2, PP_CH = 3, PP_DT = 4, PP_DAMP = 5, PP_COUNT = 8;
+constexpr int PP_GAMMA = 0, PP_GM1 = 1, PP_IGM1 = 2, PP_CH = 3, PP_DT = 4, PP_DAMP = 5, PP_T = 6, PP_COUNT = 8;
 // Loehner parameters: [0] eps [1] w_rho [2] w_p [3] tol [4] coarsen tol
 constexpr int LP_EPS = 0, LP_WRHO = 1, LP_WP = 2, LP_TOL = 3, LP_CTOL = 4, LP_COUNT = 8;
 

@@ -146,6 +146,47 @@ __device__ __forceinline__ void riemann_dir(int d, double* vl, double* vr, doubl
   }
 }
 
+// Courant quantities of one cell (Sec. 2.1): sum_d (|v_d| + c_d) / dx_d and
+// max_d (|v_d| + c_d), with the non-physical test; same arithmetic as k_cfl
+template <int ND, bool MHD>
+__device__ __forceinline__ void cfl_cell(const double* u, const PhysParams& P, const double* rd,
+                                         unsigned long long& smax, unsigned long long& cmax, int& bad) {
+  constexpr int NV = Sys<ND, MHD>::NV;
+  double v[NV];
+  cons2prim<ND, MHD>(u, v, P);
+  if (!(v[0] > 0.0) || !(v[Sys<ND, MHD>::IE] > 0.0)) {
+    bad = 1;
+    return;
+  }
+  double s = 0.0, cm = 0.0;
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    const double w = fabs(v[1 + d]) + wave_speed_dir<ND, MHD>(v, d, P);
+    const double tq = w * rd[d];
+    s = d == 0 ? tq : s + tq;
+    cm = w > cm ? w : cm;
+  }
+  const unsigned long long sb = (unsigned long long)__double_as_longlong(s);
+  const unsigned long long cb = (unsigned long long)__double_as_longlong(cm);
+  smax = sb > smax ? sb : smax;
+  cmax = cb > cmax ? cb : cmax;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x);
+
+// fold per-thread Courant maxima into the reduction words (one atomic per wave)
+__device__ __forceinline__ void cfl_fold(unsigned long long* red, unsigned long long smax, unsigned long long cmax,
+                                         int bad) {
+  smax = wave_max_u64(smax);
+  cmax = wave_max_u64(cmax);
+  bad = __any(bad);
+  if ((threadIdx.x & 63) == 0) {
+    if (smax) atomicMax(&red[0], smax);
+    if (cmax) atomicMax(&red[1], cmax);
+    if (bad) atomicOr(&red[2], 1ull);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // ghost slabs of coarse-fine faces
 // ---------------------------------------------------------------------------
@@ -351,8 +392,11 @@ __global__ void __launch_bounds__(WGS, (SPLIT && Sys<ND, MHD>::NV <= 5) ? 3 : 1)
 
   const PhysParams P = load_phys(pp);
   const double dt = pp[PP_DT];
+  if (dt == 0.0) return;  // a device-timed run that has reached its end time
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const size_t vs = (size_t)g.n * g.ncell;  // variable stride of the state
+  unsigned long long csmax = 0, ccmax = 0;
+  int cbad = 0;
 
   // ring cell of this thread (tid < 128): x ring then y ring
   int rx = 0, ry = 0, rface = 0, rlayer = 0, ra1 = 0;
@@ -613,10 +657,17 @@ __global__ void __launch_bounds__(WGS, (SPLIT && Sys<ND, MHD>::NV <= 5) ? 3 : 1)
         acc = acc + (sFy[v][(ty + 1) * NB + tx] - sFy[v][ty * NB + tx]) * rdy;
         if constexpr (ND == 3) acc = acc + zd[v];
         const double tmp = Ui[v] - dt * acc;
-        out[v * vs + (size_t)k * NB * NB] = combine<NV>(a.stage, a.rk, a.stage > 1 ? Uo[v] : 0.0, tmp);
+        const double res = combine<NV>(a.stage, a.rk, a.stage > 1 ? Uo[v] : 0.0, tmp);
+        out[v * vs + (size_t)k * NB * NB] = res;
+        Ui[v] = res;
+      }
+      if (a.cflred) {
+        const double rd[3] = {rdx, rdy, rdz};
+        cfl_cell<ND, MHD>(Ui, P, rd, csmax, ccmax, cbad);
       }
     }
   }
+  if (a.cflred) cfl_fold(a.cflred, csmax, ccmax, cbad);
 }
 
 // ---------------------------------------------------------------------------
@@ -634,6 +685,7 @@ __global__ void __launch_bounds__(WGS) k_stage_line(Geo g, StageArgs a, const do
   __shared__ double sF[NV][CH + 1];
   const PhysParams P = load_phys(pp);
   const double dt = pp[PP_DT];
+  if (dt == 0.0) return;
   const int tid = threadIdx.x;
   const int nch = (g.nx + CH - 1) / CH;
   const int leaf = sc.mode == 0 ? sc.leaf0 : (int)(blockIdx.x / nch);
@@ -693,16 +745,25 @@ __global__ void __launch_bounds__(WGS) k_stage_line(Geo g, StageArgs a, const do
   }
   __syncthreads();
   const int x = c0 + tid;
+  unsigned long long csmax = 0, ccmax = 0;
+  int cbad = 0;
   if (x < g.nx) {
+    double res[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) {
       const double acc = (sF[v][tid + 1] - sF[v][tid]) * rdx;
       const size_t id = uidx(g, v, leaf, x);
       const double tmp = a.Uin[id] - dt * acc;
       const double un = a.stage == 1 ? 0.0 : a.Un[id];
-      a.Uout[id] = combine<NV>(a.stage, a.rk, un, tmp);
+      res[v] = combine<NV>(a.stage, a.rk, un, tmp);
+      a.Uout[id] = res[v];
+    }
+    if (a.cflred) {
+      const double rd[3] = {rdx, 0.0, 0.0};
+      cfl_cell<1, MHD>(res, P, rd, csmax, ccmax, cbad);
     }
   }
+  if (a.cflred) cfl_fold(a.cflred, csmax, ccmax, cbad);
 }
 
 // ---------------------------------------------------------------------------
@@ -1013,6 +1074,38 @@ hipError_t launch_lohner(const Geo& g, const LaunchCfg& c, const double* U, cons
     BODY_L(3)
   }
 #undef BODY_L
+  return hipGetLastError();
+}
+
+__global__ void k_dt_update(unsigned long long* red, double* pp, double* t, unsigned* err, double cfl, double t_end,
+                            double glm_cr, int mhd) {
+  if (threadIdx.x != 0) return;
+  const unsigned long long sb = red[0], cb = red[1];
+  if (red[2]) *err = 1u;
+  const double smax = __longlong_as_double((long long)sb);
+  const double ch = __longlong_as_double((long long)cb);
+  const double tn = *t;
+  double dt = 0.0;
+  if (tn < t_end && smax > 0.0 && !red[2]) {
+    dt = cfl / smax;
+    const double rem = t_end - tn;
+    if (rem < dt) dt = rem;
+    err[CNT_TAKEN - CNT_ERR] += 1u;
+  }
+  *t = tn + dt;
+  pp[PP_DT] = dt;
+  if (mhd) {
+    pp[PP_CH] = ch;
+    pp[PP_DAMP] = exp(-(dt * ch) / glm_cr);
+  }
+  red[0] = 0ull;
+  red[1] = 0ull;
+  red[2] = 0ull;
+}
+
+hipError_t launch_dt_update(unsigned long long* red, double* pp, double* t, unsigned* err, double cfl, double t_end,
+                            double glm_cr, int mhd, hipStream_t st) {
+  hipLaunchKernelGGL(k_dt_update, dim3(1), dim3(64), 0, st, red, pp, t, err, cfl, t_end, glm_cr, mhd);
   return hipGetLastError();
 }
 

@@ -95,6 +95,14 @@ class GpuForest:
     def advance(self, dt: float):
         N.check(N.lib().amrv_advance(self._h, float(dt)))
 
+    def advance_cfl(self, nsteps: int, t_end: float = float("inf"), t: float = 0.0):
+        """nsteps steps with device-computed Courant time steps (no host
+        synchronisation between them).  Returns (t after, steps taken)."""
+        tt = ctypes.c_double(t)
+        n = ctypes.c_int32()
+        N.check(N.lib().amrv_advance_cfl(self._h, int(nsteps), float(t_end), ctypes.byref(tt), ctypes.byref(n)))
+        return tt.value, n.value
+
     def flag_blocks(self, with_emax: bool = False, mode: int = N.FLAG_LOHNER):
         """Refinement flags (+1/0/-1).  with_emax also returns, per leaf, the
         Loehner maximum (LOHNER mode) or the learned flagger's logit (MLP
@@ -149,6 +157,9 @@ class GpuForest:
         N.check(N.lib().amrv_autotune(self._h, int(reps)))
         return (*self.get_schedule(), self.get_variant())
 
+    def autotune_report(self) -> str:
+        return N.lib().amrv_autotune_report(self._h).decode()
+
     def use_graph(self, enable: bool = True):
         N.check(N.lib().amrv_use_graph(self._h, 1 if enable else 0))
 
@@ -166,7 +177,7 @@ class GpuForest:
 
 
 def run(forest, U0, *, t_end=None, steps=None, dts=None, schedule=None, graph=False, device="cuda:0",
-        variant=None):
+        variant=None, device_dt=False, chunk=50):
     """Drive the GPU forest like oracle.run: free Courant steps to t_end, a
     fixed step count, or a given dt sequence.  Returns (state, dts used)."""
     g = GpuForest(forest, device=device)
@@ -178,6 +189,22 @@ def run(forest, U0, *, t_end=None, steps=None, dts=None, schedule=None, graph=Fa
         g.use_graph(True)
     g.set_state(U0)
     used = []
+    if device_dt:
+        if dts is not None:
+            raise ValueError("device_dt runs choose their own time steps")
+        t, n = 0.0, 0
+        tend = float("inf") if t_end is None else float(t_end)
+        while True:
+            k = chunk if steps is None else min(chunk, steps - n)
+            if k <= 0:
+                break
+            t, taken = g.advance_cfl(k, tend, t)
+            n += taken
+            if taken < k:
+                break
+        U = g.get_state()
+        g.close()
+        return U, [None] * n
     if dts is not None:
         for dt in dts:
             g.max_dt()
