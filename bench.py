@@ -30,6 +30,27 @@ METRIC = "MCUPS (cell-updates/s) per full RK step, batched vs per-block, at 1e-1
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
+def measured_traffic(workload: str):
+    """HBM bytes per stage-kernel launch from the committed counter summary,
+    if it was taken on this workload with the current kernel sources."""
+    import hashlib
+
+    if workload != "blast":
+        return None
+    prof = os.path.join(ROOT, "profiles", "hbm_counters_3d_amr_blast.md")
+    csrc = os.path.join(ROOT, "paper_2004_03275_amd", "csrc")
+    try:
+        text = open(prof).read()
+        h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                    for f in ("kernels.hip", "physics.hpp", "internal.hpp"))).hexdigest()
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(("kernel_source_sha256", "traffic_bytes")))
+    if vals.get("kernel_source_sha256", "").strip() != h:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def make_workload(name: str):
     from paper_2004_03275_amd import workloads as W
 
@@ -301,7 +322,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": kbytes / max(launches, 1),
             "avg_launch_ms": avg_ms,
             "launches": launches,
             "algorithmic_bytes_per_cell_step": bytes_per_cell_step,
