@@ -187,8 +187,10 @@ int amrv_mlp_train(const uint16_t* X, const float* y, const int32_t* order, int6
                    void* d_workspace, size_t ws_bytes, void* hip_stream, float* loss, float* grad);
 
 /* Select the schedule of the stage update (AMRV_SCHED_*).  xcd_remap != 0
- * maps consecutive leaves to the same XCD; persistent_wgs is the persistent
- * grid size (0 = 2 per compute unit).  The default is AMRV_SCHED_GRID with
+ * keeps consecutive leaves on the same XCD (grid: the workgroup-to-leaf map;
+ * persistent: one work queue per XCD over an eighth of the leaves, drained
+ * by that XCD's workgroups first); persistent_wgs is the persistent grid size
+ * (0 = 2 per compute unit).  The default is AMRV_SCHED_GRID with
  * the remap on, or the result of amrv_autotune. */
 int amrv_set_schedule(amrv_forest* f, int32_t sched, int32_t xcd_remap, int32_t persistent_wgs);
 int amrv_get_schedule(const amrv_forest* f, int32_t* sched, int32_t* xcd_remap, int32_t* persistent_wgs);

@@ -70,7 +70,7 @@ Layout plan(const Tables& t) {
   L.off_pp = take(sizeof(double) * PP_COUNT);
   L.off_lp = take(sizeof(double) * LP_COUNT);
   L.off_red = take(sizeof(unsigned long long) * 4);
-  L.off_cnt = take(sizeof(unsigned) * 16);
+  L.off_cnt = take(sizeof(unsigned) * CNT_COUNT);
   L.off_emax = take(sizeof(double) * t.n);
   L.off_flags = take(sizeof(int8_t) * t.n);
   L.off_mw = take(sizeof(float) * MLP_NPARAM);
@@ -169,7 +169,7 @@ int enqueue_stage_update(amrv_forest* f, const StageArgs& a, int mode) {
   }
   Sched s = make_sched(f, m == AMRV_SCHED_PERSISTENT ? 2 : 1, 0);
   if (t.nd == 1) s.xcd_remap = 0;
-  if (m == AMRV_SCHED_PERSISTENT) s.counter = f->cnt + a.stage;
+  if (m == AMRV_SCHED_PERSISTENT) s.counter = f->cnt + 8 * a.stage;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (f->prof) {
     for (hipEvent_t* e : {&e0, &e1}) {
@@ -197,7 +197,7 @@ int enqueue_stage_update(amrv_forest* f, const StageArgs& a, int mode) {
 // the Courant reduction of the new state into it.
 int enqueue_step(amrv_forest* f, unsigned long long* fold = nullptr) {
   const int S = f->cfg.rk_stages;
-  if (f->sched == AMRV_SCHED_PERSISTENT && f->tab.nd > 1) HIPCHK(launch_reset_u32(f->cnt, 16, f->st));
+  if (f->sched == AMRV_SCHED_PERSISTENT && f->tab.nd > 1) HIPCHK(launch_reset_u32(f->cnt, CNT_QUEUES, f->st));
   for (int s = 1; s <= S; s++) {
     const double* in = s == 1 ? f->U[0] : (s == 2 ? f->U[1] : f->U[2]);
     double* out = s == S ? f->U[0] : (s == 1 ? f->U[1] : f->U[2]);
@@ -649,7 +649,8 @@ int amrv_autotune(amrv_forest* f, int32_t reps) {
     cands.push_back({AMRV_SCHED_GRID, 0, 0, var});
     cands.push_back({AMRV_SCHED_GRID, 1, 0, var});
     if (f->tab.nd > 1)
-      for (int k : {1, 2, 3, 4}) cands.push_back({AMRV_SCHED_PERSISTENT, 0, k * f->ncu, var});
+      for (int x : {0, 1})
+        for (int k : {2, 3, 4}) cands.push_back({AMRV_SCHED_PERSISTENT, x, k * f->ncu, var});
   }
   const int s0 = f->sched, x0 = f->xcd, p0 = f->pwgs, v0 = f->lc.variant;
   hipEvent_t e0, e1;
@@ -677,7 +678,7 @@ int amrv_autotune(amrv_forest* f, int32_t reps) {
     std::vector<float> ts;
     for (int r = 0; r < reps + 1 && !rc; r++) {
       if (c.sched == AMRV_SCHED_PERSISTENT) {
-        hipError_t e = launch_reset_u32(f->cnt, 16, f->st);
+        hipError_t e = launch_reset_u32(f->cnt, CNT_QUEUES, f->st);
         if (e != hipSuccess) rc = hip_fail(e, "reset");
       }
       (void)hipEventRecord(e0, f->st);

@@ -47,7 +47,8 @@ struct Sched {
   int xcd_remap;       // map consecutive leaves onto one XCD
   int leaf0;           // per-block mode: the leaf
   int per_xcd;         // ceil(n / 8) for the remap
-  unsigned* counter;   // persistent work counter (reset before each stage)
+  unsigned* counter;   // persistent work queues of this stage: [0] the global queue, or with
+                       // xcd_remap [x] the queue of XCD x over leaves [x*per_xcd, (x+1)*per_xcd)
 };
 
 struct StageArgs {
@@ -89,8 +90,9 @@ hipError_t launch_scale_var(double* U, const double* facp, long long count, hipS
 // reduction words are cleared for the next fold
 hipError_t launch_dt_update(unsigned long long* red, double* pp, double* t, unsigned* err, double cfl, double t_end,
                             double glm_cr, int mhd, hipStream_t st);
-// persistent counters: [1..3] stage work queues, [8] non-physical flag, [9] steps taken
-constexpr int CNT_ERR = 8, CNT_TAKEN = 9;
+// device counters: [8s .. 8s+7] the work queues of stage s = 1..3 (cleared
+// before every step), [CNT_ERR] non-physical flag, [CNT_TAKEN] steps taken
+constexpr int CNT_QUEUES = 32, CNT_ERR = 40, CNT_TAKEN = 41, CNT_COUNT = 64;
 
 // device parameter block (written once per forest, plus dt / ch per step)
 // layout: [0] gamma [1] gm1 [2] igm1 [3] ch [4] dt [5] glm damping factor

@@ -334,6 +334,25 @@ __device__ __forceinline__ int pick_leaf(const Sched& sc, int b) {
   return b;
 }
 
+// next leaf of a persistent workgroup (n when all are taken).  Workgroups are
+// dealt to the 8 XCDs round robin by index; with xcd_remap each XCD first
+// drains its own queue over a contiguous eighth of the (Morton-ordered)
+// leaves, so neighbouring leaves, whose ghost cells each reads from the
+// other, pass through the same L2, then helps with the others' queues.
+__device__ __forceinline__ int queue_next(const Sched& sc, int n) {
+  if (!sc.xcd_remap) return (int)atomicAdd(sc.counter, 1u);
+  const int home = blockIdx.x & 7;
+  for (int j = 0; j < 8; j++) {
+    const int q = (home + j) & 7;
+    const int lo = q * sc.per_xcd;
+    const int len = min(sc.per_xcd, n - lo);
+    if (len <= 0 || __atomic_load_n(sc.counter + q, __ATOMIC_RELAXED) >= (unsigned)len) continue;
+    const unsigned i = atomicAdd(sc.counter + q, 1u);
+    if (i < (unsigned)len) return lo + (int)i;
+  }
+  return n;
+}
+
 template <int ND, bool MHD>
 __device__ __forceinline__ void own_prim(const Geo& g, const double* __restrict__ U, int leaf, int x, int y, int z,
                                          double* v, const PhysParams& P) {
@@ -341,6 +360,21 @@ __device__ __forceinline__ void own_prim(const Geo& g, const double* __restrict_
   double u[NV];
   fetch_cons<NV, ND>(g, U, leaf, x, y, z, u);
   cons2prim<ND, MHD>(u, v, P);
+}
+
+// exchange the x and y components (velocity or momentum, magnetic field) of a
+// state or flux vector
+template <int ND, bool MHD>
+__device__ __forceinline__ void swap_xy(double* q) {
+  using S = Sys<ND, MHD>;
+  double t = q[1];
+  q[1] = q[2];
+  q[2] = t;
+  if constexpr (MHD) {
+    t = q[S::IB];
+    q[S::IB] = q[S::IB + 1];
+    q[S::IB + 1] = t;
+  }
 }
 
 template <int NV>
@@ -388,6 +422,7 @@ __global__ void __launch_bounds__(WGS, (SPLIT && Sys<ND, MHD>::NV <= 5) ? 3 : 1)
   auto& sSy = sS[NSB - 1];
   auto& sFx = sF[0];
   auto& sFy = sF[NSB - 1];
+  __shared__ double sZF[ND == 3 ? NV : 1][ND == 3 ? NB * NB : 1];  // +z coarse-fine face flux of the own column
   __shared__ int sLeaf;
 
   const PhysParams P = load_phys(pp);
@@ -421,7 +456,7 @@ __global__ void __launch_bounds__(WGS, (SPLIT && Sys<ND, MHD>::NV <= 5) ? 3 : 1)
   for (int iter = 0;; iter++) {
     int leaf;
     if (sc.mode == 2) {
-      if (tid == 0) sLeaf = (int)atomicAdd(sc.counter, 1u);
+      if (tid == 0) sLeaf = queue_next(sc, g.n);
       __syncthreads();
       leaf = sLeaf;
       __syncthreads();
@@ -485,6 +520,14 @@ __global__ void __launch_bounds__(WGS, (SPLIT && Sys<ND, MHD>::NV <= 5) ? 3 : 1)
 
     double V0[NV], V1[NV], C2[NV], VLz[NV], Flo[NV], Cr[NV];
     if constexpr (ND == 3) {
+      // a coarse-fine +z face: its flux comes from the fine-flux slabs, staged
+      // here once per leaf so that no plane issues a load it waits for at once
+      if (!(kinds[5] == NB_SAME || kinds[5] == NB_BND)) {
+        double F[NV];
+        cf_flux<NV, ND>(g, leaf, 5, kinds[5], tx, ty, F);
+#pragma unroll
+        for (int v = 0; v < NV; v++) sZF[v][tid] = F[v];
+      }
       double vm2[NV], vm1[NV], c[NV], lo[NV], hi[NV], vlm1[NV];
       own_prim<ND, MHD>(g, a.Uin, leaf, tx, ty, -2, vm2, P);
       own_prim<ND, MHD>(g, a.Uin, leaf, tx, ty, -1, vm1, P);
@@ -508,6 +551,11 @@ __global__ void __launch_bounds__(WGS, (SPLIT && Sys<ND, MHD>::NV <= 5) ? 3 : 1)
       cons2prim<ND, MHD>(c, V0, P);
     }
     if (ring) load_strided<NV>(rptr, rvs, Cr);
+    // vmcnt(0) here and at the end of every plane: the loads of plane k+1 were
+    // issued during plane k, and an explicit full wait where it costs nothing
+    // keeps the compiler from placing conservative waits on the next plane's
+    // fresh prefetches at the top of the loop
+    __builtin_amdgcn_s_waitcnt(0x0F70);
 
     for (int k = 0; k < NZ; k++) {
       double zd[NV];
@@ -522,7 +570,8 @@ __global__ void __launch_bounds__(WGS, (SPLIT && Sys<ND, MHD>::NV <= 5) ? 3 : 1)
           load_strided<NV>(zptr + (pn - NB) * zls, zvs, C2);
         muscl<NV, LIM>(V0, V1, V2, VR1, VL1);
         if (k == NB - 1 && !(kinds[5] == NB_SAME || kinds[5] == NB_BND)) {
-          cf_flux<NV, ND>(g, leaf, 5, kinds[5], tx, ty, Fhi);
+#pragma unroll
+          for (int v = 0; v < NV; v++) Fhi[v] = sZF[v][tid];
         } else {
           riemann<ND, MHD, FLUX, (ND == 3 ? 2 : 0)>(VLz, VR1, Fhi, P);
         }
@@ -584,47 +633,54 @@ __global__ void __launch_bounds__(WGS, (SPLIT && Sys<ND, MHD>::NV <= 5) ? 3 : 1)
           }
         }
       };
-      // (4) face fluxes from the limited states
+      // (4) face fluxes from the limited states.  A y face is solved as an x
+      // face of the state with its x and y components exchanged (and the
+      // flux exchanged back): the arithmetic is the same up to the order of
+      // the first two terms of the v.v and B.B sums, and IEEE addition is
+      // commutative, so the results are identical while a wave holding both
+      // x and y faces runs one Riemann solver instead of two.
       auto fluxes = [&](int t0, int t1) {
         for (int t = t0 + tid; t < t1; t += WGS) {
           const bool yd = t >= NFX;
           const int u = yd ? t - NFX : t;
-          double F[NV];
+          int r, m, bl, st, s0, s1;
           if (!yd) {
-            const int r = u / 17, m = u % 17;
-            const int bf = m == 0 ? 0 : (m == NB ? 1 : -1);
-            if (bf >= 0 && !(kinds[bf] == NB_SAME || kinds[bf] == NB_BND)) {
-              cf_flux<NV, ND>(g, leaf, bf, kinds[bf], r, k, F);
-            } else {
-              double vl[NV], vr[NV];
-              const int bl = (r + 2) * PW + m + 1;
-#pragma unroll
-              for (int v = 0; v < NV; v++) {
-                vl[v] = sP[v][bl] + 0.5 * sSx[v][r * 18 + m];
-                vr[v] = sP[v][bl + 1] - 0.5 * sSx[v][r * 18 + m + 1];
-              }
-              riemann<ND, MHD, FLUX, 0>(vl, vr, F, P);
-            }
-#pragma unroll
-            for (int v = 0; v < NV; v++) sFx[v][u] = F[v];
+            r = u / 17;
+            m = u % 17;
+            bl = (r + 2) * PW + m + 1;
+            st = 1;
+            s0 = r * 18 + m;
+            s1 = s0 + 1;
           } else {
-            const int m = u / NB, r = u % NB;
-            const int bf = m == 0 ? 2 : (m == NB ? 3 : -1);
-            if (bf >= 0 && !(kinds[bf] == NB_SAME || kinds[bf] == NB_BND)) {
-              cf_flux<NV, ND>(g, leaf, bf, kinds[bf], r, k, F);
-            } else {
-              double vl[NV], vr[NV];
-              const int bl = (m + 1) * PW + r + 2;
-#pragma unroll
-              for (int v = 0; v < NV; v++) {
-                vl[v] = sP[v][bl] + 0.5 * sSy[v][m * NB + r];
-                vr[v] = sP[v][bl + PW] - 0.5 * sSy[v][(m + 1) * NB + r];
-              }
-              riemann<ND, MHD, FLUX, 1>(vl, vr, F, P);
-            }
-#pragma unroll
-            for (int v = 0; v < NV; v++) sFy[v][u] = F[v];
+            m = u / NB;
+            r = u % NB;
+            bl = (m + 1) * PW + r + 2;
+            st = PW;
+            s0 = m * NB + r;
+            s1 = s0 + NB;
           }
+          const int bf = m == 0 ? 2 * yd : (m == NB ? 2 * yd + 1 : -1);
+          double F[NV];
+          if (bf >= 0 && !(kinds[bf] == NB_SAME || kinds[bf] == NB_BND)) {
+            cf_flux<NV, ND>(g, leaf, bf, kinds[bf], r, k, F);
+          } else {
+            const double* sl = &sS[yd ? NSB - 1 : 0][0][0];
+            double vl[NV], vr[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+              vl[v] = sP[v][bl] + 0.5 * sl[v * NSX + s0];
+              vr[v] = sP[v][bl + st] - 0.5 * sl[v * NSX + s1];
+            }
+            if (yd) {
+              swap_xy<ND, MHD>(vl);
+              swap_xy<ND, MHD>(vr);
+            }
+            riemann<ND, MHD, FLUX, 0>(vl, vr, F, P);
+            if (yd) swap_xy<ND, MHD>(F);
+          }
+          double* fo = &sF[yd ? NSB - 1 : 0][0][0];
+#pragma unroll
+          for (int v = 0; v < NV; v++) fo[v * NFX + u] = F[v];
         }
       };
       double accx[NV];
@@ -665,6 +721,7 @@ __global__ void __launch_bounds__(WGS, (SPLIT && Sys<ND, MHD>::NV <= 5) ? 3 : 1)
         const double rd[3] = {rdx, rdy, rdz};
         cfl_cell<ND, MHD>(Ui, P, rd, csmax, ccmax, cbad);
       }
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), see above
     }
   }
   if (a.cflred) cfl_fold(a.cflred, csmax, ccmax, cbad);

@@ -168,7 +168,8 @@ def test_schedules_and_graph_are_bitwise_equal():
     outs = []
     for sched, graph, var in [((0, 0, 0), False, 0), ((1, 0, 0), False, 0), ((1, 1, 0), False, 1),
                               ((2, 0, 64), False, 1), ((1, 1, 0), True, 0), ((2, 0, 0), True, 1),
-                              ((0, 0, 0), False, 1)]:
+                              ((0, 0, 0), False, 1), ((2, 1, 0), False, 0), ((2, 1, 24), True, 0),
+                              ((2, 1, 0), False, 1)]:
         G, _ = F.run(f, U, dts=dts, schedule=sched, graph=graph, variant=var)
         outs.append(G)
     for G in outs[1:]:
@@ -215,15 +216,40 @@ def test_device_timed_steps_match_oracle():
     assert np.array_equal(G, R)
     f, U = _blast_small()
     R, _ = oracle.run(f, U, steps=3)
-    for sched in [(2, 0, 0), (1, 1, 0)]:
+    for sched in [(2, 0, 0), (1, 1, 0), (2, 1, 0)]:
         G, _ = F.run(f, U, steps=3, device_dt=True, schedule=sched)
         _report(f"blast device-dt sched {sched}", G, R, f)
+        assert np.array_equal(G, R)
+    # the step count reported by the device (every schedule), to an end time
+    R, dts = oracle.run(f, U, t_end=2e-3)
+    for sched in [(1, 1, 0), (2, 0, 0), (2, 1, 0)]:
+        G, used = F.run(f, U, t_end=2e-3, device_dt=True, schedule=sched, chunk=4)
+        assert len(used) == len(dts), (sched, len(used), len(dts))
         assert np.array_equal(G, R)
     f, U = W.orszag_tang(4)
     R, _ = oracle.run(f, U, steps=30)
     G, _ = F.run(f, U, steps=30, device_dt=True, chunk=10)
     e = _report("ot device-dt", G, R, f)
     assert e.max() <= TOL
+
+
+def test_device_timed_run_reports_nonphysical_state():
+    """A non-physical state met during a device-timed run is reported, with
+    every schedule (the per-step queue reset must not clear the flag)."""
+    F = _gpu()
+    from paper_2004_03275_amd import _native as N
+
+    f, U = W.kh(2)
+    V = U.copy()
+    V[0, 1, 3, 4] = -1.0
+    for sched in [(1, 1, 0), (2, 0, 0), (2, 1, 0)]:
+        g = F.GpuForest(f)
+        g.set_schedule(*sched)
+        g.set_state(V)
+        with pytest.raises(N.AmrvError) as e:
+            g.advance_cfl(3, float("inf"), 0.0)
+        assert e.value.code == N.ENONPHYSICAL, sched
+        g.close()
 
 
 def test_autotune_keeps_state_and_parity():
