@@ -416,7 +416,7 @@ __global__ void __launch_bounds__(WGS, (SPLIT && Sys<ND, MHD>::NV <= 5) ? 3 : 1)
   constexpr int NFX = NB * 17;  // x faces: 16 rows x faces 0..16, [row][face]
   constexpr int NSB = SPLIT ? 1 : 2;
   __shared__ double sP[NV][PW * PW];  // primitive plane incl. x/y ghost ring, (y+2)*PW + x+2
-  __shared__ double sS[NSB][NV][NSX]; // slopes: x [row][cell+1]; y [cell+1][column]
+  __shared__ double sS[NSB][NV][NSX]; // half slopes 0.5*phi: x [row][cell+1]; y [cell+1][column]
   __shared__ double sF[NSB][NV][NFX]; // fluxes: x [row][face]; y [face][column]
   auto& sSx = sS[0];
   auto& sSy = sS[NSB - 1];
@@ -625,7 +625,9 @@ __global__ void __launch_bounds__(WGS, (SPLIT && Sys<ND, MHD>::NV <= 5) ? 3 : 1)
 #pragma unroll
           for (int v = 0; v < NV; v++) {
             const double vm = sP[v][b - st], v0 = sP[v][b], vp = sP[v][b + st];
-            const double sl = limiter<LIM>(v0 - vm, vp - v0);
+            // the half slope, formed once per cell: both face states of the
+            // cell add or subtract the same product 0.5*phi
+            const double sl = 0.5 * limiter<LIM>(v0 - vm, vp - v0);
             if (!yd)
               sSx[v][u] = sl;
             else
@@ -668,8 +670,8 @@ __global__ void __launch_bounds__(WGS, (SPLIT && Sys<ND, MHD>::NV <= 5) ? 3 : 1)
             double vl[NV], vr[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++) {
-              vl[v] = sP[v][bl] + 0.5 * sl[v * NSX + s0];
-              vr[v] = sP[v][bl + st] - 0.5 * sl[v * NSX + s1];
+              vl[v] = sP[v][bl] + sl[v * NSX + s0];
+              vr[v] = sP[v][bl + st] - sl[v * NSX + s1];
             }
             if (yd) {
               swap_xy<ND, MHD>(vl);
