@@ -186,6 +186,45 @@ int amrv_mlp_train(const uint16_t* X, const float* y, const int32_t* order, int6
                    int32_t first_batch, int32_t nbatch, float* w, float* m, float* v, const amrv_train_cfg* cfg,
                    void* d_workspace, size_t ws_bytes, void* hip_stream, float* loss, float* grad);
 
+/* Regrid plan (Sec. 1.3: refinement ratio 2; a block is refined when one of
+ * its cells exceeds the tolerance and coarsened when all of them lie below a
+ * fraction of it).  Host-only, reads no device data.
+ * flags: host int8[nleaves] as from amrv_flag_blocks (+1 split, 0 keep,
+ *   -1 merge).  A leaf flagged +1 below max_level is split into its 2^ndim
+ *   children; a complete group of 2^ndim sibling leaves, all flagged -1 and
+ *   above level 1, is merged into its parent.  2:1 balance over faces, edges
+ *   and corners is kept by also splitting every leaf that touches a split
+ *   leaf from one level coarser (until nothing changes), and by keeping a
+ *   group whose parent would touch a leaf ending more than one level finer
+ *   (other merges not counted).
+ * Order of the new list: unchanged leaves in place, a split leaf replaced by
+ *   its children (child index ox + 2 oy + 4 oz), a merged group by its parent
+ *   at the position of the group's first member; a Morton-ordered forest
+ *   stays Morton ordered.
+ * new_level [capacity], new_ijk [capacity][3]: host arrays owned by the
+ *   caller; *new_n receives the new leaf count.  If it exceeds capacity,
+ *   nothing else is written and AMRV_ENOMEM is returned (query with
+ *   capacity 0 first). */
+int amrv_regrid_plan(const amrv_forest* f, const int8_t* flags, int64_t capacity, int64_t* new_n,
+                     int32_t* new_level, int32_t* new_ijk);
+/* The same plan for a leaf list given on the host (cfg, n, level, ijk as
+ * for amrv_forest_create), without a forest or a GPU. */
+int amrv_regrid_plan_leaves(const amrv_config* cfg, int64_t nleaves, const int32_t* leaf_level,
+                            const int32_t* leaf_ijk, const int8_t* flags, int64_t capacity, int64_t* new_n,
+                            int32_t* new_level, int32_t* new_ijk);
+/* Move the current state U^n of `from` onto `to`, a forest created (same
+ * configuration, its own workspace) on a one-level regrid of `from`'s leaves
+ * (e.g. the list of amrv_regrid_plan).  A leaf of `to` that is a leaf of
+ * `from` is copied; a child of a leaf of `from` gets the parent cell plus a
+ * quarter of its minmod-limited slope per dimension, added on the cell's
+ * upper half (conservative linear prolongation, the parent's ghost cells at
+ * its boundary); a parent of 2^ndim leaves of `from` gets the pairwise-tree
+ * sum of its children's cells times 2^-ndim (restriction).  Runs on both
+ * forests' streams and returns after the transfer has completed; `from` is
+ * unchanged apart from its ghost slabs.  AMRV_EINVAL if the configurations
+ * differ or a leaf of `to` has no source. */
+int amrv_regrid_transfer(amrv_forest* from, amrv_forest* to);
+
 /* Select the schedule of the stage update (AMRV_SCHED_*).  xcd_remap != 0
  * keeps consecutive leaves on the same XCD (grid: the workgroup-to-leaf map;
  * persistent: one work queue per XCD over an eighth of the leaves, drained

@@ -63,6 +63,8 @@ def lib():
         L.orc_padded_block.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64]
         L.orc_face_kinds.argtypes = [P, ctypes.c_int64, P]
         L.orc_lohner_cells.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64]
+        L.orc_regrid_plan.argtypes = [P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P, P]
+        L.orc_regrid_transfer.argtypes = [P, P]
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_set_threads.restype = None
         L.orc_get_threads.restype = ctypes.c_int
@@ -189,6 +191,32 @@ class OracleForest:
         k = np.empty(2 * self.scheme.ndim, dtype=np.int32)
         _check(lib().orc_face_kinds(self._h, int(leaf), k.ctypes.data))
         return k
+
+
+    def regrid_plan(self, flags) -> tuple:
+        """(level [m], ijk [m, 3]) of the regridded forest for these flags."""
+        flags = np.ascontiguousarray(flags, dtype=np.int8)
+        assert flags.shape == (self.forest.n,)
+        m = ctypes.c_int64()
+        lib().orc_regrid_plan(self._h, flags.ctypes.data, 0, ctypes.byref(m), None, None)
+        lev = np.empty(max(m.value, 1), dtype=np.int32)
+        ijk = np.empty((max(m.value, 1), 3), dtype=np.int32)
+        _check(lib().orc_regrid_plan(self._h, flags.ctypes.data, m.value, ctypes.byref(m), lev.ctypes.data,
+                                     ijk.ctypes.data))
+        return lev[:m.value], ijk[:m.value]
+
+    def regrid(self, flags) -> "OracleForest":
+        """A new oracle forest on the regridded leaves, holding the transferred state."""
+        from paper_2004_03275_amd import workloads as W
+
+        lev, ijk = self.regrid_plan(flags)
+        g = OracleForest(W.Forest(self.scheme, lev, ijk))
+        _check(lib().orc_regrid_transfer(self._h, g._h))
+        return g
+
+    def transfer_to(self, other: "OracleForest"):
+        """Move this forest's state onto `other` (a one-level regrid of it)."""
+        _check(lib().orc_regrid_transfer(self._h, other._h))
 
 
 def run(forest, U0: np.ndarray, *, t_end: float | None = None, steps: int | None = None,

@@ -1205,3 +1205,291 @@ int orc_lohner_cells(orc_forest* f, int64_t leaf, double* out, int64_t n_doubles
   free(prs);
   return ok ? ORC_OK : fail(ORC_ENOMEM, "out of memory");
 }
+
+/* ------------------------------------------------------------------ */
+/* regridding (Sec. 1.3): refine flagged blocks into 2^ndim children,   */
+/* coarsen complete sibling groups whose members are all flagged for    */
+/* coarsening, keep the forest 2:1 balanced                             */
+/* ------------------------------------------------------------------ */
+
+/* Leaves touching block (l, c) across offset o (each o_d in -1, 0, 1): the
+ * leaf covering the neighbouring block region at level l, l-1 or l-2, or the
+ * leaves at levels l+1 and l+2 inside it that touch block (l, c).  Calls
+ * visit(leaf) for each; returns 0 if the region lies outside a non-periodic
+ * domain. */
+typedef void (*leaf_visit)(const orc_forest* f, int64_t leaf, void* ctx);
+
+static void touching_finer(const orc_forest* f, int l, const int64_t r[3], const int o[3], int depth,
+                           leaf_visit visit, void* ctx) {
+  /* leaves at level l+depth inside region (l, r) that touch its side facing -o */
+  int64_t span = (int64_t)1 << depth;
+  int64_t lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+  for (int e = 0; e < f->nd; e++) {
+    lo[e] = r[e] * span;
+    hi[e] = lo[e] + span;
+    if (o[e] == 1) hi[e] = lo[e] + 1;         /* neighbour on the +side: its low layer touches */
+    if (o[e] == -1) lo[e] = hi[e] - 1;        /* neighbour on the -side: its high layer touches */
+  }
+  for (int64_t k = lo[2]; k < hi[2]; k++)
+    for (int64_t j = lo[1]; j < hi[1]; j++)
+      for (int64_t i = lo[0]; i < hi[0]; i++) {
+        int64_t c[3] = {i, j, k};
+        int64_t x = lookup(f, l + depth, c);
+        if (x >= 0) visit(f, x, ctx);
+      }
+}
+
+static int touching_leaves(const orc_forest* f, int l, const int64_t c[3], const int o[3], leaf_visit visit,
+                           void* ctx) {
+  int64_t r[3] = {c[0], c[1], c[2]};
+  for (int e = 0; e < f->nd; e++) {
+    r[e] += o[e];
+    if (!wrap(f, e, &r[e], nblk(f, l, e))) return 0;
+  }
+  for (int up = 0; up <= 2 && l - up >= 1; up++) {
+    int64_t p[3] = {r[0] >> up, r[1] >> up, r[2] >> up};
+    for (int e = f->nd; e < 3; e++) p[e] = 0;
+    int64_t x = lookup(f, l - up, p);
+    if (x >= 0) {
+      visit(f, x, ctx);
+      return 1;
+    }
+  }
+  for (int depth = 1; depth <= 2; depth++) touching_finer(f, l, r, o, depth, visit, ctx);
+  return 1;
+}
+
+typedef struct {
+  int32_t* tgt;
+  int lvl;       /* refine: the refining leaf's level; coarsen: the group's level */
+  int changed;   /* refine: a coarser neighbour was marked */
+  int violates;  /* coarsen: a neighbour ends finer than the group level */
+} regrid_ctx;
+
+/* refining a leaf of level l puts children at l+1: a touching leaf of level
+ * l-1 must refine too (2:1 balance over faces, edges and corners) */
+static void visit_refine(const orc_forest* f, int64_t a, void* p) {
+  regrid_ctx* x = (regrid_ctx*)p;
+  if (f->lev[a] == x->lvl - 1 && x->tgt[a] == f->lev[a]) {
+    x->tgt[a] = f->lev[a] + 1;
+    x->changed = 1;
+  }
+}
+
+/* a group of level l coarsens to l-1: every touching leaf must end at a
+ * level <= l */
+static void visit_coarsen(const orc_forest* f, int64_t a, void* p) {
+  regrid_ctx* x = (regrid_ctx*)p;
+  (void)f;
+  if (x->tgt[a] > x->lvl) x->violates = 1;
+}
+
+static void offsets(int nd, int idx, int o[3]) {
+  /* idx in 0 .. 3^nd - 1 -> offset vector in {-1,0,1}^nd */
+  for (int e = 0; e < 3; e++) {
+    o[e] = e < nd ? idx % 3 - 1 : 0;
+    idx /= 3;
+  }
+}
+
+int orc_regrid_plan(const orc_forest* f, const int8_t* flags, int64_t cap, int64_t* new_n, int32_t* new_lev,
+                    int32_t* new_ijk) {
+  if (!f || !flags || !new_n || cap < 0 || (cap > 0 && (!new_lev || !new_ijk)))
+    return fail(ORC_EINVAL, "null argument");
+  const int nd = f->nd, nch = 1 << nd, noff = nd == 1 ? 3 : (nd == 2 ? 9 : 27);
+  int32_t* tgt = (int32_t*)malloc(sizeof(int32_t) * f->n);
+  int64_t* grp = (int64_t*)malloc(sizeof(int64_t) * f->n); /* first member of the coarsening group, or -1 */
+  if (!tgt || !grp) {
+    free(tgt);
+    free(grp);
+    return fail(ORC_ENOMEM, "out of memory");
+  }
+  /* 1. requested refinements */
+  for (int64_t b = 0; b < f->n; b++) {
+    tgt[b] = f->lev[b] + ((flags[b] > 0 && f->lev[b] < f->c.max_level) ? 1 : 0);
+    grp[b] = -1;
+  }
+  /* 2. balance: refine coarser touching leaves until nothing changes */
+  regrid_ctx x = {tgt, 0, 1, 0};
+  while (x.changed) {
+    x.changed = 0;
+    for (int64_t b = 0; b < f->n; b++) {
+      if (tgt[b] == f->lev[b]) continue;
+      int64_t c[3] = {f->ijk[3 * b], f->ijk[3 * b + 1], f->ijk[3 * b + 2]};
+      x.lvl = f->lev[b];
+      for (int i = 0; i < noff; i++) {
+        int o[3];
+        offsets(nd, i, o);
+        if (o[0] == 0 && o[1] == 0 && o[2] == 0) continue;
+        touching_leaves(f, f->lev[b], c, o, visit_refine, &x);
+      }
+    }
+  }
+  /* 3. coarsening: complete sibling groups, all flagged -1, none refining,
+   * whose parent would stay balanced against the final levels of step 2 */
+  for (int64_t b = 0; b < f->n; b++) {
+    int l = f->lev[b];
+    if (flags[b] >= 0 || l <= 1 || tgt[b] != l || grp[b] >= 0) continue;
+    int64_t P[3] = {f->ijk[3 * b] >> 1, f->ijk[3 * b + 1] >> 1, f->ijk[3 * b + 2] >> 1};
+    for (int e = nd; e < 3; e++) P[e] = 0;
+    int64_t mem[8];
+    int ok = 1;
+    for (int q = 0; q < nch && ok; q++) {
+      int64_t ch[3] = {0, 0, 0};
+      for (int e = 0; e < nd; e++) ch[e] = 2 * P[e] + ((q >> e) & 1);
+      mem[q] = lookup(f, l, ch);
+      if (mem[q] < 0 || flags[mem[q]] >= 0 || tgt[mem[q]] != l) ok = 0;
+    }
+    if (!ok) continue;
+    regrid_ctx y = {tgt, l, 0, 0};
+    for (int i = 0; i < noff; i++) {
+      int o[3];
+      offsets(nd, i, o);
+      if (o[0] == 0 && o[1] == 0 && o[2] == 0) continue;
+      touching_leaves(f, l - 1, P, o, visit_coarsen, &y);
+    }
+    if (y.violates) continue;
+    int64_t first = mem[0];
+    for (int q = 1; q < nch; q++)
+      if (mem[q] < first) first = mem[q];
+    for (int q = 0; q < nch; q++) grp[mem[q]] = first;
+  }
+  /* 4. the new leaf list: unchanged leaves in place, a refined leaf replaced
+   * by its children (child index ox + 2 oy + 4 oz), a coarsened group by its
+   * parent at the position of the group's first member */
+  int64_t m = 0;
+  for (int64_t b = 0; b < f->n; b++) {
+    if (grp[b] >= 0 && grp[b] != b) continue;
+    int cnt = (tgt[b] > f->lev[b]) ? nch : 1;
+    for (int q = 0; q < cnt; q++, m++) {
+      if (m >= cap) continue;
+      if (grp[b] == b) {
+        new_lev[m] = f->lev[b] - 1;
+        for (int e = 0; e < 3; e++) new_ijk[3 * m + e] = e < nd ? f->ijk[3 * b + e] >> 1 : 0;
+      } else if (cnt > 1) {
+        new_lev[m] = f->lev[b] + 1;
+        for (int e = 0; e < 3; e++) new_ijk[3 * m + e] = e < nd ? 2 * f->ijk[3 * b + e] + ((q >> e) & 1) : 0;
+      } else {
+        new_lev[m] = f->lev[b];
+        for (int e = 0; e < 3; e++) new_ijk[3 * m + e] = f->ijk[3 * b + e];
+      }
+    }
+  }
+  free(tgt);
+  free(grp);
+  *new_n = m;
+  if (m > cap) return fail(ORC_ENOMEM, "capacity %lld below the new leaf count %lld", (long long)cap, (long long)m);
+  return ORC_OK;
+}
+
+/* Move the state of `from` onto the leaves of `to`, a forest whose every leaf
+ * is a leaf of `from`, a child of one (refinement: conservative linear
+ * prolongation of the parent's cells, the same formula as for coarse-fine
+ * ghosts, with the parent's ghost cells for its boundary cells), or the
+ * parent of 2^ndim leaves of `from` (coarsening: restriction, the pairwise
+ * tree sum of the children's cells times 2^-ndim). */
+int orc_regrid_transfer(orc_forest* from, orc_forest* to) {
+  if (!from || !to) return fail(ORC_EINVAL, "null argument");
+  const orc_config *a = &from->c, *b = &to->c;
+  int same = a->ndim == b->ndim && a->physics == b->physics && a->max_level == b->max_level;
+  for (int d = 0; d < 3; d++)
+    same = same && a->block_nx[d] == b->block_nx[d] && a->base_blocks[d] == b->base_blocks[d] &&
+           a->bc[d][0] == b->bc[d][0];
+  if (!same) return fail(ORC_EINVAL, "the two forests differ in their configuration");
+  const orc_forest* f = from;
+  const int nd = f->nd, nv = f->nvar, nch = 1 << nd;
+  /* classify every new leaf first, so that a bad target changes nothing */
+  int64_t* src = (int64_t*)malloc(sizeof(int64_t) * to->n * 8);
+  int8_t* how = (int8_t*)malloc(to->n);
+  double* W = (double*)malloc(sizeof(double) * nv * f->npad);
+  double* Wc = (double*)malloc(sizeof(double) * nv * f->npad);
+  double* out = (double*)malloc(sizeof(double) * nv * to->n * to->ncell);
+  if (!src || !how || !W || !Wc || !out) {
+    free(src), free(how), free(W), free(Wc), free(out);
+    return fail(ORC_ENOMEM, "out of memory");
+  }
+  int bad = 0;
+  for (int64_t n = 0; n < to->n && !bad; n++) {
+    int l = to->lev[n];
+    int64_t c[3] = {to->ijk[3 * n], to->ijk[3 * n + 1], to->ijk[3 * n + 2]};
+    int64_t x = lookup(f, l, c);
+    if (x >= 0) {
+      how[n] = 0;
+      src[8 * n] = x;
+      continue;
+    }
+    int64_t p[3] = {c[0] >> 1, c[1] >> 1, c[2] >> 1};
+    for (int e = nd; e < 3; e++) p[e] = 0;
+    x = l > 1 ? lookup(f, l - 1, p) : -1;
+    if (x >= 0) {
+      how[n] = 1;
+      src[8 * n] = x;
+      continue;
+    }
+    how[n] = 2;
+    for (int q = 0; q < nch; q++) {
+      int64_t ch[3] = {0, 0, 0};
+      for (int e = 0; e < nd; e++) ch[e] = 2 * c[e] + ((q >> e) & 1);
+      src[8 * n + q] = lookup(f, l + 1, ch);
+      if (src[8 * n + q] < 0) bad = 1;
+    }
+  }
+  if (bad) {
+    free(src), free(how), free(W), free(Wc), free(out);
+    return fail(ORC_EINVAL, "the target forest is not a one-level regrid of the source forest");
+  }
+  const int h[3] = {f->nx[0] / 2, nd > 1 ? f->nx[1] / 2 : 0, nd > 2 ? f->nx[2] / 2 : 0};
+  for (int64_t n = 0; n < to->n; n++) {
+    if (how[n] == 1) fill_all(f, f->U, src[8 * n], W, Wc);
+    for (int k = 0; k < f->nx[2]; k++)
+      for (int j = 0; j < f->nx[1]; j++)
+        for (int i = 0; i < f->nx[0]; i++) {
+          int x[3] = {i, j, k};
+          int64_t dst = cidx(f, i, j, k);
+          for (int v = 0; v < nv; v++) {
+            double r;
+            if (how[n] == 0) {
+              r = st(f, f->U, v, src[8 * n], dst);
+            } else if (how[n] == 1) {
+              /* child offset within the parent and the parent cell */
+              int pc[3] = {0, 0, 0};
+              for (int e = 0; e < nd; e++) pc[e] = (int)(to->ijk[3 * n + e] & 1) * h[e] + x[e] / 2;
+              const double* w = W + (int64_t)v * f->npad;
+              double u0 = w[pidx(f, pc[0], pc[1], pc[2])];
+              r = u0;
+              for (int e = 0; e < nd; e++) {
+                int lo[3] = {pc[0], pc[1], pc[2]}, hi[3] = {pc[0], pc[1], pc[2]};
+                lo[e] -= 1;
+                hi[e] += 1;
+                double t = 0.25 * minmod(u0 - w[pidx(f, lo[0], lo[1], lo[2])], w[pidx(f, hi[0], hi[1], hi[2])] - u0);
+                r = (x[e] & 1) ? r + t : r - t;
+              }
+            } else {
+              /* the child holding this cell, and its 2^ndim fine cells */
+              int q = 0, y[3] = {0, 0, 0};
+              for (int e = 0; e < nd; e++) {
+                int qe = x[e] / h[e];
+                q |= qe << e;
+                y[e] = 2 * (x[e] - qe * h[e]);
+              }
+              double c8[8];
+              for (int a2 = 0; a2 < nch; a2++) {
+                int z[3] = {y[0], y[1], y[2]};
+                for (int e = 0; e < nd; e++) z[e] += (a2 >> e) & 1;
+                c8[a2] = st(f, f->U, v, src[8 * n + q], cidx(f, z[0], z[1], z[2]));
+              }
+              if (nd == 1)
+                r = (c8[0] + c8[1]) * 0.5;
+              else if (nd == 2)
+                r = ((c8[0] + c8[1]) + (c8[2] + c8[3])) * 0.25;
+              else
+                r = (((c8[0] + c8[1]) + (c8[2] + c8[3])) + ((c8[4] + c8[5]) + (c8[6] + c8[7]))) * 0.125;
+            }
+            out[((int64_t)v * to->n + n) * to->ncell + dst] = r;
+          }
+        }
+  }
+  memcpy(to->U, out, sizeof(double) * nv * to->n * to->ncell);
+  free(src), free(how), free(W), free(Wc), free(out);
+  return ORC_OK;
+}

@@ -80,6 +80,24 @@ int orc_padded_block(orc_forest* f, int64_t leaf, double* out, int64_t n_doubles
 int orc_face_kinds(const orc_forest* f, int64_t leaf, int32_t* kinds);
 /* Test hook: per-cell weighted Loehner estimator of one leaf, [cell]. */
 int orc_lohner_cells(orc_forest* f, int64_t leaf, double* out, int64_t n_doubles);
+/* Regrid plan (Sec. 1.3, refinement ratio 2): leaves flagged +1 (below
+ * max_level) are split into 2^ndim children; a complete group of 2^ndim
+ * sibling leaves all flagged -1 (above level 1) is merged into its parent;
+ * 2:1 balance over faces, edges and corners is kept by refining every leaf
+ * that touches a refined leaf from one level coarser (repeated until
+ * nothing changes) and by keeping a group whose parent would touch a leaf
+ * ending more than one level finer (other coarsenings ignored).  New order:
+ * unchanged leaves in place, a refined leaf replaced by its children (child
+ * index ox + 2 oy + 4 oz), a merged group by its parent at the position of
+ * the group's first member.  Writes up to `cap` leaves to new_level /
+ * new_ijk [cap][3]; *new_n is the new leaf count (ORC_ENOMEM if > cap). */
+int orc_regrid_plan(const orc_forest* f, const int8_t* flags, int64_t cap, int64_t* new_n, int32_t* new_level,
+                    int32_t* new_ijk);
+/* State of `from` onto `to` (a one-level regrid of it, same configuration):
+ * copied leaves, children by conservative linear prolongation of the parent
+ * (coarse value plus a quarter minmod slope per dimension, the parent's ghost
+ * cells at its boundary), parents by restriction of their children. */
+int orc_regrid_transfer(orc_forest* from, orc_forest* to);
 void orc_set_threads(int n);
 int orc_get_threads(void);
 const char* orc_last_error(void);

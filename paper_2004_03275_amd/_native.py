@@ -106,6 +106,10 @@ SIGNATURES = {
     "amrv_profile": ([P, ctypes.c_int32], ctypes.c_int),
     "amrv_profile_read": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                            ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "amrv_regrid_plan": ([P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P, P], ctypes.c_int),
+    "amrv_regrid_plan_leaves": ([ctypes.POINTER(Config), ctypes.c_int64, P, P, P, ctypes.c_int64,
+                                 ctypes.POINTER(ctypes.c_int64), P, P], ctypes.c_int),
+    "amrv_regrid_transfer": ([P, P], ctypes.c_int),
     "amrv_synchronize": ([P], ctypes.c_int),
     "amrv_last_error": ([], ctypes.c_char_p),
 }
@@ -157,3 +161,26 @@ def make_config(s) -> Config:
     c.lohner_w_p = s.lohner_w_p
     c.glm_cr = s.glm_cr
     return c
+
+
+def regrid_plan_leaves(forest, flags) -> tuple:
+    """Host-only regrid plan of a workloads.Forest: (level [m], ijk [m, 3])."""
+    import numpy as np
+
+    cfg = make_config(forest.scheme)
+    lev = np.ascontiguousarray(forest.level, dtype=np.int32)
+    ijk = np.ascontiguousarray(forest.ijk, dtype=np.int32)
+    flags = np.ascontiguousarray(flags, dtype=np.int8)
+    if flags.shape != (forest.n,):
+        raise ValueError("one flag per leaf")
+    m = ctypes.c_int64()
+    L = lib()
+    rc = L.amrv_regrid_plan_leaves(ctypes.byref(cfg), forest.n, lev.ctypes.data, ijk.ctypes.data, flags.ctypes.data,
+                                   0, ctypes.byref(m), None, None)
+    if rc not in (OK, ENOMEM):
+        check(rc)
+    out_l = np.empty(max(m.value, 1), dtype=np.int32)
+    out_i = np.empty((max(m.value, 1), 3), dtype=np.int32)
+    check(L.amrv_regrid_plan_leaves(ctypes.byref(cfg), forest.n, lev.ctypes.data, ijk.ctypes.data, flags.ctypes.data,
+                                    m.value, ctypes.byref(m), out_l.ctypes.data, out_i.ctypes.data))
+    return out_l[:m.value], out_i[:m.value]

@@ -13,6 +13,7 @@
 
 #include "../../include/amrv.h"
 #include "forest.hpp"
+#include "regrid.hpp"
 #include "internal.hpp"
 #include "mlp.hpp"
 
@@ -42,7 +43,7 @@ constexpr size_t ALIGN = 256;
 struct Layout {
   size_t off_U[3], off_G, off_FF, off_lvl, off_ijk, off_nbr, off_slot, off_kind, off_fslot, off_sleaf, off_sface,
       off_rlist, off_plist, off_pp, off_lp, off_red, off_cnt, off_emax, off_flags, off_mw, off_mwb, off_mx, off_mz,
-      off_munc, total;
+      off_munc, off_xfer, total;
 };
 
 Layout plan(const Tables& t) {
@@ -78,6 +79,7 @@ Layout plan(const Tables& t) {
   L.off_mx = take(sizeof(uint16_t) * MLP_NIN * t.n);
   L.off_mz = take(sizeof(float) * t.n);
   L.off_munc = take(sizeof(int8_t) * t.n);
+  L.off_xfer = take(sizeof(int32_t) * XFER_STRIDE * t.n);
   L.total = o;
   return L;
 }
@@ -116,6 +118,7 @@ struct amrv_forest {
   bool have_mlp = false;
   float margin = 2.0f;
   std::string tune_report;  // the last autotune's timing table
+  std::vector<int32_t> xfer_host;  // regrid sources while their upload is in flight
 };
 
 namespace {
@@ -602,6 +605,67 @@ int amrv_mlp_train(const uint16_t* X, const float* y, const int32_t* order, int6
   TrainHyper hp{cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, cfg->pos_weight};
   HIPCHK(launch_mlp_train(X, y, order, (int)n, batch, first_batch, nbatch, w, m, v, hp, cfg->t0, ws, loss, grad,
                           (hipStream_t)stream));
+  return AMRV_OK;
+}
+
+int amrv_regrid_plan(const amrv_forest* f, const int8_t* flags, int64_t capacity, int64_t* new_n,
+                     int32_t* new_level, int32_t* new_ijk) {
+  if (!f || !flags || !new_n || capacity < 0 || (capacity > 0 && (!new_level || !new_ijk)))
+    return fail(AMRV_EINVAL, "null argument");
+  std::vector<int32_t> lev, ijk;
+  std::string err;
+  const int rc = regrid_plan(f->cfg, f->tab, flags, lev, ijk, err);
+  if (rc) return fail(rc, err);
+  *new_n = (int64_t)lev.size();
+  if (*new_n > capacity)
+    return fail(AMRV_ENOMEM, "capacity " + std::to_string(capacity) + " below the new leaf count " +
+                                 std::to_string(*new_n));
+  std::copy(lev.begin(), lev.end(), new_level);
+  std::copy(ijk.begin(), ijk.end(), new_ijk);
+  return AMRV_OK;
+}
+
+int amrv_regrid_plan_leaves(const amrv_config* cfg, int64_t n, const int32_t* lev, const int32_t* ijk,
+                            const int8_t* flags, int64_t capacity, int64_t* new_n, int32_t* new_level,
+                            int32_t* new_ijk) {
+  if (!cfg || !flags || !new_n || capacity < 0 || (capacity > 0 && (!new_level || !new_ijk)))
+    return fail(AMRV_EINVAL, "null argument");
+  Tables t;
+  int rc = build_tables(*cfg, n, lev, ijk, t);
+  if (rc) return fail(rc, t.err);
+  std::vector<int32_t> nl, nijk;
+  std::string err;
+  rc = regrid_plan(*cfg, t, flags, nl, nijk, err);
+  if (rc) return fail(rc, err);
+  *new_n = (int64_t)nl.size();
+  if (*new_n > capacity)
+    return fail(AMRV_ENOMEM, "capacity " + std::to_string(capacity) + " below the new leaf count " +
+                                 std::to_string(*new_n));
+  std::copy(nl.begin(), nl.end(), new_level);
+  std::copy(nijk.begin(), nijk.end(), new_ijk);
+  return AMRV_OK;
+}
+
+int amrv_regrid_transfer(amrv_forest* from, amrv_forest* to) {
+  if (!from || !to || from == to) return fail(AMRV_EINVAL, "two distinct forests are needed");
+  const amrv_config &a = from->cfg, &b = to->cfg;
+  bool same = a.ndim == b.ndim && a.physics == b.physics && a.max_level == b.max_level;
+  for (int d = 0; d < 3; d++)
+    same = same && a.block_nx[d] == b.block_nx[d] && a.base_blocks[d] == b.base_blocks[d] && a.bc[d][0] == b.bc[d][0];
+  if (!same) return fail(AMRV_EINVAL, "the two forests differ in their configuration");
+  std::string err;
+  int rc = regrid_sources(from->tab, to->tab, to->xfer_host, err);
+  if (rc) return fail(rc, err);
+  int32_t* xf = (int32_t*)(to->ws + to->lay.off_xfer);
+  // ghost slabs of the source state (coarse-fine faces), then the transfer
+  rc = enqueue_ghosts(from, from->U[0], false);
+  if (rc) return rc;
+  if (from->st != to->st) HIPCHK(hipStreamSynchronize(from->st));
+  HIPCHK(hipMemcpyAsync(xf, to->xfer_host.data(), sizeof(int32_t) * to->xfer_host.size(), hipMemcpyHostToDevice,
+                        to->st));
+  HIPCHK(launch_transfer(from->geo, from->U[0], to->geo, to->U[0], xf, to->lc, to->st));
+  HIPCHK(hipStreamSynchronize(to->st));
+  to->ch = from->ch;
   return AMRV_OK;
 }
 

@@ -82,6 +82,11 @@ hipError_t launch_cfl(const Geo& g, const LaunchCfg& c, const double* U, const d
 hipError_t launch_lohner(const Geo& g, const LaunchCfg& c, const double* U, const double* physp,
                          const double* lohp, int max_level, double* emax, int8_t* flags, const int8_t* only,
                          hipStream_t st);
+// regrid: state of the leaves of `to` from the state Uf of `from` (whose
+// coarse-fine ghost slabs must hold Uf's ghosts); xfer[n_to][9] per new leaf:
+// how (0 copy, 1 prolong from the parent, 2 restrict the children) and sources
+hipError_t launch_transfer(const Geo& from, const double* Uf, const Geo& to, double* Ut, const int32_t* xfer,
+                           const LaunchCfg& c, hipStream_t st);
 hipError_t launch_set_scalars(double* dst, const double* src_host_vals, int n, hipStream_t st);
 hipError_t launch_reset_u32(unsigned* p, int n, hipStream_t st);
 hipError_t launch_scale_var(double* U, const double* facp, long long count, hipStream_t st);

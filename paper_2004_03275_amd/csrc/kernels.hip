@@ -325,6 +325,89 @@ __global__ void __launch_bounds__(WGS) k_fineflux(Geo g, const double* __restric
 }
 
 // ---------------------------------------------------------------------------
+// regrid transfer (Sec. 1.3, refinement ratio 2): one workgroup per new leaf.
+// A copied leaf takes its old cells; a child of a split leaf takes, per cell,
+// the parent cell plus a quarter of its minmod slope per dimension (x, y, z
+// order, added on the upper half), with the parent's ghost cells at its
+// boundary; a merged parent takes the pairwise-tree sum of the 2^d child
+// cells times 2^-d.  The same formulas as the coarse-fine ghost slabs.
+// ---------------------------------------------------------------------------
+
+template <int ND, int NV>
+__global__ void __launch_bounds__(WGS) k_transfer(Geo gf, const double* __restrict__ Uf, Geo gt,
+                                                  double* __restrict__ Ut, const int32_t* __restrict__ xf) {
+  const int leaf = blockIdx.x;
+  if (leaf >= gt.n) return;
+  const int how = xf[leaf * 9];
+  const int nx = gt.nx, h = nx / 2;
+  const size_t vst = (size_t)gt.n * gt.ncell;
+  int off[3] = {0, 0, 0};
+#pragma unroll
+  for (int e = 0; e < ND; e++) off[e] = gt.ijk[3 * leaf + e] & 1;
+  for (int cell = threadIdx.x; cell < gt.ncell; cell += WGS) {
+    int x[3] = {cell % nx, ND > 1 ? (cell / nx) % nx : 0, ND > 2 ? cell / (nx * nx) : 0};
+    double r[NV];
+    if (how == 0) {
+      const int src = xf[leaf * 9 + 1];
+#pragma unroll
+      for (int v = 0; v < NV; v++) r[v] = Uf[uidx(gf, v, src, cell)];
+    } else if (how == 1) {
+      const int par = xf[leaf * 9 + 1];
+      int pc[3] = {0, 0, 0};
+#pragma unroll
+      for (int e = 0; e < ND; e++) pc[e] = off[e] * h + x[e] / 2;
+      double u0[NV];
+      fetch_cons<NV, ND>(gf, Uf, par, pc[0], pc[1], pc[2], u0);
+#pragma unroll
+      for (int v = 0; v < NV; v++) r[v] = u0[v];
+#pragma unroll
+      for (int e = 0; e < ND; e++) {
+        int lo[3] = {pc[0], pc[1], pc[2]}, hi[3] = {pc[0], pc[1], pc[2]};
+        lo[e] -= 1;
+        hi[e] += 1;
+        double um[NV], up[NV];
+        fetch_cons<NV, ND>(gf, Uf, par, lo[0], lo[1], lo[2], um);
+        fetch_cons<NV, ND>(gf, Uf, par, hi[0], hi[1], hi[2], up);
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+          const double tq = 0.25 * minmod(u0[v] - um[v], up[v] - u0[v]);
+          r[v] = (x[e] & 1) ? r[v] + tq : r[v] - tq;
+        }
+      }
+    } else {
+      int q = 0, y[3] = {0, 0, 0};
+#pragma unroll
+      for (int e = 0; e < ND; e++) {
+        const int qe = x[e] / h;
+        q |= qe << e;
+        y[e] = 2 * (x[e] - qe * h);
+      }
+      const int src = xf[leaf * 9 + 1 + q];
+      double c8[1 << ND][NV];
+#pragma unroll
+      for (int a = 0; a < (1 << ND); a++) {
+        const int z0 = y[0] + (a & 1), z1 = y[1] + (ND > 1 ? (a >> 1) & 1 : 0), z2 = y[2] + (ND > 2 ? (a >> 2) & 1 : 0);
+        const int fc = cell_index(gf, z0, z1, z2);
+#pragma unroll
+        for (int v = 0; v < NV; v++) c8[a][v] = Uf[uidx(gf, v, src, fc)];
+      }
+#pragma unroll
+      for (int v = 0; v < NV; v++) {
+        if constexpr (ND == 1)
+          r[v] = (c8[0][v] + c8[1][v]) * 0.5;
+        else if constexpr (ND == 2)
+          r[v] = ((c8[0][v] + c8[1][v]) + (c8[2][v] + c8[3][v])) * 0.25;
+        else
+          r[v] = (((c8[0][v] + c8[1][v]) + (c8[2][v] + c8[3][v])) + ((c8[4][v] + c8[5][v]) + (c8[6][v] + c8[7][v]))) *
+                 0.125;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; v++) Ut[v * vst + (size_t)leaf * gt.ncell + cell] = r[v];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // stage update, 2D / 3D: one 16x16 workgroup per leaf, streaming z-planes
 // ---------------------------------------------------------------------------
 
@@ -1041,6 +1124,29 @@ hipError_t launch_restrict(const Geo& g, const LaunchCfg& c, const double* U, co
     BODY_R
   }
 #undef BODY_R
+  return hipGetLastError();
+}
+
+hipError_t launch_transfer(const Geo& from, const double* Uf, const Geo& to, double* Ut, const int32_t* xfer,
+                           const LaunchCfg& c, hipStream_t st) {
+  if (to.n <= 0) return hipSuccess;
+#define BODY_T                                                                                         \
+  if (c.mhd) {                                                                                         \
+    hipLaunchKernelGGL((k_transfer<ND, Sys<ND, true>::NV>), dim3(to.n), dim3(WGS), 0, st, from, Uf, to, Ut, xfer); \
+  } else {                                                                                             \
+    hipLaunchKernelGGL((k_transfer<ND, Sys<ND, false>::NV>), dim3(to.n), dim3(WGS), 0, st, from, Uf, to, Ut, xfer); \
+  }
+  if (c.ndim == 1) {
+    constexpr int ND = 1;
+    BODY_T
+  } else if (c.ndim == 2) {
+    constexpr int ND = 2;
+    BODY_T
+  } else {
+    constexpr int ND = 3;
+    BODY_T
+  }
+#undef BODY_T
   return hipGetLastError();
 }
 

@@ -1,0 +1,209 @@
+// regrid.cpp -- host-side regrid plan of a block forest (arXiv 2004.03275,
+// Sec. 1.3: refinement ratio 2, a block is refined when flagged, coarsened
+// only when all of its cells are below the coarsening fraction of the
+// tolerance, i.e. when all 2^d siblings of a parent are flagged -1).
+//
+// Rules (the balance of the result is 2:1 over faces, edges and corners):
+//   1. a leaf flagged +1 below max_level is split into its 2^d children;
+//   2. every leaf touching a splitting leaf from one level coarser is split
+//      as well, repeated until nothing changes (worklist over the touching-
+//      leaf lists below);
+//   3. a complete group of 2^d sibling leaves, all flagged -1, none split,
+//      above level 1, is merged into its parent unless a leaf touching the
+//      group ends (after steps 1-2, other merges ignored) finer than the
+//      group's level;
+//   4. new order: unchanged leaves in place, a split leaf replaced by its
+//      children (child index ox + 2 oy + 4 oz), a merged group by its parent
+//      at the position of its first member.
+#include "regrid.hpp"
+
+#include <algorithm>
+#include <unordered_map>
+
+namespace amrv {
+
+namespace {
+
+inline uint64_t leaf_key(int l, int64_t i, int64_t j, int64_t k) {
+  return (uint64_t(l) << 58) | (uint64_t(i) << 39) | (uint64_t(j) << 20) | uint64_t(k);
+}
+
+struct LeafIndex {
+  std::unordered_map<uint64_t, int32_t> m;
+  int32_t at(int l, const int64_t c[3]) const {
+    if (l < 1) return -1;
+    auto it = m.find(leaf_key(l, c[0], c[1], c[2]));
+    return it == m.end() ? -1 : it->second;
+  }
+};
+
+}  // namespace
+
+int regrid_plan(const amrv_config& c, const Tables& t, const int8_t* flags, std::vector<int32_t>& out_lev,
+                std::vector<int32_t>& out_ijk, std::string& err) {
+  const int nd = t.nd, nch = 1 << nd;
+  const int64_t n = t.n;
+  LeafIndex ix;
+  ix.m.reserve((size_t)n * 2);
+  for (int64_t b = 0; b < n; b++)
+    ix.m.emplace(leaf_key(t.lvl[b], t.ijk[3 * b], t.ijk[3 * b + 1], t.ijk[3 * b + 2]), (int32_t)b);
+  auto blocks = [&](int l, int d) -> int64_t { return d < nd ? (int64_t)c.base_blocks[d] << (l - 1) : 1; };
+
+  // touching leaves of every leaf: for each of the 3^d - 1 neighbouring block
+  // positions, the leaf covering it (same level or one coarser) or the finer
+  // leaves of that position adjacent to this leaf
+  std::vector<std::vector<int32_t>> touch((size_t)n);
+  int nofs = 1;
+  for (int d = 0; d < nd; d++) nofs *= 3;
+  for (int64_t b = 0; b < n; b++) {
+    const int l = t.lvl[b];
+    std::vector<int32_t>& tb = touch[(size_t)b];
+    for (int q = 0; q < nofs; q++) {
+      int o[3] = {0, 0, 0};
+      bool zero = true;
+      for (int d = 0, r = q; d < nd; d++, r /= 3) {
+        o[d] = r % 3 - 1;
+        zero = zero && o[d] == 0;
+      }
+      if (zero) continue;
+      int64_t x[3] = {0, 0, 0};
+      bool inside = true;
+      for (int d = 0; d < nd; d++) {
+        x[d] = t.ijk[3 * b + d] + o[d];
+        const int64_t ext = blocks(l, d);
+        if (x[d] < 0 || x[d] >= ext) {
+          if (c.bc[d][0] != AMRV_BC_PERIODIC) inside = false;
+          x[d] = ((x[d] % ext) + ext) % ext;
+        }
+      }
+      if (!inside) continue;
+      int32_t a = ix.at(l, x);
+      if (a < 0) {
+        const int64_t p[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
+        a = ix.at(l - 1, p);
+      }
+      if (a >= 0) {
+        tb.push_back(a);
+        continue;
+      }
+      for (int ch = 0; ch < nch; ch++) {
+        int64_t y[3] = {0, 0, 0};
+        bool adj = true;
+        for (int d = 0; d < nd; d++) {
+          const int bit = (ch >> d) & 1;
+          if ((o[d] > 0 && bit) || (o[d] < 0 && !bit)) adj = false;
+          y[d] = 2 * x[d] + bit;
+        }
+        if (!adj) continue;
+        const int32_t f = ix.at(l + 1, y);
+        if (f >= 0) tb.push_back(f);
+      }
+    }
+    std::sort(tb.begin(), tb.end());
+    tb.erase(std::unique(tb.begin(), tb.end()), tb.end());
+    tb.erase(std::remove(tb.begin(), tb.end(), (int32_t)b), tb.end());
+  }
+
+  // steps 1-2: final level of every leaf after splitting
+  std::vector<int32_t> fin(t.lvl.begin(), t.lvl.end());
+  std::vector<int32_t> work;
+  for (int64_t b = 0; b < n; b++)
+    if (flags[b] > 0 && t.lvl[b] < c.max_level) {
+      fin[b] = t.lvl[b] + 1;
+      work.push_back((int32_t)b);
+    }
+  while (!work.empty()) {
+    const int32_t b = work.back();
+    work.pop_back();
+    for (int32_t a : touch[(size_t)b])
+      if (t.lvl[a] == t.lvl[b] - 1 && fin[a] == t.lvl[a]) {
+        fin[a] = t.lvl[a] + 1;
+        work.push_back(a);
+      }
+  }
+
+  // step 3: merges; head[b] = first member (list order) of b's merged group
+  std::vector<int32_t> head((size_t)n, -1);
+  for (int64_t b = 0; b < n; b++) {
+    const int l = t.lvl[b];
+    if (flags[b] >= 0 || l <= 1 || fin[b] != l || head[b] >= 0) continue;
+    int32_t mem[8];
+    bool ok = true;
+    for (int ch = 0; ch < nch && ok; ch++) {
+      int64_t y[3] = {0, 0, 0};
+      for (int d = 0; d < nd; d++) y[d] = 2 * (t.ijk[3 * b + d] >> 1) + ((ch >> d) & 1);
+      mem[ch] = ix.at(l, y);
+      ok = mem[ch] >= 0 && flags[mem[ch]] < 0 && fin[mem[ch]] == l;
+    }
+    if (!ok) continue;
+    for (int ch = 0; ch < nch && ok; ch++)
+      for (int32_t a : touch[(size_t)mem[ch]]) {
+        if (std::find(mem, mem + nch, a) != mem + nch) continue;
+        if (fin[a] > l) {
+          ok = false;
+          break;
+        }
+      }
+    if (!ok) continue;
+    const int32_t first = *std::min_element(mem, mem + nch);
+    for (int ch = 0; ch < nch; ch++) head[mem[ch]] = first;
+  }
+
+  // step 4: the new leaf list
+  out_lev.clear();
+  out_ijk.clear();
+  for (int64_t b = 0; b < n; b++) {
+    const int l = t.lvl[b];
+    const int32_t* x = &t.ijk[3 * b];
+    if (head[b] >= 0) {
+      if (head[b] != b) continue;
+      out_lev.push_back(l - 1);
+      for (int d = 0; d < 3; d++) out_ijk.push_back(d < nd ? x[d] >> 1 : 0);
+    } else if (fin[b] > l) {
+      for (int ch = 0; ch < nch; ch++) {
+        out_lev.push_back(l + 1);
+        for (int d = 0; d < 3; d++) out_ijk.push_back(d < nd ? 2 * x[d] + ((ch >> d) & 1) : 0);
+      }
+    } else {
+      out_lev.push_back(l);
+      for (int d = 0; d < 3; d++) out_ijk.push_back(x[d]);
+    }
+  }
+  (void)err;
+  return AMRV_OK;
+}
+
+int regrid_sources(const Tables& from, const Tables& to, std::vector<int32_t>& src, std::string& err) {
+  const int nd = from.nd, nch = 1 << nd;
+  LeafIndex ix;
+  ix.m.reserve((size_t)from.n * 2);
+  for (int64_t b = 0; b < from.n; b++)
+    ix.m.emplace(leaf_key(from.lvl[b], from.ijk[3 * b], from.ijk[3 * b + 1], from.ijk[3 * b + 2]), (int32_t)b);
+  src.assign((size_t)to.n * XFER_STRIDE, -1);
+  for (int64_t b = 0; b < to.n; b++) {
+    const int l = to.lvl[b];
+    const int64_t x[3] = {to.ijk[3 * b], to.ijk[3 * b + 1], to.ijk[3 * b + 2]};
+    int32_t* s = &src[(size_t)b * XFER_STRIDE];
+    if ((s[1] = ix.at(l, x)) >= 0) {
+      s[0] = XFER_COPY;
+      continue;
+    }
+    const int64_t p[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
+    if ((s[1] = ix.at(l - 1, p)) >= 0) {
+      s[0] = XFER_PROLONG;
+      continue;
+    }
+    s[0] = XFER_RESTRICT;
+    for (int ch = 0; ch < nch; ch++) {
+      int64_t y[3] = {0, 0, 0};
+      for (int d = 0; d < nd; d++) y[d] = 2 * x[d] + ((ch >> d) & 1);
+      if ((s[1 + ch] = ix.at(l + 1, y)) < 0) {
+        err = "the target forest is not a one-level regrid of the source forest";
+        return AMRV_EINVAL;
+      }
+    }
+  }
+  return AMRV_OK;
+}
+
+}  // namespace amrv

@@ -103,6 +103,37 @@ class GpuForest:
         N.check(N.lib().amrv_advance_cfl(self._h, int(nsteps), float(t_end), ctypes.byref(tt), ctypes.byref(n)))
         return tt.value, n.value
 
+    def regrid_plan(self, flags) -> tuple:
+        """(level [m], ijk [m, 3]) of the regridded leaf list for these flags."""
+        flags = np.ascontiguousarray(flags, dtype=np.int8)
+        if flags.shape != (self.forest.n,):
+            raise ValueError("one flag per leaf")
+        m = ctypes.c_int64()
+        rc = N.lib().amrv_regrid_plan(self._h, flags.ctypes.data, 0, ctypes.byref(m), None, None)
+        if rc not in (N.OK, N.ENOMEM):
+            N.check(rc)
+        lev = np.empty(max(m.value, 1), dtype=np.int32)
+        ijk = np.empty((max(m.value, 1), 3), dtype=np.int32)
+        N.check(N.lib().amrv_regrid_plan(self._h, flags.ctypes.data, m.value, ctypes.byref(m), lev.ctypes.data,
+                                         ijk.ctypes.data))
+        return lev[:m.value], ijk[:m.value]
+
+    def regrid(self, flags) -> "GpuForest":
+        """A new forest on the regridded leaves (same device and stream,
+        schedule and variant), holding this forest's transferred state."""
+        from . import workloads as W
+
+        lev, ijk = self.regrid_plan(flags)
+        g = GpuForest(W.Forest(self.scheme, lev, ijk), device=self.device, stream=self.stream, config=self.cfg)
+        g.set_schedule(*self.get_schedule())
+        g.set_variant(self.get_variant())
+        N.check(N.lib().amrv_regrid_transfer(self._h, g._h))
+        return g
+
+    def transfer_to(self, other: "GpuForest"):
+        """Move this forest's state onto `other` (a one-level regrid of it)."""
+        N.check(N.lib().amrv_regrid_transfer(self._h, other._h))
+
     def flag_blocks(self, with_emax: bool = False, mode: int = N.FLAG_LOHNER):
         """Refinement flags (+1/0/-1).  with_emax also returns, per leaf, the
         Loehner maximum (LOHNER mode) or the learned flagger's logit (MLP

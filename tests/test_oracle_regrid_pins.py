@@ -1,0 +1,387 @@
+"""Pins of the oracle's regridding (Sec. 1.3: refinement ratio 2, refine when
+a cell exceeds the tolerance, coarsen a parent's complete set of children).
+
+The plan is checked against an independent rasterised model of the forest
+(every leaf painted onto the finest block grid): coverage, 2:1 balance over
+faces, edges and corners, and each rule of the plan (requested splits done,
+forced splits exactly those balance needs, merges exactly the allowed ones,
+order).  The transfer is pinned by conservation, exact reproduction of
+linear data, restriction of a prolongation, exact restriction of piecewise
+constant data and a hand-worked 2D example.  The host-only plan of the HIP
+library (independent C++ code) must equal the oracle's leaf for leaf.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_03275_amd import workloads as W
+
+
+# ---------------------------------------------------------------------------
+# rasterised forest model (independent of the oracle's hash lookups)
+# ---------------------------------------------------------------------------
+
+
+def raster(s, lev, ijk):
+    """owner[finest block] = leaf index; -1 if uncovered; raises on overlap."""
+    nd, L = s.ndim, s.max_level
+    shape = [s.base_blocks[d] << (L - 1) if d < nd else 1 for d in range(3)]
+    own = -np.ones(shape[::-1], dtype=np.int64)  # [z][y][x]
+    for b in range(len(lev)):
+        w = 1 << (L - lev[b])
+        sl = [slice(int(ijk[b][d]) * w, int(ijk[b][d]) * w + w) if d < nd else slice(0, 1) for d in range(3)]
+        box = own[sl[2], sl[1], sl[0]]
+        if (box >= 0).any():
+            raise AssertionError("overlapping leaves")
+        box[...] = b
+    return own
+
+
+def touching_pairs(s, own):
+    """(a, b) leaf pairs whose finest blocks touch (faces, edges, corners)."""
+    nd = s.ndim
+    pairs = set()
+    per = s.bc == W.PERIODIC
+    for off in itertools.product(*[(-1, 0, 1) if d < nd else (0,) for d in range(3)]):
+        if not any(off):
+            continue
+        sh = own
+        valid = np.ones_like(own, dtype=bool)
+        for d in range(nd):
+            ax = 2 - d
+            sh = np.roll(sh, -off[d], axis=ax)
+            if not per:
+                v = np.ones(own.shape[ax], dtype=bool)
+                if off[d] == 1:
+                    v[-1] = False
+                elif off[d] == -1:
+                    v[0] = False
+                shape = [1, 1, 1]
+                shape[ax] = own.shape[ax]
+                valid &= v.reshape(shape)
+        a, b = own[valid], sh[valid]
+        m = a != b
+        pairs.update(zip(a[m].tolist(), b[m].tolist()))
+    return pairs
+
+
+def assert_valid(s, lev, ijk):
+    own = raster(s, lev, ijk)
+    assert (own >= 0).all(), "leaves do not cover the domain"
+    for a, b in touching_pairs(s, own):
+        assert abs(int(lev[a]) - int(lev[b])) <= 1, "2:1 balance broken"
+
+
+def split_children(s, l, c):
+    nd = s.ndim
+    return [(l + 1, tuple(2 * c[d] + ((q >> d) & 1) if d < nd else 0 for d in range(3))) for q in range(1 << nd)]
+
+
+def check_rules(s, f, flags, lev, ijk):
+    """Every rule of the plan, from the rasterised model."""
+    nd, nch = s.ndim, 1 << s.ndim
+    old = {(int(f.level[b]), tuple(int(x) for x in f.ijk[b])): b for b in range(f.n)}
+    new = {(int(lev[m]), tuple(int(x) for x in ijk[m])): m for m in range(len(lev))}
+    split = set()
+    merged = {}
+    for key, b in old.items():
+        l, c = key
+        if key in new:
+            continue
+        kids = split_children(s, l, c)
+        if all(k in new for k in kids):
+            split.add(b)
+        else:
+            parent = (l - 1, tuple(c[d] >> 1 if d < nd else 0 for d in range(3)))
+            assert parent in new, "a leaf vanished"
+            merged.setdefault(parent, []).append(b)
+    # requested splits
+    for b in range(f.n):
+        if flags[b] > 0 and f.level[b] < s.max_level:
+            assert b in split, "flagged leaf not split"
+    # final level of every leaf after splitting only (merges not counted)
+    final = np.array([int(f.level[b]) + (1 if b in split else 0) for b in range(f.n)])
+    own = raster(s, f.level, f.ijk)
+    pairs = touching_pairs(s, own)
+    # forced splits: exactly the closure of the requested ones
+    for b in split:
+        if flags[b] > 0:
+            continue
+        assert any(a in split and f.level[a] == f.level[b] + 1 for x, a in pairs if x == b), "unforced split"
+    for a, b in pairs:
+        if b in split and f.level[a] == f.level[b] - 1:
+            assert a in split, "balance closure incomplete"
+    # merges: members all flagged -1 and not split, complete; allowed iff no
+    # touching leaf outside the group ends finer than the group level
+    groups = {}
+    for b in range(f.n):
+        l, c = int(f.level[b]), tuple(int(x) for x in f.ijk[b])
+        if l > 1:
+            groups.setdefault((l - 1, tuple(c[d] >> 1 if d < nd else 0 for d in range(3))), []).append(b)
+    for parent, mem in groups.items():
+        complete = len(mem) == nch
+        cand = complete and all(flags[b] < 0 and b not in split for b in mem)
+        if cand:
+            ms = set(mem)
+            ok = all(final[a] <= int(f.level[mem[0]]) for x, a in pairs if x in ms and a not in ms)
+        else:
+            ok = False
+        assert (parent in merged) == ok, f"merge rule broken at {parent}"
+        if ok:
+            assert sorted(merged[parent]) == sorted(mem)
+    return len(split), len(merged)
+
+
+def random_flags(f, rng, p_split=0.15, p_merge=0.5):
+    """Random splits, and whole sibling groups flagged for merging (random
+    per-leaf -1 flags almost never complete a group)."""
+    s = f.scheme
+    flags = np.where(rng.random(f.n) < p_split, 1, 0).astype(np.int8)
+    groups = {}
+    for b in range(f.n):
+        if f.level[b] > 1:
+            key = (int(f.level[b]), tuple(int(x) >> 1 for x in f.ijk[b]))
+            groups.setdefault(key, []).append(b)
+    for mem in groups.values():
+        if rng.random() < p_merge:
+            flags[mem] = -1
+    return flags
+
+
+def plan(f, flags):
+    o = oracle.OracleForest(f)
+    lev, ijk = o.regrid_plan(flags)
+    o.close()
+    return lev, ijk
+
+
+# ---------------------------------------------------------------------------
+
+
+def _kh_forest(levels=3):
+    s = W.kh_scheme(4)
+    s.max_level = levels
+    f, U = W.kh(scheme=s)
+    return W.Forest(s, f.level, f.ijk), U
+
+
+def _blast_small():
+    s = W.blast_scheme(base=2, max_level=3)
+    f = W.blast_forest(s, radius=0.2, buffer_cells=2.0)
+    return W.blast(s, radius=0.2, forest=f)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_plan_rules_and_validity_2d(seed):
+    rng = np.random.default_rng(seed)
+    f, _ = _kh_forest()
+    counts = []
+    for _ in range(5):
+        flags = random_flags(f, rng)
+        lev, ijk = plan(f, flags)
+        assert_valid(f.scheme, lev, ijk)
+        counts.append(check_rules(f.scheme, f, flags, lev, ijk))
+        f = W.Forest(f.scheme, lev, ijk)
+    assert sum(c[0] for c in counts) > 0 and sum(c[1] for c in counts) > 0, counts
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_plan_rules_and_validity_3d(seed):
+    rng = np.random.default_rng(seed)
+    f, _ = _blast_small()
+    counts = []
+    for _ in range(3):
+        flags = random_flags(f, rng)
+        lev, ijk = plan(f, flags)
+        assert_valid(f.scheme, lev, ijk)
+        counts.append(check_rules(f.scheme, f, flags, lev, ijk))
+        f = W.Forest(f.scheme, lev, ijk)
+    assert sum(c[0] for c in counts) > 0 and sum(c[1] for c in counts) > 0, counts
+
+
+def test_plan_keeps_morton_order():
+    f, _ = _blast_small()
+    s = f.scheme
+    key = W._morton_key(f.level, f.ijk, s.max_level, s.ndim)
+    assert (np.diff(key) > 0).all()
+    flags = np.random.default_rng(9).choice(np.array([-1, 0, 1], np.int8), f.n)
+    lev, ijk = plan(f, flags)
+    key = W._morton_key(lev, ijk, s.max_level, s.ndim)
+    assert (np.diff(key) > 0).all()
+
+
+def test_worked_example_2d():
+    """2x2 level-1 leaves, max level 3.  Split leaf 0, then its child (1, 1)
+    (level 2, touching all three other level-1 leaves at the centre): those
+    three must split as well, each in place, children in x-then-y order."""
+    s = W.kh_scheme(2)
+    s.max_level = 3
+    lev = np.array([1, 1, 1, 1], np.int32)
+    ijk = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0]], np.int32)
+    f = W.Forest(s, lev, ijk)
+    l1, i1 = plan(f, np.array([1, 0, 0, 0], np.int8))
+    assert l1.tolist() == [2, 2, 2, 2, 1, 1, 1]
+    assert i1[:4, :2].tolist() == [[0, 0], [1, 0], [0, 1], [1, 1]]
+    f1 = W.Forest(s, l1, i1)
+    l2, i2 = plan(f1, np.array([0, 0, 0, 1, 0, 0, 0], np.int8))
+    assert l2.tolist() == [2, 2, 2] + [3] * 4 + [2] * 12
+    assert i2[3:7, :2].tolist() == [[2, 2], [3, 2], [2, 3], [3, 3]]
+    assert i2[7:11, :2].tolist() == [[2, 0], [3, 0], [2, 1], [3, 1]]
+    # merging the four level-3 leaves back is allowed (no finer neighbour)
+    f2 = W.Forest(s, l2, i2)
+    fl = np.zeros(f2.n, np.int8)
+    fl[3:7] = -1
+    l3, i3 = plan(f2, fl)
+    assert l3.tolist() == [2] * 16
+    # three of four flagged: no merge; a splitting neighbour blocks a merge
+    fl[6] = 0
+    assert plan(f2, fl)[0].tolist() == l2.tolist()
+    fl = np.zeros(f2.n, np.int8)
+    fl[0:3] = -1
+    fl[7] = -1  # the fourth sibling of (0..1, 0..1) at level 2 is index 3's parent: not a leaf
+    assert plan(f2, fl)[0].tolist() == l2.tolist()
+
+
+def test_flags_outside_levels_are_ignored():
+    f, _ = _kh_forest(levels=1)
+    assert plan(f, np.ones(f.n, np.int8))[0].tolist() == f.level.tolist()
+    assert plan(f, -np.ones(f.n, np.int8))[0].tolist() == f.level.tolist()
+
+
+def test_zero_flags_change_nothing():
+    f, U = _blast_small()
+    o = oracle.OracleForest(f)
+    o.set_state(U)
+    g = o.regrid(np.zeros(f.n, np.int8))
+    assert np.array_equal(g.forest.level, f.level) and np.array_equal(g.forest.ijk, f.ijk)
+    assert np.array_equal(g.get_state(), U)
+
+
+def _totals(f, U):
+    s = f.scheme
+    vol = np.prod([(s.xmax[d] - s.xmin[d]) / (s.base_blocks[d] * s.block_nx[d]) for d in range(s.ndim)])
+    w = vol / (2.0 ** s.ndim) ** (f.level.astype(np.float64) - 1)
+    return np.array([(U[v].reshape(f.n, -1).sum(axis=1) * w).sum() for v in range(U.shape[0])])
+
+
+@pytest.mark.parametrize("case", ["kh", "blast"])
+def test_transfer_conserves(case):
+    f, U = _kh_forest() if case == "kh" else _blast_small()
+    rng = np.random.default_rng(3)
+    o = oracle.OracleForest(f)
+    o.set_state(U)
+    t0 = _totals(f, U)
+    for _ in range(3):
+        flags = random_flags(o.forest, rng, p_split=0.3)
+        o = o.regrid(flags)
+        t = _totals(o.forest, o.get_state())
+        scale = np.abs(U).reshape(U.shape[0], -1).max(axis=1) * _totals(f, np.ones_like(U))[0]
+        assert np.all(np.abs(t - t0) <= 1e-13 * scale), (t - t0) / scale
+
+
+def test_prolongation_reproduces_linear_data():
+    """Linear conserved fields on a zero-gradient 4x4 grid: children of the
+    interior leaves take the linear function at their cell centres."""
+    s = W.kh_scheme(4)
+    s.max_level = 2
+    s.bc = W.ZERO_GRADIENT
+    f0, _ = W.kh(scheme=s)
+    f = W.Forest(s, f0.level, f0.ijk)
+    xs = W.cell_centres(f)
+    coef = [(2.0, 0.3, -0.2), (0.1, 0.05, 0.02), (-0.1, 0.01, 0.04), (6.0, -0.5, 0.25)]
+    U = np.stack([a + b * xs[0] + c * xs[1] for a, b, c in coef])
+    o = oracle.OracleForest(f)
+    o.set_state(U)
+    interior = (f.ijk[:, 0] > 0) & (f.ijk[:, 0] < 3) & (f.ijk[:, 1] > 0) & (f.ijk[:, 1] < 3)
+    g = o.regrid(interior.astype(np.int8))
+    V = g.get_state()
+    xf = W.cell_centres(g.forest)
+    fine = g.forest.level == 2
+    for v, (a, b, c) in enumerate(coef):
+        expect = a + b * xf[0] + c * xf[1]
+        err = np.abs(V[v][fine] - expect[fine]).max()
+        assert err <= 1e-14 * max(1.0, abs(a)), (v, err)
+    assert np.array_equal(V[:, ~fine], U[:, ~interior])
+
+
+def test_restriction_of_prolongation_is_identity():
+    """Split every leaf of a uniform 3D forest, merge every group back: the
+    restriction of the prolongation returns each value to a few ulp."""
+    s = W.blast_scheme(base=2, max_level=2)
+    f = W.Forest(s, np.ones(8, np.int32), np.array([[i, j, k] for k in range(2) for j in range(2) for i in range(2)],
+                                                    np.int32))
+    _, U = W.blast(s, radius=0.3, forest=f)
+    o = oracle.OracleForest(f)
+    o.set_state(U)
+    up = o.regrid(np.ones(8, np.int8))
+    assert up.forest.n == 64
+    back = up.regrid(-np.ones(64, np.int8))
+    assert np.array_equal(back.forest.level, f.level) and np.array_equal(back.forest.ijk, f.ijk)
+    R = back.get_state()
+    ulp = np.spacing(np.abs(U).max(axis=tuple(range(1, U.ndim)), keepdims=True))
+    assert np.all(np.abs(R - U) <= 4 * ulp)
+    assert not np.array_equal(up.get_state()[:, ::8], U[:, :, ::2, ::2, ::2])  # the children did change
+
+
+def test_restriction_of_piecewise_constant_is_exact():
+    s = W.kh_scheme(2)
+    s.max_level = 2
+    lev = np.full(16, 2, np.int32)
+    ijk = np.array([[i, j, 0] for j in range(4) for i in range(4)], np.int32)
+    f = W.Forest(s, lev, ijk)
+    rng = np.random.default_rng(5)
+    # value constant over each 2x2 group of fine cells
+    U = np.empty(f.state_shape())
+    for v in range(U.shape[0]):
+        coarse = rng.uniform(1, 2, (16, 8, 8))
+        U[v] = np.repeat(np.repeat(coarse, 2, axis=1), 2, axis=2)
+    o = oracle.OracleForest(f)
+    o.set_state(U)
+    g = o.regrid(-np.ones(16, np.int8))
+    assert g.forest.n == 4
+    V = g.get_state()
+    for m in range(4):
+        ci, cj = g.forest.ijk[m][:2]
+        for q in range(4):
+            child = [b for b in range(16) if tuple(ijk[b][:2]) == (2 * ci + (q & 1), 2 * cj + (q >> 1))][0]
+            blk = V[:, m, 8 * (q >> 1):8 * (q >> 1) + 8, 8 * (q & 1):8 * (q & 1) + 8]
+            assert np.array_equal(blk, U[:, child, ::2, ::2])
+
+
+def test_transfer_rejects_a_non_regrid():
+    f, U = _blast_small()
+    o = oracle.OracleForest(f)
+    o.set_state(U)
+    s = f.scheme
+    lev = np.array([1] * 8, np.int32)
+    ijk = np.array([[i, j, k] for k in range(2) for j in range(2) for i in range(2)], np.int32)
+    other = oracle.OracleForest(W.Forest(s, lev, ijk))
+    if f.level.max() >= 3:
+        with pytest.raises(oracle.OracleError) as e:
+            o.transfer_to(other)
+        assert e.value.code == -1
+
+
+def test_library_plan_equals_oracle_plan():
+    """The HIP library's host-side plan (independent C++) against the oracle."""
+    from paper_2004_03275_amd import _native as N
+
+    rng = np.random.default_rng(11)
+    for make in (_kh_forest, _blast_small):
+        f = make()[0]
+        for _ in range(4):
+            flags = random_flags(f, rng)
+            lo, io = plan(f, flags)
+            lg, ig = N.regrid_plan_leaves(f, flags)
+            assert np.array_equal(lo, lg) and np.array_equal(io, ig)
+            f = W.Forest(f.scheme, lo, io)
+    s = W.blast_scheme()
+    f = W.blast_forest(s)
+    for flags in (rng.choice(np.array([-1, 0, 1], np.int8), f.n, p=[0.5, 0.45, 0.05]),
+                  random_flags(f, rng, p_split=0.05)):
+        lo, io = plan(f, flags)
+        lg, ig = N.regrid_plan_leaves(f, flags)
+        assert np.array_equal(lo, lg) and np.array_equal(io, ig)
+        assert lo.size != f.n
