@@ -1439,7 +1439,20 @@ int orc_regrid_transfer(orc_forest* from, orc_forest* to) {
     return fail(ORC_EINVAL, "the target forest is not a one-level regrid of the source forest");
   }
   const int h[3] = {f->nx[0] / 2, nd > 1 ? f->nx[1] / 2 : 0, nd > 2 ? f->nx[2] / 2 : 0};
+  free(W);
+  free(Wc);
+  int oom = 0;
+#pragma omp parallel
+  {
+    double* W = (double*)malloc(sizeof(double) * nv * f->npad);
+    double* Wc = (double*)malloc(sizeof(double) * nv * f->npad);
+    if (!W || !Wc) {
+#pragma omp atomic write
+      oom = 1;
+    }
+#pragma omp for schedule(dynamic, 4)
   for (int64_t n = 0; n < to->n; n++) {
+    if (oom) continue;
     if (how[n] == 1) fill_all(f, f->U, src[8 * n], W, Wc);
     for (int k = 0; k < f->nx[2]; k++)
       for (int j = 0; j < f->nx[1]; j++)
@@ -1489,7 +1502,14 @@ int orc_regrid_transfer(orc_forest* from, orc_forest* to) {
           }
         }
   }
+    free(W);
+    free(Wc);
+  }
+  if (oom) {
+    free(src), free(how), free(out);
+    return fail(ORC_ENOMEM, "out of memory");
+  }
   memcpy(to->U, out, sizeof(double) * nv * to->n * to->ncell);
-  free(src), free(how), free(W), free(Wc), free(out);
+  free(src), free(how), free(out);
   return ORC_OK;
 }

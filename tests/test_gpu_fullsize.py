@@ -91,3 +91,10 @@ def test_blast_full_size_two_steps_and_flags():
           f"coarsen {int(np.sum(fo == -1))}; identical {np.array_equal(fg, fo)}", flush=True)
     assert np.array_equal(fg, fo)
     assert np.array_equal(eg, eo)
+    # regrid on these flags: the same leaves and the same transferred state
+    g2, o2 = g.regrid(fg), o.regrid(fo)
+    assert np.array_equal(g2.forest.level, o2.forest.level) and np.array_equal(g2.forest.ijk, o2.forest.ijk)
+    nbad = int(np.count_nonzero(g2.get_state() != o2.get_state()))
+    print(f"[full] blast regrid: {f.n} -> {g2.forest.n} leaves {g2.forest.level_counts()}, differing values {nbad}",
+          flush=True)
+    assert nbad == 0

@@ -1,0 +1,135 @@
+"""Regridding on the GPU (plan through the forest, transfer kernel) against
+the oracle, through the C-ABI.  Plans are integer work and must match leaf
+for leaf; transferred states are formed in the oracle's order with
+contraction off and must match bit for bit, also after further steps."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_03275_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _F():
+    from paper_2004_03275_amd import forest as F
+
+    return F
+
+
+def random_flags(f, rng, p_split=0.2, p_merge=0.5):
+    flags = np.where(rng.random(f.n) < p_split, 1, 0).astype(np.int8)
+    groups = {}
+    for b in range(f.n):
+        if f.level[b] > 1:
+            groups.setdefault((int(f.level[b]), tuple(int(x) >> 1 for x in f.ijk[b])), []).append(b)
+    for mem in groups.values():
+        if rng.random() < p_merge:
+            flags[mem] = -1
+    return flags
+
+
+def _blast_small():
+    s = W.blast_scheme(base=2, max_level=3)
+    f = W.blast_forest(s, radius=0.2, buffer_cells=2.0)
+    return W.blast(s, radius=0.2, forest=f)
+
+
+def _amr2d():
+    s = W.Scheme(ndim=2, block_nx=(16, 16), base_blocks=(4, 4), max_level=3, flux=W.HLLC, limiter=W.VANLEER,
+                 rk_stages=3, cfl=0.8, bc=W.PERIODIC)
+    f = W.refined_forest(s, lambda l, c: abs((c[0] + 0.5) / (4 << (l - 1)) - 0.5) < 0.2
+                         and abs((c[1] + 0.5) / (4 << (l - 1)) - 0.45) < 0.2)
+    xs = W.cell_centres(f)
+    inner = np.abs(xs[1] - 0.5) < 0.25
+    rho = np.where(inner, 2.0, 1.0)
+    u = np.where(inner, 0.5, -0.5)
+    v = 0.05 * np.sin(4 * np.pi * xs[0])
+    return f, W.state_from_primitive(f, rho, [u, v], np.full_like(rho, 2.5))
+
+
+def _sod_blocks():
+    f, U = W.sod(1024, nblocks=64)
+    s = f.scheme
+    s.max_level = 3
+    return W.Forest(s, f.level, f.ijk), U
+
+
+CASES = {"blast3d": _blast_small, "amr2d": _amr2d, "sod1d": _sod_blocks}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_regrid_matches_oracle(case):
+    F = _F()
+    f, U = CASES[case]()
+    rng = np.random.default_rng(7)
+    o = oracle.OracleForest(f)
+    o.set_state(U)
+    g = F.GpuForest(f)
+    g.set_state(U)
+    for it in range(3):
+        flags = random_flags(o.forest, rng)
+        lo, io = o.regrid_plan(flags)
+        lg, ig = g.regrid_plan(flags)
+        assert np.array_equal(lo, lg) and np.array_equal(io, ig)
+        o2, g2 = o.regrid(flags), g.regrid(flags)
+        Ro, Rg = o2.get_state(), g2.get_state()
+        nbad = int(np.count_nonzero(Ro != Rg))
+        print(f"[regrid] {case} pass {it}: {o.forest.n} -> {o2.forest.n} leaves, differing values {nbad}", flush=True)
+        assert nbad == 0
+        o.close()
+        g.close()
+        o, g = o2, g2
+
+
+@pytest.mark.parametrize("case", ["blast3d", "amr2d"])
+def test_steps_after_loehner_regrid_match_oracle(case):
+    """Evolve, regrid on the Loehner flags of the evolved state, evolve on."""
+    F = _F()
+    f, U = CASES[case]()
+    o = oracle.OracleForest(f)
+    o.set_state(U)
+    g = F.GpuForest(f)
+    g.set_state(U)
+    for rnd in range(2):
+        for _ in range(3):
+            dt = o.max_dt()
+            o.advance(dt)
+            g.max_dt()
+            g.advance(dt)
+        fo = o.flag_blocks()
+        fg = g.flag_blocks()
+        assert np.array_equal(fo, fg)
+        o, g = o.regrid(fo), g.regrid(fg)
+        print(f"[regrid] {case} round {rnd}: {o.forest.level_counts()}", flush=True)
+        assert np.array_equal(o.get_state(), g.get_state())
+    for _ in range(3):
+        dt = o.max_dt()
+        assert g.max_dt() == dt
+        o.advance(dt)
+        g.advance(dt)
+    assert np.array_equal(o.get_state(), g.get_state())
+
+
+def test_transfer_rejects_a_non_regrid():
+    F = _F()
+    from paper_2004_03275_amd import _native as N
+
+    f, U = _blast_small()
+    g = F.GpuForest(f)
+    g.set_state(U)
+    s = f.scheme
+    other = F.GpuForest(W.Forest(s, np.ones(8, np.int32),
+                                 np.array([[i, j, k] for k in range(2) for j in range(2) for i in range(2)], np.int32)))
+    with pytest.raises(N.AmrvError) as e:
+        g.transfer_to(other)
+    assert e.value.code == N.EINVAL
+    # plan capacity too small: ENOMEM with the count
+    import ctypes
+
+    m = ctypes.c_int64()
+    flags = np.ones(f.n, np.int8)
+    lev = np.empty(1, np.int32)
+    ijk = np.empty((1, 3), np.int32)
+    rc = N.lib().amrv_regrid_plan(g._h, flags.ctypes.data, 1, ctypes.byref(m), lev.ctypes.data, ijk.ctypes.data)
+    assert rc == N.ENOMEM and m.value > f.n
