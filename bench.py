@@ -89,6 +89,10 @@ def main():
     ap.add_argument("--tune-reps", type=int, default=5)
     ap.add_argument("--host-dt", action="store_true",
                     help="time steps as amrv_max_dt + amrv_advance (host-side dt) instead of amrv_advance_cfl")
+    ap.add_argument("--adaptive-steps", type=int, default=None,
+                    help="also run this many steps from the initial state with regridding (default 20 on the "
+                         "3D blast, 0 elsewhere)")
+    ap.add_argument("--regrid-every", type=int, default=5)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -282,6 +286,47 @@ def main():
             log(f"flagger: Loehner {tl:.2f} ms, MLP {tm:.2f} ms, fallback {tf:.2f} ms; "
                 f"disagreement {flagger['flag_disagreement']:.4f} (fallback {flagger['fallback_flag_disagreement']:.4f})")
 
+    # adaptive run: Loehner flags and a regrid (plan, new forest, transfer)
+    # every regrid_every steps, from the initial state, timed as a whole
+    adaptive = None
+    nad = args.adaptive_steps if args.adaptive_steps is not None else (20 if args.workload == "blast" else 0)
+    if nad > 0:
+        g.use_graph(False)
+        g.set_schedule(*sched[:3])
+        g.set_variant(sched[3])
+        g.set_state(U0)
+        ga = g
+        t_ad, done, updates, regrid_ms, regrids, counts = 0.0, 0, 0, 0.0, 0, []
+        g.synchronize()
+        t0 = time.perf_counter()
+        while done < nad:
+            m = min(args.regrid_every, nad - done)
+            t_ad, _ = ga.advance_cfl(m, float("inf"), t_ad)
+            updates += ga.forest.n * s.cells_per_block * m
+            done += m
+            if done < nad:
+                ga.synchronize()
+                r0 = time.perf_counter()
+                nxt = ga.regrid(ga.flag_blocks())
+                if ga is not g:
+                    ga.close()
+                ga = nxt
+                regrid_ms += (time.perf_counter() - r0) * 1e3
+                regrids += 1
+                counts.append(ga.forest.n)
+        ga.synchronize()
+        ael = time.perf_counter() - t0
+        adaptive = {"value": updates / ael / 1e6, "unit": "MCUPS", "steps": nad, "regrid_every": args.regrid_every,
+                     "regrids": regrids, "regrid_ms_avg": regrid_ms / max(regrids, 1),
+                     "leaves_after_each_regrid": counts, "final_levels": {str(k): v for k, v in
+                                                                           ga.forest.level_counts().items()},
+                     "note": "cell updates of the current forest per step; regrid = Loehner flags, plan, new "
+                             "forest (workspace, tables), transfer"}
+        log(f"adaptive: {adaptive['value']:.1f} MCUPS over {nad} steps, {regrids} regrids of "
+            f"{adaptive['regrid_ms_avg']:.1f} ms, leaves {counts}")
+        if ga is not g:
+            ga.close()
+
     names = {0: "per_block", 1: "grid", 2: "persistent"}
     bytes_per_cell_step = (2 + 3 * (s.rk_stages - 1)) * s.nvar * 8
     out = {
@@ -333,6 +378,7 @@ def main():
         "per_block": per_block,
         "parity": parity,
         "learned_flagger": flagger,
+        "adaptive": adaptive,
     }
     print(json.dumps(out), flush=True)
 
