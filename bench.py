@@ -30,13 +30,13 @@ METRIC = "MCUPS (cell-updates/s) per full RK step, batched vs per-block, at 1e-1
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per stage-kernel launch from the committed counter summary,
-    if it was taken on this workload with the current kernel sources."""
+def measured_counters(workload: str) -> dict:
+    """HBM bytes per stage-kernel launch and the VALU / FP64 issue fractions
+    from the committed counter summary, if it was taken on this workload with
+    the current kernel sources (else an empty dict)."""
     import hashlib
-
     if workload != "blast":
-        return None
+        return {}
     prof = os.path.join(ROOT, "profiles", "hbm_counters_3d_amr_blast.md")
     csrc = os.path.join(ROOT, "paper_2004_03275_amd", "csrc")
     try:
@@ -44,11 +44,12 @@ def measured_traffic(workload: str):
         h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
                                     for f in ("kernels.hip", "physics.hpp", "internal.hpp"))).hexdigest()
     except OSError:
-        return None
-    vals = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(("kernel_source_sha256", "traffic_bytes")))
+        return {}
+    keys = ("kernel_source_sha256", "traffic_bytes_per_launch", "valu_issue_frac", "fp64_issue_frac")
+    vals = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(keys))
     if vals.get("kernel_source_sha256", "").strip() != h:
-        return None
-    return float(vals["traffic_bytes_per_launch"])
+        return {}
+    return {k: float(vals[k]) for k in keys[1:] if k in vals}
 
 
 def make_workload(name: str):
@@ -327,6 +328,7 @@ def main():
         if ga is not g:
             ga.close()
 
+    counters = measured_counters(args.workload)
     names = {0: "per_block", 1: "grid", 2: "persistent"}
     bytes_per_cell_step = (2 + 3 * (s.rk_stages - 1)) * s.nvar * 8
     out = {
@@ -367,12 +369,15 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.workload),
+            "traffic": counters.get("traffic_bytes_per_launch"),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "algorithmic_bytes_per_launch": kbytes / max(launches, 1),
             "avg_launch_ms": avg_ms,
             "launches": launches,
             "algorithmic_bytes_per_cell_step": bytes_per_cell_step,
+            "valu_issue_frac": counters.get("valu_issue_frac"),
+            "fp64_issue_frac": counters.get("fp64_issue_frac"),
+            "counters": "profiles/hbm_counters_3d_amr_blast.md" if counters else None,
         },
         "cpu_baseline": cpu,
         "per_block": per_block,

@@ -153,8 +153,7 @@ int stage_grid(const amrv_forest* f, int mode) {
 int enqueue_ghosts(amrv_forest* f, const double* U, bool fluxes) {
   const int nr = (int)f->tab.rlist.size(), np = (int)f->tab.plist.size();
   if (nr) HIPCHK(launch_restrict(f->geo, f->lc, U, f->rlist, nr, f->st));
-  if (np) HIPCHK(launch_prolong(f->geo, f->lc, U, f->plist, np, f->st));
-  if (np && fluxes) HIPCHK(launch_fineflux(f->geo, f->lc, U, f->pp, f->plist, np, f->st));
+  if (np) HIPCHK(launch_prolong(f->geo, f->lc, U, f->pp, f->plist, np, fluxes, f->st));
   return AMRV_OK;
 }
 

@@ -71,10 +71,10 @@ struct LaunchCfg {
 
 hipError_t launch_restrict(const Geo& g, const LaunchCfg& c, const double* U, const int32_t* list, int nlist,
                            hipStream_t st);
-hipError_t launch_prolong(const Geo& g, const LaunchCfg& c, const double* U, const int32_t* list, int nlist,
-                          hipStream_t st);
-hipError_t launch_fineflux(const Geo& g, const LaunchCfg& c, const double* U, const double* physp,
-                           const int32_t* list, int nlist, hipStream_t st);
+// fine-side ghost slabs (prolongation) and, with fluxes, the fine-side face
+// fluxes of the same coarse-fine faces
+hipError_t launch_prolong(const Geo& g, const LaunchCfg& c, const double* U, const double* physp,
+                          const int32_t* list, int nlist, bool fluxes, hipStream_t st);
 hipError_t launch_stage(const Geo& g, const LaunchCfg& c, const StageArgs& a, const double* physp, const Sched& s,
                         int grid, hipStream_t st);
 hipError_t launch_cfl(const Geo& g, const LaunchCfg& c, const double* U, const double* physp,

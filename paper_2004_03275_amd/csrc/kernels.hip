@@ -4,10 +4,10 @@
 // 16^d blocks (Sec. 1.3) is:
 //   k_restrict   coarse-side ghost slabs of coarse-fine faces: mean of the
 //                2^d finer cells (pairwise sum, times 2^-d)
-//   k_prolong    fine-side ghost slabs: coarse value plus a quarter of its
-//                minmod slope per dimension
-//   k_fineflux   fine-side face fluxes of coarse-fine faces (the coarse side
-//                replaces its own flux by their mean: conservation)
+//   k_prolong_flux  fine-side ghost slabs (coarse value plus a quarter of
+//                its minmod slope per dimension) and the fine-side face
+//                fluxes of the same faces (the coarse side replaces its own
+//                flux by their mean: conservation)
 //   k_stage      per leaf: primitive variables, MUSCL states, Riemann fluxes,
 //                flux divergence and the SSP combination.  Same-level and
 //                boundary ghosts are gathered straight from the neighbour's
@@ -191,84 +191,104 @@ __device__ __forceinline__ void cfl_fold(unsigned long long* red, unsigned long 
 // ghost slabs of coarse-fine faces
 // ---------------------------------------------------------------------------
 
+// one thread per transverse position t of a coarse-side slot, both ghost
+// layers; the two children along x of every restricted cell are adjacent in
+// memory (x is the fastest index, the pair starts at an even x), so they come
+// in one 16-byte load
 template <int ND, int NV>
 __global__ void __launch_bounds__(WGS) k_restrict(Geo g, const double* __restrict__ U, const int32_t* __restrict__ list,
                                                   int nlist) {
   const long long i = (long long)blockIdx.x * WGS + threadIdx.x;
-  const long long per = 2LL * g.T;
-  if (i >= nlist * per) return;
-  const int slot = list[i / per];
-  const int rem = (int)(i % per);
-  const int layer = rem / g.T, t = rem % g.T;
+  if (i >= (long long)nlist * g.T) return;
+  const int slot = list[i / g.T];
+  const int t = (int)(i % g.T);
   const int a1 = ND > 1 ? t % g.nx : 0, a2 = ND > 2 ? t / g.nx : 0;
   const int f = g.sface[slot];
   const int d = f >> 1, hi = f & 1;
   const int half = g.nx >> 1;
   const int q = (ND > 1 ? (a1 >= half) : 0) + (ND > 2 ? 2 * (a2 >= half) : 0);
   const int fine = g.sleaf[g.fslot[slot * 4 + q]];
-  double acc[8][NV];
+  const size_t vs = (size_t)g.n * g.ncell;
+  const double* base = U + (size_t)fine * g.ncell;
 #pragma unroll
-  for (int o = 0; o < (1 << ND); o++) {
-    int c[3] = {0, 0, 0};
+  for (int layer = 0; layer < 2; layer++) {
+    double acc[8][NV];
 #pragma unroll
-    for (int e = 0; e < ND; e++) {
-      const int oe = (o >> e) & 1;
-      if (e == d)
-        c[e] = hi ? 2 * layer + oe : g.nx - 2 - 2 * layer + oe;
-      else
-        c[e] = (2 * ((e == (d == 0 ? 1 : 0)) ? a1 : a2) + oe) % g.nx;
+    for (int o = 0; o < (1 << ND); o += 2) {
+      int c[3] = {0, 0, 0};
+#pragma unroll
+      for (int e = 0; e < ND; e++) {
+        const int oe = (o >> e) & 1;
+        if (e == d)
+          c[e] = hi ? 2 * layer + oe : g.nx - 2 - 2 * layer + oe;
+        else
+          c[e] = (2 * ((e == (d == 0 ? 1 : 0)) ? a1 : a2) + oe) % g.nx;
+      }
+      const int cell = cell_index(g, c[0], c[1], c[2]);
+#pragma unroll
+      for (int v = 0; v < NV; v++) {
+        const double2 pr = *reinterpret_cast<const double2*>(base + v * vs + cell);
+        acc[o][v] = pr.x;
+        acc[o + 1][v] = pr.y;
+      }
     }
-    const int cell = cell_index(g, c[0], c[1], c[2]);
+    const size_t out = (size_t)slot * NV * 2 * g.T + (size_t)layer * g.T + t;
 #pragma unroll
-    for (int v = 0; v < NV; v++) acc[o][v] = U[uidx(g, v, fine, cell)];
-  }
-  const size_t base = (size_t)slot * NV * 2 * g.T + (size_t)layer * g.T + t;
-#pragma unroll
-  for (int v = 0; v < NV; v++) {
-    double r;
-    if constexpr (ND == 1)
-      r = (acc[0][v] + acc[1][v]) * 0.5;
-    else if constexpr (ND == 2)
-      r = ((acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v])) * 0.25;
-    else
-      r = (((acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v])) + ((acc[4][v] + acc[5][v]) + (acc[6][v] + acc[7][v]))) *
-          0.125;
-    g.G[base + (size_t)v * 2 * g.T] = r;
+    for (int v = 0; v < NV; v++) {
+      double r;
+      if constexpr (ND == 1)
+        r = (acc[0][v] + acc[1][v]) * 0.5;
+      else if constexpr (ND == 2)
+        r = ((acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v])) * 0.25;
+      else
+        r = (((acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v])) + ((acc[4][v] + acc[5][v]) + (acc[6][v] + acc[7][v]))) *
+            0.125;
+      g.G[out + (size_t)v * 2 * g.T] = r;
+    }
   }
 }
 
-template <int ND, int NV>
-__global__ void __launch_bounds__(WGS) k_prolong(Geo g, const double* __restrict__ U, const int32_t* __restrict__ list,
-                                                 int nlist) {
+// Fine side of a coarse-fine face, one thread per transverse position t:
+// both prolonged ghost layers (they lie in the same coarse cell and differ
+// only in the half along the face normal, so they share the coarse value and
+// its limited slopes), and with `fluxes` the face flux from the two interior
+// cells and the two ghosts.  Prolongation never reads a prolonged value:
+// with 2:1 balance over edges and corners the coarse stencil only touches
+// coarse interior cells and restricted or same-level ghosts.
+template <int ND, bool MHD, int FLUX, int LIM>
+__global__ void __launch_bounds__(WGS) k_prolong_flux(Geo g, const double* __restrict__ U,
+                                                      const double* __restrict__ pp,
+                                                      const int32_t* __restrict__ list, int nlist, int fluxes) {
+  using S = Sys<ND, MHD>;
+  constexpr int NV = S::NV;
   const long long i = (long long)blockIdx.x * WGS + threadIdx.x;
-  const long long per = 2LL * g.T;
-  if (i >= nlist * per) return;
-  const int slot = list[i / per];
-  const int rem = (int)(i % per);
-  const int layer = rem / g.T, t = rem % g.T;
+  if (i >= (long long)nlist * g.T) return;
+  const int slot = list[i / g.T];
+  const int t = (int)(i % g.T);
   const int a1 = ND > 1 ? t % g.nx : 0, a2 = ND > 2 ? t / g.nx : 0;
   const int fine = g.sleaf[slot];
   const int f = g.sface[slot];
   const int d = f >> 1, hi = f & 1;
   const int C = g.nbr[fine * 6 + f];
-  int cc[3] = {0, 0, 0}, par[3] = {0, 0, 0};
+  int cc[3] = {0, 0, 0}, par0[3] = {0, 0, 0}, par1[3] = {0, 0, 0};
 #pragma unroll
   for (int e = 0; e < ND; e++) {
-    int loc;
-    if (e == d)
-      loc = hi ? g.nx + layer : -1 - layer;
-    else
-      loc = (e == (d == 0 ? 1 : 0)) ? a1 : a2;
-    const long long gl = (long long)g.ijk[fine * 3 + e] * g.nx + loc;  // fine global coordinate
-    const long long gc = gl >> 1;                                       // coarse global (floor)
+    const int loc0 = e == d ? (hi ? g.nx : -1) : ((e == (d == 0 ? 1 : 0)) ? a1 : a2);
+    const int loc1 = e == d ? (hi ? g.nx + 1 : -2) : loc0;
+    const long long gl0 = (long long)g.ijk[fine * 3 + e] * g.nx + loc0;  // fine global coordinates
+    const long long gl1 = (long long)g.ijk[fine * 3 + e] * g.nx + loc1;
+    const long long gc = gl0 >> 1;                                         // the coarse cell (floor)
     cc[e] = (int)(((gc % g.nx) + g.nx) % g.nx);
-    par[e] = (int)(gl & 1);
+    par0[e] = (int)(gl0 & 1);
+    par1[e] = (int)(gl1 & 1);
   }
-  double u0[NV];
+  double u0[NV], r0[NV], r1[NV];
   fetch_cons<NV, ND>(g, U, C, cc[0], cc[1], cc[2], u0);
-  double res[NV];
 #pragma unroll
-  for (int v = 0; v < NV; v++) res[v] = u0[v];
+  for (int v = 0; v < NV; v++) {
+    r0[v] = u0[v];
+    r1[v] = u0[v];
+  }
 #pragma unroll
   for (int e = 0; e < ND; e++) {
     double um[NV], up[NV];
@@ -280,48 +300,52 @@ __global__ void __launch_bounds__(WGS) k_prolong(Geo g, const double* __restrict
 #pragma unroll
     for (int v = 0; v < NV; v++) {
       const double tq = 0.25 * minmod(u0[v] - um[v], up[v] - u0[v]);
-      res[v] = par[e] ? res[v] + tq : res[v] - tq;
+      r0[v] = par0[e] ? r0[v] + tq : r0[v] - tq;
+      r1[v] = par1[e] ? r1[v] + tq : r1[v] - tq;
     }
   }
-  const size_t base = (size_t)slot * NV * 2 * g.T + (size_t)layer * g.T + t;
+  const size_t base = (size_t)slot * NV * 2 * g.T + t;
 #pragma unroll
-  for (int v = 0; v < NV; v++) g.G[base + (size_t)v * 2 * g.T] = res[v];
-}
-
-// fine-side flux of each coarse-fine face (list of COARSER slots)
-template <int ND, bool MHD, int FLUX, int LIM>
-__global__ void __launch_bounds__(WGS) k_fineflux(Geo g, const double* __restrict__ U, const double* __restrict__ pp,
-                                                  const int32_t* __restrict__ list, int nlist) {
-  using S = Sys<ND, MHD>;
-  constexpr int NV = S::NV;
-  const long long i = (long long)blockIdx.x * WGS + threadIdx.x;
-  if (i >= (long long)nlist * g.T) return;
+  for (int v = 0; v < NV; v++) {
+    g.G[base + (size_t)v * 2 * g.T] = r0[v];
+    g.G[base + (size_t)v * 2 * g.T + g.T] = r1[v];
+  }
+  if (!fluxes) return;
+  // face between cells m-1 and m along d: interior cells m-2, m-1 (hi) or
+  // m, m+1 (lo), ghosts layer 0 next to the face, layer 1 beyond it
   const PhysParams P = load_phys(pp);
-  const int slot = list[i / g.T];
-  const int t = (int)(i % g.T);
-  const int a1 = ND > 1 ? t % g.nx : 0, a2 = ND > 2 ? t / g.nx : 0;
-  const int leaf = g.sleaf[slot];
-  const int f = g.sface[slot];
-  const int d = f >> 1, hi = f & 1;
-  const int m = hi ? g.nx : 0;  // face between cells m-1 and m along d
-  double V[4][NV];
+  double W[4][NV];  // interior cells (nearer the face last), then ghost layers 0, 1
+  const int m = hi ? g.nx : 0;
 #pragma unroll
-  for (int j = 0; j < 4; j++) {
+  for (int j = 0; j < 2; j++) {
     int c[3] = {0, 0, 0};
-    c[d] = m - 2 + j;
+    c[d] = hi ? m - 2 + j : m + 1 - j;
     if (ND > 1) c[d == 0 ? 1 : 0] = a1;
     if (ND > 2) c[d == 2 ? 1 : 2] = a2;
     double u[NV];
-    fetch_cons<NV, ND>(g, U, leaf, c[0], c[1], c[2], u);
-    cons2prim<ND, MHD>(u, V[j], P);
-  }
-  double lo[NV], vl[NV], vr[NV], hi_[NV], F[NV];
-  muscl<NV, LIM>(V[0], V[1], V[2], lo, vl);
-  muscl<NV, LIM>(V[1], V[2], V[3], vr, hi_);
-  riemann_dir<ND, MHD, FLUX>(d, vl, vr, F, P);
-  const size_t base = (size_t)slot * NV * g.T + t;
+    const int cell = cell_index(g, c[0], c[1], c[2]);
 #pragma unroll
-  for (int v = 0; v < NV; v++) g.FF[base + (size_t)v * g.T] = F[v];
+    for (int v = 0; v < NV; v++) u[v] = U[uidx(g, v, fine, cell)];
+    cons2prim<ND, MHD>(u, W[j], P);
+  }
+  cons2prim<ND, MHD>(r0, W[2], P);
+  cons2prim<ND, MHD>(r1, W[3], P);
+  // the four cells in increasing coordinate along d
+  double V0[NV], V1[NV], V2[NV], V3[NV];
+#pragma unroll
+  for (int v = 0; v < NV; v++) {
+    V0[v] = hi ? W[0][v] : W[3][v];
+    V1[v] = hi ? W[1][v] : W[2][v];
+    V2[v] = hi ? W[2][v] : W[1][v];
+    V3[v] = hi ? W[3][v] : W[0][v];
+  }
+  double lo_[NV], vl[NV], vr[NV], hi_[NV], F[NV];
+  muscl<NV, LIM>(V0, V1, V2, lo_, vl);
+  muscl<NV, LIM>(V1, V2, V3, vr, hi_);
+  riemann_dir<ND, MHD, FLUX>(d, vl, vr, F, P);
+  const size_t fb = (size_t)slot * NV * g.T + t;
+#pragma unroll
+  for (int v = 0; v < NV; v++) g.FF[fb + (size_t)v * g.T] = F[v];
 }
 
 // ---------------------------------------------------------------------------
@@ -1106,7 +1130,7 @@ static inline unsigned blocks_for(long long work) { return (unsigned)((work + WG
 hipError_t launch_restrict(const Geo& g, const LaunchCfg& c, const double* U, const int32_t* list, int nlist,
                            hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  const unsigned nb = blocks_for((long long)nlist * 2 * g.T);
+  const unsigned nb = blocks_for((long long)nlist * g.T);
 #define BODY_R                                                                                 \
   if (c.mhd) {                                                                                 \
     hipLaunchKernelGGL((k_restrict<ND, Sys<ND, true>::NV>), dim3(nb), dim3(WGS), 0, st, g, U, list, nlist); \
@@ -1150,38 +1174,15 @@ hipError_t launch_transfer(const Geo& from, const double* Uf, const Geo& to, dou
   return hipGetLastError();
 }
 
-hipError_t launch_prolong(const Geo& g, const LaunchCfg& c, const double* U, const int32_t* list, int nlist,
-                          hipStream_t st) {
-  if (nlist <= 0) return hipSuccess;
-  const unsigned nb = blocks_for((long long)nlist * 2 * g.T);
-#define BODY_P                                                                                \
-  if (c.mhd) {                                                                                \
-    hipLaunchKernelGGL((k_prolong<ND, Sys<ND, true>::NV>), dim3(nb), dim3(WGS), 0, st, g, U, list, nlist); \
-  } else {                                                                                    \
-    hipLaunchKernelGGL((k_prolong<ND, Sys<ND, false>::NV>), dim3(nb), dim3(WGS), 0, st, g, U, list, nlist); \
-  }
-  if (c.ndim == 1) {
-    constexpr int ND = 1;
-    BODY_P
-  } else if (c.ndim == 2) {
-    constexpr int ND = 2;
-    BODY_P
-  } else {
-    constexpr int ND = 3;
-    BODY_P
-  }
-#undef BODY_P
-  return hipGetLastError();
-}
-
-hipError_t launch_fineflux(const Geo& g, const LaunchCfg& c, const double* U, const double* physp,
-                           const int32_t* list, int nlist, hipStream_t st) {
+hipError_t launch_prolong(const Geo& g, const LaunchCfg& c, const double* U, const double* physp,
+                          const int32_t* list, int nlist, bool fluxes, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
   const unsigned nb = blocks_for((long long)nlist * g.T);
   dispatch(c, [&](auto nd, auto mhd, auto fl, auto lm) {
     constexpr int ND = decltype(nd)::value, FL = decltype(fl)::value, LM = decltype(lm)::value;
     constexpr bool MHD = decltype(mhd)::value != 0;
-    hipLaunchKernelGGL((k_fineflux<ND, MHD, FL, LM>), dim3(nb), dim3(WGS), 0, st, g, U, physp, list, nlist);
+    hipLaunchKernelGGL((k_prolong_flux<ND, MHD, FL, LM>), dim3(nb), dim3(WGS), 0, st, g, U, physp, list, nlist,
+                       fluxes ? 1 : 0);
   });
   return hipGetLastError();
 }
