@@ -50,6 +50,7 @@ extern "C" {
 #define AMRV_HLLC 2
 #define AMRV_MINMOD 0
 #define AMRV_VANLEER 1
+#define AMRV_MC 2 /* monotonized central ('woodward', Sec. 2.3.1) */
 #define AMRV_BC_PERIODIC 0
 #define AMRV_BC_ZERO_GRADIENT 1
 
@@ -77,7 +78,7 @@ typedef struct {
   int32_t max_level;       /* 1 = pure domain decomposition */
   int32_t physics;         /* AMRV_EULER or AMRV_MHD_GLM */
   int32_t flux;            /* AMRV_TVDLF, AMRV_HLL, AMRV_HLLC (HLLC: Euler only) */
-  int32_t limiter;         /* AMRV_MINMOD or AMRV_VANLEER */
+  int32_t limiter;         /* AMRV_MINMOD, AMRV_VANLEER or AMRV_MC */
   int32_t rk_stages;       /* 2 (SSP-RK2) or 3 (SSP-RK3) */
   int32_t bc[3][2];        /* AMRV_BC_*, same value on both sides of a dimension */
   int32_t pad_;

@@ -65,6 +65,8 @@ def lib():
         L.orc_lohner_cells.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64]
         L.orc_regrid_plan.argtypes = [P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P, P]
         L.orc_regrid_transfer.argtypes = [P, P]
+        L.orc_limiter_value.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        L.orc_limiter_value.restype = ctypes.c_double
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_set_threads.restype = None
         L.orc_get_threads.restype = ctypes.c_int
@@ -109,6 +111,11 @@ def make_config(s) -> _Config:
     c.lohner_w_p = s.lohner_w_p
     c.glm_cr = s.glm_cr
     return c
+
+
+def limiter_value(kind: int, a: float, b: float) -> float:
+    """The oracle's limited slope for backward / forward differences a, b."""
+    return float(lib().orc_limiter_value(int(kind), float(a), float(b)))
 
 
 def set_threads(n: int):

@@ -41,7 +41,7 @@
 enum { NB_SAME = 0, NB_COARSER = 1, NB_FINER = 2, NB_BND = 3 };
 enum { PHYS_EULER = 0, PHYS_MHD = 1 };
 enum { FLUX_TVDLF = 0, FLUX_HLL = 1, FLUX_HLLC = 2 };
-enum { LIM_MINMOD = 0, LIM_VANLEER = 1 };
+enum { LIM_MINMOD = 0, LIM_VANLEER = 1, LIM_MC = 2 };
 
 static __thread char g_err[512];
 
@@ -353,12 +353,23 @@ static void riemann(const orc_forest* f, const double* vl_in, const double* vr_i
 /* Slope limiters on the backward and forward differences (the paper names
  * minmod-type and other limited reconstructions, Sec. 2.2-2.4; formulas are
  * the textbook ones): minmod picks the smaller magnitude, van Leer the
- * harmonic mean 2ab/(a+b); both vanish at extrema (a b <= 0). */
-static double limiter(const orc_forest* f, double a, double b) {
+ * harmonic mean 2ab/(a+b), the monotonized central limiter of Sec. 2.3.1
+ * ('woodward') the smallest in magnitude of 2a, the central difference
+ * (a+b)/2 and 2b; all vanish at extrema (a b <= 0). */
+static double limit_ab(int kind, double a, double b) {
   if (a * b <= 0.0) return 0.0;
-  if (f->c.limiter == LIM_MINMOD) return fabs(a) < fabs(b) ? a : b;
+  if (kind == LIM_MINMOD) return fabs(a) < fabs(b) ? a : b;
+  if (kind == LIM_MC) {
+    double ta = 2.0 * a, tb = 2.0 * b, c = 0.5 * (a + b);
+    double m = fabs(ta) < fabs(tb) ? ta : tb;
+    return fabs(c) < fabs(m) ? c : m;
+  }
   return 2.0 * a * b / (a + b);
 }
+
+static double limiter(const orc_forest* f, double a, double b) { return limit_ab(f->c.limiter, a, b); }
+
+double orc_limiter_value(int kind, double a, double b) { return limit_ab(kind, a, b); }
 
 static double minmod(double a, double b) {
   if (a * b <= 0.0) return 0.0;
@@ -454,7 +465,7 @@ int orc_forest_create(const orc_config* cfg, int64_t n, const int32_t* lev, cons
   if (c->flux < 0 || c->flux > 2) return fail(ORC_EINVAL, "bad flux");
   if (c->physics == PHYS_MHD && c->flux == FLUX_HLLC)
     return fail(ORC_EINVAL, "HLLC is implemented for hydrodynamics only");
-  if (c->limiter < 0 || c->limiter > 1) return fail(ORC_EINVAL, "bad limiter");
+  if (c->limiter < 0 || c->limiter > 2) return fail(ORC_EINVAL, "bad limiter");
   if (c->rk_stages != 2 && c->rk_stages != 3) return fail(ORC_EINVAL, "rk_stages must be 2 or 3");
   if (!(c->gamma > 1.0) || !(c->cfl > 0.0)) return fail(ORC_EINVAL, "gamma must be > 1, cfl > 0");
   for (int d = 0; d < c->ndim; d++) {

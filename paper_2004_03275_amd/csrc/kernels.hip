@@ -1100,6 +1100,8 @@ static void dispatch(const LaunchCfg& c, Fn&& fn) {
   auto lim = [&](auto nd, auto mhd, auto fl) {
     if (c.lim == LIM_MINMOD)
       fn(nd, mhd, fl, IC<LIM_MINMOD>{});
+    else if (c.lim == LIM_MC)
+      fn(nd, mhd, fl, IC<LIM_MC>{});
     else
       fn(nd, mhd, fl, IC<LIM_VANLEER>{});
   };

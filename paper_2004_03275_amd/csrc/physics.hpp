@@ -13,7 +13,7 @@
 namespace amrv {
 
 enum { FLX_TVDLF = 0, FLX_HLL = 1, FLX_HLLC = 2 };
-enum { LIM_MINMOD = 0, LIM_VANLEER = 1 };
+enum { LIM_MINMOD = 0, LIM_VANLEER = 1, LIM_MC = 2 };
 
 struct PhysParams {
   double gamma;
@@ -159,11 +159,18 @@ __device__ __forceinline__ double wave_speed_dir(const double* v, int n, const P
   return 0.0;
 }
 
+// limited slope from the backward and forward differences: minmod (smaller
+// magnitude), van Leer (harmonic mean 2ab/(a+b)), monotonized central
+// (smallest magnitude of 2a, (a+b)/2, 2b); zero at extrema
 template <int LIM>
 __device__ __forceinline__ double limiter(double a, double b) {
   if (a * b <= 0.0) return 0.0;
   if constexpr (LIM == LIM_MINMOD) {
     return fabs(a) < fabs(b) ? a : b;
+  } else if constexpr (LIM == LIM_MC) {
+    const double ta = 2.0 * a, tb = 2.0 * b, c = 0.5 * (a + b);
+    const double m = fabs(ta) < fabs(tb) ? ta : tb;
+    return fabs(c) < fabs(m) ? c : m;
   } else {
     return 2.0 * a * b / (a + b);
   }

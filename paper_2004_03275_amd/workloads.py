@@ -36,6 +36,7 @@ HLLC = 2
 
 MINMOD = 0
 VANLEER = 1
+MC = 2  # monotonized central ('woodward')
 
 
 @dataclasses.dataclass

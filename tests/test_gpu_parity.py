@@ -101,7 +101,8 @@ def test_sod_full_run_matches_oracle():
     assert np.array_equal(G, R)
 
 
-@pytest.mark.parametrize("flux,lim", [(W.HLLC, W.VANLEER), (W.HLL, W.MINMOD), (W.TVDLF, W.VANLEER)])
+@pytest.mark.parametrize("flux,lim", [(W.HLLC, W.VANLEER), (W.HLL, W.MINMOD), (W.TVDLF, W.VANLEER), (W.HLLC, W.MC),
+                                      (W.TVDLF, W.MC)])
 def test_kh_small_matches_oracle(flux, lim):
     F = _gpu()
     s = W.kh_scheme(4)
@@ -145,6 +146,27 @@ def test_blast_small_amr_matches_oracle():
     G, _ = F.run(f, U, dts=dts)
     e = _report(f"blast small ({f.level_counts()})", G, R, f)
     assert e.max() <= TOL
+
+
+@pytest.mark.parametrize("lim", [W.MC, W.MINMOD])
+def test_blast_small_other_limiters_match_oracle(lim):
+    F = _gpu()
+    f, U = _blast_small()
+    f.scheme.limiter = lim
+    R, dts = oracle.run(f, U, steps=3)
+    G, _ = F.run(f, U, dts=dts)
+    _report(f"blast small limiter {lim}", G, R, f)
+    assert np.array_equal(G, R)
+
+
+def test_sod_monotonized_central_matches_oracle():
+    F = _gpu()
+    f, U = W.sod(1024, nblocks=8)
+    f.scheme.limiter = W.MC
+    R, dts = oracle.run(f, U, t_end=0.2)
+    G, gdts = F.run(f, U, t_end=0.2)
+    assert len(gdts) == len(dts)
+    assert np.array_equal(G, R)
 
 
 def test_flags_identical():
