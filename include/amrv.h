@@ -51,6 +51,7 @@ extern "C" {
 #define AMRV_MINMOD 0
 #define AMRV_VANLEER 1
 #define AMRV_MC 2 /* monotonized central ('woodward', Sec. 2.3.1) */
+#define AMRV_KOREN 3 /* Koren (Sec. 2.2, 2.3.2); runs the split stage-kernel variant */
 #define AMRV_BC_PERIODIC 0
 #define AMRV_BC_ZERO_GRADIENT 1
 
@@ -78,7 +79,7 @@ typedef struct {
   int32_t max_level;       /* 1 = pure domain decomposition */
   int32_t physics;         /* AMRV_EULER or AMRV_MHD_GLM */
   int32_t flux;            /* AMRV_TVDLF, AMRV_HLL, AMRV_HLLC (HLLC: Euler only) */
-  int32_t limiter;         /* AMRV_MINMOD, AMRV_VANLEER or AMRV_MC */
+  int32_t limiter;         /* AMRV_MINMOD, AMRV_VANLEER, AMRV_MC or AMRV_KOREN */
   int32_t rk_stages;       /* 2 (SSP-RK2) or 3 (SSP-RK3) */
   int32_t bc[3][2];        /* AMRV_BC_*, same value on both sides of a dimension */
   int32_t pad_;

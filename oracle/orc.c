@@ -41,7 +41,7 @@
 enum { NB_SAME = 0, NB_COARSER = 1, NB_FINER = 2, NB_BND = 3 };
 enum { PHYS_EULER = 0, PHYS_MHD = 1 };
 enum { FLUX_TVDLF = 0, FLUX_HLL = 1, FLUX_HLLC = 2 };
-enum { LIM_MINMOD = 0, LIM_VANLEER = 1, LIM_MC = 2 };
+enum { LIM_MINMOD = 0, LIM_VANLEER = 1, LIM_MC = 2, LIM_KOREN = 3 };
 
 static __thread char g_err[512];
 
@@ -350,17 +350,22 @@ static void riemann(const orc_forest* f, const double* vl_in, const double* vr_i
   }
 }
 
-/* Slope limiters on the backward and forward differences (the paper names
- * minmod-type and other limited reconstructions, Sec. 2.2-2.4; formulas are
- * the textbook ones): minmod picks the smaller magnitude, van Leer the
+/* Limited slope of a cell toward one of its faces, from the difference a
+ * on the side away from that face and the difference b toward it (the paper
+ * names minmod-type and other limited reconstructions, Sec. 2.2-2.4, with the
+ * textbook formulas): minmod picks the smaller magnitude, van Leer the
  * harmonic mean 2ab/(a+b), the monotonized central limiter of Sec. 2.3.1
  * ('woodward') the smallest in magnitude of 2a, the central difference
- * (a+b)/2 and 2b; all vanish at extrema (a b <= 0). */
+ * (a+b)/2 and 2b, Koren's limiter (Sec. 2.2, 2.3.2) the smallest of 2a, the
+ * third-order (kappa = 1/3) combination (a+2b)/3 and 2b.  All vanish at
+ * extrema (a b <= 0).  The first three are symmetric in a and b; Koren's is
+ * not, so a cell's two faces get different slopes. */
 static double limit_ab(int kind, double a, double b) {
   if (a * b <= 0.0) return 0.0;
   if (kind == LIM_MINMOD) return fabs(a) < fabs(b) ? a : b;
-  if (kind == LIM_MC) {
-    double ta = 2.0 * a, tb = 2.0 * b, c = 0.5 * (a + b);
+  if (kind == LIM_MC || kind == LIM_KOREN) {
+    double ta = 2.0 * a, tb = 2.0 * b;
+    double c = kind == LIM_MC ? 0.5 * (a + b) : (a + 2.0 * b) / 3.0;
     double m = fabs(ta) < fabs(tb) ? ta : tb;
     return fabs(c) < fabs(m) ? c : m;
   }
@@ -465,7 +470,7 @@ int orc_forest_create(const orc_config* cfg, int64_t n, const int32_t* lev, cons
   if (c->flux < 0 || c->flux > 2) return fail(ORC_EINVAL, "bad flux");
   if (c->physics == PHYS_MHD && c->flux == FLUX_HLLC)
     return fail(ORC_EINVAL, "HLLC is implemented for hydrodynamics only");
-  if (c->limiter < 0 || c->limiter > 2) return fail(ORC_EINVAL, "bad limiter");
+  if (c->limiter < 0 || c->limiter > 3) return fail(ORC_EINVAL, "bad limiter");
   if (c->rk_stages != 2 && c->rk_stages != 3) return fail(ORC_EINVAL, "rk_stages must be 2 or 3");
   if (!(c->gamma > 1.0) || !(c->cfl > 0.0)) return fail(ORC_EINVAL, "gamma must be > 1, cfl > 0");
   for (int d = 0; d < c->ndim; d++) {
@@ -819,8 +824,10 @@ static void face_flux(const orc_forest* f, const double* P, int d, const int x[3
   double vl[NVMAX], vr[NVMAX];
   for (int k = 0; k < nv; k++) {
     const double* p = P + (int64_t)k * f->npad;
+    /* left state: cell m-1 toward its upper face (away: backward difference);
+     * right state: cell m toward its lower face (away: forward difference) */
     double sl = limiter(f, p[im1] - p[im2], p[i0] - p[im1]);
-    double sr = limiter(f, p[i0] - p[im1], p[ip1] - p[i0]);
+    double sr = limiter(f, p[ip1] - p[i0], p[i0] - p[im1]);
     vl[k] = p[im1] + 0.5 * sl;
     vr[k] = p[i0] - 0.5 * sr;
   }

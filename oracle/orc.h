@@ -44,7 +44,7 @@ typedef struct {
   int32_t max_level;       /* refine_max_level of Sec. 1.3 (1 = pure decomposition) */
   int32_t physics;         /* 0 = Euler (HD), 1 = ideal MHD with GLM cleaning */
   int32_t flux;            /* 0 = TVDLF, 1 = HLL, 2 = HLLC */
-  int32_t limiter;         /* 0 = minmod, 1 = van Leer, 2 = monotonized central */
+  int32_t limiter;         /* 0 = minmod, 1 = van Leer, 2 = monotonized central, 3 = Koren */
   int32_t rk_stages;       /* 2 = SSP-RK2, 3 = SSP-RK3 */
   int32_t bc[3][2];        /* per dimension, low/high side: 0 periodic, 1 zero gradient */
   int32_t pad_;
@@ -98,8 +98,9 @@ int orc_regrid_plan(const orc_forest* f, const int8_t* flags, int64_t cap, int64
  * (coarse value plus a quarter minmod slope per dimension, the parent's ghost
  * cells at its boundary), parents by restriction of their children. */
 int orc_regrid_transfer(orc_forest* from, orc_forest* to);
-/* Test hook: the limited slope of a cell from its backward and forward
- * differences a, b (limiter 0 minmod, 1 van Leer, 2 monotonized central). */
+/* Test hook: the limited slope of a cell toward a face from the difference a
+ * away from the face and b toward it (limiter 0 minmod, 1 van Leer,
+ * 2 monotonized central, 3 Koren). */
 double orc_limiter_value(int limiter, double a, double b);
 void orc_set_threads(int n);
 int orc_get_threads(void);

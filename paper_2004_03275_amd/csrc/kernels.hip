@@ -513,7 +513,7 @@ __device__ __forceinline__ void load_strided(const double* __restrict__ p, size_
 // of LDS arrays (5 barriers per plane, 40% less LDS, so more workgroups fit
 // on a compute unit).  Both evaluate identical expressions.
 template <int ND, bool MHD, int FLUX, int LIM, bool SPLIT>
-__global__ void __launch_bounds__(WGS, (SPLIT && Sys<ND, MHD>::NV <= 5) ? 3 : 1) k_stage_tile(Geo g, StageArgs a, const double* __restrict__ pp,
+__global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, MHD>::NV <= 5) ? 3 : 1) k_stage_tile(Geo g, StageArgs a, const double* __restrict__ pp,
                                                                   Sched sc) {
   using S = Sys<ND, MHD>;
   constexpr int NV = S::NV;
@@ -522,11 +522,17 @@ __global__ void __launch_bounds__(WGS, (SPLIT && Sys<ND, MHD>::NV <= 5) ? 3 : 1)
   constexpr int NSX = NB * 18;  // x slopes: 16 rows x cells -1..16, [row][cell+1]
   constexpr int NFX = NB * 17;  // x faces: 16 rows x faces 0..16, [row][face]
   constexpr int NSB = SPLIT ? 1 : 2;
+  // an asymmetric limiter keeps two half slopes per cell (toward the upper
+  // and toward the lower face) and runs the split variant only
+  constexpr bool ASYM = lim_asym<LIM>();
+  static_assert(!ASYM || SPLIT, "asymmetric limiters use the split variant");
+  constexpr int NSS = (SPLIT && !ASYM) ? 1 : 2;
   __shared__ double sP[NV][PW * PW];  // primitive plane incl. x/y ghost ring, (y+2)*PW + x+2
-  __shared__ double sS[NSB][NV][NSX]; // half slopes 0.5*phi: x [row][cell+1]; y [cell+1][column]
+  __shared__ double sS[NSS][NV][NSX]; // half slopes 0.5*phi: x [row][cell+1]; y [cell+1][column]
+                                      // (asymmetric: [0] toward the upper, [1] toward the lower face)
   __shared__ double sF[NSB][NV][NFX]; // fluxes: x [row][face]; y [face][column]
   auto& sSx = sS[0];
-  auto& sSy = sS[NSB - 1];
+  auto& sSy = sS[NSS - 1];
   auto& sFx = sF[0];
   auto& sFy = sF[NSB - 1];
   __shared__ double sZF[ND == 3 ? NV : 1][ND == 3 ? NB * NB : 1];  // +z coarse-fine face flux of the own column
@@ -734,11 +740,16 @@ __global__ void __launch_bounds__(WGS, (SPLIT && Sys<ND, MHD>::NV <= 5) ? 3 : 1)
             const double vm = sP[v][b - st], v0 = sP[v][b], vp = sP[v][b + st];
             // the half slope, formed once per cell: both face states of the
             // cell add or subtract the same product 0.5*phi
-            const double sl = 0.5 * limiter<LIM>(v0 - vm, vp - v0);
-            if (!yd)
+            const double sa = v0 - vm, sb = vp - v0;
+            const double sl = 0.5 * limiter<LIM>(sa, sb);
+            if constexpr (ASYM) {
+              sS[0][v][u] = sl;
+              sS[1][v][u] = 0.5 * limiter<LIM>(sb, sa);
+            } else if (!yd) {
               sSx[v][u] = sl;
-            else
+            } else {
               sSy[v][u] = sl;
+            }
           }
         }
       };
@@ -773,12 +784,13 @@ __global__ void __launch_bounds__(WGS, (SPLIT && Sys<ND, MHD>::NV <= 5) ? 3 : 1)
           if (bf >= 0 && !(kinds[bf] == NB_SAME || kinds[bf] == NB_BND)) {
             cf_flux<NV, ND>(g, leaf, bf, kinds[bf], r, k, F);
           } else {
-            const double* sl = &sS[yd ? NSB - 1 : 0][0][0];
+            const double* slu = &sS[ASYM ? 0 : (yd ? NSS - 1 : 0)][0][0];  // toward the upper face
+            const double* sll = &sS[ASYM ? 1 : (yd ? NSS - 1 : 0)][0][0];  // toward the lower face
             double vl[NV], vr[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++) {
-              vl[v] = sP[v][bl] + sl[v * NSX + s0];
-              vr[v] = sP[v][bl + st] - sl[v * NSX + s1];
+              vl[v] = sP[v][bl] + slu[v * NSX + s0];
+              vr[v] = sP[v][bl + st] - sll[v * NSX + s1];
             }
             if (yd) {
               swap_xy<ND, MHD>(vl);
@@ -1102,6 +1114,8 @@ static void dispatch(const LaunchCfg& c, Fn&& fn) {
       fn(nd, mhd, fl, IC<LIM_MINMOD>{});
     else if (c.lim == LIM_MC)
       fn(nd, mhd, fl, IC<LIM_MC>{});
+    else if (c.lim == LIM_KOREN)
+      fn(nd, mhd, fl, IC<LIM_KOREN>{});
     else
       fn(nd, mhd, fl, IC<LIM_VANLEER>{});
   };
@@ -1196,9 +1210,9 @@ hipError_t launch_stage(const Geo& g, const LaunchCfg& c, const StageArgs& a, co
     constexpr bool MHD = decltype(mhd)::value != 0;
     if constexpr (ND == 1)
       hipLaunchKernelGGL((k_stage_line<MHD, FL, LM>), dim3(grid), dim3(WGS), 0, st, g, a, physp, s);
-    else if (c.variant == 1)
+    else if (c.variant == 1 || lim_asym<LM>())
       hipLaunchKernelGGL((k_stage_tile<ND, MHD, FL, LM, true>), dim3(grid), dim3(WGS), 0, st, g, a, physp, s);
-    else
+    else if constexpr (!lim_asym<LM>())
       hipLaunchKernelGGL((k_stage_tile<ND, MHD, FL, LM, false>), dim3(grid), dim3(WGS), 0, st, g, a, physp, s);
   });
   return hipGetLastError();

@@ -13,7 +13,12 @@
 namespace amrv {
 
 enum { FLX_TVDLF = 0, FLX_HLL = 1, FLX_HLLC = 2 };
-enum { LIM_MINMOD = 0, LIM_VANLEER = 1, LIM_MC = 2 };
+enum { LIM_MINMOD = 0, LIM_VANLEER = 1, LIM_MC = 2, LIM_KOREN = 3 };
+
+// limiters whose slope toward a face depends on which face (not symmetric in
+// the two differences): a cell keeps two slopes
+template <int LIM>
+constexpr bool lim_asym() { return LIM == LIM_KOREN; }
 
 struct PhysParams {
   double gamma;
@@ -159,16 +164,19 @@ __device__ __forceinline__ double wave_speed_dir(const double* v, int n, const P
   return 0.0;
 }
 
-// limited slope from the backward and forward differences: minmod (smaller
-// magnitude), van Leer (harmonic mean 2ab/(a+b)), monotonized central
-// (smallest magnitude of 2a, (a+b)/2, 2b); zero at extrema
+// limited slope of a cell toward a face from the difference a away from it
+// and b toward it: minmod (smaller magnitude), van Leer (harmonic mean
+// 2ab/(a+b)), monotonized central (smallest magnitude of 2a, (a+b)/2, 2b),
+// Koren (smallest of 2a, (a+2b)/3, 2b); zero at extrema.  All but Koren are
+// symmetric in a and b, bit for bit.
 template <int LIM>
 __device__ __forceinline__ double limiter(double a, double b) {
   if (a * b <= 0.0) return 0.0;
   if constexpr (LIM == LIM_MINMOD) {
     return fabs(a) < fabs(b) ? a : b;
-  } else if constexpr (LIM == LIM_MC) {
-    const double ta = 2.0 * a, tb = 2.0 * b, c = 0.5 * (a + b);
+  } else if constexpr (LIM == LIM_MC || LIM == LIM_KOREN) {
+    const double ta = 2.0 * a, tb = 2.0 * b;
+    const double c = LIM == LIM_MC ? 0.5 * (a + b) : (a + 2.0 * b) / 3.0;
     const double m = fabs(ta) < fabs(tb) ? ta : tb;
     return fabs(c) < fabs(m) ? c : m;
   } else {
@@ -284,14 +292,20 @@ __device__ __forceinline__ void riemann(double* vl, double* vr, double* F, const
 }
 
 // limited face states of a cell from its two neighbours along one direction:
-// hi = v0 + 0.5*phi (value at the cell's upper face), lo = v0 - 0.5*phi
+// hi = v0 + 0.5*phi(backward, forward) (value at the cell's upper face),
+// lo = v0 - 0.5*phi(forward, backward) (lower face; the same phi unless the
+// limiter is asymmetric)
 template <int NV, int LIM>
 __device__ __forceinline__ void muscl(const double* vm, const double* v0, const double* vp, double* lo, double* hi) {
 #pragma unroll
   for (int k = 0; k < NV; k++) {
-    const double s = limiter<LIM>(v0[k] - vm[k], vp[k] - v0[k]);
+    const double a = v0[k] - vm[k], b = vp[k] - v0[k];
+    const double s = limiter<LIM>(a, b);
     hi[k] = v0[k] + 0.5 * s;
-    lo[k] = v0[k] - 0.5 * s;
+    if constexpr (lim_asym<LIM>())
+      lo[k] = v0[k] - 0.5 * limiter<LIM>(b, a);
+    else
+      lo[k] = v0[k] - 0.5 * s;
   }
 }
 

@@ -37,6 +37,7 @@ HLLC = 2
 MINMOD = 0
 VANLEER = 1
 MC = 2  # monotonized central ('woodward')
+KOREN = 3
 
 
 @dataclasses.dataclass

@@ -102,7 +102,7 @@ def test_sod_full_run_matches_oracle():
 
 
 @pytest.mark.parametrize("flux,lim", [(W.HLLC, W.VANLEER), (W.HLL, W.MINMOD), (W.TVDLF, W.VANLEER), (W.HLLC, W.MC),
-                                      (W.TVDLF, W.MC)])
+                                      (W.TVDLF, W.MC), (W.HLLC, W.KOREN), (W.HLL, W.KOREN)])
 def test_kh_small_matches_oracle(flux, lim):
     F = _gpu()
     s = W.kh_scheme(4)
@@ -148,7 +148,7 @@ def test_blast_small_amr_matches_oracle():
     assert e.max() <= TOL
 
 
-@pytest.mark.parametrize("lim", [W.MC, W.MINMOD])
+@pytest.mark.parametrize("lim", [W.MC, W.MINMOD, W.KOREN])
 def test_blast_small_other_limiters_match_oracle(lim):
     F = _gpu()
     f, U = _blast_small()
@@ -159,13 +159,23 @@ def test_blast_small_other_limiters_match_oracle(lim):
     assert np.array_equal(G, R)
 
 
-def test_sod_monotonized_central_matches_oracle():
+@pytest.mark.parametrize("lim", [W.MC, W.KOREN])
+def test_sod_other_limiters_match_oracle(lim):
     F = _gpu()
     f, U = W.sod(1024, nblocks=8)
-    f.scheme.limiter = W.MC
+    f.scheme.limiter = lim
     R, dts = oracle.run(f, U, t_end=0.2)
     G, gdts = F.run(f, U, t_end=0.2)
     assert len(gdts) == len(dts)
+    assert np.array_equal(G, R)
+
+
+def test_orszag_tang_koren_matches_oracle():
+    F = _gpu()
+    f, U = W.orszag_tang(4)
+    f.scheme.limiter = W.KOREN
+    R, dts = oracle.run(f, U, steps=20)
+    G, _ = F.run(f, U, dts=dts)
     assert np.array_equal(G, R)
 
 
