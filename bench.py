@@ -68,6 +68,12 @@ def make_workload(name: str):
     elif name == "sod":
         f, U = W.sod(1024)
         desc = "1d_sod"
+    elif name == "mhdblast2d":
+        f, U = W.mhd_blast(2, base=4, max_level=4)
+        desc = "2d_amr_mhd_blast"
+    elif name == "mhdblast3d":
+        f, U = W.mhd_blast(3, base=4, max_level=3)
+        desc = "3d_amr_mhd_blast"
     else:
         raise SystemExit(f"unknown workload {name}")
     return desc, f, U
@@ -78,7 +84,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="blast", choices=["blast", "kh", "ot", "sod"])
+    ap.add_argument("--workload", default="blast", choices=["blast", "kh", "ot", "sod", "mhdblast2d", "mhdblast3d"])
     ap.add_argument("--flag-every", type=int, default=10)
     ap.add_argument("--per-block-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")

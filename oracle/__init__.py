@@ -227,9 +227,12 @@ class OracleForest:
 
 
 def run(forest, U0: np.ndarray, *, t_end: float | None = None, steps: int | None = None,
-        dts=None):
+        dts=None, ramp_steps: int = 0):
     """Drive the oracle: free Courant steps to t_end, a fixed step count, or a
-    given dt sequence (lockstep runs).  Returns (state, list of dt used)."""
+    given dt sequence (lockstep runs); ramp_steps > 0 scales the Courant step
+    of the first steps by workloads.courant_ramp.  Returns (state, dts used)."""
+    from paper_2004_03275_amd.workloads import courant_ramp
+
     o = OracleForest(forest)
     o.set_state(U0)
     used = []
@@ -244,7 +247,7 @@ def run(forest, U0: np.ndarray, *, t_end: float | None = None, steps: int | None
         while True:
             if steps is not None and n >= steps:
                 break
-            dt = o.max_dt()
+            dt = o.max_dt() * courant_ramp(n, ramp_steps)
             if t_end is not None:
                 if t >= t_end:
                     break

@@ -208,9 +208,13 @@ class GpuForest:
 
 
 def run(forest, U0, *, t_end=None, steps=None, dts=None, schedule=None, graph=False, device="cuda:0",
-        variant=None, device_dt=False, chunk=50):
+        variant=None, device_dt=False, chunk=50, ramp_steps=0):
     """Drive the GPU forest like oracle.run: free Courant steps to t_end, a
-    fixed step count, or a given dt sequence.  Returns (state, dts used)."""
+    fixed step count, or a given dt sequence; ramp_steps > 0 scales the first
+    Courant steps by workloads.courant_ramp (host-chosen steps only).
+    Returns (state, dts used)."""
+    from .workloads import courant_ramp
+
     g = GpuForest(forest, device=device)
     if schedule is not None:
         g.set_schedule(*schedule)
@@ -221,8 +225,8 @@ def run(forest, U0, *, t_end=None, steps=None, dts=None, schedule=None, graph=Fa
     g.set_state(U0)
     used = []
     if device_dt:
-        if dts is not None:
-            raise ValueError("device_dt runs choose their own time steps")
+        if dts is not None or ramp_steps:
+            raise ValueError("device_dt runs choose their own time steps (no ramp)")
         t, n = 0.0, 0
         tend = float("inf") if t_end is None else float(t_end)
         while True:
@@ -246,7 +250,7 @@ def run(forest, U0, *, t_end=None, steps=None, dts=None, schedule=None, graph=Fa
         while True:
             if steps is not None and n >= steps:
                 break
-            dt = g.max_dt()
+            dt = g.max_dt() * courant_ramp(n, ramp_steps)
             if t_end is not None:
                 if t >= t_end:
                     break

@@ -434,6 +434,48 @@ def blast(scheme: Scheme | None = None, radius: float = 0.1, p_in: float = 100.0
     return f, state_from_primitive(f, rho, vel, p)
 
 
+def mhd_blast_scheme(ndim: int = 2, base: int = 4, max_level: int = 4, limiter: int = KOREN) -> Scheme:
+    """The paper's MHD blast (Sec. 2.4) on [-0.5, 0.5]^ndim: gamma 5/3,
+    three-step Runge-Kutta, Courant number 0.9 (the drivers ramp the first
+    10 steps), periodic sides, 16-cell blocks on a 64-cell base grid.  HLL
+    with GLM cleaning and Koren's limiter stand in for the paper's MHD-HLLC
+    flux, Cada limiter and multigrid div B control."""
+    nd = ndim
+    return Scheme(ndim=nd, block_nx=(16,) * nd, base_blocks=(base,) * nd, max_level=max_level,
+                  xmin=(-0.5,) * nd, xmax=(0.5,) * nd, physics=MHD, gamma=5.0 / 3.0, flux=HLL,
+                  limiter=limiter, rk_stages=3, cfl=0.9, bc=PERIODIC)
+
+
+def mhd_blast(ndim: int = 2, base: int = 4, max_level: int = 4, radius: float = 0.1, p_in: float = 10.0,
+              p_out: float = 0.1, buffer_cells: float = 4.0, scheme: Scheme | None = None,
+              forest: Forest | None = None):
+    """rho = 1, v = 0, p = p_in within ``radius`` of the origin (cell
+    centres) else p_out, uniform B = (1, 1[, 1])/sqrt(ndim), psi = 0: plasma
+    beta 0.2 outside and 20 inside (mu0 = 1).  The forest is refined around
+    the blast surface like the hydrodynamic blast's."""
+    s = scheme or mhd_blast_scheme(ndim, base, max_level)
+    f = forest or blast_forest(s, radius, (0.0, 0.0, 0.0), buffer_cells)
+    xs = cell_centres(f)
+    r2 = np.zeros_like(xs[0])
+    for d in range(s.ndim):
+        r2 = r2 + xs[d] ** 2
+    rho = np.ones_like(r2)
+    p = np.where(r2 < radius * radius, p_in, p_out)
+    vel = [np.zeros_like(r2) for _ in range(s.ndim)]
+    b0 = 1.0 / math.sqrt(s.ndim)
+    B = [np.full_like(r2, b0) for _ in range(s.ndim)]
+    return f, state_from_primitive(f, rho, vel, p, B)
+
+
+def courant_ramp(step: int, ramp_steps: int) -> float:
+    """Factor on the Courant time step of step ``step`` (from 0): the paper
+    reduces the first 10 steps of its MHD blast gradually (Sec. 2.4); read
+    here as a linear ramp (step + 1) / ramp_steps."""
+    if ramp_steps <= 0 or step >= ramp_steps:
+        return 1.0
+    return (step + 1) / ramp_steps
+
+
 def relative_l1(U: np.ndarray, R: np.ndarray, forest: Forest) -> np.ndarray:
     """Per conserved variable: sum |U - R| dV / max(sum |R| dV, 1e-6 sum |E_R| dV),
     with dV the cell volume of each leaf's level."""

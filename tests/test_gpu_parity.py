@@ -179,6 +179,19 @@ def test_orszag_tang_koren_matches_oracle():
     assert np.array_equal(G, R)
 
 
+@pytest.mark.parametrize("nd", [2, 3])
+def test_mhd_blast_matches_oracle(nd):
+    """The paper's MHD blast (Sec. 2.4) on a small AMR forest, with the
+    Courant ramp: exercises the 2D and 3D MHD stage kernels."""
+    F = _gpu()
+    f, U = W.mhd_blast(nd, base=2, max_level=3)
+    R, dts = oracle.run(f, U, steps=6, ramp_steps=10)
+    G, gdts = F.run(f, U, steps=6, ramp_steps=10)
+    assert gdts == dts
+    _report(f"mhd blast {nd}D ({f.level_counts()})", G, R, f)
+    assert np.array_equal(G, R)
+
+
 def test_flags_identical():
     F = _gpu()
     for name, (f, U) in {"kh": W.kh(4), "blast": _blast_small(), "ot": W.orszag_tang(4)}.items():

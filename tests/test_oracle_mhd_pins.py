@@ -10,10 +10,13 @@
   of the system): B_x - B0 = d sin(2 pi x) cos(2 pi tau), psi = -c_h d
   cos(2 pi x) sin(2 pi tau), tau = sum c_h dt; and the once-per-step damping
   multiplies psi by exp(-dt c_h / c_r).
+* The paper's MHD blast (Sec. 2.4; uniform B along the diagonal) stays
+  point symmetric and symmetric under x <-> y with the components exchanged.
 """
 import math
 
 import numpy as np
+import pytest
 
 import oracle
 from paper_2004_03275_amd import workloads as W
@@ -123,3 +126,50 @@ def test_glm_damping_factor():
     assert 0.1 < damp < 0.95
     for v in range(6):  # the rest stays uniform and unchanged up to rounding
         assert np.allclose(R[v], U[v], rtol=1e-13, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# the paper's MHD blast (Sec. 2.4): symmetries of the setup
+# ---------------------------------------------------------------------------
+
+
+def _global_2d(f, U):
+    """State of a uniform 2D forest as [var][y][x] over the whole domain."""
+    s = f.scheme
+    nb = s.block_nx[0]
+    G = np.empty((U.shape[0], s.base_blocks[1] * nb, s.base_blocks[0] * nb))
+    for b in range(f.n):
+        i, j = int(f.ijk[b][0]), int(f.ijk[b][1])
+        G[:, j * nb:(j + 1) * nb, i * nb:(i + 1) * nb] = U[:, b]
+    return G
+
+
+def test_mhd_blast_point_and_diagonal_symmetry():
+    """rho, p radial, v = 0, B uniform along the diagonal: the solution stays
+    point symmetric (rho even, v odd, B even under x -> -x) and symmetric
+    under x <-> y with the x and y components exchanged."""
+    f, U = W.mhd_blast(2, base=4, max_level=1)
+    R, dts = oracle.run(f, U, steps=25, ramp_steps=10)
+    assert dts[0] * 10 == pytest.approx(dts[1] * 5, rel=0.5)  # the ramp is on
+    G = _global_2d(f, R)
+    scale = np.abs(G).reshape(G.shape[0], -1).max(axis=1)
+    # point symmetry (the grid is symmetric about the origin)
+    P = G[:, ::-1, ::-1]
+    assert np.all(np.abs(G[0] - P[0]) <= 1e-11 * scale[0])
+    for k in (1, 2):
+        assert np.all(np.abs(G[k] + P[k]) <= 1e-11 * scale[k] + 1e-14)
+    for k in (3, 4, 5):
+        assert np.all(np.abs(G[k] - P[k]) <= 1e-11 * scale[k])
+    # diagonal mirror: transpose, exchange x and y components
+    T = np.transpose(G, (0, 2, 1))
+    assert np.all(np.abs(G[0] - T[0]) <= 1e-11 * scale[0])
+    assert np.all(np.abs(G[1] - T[2]) <= 1e-11 * scale[1] + 1e-14)
+    assert np.all(np.abs(G[3] - T[3]) <= 1e-11 * scale[3])
+    assert np.all(np.abs(G[4] - T[5]) <= 1e-11 * scale[4])
+    # the blast has moved: not trivially symmetric because nothing happened
+    assert np.abs(G[1]).max() > 0.1
+
+
+def test_courant_ramp():
+    assert [W.courant_ramp(n, 10) for n in range(12)] == [(n + 1) / 10 for n in range(10)] + [1.0, 1.0]
+    assert W.courant_ramp(0, 0) == 1.0
