@@ -102,6 +102,9 @@ def main():
                     help="also run this many steps from the initial state with regridding (default 20 on the "
                          "3D blast, 0 elsewhere)")
     ap.add_argument("--regrid-every", type=int, default=5)
+    ap.add_argument("--adaptive-flagger", default="lohner", choices=["lohner", "mlp"],
+                    help="flags of the adaptive run: Loehner, or the learned flagger with Loehner fallback "
+                         "(judged against full Loehner flags every second regrid)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -308,6 +311,14 @@ def main():
         g.set_state(U0)
         ga = g
         t_ad, done, updates, regrid_ms, regrids, counts = 0.0, 0, 0, 0.0, 0, []
+        use_mlp = args.adaptive_flagger == "mlp" and s.ndim > 1
+        judge = []
+        if use_mlp:
+            from paper_2004_03275_amd import mlp as MLP
+
+            wts = MLP.trained_weights()
+            g.mlp_set_weights(wts)
+            g.mlp_set_margin(2.0)
         g.synchronize()
         t0 = time.perf_counter()
         while done < nad:
@@ -318,7 +329,17 @@ def main():
             if done < nad:
                 ga.synchronize()
                 r0 = time.perf_counter()
-                nxt = ga.regrid(ga.flag_blocks())
+                if use_mlp:
+                    flags = ga.flag_blocks(mode=N.FLAG_MLP_FALLBACK)
+                    if regrids % 2 == 1:
+                        ref = ga.flag_blocks()
+                        judge.append(float(np.mean((flags == 1) != (ref == 1))))
+                else:
+                    flags = ga.flag_blocks()
+                nxt = ga.regrid(flags)
+                if use_mlp:
+                    nxt.mlp_set_weights(wts)
+                    nxt.mlp_set_margin(2.0)
                 if ga is not g:
                     ga.close()
                 ga = nxt
@@ -331,7 +352,9 @@ def main():
                      "regrids": regrids, "regrid_ms_avg": regrid_ms / max(regrids, 1),
                      "leaves_after_each_regrid": counts, "final_levels": {str(k): v for k, v in
                                                                            ga.forest.level_counts().items()},
-                     "note": "cell updates of the current forest per step; regrid = Loehner flags, plan, new "
+                     "flagger": "mlp_fallback" if use_mlp else "lohner",
+                     "judge_refine_disagreement": judge if use_mlp else None,
+                     "note": "cell updates of the current forest per step; regrid = flags, plan, new "
                              "forest (workspace, tables), transfer"}
         log(f"adaptive: {adaptive['value']:.1f} MCUPS over {nad} steps, {regrids} regrids of "
             f"{adaptive['regrid_ms_avg']:.1f} ms, leaves {counts}")

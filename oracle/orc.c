@@ -311,7 +311,76 @@ static void riemann(const orc_forest* f, const double* vl_in, const double* vr_i
       for (int k = 0; k < nv; k++)
         F[k] = ((sr * fl[k] - sl * fr[k]) + (sl * sr) * (ur[k] - ul[k])) * ids;
     }
-  } else { /* HLLC, hydrodynamics only */
+  } else if (f->mhd) {
+    /* HLLC for MHD, after Li (2005) as cited by the paper (Sec. 2.4): total
+     * pressure p_T = p + B.B/2 in the contact speed and the star pressure,
+     * normal field B_n from the GLM sub-solve on both sides; in the star
+     * region the transverse velocity and field come from the HLL state
+     * (the same on both sides), or, where B_n = 0, from the side's own
+     * velocity and its field compressed like the density; star energy
+     * E* = ((S_K - u_K) E_K - p_TK u_K + p_T* S_M + B_n (v_K.B_K - v*.B*)) / (S_K - S_M). */
+    const int ie = iE(f), ib = iB(f), nd = f->nd;
+    double sl = dmin(unl - cl, unr - cr);
+    double sr = dmax(unl + cl, unr + cr);
+    if (sl >= 0.0) {
+      for (int k = 0; k < nv; k++) F[k] = fl[k];
+    } else if (sr <= 0.0) {
+      for (int k = 0; k < nv; k++) F[k] = fr[k];
+    } else {
+      double bbl = vl[ib] * vl[ib], bbr = vr[ib] * vr[ib];
+      for (int d = 1; d < nd; d++) {
+        bbl = bbl + vl[ib + d] * vl[ib + d];
+        bbr = bbr + vr[ib + d] * vr[ib + d];
+      }
+      double ptl = vl[ie] + 0.5 * bbl, ptr = vr[ie] + 0.5 * bbr;
+      double rl = vl[0] * (sl - unl);
+      double rr = vr[0] * (sr - unr);
+      double sm = ((ptr - ptl) + unl * rl - unr * rr) / (rl - rr);
+      double ids = 1.0 / (sr - sl);
+      double uh[NVMAX]; /* HLL state: density, momenta, field */
+      for (int k = 0; k <= nd; k++) uh[k] = ((sr * ur[k] - sl * ul[k]) - (fr[k] - fl[k])) * ids;
+      for (int d = 0; d < nd; d++)
+        uh[ib + d] = ((sr * ur[ib + d] - sl * ul[ib + d]) - (fr[ib + d] - fl[ib + d])) * ids;
+      const int left = sm >= 0.0;
+      const double* vk = left ? vl : vr;
+      const double* uk = left ? ul : ur;
+      const double* fk = left ? fl : fr;
+      double sk = left ? sl : sr;
+      double rk = left ? rl : rr;
+      double unk = vk[1 + n], ptk = left ? ptl : ptr;
+      double inv = 1.0 / (sk - sm);
+      double coef = rk * inv;
+      double pts = ptk + rk * (sm - unk);
+      double bn = bns;
+      double vs[3] = {0.0, 0.0, 0.0}, bs[3] = {0.0, 0.0, 0.0};
+      for (int d = 0; d < nd; d++) {
+        if (d == n) {
+          vs[d] = sm;
+          bs[d] = bn;
+        } else if (bn == 0.0) {
+          vs[d] = vk[1 + d];
+          bs[d] = vk[ib + d] * ((sk - unk) * inv);
+        } else {
+          vs[d] = uh[1 + d] / uh[0];
+          bs[d] = uh[ib + d];
+        }
+      }
+      double vbk = vk[1] * vk[ib], vbs = vs[0] * bs[0];
+      for (int d = 1; d < nd; d++) {
+        vbk = vbk + vk[1 + d] * vk[ib + d];
+        vbs = vbs + vs[d] * bs[d];
+      }
+      double us[NVMAX];
+      us[0] = coef;
+      for (int d = 0; d < nd; d++) {
+        us[1 + d] = coef * vs[d];
+        us[ib + d] = bs[d];
+      }
+      us[ie] = ((sk - unk) * uk[ie] - ptk * unk + pts * sm + bn * (vbk - vbs)) * inv;
+      us[iPsi(f)] = uk[iPsi(f)];
+      for (int k = 0; k < nv; k++) F[k] = fk[k] + sk * (us[k] - uk[k]);
+    }
+  } else { /* HLLC, hydrodynamics */
     const int ie = iE(f);
     double sl = dmin(unl - cl, unr - cr);
     double sr = dmax(unl + cl, unr + cr);
@@ -468,8 +537,6 @@ int orc_forest_create(const orc_config* cfg, int64_t n, const int32_t* lev, cons
   if (c->max_level < 1 || c->max_level > 12) return fail(ORC_EINVAL, "max_level out of range");
   if (c->physics != PHYS_EULER && c->physics != PHYS_MHD) return fail(ORC_EINVAL, "bad physics");
   if (c->flux < 0 || c->flux > 2) return fail(ORC_EINVAL, "bad flux");
-  if (c->physics == PHYS_MHD && c->flux == FLUX_HLLC)
-    return fail(ORC_EINVAL, "HLLC is implemented for hydrodynamics only");
   if (c->limiter < 0 || c->limiter > 3) return fail(ORC_EINVAL, "bad limiter");
   if (c->rk_stages != 2 && c->rk_stages != 3) return fail(ORC_EINVAL, "rk_stages must be 2 or 3");
   if (!(c->gamma > 1.0) || !(c->cfl > 0.0)) return fail(ORC_EINVAL, "gamma must be > 1, cfl > 0");

@@ -1122,10 +1122,10 @@ static void dispatch(const LaunchCfg& c, Fn&& fn) {
   auto flx = [&](auto nd, auto mhd) {
     if (c.flux == FLX_TVDLF)
       lim(nd, mhd, IC<FLX_TVDLF>{});
-    else if (c.flux == FLX_HLL || decltype(mhd)::value)
+    else if (c.flux == FLX_HLL)
       lim(nd, mhd, IC<FLX_HLL>{});
     else
-      lim(nd, mhd, IC<(decltype(mhd)::value ? FLX_HLL : FLX_HLLC)>{});
+      lim(nd, mhd, IC<FLX_HLLC>{});
   };
   auto phys = [&](auto nd) {
     if (c.mhd)

@@ -238,14 +238,101 @@ __device__ __forceinline__ void hllc_flux(const double* vl, const double* vr, do
   }
 }
 
+// HLLC for MHD after Li (2005): total pressure p_T = p + B.B/2 in the
+// contact speed and star pressure, the GLM normal field on both sides
+// (already in vl, vr); in the star region the transverse velocity and field
+// are the HLL state's (the same on both sides), or where B_n = 0 the side's
+// own velocity and its field compressed like the density; star energy
+// E* = ((S_K-u_K) E_K - p_TK u_K + p_T* S_M + B_n (v_K.B_K - v*.B*)) / (S_K-S_M).
+template <int ND, int N>
+__device__ __forceinline__ void hllc_mhd(const double* vl, const double* vr, const double* ul, const double* ur,
+                                         const double* fl, const double* fr, double cl, double cr, double* F) {
+  using S = Sys<ND, true>;
+  constexpr int NV = S::NV, ie = S::IE, ib = S::IB;
+  const double unl = vl[1 + N], unr = vr[1 + N];
+  const double sl = dmin(unl - cl, unr - cr);
+  const double sr = dmax(unl + cl, unr + cr);
+  if (sl >= 0.0) {
+#pragma unroll
+    for (int k = 0; k < NV; k++) F[k] = fl[k];
+    return;
+  }
+  if (sr <= 0.0) {
+#pragma unroll
+    for (int k = 0; k < NV; k++) F[k] = fr[k];
+    return;
+  }
+  double bbl = vl[ib] * vl[ib], bbr = vr[ib] * vr[ib];
+#pragma unroll
+  for (int d = 1; d < ND; d++) {
+    bbl = bbl + vl[ib + d] * vl[ib + d];
+    bbr = bbr + vr[ib + d] * vr[ib + d];
+  }
+  const double ptl = vl[ie] + 0.5 * bbl, ptr = vr[ie] + 0.5 * bbr;
+  const double rl = vl[0] * (sl - unl);
+  const double rr = vr[0] * (sr - unr);
+  const double sm = ((ptr - ptl) + unl * rl - unr * rr) / (rl - rr);
+  const double ids = 1.0 / (sr - sl);
+  double uh[NV];  // HLL state of density, momenta and field
+#pragma unroll
+  for (int k = 0; k <= ND; k++) uh[k] = ((sr * ur[k] - sl * ul[k]) - (fr[k] - fl[k])) * ids;
+#pragma unroll
+  for (int d = 0; d < ND; d++) uh[ib + d] = ((sr * ur[ib + d] - sl * ul[ib + d]) - (fr[ib + d] - fl[ib + d])) * ids;
+  const bool left = sm >= 0.0;
+  double vk[NV], uk[NV], fk[NV];
+#pragma unroll
+  for (int k = 0; k < NV; k++) {
+    vk[k] = left ? vl[k] : vr[k];
+    uk[k] = left ? ul[k] : ur[k];
+    fk[k] = left ? fl[k] : fr[k];
+  }
+  const double sk = left ? sl : sr;
+  const double rk = left ? rl : rr;
+  const double unk = vk[1 + N], ptk = left ? ptl : ptr;
+  const double inv = 1.0 / (sk - sm);
+  const double coef = rk * inv;
+  const double pts = ptk + rk * (sm - unk);
+  const double bn = vk[ib + N];
+  double vs[ND], bs[ND];
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    if (d == N) {
+      vs[d] = sm;
+      bs[d] = bn;
+    } else if (bn == 0.0) {
+      vs[d] = vk[1 + d];
+      bs[d] = vk[ib + d] * ((sk - unk) * inv);
+    } else {
+      vs[d] = uh[1 + d] / uh[0];
+      bs[d] = uh[ib + d];
+    }
+  }
+  double vbk = vk[1] * vk[ib], vbs = vs[0] * bs[0];
+#pragma unroll
+  for (int d = 1; d < ND; d++) {
+    vbk = vbk + vk[1 + d] * vk[ib + d];
+    vbs = vbs + vs[d] * bs[d];
+  }
+  double us[NV];
+  us[0] = coef;
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    us[1 + d] = coef * vs[d];
+    us[ib + d] = bs[d];
+  }
+  us[ie] = ((sk - unk) * uk[ie] - ptk * unk + pts * sm + bn * (vbk - vbs)) * inv;
+  us[S::IP] = uk[S::IP];
+#pragma unroll
+  for (int k = 0; k < NV; k++) F[k] = fk[k] + sk * (us[k] - uk[k]);
+}
+
 // Approximate Riemann flux normal to N from left/right primitive face states.
 // vl/vr are modified only for MHD (normal field replaced by the GLM value).
 template <int ND, bool MHD, int FLUX, int N>
 __device__ __forceinline__ void riemann(double* vl, double* vr, double* F, const PhysParams& P) {
   using S = Sys<ND, MHD>;
   constexpr int NV = S::NV;
-  if constexpr (FLUX == FLX_HLLC) {
-    static_assert(!MHD, "HLLC is implemented for hydrodynamics only");
+  if constexpr (FLUX == FLX_HLLC && !MHD) {
     hllc_flux<ND, N>(vl, vr, F, P);
     return;
   } else {
@@ -269,6 +356,8 @@ __device__ __forceinline__ void riemann(double* vl, double* vr, double* F, const
       const double cmax = dmax(fabs(unl) + cl, fabs(unr) + cr);
 #pragma unroll
       for (int k = 0; k < NV; k++) F[k] = 0.5 * ((fl[k] + fr[k]) - cmax * (ur[k] - ul[k]));
+    } else if constexpr (FLUX == FLX_HLLC) {
+      hllc_mhd<ND, N>(vl, vr, ul, ur, fl, fr, cl, cr, F);
     } else {
       const double sl = dmin(unl - cl, unr - cr);
       const double sr = dmax(unl + cl, unr + cr);

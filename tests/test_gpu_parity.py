@@ -170,6 +170,15 @@ def test_sod_other_limiters_match_oracle(lim):
     assert np.array_equal(G, R)
 
 
+def test_orszag_tang_hllc_matches_oracle():
+    F = _gpu()
+    f, U = W.orszag_tang(4)
+    f.scheme.flux = W.HLLC
+    R, dts = oracle.run(f, U, steps=20)
+    G, _ = F.run(f, U, dts=dts)
+    assert np.array_equal(G, R)
+
+
 def test_orszag_tang_koren_matches_oracle():
     F = _gpu()
     f, U = W.orszag_tang(4)
@@ -179,12 +188,12 @@ def test_orszag_tang_koren_matches_oracle():
     assert np.array_equal(G, R)
 
 
-@pytest.mark.parametrize("nd", [2, 3])
-def test_mhd_blast_matches_oracle(nd):
+@pytest.mark.parametrize("nd,flux", [(2, W.HLLC), (3, W.HLLC), (2, W.HLL), (3, W.HLL)])
+def test_mhd_blast_matches_oracle(nd, flux):
     """The paper's MHD blast (Sec. 2.4) on a small AMR forest, with the
     Courant ramp: exercises the 2D and 3D MHD stage kernels."""
     F = _gpu()
-    f, U = W.mhd_blast(nd, base=2, max_level=3)
+    f, U = W.mhd_blast(nd, scheme=W.mhd_blast_scheme(nd, base=2, max_level=3, flux=flux))
     R, dts = oracle.run(f, U, steps=6, ramp_steps=10)
     G, gdts = F.run(f, U, steps=6, ramp_steps=10)
     assert gdts == dts

@@ -22,17 +22,17 @@ import oracle
 from paper_2004_03275_amd import workloads as W
 
 
-def _line_mhd(n, cr=0.18):
+def _line_mhd(n, cr=0.18, flux=W.HLL):
     s = W.Scheme(ndim=2, block_nx=(n, 4), base_blocks=(1, 1), max_level=1, xmin=(0.0, 0.0),
-                 xmax=(1.0, 4.0 / n), physics=W.MHD, gamma=5.0 / 3.0, flux=W.HLL, limiter=W.VANLEER, rk_stages=3,
+                 xmax=(1.0, 4.0 / n), physics=W.MHD, gamma=5.0 / 3.0, flux=flux, limiter=W.VANLEER, rk_stages=3,
                  cfl=0.8, bc=W.PERIODIC, glm_cr=cr)
     f = W.uniform_forest(s)
     x, _ = W.cell_centres(f)
     return s, f, x
 
 
-def _alfven(n, direction=+1, amp=1e-3, t_end=0.25):
-    s, f, x = _line_mhd(n)
+def _alfven(n, direction=+1, amp=1e-3, t_end=0.25, flux=W.HLL):
+    s, f, x = _line_mhd(n, flux=flux)
     one = np.ones_like(x)
     dv = amp * np.sin(2 * np.pi * x)
     U = W.state_from_primitive(f, one, [0 * one, dv], one, [one, -direction * dv])
@@ -43,8 +43,9 @@ def _alfven(n, direction=+1, amp=1e-3, t_end=0.25):
     return float(np.mean(np.abs(vy - exact))) / amp
 
 
-def test_alfven_wave_converges_to_the_travelling_solution():
-    errs = [_alfven(n) for n in (32, 64, 128)]
+@pytest.mark.parametrize("flux", [W.HLL, W.HLLC])
+def test_alfven_wave_converges_to_the_travelling_solution(flux):
+    errs = [_alfven(n, flux=flux) for n in (32, 64, 128)]
     # second-order scheme with limiter clipping at extrema: order >= 1.3
     assert errs[2] < 0.02, errs
     assert errs[0] / errs[1] > 2.4 and errs[1] / errs[2] > 2.4, errs
@@ -148,7 +149,8 @@ def test_mhd_blast_point_and_diagonal_symmetry():
     """rho, p radial, v = 0, B uniform along the diagonal: the solution stays
     point symmetric (rho even, v odd, B even under x -> -x) and symmetric
     under x <-> y with the x and y components exchanged."""
-    f, U = W.mhd_blast(2, base=4, max_level=1)
+    s = W.mhd_blast_scheme(2, base=4, max_level=1, flux=W.HLL)
+    f, U = W.mhd_blast(2, scheme=s)
     R, dts = oracle.run(f, U, steps=25, ramp_steps=10)
     assert dts[0] * 10 == pytest.approx(dts[1] * 5, rel=0.5)  # the ramp is on
     G = _global_2d(f, R)
@@ -173,3 +175,71 @@ def test_mhd_blast_point_and_diagonal_symmetry():
 def test_courant_ramp():
     assert [W.courant_ramp(n, 10) for n in range(12)] == [(n + 1) / 10 for n in range(10)] + [1.0, 1.0]
     assert W.courant_ramp(0, 0) == 1.0
+
+
+# ---------------------------------------------------------------------------
+# HLLC for MHD (Li 2005, the flux of the paper's MHD blast)
+# ---------------------------------------------------------------------------
+
+
+def test_mhd_hllc_without_field_is_the_hydrodynamic_hllc():
+    """B = 0, psi = 0: the MHD HLLC flux takes the B_n = 0 branch and must
+    give the hydrodynamic HLLC solution (up to the rounding of the fast
+    speed formula)."""
+    s = W.kh_scheme(2)
+    f, U = W.kh(scheme=s)
+    Re, dts = oracle.run(f, U, steps=20)
+    sm = W.Scheme(ndim=2, block_nx=(16, 16), base_blocks=(2, 2), max_level=1, physics=W.MHD, gamma=1.4,
+                  flux=W.HLLC, limiter=W.VANLEER, rk_stages=3, cfl=0.8, bc=W.PERIODIC)
+    fm = W.Forest(sm, f.level, f.ijk)
+    rho = U[0]
+    u, v = U[1] / rho, U[2] / rho
+    p = 0.4 * (U[3] - 0.5 * (U[1] ** 2 + U[2] ** 2) / rho)
+    z = np.zeros_like(rho)
+    Rm, _ = oracle.run(fm, W.state_from_primitive(fm, rho, [u, v], p, [z, z]), dts=dts)
+    for k in range(4):
+        assert np.abs(Re[k] - Rm[k]).max() <= 1e-12 * np.abs(Re[k]).max(), k
+    assert np.abs(Rm[4:]).max() == 0.0
+
+
+def _contact(flux, steps=20):
+    """A stationary tangential discontinuity in x: density and v_y jump,
+    B = (0, 0.8) tangential, total pressure continuous, B_n = 0."""
+    s = W.Scheme(ndim=2, block_nx=(32, 4), base_blocks=(1, 1), max_level=1, xmin=(0.0, 0.0), xmax=(1.0, 0.125),
+                 physics=W.MHD, gamma=5.0 / 3.0, flux=flux, limiter=W.VANLEER, rk_stages=3, cfl=0.8,
+                 bc=W.PERIODIC)
+    f = W.uniform_forest(s)
+    x, _ = W.cell_centres(f)
+    one = np.ones_like(x)
+    inner = np.abs(x - 0.5) < 0.25
+    rho = np.where(inner, 2.0, 1.0)
+    vy = np.where(inner, 0.5, -0.5)
+    U = W.state_from_primitive(f, rho, [0 * one, vy], one, [0 * one, 0.8 * one])
+    R, _ = oracle.run(f, U, steps=steps)
+    return U, R
+
+
+def test_mhd_hllc_keeps_a_tangential_discontinuity():
+    """The B_n = 0 branch keeps each side's transverse velocity and field: the
+    discontinuity stays exact; HLL (and an HLL-averaged star state) smear it."""
+    U, R = _contact(W.HLLC)
+    assert np.abs(R[0] - U[0]).max() <= 1e-14
+    assert np.abs(R[2] - U[2]).max() <= 1e-14
+    U, R = _contact(W.HLL)
+    assert np.abs(R[0] - U[0]).max() > 1e-3
+    assert np.abs(R[2] - U[2]).max() > 1e-3
+
+
+def test_mhd_blast_with_hllc_keeps_its_symmetries():
+    s = W.mhd_blast_scheme(2, base=4, max_level=1, flux=W.HLLC)
+    f, U = W.mhd_blast(2, scheme=s)
+    R, _ = oracle.run(f, U, steps=25, ramp_steps=10)
+    G = _global_2d(f, R)
+    scale = np.abs(G).reshape(G.shape[0], -1).max(axis=1)
+    P = G[:, ::-1, ::-1]
+    T = np.transpose(G, (0, 2, 1))
+    assert np.all(np.abs(G[0] - P[0]) <= 1e-11 * scale[0])
+    assert np.all(np.abs(G[1] + P[1]) <= 1e-11 * scale[1] + 1e-14)
+    assert np.all(np.abs(G[0] - T[0]) <= 1e-11 * scale[0])
+    assert np.all(np.abs(G[4] - T[5]) <= 1e-11 * scale[4])
+    assert np.abs(G[1]).max() > 0.1
