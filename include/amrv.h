@@ -139,7 +139,10 @@ int amrv_advance(amrv_forest* f, double dt);
  * dt > 0.  Synchronises at the end; AMRV_ENONPHYSICAL if a step met a
  * non-physical state (the steps after it do nothing).  The same arithmetic
  * as amrv_max_dt + amrv_advance, except that the MHD damping factor is
- * evaluated on the device. */
+ * evaluated on the device.  The Courant reduction of the starting state is
+ * computed first unless the previous amrv_advance_cfl (all steps taken) or
+ * amrv_max_dt already left it for the current state; the state must then
+ * not have been changed other than through this API since. */
 int amrv_advance_cfl(amrv_forest* f, int32_t nsteps, double t_end, double* t, int32_t* taken);
 
 /* Refinement flags, one int8 per leaf into host memory.

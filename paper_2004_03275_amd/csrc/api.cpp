@@ -119,6 +119,7 @@ struct amrv_forest {
   float margin = 2.0f;
   std::string tune_report;  // the last autotune's timing table
   std::vector<int32_t> xfer_host;  // regrid sources while their upload is in flight
+  bool fold_valid = false;         // the reduction words hold the Courant fold of U^n
 };
 
 namespace {
@@ -416,6 +417,7 @@ int amrv_set_state(amrv_forest* f, const double* U, int64_t nd, int32_t on_devic
   HIPCHK(hipMemcpyAsync(f->U[0], U, sizeof(double) * nd, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                         f->st));
   if (!on_device) HIPCHK(hipStreamSynchronize(f->st));
+  f->fold_valid = false;
   return AMRV_OK;
 }
 
@@ -435,6 +437,7 @@ int amrv_max_dt(amrv_forest* f, double* dt_out) {
   unsigned long long h[4] = {0, 0, 0, 0};
   HIPCHK(hipMemcpyAsync(h, f->red, sizeof h, hipMemcpyDeviceToHost, f->st));
   HIPCHK(hipStreamSynchronize(f->st));
+  f->fold_valid = true;
   if (h[2]) return fail(AMRV_ENONPHYSICAL, "non-physical state (rho <= 0, p <= 0 or NaN)");
   double smax, cmax;
   std::memcpy(&smax, &h[0], 8);
@@ -454,6 +457,7 @@ int amrv_advance(amrv_forest* f, double dt) {
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(AMRV_EINVAL, "dt must be positive and finite");
   if (f->cfg.physics == AMRV_MHD_GLM && !(f->ch > 0.0)) return fail(AMRV_EINVAL, "MHD needs amrv_max_dt first");
   const double damp = f->cfg.physics == AMRV_MHD_GLM ? std::exp(-(dt * f->ch) / f->cfg.glm_cr) : 1.0;
+  f->fold_valid = false;
   int rc = set_scalars(f, PP_DT, {dt, damp});
   if (rc) return rc;
   if (f->graph_on && !f->prof) {
@@ -471,12 +475,16 @@ int amrv_advance_cfl(amrv_forest* f, int32_t nsteps, double t_end, double* t, in
   if (!f || !t) return fail(AMRV_EINVAL, "null argument");
   if (nsteps < 0) return fail(AMRV_EINVAL, "nsteps must be >= 0");
   if (!std::isfinite(*t) || std::isnan(t_end)) return fail(AMRV_EINVAL, "bad time");
-  // initial fold: the Courant reduction of the current state
-  HIPCHK(launch_reset_u32((unsigned*)f->red, 8, f->st));
+  // initial fold: the Courant reduction of the current state, unless the
+  // last step of the previous call (or amrv_max_dt) left it in place
   HIPCHK(launch_reset_u32(f->cnt + CNT_ERR, 2, f->st));
   int rc = set_scalars(f, PP_T, {*t});
   if (rc) return rc;
-  HIPCHK(launch_cfl(f->geo, f->lc, f->U[0], f->pp, f->red, f->st));
+  if (!f->fold_valid) {
+    HIPCHK(launch_reset_u32((unsigned*)f->red, 8, f->st));
+    HIPCHK(launch_cfl(f->geo, f->lc, f->U[0], f->pp, f->red, f->st));
+  }
+  f->fold_valid = false;
   const bool graph = f->st != nullptr && f->sched != AMRV_SCHED_PER_BLOCK && !f->prof;
   if (graph && (!f->dexec || f->dt_tend != t_end)) {
     if (f->dexec) (void)hipGraphExecDestroy(f->dexec);
@@ -511,6 +519,8 @@ int amrv_advance_cfl(amrv_forest* f, int32_t nsteps, double t_end, double* t, in
   HIPCHK(hipStreamSynchronize(f->st));
   *t = th;
   if (taken) *taken = (int32_t)cw[1];
+  // every step folded the Courant reduction of its result: it stays valid
+  f->fold_valid = (int64_t)cw[1] == (int64_t)nsteps && !cw[0];
   // the GLM speed of the latest fold (the next amrv_advance needs it)
   if (f->cfg.physics == AMRV_MHD_GLM) {
     double ch = 0.0;
@@ -663,6 +673,7 @@ int amrv_regrid_transfer(amrv_forest* from, amrv_forest* to) {
   HIPCHK(hipMemcpyAsync(xf, to->xfer_host.data(), sizeof(int32_t) * to->xfer_host.size(), hipMemcpyHostToDevice,
                         to->st));
   HIPCHK(launch_transfer(from->geo, from->U[0], to->geo, to->U[0], xf, to->lc, to->st));
+  to->fold_valid = false;
   HIPCHK(hipStreamSynchronize(to->st));
   to->ch = from->ch;
   return AMRV_OK;

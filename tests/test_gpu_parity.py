@@ -287,6 +287,35 @@ def test_device_timed_steps_match_oracle():
     assert e.max() <= TOL
 
 
+def test_device_timed_calls_reuse_the_fold_only_while_valid():
+    """Consecutive amrv_advance_cfl calls reuse the Courant reduction folded
+    by the previous call's last step; set_state or a host-timed step in
+    between forces a fresh one."""
+    F = _gpu()
+    f, U = W.kh(4)
+    R, _ = oracle.run(f, U, steps=6)
+    g = F.GpuForest(f)
+    g.set_state(U)
+    t, n = g.advance_cfl(3, float("inf"), 0.0)
+    t, n2 = g.advance_cfl(3, float("inf"), t)
+    assert n == n2 == 3 and np.array_equal(g.get_state(), R)
+    # a new state: the stale fold must not be used
+    g.set_state(U)
+    g.advance_cfl(2, float("inf"), 0.0)
+    g.set_state(U)
+    t, _ = g.advance_cfl(6, float("inf"), 0.0)
+    assert np.array_equal(g.get_state(), R)
+    # a host-timed step in between
+    R2, dts = oracle.run(f, U, steps=5)
+    g.set_state(U)
+    t, _ = g.advance_cfl(2, float("inf"), 0.0)
+    dt = g.max_dt()
+    g.advance(dt)
+    t, _ = g.advance_cfl(2, float("inf"), t + dt)
+    assert np.array_equal(g.get_state(), R2)
+    g.close()
+
+
 def test_device_timed_run_reports_nonphysical_state():
     """A non-physical state met during a device-timed run is reported, with
     every schedule (the per-step queue reset must not clear the flag)."""
