@@ -96,7 +96,7 @@ def main():
     ap.add_argument("--tune-reps", type=int, default=5)
     ap.add_argument("--host-dt", action="store_true",
                     help="time steps as amrv_max_dt + amrv_advance (host-side dt) instead of amrv_advance_cfl")
-    ap.add_argument("--limiter", default=None, choices=["minmod", "vanleer", "mc", "koren"],
+    ap.add_argument("--limiter", default=None, choices=["minmod", "vanleer", "mc", "koren", "cada"],
                     help="override the workload's limiter")
     ap.add_argument("--adaptive-steps", type=int, default=None,
                     help="also run this many steps from the initial state with regridding (default 20 on the "
@@ -126,7 +126,8 @@ def main():
     desc, f, U0 = make_workload(args.workload)
     s = f.scheme
     if args.limiter:
-        s.limiter = {"minmod": W.MINMOD, "vanleer": W.VANLEER, "mc": W.MC, "koren": W.KOREN}[args.limiter]
+        s.limiter = {"minmod": W.MINMOD, "vanleer": W.VANLEER, "mc": W.MC, "koren": W.KOREN,
+                      "cada": W.CADA}[args.limiter]
     cells = f.n * s.cells_per_block
     log(f"workload {desc}: {f.n} leaves {f.level_counts()}, {cells} cells")
 
@@ -385,7 +386,7 @@ def main():
             "block": list(s.block_nx[: s.ndim]),
             "nvar": s.nvar,
             "flux": ["tvdlf", "hll", "hllc"][s.flux],
-            "limiter": ["minmod", "vanleer", "mc", "koren"][s.limiter],
+            "limiter": ["minmod", "vanleer", "mc", "koren", "cada"][s.limiter],
             "rk_stages": s.rk_stages,
             "gamma": s.gamma,
             "cfl": s.cfl,

@@ -52,6 +52,8 @@ extern "C" {
 #define AMRV_VANLEER 1
 #define AMRV_MC 2 /* monotonized central ('woodward', Sec. 2.3.1) */
 #define AMRV_KOREN 3 /* Koren (Sec. 2.2, 2.3.2); runs the split stage-kernel variant */
+#define AMRV_CADA 4  /* Cada's third order (Sec. 2.4 blast runs; LimO3 of Cada and Torrilhon 2009,
+                        without its smoothness switch); split variant */
 #define AMRV_BC_PERIODIC 0
 #define AMRV_BC_ZERO_GRADIENT 1
 
@@ -79,7 +81,7 @@ typedef struct {
   int32_t max_level;       /* 1 = pure domain decomposition */
   int32_t physics;         /* AMRV_EULER or AMRV_MHD_GLM */
   int32_t flux;            /* AMRV_TVDLF, AMRV_HLL, AMRV_HLLC (HLLC: Euler only) */
-  int32_t limiter;         /* AMRV_MINMOD, AMRV_VANLEER, AMRV_MC or AMRV_KOREN */
+  int32_t limiter;         /* AMRV_MINMOD, AMRV_VANLEER, AMRV_MC, AMRV_KOREN or AMRV_CADA */
   int32_t rk_stages;       /* 2 (SSP-RK2) or 3 (SSP-RK3) */
   int32_t bc[3][2];        /* AMRV_BC_*, same value on both sides of a dimension */
   int32_t pad_;

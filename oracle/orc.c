@@ -41,7 +41,7 @@
 enum { NB_SAME = 0, NB_COARSER = 1, NB_FINER = 2, NB_BND = 3 };
 enum { PHYS_EULER = 0, PHYS_MHD = 1 };
 enum { FLUX_TVDLF = 0, FLUX_HLL = 1, FLUX_HLLC = 2 };
-enum { LIM_MINMOD = 0, LIM_VANLEER = 1, LIM_MC = 2, LIM_KOREN = 3 };
+enum { LIM_MINMOD = 0, LIM_VANLEER = 1, LIM_MC = 2, LIM_KOREN = 3, LIM_CADA = 4 };
 
 static __thread char g_err[512];
 
@@ -428,8 +428,33 @@ static void riemann(const orc_forest* f, const double* vl_in, const double* vr_i
  * (a+b)/2 and 2b, Koren's limiter (Sec. 2.2, 2.3.2) the smallest of 2a, the
  * third-order (kappa = 1/3) combination (a+2b)/3 and 2b.  All vanish at
  * extrema (a b <= 0).  The first three are symmetric in a and b; Koren's is
- * not, so a cell's two faces get different slopes. */
+ * not, so a cell's two faces get different slopes.
+ *
+ * Cada's third-order limiter (Sec. 2.4 MHD blast runs; Cada and Torrilhon
+ * 2009, the limited function 'LimO3'): with theta = a/b the slope is
+ * b H(theta), H(theta) = max(0, min(p3, max(-theta/2, min(2 theta, p3,
+ * 1.6)))) and p3 = (2 + theta)/3 the unlimited third-order value.  It is
+ * not zero at extrema (-2 < theta < 0) and not symmetric.  Written here
+ * without the division: for b > 0 every candidate of H times b is a
+ * candidate in a and b (p3 b = (a + 2b)/3), and b < 0 follows from
+ * s(-a, -b) = -s(a, b); b = 0 gives 0 (H is bounded).  The smoothness switch
+ * of that paper (unlimited p3 where the differences are small against a
+ * radius times the cell size) is not applied: the radius -> 0 case. */
+static double smaller(double x, double y) { return y < x ? y : x; }
+static double larger(double x, double y) { return y > x ? y : x; }
+
+static double cada(double a, double b) {
+  if (b == 0.0) return 0.0;
+  const double sg = b > 0.0 ? 1.0 : -1.0;
+  const double ap = sg * a, bp = sg * b;
+  const double p3 = (ap + 2.0 * bp) / 3.0;
+  const double in = smaller(smaller(2.0 * ap, p3), 1.6 * bp);
+  const double r = larger(0.0, smaller(p3, larger(-0.5 * ap, in)));
+  return sg * r;
+}
+
 static double limit_ab(int kind, double a, double b) {
+  if (kind == LIM_CADA) return cada(a, b);
   if (a * b <= 0.0) return 0.0;
   if (kind == LIM_MINMOD) return fabs(a) < fabs(b) ? a : b;
   if (kind == LIM_MC || kind == LIM_KOREN) {
@@ -537,7 +562,7 @@ int orc_forest_create(const orc_config* cfg, int64_t n, const int32_t* lev, cons
   if (c->max_level < 1 || c->max_level > 12) return fail(ORC_EINVAL, "max_level out of range");
   if (c->physics != PHYS_EULER && c->physics != PHYS_MHD) return fail(ORC_EINVAL, "bad physics");
   if (c->flux < 0 || c->flux > 2) return fail(ORC_EINVAL, "bad flux");
-  if (c->limiter < 0 || c->limiter > 3) return fail(ORC_EINVAL, "bad limiter");
+  if (c->limiter < 0 || c->limiter > 4) return fail(ORC_EINVAL, "bad limiter");
   if (c->rk_stages != 2 && c->rk_stages != 3) return fail(ORC_EINVAL, "rk_stages must be 2 or 3");
   if (!(c->gamma > 1.0) || !(c->cfl > 0.0)) return fail(ORC_EINVAL, "gamma must be > 1, cfl > 0");
   for (int d = 0; d < c->ndim; d++) {

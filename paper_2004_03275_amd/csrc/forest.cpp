@@ -47,7 +47,8 @@ int build_tables(const amrv_config& c, int64_t n, const int32_t* lev, const int3
   if (c.max_level < 1 || c.max_level > MAXLEV - 1) return fail(AMRV_EINVAL, "max_level out of range");
   if (c.physics != AMRV_EULER && c.physics != AMRV_MHD_GLM) return fail(AMRV_EINVAL, "unknown physics");
   if (c.flux < AMRV_TVDLF || c.flux > AMRV_HLLC) return fail(AMRV_EINVAL, "unknown flux");
-  if (c.limiter != AMRV_MINMOD && c.limiter != AMRV_VANLEER && c.limiter != AMRV_MC && c.limiter != AMRV_KOREN)
+  if (c.limiter != AMRV_MINMOD && c.limiter != AMRV_VANLEER && c.limiter != AMRV_MC && c.limiter != AMRV_KOREN &&
+      c.limiter != AMRV_CADA)
     return fail(AMRV_EINVAL, "unknown limiter");
   if (c.rk_stages != 2 && c.rk_stages != 3) return fail(AMRV_EINVAL, "rk_stages must be 2 or 3");
   if (!(c.gamma > 1.0) || !(c.cfl > 0.0)) return fail(AMRV_EINVAL, "gamma must exceed 1 and cfl be positive");

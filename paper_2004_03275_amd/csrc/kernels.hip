@@ -1106,7 +1106,7 @@ template <int V>
 using IC = std::integral_constant<int, V>;
 
 // call fn(IC<ndim>, IC<mhd>, IC<flux>, IC<limiter>) for the runtime
-// configuration; MHD has no HLLC instance
+// configuration
 template <class Fn>
 static void dispatch(const LaunchCfg& c, Fn&& fn) {
   auto lim = [&](auto nd, auto mhd, auto fl) {
@@ -1116,6 +1116,8 @@ static void dispatch(const LaunchCfg& c, Fn&& fn) {
       fn(nd, mhd, fl, IC<LIM_MC>{});
     else if (c.lim == LIM_KOREN)
       fn(nd, mhd, fl, IC<LIM_KOREN>{});
+    else if (c.lim == LIM_CADA)
+      fn(nd, mhd, fl, IC<LIM_CADA>{});
     else
       fn(nd, mhd, fl, IC<LIM_VANLEER>{});
   };

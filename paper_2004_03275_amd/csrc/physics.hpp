@@ -13,12 +13,12 @@
 namespace amrv {
 
 enum { FLX_TVDLF = 0, FLX_HLL = 1, FLX_HLLC = 2 };
-enum { LIM_MINMOD = 0, LIM_VANLEER = 1, LIM_MC = 2, LIM_KOREN = 3 };
+enum { LIM_MINMOD = 0, LIM_VANLEER = 1, LIM_MC = 2, LIM_KOREN = 3, LIM_CADA = 4 };
 
 // limiters whose slope toward a face depends on which face (not symmetric in
 // the two differences): a cell keeps two slopes
 template <int LIM>
-constexpr bool lim_asym() { return LIM == LIM_KOREN; }
+constexpr bool lim_asym() { return LIM == LIM_KOREN || LIM == LIM_CADA; }
 
 struct PhysParams {
   double gamma;
@@ -168,9 +168,26 @@ __device__ __forceinline__ double wave_speed_dir(const double* v, int n, const P
 // and b toward it: minmod (smaller magnitude), van Leer (harmonic mean
 // 2ab/(a+b)), monotonized central (smallest magnitude of 2a, (a+b)/2, 2b),
 // Koren (smallest of 2a, (a+2b)/3, 2b); zero at extrema.  All but Koren are
-// symmetric in a and b, bit for bit.
+// symmetric in a and b, bit for bit.  Cada's third-order limiter (LimO3 of
+// Cada and Torrilhon 2009, without its smoothness switch) is b H(a/b) with
+// H(t) = max(0, min(p3, max(-t/2, min(2t, p3, 1.6)))), p3 = (2 + t)/3: for
+// b > 0 the candidates scale by b exactly, b < 0 is the odd mirror, b = 0
+// gives 0; it keeps a slope at extrema (-2 < a/b < 0).
 template <int LIM>
 __device__ __forceinline__ double limiter(double a, double b) {
+  if constexpr (LIM == LIM_CADA) {
+    const double sg = b > 0.0 ? 1.0 : -1.0;
+    const double ap = sg * a, bp = sg * b;
+    const double p3 = (ap + 2.0 * bp) / 3.0;
+    double in = 2.0 * ap;
+    in = p3 < in ? p3 : in;
+    in = 1.6 * bp < in ? 1.6 * bp : in;
+    double m = -0.5 * ap;
+    m = in > m ? in : m;
+    m = m < p3 ? m : p3;
+    m = m > 0.0 ? m : 0.0;
+    return b == 0.0 ? 0.0 : sg * m;
+  }
   if (a * b <= 0.0) return 0.0;
   if constexpr (LIM == LIM_MINMOD) {
     return fabs(a) < fabs(b) ? a : b;

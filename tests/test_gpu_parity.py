@@ -102,7 +102,8 @@ def test_sod_full_run_matches_oracle():
 
 
 @pytest.mark.parametrize("flux,lim", [(W.HLLC, W.VANLEER), (W.HLL, W.MINMOD), (W.TVDLF, W.VANLEER), (W.HLLC, W.MC),
-                                      (W.TVDLF, W.MC), (W.HLLC, W.KOREN), (W.HLL, W.KOREN)])
+                                      (W.TVDLF, W.MC), (W.HLLC, W.KOREN), (W.HLL, W.KOREN),
+                                      (W.HLLC, W.CADA), (W.TVDLF, W.CADA)])
 def test_kh_small_matches_oracle(flux, lim):
     F = _gpu()
     s = W.kh_scheme(4)
@@ -148,7 +149,7 @@ def test_blast_small_amr_matches_oracle():
     assert e.max() <= TOL
 
 
-@pytest.mark.parametrize("lim", [W.MC, W.MINMOD, W.KOREN])
+@pytest.mark.parametrize("lim", [W.MC, W.MINMOD, W.KOREN, W.CADA])
 def test_blast_small_other_limiters_match_oracle(lim):
     F = _gpu()
     f, U = _blast_small()
@@ -159,7 +160,7 @@ def test_blast_small_other_limiters_match_oracle(lim):
     assert np.array_equal(G, R)
 
 
-@pytest.mark.parametrize("lim", [W.MC, W.KOREN])
+@pytest.mark.parametrize("lim", [W.MC, W.KOREN, W.CADA])
 def test_sod_other_limiters_match_oracle(lim):
     F = _gpu()
     f, U = W.sod(1024, nblocks=8)

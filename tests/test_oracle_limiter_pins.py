@@ -1,38 +1,48 @@
 """Pins of the oracle's slope limiters: minmod, van Leer, the monotonized
-central ('woodward') limiter of the paper's Gresho vortex runs (Sec. 2.3.1)
-and Koren's limiter of its shallow-water and Karman runs (Sec. 2.2, 2.3.2).
+central ('woodward') limiter of the paper's Gresho vortex runs (Sec. 2.3.1),
+Koren's limiter of its shallow-water and Karman runs (Sec. 2.2, 2.3.2) and
+Cada's third-order limiter of its MHD blast runs (Sec. 2.4; the LimO3
+function of Cada and Torrilhon 2009).
 A limiter here takes the difference a on the side of the cell away from the
 face and b toward it.  Values for hand-worked pairs, the symmetry and sign
 properties of a TVD limiter (Koren's is deliberately asymmetric), the
 central branch of the monotonized central limiter, the third-order branch
 of Koren's, convergence of a smooth 1D entropy wave in the full scheme, and
-mirror symmetry of a shock tube with the asymmetric limiter."""
+mirror symmetry of a shock tube with the asymmetric limiters, the published
+ratio form of Cada's limiter, and exact face values of the third-order
+limiters on a quadratic profile."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_2004_03275_amd import workloads as W
 
-MM, VL, MC, KO = W.MINMOD, W.VANLEER, W.MC, W.KOREN
+MM, VL, MC, KO, CA = W.MINMOD, W.VANLEER, W.MC, W.KOREN, W.CADA
 
 # (a, b): difference away from and toward the face; expected slopes worked
 # by hand.  minmod: smaller magnitude; van Leer: 2ab/(a+b); MC: min(|2a|,
-# |a+b|/2, |2b|); Koren: min(|2a|, |a+2b|/3, |2b|), all with the common sign
+# |a+b|/2, |2b|); Koren: min(|2a|, |a+2b|/3, |2b|), all with the common sign;
+# Cada (b > 0): max(0, min(p3, max(-a/2, min(2a, p3, 1.6 b)))), p3 = (a+2b)/3
 TABLE = [
-    ((1.0, 3.0), {MM: 1.0, VL: 1.5, MC: 2.0, KO: 2.0}),
-    ((3.0, 1.0), {MM: 1.0, VL: 1.5, MC: 2.0, KO: 5.0 / 3.0}),
-    ((4.0, 5.0), {MM: 4.0, VL: 40.0 / 9.0, MC: 4.5, KO: 14.0 / 3.0}),
-    ((1.0, 10.0), {MM: 1.0, VL: 20.0 / 11.0, MC: 2.0, KO: 2.0}),
-    ((2.0, 3.0), {KO: 8.0 / 3.0}),
-    ((3.0, 2.0), {KO: 7.0 / 3.0}),
-    ((1.0, 4.0), {KO: 2.0}),
-    ((4.0, 1.0), {KO: 2.0}),
-    ((2.0, 2.0), {MM: 2.0, VL: 2.0, MC: 2.0, KO: 2.0}),
-    ((-1.0, -3.0), {MM: -1.0, VL: -1.5, MC: -2.0, KO: -2.0}),
-    ((-6.0, -2.0), {MM: -2.0, VL: -3.0, MC: -4.0, KO: -10.0 / 3.0}),
-    ((1.0, -1.0), {MM: 0.0, VL: 0.0, MC: 0.0, KO: 0.0}),
-    ((0.0, 5.0), {MM: 0.0, VL: 0.0, MC: 0.0, KO: 0.0}),
-    ((5.0, 0.0), {MM: 0.0, VL: 0.0, MC: 0.0, KO: 0.0}),
+    ((1.0, 3.0), {MM: 1.0, VL: 1.5, MC: 2.0, KO: 2.0, CA: 2.0}),
+    ((3.0, 1.0), {MM: 1.0, VL: 1.5, MC: 2.0, KO: 5.0 / 3.0, CA: 1.6}),
+    ((4.0, 5.0), {MM: 4.0, VL: 40.0 / 9.0, MC: 4.5, KO: 14.0 / 3.0, CA: 14.0 / 3.0}),
+    ((1.0, 10.0), {MM: 1.0, VL: 20.0 / 11.0, MC: 2.0, KO: 2.0, CA: 2.0}),
+    ((2.0, 3.0), {KO: 8.0 / 3.0, CA: 8.0 / 3.0}),
+    ((3.0, 2.0), {KO: 7.0 / 3.0, CA: 7.0 / 3.0}),
+    ((1.0, 4.0), {KO: 2.0, CA: 2.0}),
+    ((4.0, 1.0), {KO: 2.0, CA: 1.6}),
+    ((2.0, 2.0), {MM: 2.0, VL: 2.0, MC: 2.0, KO: 2.0, CA: 2.0}),
+    ((-1.0, -3.0), {MM: -1.0, VL: -1.5, MC: -2.0, KO: -2.0, CA: -2.0}),
+    ((-6.0, -2.0), {MM: -2.0, VL: -3.0, MC: -4.0, KO: -10.0 / 3.0, CA: -3.2}),
+    ((1.0, -1.0), {MM: 0.0, VL: 0.0, MC: 0.0, KO: 0.0, CA: -1.0 / 3.0}),
+    ((-1.0, 1.0), {CA: 1.0 / 3.0}),
+    ((-0.5, 1.0), {CA: 0.25}),
+    ((-1.5, 1.0), {CA: 1.0 / 6.0}),
+    ((-2.0, 1.0), {CA: 0.0}),
+    ((-3.0, 1.0), {CA: 0.0}),
+    ((0.0, 5.0), {MM: 0.0, VL: 0.0, MC: 0.0, KO: 0.0, CA: 0.0}),
+    ((5.0, 0.0), {MM: 0.0, VL: 0.0, MC: 0.0, KO: 0.0, CA: 0.0}),
 ]
 
 
@@ -76,6 +86,59 @@ def test_limiter_properties():
     assert oracle.limiter_value(KO, 5.0, 1.0) == 2.0
 
 
+def _cada_ratio_form(a, b):
+    """The published form: b H(theta), theta = a/b."""
+    t = a / b
+    p3 = (2.0 + t) / 3.0
+    return b * max(0.0, min(p3, max(-0.5 * t, min(2.0 * t, p3, 1.6))))
+
+
+def test_cada_properties():
+    rng = np.random.default_rng(5)
+    a = rng.normal(size=6000) * np.exp(rng.uniform(-6, 6, 6000))
+    b = rng.normal(size=6000) * np.exp(rng.uniform(-6, 6, 6000))
+    n_extremum = 0
+    for x, y in zip(a, b):
+        p = oracle.limiter_value(CA, x, y)
+        assert -p == oracle.limiter_value(CA, -x, -y)                 # odd, bit for bit
+        assert p == pytest.approx(_cada_ratio_form(x, y), rel=4e-16, abs=4e-16 * abs(y))
+        assert p * y >= 0.0 and abs(p) <= 1.6 * abs(y)                # 0 <= H <= 1.6
+        t = x / y
+        if -2.0 <= t <= -0.8 or 0.4 <= t <= 2.8:                      # third-order branch
+            assert p == (x + 2.0 * y) / 3.0
+        elif -0.8 < t < 0.0:
+            assert p == -0.5 * x
+        elif t > 2.8:
+            assert p == 1.6 * y
+        elif 0.0 <= t < 0.4:
+            assert p == 2.0 * x
+        else:
+            assert p == 0.0
+        n_extremum += (x * y < 0) and p != 0.0
+    assert n_extremum > 500          # keeps a slope at extrema, unlike the TVD limiters
+    assert oracle.limiter_value(CA, 1.0, 3.0) != oracle.limiter_value(CA, 3.0, 1.0)
+
+
+@pytest.mark.parametrize("lim", [KO, CA])
+def test_third_order_limiters_exact_on_a_quadratic(lim):
+    """Cell averages of x^2 on cells [ih, (i+1)h], i >= 1: the two
+    differences are 2i h^2 and (2i+2) h^2, their ratio lies in the
+    third-order branch, and the reconstructed face values are the exact
+    point values i^2 h^2 and (i+1)^2 h^2."""
+    h = 0.01
+    avg = lambda i: h * h * (i * i + i + 1.0 / 3.0)
+    for i in range(1, 60):
+        dm, dp = avg(i) - avg(i - 1), avg(i + 1) - avg(i)
+        hi = avg(i) + 0.5 * oracle.limiter_value(lim, dm, dp)
+        lo = avg(i) - 0.5 * oracle.limiter_value(lim, dp, dm)
+        assert hi == pytest.approx((i + 1) ** 2 * h * h, rel=1e-12)
+        assert lo == pytest.approx(i * i * h * h, rel=1e-12)
+    # a TVD second-order limiter is not exact there
+    i = 5
+    dm, dp = avg(i) - avg(i - 1), avg(i + 1) - avg(i)
+    assert avg(i) + 0.5 * oracle.limiter_value(VL, dm, dp) != pytest.approx((i + 1) ** 2 * h * h, rel=1e-6)
+
+
 def _entropy_wave(n, lim, t_end=0.25):
     """rho = 1 + 0.2 sin(2 pi x), u = 1, p = 1 on a periodic [0, 1]: the exact
     solution is the profile shifted by t.  L1 error of rho at t_end."""
@@ -93,7 +156,7 @@ def _entropy_wave(n, lim, t_end=0.25):
     return float(np.abs(R[0] - exact).mean())
 
 
-@pytest.mark.parametrize("lim", [VL, MC, KO])
+@pytest.mark.parametrize("lim", [VL, MC, KO, CA])
 def test_second_order_on_a_smooth_wave(lim):
     e = [_entropy_wave(n, lim) for n in (64, 128, 256)]
     orders = [np.log2(e[i] / e[i + 1]) for i in range(2)]
@@ -108,13 +171,21 @@ def test_koren_sharper_than_van_leer():
     assert _entropy_wave(128, KO) < _entropy_wave(128, VL)
 
 
-def test_mirrored_shock_tube_with_koren():
+def test_third_order_limiters_beat_second_order_on_a_smooth_wave():
+    e = {lim: [_entropy_wave(n, lim) for n in (64, 128, 256)] for lim in (KO, CA)}
+    for lim in (KO, CA):
+        assert np.log2(e[lim][1] / e[lim][2]) > 2.15, (lim, e[lim])
+        assert e[lim][2] < 0.4 * _entropy_wave(256, VL)
+
+
+@pytest.mark.parametrize("lim", [KO, CA])
+def test_mirrored_shock_tube_with_asymmetric_limiters(lim):
     """Sod tube and its mirror image (x -> 1 - x, u -> -u): with an
     asymmetric limiter the two faces of a cell take different slopes, and
     only the face-correct assignment keeps the mirror symmetry."""
     def run(mirror):
         f, U = W.sod(512, nblocks=8)
-        f.scheme.limiter = KO
+        f.scheme.limiter = lim
         if mirror:
             U = U[:, ::-1, ::-1].copy()
             U[1] = -U[1]
@@ -124,4 +195,4 @@ def test_mirrored_shock_tube_with_koren():
     Bm = B[:, ::-1, ::-1].copy()
     Bm[1] = -Bm[1]
     assert np.abs(A - Bm).max() <= 1e-12 * np.abs(A).max()
-    assert oracle.limiter_value(KO, 1.0, 3.0) != oracle.limiter_value(KO, 3.0, 1.0)
+    assert oracle.limiter_value(lim, 1.0, 3.0) != oracle.limiter_value(lim, 3.0, 1.0)
