@@ -74,6 +74,9 @@ def make_workload(name: str):
     elif name == "mhdblast3d":
         f, U = W.mhd_blast(3, base=4, max_level=3)
         desc = "3d_amr_mhd_blast"
+    elif name == "dambreak2d":
+        f, U = W.dam_break()
+        desc = "2d_amr_shallow_water_dam_break"
     else:
         raise SystemExit(f"unknown workload {name}")
     return desc, f, U
@@ -84,7 +87,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="blast", choices=["blast", "kh", "ot", "sod", "mhdblast2d", "mhdblast3d"])
+    ap.add_argument("--workload", default="blast", choices=["blast", "kh", "ot", "sod", "mhdblast2d", "mhdblast3d",
+                                                             "dambreak2d"])
     ap.add_argument("--flag-every", type=int, default=10)
     ap.add_argument("--per-block-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -385,6 +389,7 @@ def main():
             "cells": cells,
             "block": list(s.block_nx[: s.ndim]),
             "nvar": s.nvar,
+            "physics": ["euler", "mhd_glm", "polytrope"][s.physics],
             "flux": ["tvdlf", "hll", "hllc"][s.flux],
             "limiter": ["minmod", "vanleer", "mc", "koren", "cada"][s.limiter],
             "rk_stages": s.rk_stages,

@@ -45,6 +45,10 @@ extern "C" {
 
 #define AMRV_EULER 0
 #define AMRV_MHD_GLM 1
+/* polytrope without energy equation (Sec. 2.2): state (rho, m), p = c_ad rho^gamma,
+   c^2 = gamma c_ad rho^(gamma-1); the shallow water equations for rho = h,
+   c_ad = 1/2, gamma = 2.  TVDLF or HLL. */
+#define AMRV_POLYTROPE 2
 #define AMRV_TVDLF 0
 #define AMRV_HLL 1
 #define AMRV_HLLC 2
@@ -72,15 +76,15 @@ typedef struct amrv_forest amrv_forest;
 /* Problem description (par-file keys of Sec. 1.3: block size, base domain
  * size in blocks, refine_max_level, xprobmin/xprobmax; Courant number of
  * Sec. 2.1; scheme choice of Sec. 1.3; Loehner tolerances of Sec. 1.3).
- * Field order is part of the ABI: 20 int32 followed by 14 double. */
+ * Field order is part of the ABI: 20 int32 followed by 15 double. */
 typedef struct {
   int32_t ndim;            /* 1, 2 or 3 */
   int32_t block_nx[3];     /* cells per block; 1D: any even nx >= 4; 2D/3D: 16 */
   int32_t nghost;          /* must be 2 */
   int32_t base_blocks[3];  /* level-1 blocks per dimension */
   int32_t max_level;       /* 1 = pure domain decomposition */
-  int32_t physics;         /* AMRV_EULER or AMRV_MHD_GLM */
-  int32_t flux;            /* AMRV_TVDLF, AMRV_HLL, AMRV_HLLC (HLLC: Euler only) */
+  int32_t physics;         /* AMRV_EULER, AMRV_MHD_GLM or AMRV_POLYTROPE */
+  int32_t flux;            /* AMRV_TVDLF, AMRV_HLL, AMRV_HLLC (HLLC: not the polytrope) */
   int32_t limiter;         /* AMRV_MINMOD, AMRV_VANLEER, AMRV_MC, AMRV_KOREN or AMRV_CADA */
   int32_t rk_stages;       /* 2 (SSP-RK2) or 3 (SSP-RK3) */
   int32_t bc[3][2];        /* AMRV_BC_*, same value on both sides of a dimension */
@@ -92,6 +96,7 @@ typedef struct {
   double lohner_eps;           /* noise filter of the estimator */
   double lohner_w_rho, lohner_w_p;
   double glm_cr;               /* GLM damping length c_r */
+  double cad;                  /* c_ad of the polytrope (> 0; read only for AMRV_POLYTROPE) */
 } amrv_config;
 
 /* Device bytes the forest needs for this leaf list (three state copies,

@@ -40,6 +40,7 @@ class _Config(ctypes.Structure):
         ("lohner_w_rho", ctypes.c_double),
         ("lohner_w_p", ctypes.c_double),
         ("glm_cr", ctypes.c_double),
+        ("cad", ctypes.c_double),
     ]
 
 
@@ -110,6 +111,7 @@ def make_config(s) -> _Config:
     c.lohner_w_rho = s.lohner_w_rho
     c.lohner_w_p = s.lohner_w_p
     c.glm_cr = s.glm_cr
+    c.cad = s.cad
     return c
 
 

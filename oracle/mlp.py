@@ -59,8 +59,11 @@ def bf16(x: np.ndarray) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 
-def _pressure(U: np.ndarray, ndim: int, gamma: float, mhd: bool) -> np.ndarray:
+def _pressure(U: np.ndarray, ndim: int, gamma: float, mhd: bool, cad=None) -> np.ndarray:
     rho = U[0]
+    if cad is not None:  # polytrope: c_ad rho^gamma (rho^1, rho^2 exact)
+        e = rho if gamma == 1.0 else rho * rho if gamma == 2.0 else np.power(rho, gamma)
+        return cad * e
     inv = 1.0 / rho
     mm = U[1] * U[1]
     for d in range(1, ndim):
@@ -97,10 +100,11 @@ def _pool(q: np.ndarray, ndim: int) -> np.ndarray:
     return out
 
 
-def leaf_features(U_leaf: np.ndarray, ndim: int, gamma: float, mhd: bool = False) -> np.ndarray:
-    """bfloat16 bit patterns [128] of one leaf's conserved state [nvar, (nz,) ny, nx]."""
+def leaf_features(U_leaf: np.ndarray, ndim: int, gamma: float, mhd: bool = False, cad=None) -> np.ndarray:
+    """bfloat16 bit patterns [128] of one leaf's conserved state [nvar, (nz,) ny, nx]
+    (``cad`` given: the polytrope's state)."""
     rho = U_leaf[0]
-    p = _pressure(U_leaf, ndim, gamma, mhd)
+    p = _pressure(U_leaf, ndim, gamma, mhd, cad)
     feats = np.empty(NIN, dtype=np.float32)
     for v, q in enumerate((rho, p)):
         means = _pool(q, ndim)
@@ -113,10 +117,10 @@ def leaf_features(U_leaf: np.ndarray, ndim: int, gamma: float, mhd: bool = False
     return bf16_bits(feats)
 
 
-def features(U: np.ndarray, ndim: int, gamma: float, mhd: bool = False, leaves=None) -> np.ndarray:
+def features(U: np.ndarray, ndim: int, gamma: float, mhd: bool = False, leaves=None, cad=None) -> np.ndarray:
     """[n, 128] bfloat16 bit patterns for the leaves of a state [nvar, n, ...]."""
     idx = range(U.shape[1]) if leaves is None else leaves
-    return np.stack([leaf_features(U[:, b], ndim, gamma, mhd) for b in idx])
+    return np.stack([leaf_features(U[:, b], ndim, gamma, mhd, cad) for b in idx])
 
 
 # ---------------------------------------------------------------------------

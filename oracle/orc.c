@@ -39,7 +39,7 @@
 #define NVMAX 9
 
 enum { NB_SAME = 0, NB_COARSER = 1, NB_FINER = 2, NB_BND = 3 };
-enum { PHYS_EULER = 0, PHYS_MHD = 1 };
+enum { PHYS_EULER = 0, PHYS_MHD = 1, PHYS_POLY = 2 };
 enum { FLUX_TVDLF = 0, FLUX_HLL = 1, FLUX_HLLC = 2 };
 enum { LIM_MINMOD = 0, LIM_VANLEER = 1, LIM_MC = 2, LIM_KOREN = 3, LIM_CADA = 4 };
 
@@ -73,7 +73,7 @@ int orc_get_threads(void) {
 
 struct orc_forest {
   orc_config c;
-  int nd, nvar, ng, mhd;
+  int nd, nvar, ng, mhd, poly;
   int64_t n;
   int32_t* lev;
   int32_t* ijk;
@@ -165,7 +165,15 @@ static int iE(const orc_forest* f) { return 1 + f->nd; }
 static int iB(const orc_forest* f) { return 2 + f->nd; }
 static int iPsi(const orc_forest* f) { return 2 + 2 * f->nd; }
 
-/* phys_to_primitive: v = m / rho (via 1/rho), p = (gamma-1)(E - m.m/(2 rho) [- B.B/2]) */
+/* Polytropic closure without an energy equation (Sec. 2.2): p = c_ad rho^gamma,
+ * c^2 = gamma c_ad rho^(gamma-1); with rho = h, c_ad = 1/2, gamma = 2 these
+ * are the shallow water equations.  The exponents 0, 1 and 2 are exact
+ * (rho^2 = rho*rho); others go through pow. */
+static double rpow(double r, double e) { return e == 1.0 ? r : e == 2.0 ? r * r : pow(r, e); }
+static double poly_p(const orc_forest* f, double rho) { return f->c.cad * rpow(rho, f->c.gamma); }
+
+/* phys_to_primitive: v = m / rho (via 1/rho), p = (gamma-1)(E - m.m/(2 rho) [- B.B/2]);
+ * the polytrope's primitive vector is (rho, v) (its pressure follows from rho) */
 static void to_prim(const orc_forest* f, const double* u, double* v) {
   const int nd = f->nd;
   const double gm1 = f->c.gamma - 1.0;
@@ -177,6 +185,7 @@ static void to_prim(const orc_forest* f, const double* u, double* v) {
     v[1 + d] = u[1 + d] * inv;
     mm = mm + u[1 + d] * u[1 + d];
   }
+  if (f->poly) return;
   if (!f->mhd) {
     v[iE(f)] = gm1 * (u[iE(f)] - 0.5 * mm * inv);
   } else {
@@ -202,6 +211,7 @@ static void to_cons(const orc_forest* f, const double* v, double* u) {
     u[1 + d] = rho * v[1 + d];
     vv = vv + v[1 + d] * v[1 + d];
   }
+  if (f->poly) return;
   if (!f->mhd) {
     u[iE(f)] = v[iE(f)] * igm1 + 0.5 * rho * vv;
   } else {
@@ -221,8 +231,16 @@ static void to_cons(const orc_forest* f, const double* v, double* u) {
 static void phys_flux(const orc_forest* f, const double* v, const double* u, int n, double* F) {
   const int nd = f->nd;
   const double vn = v[1 + n];
-  const double p = v[iE(f)];
   F[0] = u[1 + n];
+  if (f->poly) {
+    const double p = poly_p(f, v[0]);
+    for (int d = 0; d < nd; d++) {
+      F[1 + d] = u[1 + d] * vn;
+      if (d == n) F[1 + d] = F[1 + d] + p;
+    }
+    return;
+  }
+  const double p = v[iE(f)];
   if (!f->mhd) {
     for (int d = 0; d < nd; d++) {
       F[1 + d] = u[1 + d] * vn;
@@ -248,9 +266,10 @@ static void phys_flux(const orc_forest* f, const double* v, const double* u, int
 }
 
 /* phys_get_cmax (Sec. 1.2): HD sound speed sqrt(gamma p / rho); MHD fast
- * magnetosonic speed in direction n. */
+ * magnetosonic speed in direction n; the polytrope's sqrt(gamma c_ad rho^(gamma-1)). */
 static double speed(const orc_forest* f, const double* v, int n) {
   const double g = f->c.gamma;
+  if (f->poly) return sqrt(g * f->c.cad * rpow(v[0], g - 1.0));
   if (!f->mhd) return sqrt(g * v[iE(f)] / v[0]);
   const int nd = f->nd;
   double irho = 1.0 / v[0];
@@ -560,11 +579,18 @@ int orc_forest_create(const orc_config* cfg, int64_t n, const int32_t* lev, cons
   if (c->ndim < 1 || c->ndim > 3) return fail(ORC_EINVAL, "ndim must be 1..3");
   if (c->nghost != 2) return fail(ORC_EINVAL, "nghost must be 2");
   if (c->max_level < 1 || c->max_level > 12) return fail(ORC_EINVAL, "max_level out of range");
-  if (c->physics != PHYS_EULER && c->physics != PHYS_MHD) return fail(ORC_EINVAL, "bad physics");
+  if (c->physics != PHYS_EULER && c->physics != PHYS_MHD && c->physics != PHYS_POLY)
+    return fail(ORC_EINVAL, "bad physics");
   if (c->flux < 0 || c->flux > 2) return fail(ORC_EINVAL, "bad flux");
   if (c->limiter < 0 || c->limiter > 4) return fail(ORC_EINVAL, "bad limiter");
   if (c->rk_stages != 2 && c->rk_stages != 3) return fail(ORC_EINVAL, "rk_stages must be 2 or 3");
-  if (!(c->gamma > 1.0) || !(c->cfl > 0.0)) return fail(ORC_EINVAL, "gamma must be > 1, cfl > 0");
+  if (c->physics == PHYS_POLY) {
+    if (!(c->gamma >= 1.0) || !(c->cad > 0.0) || !(c->cfl > 0.0))
+      return fail(ORC_EINVAL, "polytrope needs gamma >= 1, c_ad > 0, cfl > 0");
+    if (c->flux == FLUX_HLLC) return fail(ORC_EINVAL, "HLLC needs the energy equation (not the polytrope)");
+  } else if (!(c->gamma > 1.0) || !(c->cfl > 0.0)) {
+    return fail(ORC_EINVAL, "gamma must be > 1, cfl > 0");
+  }
   for (int d = 0; d < c->ndim; d++) {
     if (c->block_nx[d] < 4 || (c->block_nx[d] & 1))
       return fail(ORC_EINVAL, "block_nx must be even and >= 4");
@@ -578,7 +604,8 @@ int orc_forest_create(const orc_config* cfg, int64_t n, const int32_t* lev, cons
   f->c = *c;
   f->nd = c->ndim;
   f->mhd = c->physics == PHYS_MHD;
-  f->nvar = f->mhd ? 3 + 2 * f->nd : 2 + f->nd;
+  f->poly = c->physics == PHYS_POLY;
+  f->nvar = f->mhd ? 3 + 2 * f->nd : f->poly ? 1 + f->nd : 2 + f->nd;
   f->ng = c->nghost;
   f->n = n;
   f->ncell = 1;
@@ -1150,6 +1177,16 @@ int orc_advance(orc_forest* f, double dt) {
 /* Courant time step (Sec. 2.1: Courant number, phys_get_cmax)          */
 /* ------------------------------------------------------------------ */
 
+/* rho <= 0, p <= 0 or NaN (the polytrope: rho <= 0 or a velocity that is
+ * NaN or overflows, its pressure being positive with rho) */
+static int nonphysical(const orc_forest* f, const double* v) {
+  if (!(v[0] > 0.0)) return 1;
+  if (!f->poly) return !(v[iE(f)] > 0.0);
+  double vv = 0.0;
+  for (int d = 0; d < f->nd; d++) vv = vv + v[1 + d] * v[1 + d];
+  return !(vv < INFINITY);
+}
+
 static int check_physical(const orc_forest* f, const double* S) {
   int bad = 0;
 #pragma omp parallel for reduction(| : bad) schedule(static)
@@ -1158,7 +1195,7 @@ static int check_physical(const orc_forest* f, const double* S) {
       double u[NVMAX], v[NVMAX];
       for (int k = 0; k < f->nvar; k++) u[k] = st(f, S, k, b, c);
       to_prim(f, u, v);
-      if (!(v[0] > 0.0) || !(v[iE(f)] > 0.0)) bad = 1;
+      if (nonphysical(f, v)) bad = 1;
     }
   if (bad) return fail(ORC_ENONPHYSICAL, "non-physical state (rho <= 0, p <= 0 or NaN)");
   return ORC_OK;
@@ -1180,7 +1217,7 @@ int orc_max_dt(orc_forest* f, double* dt_out) {
       double u[NVMAX], v[NVMAX];
       for (int k = 0; k < f->nvar; k++) u[k] = st(f, f->U, k, b, c);
       to_prim(f, u, v);
-      if (!(v[0] > 0.0) || !(v[iE(f)] > 0.0)) {
+      if (nonphysical(f, v)) {
         bad = 1;
         continue;
       }
@@ -1251,7 +1288,7 @@ int orc_flag_blocks(orc_forest* f, int8_t* flags, double* emax_out) {
       padded_prim(f, w.W, w.P);
       for (int64_t c = 0; c < f->npad; c++) {
         rho[c] = w.P[c];
-        prs[c] = w.P[(int64_t)iE(f) * f->npad + c];
+        prs[c] = f->poly ? poly_p(f, w.P[c]) : w.P[(int64_t)iE(f) * f->npad + c];
       }
       double emax = 0.0;
       for (int k = 0; k < f->nx[2]; k++)
@@ -1300,7 +1337,7 @@ int orc_lohner_cells(orc_forest* f, int64_t leaf, double* out, int64_t n_doubles
     padded_prim(f, w.W, w.P);
     for (int64_t c = 0; c < f->npad; c++) {
       rho[c] = w.P[c];
-      prs[c] = w.P[(int64_t)iE(f) * f->npad + c];
+      prs[c] = f->poly ? poly_p(f, w.P[c]) : w.P[(int64_t)iE(f) * f->npad + c];
     }
     for (int k = 0; k < f->nx[2]; k++)
       for (int j = 0; j < f->nx[1]; j++)

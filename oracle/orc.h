@@ -35,16 +35,18 @@ extern "C" {
 
 typedef struct orc_forest orc_forest;
 
-/* Field order is part of the contract: 20 int32 then 11 double. */
+/* Field order is part of the contract: 20 int32 then 12 double. */
 typedef struct {
   int32_t ndim;            /* 1, 2 or 3 */
   int32_t block_nx[3];     /* interior cells per block and dimension (1 if unused) */
   int32_t nghost;          /* ghost layers; must be 2 */
   int32_t base_blocks[3];  /* level-1 blocks per dimension */
   int32_t max_level;       /* refine_max_level of Sec. 1.3 (1 = pure decomposition) */
-  int32_t physics;         /* 0 = Euler (HD), 1 = ideal MHD with GLM cleaning */
+  int32_t physics;         /* 0 = Euler (HD), 1 = ideal MHD with GLM cleaning, 2 = polytrope
+                              p = c_ad rho^gamma without energy equation (shallow water:
+                              c_ad = 1/2, gamma = 2; TVDLF or HLL) */
   int32_t flux;            /* 0 = TVDLF, 1 = HLL, 2 = HLLC */
-  int32_t limiter;         /* 0 = minmod, 1 = van Leer, 2 = monotonized central, 3 = Koren */
+  int32_t limiter;         /* 0 = minmod, 1 = van Leer, 2 = monotonized central, 3 = Koren, 4 = Cada */
   int32_t rk_stages;       /* 2 = SSP-RK2, 3 = SSP-RK3 */
   int32_t bc[3][2];        /* per dimension, low/high side: 0 periodic, 1 zero gradient */
   int32_t pad_;
@@ -52,6 +54,7 @@ typedef struct {
   double gamma, cfl;
   double lohner_tol, lohner_coarsen_frac, lohner_eps, lohner_w_rho, lohner_w_p;
   double glm_cr;
+  double cad;              /* c_ad of the polytrope */
 } orc_config;
 
 int orc_forest_create(const orc_config* cfg, int64_t nleaves,

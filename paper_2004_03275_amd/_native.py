@@ -56,6 +56,7 @@ class Config(ctypes.Structure):
         ("lohner_w_rho", ctypes.c_double),
         ("lohner_w_p", ctypes.c_double),
         ("glm_cr", ctypes.c_double),
+        ("cad", ctypes.c_double),
     ]
 
 
@@ -160,6 +161,7 @@ def make_config(s) -> Config:
     c.lohner_w_rho = s.lohner_w_rho
     c.lohner_w_p = s.lohner_w_p
     c.glm_cr = s.glm_cr
+    c.cad = s.cad
     return c
 
 

@@ -356,7 +356,8 @@ int amrv_forest_create(const amrv_config* cfg, int64_t n, const int32_t* lev, co
       }
     }
   f->lc.ndim = t.nd;
-  f->lc.mhd = cfg->physics == AMRV_MHD_GLM;
+  static_assert(AMRV_EULER == PH_EULER && AMRV_MHD_GLM == PH_MHD && AMRV_POLYTROPE == PH_POLY, "physics codes");
+  f->lc.phys = cfg->physics;
   f->lc.flux = cfg->flux;
   f->lc.lim = cfg->limiter;
   f->lc.variant = 0;
@@ -370,6 +371,8 @@ int amrv_forest_create(const amrv_config* cfg, int64_t n, const int32_t* lev, co
   pp[PP_GAMMA] = cfg->gamma;
   pp[PP_GM1] = cfg->gamma - 1.0;
   pp[PP_IGM1] = 1.0 / (cfg->gamma - 1.0);
+  pp[PP_CAD] = cfg->cad;
+  pp[PP_GCAD] = cfg->gamma * cfg->cad;
   double lp[LP_COUNT] = {0};
   lp[LP_EPS] = cfg->lohner_eps;
   lp[LP_WRHO] = cfg->lohner_w_rho;

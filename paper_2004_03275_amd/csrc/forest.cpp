@@ -45,13 +45,20 @@ int build_tables(const amrv_config& c, int64_t n, const int32_t* lev, const int3
   if (c.ndim < 1 || c.ndim > 3) return fail(AMRV_EINVAL, "ndim must be 1, 2 or 3");
   if (c.nghost != 2) return fail(AMRV_EINVAL, "nghost must be 2");
   if (c.max_level < 1 || c.max_level > MAXLEV - 1) return fail(AMRV_EINVAL, "max_level out of range");
-  if (c.physics != AMRV_EULER && c.physics != AMRV_MHD_GLM) return fail(AMRV_EINVAL, "unknown physics");
+  if (c.physics != AMRV_EULER && c.physics != AMRV_MHD_GLM && c.physics != AMRV_POLYTROPE)
+    return fail(AMRV_EINVAL, "unknown physics");
   if (c.flux < AMRV_TVDLF || c.flux > AMRV_HLLC) return fail(AMRV_EINVAL, "unknown flux");
   if (c.limiter != AMRV_MINMOD && c.limiter != AMRV_VANLEER && c.limiter != AMRV_MC && c.limiter != AMRV_KOREN &&
       c.limiter != AMRV_CADA)
     return fail(AMRV_EINVAL, "unknown limiter");
   if (c.rk_stages != 2 && c.rk_stages != 3) return fail(AMRV_EINVAL, "rk_stages must be 2 or 3");
-  if (!(c.gamma > 1.0) || !(c.cfl > 0.0)) return fail(AMRV_EINVAL, "gamma must exceed 1 and cfl be positive");
+  if (c.physics == AMRV_POLYTROPE) {
+    if (!(c.gamma >= 1.0) || !(c.cad > 0.0) || !(c.cfl > 0.0))
+      return fail(AMRV_EINVAL, "the polytrope needs gamma >= 1, c_ad > 0 and a positive cfl");
+    if (c.flux == AMRV_HLLC) return fail(AMRV_EINVAL, "HLLC needs the energy equation (not the polytrope)");
+  } else if (!(c.gamma > 1.0) || !(c.cfl > 0.0)) {
+    return fail(AMRV_EINVAL, "gamma must exceed 1 and cfl be positive");
+  }
   const int nd = c.ndim;
   for (int d = 0; d < nd; d++) {
     if (c.block_nx[d] < 4 || (c.block_nx[d] & 1)) return fail(AMRV_EINVAL, "block_nx must be even and >= 4");
@@ -73,7 +80,7 @@ int build_tables(const amrv_config& c, int64_t n, const int32_t* lev, const int3
   t.ncell = 1;
   for (int d = 0; d < nd; d++) t.ncell *= c.block_nx[d];
   t.T = t.ncell / t.nx;
-  t.nvar = c.physics == AMRV_EULER ? 2 + nd : 3 + 2 * nd;
+  t.nvar = c.physics == AMRV_MHD_GLM ? 3 + 2 * nd : c.physics == AMRV_POLYTROPE ? 1 + nd : 2 + nd;
 
   auto nblk = [&](int l, int d) -> int64_t { return d < nd ? (int64_t)c.base_blocks[d] << (l - 1) : 1; };
   auto periodic = [&](int d) { return c.bc[d][0] == AMRV_BC_PERIODIC; };

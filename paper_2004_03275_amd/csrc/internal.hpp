@@ -63,9 +63,15 @@ struct StageArgs {
 
 struct Kernels;  // forward
 
+// physics: Euler (energy equation), ideal MHD with GLM cleaning, and the
+// polytrope p = c_ad rho^gamma without energy equation (shallow water for
+// rho = h, c_ad = 1/2, gamma = 2); the values of AMRV_EULER, AMRV_MHD_GLM and
+// AMRV_POLYTROPE
+enum { PH_EULER = 0, PH_MHD = 1, PH_POLY = 2 };
+
 // launchers (kernels.hip)
 struct LaunchCfg {
-  int ndim, mhd, flux, lim;
+  int ndim, phys, flux, lim;  // phys: PH_EULER, PH_MHD or PH_POLY
   int variant;  // stage kernel: 0 combined x/y phases, 1 split x then y
 };
 
@@ -101,7 +107,9 @@ constexpr int CNT_QUEUES = 32, CNT_ERR = 40, CNT_TAKEN = 41, CNT_COUNT = 64;
 
 // device parameter block (written once per forest, plus dt / ch per step)
 // layout: [0] gamma [1] gm1 [2] igm1 [3] ch [4] dt [5] glm damping factor
-constexpr int PP_GAMMA = 0, PP_GM1 = 1, PP_IGM1 = 2, PP_CH = 3, PP_DT = 4, PP_DAMP = 5, PP_T = 6, PP_COUNT = 8;
+// [6] time [7] c_ad [8] gamma * c_ad
+constexpr int PP_GAMMA = 0, PP_GM1 = 1, PP_IGM1 = 2, PP_CH = 3, PP_DT = 4, PP_DAMP = 5, PP_T = 6, PP_CAD = 7,
+              PP_GCAD = 8, PP_COUNT = 16;
 // Loehner parameters: [0] eps [1] w_rho [2] w_p [3] tol [4] coarsen tol
 constexpr int LP_EPS = 0, LP_WRHO = 1, LP_WP = 2, LP_TOL = 3, LP_CTOL = 4, LP_COUNT = 8;
 

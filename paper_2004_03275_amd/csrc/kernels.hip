@@ -130,38 +130,40 @@ __device__ __forceinline__ PhysParams load_phys(const double* __restrict__ pp) {
   P.gm1 = pp[PP_GM1];
   P.igm1 = pp[PP_IGM1];
   P.ch = pp[PP_CH];
+  P.cad = pp[PP_CAD];
+  P.gcad = pp[PP_GCAD];
   return P;
 }
 
-template <int ND, bool MHD, int FLUX>
+template <int ND, int PH, int FLUX>
 __device__ __forceinline__ void riemann_dir(int d, double* vl, double* vr, double* F, const PhysParams& P) {
   if (d == 0) {
-    riemann<ND, MHD, FLUX, 0>(vl, vr, F, P);
+    riemann<ND, PH, FLUX, 0>(vl, vr, F, P);
   } else if constexpr (ND > 1) {
     if (d == 1) {
-      riemann<ND, MHD, FLUX, (ND > 1 ? 1 : 0)>(vl, vr, F, P);
+      riemann<ND, PH, FLUX, (ND > 1 ? 1 : 0)>(vl, vr, F, P);
     } else if constexpr (ND > 2) {
-      riemann<ND, MHD, FLUX, (ND > 2 ? 2 : 0)>(vl, vr, F, P);
+      riemann<ND, PH, FLUX, (ND > 2 ? 2 : 0)>(vl, vr, F, P);
     }
   }
 }
 
 // Courant quantities of one cell (Sec. 2.1): sum_d (|v_d| + c_d) / dx_d and
 // max_d (|v_d| + c_d), with the non-physical test; same arithmetic as k_cfl
-template <int ND, bool MHD>
+template <int ND, int PH>
 __device__ __forceinline__ void cfl_cell(const double* u, const PhysParams& P, const double* rd,
                                          unsigned long long& smax, unsigned long long& cmax, int& bad) {
-  constexpr int NV = Sys<ND, MHD>::NV;
+  constexpr int NV = Sys<ND, PH>::NV;
   double v[NV];
-  cons2prim<ND, MHD>(u, v, P);
-  if (!(v[0] > 0.0) || !(v[Sys<ND, MHD>::IE] > 0.0)) {
+  cons2prim<ND, PH>(u, v, P);
+  if (nonphysical<ND, PH>(v)) {
     bad = 1;
     return;
   }
   double s = 0.0, cm = 0.0;
 #pragma unroll
   for (int d = 0; d < ND; d++) {
-    const double w = fabs(v[1 + d]) + wave_speed_dir<ND, MHD>(v, d, P);
+    const double w = fabs(v[1 + d]) + wave_speed_dir<ND, PH>(v, d, P);
     const double tq = w * rd[d];
     s = d == 0 ? tq : s + tq;
     cm = w > cm ? w : cm;
@@ -255,11 +257,11 @@ __global__ void __launch_bounds__(WGS) k_restrict(Geo g, const double* __restric
 // cells and the two ghosts.  Prolongation never reads a prolonged value:
 // with 2:1 balance over edges and corners the coarse stencil only touches
 // coarse interior cells and restricted or same-level ghosts.
-template <int ND, bool MHD, int FLUX, int LIM>
+template <int ND, int PH, int FLUX, int LIM>
 __global__ void __launch_bounds__(WGS) k_prolong_flux(Geo g, const double* __restrict__ U,
                                                       const double* __restrict__ pp,
                                                       const int32_t* __restrict__ list, int nlist, int fluxes) {
-  using S = Sys<ND, MHD>;
+  using S = Sys<ND, PH>;
   constexpr int NV = S::NV;
   const long long i = (long long)blockIdx.x * WGS + threadIdx.x;
   if (i >= (long long)nlist * g.T) return;
@@ -326,10 +328,10 @@ __global__ void __launch_bounds__(WGS) k_prolong_flux(Geo g, const double* __res
     const int cell = cell_index(g, c[0], c[1], c[2]);
 #pragma unroll
     for (int v = 0; v < NV; v++) u[v] = U[uidx(g, v, fine, cell)];
-    cons2prim<ND, MHD>(u, W[j], P);
+    cons2prim<ND, PH>(u, W[j], P);
   }
-  cons2prim<ND, MHD>(r0, W[2], P);
-  cons2prim<ND, MHD>(r1, W[3], P);
+  cons2prim<ND, PH>(r0, W[2], P);
+  cons2prim<ND, PH>(r1, W[3], P);
   // the four cells in increasing coordinate along d
   double V0[NV], V1[NV], V2[NV], V3[NV];
 #pragma unroll
@@ -342,7 +344,7 @@ __global__ void __launch_bounds__(WGS) k_prolong_flux(Geo g, const double* __res
   double lo_[NV], vl[NV], vr[NV], hi_[NV], F[NV];
   muscl<NV, LIM>(V0, V1, V2, lo_, vl);
   muscl<NV, LIM>(V1, V2, V3, vr, hi_);
-  riemann_dir<ND, MHD, FLUX>(d, vl, vr, F, P);
+  riemann_dir<ND, PH, FLUX>(d, vl, vr, F, P);
   const size_t fb = (size_t)slot * NV * g.T + t;
 #pragma unroll
   for (int v = 0; v < NV; v++) g.FF[fb + (size_t)v * g.T] = F[v];
@@ -460,24 +462,24 @@ __device__ __forceinline__ int queue_next(const Sched& sc, int n) {
   return n;
 }
 
-template <int ND, bool MHD>
+template <int ND, int PH>
 __device__ __forceinline__ void own_prim(const Geo& g, const double* __restrict__ U, int leaf, int x, int y, int z,
                                          double* v, const PhysParams& P) {
-  constexpr int NV = Sys<ND, MHD>::NV;
+  constexpr int NV = Sys<ND, PH>::NV;
   double u[NV];
   fetch_cons<NV, ND>(g, U, leaf, x, y, z, u);
-  cons2prim<ND, MHD>(u, v, P);
+  cons2prim<ND, PH>(u, v, P);
 }
 
 // exchange the x and y components (velocity or momentum, magnetic field) of a
 // state or flux vector
-template <int ND, bool MHD>
+template <int ND, int PH>
 __device__ __forceinline__ void swap_xy(double* q) {
-  using S = Sys<ND, MHD>;
+  using S = Sys<ND, PH>;
   double t = q[1];
   q[1] = q[2];
   q[2] = t;
-  if constexpr (MHD) {
+  if constexpr (PH == PH_MHD) {
     t = q[S::IB];
     q[S::IB] = q[S::IB + 1];
     q[S::IB + 1] = t;
@@ -512,10 +514,10 @@ __device__ __forceinline__ void load_strided(const double* __restrict__ p, size_
 // plane, separate x/y LDS arrays).  SPLIT = true: x, then y, through one set
 // of LDS arrays (5 barriers per plane, 40% less LDS, so more workgroups fit
 // on a compute unit).  Both evaluate identical expressions.
-template <int ND, bool MHD, int FLUX, int LIM, bool SPLIT>
-__global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, MHD>::NV <= 5) ? 3 : 1) k_stage_tile(Geo g, StageArgs a, const double* __restrict__ pp,
+template <int ND, int PH, int FLUX, int LIM, bool SPLIT>
+__global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>::NV <= 5) ? 3 : 1) k_stage_tile(Geo g, StageArgs a, const double* __restrict__ pp,
                                                                   Sched sc) {
-  using S = Sys<ND, MHD>;
+  using S = Sys<ND, PH>;
   constexpr int NV = S::NV;
   constexpr int PW = NB + 4;
   constexpr int NZ = ND == 3 ? NB : 1;
@@ -642,17 +644,17 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, MHD
         for (int v = 0; v < NV; v++) sZF[v][tid] = F[v];
       }
       double vm2[NV], vm1[NV], c[NV], lo[NV], hi[NV], vlm1[NV];
-      own_prim<ND, MHD>(g, a.Uin, leaf, tx, ty, -2, vm2, P);
-      own_prim<ND, MHD>(g, a.Uin, leaf, tx, ty, -1, vm1, P);
+      own_prim<ND, PH>(g, a.Uin, leaf, tx, ty, -2, vm2, P);
+      own_prim<ND, PH>(g, a.Uin, leaf, tx, ty, -1, vm1, P);
       load_strided<NV>(own, vs, c);
-      cons2prim<ND, MHD>(c, V0, P);
+      cons2prim<ND, PH>(c, V0, P);
       load_strided<NV>(own + NB * NB, vs, c);
-      cons2prim<ND, MHD>(c, V1, P);
+      cons2prim<ND, PH>(c, V1, P);
       load_strided<NV>(own + 2 * NB * NB, vs, C2);
       muscl<NV, LIM>(vm2, vm1, V0, lo, vlm1);
       muscl<NV, LIM>(vm1, V0, V1, lo, hi);
       if (kinds[4] == NB_SAME || kinds[4] == NB_BND) {
-        riemann<ND, MHD, FLUX, (ND == 3 ? 2 : 0)>(vlm1, lo, Flo, P);
+        riemann<ND, PH, FLUX, (ND == 3 ? 2 : 0)>(vlm1, lo, Flo, P);
       } else {
         cf_flux<NV, ND>(g, leaf, 4, kinds[4], tx, ty, Flo);
       }
@@ -661,7 +663,7 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, MHD
     } else {
       double c[NV];
       load_strided<NV>(own, vs, c);
-      cons2prim<ND, MHD>(c, V0, P);
+      cons2prim<ND, PH>(c, V0, P);
     }
     if (ring) load_strided<NV>(rptr, rvs, Cr);
     // vmcnt(0) here and at the end of every plane: the loads of plane k+1 were
@@ -675,7 +677,7 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, MHD
       if constexpr (ND == 3) {
         // (1) z direction: prefetched plane k+2, slope of cell k+1, face k+1/2
         double V2[NV], VR1[NV], VL1[NV], Fhi[NV];
-        cons2prim<ND, MHD>(C2, V2, P);
+        cons2prim<ND, PH>(C2, V2, P);
         const int pn = k + 3;
         if (pn < NB)
           load_strided<NV>(own + pn * NB * NB, vs, C2);
@@ -686,7 +688,7 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, MHD
 #pragma unroll
           for (int v = 0; v < NV; v++) Fhi[v] = sZF[v][tid];
         } else {
-          riemann<ND, MHD, FLUX, (ND == 3 ? 2 : 0)>(VLz, VR1, Fhi, P);
+          riemann<ND, PH, FLUX, (ND == 3 ? 2 : 0)>(VLz, VR1, Fhi, P);
         }
 #pragma unroll
         for (int v = 0; v < NV; v++) {
@@ -707,7 +709,7 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, MHD
       }
       if (ring) {
         double w[NV];
-        cons2prim<ND, MHD>(Cr, w, P);
+        cons2prim<ND, PH>(Cr, w, P);
 #pragma unroll
         for (int v = 0; v < NV; v++) sP[v][rdst] = w[v];
         if (k + 1 < NZ) load_strided<NV>(rptr + (k + 1) * rks, rvs, Cr);
@@ -793,11 +795,11 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, MHD
               vr[v] = sP[v][bl + st] - sll[v * NSX + s1];
             }
             if (yd) {
-              swap_xy<ND, MHD>(vl);
-              swap_xy<ND, MHD>(vr);
+              swap_xy<ND, PH>(vl);
+              swap_xy<ND, PH>(vr);
             }
-            riemann<ND, MHD, FLUX, 0>(vl, vr, F, P);
-            if (yd) swap_xy<ND, MHD>(F);
+            riemann<ND, PH, FLUX, 0>(vl, vr, F, P);
+            if (yd) swap_xy<ND, PH>(F);
           }
           double* fo = &sF[yd ? NSB - 1 : 0][0][0];
 #pragma unroll
@@ -840,7 +842,7 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, MHD
       }
       if (a.cflred) {
         const double rd[3] = {rdx, rdy, rdz};
-        cfl_cell<ND, MHD>(Ui, P, rd, csmax, ccmax, cbad);
+        cfl_cell<ND, PH>(Ui, P, rd, csmax, ccmax, cbad);
       }
       __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), see above
     }
@@ -852,9 +854,9 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, MHD
 // stage update, 1D: a leaf of nx cells in chunks of 256, one workgroup each
 // ---------------------------------------------------------------------------
 
-template <bool MHD, int FLUX, int LIM>
+template <int PH, int FLUX, int LIM>
 __global__ void __launch_bounds__(WGS) k_stage_line(Geo g, StageArgs a, const double* __restrict__ pp, Sched sc) {
-  using S = Sys<1, MHD>;
+  using S = Sys<1, PH>;
   constexpr int NV = S::NV;
   constexpr int CH = WGS;
   __shared__ double sP[NV][CH + 4];
@@ -878,7 +880,7 @@ __global__ void __launch_bounds__(WGS) k_stage_line(Geo g, StageArgs a, const do
     if (x > g.nx + 1) continue;
     double u[NV], w[NV];
     fetch_cons<NV, 1>(g, a.Uin, leaf, x, 0, 0, u);
-    cons2prim<1, MHD>(u, w, P);
+    cons2prim<1, PH>(u, w, P);
 #pragma unroll
     for (int v = 0; v < NV; v++) sP[v][t] = w[v];
   }
@@ -916,7 +918,7 @@ __global__ void __launch_bounds__(WGS) k_stage_line(Geo g, StageArgs a, const do
         vl[v] = sL[v][t];
         vr[v] = sR[v][t + 1];
       }
-      riemann<1, MHD, FLUX, 0>(vl, vr, F, P);
+      riemann<1, PH, FLUX, 0>(vl, vr, F, P);
     }
 #pragma unroll
     for (int v = 0; v < NV; v++) sF[v][t] = F[v];
@@ -938,7 +940,7 @@ __global__ void __launch_bounds__(WGS) k_stage_line(Geo g, StageArgs a, const do
     }
     if (a.cflred) {
       const double rd[3] = {rdx, 0.0, 0.0};
-      cfl_cell<1, MHD>(res, P, rd, csmax, ccmax, cbad);
+      cfl_cell<1, PH>(res, P, rd, csmax, ccmax, cbad);
     }
   }
   if (a.cflred) cfl_fold(a.cflred, csmax, ccmax, cbad);
@@ -960,10 +962,10 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
 // red[0] = bits of max_cells sum_d (|v_d|+c_d)/dx_d, red[1] = bits of the max
 // signal speed (GLM c_h), red[2] = non-physical flag.  Non-negative doubles
 // order like their bit patterns, so integer atomics give the exact maximum.
-template <int ND, bool MHD>
+template <int ND, int PH>
 __global__ void __launch_bounds__(WGS) k_cfl(Geo g, const double* __restrict__ U, const double* __restrict__ pp,
                                              unsigned long long* red) {
-  constexpr int NV = Sys<ND, MHD>::NV;
+  constexpr int NV = Sys<ND, PH>::NV;
   const PhysParams P = load_phys(pp);
   const long long total = (long long)g.n * g.ncell;
   unsigned long long smax = 0, cmax = 0;
@@ -973,8 +975,8 @@ __global__ void __launch_bounds__(WGS) k_cfl(Geo g, const double* __restrict__ U
     double u[NV], v[NV];
 #pragma unroll
     for (int k = 0; k < NV; k++) u[k] = U[uidx(g, k, leaf, cell)];
-    cons2prim<ND, MHD>(u, v, P);
-    if (!(v[0] > 0.0) || !(v[Sys<ND, MHD>::IE] > 0.0)) {
+    cons2prim<ND, PH>(u, v, P);
+    if (nonphysical<ND, PH>(v)) {
       bad = 1;
       continue;
     }
@@ -982,7 +984,7 @@ __global__ void __launch_bounds__(WGS) k_cfl(Geo g, const double* __restrict__ U
     double s = 0.0, cm = 0.0;
 #pragma unroll
     for (int d = 0; d < ND; d++) {
-      const double w = fabs(v[1 + d]) + wave_speed_dir<ND, MHD>(v, d, P);
+      const double w = fabs(v[1 + d]) + wave_speed_dir<ND, PH>(v, d, P);
       const double tq = w * g.rdx[lvl][d];
       s = d == 0 ? tq : s + tq;
       cm = w > cm ? w : cm;
@@ -1006,18 +1008,18 @@ __global__ void __launch_bounds__(WGS) k_cfl(Geo g, const double* __restrict__ U
 // Loehner flags (Sec. 1.3): one workgroup per leaf
 // ---------------------------------------------------------------------------
 
-template <int ND, bool MHD>
+template <int ND, int PH>
 __device__ __forceinline__ void rho_p(const Geo& g, const double* __restrict__ U, int leaf, int x, int y, int z,
                                       const PhysParams& P, double& rho, double& p) {
-  constexpr int NV = Sys<ND, MHD>::NV;
+  constexpr int NV = Sys<ND, PH>::NV;
   double u[NV], v[NV];
   fetch_cons<NV, ND>(g, U, leaf, x, y, z, u);
-  cons2prim<ND, MHD>(u, v, P);
+  cons2prim<ND, PH>(u, v, P);
   rho = v[0];
-  p = v[Sys<ND, MHD>::IE];
+  p = pressure<ND, PH>(v, P);
 }
 
-template <int ND, bool MHD>
+template <int ND, int PH>
 __global__ void __launch_bounds__(WGS) k_lohner(Geo g, const double* __restrict__ U, const double* __restrict__ pp,
                                                 const double* __restrict__ lp, int max_level, double* emax_out,
                                                 int8_t* flags, const int8_t* __restrict__ only) {
@@ -1032,7 +1034,7 @@ __global__ void __launch_bounds__(WGS) k_lohner(Geo g, const double* __restrict_
     const int y = ND > 1 ? (cell / g.nx) % g.nx : 0;
     const int z = ND > 2 ? cell / (g.nx * g.nx) : 0;
     double r0, p0;
-    rho_p<ND, MHD>(g, U, leaf, x, y, z, P, r0, p0);
+    rho_p<ND, PH>(g, U, leaf, x, y, z, P, r0, p0);
     double nr = 0.0, dr = 0.0, np = 0.0, dp = 0.0;
 #pragma unroll
     for (int d = 0; d < ND; d++) {
@@ -1040,8 +1042,8 @@ __global__ void __launch_bounds__(WGS) k_lohner(Geo g, const double* __restrict_
       lo[d] -= 1;
       hi[d] += 1;
       double rm, pm, rp, pq;
-      rho_p<ND, MHD>(g, U, leaf, lo[0], lo[1], lo[2], P, rm, pm);
-      rho_p<ND, MHD>(g, U, leaf, hi[0], hi[1], hi[2], P, rp, pq);
+      rho_p<ND, PH>(g, U, leaf, lo[0], lo[1], lo[2], P, rm, pm);
+      rho_p<ND, PH>(g, U, leaf, hi[0], hi[1], hi[2], P, rp, pq);
       const double d2r = rp - 2.0 * r0 + rm;
       const double ddr = fabs(rp - r0) + fabs(r0 - rm) + eps * (fabs(rp) + 2.0 * fabs(r0) + fabs(rm));
       const double d2p = pq - 2.0 * p0 + pm;
@@ -1105,35 +1107,43 @@ __global__ void k_scale(double* U, const double* __restrict__ facp, long long co
 template <int V>
 using IC = std::integral_constant<int, V>;
 
-// call fn(IC<ndim>, IC<mhd>, IC<flux>, IC<limiter>) for the runtime
-// configuration
+// call fn(IC<ndim>, IC<physics>, IC<flux>, IC<limiter>) for the runtime
+// configuration; the polytrope has no HLLC instance
 template <class Fn>
 static void dispatch(const LaunchCfg& c, Fn&& fn) {
-  auto lim = [&](auto nd, auto mhd, auto fl) {
+  auto lim = [&](auto nd, auto ph, auto fl) {
     if (c.lim == LIM_MINMOD)
-      fn(nd, mhd, fl, IC<LIM_MINMOD>{});
+      fn(nd, ph, fl, IC<LIM_MINMOD>{});
     else if (c.lim == LIM_MC)
-      fn(nd, mhd, fl, IC<LIM_MC>{});
+      fn(nd, ph, fl, IC<LIM_MC>{});
     else if (c.lim == LIM_KOREN)
-      fn(nd, mhd, fl, IC<LIM_KOREN>{});
+      fn(nd, ph, fl, IC<LIM_KOREN>{});
     else if (c.lim == LIM_CADA)
-      fn(nd, mhd, fl, IC<LIM_CADA>{});
+      fn(nd, ph, fl, IC<LIM_CADA>{});
     else
-      fn(nd, mhd, fl, IC<LIM_VANLEER>{});
+      fn(nd, ph, fl, IC<LIM_VANLEER>{});
   };
-  auto flx = [&](auto nd, auto mhd) {
+  auto flx = [&](auto nd, auto ph) {
     if (c.flux == FLX_TVDLF)
-      lim(nd, mhd, IC<FLX_TVDLF>{});
+      lim(nd, ph, IC<FLX_TVDLF>{});
     else if (c.flux == FLX_HLL)
-      lim(nd, mhd, IC<FLX_HLL>{});
+      lim(nd, ph, IC<FLX_HLL>{});
     else
-      lim(nd, mhd, IC<FLX_HLLC>{});
+      lim(nd, ph, IC<FLX_HLLC>{});
+  };
+  auto poly_flx = [&](auto nd) {
+    if (c.flux == FLX_TVDLF)
+      lim(nd, IC<PH_POLY>{}, IC<FLX_TVDLF>{});
+    else
+      lim(nd, IC<PH_POLY>{}, IC<FLX_HLL>{});
   };
   auto phys = [&](auto nd) {
-    if (c.mhd)
-      flx(nd, IC<1>{});
+    if (c.phys == PH_MHD)
+      flx(nd, IC<PH_MHD>{});
+    else if (c.phys == PH_POLY)
+      poly_flx(nd);
     else
-      flx(nd, IC<0>{});
+      flx(nd, IC<PH_EULER>{});
   };
   if (c.ndim == 1)
     phys(IC<1>{});
@@ -1149,11 +1159,13 @@ hipError_t launch_restrict(const Geo& g, const LaunchCfg& c, const double* U, co
                            hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
   const unsigned nb = blocks_for((long long)nlist * g.T);
-#define BODY_R                                                                                 \
-  if (c.mhd) {                                                                                 \
-    hipLaunchKernelGGL((k_restrict<ND, Sys<ND, true>::NV>), dim3(nb), dim3(WGS), 0, st, g, U, list, nlist); \
-  } else {                                                                                     \
-    hipLaunchKernelGGL((k_restrict<ND, Sys<ND, false>::NV>), dim3(nb), dim3(WGS), 0, st, g, U, list, nlist); \
+#define BODY_R                                                                                                        \
+  if (c.phys == PH_MHD) {                                                                                             \
+    hipLaunchKernelGGL((k_restrict<ND, Sys<ND, PH_MHD>::NV>), dim3(nb), dim3(WGS), 0, st, g, U, list, nlist);         \
+  } else if (c.phys == PH_POLY) {                                                                                     \
+    hipLaunchKernelGGL((k_restrict<ND, Sys<ND, PH_POLY>::NV>), dim3(nb), dim3(WGS), 0, st, g, U, list, nlist);        \
+  } else {                                                                                                            \
+    hipLaunchKernelGGL((k_restrict<ND, Sys<ND, PH_EULER>::NV>), dim3(nb), dim3(WGS), 0, st, g, U, list, nlist);       \
   }
   if (c.ndim == 1) {
     constexpr int ND = 1;
@@ -1172,11 +1184,13 @@ hipError_t launch_restrict(const Geo& g, const LaunchCfg& c, const double* U, co
 hipError_t launch_transfer(const Geo& from, const double* Uf, const Geo& to, double* Ut, const int32_t* xfer,
                            const LaunchCfg& c, hipStream_t st) {
   if (to.n <= 0) return hipSuccess;
-#define BODY_T                                                                                         \
-  if (c.mhd) {                                                                                         \
-    hipLaunchKernelGGL((k_transfer<ND, Sys<ND, true>::NV>), dim3(to.n), dim3(WGS), 0, st, from, Uf, to, Ut, xfer); \
-  } else {                                                                                             \
-    hipLaunchKernelGGL((k_transfer<ND, Sys<ND, false>::NV>), dim3(to.n), dim3(WGS), 0, st, from, Uf, to, Ut, xfer); \
+#define BODY_T                                                                                                        \
+  if (c.phys == PH_MHD) {                                                                                             \
+    hipLaunchKernelGGL((k_transfer<ND, Sys<ND, PH_MHD>::NV>), dim3(to.n), dim3(WGS), 0, st, from, Uf, to, Ut, xfer);  \
+  } else if (c.phys == PH_POLY) {                                                                                     \
+    hipLaunchKernelGGL((k_transfer<ND, Sys<ND, PH_POLY>::NV>), dim3(to.n), dim3(WGS), 0, st, from, Uf, to, Ut, xfer); \
+  } else {                                                                                                            \
+    hipLaunchKernelGGL((k_transfer<ND, Sys<ND, PH_EULER>::NV>), dim3(to.n), dim3(WGS), 0, st, from, Uf, to, Ut, xfer); \
   }
   if (c.ndim == 1) {
     constexpr int ND = 1;
@@ -1196,10 +1210,10 @@ hipError_t launch_prolong(const Geo& g, const LaunchCfg& c, const double* U, con
                           const int32_t* list, int nlist, bool fluxes, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
   const unsigned nb = blocks_for((long long)nlist * g.T);
-  dispatch(c, [&](auto nd, auto mhd, auto fl, auto lm) {
+  dispatch(c, [&](auto nd, auto ph, auto fl, auto lm) {
     constexpr int ND = decltype(nd)::value, FL = decltype(fl)::value, LM = decltype(lm)::value;
-    constexpr bool MHD = decltype(mhd)::value != 0;
-    hipLaunchKernelGGL((k_prolong_flux<ND, MHD, FL, LM>), dim3(nb), dim3(WGS), 0, st, g, U, physp, list, nlist,
+    constexpr int PH = decltype(ph)::value;
+    hipLaunchKernelGGL((k_prolong_flux<ND, PH, FL, LM>), dim3(nb), dim3(WGS), 0, st, g, U, physp, list, nlist,
                        fluxes ? 1 : 0);
   });
   return hipGetLastError();
@@ -1207,15 +1221,15 @@ hipError_t launch_prolong(const Geo& g, const LaunchCfg& c, const double* U, con
 
 hipError_t launch_stage(const Geo& g, const LaunchCfg& c, const StageArgs& a, const double* physp, const Sched& s,
                         int grid, hipStream_t st) {
-  dispatch(c, [&](auto nd, auto mhd, auto fl, auto lm) {
+  dispatch(c, [&](auto nd, auto ph, auto fl, auto lm) {
     constexpr int ND = decltype(nd)::value, FL = decltype(fl)::value, LM = decltype(lm)::value;
-    constexpr bool MHD = decltype(mhd)::value != 0;
+    constexpr int PH = decltype(ph)::value;
     if constexpr (ND == 1)
-      hipLaunchKernelGGL((k_stage_line<MHD, FL, LM>), dim3(grid), dim3(WGS), 0, st, g, a, physp, s);
+      hipLaunchKernelGGL((k_stage_line<PH, FL, LM>), dim3(grid), dim3(WGS), 0, st, g, a, physp, s);
     else if (c.variant == 1 || lim_asym<LM>())
-      hipLaunchKernelGGL((k_stage_tile<ND, MHD, FL, LM, true>), dim3(grid), dim3(WGS), 0, st, g, a, physp, s);
+      hipLaunchKernelGGL((k_stage_tile<ND, PH, FL, LM, true>), dim3(grid), dim3(WGS), 0, st, g, a, physp, s);
     else if constexpr (!lim_asym<LM>())
-      hipLaunchKernelGGL((k_stage_tile<ND, MHD, FL, LM, false>), dim3(grid), dim3(WGS), 0, st, g, a, physp, s);
+      hipLaunchKernelGGL((k_stage_tile<ND, PH, FL, LM, false>), dim3(grid), dim3(WGS), 0, st, g, a, physp, s);
   });
   return hipGetLastError();
 }
@@ -1225,11 +1239,13 @@ hipError_t launch_cfl(const Geo& g, const LaunchCfg& c, const double* U, const d
   const long long total = (long long)g.n * g.ncell;
   long long nb = (total + WGS - 1) / WGS;
   if (nb > 4096) nb = 4096;
-#define BODY_C(ND)                                                                                            \
-  if (c.mhd)                                                                                                  \
-    hipLaunchKernelGGL((k_cfl<ND, true>), dim3((unsigned)nb), dim3(WGS), 0, st, g, U, physp, red);             \
-  else                                                                                                        \
-    hipLaunchKernelGGL((k_cfl<ND, false>), dim3((unsigned)nb), dim3(WGS), 0, st, g, U, physp, red);
+#define BODY_C(ND)                                                                                                    \
+  if (c.phys == PH_MHD)                                                                                               \
+    hipLaunchKernelGGL((k_cfl<ND, PH_MHD>), dim3((unsigned)nb), dim3(WGS), 0, st, g, U, physp, red);                  \
+  else if (c.phys == PH_POLY)                                                                                         \
+    hipLaunchKernelGGL((k_cfl<ND, PH_POLY>), dim3((unsigned)nb), dim3(WGS), 0, st, g, U, physp, red);                 \
+  else                                                                                                                \
+    hipLaunchKernelGGL((k_cfl<ND, PH_EULER>), dim3((unsigned)nb), dim3(WGS), 0, st, g, U, physp, red);
   if (c.ndim == 1) {
     BODY_C(1)
   } else if (c.ndim == 2) {
@@ -1243,12 +1259,15 @@ hipError_t launch_cfl(const Geo& g, const LaunchCfg& c, const double* U, const d
 
 hipError_t launch_lohner(const Geo& g, const LaunchCfg& c, const double* U, const double* physp, const double* lohp,
                          int max_level, double* emax, int8_t* flags, const int8_t* only, hipStream_t st) {
-#define BODY_L(ND)                                                                                                   \
-  if (c.mhd)                                                                                                         \
-    hipLaunchKernelGGL((k_lohner<ND, true>), dim3(g.n), dim3(WGS), 0, st, g, U, physp, lohp, max_level, emax, flags, \
-                       only);                                                                                        \
-  else                                                                                                               \
-    hipLaunchKernelGGL((k_lohner<ND, false>), dim3(g.n), dim3(WGS), 0, st, g, U, physp, lohp, max_level, emax, flags, \
+#define BODY_L(ND)                                                                                                    \
+  if (c.phys == PH_MHD)                                                                                               \
+    hipLaunchKernelGGL((k_lohner<ND, PH_MHD>), dim3(g.n), dim3(WGS), 0, st, g, U, physp, lohp, max_level, emax, flags, \
+                       only);                                                                                         \
+  else if (c.phys == PH_POLY)                                                                                         \
+    hipLaunchKernelGGL((k_lohner<ND, PH_POLY>), dim3(g.n), dim3(WGS), 0, st, g, U, physp, lohp, max_level, emax, flags, \
+                       only);                                                                                         \
+  else                                                                                                                \
+    hipLaunchKernelGGL((k_lohner<ND, PH_EULER>), dim3(g.n), dim3(WGS), 0, st, g, U, physp, lohp, max_level, emax, flags, \
                        only);
   if (c.ndim == 1) {
     BODY_L(1)

@@ -67,10 +67,10 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 // features
 // ---------------------------------------------------------------------------
 
-template <int ND, bool MHD>
+template <int ND, int PH>
 __global__ void __launch_bounds__(128) k_mlp_features(Geo g, const double* __restrict__ U,
                                                       const double* __restrict__ pp, uint16_t* __restrict__ X) {
-  using S = Sys<ND, MHD>;
+  using S = Sys<ND, PH>;
   constexpr int NV = S::NV;
   __shared__ double means[2][64];
   __shared__ double mtot[2];
@@ -82,6 +82,8 @@ __global__ void __launch_bounds__(128) k_mlp_features(Geo g, const double* __res
   P.gm1 = pp[PP_GM1];
   P.igm1 = pp[PP_IGM1];
   P.ch = 0.0;
+  P.cad = pp[PP_CAD];
+  P.gcad = pp[PP_GCAD];
   const size_t vs = (size_t)g.n * g.ncell;
   const double* base = U + (size_t)leaf * g.ncell;
   double s = 0.0;
@@ -98,8 +100,8 @@ __global__ void __launch_bounds__(128) k_mlp_features(Geo g, const double* __res
             double u[NV], v[NV];
 #pragma unroll
             for (int c = 0; c < NV; c++) u[c] = base[c * vs + cell];
-            cons2prim<ND, MHD>(u, v, P);
-            q = v[S::IE];
+            cons2prim<ND, PH>(u, v, P);
+            q = pressure<ND, PH>(v, P);
           }
           s = s + q;
         }
@@ -116,8 +118,8 @@ __global__ void __launch_bounds__(128) k_mlp_features(Geo g, const double* __res
           double u[NV], v[NV];
 #pragma unroll
           for (int c = 0; c < NV; c++) u[c] = base[c * vs + cell];
-          cons2prim<ND, MHD>(u, v, P);
-          q = v[S::IE];
+          cons2prim<ND, PH>(u, v, P);
+          q = pressure<ND, PH>(v, P);
         }
         s = s + q;
       }
@@ -428,16 +430,19 @@ __global__ void __launch_bounds__(256) k_mlp_train(const uint16_t* __restrict__ 
 
 hipError_t launch_mlp_features(const Geo& g, const LaunchCfg& c, const double* U, const double* physp, uint16_t* X,
                                hipStream_t st) {
+  auto go = [&](auto nd) {
+    constexpr int ND = decltype(nd)::value;
+    if (c.phys == PH_MHD)
+      hipLaunchKernelGGL((k_mlp_features<ND, PH_MHD>), dim3(g.n), dim3(128), 0, st, g, U, physp, X);
+    else if (c.phys == PH_POLY)
+      hipLaunchKernelGGL((k_mlp_features<ND, PH_POLY>), dim3(g.n), dim3(128), 0, st, g, U, physp, X);
+    else
+      hipLaunchKernelGGL((k_mlp_features<ND, PH_EULER>), dim3(g.n), dim3(128), 0, st, g, U, physp, X);
+  };
   if (c.ndim == 2) {
-    if (c.mhd)
-      hipLaunchKernelGGL((k_mlp_features<2, true>), dim3(g.n), dim3(128), 0, st, g, U, physp, X);
-    else
-      hipLaunchKernelGGL((k_mlp_features<2, false>), dim3(g.n), dim3(128), 0, st, g, U, physp, X);
+    go(std::integral_constant<int, 2>{});
   } else if (c.ndim == 3) {
-    if (c.mhd)
-      hipLaunchKernelGGL((k_mlp_features<3, true>), dim3(g.n), dim3(128), 0, st, g, U, physp, X);
-    else
-      hipLaunchKernelGGL((k_mlp_features<3, false>), dim3(g.n), dim3(128), 0, st, g, U, physp, X);
+    go(std::integral_constant<int, 3>{});
   } else {
     return hipErrorInvalidValue;
   }

@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "internal.hpp"
+
 namespace amrv {
 
 enum { FLX_TVDLF = 0, FLX_HLL = 1, FLX_HLLC = 2 };
@@ -25,12 +27,14 @@ struct PhysParams {
   double gm1;   // gamma - 1
   double igm1;  // 1 / (gamma - 1)
   double ch;    // GLM cleaning speed (MHD)
+  double cad;   // c_ad of the polytrope
+  double gcad;  // gamma * c_ad
 };
 
-template <int ND, bool MHD>
+template <int ND, int PH>
 struct Sys {
-  static constexpr int NV = MHD ? 3 + 2 * ND : 2 + ND;
-  static constexpr int IE = 1 + ND;   // energy / pressure
+  static constexpr int NV = PH == PH_MHD ? 3 + 2 * ND : PH == PH_POLY ? 1 + ND : 2 + ND;
+  static constexpr int IE = 1 + ND;   // energy / pressure (Euler, MHD)
   static constexpr int IB = 2 + ND;   // first magnetic component
   static constexpr int IP = 2 + 2 * ND;  // psi
 };
@@ -38,11 +42,39 @@ struct Sys {
 __device__ __forceinline__ double dmin(double a, double b) { return a < b ? a : b; }
 __device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
 
+// rho^e of the polytrope: the exponents 1 and 2 are exact (rho*rho), others
+// go through pow (exponent 0 gives 1)
+__device__ __forceinline__ double rpow(double r, double e) { return e == 1.0 ? r : e == 2.0 ? r * r : pow(r, e); }
+
+// pressure of a primitive state: its own entry, or c_ad rho^gamma
+template <int ND, int PH>
+__device__ __forceinline__ double pressure(const double* v, const PhysParams& P) {
+  if constexpr (PH == PH_POLY)
+    return P.cad * rpow(v[0], P.gamma);
+  else
+    return v[Sys<ND, PH>::IE];
+}
+
+// rho <= 0, p <= 0 or NaN; the polytrope (whose pressure is positive with
+// rho): rho <= 0 or a velocity that is NaN or overflows
+template <int ND, int PH>
+__device__ __forceinline__ bool nonphysical(const double* v) {
+  if constexpr (PH == PH_POLY) {
+    double vv = v[1] * v[1];
+#pragma unroll
+    for (int d = 1; d < ND; d++) vv = vv + v[1 + d] * v[1 + d];
+    return !(v[0] > 0.0) || !(vv < __builtin_huge_val());
+  } else {
+    return !(v[0] > 0.0) || !(v[Sys<ND, PH>::IE] > 0.0);
+  }
+}
+
 // conserved -> primitive: 1/rho once, v = m * (1/rho),
-// p = (gamma-1) * ((E - (0.5*m.m)*(1/rho)) [- 0.5*B.B])
-template <int ND, bool MHD>
+// p = (gamma-1) * ((E - (0.5*m.m)*(1/rho)) [- 0.5*B.B]); the polytrope's
+// primitive state is (rho, v)
+template <int ND, int PH>
 __device__ __forceinline__ void cons2prim(const double* u, double* v, const PhysParams& P) {
-  using S = Sys<ND, MHD>;
+  using S = Sys<ND, PH>;
   const double rho = u[0];
   const double inv = 1.0 / rho;
   double mm = u[1] * u[1];
@@ -53,7 +85,9 @@ __device__ __forceinline__ void cons2prim(const double* u, double* v, const Phys
     v[1 + d] = u[1 + d] * inv;
     mm = mm + u[1 + d] * u[1 + d];
   }
-  if constexpr (!MHD) {
+  if constexpr (PH == PH_POLY) {
+    return;
+  } else if constexpr (PH == PH_EULER) {
     v[S::IE] = P.gm1 * (u[S::IE] - 0.5 * mm * inv);
   } else {
     double bb = u[S::IB] * u[S::IB];
@@ -69,9 +103,9 @@ __device__ __forceinline__ void cons2prim(const double* u, double* v, const Phys
 }
 
 // primitive -> conserved: m = rho v, E = p*(1/(gamma-1)) + (0.5*rho)*v.v [+ 0.5*B.B]
-template <int ND, bool MHD>
+template <int ND, int PH>
 __device__ __forceinline__ void prim2cons(const double* v, double* u, const PhysParams& P) {
-  using S = Sys<ND, MHD>;
+  using S = Sys<ND, PH>;
   const double rho = v[0];
   double vv = v[1] * v[1];
   u[0] = rho;
@@ -81,7 +115,9 @@ __device__ __forceinline__ void prim2cons(const double* v, double* u, const Phys
     u[1 + d] = rho * v[1 + d];
     vv = vv + v[1 + d] * v[1 + d];
   }
-  if constexpr (!MHD) {
+  if constexpr (PH == PH_POLY) {
+    return;
+  } else if constexpr (PH == PH_EULER) {
     u[S::IE] = v[S::IE] * P.igm1 + 0.5 * rho * vv;
   } else {
     double bb = v[S::IB] * v[S::IB];
@@ -97,13 +133,19 @@ __device__ __forceinline__ void prim2cons(const double* v, double* u, const Phys
 }
 
 // physical flux normal to direction n (compile-time)
-template <int ND, bool MHD, int N>
-__device__ __forceinline__ void phys_flux(const double* v, const double* u, double* F) {
-  using S = Sys<ND, MHD>;
+template <int ND, int PH, int N>
+__device__ __forceinline__ void phys_flux(const double* v, const double* u, double* F, const PhysParams& P) {
+  using S = Sys<ND, PH>;
   const double vn = v[1 + N];
-  const double p = v[S::IE];
+  const double p = pressure<ND, PH>(v, P);
   F[0] = u[1 + N];
-  if constexpr (!MHD) {
+  if constexpr (PH == PH_POLY) {
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+      F[1 + d] = u[1 + d] * vn;
+      if (d == N) F[1 + d] = F[1 + d] + p;
+    }
+  } else if constexpr (PH == PH_EULER) {
 #pragma unroll
     for (int d = 0; d < ND; d++) {
       F[1 + d] = u[1 + d] * vn;
@@ -132,11 +174,14 @@ __device__ __forceinline__ void phys_flux(const double* v, const double* u, doub
   }
 }
 
-// signal speed: sound speed sqrt((gamma*p)/rho), or the MHD fast speed along N
-template <int ND, bool MHD, int N>
+// signal speed: sound speed sqrt((gamma*p)/rho), the polytrope's
+// sqrt((gamma*c_ad) * rho^(gamma-1)), or the MHD fast speed along N
+template <int ND, int PH, int N>
 __device__ __forceinline__ double wave_speed(const double* v, const PhysParams& P) {
-  using S = Sys<ND, MHD>;
-  if constexpr (!MHD) {
+  using S = Sys<ND, PH>;
+  if constexpr (PH == PH_POLY) {
+    return sqrt(P.gcad * rpow(v[0], P.gm1));
+  } else if constexpr (PH == PH_EULER) {
     return sqrt(P.gamma * v[S::IE] / v[0]);
   } else {
     const double irho = 1.0 / v[0];
@@ -154,13 +199,13 @@ __device__ __forceinline__ double wave_speed(const double* v, const PhysParams& 
 }
 
 // runtime-direction wrapper
-template <int ND, bool MHD>
+template <int ND, int PH>
 __device__ __forceinline__ double wave_speed_dir(const double* v, int n, const PhysParams& P) {
-  if (n == 0) return wave_speed<ND, MHD, 0>(v, P);
+  if (n == 0) return wave_speed<ND, PH, 0>(v, P);
   if constexpr (ND > 1) {
-    if (n == 1) return wave_speed<ND, MHD, (ND > 1 ? 1 : 0)>(v, P);
+    if (n == 1) return wave_speed<ND, PH, (ND > 1 ? 1 : 0)>(v, P);
   }
-  if constexpr (ND > 2) return wave_speed<ND, MHD, (ND > 2 ? 2 : 0)>(v, P);
+  if constexpr (ND > 2) return wave_speed<ND, PH, (ND > 2 ? 2 : 0)>(v, P);
   return 0.0;
 }
 
@@ -213,10 +258,10 @@ __device__ __forceinline__ double minmod(double a, double b) {
 // quantity is the textbook one in a fixed order.
 template <int ND, int N>
 __device__ __forceinline__ void hllc_flux(const double* vl, const double* vr, double* F, const PhysParams& P) {
-  using S = Sys<ND, false>;
+  using S = Sys<ND, PH_EULER>;
   constexpr int NV = S::NV, ie = S::IE;
-  const double cl = wave_speed<ND, false, N>(vl, P);
-  const double cr = wave_speed<ND, false, N>(vr, P);
+  const double cl = wave_speed<ND, PH_EULER, N>(vl, P);
+  const double cr = wave_speed<ND, PH_EULER, N>(vr, P);
   const double unl = vl[1 + N], unr = vr[1 + N];
   const double sl = dmin(unl - cl, unr - cr);
   const double sr = dmax(unl + cl, unr + cr);
@@ -230,8 +275,8 @@ __device__ __forceinline__ void hllc_flux(const double* vl, const double* vr, do
 #pragma unroll
   for (int k = 0; k < NV; k++) vk[k] = left ? vl[k] : vr[k];
   double uk[NV], fk[NV];
-  prim2cons<ND, false>(vk, uk, P);
-  phys_flux<ND, false, N>(vk, uk, fk);
+  prim2cons<ND, PH_EULER>(vk, uk, P);
+  phys_flux<ND, PH_EULER, N>(vk, uk, fk, P);
   if (star) {
     // star state rho_K (S_K - u_K)/(S_K - S_M) (1, S_M, v_t, .); energy in the
     // star-pressure form E* = ((S_K - u_K) E_K - p_K u_K + p* S_M)/(S_K - S_M),
@@ -264,7 +309,7 @@ __device__ __forceinline__ void hllc_flux(const double* vl, const double* vr, do
 template <int ND, int N>
 __device__ __forceinline__ void hllc_mhd(const double* vl, const double* vr, const double* ul, const double* ur,
                                          const double* fl, const double* fr, double cl, double cr, double* F) {
-  using S = Sys<ND, true>;
+  using S = Sys<ND, PH_MHD>;
   constexpr int NV = S::NV, ie = S::IE, ib = S::IB;
   const double unl = vl[1 + N], unr = vr[1 + N];
   const double sl = dmin(unl - cl, unr - cr);
@@ -345,16 +390,17 @@ __device__ __forceinline__ void hllc_mhd(const double* vl, const double* vr, con
 
 // Approximate Riemann flux normal to N from left/right primitive face states.
 // vl/vr are modified only for MHD (normal field replaced by the GLM value).
-template <int ND, bool MHD, int FLUX, int N>
+template <int ND, int PH, int FLUX, int N>
 __device__ __forceinline__ void riemann(double* vl, double* vr, double* F, const PhysParams& P) {
-  using S = Sys<ND, MHD>;
+  using S = Sys<ND, PH>;
   constexpr int NV = S::NV;
-  if constexpr (FLUX == FLX_HLLC && !MHD) {
+  static_assert(!(PH == PH_POLY && FLUX == FLX_HLLC), "HLLC needs the energy equation");
+  if constexpr (FLUX == FLX_HLLC && PH == PH_EULER) {
     hllc_flux<ND, N>(vl, vr, F, P);
     return;
   } else {
     double bns = 0.0, psis = 0.0;
-    if constexpr (MHD) {
+    if constexpr (PH == PH_MHD) {
       constexpr int ib = S::IB + N, ip = S::IP;
       bns = 0.5 * (vl[ib] + vr[ib]) - 0.5 * (vr[ip] - vl[ip]) / P.ch;
       psis = 0.5 * (vl[ip] + vr[ip]) - 0.5 * P.ch * (vr[ib] - vl[ib]);
@@ -362,18 +408,18 @@ __device__ __forceinline__ void riemann(double* vl, double* vr, double* F, const
       vr[ib] = bns;
     }
     double ul[NV], ur[NV], fl[NV], fr[NV];
-    prim2cons<ND, MHD>(vl, ul, P);
-    prim2cons<ND, MHD>(vr, ur, P);
-    phys_flux<ND, MHD, N>(vl, ul, fl);
-    phys_flux<ND, MHD, N>(vr, ur, fr);
-    const double cl = wave_speed<ND, MHD, N>(vl, P);
-    const double cr = wave_speed<ND, MHD, N>(vr, P);
+    prim2cons<ND, PH>(vl, ul, P);
+    prim2cons<ND, PH>(vr, ur, P);
+    phys_flux<ND, PH, N>(vl, ul, fl, P);
+    phys_flux<ND, PH, N>(vr, ur, fr, P);
+    const double cl = wave_speed<ND, PH, N>(vl, P);
+    const double cr = wave_speed<ND, PH, N>(vr, P);
     const double unl = vl[1 + N], unr = vr[1 + N];
     if constexpr (FLUX == FLX_TVDLF) {
       const double cmax = dmax(fabs(unl) + cl, fabs(unr) + cr);
 #pragma unroll
       for (int k = 0; k < NV; k++) F[k] = 0.5 * ((fl[k] + fr[k]) - cmax * (ur[k] - ul[k]));
-    } else if constexpr (FLUX == FLX_HLLC) {
+    } else if constexpr (FLUX == FLX_HLLC && PH == PH_MHD) {
       hllc_mhd<ND, N>(vl, vr, ul, ur, fl, fr, cl, cr, F);
     } else {
       const double sl = dmin(unl - cl, unr - cr);
@@ -390,7 +436,7 @@ __device__ __forceinline__ void riemann(double* vl, double* vr, double* F, const
         for (int k = 0; k < NV; k++) F[k] = ((sr * fl[k] - sl * fr[k]) + (sl * sr) * (ur[k] - ul[k])) * ids;
       }
     }
-    if constexpr (MHD) {
+    if constexpr (PH == PH_MHD) {
       F[S::IB + N] = psis;
       F[S::IP] = P.ch * P.ch * bns;
     }
