@@ -193,17 +193,19 @@ __device__ __forceinline__ void cfl_fold(unsigned long long* red, unsigned long 
 // ghost slabs of coarse-fine faces
 // ---------------------------------------------------------------------------
 
-// one thread per transverse position t of a coarse-side slot, both ghost
-// layers; the two children along x of every restricted cell are adjacent in
-// memory (x is the fastest index, the pair starts at an even x), so they come
-// in one 16-byte load
+// one thread per coarse ghost cell (slot, transverse position t, layer); the
+// two children along x of every restricted cell are adjacent in memory (x is
+// the fastest index, the pair starts at an even x), so they come in one
+// 16-byte load, and the two layers of one position are neighbouring lanes:
+// on an x face the pair of lanes reads 32 contiguous bytes of each fine row
 template <int ND, int NV>
 __global__ void __launch_bounds__(WGS) k_restrict(Geo g, const double* __restrict__ U, const int32_t* __restrict__ list,
                                                   int nlist) {
   const long long i = (long long)blockIdx.x * WGS + threadIdx.x;
-  if (i >= (long long)nlist * g.T) return;
-  const int slot = list[i / g.T];
-  const int t = (int)(i % g.T);
+  if (i >= (long long)nlist * 2 * g.T) return;
+  const int slot = list[i / (2 * g.T)];
+  const int rem = (int)(i % (2 * g.T));
+  const int layer = rem & 1, t = rem >> 1;
   const int a1 = ND > 1 ? t % g.nx : 0, a2 = ND > 2 ? t / g.nx : 0;
   const int f = g.sface[slot];
   const int d = f >> 1, hi = f & 1;
@@ -212,41 +214,38 @@ __global__ void __launch_bounds__(WGS) k_restrict(Geo g, const double* __restric
   const int fine = g.sleaf[g.fslot[slot * 4 + q]];
   const size_t vs = (size_t)g.n * g.ncell;
   const double* base = U + (size_t)fine * g.ncell;
+  double acc[8][NV];
 #pragma unroll
-  for (int layer = 0; layer < 2; layer++) {
-    double acc[8][NV];
+  for (int o = 0; o < (1 << ND); o += 2) {
+    int c[3] = {0, 0, 0};
 #pragma unroll
-    for (int o = 0; o < (1 << ND); o += 2) {
-      int c[3] = {0, 0, 0};
-#pragma unroll
-      for (int e = 0; e < ND; e++) {
-        const int oe = (o >> e) & 1;
-        if (e == d)
-          c[e] = hi ? 2 * layer + oe : g.nx - 2 - 2 * layer + oe;
-        else
-          c[e] = (2 * ((e == (d == 0 ? 1 : 0)) ? a1 : a2) + oe) % g.nx;
-      }
-      const int cell = cell_index(g, c[0], c[1], c[2]);
-#pragma unroll
-      for (int v = 0; v < NV; v++) {
-        const double2 pr = *reinterpret_cast<const double2*>(base + v * vs + cell);
-        acc[o][v] = pr.x;
-        acc[o + 1][v] = pr.y;
-      }
+    for (int e = 0; e < ND; e++) {
+      const int oe = (o >> e) & 1;
+      if (e == d)
+        c[e] = hi ? 2 * layer + oe : g.nx - 2 - 2 * layer + oe;
+      else
+        c[e] = (2 * ((e == (d == 0 ? 1 : 0)) ? a1 : a2) + oe) % g.nx;
     }
-    const size_t out = (size_t)slot * NV * 2 * g.T + (size_t)layer * g.T + t;
+    const int cell = cell_index(g, c[0], c[1], c[2]);
 #pragma unroll
     for (int v = 0; v < NV; v++) {
-      double r;
-      if constexpr (ND == 1)
-        r = (acc[0][v] + acc[1][v]) * 0.5;
-      else if constexpr (ND == 2)
-        r = ((acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v])) * 0.25;
-      else
-        r = (((acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v])) + ((acc[4][v] + acc[5][v]) + (acc[6][v] + acc[7][v]))) *
-            0.125;
-      g.G[out + (size_t)v * 2 * g.T] = r;
+      const double2 pr = *reinterpret_cast<const double2*>(base + v * vs + cell);
+      acc[o][v] = pr.x;
+      acc[o + 1][v] = pr.y;
     }
+  }
+  const size_t out = (size_t)slot * NV * 2 * g.T + (size_t)layer * g.T + t;
+#pragma unroll
+  for (int v = 0; v < NV; v++) {
+    double r;
+    if constexpr (ND == 1)
+      r = (acc[0][v] + acc[1][v]) * 0.5;
+    else if constexpr (ND == 2)
+      r = ((acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v])) * 0.25;
+    else
+      r = (((acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v])) + ((acc[4][v] + acc[5][v]) + (acc[6][v] + acc[7][v]))) *
+          0.125;
+    g.G[out + (size_t)v * 2 * g.T] = r;
   }
 }
 
@@ -634,6 +633,7 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
     }
 
     double V0[NV], V1[NV], C2[NV], VLz[NV], Flo[NV], Cr[NV];
+    double Cq0[NV], Cq1[NV];  // conserved planes k, k+1 (the update operands)
     if constexpr (ND == 3) {
       // a coarse-fine +z face: its flux comes from the fine-flux slabs, staged
       // here once per leaf so that no plane issues a load it waits for at once
@@ -646,10 +646,10 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
       double vm2[NV], vm1[NV], c[NV], lo[NV], hi[NV], vlm1[NV];
       own_prim<ND, PH>(g, a.Uin, leaf, tx, ty, -2, vm2, P);
       own_prim<ND, PH>(g, a.Uin, leaf, tx, ty, -1, vm1, P);
-      load_strided<NV>(own, vs, c);
-      cons2prim<ND, PH>(c, V0, P);
-      load_strided<NV>(own + NB * NB, vs, c);
-      cons2prim<ND, PH>(c, V1, P);
+      load_strided<NV>(own, vs, Cq0);
+      cons2prim<ND, PH>(Cq0, V0, P);
+      load_strided<NV>(own + NB * NB, vs, Cq1);
+      cons2prim<ND, PH>(Cq1, V1, P);
       load_strided<NV>(own + 2 * NB * NB, vs, C2);
       muscl<NV, LIM>(vm2, vm1, V0, lo, vlm1);
       muscl<NV, LIM>(vm1, V0, V1, lo, hi);
@@ -666,18 +666,29 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
       cons2prim<ND, PH>(c, V0, P);
     }
     if (ring) load_strided<NV>(rptr, rvs, Cr);
-    // vmcnt(0) here and at the end of every plane: the loads of plane k+1 were
-    // issued during plane k, and an explicit full wait where it costs nothing
-    // keeps the compiler from placing conservative waits on the next plane's
-    // fresh prefetches at the top of the loop
+    // vmcnt(0) once before the plane loop: the first planes' loads are all
+    // needed at once.  Inside the loop the compiler's own waits apply: the
+    // loads of plane k+1 are issued during plane k, and the stores of plane
+    // k are not waited for before the next plane's work
     __builtin_amdgcn_s_waitcnt(0x0F70);
 
+    double Ui[NV], Uo[NV];
     for (int k = 0; k < NZ; k++) {
       double zd[NV];
       if constexpr (ND == 3) {
         // (1) z direction: prefetched plane k+2, slope of cell k+1, face k+1/2
         double V2[NV], VR1[NV], VL1[NV], Fhi[NV];
         cons2prim<ND, PH>(C2, V2, P);
+        if constexpr (!SPLIT) {
+          // the conserved values of plane k, loaded two planes ago for its
+          // primitives, stay in registers as the update operand (no reload)
+#pragma unroll
+          for (int v = 0; v < NV; v++) {
+            Ui[v] = Cq0[v];
+            Cq0[v] = Cq1[v];
+            Cq1[v] = C2[v];
+          }
+        }
         const int pn = k + 3;
         if (pn < NB)
           load_strided<NV>(own + pn * NB * NB, vs, C2);
@@ -714,10 +725,10 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
         for (int v = 0; v < NV; v++) sP[v][rdst] = w[v];
         if (k + 1 < NZ) load_strided<NV>(rptr + (k + 1) * rks, rvs, Cr);
       }
-      // operands of this plane's update (loaded early, consumed in phase 5)
-      double Ui[NV], Uo[NV];
+      // operands of this plane's update (loaded early, consumed in phase 5;
+      // in 3D the combined variant already holds U_in of the plane)
       if constexpr (!SPLIT) {
-        load_strided<NV>(own + k * NB * NB, vs, Ui);
+        if constexpr (ND != 3) load_strided<NV>(own + k * NB * NB, vs, Ui);
         if (a.stage > 1) load_strided<NV>(ownn + k * NB * NB, vs, Uo);
       }
       __syncthreads();
@@ -844,7 +855,6 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
         const double rd[3] = {rdx, rdy, rdz};
         cfl_cell<ND, PH>(Ui, P, rd, csmax, ccmax, cbad);
       }
-      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), see above
     }
   }
   if (a.cflred) cfl_fold(a.cflred, csmax, ccmax, cbad);
@@ -1158,7 +1168,7 @@ static inline unsigned blocks_for(long long work) { return (unsigned)((work + WG
 hipError_t launch_restrict(const Geo& g, const LaunchCfg& c, const double* U, const int32_t* list, int nlist,
                            hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  const unsigned nb = blocks_for((long long)nlist * g.T);
+  const unsigned nb = blocks_for((long long)nlist * 2 * g.T);
 #define BODY_R                                                                                                        \
   if (c.phys == PH_MHD) {                                                                                             \
     hipLaunchKernelGGL((k_restrict<ND, Sys<ND, PH_MHD>::NV>), dim3(nb), dim3(WGS), 0, st, g, U, list, nlist);         \
