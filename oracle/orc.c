@@ -456,14 +456,15 @@ static void riemann(const orc_forest* f, const double* vl_in, const double* vr_i
  * not zero at extrema (-2 < theta < 0) and not symmetric.  Written here
  * without the division: for b > 0 every candidate of H times b is a
  * candidate in a and b (p3 b = (a + 2b)/3), and b < 0 follows from
- * s(-a, -b) = -s(a, b); b = 0 gives 0 (H is bounded).  The smoothness switch
+ * s(-a, -b) = -s(a, b); b = 0 gives 0 (H is bounded), and so does a = 0
+ * (H(0) = 0).  The smoothness switch
  * of that paper (unlimited p3 where the differences are small against a
  * radius times the cell size) is not applied: the radius -> 0 case. */
 static double smaller(double x, double y) { return y < x ? y : x; }
 static double larger(double x, double y) { return y > x ? y : x; }
 
 static double cada(double a, double b) {
-  if (b == 0.0) return 0.0;
+  if (a == 0.0 || b == 0.0) return 0.0; /* H bounded, H(0) = 0 */
   const double sg = b > 0.0 ? 1.0 : -1.0;
   const double ap = sg * a, bp = sg * b;
   const double p3 = (ap + 2.0 * bp) / 3.0;

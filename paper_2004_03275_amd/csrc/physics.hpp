@@ -217,10 +217,11 @@ __device__ __forceinline__ double wave_speed_dir(const double* v, int n, const P
 // Cada and Torrilhon 2009, without its smoothness switch) is b H(a/b) with
 // H(t) = max(0, min(p3, max(-t/2, min(2t, p3, 1.6)))), p3 = (2 + t)/3: for
 // b > 0 the candidates scale by b exactly, b < 0 is the odd mirror, b = 0
-// gives 0; it keeps a slope at extrema (-2 < a/b < 0).
+// gives 0, as does a = 0; it keeps a slope at extrema (-2 < a/b < 0).
 template <int LIM>
 __device__ __forceinline__ double limiter(double a, double b) {
   if constexpr (LIM == LIM_CADA) {
+    if (a == 0.0 || b == 0.0) return 0.0;  // H bounded, H(0) = 0
     const double sg = b > 0.0 ? 1.0 : -1.0;
     const double ap = sg * a, bp = sg * b;
     const double p3 = (ap + 2.0 * bp) / 3.0;
@@ -231,7 +232,7 @@ __device__ __forceinline__ double limiter(double a, double b) {
     m = in > m ? in : m;
     m = m < p3 ? m : p3;
     m = m > 0.0 ? m : 0.0;
-    return b == 0.0 ? 0.0 : sg * m;
+    return sg * m;
   }
   if (a * b <= 0.0) return 0.0;
   if constexpr (LIM == LIM_MINMOD) {
