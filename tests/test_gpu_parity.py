@@ -160,6 +160,21 @@ def test_blast_small_other_limiters_match_oracle(lim):
     assert np.array_equal(G, R)
 
 
+@pytest.mark.parametrize("n,nb,flux,lim", [(1000, 1, W.TVDLF, W.MINMOD), (900, 3, W.HLLC, W.VANLEER),
+                                          (1000, 1, W.HLL, W.CADA), (68, 1, W.HLLC, W.KOREN)])
+def test_ragged_1d_blocks_match_oracle(n, nb, flux, lim):
+    """1D leaves whose length is not a multiple of the 256-cell chunk of a
+    workgroup (1000 = 3*256 + 232, 300, 68): the last chunk is partial."""
+    F = _gpu()
+    f, U = W.sod(n, nblocks=nb)
+    f.scheme.flux, f.scheme.limiter = flux, lim
+    R, dts = oracle.run(f, U, t_end=0.1)
+    G, used = F.run(f, U, t_end=0.1)
+    assert len(used) == len(dts)
+    _report(f"ragged 1D n={n} blocks={nb}", G, R, f)
+    assert np.array_equal(G, R)
+
+
 @pytest.mark.parametrize("lim", [W.MC, W.KOREN, W.CADA])
 def test_sod_other_limiters_match_oracle(lim):
     F = _gpu()
