@@ -175,14 +175,12 @@ def regrid_plan_leaves(forest, flags) -> tuple:
     flags = np.ascontiguousarray(flags, dtype=np.int8)
     if flags.shape != (forest.n,):
         raise ValueError("one flag per leaf")
+    # at most every leaf splits: one call with room for that
+    cap = forest.n << forest.scheme.ndim
     m = ctypes.c_int64()
-    L = lib()
-    rc = L.amrv_regrid_plan_leaves(ctypes.byref(cfg), forest.n, lev.ctypes.data, ijk.ctypes.data, flags.ctypes.data,
-                                   0, ctypes.byref(m), None, None)
-    if rc not in (OK, ENOMEM):
-        check(rc)
-    out_l = np.empty(max(m.value, 1), dtype=np.int32)
-    out_i = np.empty((max(m.value, 1), 3), dtype=np.int32)
-    check(L.amrv_regrid_plan_leaves(ctypes.byref(cfg), forest.n, lev.ctypes.data, ijk.ctypes.data, flags.ctypes.data,
-                                    m.value, ctypes.byref(m), out_l.ctypes.data, out_i.ctypes.data))
-    return out_l[:m.value], out_i[:m.value]
+    out_l = np.empty(cap, dtype=np.int32)
+    out_i = np.empty((cap, 3), dtype=np.int32)
+    check(lib().amrv_regrid_plan_leaves(ctypes.byref(cfg), forest.n, lev.ctypes.data, ijk.ctypes.data,
+                                        flags.ctypes.data, cap, ctypes.byref(m), out_l.ctypes.data,
+                                        out_i.ctypes.data))
+    return out_l[:m.value].copy(), out_i[:m.value].copy()

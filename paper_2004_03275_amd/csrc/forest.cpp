@@ -8,31 +8,10 @@
 #include "forest.hpp"
 
 #include <cstdio>
-#include <unordered_map>
+
+#include "leafhash.hpp"
 
 namespace amrv {
-
-namespace {
-
-struct Key {
-  int l;
-  int64_t c[3];
-};
-
-inline uint64_t pack(int l, int64_t i, int64_t j, int64_t k) {
-  return (uint64_t(l) << 60) ^ (uint64_t(i) << 40) ^ (uint64_t(j) << 20) ^ uint64_t(k);
-}
-
-struct Index {
-  std::unordered_map<uint64_t, int32_t> map;
-  int32_t find(int l, int64_t i, int64_t j, int64_t k) const {
-    if (l < 1 || i < 0 || j < 0 || k < 0) return -1;
-    auto it = map.find(pack(l, i, j, k));
-    return it == map.end() ? -1 : it->second;
-  }
-};
-
-}  // namespace
 
 int build_tables(const amrv_config& c, int64_t n, const int32_t* lev, const int32_t* ijk, Tables& t) {
   t = Tables();
@@ -85,8 +64,9 @@ int build_tables(const amrv_config& c, int64_t n, const int32_t* lev, const int3
   auto nblk = [&](int l, int d) -> int64_t { return d < nd ? (int64_t)c.base_blocks[d] << (l - 1) : 1; };
   auto periodic = [&](int d) { return c.bc[d][0] == AMRV_BC_PERIODIC; };
 
-  Index idx;
-  idx.map.reserve((size_t)n * 2);
+  for (int d = 0; d < nd; d++)
+    if (nblk(c.max_level, d) >= LeafHash::kMaxBlocks) return fail(AMRV_EINVAL, "domain too large in blocks");
+  LeafHash idx((size_t)n);
   t.lvl.assign(lev, lev + n);
   t.ijk.assign(ijk, ijk + 3 * n);
   for (int64_t b = 0; b < n; b++) {
@@ -94,8 +74,9 @@ int build_tables(const amrv_config& c, int64_t n, const int32_t* lev, const int3
     if (l < 1 || l > c.max_level) return fail(AMRV_EINVAL, "leaf level out of range");
     for (int d = 0; d < 3; d++)
       if (ijk[3 * b + d] < 0 || ijk[3 * b + d] >= nblk(l, d)) return fail(AMRV_EINVAL, "leaf coordinate out of range");
-    if (!idx.map.emplace(pack(l, ijk[3 * b], ijk[3 * b + 1], ijk[3 * b + 2]), (int32_t)b).second)
-      return fail(AMRV_EUNBALANCED, "duplicate leaf");
+    const uint64_t key = LeafHash::key(l, ijk[3 * b], ijk[3 * b + 1], ijk[3 * b + 2]);
+    if (idx.get(key) >= 0) return fail(AMRV_EUNBALANCED, "duplicate leaf");
+    idx.put(key, (int32_t)b);
   }
   // cover without overlap: no leaf below another, total volume = domain
   int64_t vol = 0, dom = 1;

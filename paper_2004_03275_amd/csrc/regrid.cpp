@@ -18,23 +18,20 @@
 #include "regrid.hpp"
 
 #include <algorithm>
-#include <unordered_map>
+
+#include "leafhash.hpp"
 
 namespace amrv {
 
 namespace {
 
-inline uint64_t leaf_key(int l, int64_t i, int64_t j, int64_t k) {
-  return (uint64_t(l) << 58) | (uint64_t(i) << 39) | (uint64_t(j) << 20) | uint64_t(k);
-}
-
 struct LeafIndex {
-  std::unordered_map<uint64_t, int32_t> m;
-  int32_t at(int l, const int64_t c[3]) const {
-    if (l < 1) return -1;
-    auto it = m.find(leaf_key(l, c[0], c[1], c[2]));
-    return it == m.end() ? -1 : it->second;
+  LeafHash h;
+  explicit LeafIndex(const Tables& t) : h((size_t)t.n) {
+    for (int64_t b = 0; b < t.n; b++)
+      h.put(LeafHash::key(t.lvl[b], t.ijk[3 * b], t.ijk[3 * b + 1], t.ijk[3 * b + 2]), (int32_t)b);
   }
+  int32_t at(int l, const int64_t c[3]) const { return h.find(l, c[0], c[1], c[2]); }
 };
 
 }  // namespace
@@ -43,21 +40,20 @@ int regrid_plan(const amrv_config& c, const Tables& t, const int8_t* flags, std:
                 std::vector<int32_t>& out_ijk, std::string& err) {
   const int nd = t.nd, nch = 1 << nd;
   const int64_t n = t.n;
-  LeafIndex ix;
-  ix.m.reserve((size_t)n * 2);
-  for (int64_t b = 0; b < n; b++)
-    ix.m.emplace(leaf_key(t.lvl[b], t.ijk[3 * b], t.ijk[3 * b + 1], t.ijk[3 * b + 2]), (int32_t)b);
+  const LeafIndex ix(t);
   auto blocks = [&](int l, int d) -> int64_t { return d < nd ? (int64_t)c.base_blocks[d] << (l - 1) : 1; };
 
   // touching leaves of every leaf: for each of the 3^d - 1 neighbouring block
   // positions, the leaf covering it (same level or one coarser) or the finer
   // leaves of that position adjacent to this leaf
-  std::vector<std::vector<int32_t>> touch((size_t)n);
+  std::vector<int64_t> toff((size_t)n + 1, 0);
+  std::vector<int32_t> tlist;
+  tlist.reserve((size_t)n * 32);
   int nofs = 1;
   for (int d = 0; d < nd; d++) nofs *= 3;
   for (int64_t b = 0; b < n; b++) {
     const int l = t.lvl[b];
-    std::vector<int32_t>& tb = touch[(size_t)b];
+    const size_t t0 = tlist.size();
     for (int q = 0; q < nofs; q++) {
       int o[3] = {0, 0, 0};
       bool zero = true;
@@ -83,7 +79,7 @@ int regrid_plan(const amrv_config& c, const Tables& t, const int8_t* flags, std:
         a = ix.at(l - 1, p);
       }
       if (a >= 0) {
-        tb.push_back(a);
+        tlist.push_back(a);
         continue;
       }
       for (int ch = 0; ch < nch; ch++) {
@@ -96,13 +92,19 @@ int regrid_plan(const amrv_config& c, const Tables& t, const int8_t* flags, std:
         }
         if (!adj) continue;
         const int32_t f = ix.at(l + 1, y);
-        if (f >= 0) tb.push_back(f);
+        if (f >= 0) tlist.push_back(f);
       }
     }
-    std::sort(tb.begin(), tb.end());
-    tb.erase(std::unique(tb.begin(), tb.end()), tb.end());
-    tb.erase(std::remove(tb.begin(), tb.end(), (int32_t)b), tb.end());
+    auto first = tlist.begin() + (std::ptrdiff_t)t0;
+    std::sort(first, tlist.end());
+    auto last = std::unique(first, tlist.end());
+    last = std::remove(first, last, (int32_t)b);
+    tlist.erase(last, tlist.end());
+    toff[(size_t)b + 1] = (int64_t)tlist.size();
   }
+  auto touching = [&](int32_t b) {
+    return std::make_pair(tlist.data() + toff[(size_t)b], tlist.data() + toff[(size_t)b + 1]);
+  };
 
   // steps 1-2: final level of every leaf after splitting
   std::vector<int32_t> fin(t.lvl.begin(), t.lvl.end());
@@ -115,11 +117,14 @@ int regrid_plan(const amrv_config& c, const Tables& t, const int8_t* flags, std:
   while (!work.empty()) {
     const int32_t b = work.back();
     work.pop_back();
-    for (int32_t a : touch[(size_t)b])
+    const auto tb = touching(b);
+    for (const int32_t* p = tb.first; p != tb.second; p++) {
+      const int32_t a = *p;
       if (t.lvl[a] == t.lvl[b] - 1 && fin[a] == t.lvl[a]) {
         fin[a] = t.lvl[a] + 1;
         work.push_back(a);
       }
+    }
   }
 
   // step 3: merges; head[b] = first member (list order) of b's merged group
@@ -136,14 +141,17 @@ int regrid_plan(const amrv_config& c, const Tables& t, const int8_t* flags, std:
       ok = mem[ch] >= 0 && flags[mem[ch]] < 0 && fin[mem[ch]] == l;
     }
     if (!ok) continue;
-    for (int ch = 0; ch < nch && ok; ch++)
-      for (int32_t a : touch[(size_t)mem[ch]]) {
+    for (int ch = 0; ch < nch && ok; ch++) {
+      const auto tm = touching(mem[ch]);
+      for (const int32_t* p = tm.first; p != tm.second; p++) {
+        const int32_t a = *p;
         if (std::find(mem, mem + nch, a) != mem + nch) continue;
         if (fin[a] > l) {
           ok = false;
           break;
         }
       }
+    }
     if (!ok) continue;
     const int32_t first = *std::min_element(mem, mem + nch);
     for (int ch = 0; ch < nch; ch++) head[mem[ch]] = first;
@@ -175,10 +183,7 @@ int regrid_plan(const amrv_config& c, const Tables& t, const int8_t* flags, std:
 
 int regrid_sources(const Tables& from, const Tables& to, std::vector<int32_t>& src, std::string& err) {
   const int nd = from.nd, nch = 1 << nd;
-  LeafIndex ix;
-  ix.m.reserve((size_t)from.n * 2);
-  for (int64_t b = 0; b < from.n; b++)
-    ix.m.emplace(leaf_key(from.lvl[b], from.ijk[3 * b], from.ijk[3 * b + 1], from.ijk[3 * b + 2]), (int32_t)b);
+  const LeafIndex ix(from);
   src.assign((size_t)to.n * XFER_STRIDE, -1);
   for (int64_t b = 0; b < to.n; b++) {
     const int l = to.lvl[b];

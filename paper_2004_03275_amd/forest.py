@@ -108,15 +108,14 @@ class GpuForest:
         flags = np.ascontiguousarray(flags, dtype=np.int8)
         if flags.shape != (self.forest.n,):
             raise ValueError("one flag per leaf")
+        # at most every leaf splits: one call with room for that
+        cap = self.forest.n << self.scheme.ndim
         m = ctypes.c_int64()
-        rc = N.lib().amrv_regrid_plan(self._h, flags.ctypes.data, 0, ctypes.byref(m), None, None)
-        if rc not in (N.OK, N.ENOMEM):
-            N.check(rc)
-        lev = np.empty(max(m.value, 1), dtype=np.int32)
-        ijk = np.empty((max(m.value, 1), 3), dtype=np.int32)
-        N.check(N.lib().amrv_regrid_plan(self._h, flags.ctypes.data, m.value, ctypes.byref(m), lev.ctypes.data,
+        lev = np.empty(cap, dtype=np.int32)
+        ijk = np.empty((cap, 3), dtype=np.int32)
+        N.check(N.lib().amrv_regrid_plan(self._h, flags.ctypes.data, cap, ctypes.byref(m), lev.ctypes.data,
                                          ijk.ctypes.data))
-        return lev[:m.value], ijk[:m.value]
+        return lev[:m.value].copy(), ijk[:m.value].copy()
 
     def regrid(self, flags) -> "GpuForest":
         """A new forest on the regridded leaves (same device and stream,
