@@ -9,7 +9,10 @@
  * Sec. 2.4), coarse-fine flux replacement for conservation (Sec. 1.1), SSP
  * Runge-Kutta stages (Sec. 2.1-2.4), the Courant time step (Sec. 2.1,
  * phys_get_cmax) and the Loehner refine/coarsen flags (Sec. 1.3).  Ideal MHD
- * uses HLL with mixed GLM divergence cleaning.
+ * uses HLL or HLLC (after Li 2005, Sec. 2.4) with mixed GLM divergence
+ * cleaning; the polytrope without energy equation (Sec. 2.2) gives the
+ * shallow water equations.  Limiters: minmod, van Leer, monotonized central,
+ * Koren and Cada's third-order limiter (Sec. 2.2-2.4).
  *
  * Every operation runs in hand-written HIP kernels for gfx950 in binary64.
  *
@@ -24,7 +27,7 @@
  *    of its own.  The HIP stream is borrowed; all work is enqueued on it.
  *  - State layout: conserved binary64 U[var][leaf][z][y][x], interior cells
  *    only, leaves in the caller's order.  Hydrodynamics: var = (rho, m_x,
- *    [m_y, m_z,] E); MHD: (rho, m.., E, B.., psi).
+ *    [m_y, m_z,] E); MHD: (rho, m.., E, B.., psi); polytrope: (rho, m..).
  */
 #ifndef AMRV_H
 #define AMRV_H
@@ -123,9 +126,10 @@ int amrv_set_state(amrv_forest* f, const double* U, int64_t n_doubles, int32_t o
 int amrv_get_state(amrv_forest* f, double* U, int64_t n_doubles, int32_t on_device);
 
 /* Courant time step dt = cfl / max_cells sum_d (|v_d| + c_d)/dx_d of the
- * current state (Sec. 2.1; c = sound speed, or fast speed for MHD).
- * Synchronises; returns AMRV_ENONPHYSICAL if any cell has rho <= 0, p <= 0 or
- * NaN.  For MHD it also records the GLM speed c_h = max |v_d| + c_f,d used by
+ * current state (Sec. 2.1; c = sound speed, the fast speed for MHD, or
+ * sqrt(gamma c_ad rho^(gamma-1)) for the polytrope).  Synchronises; returns
+ * AMRV_ENONPHYSICAL if any cell has rho <= 0, p <= 0 or NaN (the polytrope:
+ * rho <= 0 or a velocity that is NaN or overflows).  For MHD it also records the GLM speed c_h = max |v_d| + c_f,d used by
  * the following amrv_advance calls. */
 int amrv_max_dt(amrv_forest* f, double* dt_out);
 /* GLM cleaning speed recorded by the last amrv_max_dt (0 before any). */
