@@ -261,6 +261,26 @@ int capture_graph(amrv_forest* f) {
   return AMRV_OK;
 }
 
+// The tables of the last amrv_workspace_bytes call on this thread, kept for
+// the amrv_forest_create call that normally follows with the same leaf list
+// (the pair is how a caller sizes and then creates a forest; building the
+// tables once saves a pass over the leaves).  Reused only on an exact match
+// of the configuration and the leaf arrays.
+struct TableCache {
+  bool valid = false;
+  amrv_config cfg{};
+  std::vector<int32_t> lev, ijk;
+  Tables tab;
+};
+thread_local TableCache g_tables;
+
+bool cache_matches(const amrv_config& c, int64_t n, const int32_t* lev, const int32_t* ijk) {
+  const TableCache& k = g_tables;
+  return k.valid && std::memcmp(&k.cfg, &c, sizeof c) == 0 && (int64_t)k.lev.size() == n && lev && ijk &&
+         std::memcmp(k.lev.data(), lev, sizeof(int32_t) * (size_t)n) == 0 &&
+         std::memcmp(k.ijk.data(), ijk, sizeof(int32_t) * 3 * (size_t)n) == 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -272,13 +292,20 @@ size_t amrv_workspace_bytes(const amrv_config* cfg, int64_t n, const int32_t* le
     g_err = "null config";
     return 0;
   }
+  g_tables.valid = false;
   Tables t;
   const int rc = build_tables(*cfg, n, lev, ijk, t);
   if (rc) {
     g_err = t.err;
     return 0;
   }
-  return plan(t).total;
+  const size_t total = plan(t).total;
+  g_tables.cfg = *cfg;
+  g_tables.lev.assign(lev, lev + n);
+  g_tables.ijk.assign(ijk, ijk + 3 * n);
+  g_tables.tab = std::move(t);
+  g_tables.valid = true;
+  return total;
 }
 
 int amrv_forest_create(const amrv_config* cfg, int64_t n, const int32_t* lev, const int32_t* ijk, void* d_ws,
@@ -287,7 +314,13 @@ int amrv_forest_create(const amrv_config* cfg, int64_t n, const int32_t* lev, co
   *out = nullptr;
   amrv_forest* f = new amrv_forest();
   f->cfg = *cfg;
-  int rc = build_tables(*cfg, n, lev, ijk, f->tab);
+  int rc = AMRV_OK;
+  if (cache_matches(*cfg, n, lev, ijk)) {
+    f->tab = std::move(g_tables.tab);
+    g_tables.valid = false;
+  } else {
+    rc = build_tables(*cfg, n, lev, ijk, f->tab);
+  }
   if (rc) {
     std::string m = f->tab.err;
     delete f;

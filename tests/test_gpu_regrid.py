@@ -55,7 +55,17 @@ def _sod_blocks():
     return W.Forest(s, f.level, f.ijk), U
 
 
-CASES = {"blast3d": _blast_small, "amr2d": _amr2d, "sod1d": _sod_blocks}
+def _mhd_blast():
+    """The paper's MHD blast (2D, MHD-HLLC, Cada's limiter, GLM)."""
+    return W.mhd_blast(2, scheme=W.mhd_blast_scheme(2, base=2, max_level=3))
+
+
+def _dam_break():
+    """The paper's dam break (shallow-water polytrope, HLL, Koren)."""
+    return W.dam_break(base=4, max_level=3, buffer_cells=2.0)
+
+
+CASES = {"blast3d": _blast_small, "amr2d": _amr2d, "sod1d": _sod_blocks, "mhd2d": _mhd_blast, "dam2d": _dam_break}
 
 
 @pytest.mark.parametrize("case", list(CASES))
@@ -82,7 +92,7 @@ def test_regrid_matches_oracle(case):
         o, g = o2, g2
 
 
-@pytest.mark.parametrize("case", ["blast3d", "amr2d"])
+@pytest.mark.parametrize("case", ["blast3d", "amr2d", "mhd2d", "dam2d"])
 def test_steps_after_loehner_regrid_match_oracle(case):
     """Evolve, regrid on the Loehner flags of the evolved state, evolve on."""
     F = _F()
