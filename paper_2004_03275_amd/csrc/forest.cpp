@@ -10,6 +10,7 @@
 #include <cstdio>
 
 #include "leafhash.hpp"
+#include "parallel.hpp"
 
 namespace amrv {
 
@@ -78,19 +79,47 @@ int build_tables(const amrv_config& c, int64_t n, const int32_t* lev, const int3
     if (idx.get(key) >= 0) return fail(AMRV_EUNBALANCED, "duplicate leaf");
     idx.put(key, (int32_t)b);
   }
+  // The checks and tables below run over chunks of the leaf list on a few
+  // threads.  A chunk stops at its first failing leaf; the failure of the
+  // lowest chunk is reported, i.e. the first failing leaf in list order,
+  // as a serial pass would.
+  struct ChunkErr {
+    int code = AMRV_OK;
+    const char* msg = nullptr;
+  };
+  constexpr int MAXCH = 16;
+  ChunkErr errs[MAXCH];
+  bool ok = true;
+  auto first_error = [&]() -> int {
+    if (!ok) return fail(AMRV_ENOMEM, "host out of memory");
+    for (const ChunkErr& e : errs)
+      if (e.msg) return fail(e.code, e.msg);
+    return AMRV_OK;
+  };
+
   // cover without overlap: no leaf below another, total volume = domain
-  int64_t vol = 0, dom = 1;
+  int64_t dom = 1;
   for (int d = 0; d < nd; d++) dom *= c.base_blocks[d];
   dom <<= nd * (c.max_level - 1);
-  for (int64_t b = 0; b < n; b++) {
-    const int l = lev[b];
-    for (int a = 1; a < l; a++) {
-      const int sh = l - a;
-      if (idx.find(a, ijk[3 * b] >> sh, nd > 1 ? ijk[3 * b + 1] >> sh : 0, nd > 2 ? ijk[3 * b + 2] >> sh : 0) >= 0)
-        return fail(AMRV_EUNBALANCED, "leaf overlaps a coarser leaf");
+  int64_t vols[MAXCH] = {0};
+  parallel_chunks(n, [&](int ci, int64_t b0, int64_t b1) {
+    int64_t v = 0;
+    for (int64_t b = b0; b < b1; b++) {
+      const int l = lev[b];
+      for (int a = 1; a < l; a++) {
+        const int sh = l - a;
+        if (idx.find(a, ijk[3 * b] >> sh, nd > 1 ? ijk[3 * b + 1] >> sh : 0, nd > 2 ? ijk[3 * b + 2] >> sh : 0) >= 0) {
+          errs[ci] = {AMRV_EUNBALANCED, "leaf overlaps a coarser leaf"};
+          return;
+        }
+      }
+      v += (int64_t)1 << (nd * (c.max_level - l));
     }
-    vol += (int64_t)1 << (nd * (c.max_level - l));
-  }
+    vols[ci] = v;
+  }, &ok);
+  if (int rc = first_error()) return rc;
+  int64_t vol = 0;
+  for (int64_t v : vols) vol += v;
   if (vol != dom) return fail(AMRV_EUNBALANCED, "leaves do not cover the domain");
 
   // 2:1 balance over faces, edges and corners
@@ -102,101 +131,123 @@ int build_tables(const amrv_config& c, int64_t n, const int32_t* lev, const int3
   };
   int nofs = 1;
   for (int d = 0; d < nd; d++) nofs *= 3;
-  for (int64_t b = 0; b < n; b++) {
-    const int l = lev[b];
-    for (int q = 0; q < nofs; q++) {
-      int o[3] = {0, 0, 0}, r = q;
-      bool zero = true;
-      for (int d = 0; d < nd; d++) {
-        o[d] = r % 3 - 1;
-        r /= 3;
-        zero = zero && o[d] == 0;
-      }
-      if (zero) continue;
-      int64_t x[3] = {0, 0, 0};
-      bool in = true;
-      for (int d = 0; d < nd; d++) {
-        x[d] = ijk[3 * b + d] + o[d];
-        in = in && wrapc(d, x[d], nblk(l, d));
-      }
-      if (!in) continue;
-      if (idx.find(l, x[0], x[1], x[2]) >= 0) continue;
-      if (l > 1 && idx.find(l - 1, x[0] >> 1, x[1] >> 1, x[2] >> 1) >= 0) continue;
-      if (l + 1 > c.max_level) return fail(AMRV_EUNBALANCED, "forest is not 2:1 balanced");
-      for (int ch = 0; ch < (1 << nd); ch++) {
-        int64_t y[3] = {0, 0, 0};
-        bool touch = true;
+  parallel_chunks(n, [&](int ci, int64_t b0, int64_t b1) {
+    for (int64_t b = b0; b < b1; b++) {
+      const int l = lev[b];
+      for (int q = 0; q < nofs; q++) {
+        int o[3] = {0, 0, 0}, r = q;
+        bool zero = true;
         for (int d = 0; d < nd; d++) {
-          const int bit = (ch >> d) & 1;
-          if ((o[d] == 1 && bit) || (o[d] == -1 && !bit)) touch = false;
-          y[d] = 2 * x[d] + bit;
+          o[d] = r % 3 - 1;
+          r /= 3;
+          zero = zero && o[d] == 0;
         }
-        if (touch && idx.find(l + 1, y[0], y[1], y[2]) < 0) return fail(AMRV_EUNBALANCED, "forest is not 2:1 balanced");
+        if (zero) continue;
+        int64_t x[3] = {0, 0, 0};
+        bool in = true;
+        for (int d = 0; d < nd; d++) {
+          x[d] = ijk[3 * b + d] + o[d];
+          in = in && wrapc(d, x[d], nblk(l, d));
+        }
+        if (!in) continue;
+        if (idx.find(l, x[0], x[1], x[2]) >= 0) continue;
+        if (l > 1 && idx.find(l - 1, x[0] >> 1, x[1] >> 1, x[2] >> 1) >= 0) continue;
+        bool bad = l + 1 > c.max_level;
+        for (int ch = 0; ch < (1 << nd) && !bad; ch++) {
+          int64_t y[3] = {0, 0, 0};
+          bool touch = true;
+          for (int d = 0; d < nd; d++) {
+            const int bit = (ch >> d) & 1;
+            if ((o[d] == 1 && bit) || (o[d] == -1 && !bit)) touch = false;
+            y[d] = 2 * x[d] + bit;
+          }
+          bad = touch && idx.find(l + 1, y[0], y[1], y[2]) < 0;
+        }
+        if (bad) {
+          errs[ci] = {AMRV_EUNBALANCED, "forest is not 2:1 balanced"};
+          return;
+        }
       }
     }
-  }
+  }, &ok);
+  if (int rc = first_error()) return rc;
 
-  // faces: kind, neighbour, slot
+  // faces: kind and neighbour (per leaf), then slots in leaf and face order
   t.kind.assign((size_t)6 * n, (int8_t)NB_BND);
   t.nbr.assign((size_t)6 * n, -1);
   t.slot.assign((size_t)6 * n, -1);
-  for (int64_t b = 0; b < n; b++) {
-    const int l = lev[b];
-    for (int f = 0; f < 2 * nd; f++) {
-      const int d = f >> 1, s = (f & 1) ? 1 : -1;
-      int64_t x[3] = {ijk[3 * b], ijk[3 * b + 1], ijk[3 * b + 2]};
-      x[d] += s;
-      int8_t k;
-      int32_t nb;
-      if (!wrapc(d, x[d], nblk(l, d))) {
-        k = NB_BND;
-        nb = (int32_t)b;
-      } else if ((nb = idx.find(l, x[0], x[1], x[2])) >= 0) {
-        k = NB_SAME;
-      } else if (l > 1 && (nb = idx.find(l - 1, x[0] >> 1, x[1] >> 1, x[2] >> 1)) >= 0) {
-        k = NB_COARSER;
-      } else {
-        k = NB_FINER;
-        nb = -1;
-      }
-      t.kind[6 * b + f] = k;
-      t.nbr[6 * b + f] = nb;
-      if (k == NB_COARSER || k == NB_FINER) {
-        t.slot[6 * b + f] = (int32_t)t.sleaf.size();
-        t.sleaf.push_back((int32_t)b);
-        t.sface.push_back(f);
-        if (k == NB_FINER)
-          t.rlist.push_back(t.slot[6 * b + f]);
-        else
-          t.plist.push_back(t.slot[6 * b + f]);
+  parallel_chunks(n, [&](int, int64_t b0, int64_t b1) {
+    for (int64_t b = b0; b < b1; b++) {
+      const int l = lev[b];
+      for (int f = 0; f < 2 * nd; f++) {
+        const int d = f >> 1, s = (f & 1) ? 1 : -1;
+        int64_t x[3] = {ijk[3 * b], ijk[3 * b + 1], ijk[3 * b + 2]};
+        x[d] += s;
+        int8_t k;
+        int32_t nb;
+        if (!wrapc(d, x[d], nblk(l, d))) {
+          k = NB_BND;
+          nb = (int32_t)b;
+        } else if ((nb = idx.find(l, x[0], x[1], x[2])) >= 0) {
+          k = NB_SAME;
+        } else if (l > 1 && (nb = idx.find(l - 1, x[0] >> 1, x[1] >> 1, x[2] >> 1)) >= 0) {
+          k = NB_COARSER;
+        } else {
+          k = NB_FINER;
+          nb = -1;
+        }
+        t.kind[6 * b + f] = k;
+        t.nbr[6 * b + f] = nb;
       }
     }
-  }
+  }, &ok);
+  if (int rc = first_error()) return rc;
+  for (int64_t b = 0; b < n; b++)
+    for (int f = 0; f < 2 * nd; f++) {
+      const int8_t k = t.kind[6 * b + f];
+      if (k != NB_COARSER && k != NB_FINER) continue;
+      t.slot[6 * b + f] = (int32_t)t.sleaf.size();
+      t.sleaf.push_back((int32_t)b);
+      t.sface.push_back(f);
+      if (k == NB_FINER)
+        t.rlist.push_back(t.slot[6 * b + f]);
+      else
+        t.plist.push_back(t.slot[6 * b + f]);
+    }
   t.nslot = (int)t.sleaf.size();
   t.fslot.assign((size_t)4 * t.nslot, -1);
-  for (int s = 0; s < t.nslot; s++) {
-    const int64_t b = t.sleaf[s];
-    const int f = t.sface[s];
-    if (t.kind[6 * b + f] != NB_FINER) continue;
-    const int l = lev[b];
-    const int d = f >> 1, side = (f & 1) ? 1 : -1;
-    int64_t x[3] = {ijk[3 * b], ijk[3 * b + 1], ijk[3 * b + 2]};
-    x[d] += side;
-    wrapc(d, x[d], nblk(l, d));
-    const int e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;
-    const int nq = 1 << (nd - 1);
-    for (int q = 0; q < nq; q++) {
-      int64_t y[3] = {2 * x[0], nd > 1 ? 2 * x[1] : 0, nd > 2 ? 2 * x[2] : 0};
-      y[d] += side < 0 ? 1 : 0;
-      if (nd > 1) y[e1] += q & 1;
-      if (nd > 2) y[e2] += (q >> 1) & 1;
-      const int32_t fl = idx.find(l + 1, y[0], y[1], y[2]);
-      if (fl < 0) return fail(AMRV_EUNBALANCED, "finer neighbour is not a leaf");
-      const int back = 2 * d + (side < 0 ? 1 : 0);
-      if (t.kind[6 * fl + back] != NB_COARSER) return fail(AMRV_EUNBALANCED, "inconsistent coarse-fine face");
-      t.fslot[4 * s + q] = t.slot[6 * fl + back];
+  parallel_chunks(t.nslot, [&](int ci, int64_t s0, int64_t s1) {
+    for (int64_t s = s0; s < s1; s++) {
+      const int64_t b = t.sleaf[s];
+      const int f = t.sface[s];
+      if (t.kind[6 * b + f] != NB_FINER) continue;
+      const int l = lev[b];
+      const int d = f >> 1, side = (f & 1) ? 1 : -1;
+      int64_t x[3] = {ijk[3 * b], ijk[3 * b + 1], ijk[3 * b + 2]};
+      x[d] += side;
+      wrapc(d, x[d], nblk(l, d));
+      const int e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;
+      const int nq = 1 << (nd - 1);
+      for (int q = 0; q < nq; q++) {
+        int64_t y[3] = {2 * x[0], nd > 1 ? 2 * x[1] : 0, nd > 2 ? 2 * x[2] : 0};
+        y[d] += side < 0 ? 1 : 0;
+        if (nd > 1) y[e1] += q & 1;
+        if (nd > 2) y[e2] += (q >> 1) & 1;
+        const int32_t fl = idx.find(l + 1, y[0], y[1], y[2]);
+        if (fl < 0) {
+          errs[ci] = {AMRV_EUNBALANCED, "finer neighbour is not a leaf"};
+          return;
+        }
+        const int back = 2 * d + (side < 0 ? 1 : 0);
+        if (t.kind[6 * fl + back] != NB_COARSER) {
+          errs[ci] = {AMRV_EUNBALANCED, "inconsistent coarse-fine face"};
+          return;
+        }
+        t.fslot[4 * s + q] = t.slot[6 * fl + back];
+      }
     }
-  }
+  }, &ok);
+  if (int rc = first_error()) return rc;
   return AMRV_OK;
 }
 

@@ -17,8 +17,7 @@ class LeafHash {
   explicit LeafHash(size_t n) {
     size_t cap = 16;
     while (cap < 2 * n + 16) cap <<= 1;
-    keys_.assign(cap, kEmpty);
-    vals_.assign(cap, -1);
+    tab_.assign(cap, Entry{kEmpty, -1});
     mask_ = cap - 1;
   }
 
@@ -28,16 +27,16 @@ class LeafHash {
 
   void put(uint64_t k, int32_t v) {
     size_t h = slot(k);
-    while (keys_[h] != kEmpty && keys_[h] != k) h = (h + 1) & mask_;
-    keys_[h] = k;
-    vals_[h] = v;
+    while (tab_[h].key != kEmpty && tab_[h].key != k) h = (h + 1) & mask_;
+    tab_[h] = Entry{k, v};
   }
 
   // the leaf index, or -1
   int32_t get(uint64_t k) const {
     for (size_t h = slot(k);; h = (h + 1) & mask_) {
-      if (keys_[h] == k) return vals_[h];
-      if (keys_[h] == kEmpty) return -1;
+      const Entry& e = tab_[h];
+      if (e.key == k) return e.val;
+      if (e.key == kEmpty) return -1;
     }
   }
 
@@ -49,14 +48,17 @@ class LeafHash {
 
  private:
   static constexpr uint64_t kEmpty = ~uint64_t(0);
+  struct Entry {
+    uint64_t key;
+    int64_t val;  // 16-byte entries: key and value in one cache line
+  };
   size_t slot(uint64_t k) const {
     k ^= k >> 33;
     k *= 0xff51afd7ed558ccdull;
     k ^= k >> 33;
     return size_t(k) & mask_;
   }
-  std::vector<uint64_t> keys_;
-  std::vector<int32_t> vals_;
+  std::vector<Entry> tab_;
   size_t mask_ = 0;
 };
 

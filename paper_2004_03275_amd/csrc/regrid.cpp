@@ -20,6 +20,7 @@
 #include <algorithm>
 
 #include "leafhash.hpp"
+#include "parallel.hpp"
 
 namespace amrv {
 
@@ -46,62 +47,77 @@ int regrid_plan(const amrv_config& c, const Tables& t, const int8_t* flags, std:
   // touching leaves of every leaf: for each of the 3^d - 1 neighbouring block
   // positions, the leaf covering it (same level or one coarser) or the finer
   // leaves of that position adjacent to this leaf
+  // built in chunks of the leaf list on a few threads, then concatenated in
+  // leaf order (toff[b] .. toff[b+1] in tlist)
+  constexpr int MAXCH = 16;
+  std::vector<int32_t> clist[MAXCH];
   std::vector<int64_t> toff((size_t)n + 1, 0);
-  std::vector<int32_t> tlist;
-  tlist.reserve((size_t)n * 32);
   int nofs = 1;
   for (int d = 0; d < nd; d++) nofs *= 3;
-  for (int64_t b = 0; b < n; b++) {
-    const int l = t.lvl[b];
-    const size_t t0 = tlist.size();
-    for (int q = 0; q < nofs; q++) {
-      int o[3] = {0, 0, 0};
-      bool zero = true;
-      for (int d = 0, r = q; d < nd; d++, r /= 3) {
-        o[d] = r % 3 - 1;
-        zero = zero && o[d] == 0;
-      }
-      if (zero) continue;
-      int64_t x[3] = {0, 0, 0};
-      bool inside = true;
-      for (int d = 0; d < nd; d++) {
-        x[d] = t.ijk[3 * b + d] + o[d];
-        const int64_t ext = blocks(l, d);
-        if (x[d] < 0 || x[d] >= ext) {
-          if (c.bc[d][0] != AMRV_BC_PERIODIC) inside = false;
-          x[d] = ((x[d] % ext) + ext) % ext;
+  bool ok = true;
+  const int nchunks = parallel_chunks(n, [&](int ci, int64_t b0, int64_t b1) {
+    std::vector<int32_t>& tl = clist[ci];
+    tl.reserve((size_t)(b1 - b0) * 32);
+    for (int64_t b = b0; b < b1; b++) {
+      const int l = t.lvl[b];
+      const size_t t0 = tl.size();
+      for (int q = 0; q < nofs; q++) {
+        int o[3] = {0, 0, 0};
+        bool zero = true;
+        for (int d = 0, r = q; d < nd; d++, r /= 3) {
+          o[d] = r % 3 - 1;
+          zero = zero && o[d] == 0;
         }
-      }
-      if (!inside) continue;
-      int32_t a = ix.at(l, x);
-      if (a < 0) {
-        const int64_t p[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
-        a = ix.at(l - 1, p);
-      }
-      if (a >= 0) {
-        tlist.push_back(a);
-        continue;
-      }
-      for (int ch = 0; ch < nch; ch++) {
-        int64_t y[3] = {0, 0, 0};
-        bool adj = true;
+        if (zero) continue;
+        int64_t x[3] = {0, 0, 0};
+        bool inside = true;
         for (int d = 0; d < nd; d++) {
-          const int bit = (ch >> d) & 1;
-          if ((o[d] > 0 && bit) || (o[d] < 0 && !bit)) adj = false;
-          y[d] = 2 * x[d] + bit;
+          x[d] = t.ijk[3 * b + d] + o[d];
+          const int64_t ext = blocks(l, d);
+          if (x[d] < 0 || x[d] >= ext) {
+            if (c.bc[d][0] != AMRV_BC_PERIODIC) inside = false;
+            x[d] = ((x[d] % ext) + ext) % ext;
+          }
         }
-        if (!adj) continue;
-        const int32_t f = ix.at(l + 1, y);
-        if (f >= 0) tlist.push_back(f);
+        if (!inside) continue;
+        int32_t a = ix.at(l, x);
+        if (a < 0) {
+          const int64_t p[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
+          a = ix.at(l - 1, p);
+        }
+        if (a >= 0) {
+          tl.push_back(a);
+          continue;
+        }
+        for (int ch = 0; ch < nch; ch++) {
+          int64_t y[3] = {0, 0, 0};
+          bool adj = true;
+          for (int d = 0; d < nd; d++) {
+            const int bit = (ch >> d) & 1;
+            if ((o[d] > 0 && bit) || (o[d] < 0 && !bit)) adj = false;
+            y[d] = 2 * x[d] + bit;
+          }
+          if (!adj) continue;
+          const int32_t f = ix.at(l + 1, y);
+          if (f >= 0) tl.push_back(f);
+        }
       }
+      // duplicates (a coarser leaf touching along a face and its edges) and
+      // the leaf itself (periodic wrap of a one-block domain) may remain: the
+      // closure and the merge test below give the same result with them
+      toff[(size_t)b + 1] = (int64_t)(tl.size() - t0);  // count, summed below
     }
-    auto first = tlist.begin() + (std::ptrdiff_t)t0;
-    std::sort(first, tlist.end());
-    auto last = std::unique(first, tlist.end());
-    last = std::remove(first, last, (int32_t)b);
-    tlist.erase(last, tlist.end());
-    toff[(size_t)b + 1] = (int64_t)tlist.size();
+  }, &ok);
+  if (!ok) {
+    err = "host out of memory";
+    return AMRV_ENOMEM;
   }
+  std::vector<int32_t> tlist;
+  size_t total = 0;
+  for (int ci = 0; ci < nchunks; ci++) total += clist[ci].size();
+  tlist.reserve(total);
+  for (int ci = 0; ci < nchunks; ci++) tlist.insert(tlist.end(), clist[ci].begin(), clist[ci].end());
+  for (int64_t b = 0; b < n; b++) toff[(size_t)b + 1] += toff[(size_t)b];
   auto touching = [&](int32_t b) {
     return std::make_pair(tlist.data() + toff[(size_t)b], tlist.data() + toff[(size_t)b + 1]);
   };
@@ -129,9 +145,10 @@ int regrid_plan(const amrv_config& c, const Tables& t, const int8_t* flags, std:
 
   // step 3: merges; head[b] = first member (list order) of b's merged group
   std::vector<int32_t> head((size_t)n, -1);
+  std::vector<int8_t> seen((size_t)n, 0);  // the leaf's sibling group was examined
   for (int64_t b = 0; b < n; b++) {
     const int l = t.lvl[b];
-    if (flags[b] >= 0 || l <= 1 || fin[b] != l || head[b] >= 0) continue;
+    if (flags[b] >= 0 || l <= 1 || fin[b] != l || seen[b]) continue;
     int32_t mem[8];
     bool ok = true;
     for (int ch = 0; ch < nch && ok; ch++) {
@@ -141,6 +158,7 @@ int regrid_plan(const amrv_config& c, const Tables& t, const int8_t* flags, std:
       ok = mem[ch] >= 0 && flags[mem[ch]] < 0 && fin[mem[ch]] == l;
     }
     if (!ok) continue;
+    for (int ch = 0; ch < nch; ch++) seen[mem[ch]] = 1;
     for (int ch = 0; ch < nch && ok; ch++) {
       const auto tm = touching(mem[ch]);
       for (const int32_t* p = tm.first; p != tm.second; p++) {
