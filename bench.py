@@ -102,6 +102,8 @@ def main():
                     help="time steps as amrv_max_dt + amrv_advance (host-side dt) instead of amrv_advance_cfl")
     ap.add_argument("--limiter", default=None, choices=["minmod", "vanleer", "mc", "koren", "cada"],
                     help="override the workload's limiter")
+    ap.add_argument("--cada-radius", type=float, default=None,
+                    help="radius of Cada's smoothness switch (with --limiter cada)")
     ap.add_argument("--adaptive-steps", type=int, default=None,
                     help="also run this many steps from the initial state with regridding (default 20 on the "
                          "3D blast, 0 elsewhere)")
@@ -132,6 +134,8 @@ def main():
     if args.limiter:
         s.limiter = {"minmod": W.MINMOD, "vanleer": W.VANLEER, "mc": W.MC, "koren": W.KOREN,
                       "cada": W.CADA}[args.limiter]
+    if args.cada_radius is not None:
+        s.cada_radius = args.cada_radius
     cells = f.n * s.cells_per_block
     log(f"workload {desc}: {f.n} leaves {f.level_counts()}, {cells} cells")
 
@@ -392,6 +396,7 @@ def main():
             "physics": ["euler", "mhd_glm", "polytrope"][s.physics],
             "flux": ["tvdlf", "hll", "hllc"][s.flux],
             "limiter": ["minmod", "vanleer", "mc", "koren", "cada"][s.limiter],
+            "cada_radius": s.cada_radius,
             "rk_stages": s.rk_stages,
             "gamma": s.gamma,
             "cfl": s.cfl,

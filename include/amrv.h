@@ -79,7 +79,7 @@ typedef struct amrv_forest amrv_forest;
 /* Problem description (par-file keys of Sec. 1.3: block size, base domain
  * size in blocks, refine_max_level, xprobmin/xprobmax; Courant number of
  * Sec. 2.1; scheme choice of Sec. 1.3; Loehner tolerances of Sec. 1.3).
- * Field order is part of the ABI: 20 int32 followed by 15 double. */
+ * Field order is part of the ABI: 20 int32 followed by 16 double. */
 typedef struct {
   int32_t ndim;            /* 1, 2 or 3 */
   int32_t block_nx[3];     /* cells per block; 1D: any even nx >= 4; 2D/3D: 16 */
@@ -100,6 +100,8 @@ typedef struct {
   double lohner_w_rho, lohner_w_p;
   double glm_cr;               /* GLM damping length c_r */
   double cad;                  /* c_ad of the polytrope (> 0; read only for AMRV_POLYTROPE) */
+  double cada_radius;          /* r >= 0 of Cada's smoothness switch: with AMRV_CADA the unlimited
+                                  third-order slope (a+2b)/3 where a^2+b^2 <= (r dx)^2 (0: never) */
 } amrv_config;
 
 /* Device bytes the forest needs for this leaf list (three state copies,

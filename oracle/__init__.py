@@ -41,6 +41,7 @@ class _Config(ctypes.Structure):
         ("lohner_w_p", ctypes.c_double),
         ("glm_cr", ctypes.c_double),
         ("cad", ctypes.c_double),
+        ("cada_radius", ctypes.c_double),
     ]
 
 
@@ -66,7 +67,7 @@ def lib():
         L.orc_lohner_cells.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64]
         L.orc_regrid_plan.argtypes = [P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P, P]
         L.orc_regrid_transfer.argtypes = [P, P]
-        L.orc_limiter_value.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        L.orc_limiter_value.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.orc_limiter_value.restype = ctypes.c_double
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_set_threads.restype = None
@@ -112,12 +113,14 @@ def make_config(s) -> _Config:
     c.lohner_w_p = s.lohner_w_p
     c.glm_cr = s.glm_cr
     c.cad = s.cad
+    c.cada_radius = s.cada_radius
     return c
 
 
-def limiter_value(kind: int, a: float, b: float) -> float:
-    """The oracle's limited slope for backward / forward differences a, b."""
-    return float(lib().orc_limiter_value(int(kind), float(a), float(b)))
+def limiter_value(kind: int, a: float, b: float, thr2: float = 0.0) -> float:
+    """The oracle's limited slope for the differences a (away from the face)
+    and b (toward it); thr2 = (r dx)^2 of Cada's smoothness switch."""
+    return float(lib().orc_limiter_value(int(kind), float(a), float(b), float(thr2)))
 
 
 def set_threads(n: int):

@@ -453,7 +453,10 @@ static void riemann(const orc_forest* f, const double* vl_in, const double* vr_i
  * 2009, the limited function 'LimO3'): with theta = a/b the slope is
  * b H(theta), H(theta) = max(0, min(p3, max(-theta/2, min(2 theta, p3,
  * 1.6)))) and p3 = (2 + theta)/3 the unlimited third-order value.  It is
- * not zero at extrema (-2 < theta < 0) and not symmetric.  Written here
+ * not zero at extrema (-2 < theta < 0) and not symmetric.  With the
+ * smoothness switch of that paper (radius r > 0), the unlimited third-order
+ * slope (a + 2b)/3 is taken where a^2 + b^2 <= (r dx)^2 (the switch without
+ * its blending width); thr2 = (r dx)^2, 0 for no switch.  Written here
  * without the division: for b > 0 every candidate of H times b is a
  * candidate in a and b (p3 b = (a + 2b)/3), and b < 0 follows from
  * s(-a, -b) = -s(a, b); b = 0 gives 0 (H is bounded), and so does a = 0
@@ -463,7 +466,9 @@ static void riemann(const orc_forest* f, const double* vl_in, const double* vr_i
 static double smaller(double x, double y) { return y < x ? y : x; }
 static double larger(double x, double y) { return y > x ? y : x; }
 
-static double cada(double a, double b) {
+static double cada(double a, double b, double thr2) {
+  if (a == 0.0 && b == 0.0) return 0.0; /* flat: every branch gives 0 */
+  if (thr2 > 0.0 && a * a + b * b <= thr2) return (a + 2.0 * b) / 3.0;
   if (a == 0.0 || b == 0.0) return 0.0; /* H bounded, H(0) = 0 */
   const double sg = b > 0.0 ? 1.0 : -1.0;
   const double ap = sg * a, bp = sg * b;
@@ -473,8 +478,8 @@ static double cada(double a, double b) {
   return sg * r;
 }
 
-static double limit_ab(int kind, double a, double b) {
-  if (kind == LIM_CADA) return cada(a, b);
+static double limit_ab(int kind, double a, double b, double thr2) {
+  if (kind == LIM_CADA) return cada(a, b, thr2);
   if (a * b <= 0.0) return 0.0;
   if (kind == LIM_MINMOD) return fabs(a) < fabs(b) ? a : b;
   if (kind == LIM_MC || kind == LIM_KOREN) {
@@ -486,9 +491,11 @@ static double limit_ab(int kind, double a, double b) {
   return 2.0 * a * b / (a + b);
 }
 
-static double limiter(const orc_forest* f, double a, double b) { return limit_ab(f->c.limiter, a, b); }
+static double limiter(const orc_forest* f, double a, double b, double thr2) {
+  return limit_ab(f->c.limiter, a, b, thr2);
+}
 
-double orc_limiter_value(int kind, double a, double b) { return limit_ab(kind, a, b); }
+double orc_limiter_value(int kind, double a, double b, double thr2) { return limit_ab(kind, a, b, thr2); }
 
 static double minmod(double a, double b) {
   if (a * b <= 0.0) return 0.0;
@@ -503,6 +510,14 @@ static double minmod(double a, double b) {
 static double rdx(const orc_forest* f, int l, int d) {
   double dx = (f->c.xmax[d] - f->c.xmin[d]) / (double)ncells_dom(f, l, d);
   return 1.0 / dx;
+}
+
+/* (r dx)^2 of Cada's smoothness switch along d at level l; 0 without it */
+static double cada_thr2(const orc_forest* f, int l, int d) {
+  if (!(f->c.cada_radius > 0.0)) return 0.0;
+  double dx = (f->c.xmax[d] - f->c.xmin[d]) / (double)ncells_dom(f, l, d);
+  double rd = f->c.cada_radius * dx;
+  return rd * rd;
 }
 
 static int64_t pidx(const orc_forest* f, int i, int j, int k) {
@@ -584,6 +599,7 @@ int orc_forest_create(const orc_config* cfg, int64_t n, const int32_t* lev, cons
     return fail(ORC_EINVAL, "bad physics");
   if (c->flux < 0 || c->flux > 2) return fail(ORC_EINVAL, "bad flux");
   if (c->limiter < 0 || c->limiter > 4) return fail(ORC_EINVAL, "bad limiter");
+  if (!(c->cada_radius >= 0.0) || !(c->cada_radius < INFINITY)) return fail(ORC_EINVAL, "bad Cada radius");
   if (c->rk_stages != 2 && c->rk_stages != 3) return fail(ORC_EINVAL, "rk_stages must be 2 or 3");
   if (c->physics == PHYS_POLY) {
     if (!(c->gamma >= 1.0) || !(c->cad > 0.0) || !(c->cfl > 0.0))
@@ -933,7 +949,7 @@ static void padded_prim(const orc_forest* f, const double* W, double* P) {
  * of local cell x (x[d] in 0..nx): left state from cell x-e_d extrapolated by
  * half its limited slope, right state from cell x likewise (Sec. 2.2 limited
  * reconstruction in primitive variables). */
-static void face_flux(const orc_forest* f, const double* P, int d, const int x[3], double* F) {
+static void face_flux(const orc_forest* f, const double* P, int d, const int x[3], double thr2, double* F) {
   const int nv = f->nvar;
   int m2[3] = {x[0], x[1], x[2]}, m1[3] = {x[0], x[1], x[2]}, p1[3] = {x[0], x[1], x[2]};
   m2[d] -= 2;
@@ -946,8 +962,8 @@ static void face_flux(const orc_forest* f, const double* P, int d, const int x[3
     const double* p = P + (int64_t)k * f->npad;
     /* left state: cell m-1 toward its upper face (away: backward difference);
      * right state: cell m toward its lower face (away: forward difference) */
-    double sl = limiter(f, p[im1] - p[im2], p[i0] - p[im1]);
-    double sr = limiter(f, p[ip1] - p[i0], p[i0] - p[im1]);
+    double sl = limiter(f, p[im1] - p[im2], p[i0] - p[im1], thr2);
+    double sr = limiter(f, p[ip1] - p[i0], p[i0] - p[im1], thr2);
     vl[k] = p[im1] + 0.5 * sl;
     vr[k] = p[i0] - 0.5 * sr;
   }
@@ -1024,7 +1040,7 @@ static void record_fine_fluxes(const orc_forest* f, const double* S, int64_t b, 
           if (x[d] != 0) continue;
           x[d] = s < 0 ? 0 : f->nx[d];
           double F[NVMAX];
-          face_flux(f, w->P, d, x, F);
+          face_flux(f, w->P, d, x, cada_thr2(f, f->lev[b], d), F);
           int64_t t = tidx(f, d, x);
           for (int v = 0; v < nv; v++) out[v * nt + t] = F[v];
         }
@@ -1047,7 +1063,7 @@ static void update_leaf(const orc_forest* f, const double* S, const double* Un, 
         for (int i = 0; i < e[0]; i++) {
           int x[3] = {i, j, k};
           double F[NVMAX];
-          face_flux(f, w->P, d, x, F);
+          face_flux(f, w->P, d, x, cada_thr2(f, l, d), F);
           int64_t q = fidx(f, d, x);
           for (int v = 0; v < nv; v++) w->F[d][v * nf + q] = F[v];
         }

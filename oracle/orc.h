@@ -35,7 +35,7 @@ extern "C" {
 
 typedef struct orc_forest orc_forest;
 
-/* Field order is part of the contract: 20 int32 then 12 double. */
+/* Field order is part of the contract: 20 int32 then 13 double. */
 typedef struct {
   int32_t ndim;            /* 1, 2 or 3 */
   int32_t block_nx[3];     /* interior cells per block and dimension (1 if unused) */
@@ -55,6 +55,7 @@ typedef struct {
   double lohner_tol, lohner_coarsen_frac, lohner_eps, lohner_w_rho, lohner_w_p;
   double glm_cr;
   double cad;              /* c_ad of the polytrope */
+  double cada_radius;      /* r of Cada's smoothness switch (0: no switch) */
 } orc_config;
 
 int orc_forest_create(const orc_config* cfg, int64_t nleaves,
@@ -104,7 +105,7 @@ int orc_regrid_transfer(orc_forest* from, orc_forest* to);
 /* Test hook: the limited slope of a cell toward a face from the difference a
  * away from the face and b toward it (limiter 0 minmod, 1 van Leer,
  * 2 monotonized central, 3 Koren). */
-double orc_limiter_value(int limiter, double a, double b);
+double orc_limiter_value(int limiter, double a, double b, double thr2);
 void orc_set_threads(int n);
 int orc_get_threads(void);
 const char* orc_last_error(void);

@@ -57,6 +57,7 @@ class Config(ctypes.Structure):
         ("lohner_w_p", ctypes.c_double),
         ("glm_cr", ctypes.c_double),
         ("cad", ctypes.c_double),
+        ("cada_radius", ctypes.c_double),
     ]
 
 
@@ -162,6 +163,7 @@ def make_config(s) -> Config:
     c.lohner_w_p = s.lohner_w_p
     c.glm_cr = s.glm_cr
     c.cad = s.cad
+    c.cada_radius = s.cada_radius
     return c
 
 

@@ -406,6 +406,13 @@ int amrv_forest_create(const amrv_config* cfg, int64_t n, const int32_t* lev, co
   pp[PP_IGM1] = 1.0 / (cfg->gamma - 1.0);
   pp[PP_CAD] = cfg->cad;
   pp[PP_GCAD] = cfg->gamma * cfg->cad;
+  for (int l = 1; l <= cfg->max_level && l < MAXLEV; l++)
+    for (int d = 0; d < t.nd; d++)
+      if (cfg->cada_radius > 0.0) {
+        const double cells = (double)(((int64_t)cfg->base_blocks[d] << (l - 1)) * cfg->block_nx[d]);
+        const double rd = cfg->cada_radius * ((cfg->xmax[d] - cfg->xmin[d]) / cells);
+        pp[PP_CTHR + 3 * l + d] = rd * rd;
+      }
   double lp[LP_COUNT] = {0};
   lp[LP_EPS] = cfg->lohner_eps;
   lp[LP_WRHO] = cfg->lohner_w_rho;

@@ -32,6 +32,7 @@ int build_tables(const amrv_config& c, int64_t n, const int32_t* lev, const int3
       c.limiter != AMRV_CADA)
     return fail(AMRV_EINVAL, "unknown limiter");
   if (c.rk_stages != 2 && c.rk_stages != 3) return fail(AMRV_EINVAL, "rk_stages must be 2 or 3");
+  if (!(c.cada_radius >= 0.0) || !(c.cada_radius < 1e300)) return fail(AMRV_EINVAL, "bad Cada radius");
   if (c.physics == AMRV_POLYTROPE) {
     if (!(c.gamma >= 1.0) || !(c.cad > 0.0) || !(c.cfl > 0.0))
       return fail(AMRV_EINVAL, "the polytrope needs gamma >= 1, c_ad > 0 and a positive cfl");

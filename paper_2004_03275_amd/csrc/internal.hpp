@@ -107,9 +107,10 @@ constexpr int CNT_QUEUES = 32, CNT_ERR = 40, CNT_TAKEN = 41, CNT_COUNT = 64;
 
 // device parameter block (written once per forest, plus dt / ch per step)
 // layout: [0] gamma [1] gm1 [2] igm1 [3] ch [4] dt [5] glm damping factor
-// [6] time [7] c_ad [8] gamma * c_ad
+// [6] time [7] c_ad [8] gamma * c_ad; from [16]: (r dx)^2 of Cada's smoothness
+// switch per level and dimension, [16 + 3 l + d] (0: none)
 constexpr int PP_GAMMA = 0, PP_GM1 = 1, PP_IGM1 = 2, PP_CH = 3, PP_DT = 4, PP_DAMP = 5, PP_T = 6, PP_CAD = 7,
-              PP_GCAD = 8, PP_COUNT = 16;
+              PP_GCAD = 8, PP_CTHR = 16, PP_COUNT = PP_CTHR + 3 * MAXLEV;
 // Loehner parameters: [0] eps [1] w_rho [2] w_p [3] tol [4] coarsen tol
 constexpr int LP_EPS = 0, LP_WRHO = 1, LP_WP = 2, LP_TOL = 3, LP_CTOL = 4, LP_COUNT = 8;
 

@@ -341,8 +341,9 @@ __global__ void __launch_bounds__(WGS) k_prolong_flux(Geo g, const double* __res
     V3[v] = hi ? W[3][v] : W[0][v];
   }
   double lo_[NV], vl[NV], vr[NV], hi_[NV], F[NV];
-  muscl<NV, LIM>(V0, V1, V2, lo_, vl);
-  muscl<NV, LIM>(V1, V2, V3, vr, hi_);
+  const double th = pp[PP_CTHR + 3 * g.lvl[fine] + d];
+  muscl<NV, LIM>(V0, V1, V2, lo_, vl, th);
+  muscl<NV, LIM>(V1, V2, V3, vr, hi_, th);
   riemann_dir<ND, PH, FLUX>(d, vl, vr, F, P);
   const size_t fb = (size_t)slot * NV * g.T + t;
 #pragma unroll
@@ -582,6 +583,9 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
 
     const int lvl = g.lvl[leaf];
     const double rdx = g.rdx[lvl][0], rdy = g.rdx[lvl][1], rdz = ND == 3 ? g.rdx[lvl][2] : 0.0;
+    // (r dx)^2 of Cada's smoothness switch per direction (0: none)
+    const double thx = pp[PP_CTHR + 3 * lvl], thy = pp[PP_CTHR + 3 * lvl + 1],
+                 thz = ND == 3 ? pp[PP_CTHR + 3 * lvl + 2] : 0.0;
     int kinds[2 * ND];
 #pragma unroll
     for (int f = 0; f < 2 * ND; f++) kinds[f] = g.kind[leaf * 6 + f];
@@ -651,8 +655,8 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
       load_strided<NV>(own + NB * NB, vs, Cq1);
       cons2prim<ND, PH>(Cq1, V1, P);
       load_strided<NV>(own + 2 * NB * NB, vs, C2);
-      muscl<NV, LIM>(vm2, vm1, V0, lo, vlm1);
-      muscl<NV, LIM>(vm1, V0, V1, lo, hi);
+      muscl<NV, LIM>(vm2, vm1, V0, lo, vlm1, thz);
+      muscl<NV, LIM>(vm1, V0, V1, lo, hi, thz);
       if (kinds[4] == NB_SAME || kinds[4] == NB_BND) {
         riemann<ND, PH, FLUX, (ND == 3 ? 2 : 0)>(vlm1, lo, Flo, P);
       } else {
@@ -694,7 +698,7 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
           load_strided<NV>(own + pn * NB * NB, vs, C2);
         else if (pn < NB + 2)
           load_strided<NV>(zptr + (pn - NB) * zls, zvs, C2);
-        muscl<NV, LIM>(V0, V1, V2, VR1, VL1);
+        muscl<NV, LIM>(V0, V1, V2, VR1, VL1, thz);
         if (k == NB - 1 && !(kinds[5] == NB_SAME || kinds[5] == NB_BND)) {
 #pragma unroll
           for (int v = 0; v < NV; v++) Fhi[v] = sZF[v][tid];
@@ -754,10 +758,11 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
             // the half slope, formed once per cell: both face states of the
             // cell add or subtract the same product 0.5*phi
             const double sa = v0 - vm, sb = vp - v0;
-            const double sl = 0.5 * limiter<LIM>(sa, sb);
+            const double th = yd ? thy : thx;
+            const double sl = 0.5 * limiter<LIM>(sa, sb, th);
             if constexpr (ASYM) {
               sS[0][v][u] = sl;
-              sS[1][v][u] = 0.5 * limiter<LIM>(sb, sa);
+              sS[1][v][u] = 0.5 * limiter<LIM>(sb, sa, th);
             } else if (!yd) {
               sSx[v][u] = sl;
             } else {
@@ -905,7 +910,7 @@ __global__ void __launch_bounds__(WGS) k_stage_line(Geo g, StageArgs a, const do
       v0[v] = sP[v][t + 1];
       vp[v] = sP[v][t + 2];
     }
-    muscl<NV, LIM>(vm, v0, vp, lo, hi);
+    muscl<NV, LIM>(vm, v0, vp, lo, hi, pp[PP_CTHR + 3 * lvl]);
 #pragma unroll
     for (int v = 0; v < NV; v++) {
       sL[v][t] = hi[v];

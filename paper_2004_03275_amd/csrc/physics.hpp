@@ -217,10 +217,14 @@ __device__ __forceinline__ double wave_speed_dir(const double* v, int n, const P
 // Cada and Torrilhon 2009, without its smoothness switch) is b H(a/b) with
 // H(t) = max(0, min(p3, max(-t/2, min(2t, p3, 1.6)))), p3 = (2 + t)/3: for
 // b > 0 the candidates scale by b exactly, b < 0 is the odd mirror, b = 0
-// gives 0, as does a = 0; it keeps a slope at extrema (-2 < a/b < 0).
+// gives 0, as does a = 0; it keeps a slope at extrema (-2 < a/b < 0).  With
+// that paper's smoothness switch (thr2 = (r dx)^2 > 0) it is the unlimited
+// third-order slope (a + 2b)/3 where a^2 + b^2 <= thr2.
 template <int LIM>
-__device__ __forceinline__ double limiter(double a, double b) {
+__device__ __forceinline__ double limiter(double a, double b, double thr2 = 0.0) {
   if constexpr (LIM == LIM_CADA) {
+    if (a == 0.0 && b == 0.0) return 0.0;  // flat: every branch gives 0
+    if (thr2 > 0.0 && a * a + b * b <= thr2) return (a + 2.0 * b) / 3.0;
     if (a == 0.0 || b == 0.0) return 0.0;  // H bounded, H(0) = 0
     const double sg = b > 0.0 ? 1.0 : -1.0;
     const double ap = sg * a, bp = sg * b;
@@ -449,14 +453,15 @@ __device__ __forceinline__ void riemann(double* vl, double* vr, double* F, const
 // lo = v0 - 0.5*phi(forward, backward) (lower face; the same phi unless the
 // limiter is asymmetric)
 template <int NV, int LIM>
-__device__ __forceinline__ void muscl(const double* vm, const double* v0, const double* vp, double* lo, double* hi) {
+__device__ __forceinline__ void muscl(const double* vm, const double* v0, const double* vp, double* lo, double* hi,
+                                      double thr2 = 0.0) {
 #pragma unroll
   for (int k = 0; k < NV; k++) {
     const double a = v0[k] - vm[k], b = vp[k] - v0[k];
-    const double s = limiter<LIM>(a, b);
+    const double s = limiter<LIM>(a, b, thr2);
     hi[k] = v0[k] + 0.5 * s;
     if constexpr (lim_asym<LIM>())
-      lo[k] = v0[k] - 0.5 * limiter<LIM>(b, a);
+      lo[k] = v0[k] - 0.5 * limiter<LIM>(b, a, thr2);
     else
       lo[k] = v0[k] - 0.5 * s;
   }

@@ -67,6 +67,7 @@ class Scheme:
     lohner_w_p: float = 0.5
     glm_cr: float = 0.18
     cad: float = 1.0  # c_ad of the polytrope
+    cada_radius: float = 0.0  # r of Cada's smoothness switch (0: the limited function alone)
 
     def __post_init__(self):
         nd = self.ndim

@@ -175,6 +175,35 @@ def test_ragged_1d_blocks_match_oracle(n, nb, flux, lim):
     assert np.array_equal(G, R)
 
 
+@pytest.mark.parametrize("case", ["blast3d", "kh2d", "sod1d", "mhd2d"])
+def test_cada_switch_matches_oracle(case):
+    """Cada's limiter with its smoothness switch (the radius scales with each
+    level's cell size): exercised in the 3D, 2D, 1D and MHD kernels and in the
+    fine-side fluxes of coarse-fine faces."""
+    F = _gpu()
+    if case == "blast3d":
+        f, U = _blast_small()
+        f.scheme.limiter, f.scheme.cada_radius = W.CADA, 0.5
+        steps = 3
+    elif case == "kh2d":
+        f, U = W.kh(4)
+        f.scheme.limiter, f.scheme.cada_radius = W.CADA, 0.3
+        steps = 20
+    elif case == "sod1d":
+        f, U = W.sod(1000, nblocks=4)
+        f.scheme.limiter, f.scheme.cada_radius = W.CADA, 0.5
+        steps = 60
+    else:
+        s = W.mhd_blast_scheme(2, base=2, max_level=3)
+        s.cada_radius = 0.2
+        f, U = W.mhd_blast(2, scheme=s)
+        steps = 6
+    R, dts = oracle.run(f, U, steps=steps)
+    G, _ = F.run(f, U, dts=dts)
+    _report(f"cada switch {case}", G, R, f)
+    assert np.array_equal(G, R)
+
+
 @pytest.mark.parametrize("lim", [W.MC, W.KOREN, W.CADA])
 def test_sod_other_limiters_match_oracle(lim):
     F = _gpu()

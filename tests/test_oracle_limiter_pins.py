@@ -9,8 +9,11 @@ properties of a TVD limiter (Koren's is deliberately asymmetric), the
 central branch of the monotonized central limiter, the third-order branch
 of Koren's, convergence of a smooth 1D entropy wave in the full scheme, and
 mirror symmetry of a shock tube with the asymmetric limiters, the published
-ratio form of Cada's limiter, and exact face values of the third-order
-limiters on a quadratic profile."""
+ratio form of Cada's limiter, exact face values of the third-order
+limiters on a quadratic profile, and Cada's smoothness switch (the unlimited
+third-order slope where both differences are small against a radius times
+the cell size): its values, third-order convergence on the smooth wave and
+limited shock tubes."""
 import numpy as np
 import pytest
 
@@ -196,3 +199,67 @@ def test_mirrored_shock_tube_with_asymmetric_limiters(lim):
     Bm[1] = -Bm[1]
     assert np.abs(A - Bm).max() <= 1e-12 * np.abs(A).max()
     assert oracle.limiter_value(lim, 1.0, 3.0) != oracle.limiter_value(lim, 3.0, 1.0)
+
+
+# ---------------------------------------------------------------------------
+# Cada's smoothness switch: thr2 = (r dx)^2
+# ---------------------------------------------------------------------------
+
+
+def test_cada_switch_values():
+    rng = np.random.default_rng(11)
+    for _ in range(4000):
+        a, b = rng.normal(size=2) * np.exp(rng.uniform(-4, 4, 2))
+        thr2 = float(np.exp(rng.uniform(-8, 8)))
+        p = oracle.limiter_value(CA, a, b, thr2)
+        if a * a + b * b <= thr2:
+            assert p == (a + 2.0 * b) / 3.0          # unlimited, also at extrema
+        else:
+            assert p == oracle.limiter_value(CA, a, b)
+    # at an extremum the switch keeps the third-order slope, LimO3 a smaller one
+    assert oracle.limiter_value(CA, -1.0, 2.0, 10.0) == 1.0
+    assert oracle.limiter_value(CA, -1.0, 2.0) == 0.5
+    assert oracle.limiter_value(CA, 0.0, 3.0, 10.0) == 2.0
+    assert oracle.limiter_value(CA, 0.0, 3.0) == 0.0
+    # other limiters ignore it
+    for kind in (MM, VL, MC, KO):
+        assert oracle.limiter_value(kind, -1.0, 2.0, 10.0) == oracle.limiter_value(kind, -1.0, 2.0)
+
+
+def _entropy_wave_r(n, r, t_end=0.25):
+    s = W.Scheme(ndim=1, block_nx=(n // 4,), base_blocks=(4,), max_level=1, flux=W.HLLC, limiter=CA,
+                 rk_stages=3, cfl=0.5, bc=W.PERIODIC, cada_radius=r)
+    f = W.uniform_forest(s)
+    (x,) = W.cell_centres(f)
+    h = 1.0 / n
+    sav = lambda y: (np.cos(2 * np.pi * (y - h / 2)) - np.cos(2 * np.pi * (y + h / 2))) / (2 * np.pi * h)
+    U = W.state_from_primitive(f, 1.0 + 0.2 * sav(x), [np.ones_like(x)], np.ones_like(x))
+    R, _ = oracle.run(f, U, t_end=t_end)
+    return float(np.abs(R[0] - (1.0 + 0.2 * sav(x - t_end))).mean())
+
+
+def test_cada_switch_gives_third_order_on_a_smooth_wave():
+    """The limited function clips the slopes next to the wave's extrema
+    (about second order); with the switch the scheme is third order."""
+    e = [_entropy_wave_r(n, 1.0) for n in (64, 128, 256)]
+    orders = [np.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert min(orders) > 2.9, (e, orders)
+    assert e[2] < 0.05 * _entropy_wave_r(256, 0.0)
+
+
+def test_cada_switch_still_limits_a_shock_tube():
+    """Across the Sod tube's jumps the differences exceed any small radius:
+    the solution stays as close to the exact one as without the switch."""
+    from oracle import exact_riemann as E
+
+    def err(r):
+        f, U = W.sod(512, nblocks=8)
+        f.scheme.limiter, f.scheme.cada_radius = CA, r
+        R, _ = oracle.run(f, U, t_end=0.2)
+        (x,) = W.cell_centres(f)
+        rho, _, _ = E.sod_profile(x.ravel(), 0.2)
+        return float(np.abs(R[0].ravel() - rho).mean()), float(R[0].min())
+
+    e0, m0 = err(0.0)
+    e1, m1 = err(0.5)
+    assert e1 < 1.1 * e0 and m1 > 0.1, (e0, e1, m1)
