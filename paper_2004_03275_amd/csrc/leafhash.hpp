@@ -17,7 +17,7 @@ class LeafHash {
   explicit LeafHash(size_t n) {
     size_t cap = 16;
     while (cap < 2 * n + 16) cap <<= 1;
-    tab_.assign(cap, Entry{kEmpty, -1});
+    tab_.assign(cap, Entry{kEmpty, -1, 0});
     mask_ = cap - 1;
   }
 
@@ -28,7 +28,7 @@ class LeafHash {
   void put(uint64_t k, int32_t v) {
     size_t h = slot(k);
     while (tab_[h].key != kEmpty && tab_[h].key != k) h = (h + 1) & mask_;
-    tab_[h] = Entry{k, v};
+    tab_[h] = Entry{k, v, 0};
   }
 
   // the leaf index, or -1
@@ -48,9 +48,10 @@ class LeafHash {
 
  private:
   static constexpr uint64_t kEmpty = ~uint64_t(0);
-  struct Entry {
+  struct Entry {  // 16 bytes: key and value in one cache line
     uint64_t key;
-    int64_t val;  // 16-byte entries: key and value in one cache line
+    int32_t val;
+    int32_t unused;
   };
   size_t slot(uint64_t k) const {
     k ^= k >> 33;
