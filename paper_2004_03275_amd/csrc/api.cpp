@@ -56,7 +56,9 @@ Layout plan(const Tables& t) {
   };
   const size_t state = sizeof(double) * (size_t)t.nvar * (size_t)t.n * (size_t)t.ncell;
   for (int i = 0; i < 3; i++) L.off_U[i] = take(state);
-  L.off_G = take(sizeof(double) * (size_t)std::max(1, t.nslot) * t.nvar * 2 * t.T);
+  // three ghost-slab buffers: stage s of a step reads buffer s-1 and, in the
+  // 3D combined variant, writes the restriction of its result to buffer s mod S
+  L.off_G = take(3 * sizeof(double) * (size_t)std::max(1, t.nslot) * t.nvar * 2 * t.T);
   L.off_FF = take(sizeof(double) * (size_t)std::max(1, t.nslot) * t.nvar * t.T);
   L.off_lvl = take(sizeof(int32_t) * t.n);
   L.off_ijk = take(sizeof(int32_t) * 3 * t.n);
@@ -120,6 +122,8 @@ struct amrv_forest {
   std::string tune_report;  // the last autotune's timing table
   std::vector<int32_t> xfer_host;  // regrid sources while their upload is in flight
   bool fold_valid = false;         // the reduction words hold the Courant fold of U^n
+  double* Gb[3] = {nullptr, nullptr, nullptr};  // ghost-slab buffers (geo.G = Gb[0])
+  bool rvalid = false;             // Gb[0]'s coarse-side slots hold the restriction of U^n
 };
 
 namespace {
@@ -150,15 +154,23 @@ int stage_grid(const amrv_forest* f, int mode) {
   return f->xcd ? 8 * (int)((t.n + 7) / 8) : (int)t.n;
 }
 
-// enqueue the coarse-fine pre-pass on state U
-int enqueue_ghosts(amrv_forest* f, const double* U, bool fluxes) {
+// enqueue the coarse-fine pre-pass on state U into geo's ghost-slab buffer;
+// restriction skipped when the buffer already holds it
+int enqueue_ghosts(amrv_forest* f, const Geo& geo, const double* U, bool fluxes, bool restrict_too = true) {
   const int nr = (int)f->tab.rlist.size(), np = (int)f->tab.plist.size();
-  if (nr) HIPCHK(launch_restrict(f->geo, f->lc, U, f->rlist, nr, f->st));
-  if (np) HIPCHK(launch_prolong(f->geo, f->lc, U, f->pp, f->plist, np, fluxes, f->st));
+  if (nr && restrict_too) HIPCHK(launch_restrict(geo, f->lc, U, f->rlist, nr, f->st));
+  if (np) HIPCHK(launch_prolong(geo, f->lc, U, f->pp, f->plist, np, fluxes, f->st));
   return AMRV_OK;
 }
 
-int enqueue_stage_update(amrv_forest* f, const StageArgs& a, int mode) {
+// the stage kernel restricts its own result (3D combined variant, not MHD,
+// whose damping of psi after the step would make the restriction stale)
+bool fused_restriction(const amrv_forest* f) {
+  return f->tab.nd == 3 && f->lc.variant == 0 && f->lc.phys != PH_MHD && f->lc.lim != AMRV_KOREN &&
+         f->lc.lim != AMRV_CADA && !f->tab.rlist.empty();
+}
+
+int enqueue_stage_update(amrv_forest* f, const Geo& geo, const StageArgs& a, int mode) {
   const Tables& t = f->tab;
   int m = mode;
   if (t.nd == 1 && m == AMRV_SCHED_PERSISTENT) m = AMRV_SCHED_GRID;
@@ -166,7 +178,7 @@ int enqueue_stage_update(amrv_forest* f, const StageArgs& a, int mode) {
     const int grid = stage_grid(f, m);
     for (int64_t b = 0; b < t.n; b++) {
       Sched s = make_sched(f, 0, (int)b);
-      HIPCHK(launch_stage(f->geo, f->lc, a, f->pp, s, grid, f->st));
+      HIPCHK(launch_stage(geo, f->lc, a, f->pp, s, grid, f->st));
     }
     return AMRV_OK;
   }
@@ -185,7 +197,7 @@ int enqueue_stage_update(amrv_forest* f, const StageArgs& a, int mode) {
     }
     HIPCHK(hipEventRecord(e0, f->st));
   }
-  HIPCHK(launch_stage(f->geo, f->lc, a, f->pp, s, stage_grid(f, m), f->st));
+  HIPCHK(launch_stage(geo, f->lc, a, f->pp, s, stage_grid(f, m), f->st));
   if (f->prof) {
     HIPCHK(hipEventRecord(e1, f->st));
     f->ev.emplace_back(e0, e1);
@@ -197,14 +209,22 @@ int enqueue_stage_update(amrv_forest* f, const StageArgs& a, int mode) {
 
 // one full SSP step on the forest's stream; dt and the damping factor are
 // read from the device parameter block.  fold != null: the last stage folds
-// the Courant reduction of the new state into it.
-int enqueue_step(amrv_forest* f, unsigned long long* fold = nullptr) {
+// the Courant reduction of the new state into it.  With the fused restriction
+// stage s reads ghost-slab buffer s-1 and restricts its result into buffer
+// s mod S, so only the first stage after a state change runs the separate
+// restriction (assume_valid: the caller guarantees Gb[0] holds it, as before
+// a captured step).
+int enqueue_step(amrv_forest* f, unsigned long long* fold = nullptr, bool assume_valid = false) {
   const int S = f->cfg.rk_stages;
+  const bool fused = fused_restriction(f);
   if (f->sched == AMRV_SCHED_PERSISTENT && f->tab.nd > 1) HIPCHK(launch_reset_u32(f->cnt, CNT_QUEUES, f->st));
   for (int s = 1; s <= S; s++) {
     const double* in = s == 1 ? f->U[0] : (s == 2 ? f->U[1] : f->U[2]);
     double* out = s == S ? f->U[0] : (s == 1 ? f->U[1] : f->U[2]);
-    int rc = enqueue_ghosts(f, in, true);
+    Geo geo = f->geo;
+    if (fused) geo.G = f->Gb[s - 1];
+    const bool restrict_too = !fused || (s == 1 && !assume_valid && !f->rvalid);
+    int rc = enqueue_ghosts(f, geo, in, true, restrict_too);
     if (rc) return rc;
     StageArgs a{};
     a.Uin = in;
@@ -214,9 +234,11 @@ int enqueue_step(amrv_forest* f, unsigned long long* fold = nullptr) {
     a.stage = s;
     a.rk = S;
     a.cflred = s == S ? fold : nullptr;
-    rc = enqueue_stage_update(f, a, f->sched);
+    a.Gw = fused ? f->Gb[s % S] : nullptr;
+    rc = enqueue_stage_update(f, geo, a, f->sched);
     if (rc) return rc;
   }
+  f->rvalid = fused;
   if (f->cfg.physics == AMRV_MHD_GLM) {
     const int ip = 2 + 2 * f->tab.nd;
     double* psi = f->U[0] + (size_t)ip * f->tab.n * f->tab.ncell;
@@ -238,16 +260,25 @@ void drop_graph(amrv_forest* f) {
 }
 
 // a device-timed step: dt from the previous fold, then the step with a fold
-int enqueue_device_step(amrv_forest* f, double t_end) {
+int enqueue_device_step(amrv_forest* f, double t_end, bool assume_valid = false) {
   HIPCHK(launch_dt_update(f->red, f->pp, f->pp + PP_T, f->cnt + CNT_ERR, f->cfg.cfl, t_end, f->cfg.glm_cr,
                           f->cfg.physics == AMRV_MHD_GLM, f->st));
-  return enqueue_step(f, f->red);
+  return enqueue_step(f, f->red, assume_valid);
+}
+
+// before replaying a captured step (which assumes it): the restriction of
+// U^n in ghost-slab buffer 0
+int ensure_restricted(amrv_forest* f) {
+  if (!fused_restriction(f) || f->rvalid) return AMRV_OK;
+  HIPCHK(launch_restrict(f->geo, f->lc, f->U[0], f->rlist, (int)f->tab.rlist.size(), f->st));
+  f->rvalid = true;
+  return AMRV_OK;
 }
 
 int capture_graph(amrv_forest* f) {
   drop_graph(f);
   HIPCHK(hipStreamBeginCapture(f->st, hipStreamCaptureModeThreadLocal));
-  int rc = enqueue_step(f);
+  int rc = enqueue_step(f, nullptr, true);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(f->st, &g);
   if (rc) {
@@ -378,6 +409,7 @@ int amrv_forest_create(const amrv_config* cfg, int64_t n, const int32_t* lev, co
   g.sleaf = (const int32_t*)(f->ws + L.off_sleaf);
   g.sface = (const int32_t*)(f->ws + L.off_sface);
   g.G = (double*)(f->ws + L.off_G);
+  for (int i = 0; i < 3; i++) f->Gb[i] = g.G + (size_t)i * std::max(1, t.nslot) * t.nvar * 2 * t.T;
   g.FF = (double*)(f->ws + L.off_FF);
   for (int l = 0; l < MAXLEV; l++)
     for (int d = 0; d < 3; d++) {
@@ -461,6 +493,7 @@ int amrv_set_state(amrv_forest* f, const double* U, int64_t nd, int32_t on_devic
                         f->st));
   if (!on_device) HIPCHK(hipStreamSynchronize(f->st));
   f->fold_valid = false;
+  f->rvalid = false;
   return AMRV_OK;
 }
 
@@ -504,11 +537,14 @@ int amrv_advance(amrv_forest* f, double dt) {
   int rc = set_scalars(f, PP_DT, {dt, damp});
   if (rc) return rc;
   if (f->graph_on && !f->prof) {
+    rc = ensure_restricted(f);
+    if (rc) return rc;
     if (!f->graph_valid) {
       rc = capture_graph(f);
       if (rc) return rc;
     }
     HIPCHK(hipGraphLaunch(f->gexec, f->st));
+    f->rvalid = fused_restriction(f);
     return AMRV_OK;
   }
   return enqueue_step(f);
@@ -529,13 +565,17 @@ int amrv_advance_cfl(amrv_forest* f, int32_t nsteps, double t_end, double* t, in
   }
   f->fold_valid = false;
   const bool graph = f->st != nullptr && f->sched != AMRV_SCHED_PER_BLOCK && !f->prof;
+  if (graph) {
+    rc = ensure_restricted(f);
+    if (rc) return rc;
+  }
   if (graph && (!f->dexec || f->dt_tend != t_end)) {
     if (f->dexec) (void)hipGraphExecDestroy(f->dexec);
     if (f->dgraph) (void)hipGraphDestroy(f->dgraph);
     f->dexec = nullptr;
     f->dgraph = nullptr;
     HIPCHK(hipStreamBeginCapture(f->st, hipStreamCaptureModeThreadLocal));
-    rc = enqueue_device_step(f, t_end);
+    rc = enqueue_device_step(f, t_end, true);
     hipGraph_t gr = nullptr;
     hipError_t e = hipStreamEndCapture(f->st, &gr);
     if (rc) {
@@ -550,6 +590,7 @@ int amrv_advance_cfl(amrv_forest* f, int32_t nsteps, double t_end, double* t, in
   for (int i = 0; i < nsteps; i++) {
     if (graph) {
       HIPCHK(hipGraphLaunch(f->dexec, f->st));
+      f->rvalid = fused_restriction(f);
     } else {
       rc = enqueue_device_step(f, t_end);
       if (rc) return rc;
@@ -594,7 +635,8 @@ int amrv_flag_blocks(amrv_forest* f, int32_t mode, int8_t* flags_out, double* em
     if (mode == AMRV_FLAG_MLP_FALLBACK) only = unc;
   }
   if (mode != AMRV_FLAG_MLP) {
-    int rc = enqueue_ghosts(f, f->U[0], false);
+    int rc = enqueue_ghosts(f, f->geo, f->U[0], false);
+    f->rvalid = true;  // buffer 0 now restricts U^n
     if (rc) return rc;
     HIPCHK(launch_lohner(f->geo, f->lc, f->U[0], f->pp, f->lp, f->cfg.max_level, f->emax, f->flags, only, f->st));
   }
@@ -710,7 +752,9 @@ int amrv_regrid_transfer(amrv_forest* from, amrv_forest* to) {
   if (rc) return fail(rc, err);
   int32_t* xf = (int32_t*)(to->ws + to->lay.off_xfer);
   // ghost slabs of the source state (coarse-fine faces), then the transfer
-  rc = enqueue_ghosts(from, from->U[0], false);
+  rc = enqueue_ghosts(from, from->geo, from->U[0], false);
+  from->rvalid = true;
+  to->rvalid = false;
   if (rc) return rc;
   if (from->st != to->st) HIPCHK(hipStreamSynchronize(from->st));
   HIPCHK(hipMemcpyAsync(xf, to->xfer_host.data(), sizeof(int32_t) * to->xfer_host.size(), hipMemcpyHostToDevice,
@@ -799,7 +843,7 @@ int amrv_autotune(amrv_forest* f, int32_t reps) {
         if (e != hipSuccess) rc = hip_fail(e, "reset");
       }
       (void)hipEventRecord(e0, f->st);
-      if (!rc) rc = enqueue_stage_update(f, a, c.sched);
+      if (!rc) rc = enqueue_stage_update(f, f->geo, a, c.sched);
       (void)hipEventRecord(e1, f->st);
       (void)hipEventSynchronize(e1);
       float ms = 0;

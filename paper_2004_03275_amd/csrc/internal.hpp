@@ -59,6 +59,8 @@ struct StageArgs {
   int stage;           // 1..rk
   int rk;              // 2 or 3
   unsigned long long* cflred;  // last stage: fold the Courant reduction of the new state here (or null)
+  double* Gw;          // 3D combined variant: restrict the stage output onto the coarse neighbours'
+                       // ghost slabs of this buffer (the G layout), or null
 };
 
 struct Kernels;  // forward

@@ -500,6 +500,42 @@ __device__ __forceinline__ void load_strided(const double* __restrict__ p, size_
   for (int v = 0; v < NV; v++) u[v] = p[v * vs];
 }
 
+// (6) of the 3D stage update: restriction of a leaf's new state onto the
+// ghost slabs of its coarser neighbours (buffer a.Gw): after all planes are
+// stored, the 2 layers x 8 x 8 coarse ghost cells of each such face, one
+// thread each (tid < 128), from the 2x2x2 fine cells just written
+// (cache-hot), summed in the order of the separate restriction pass.
+template <int NV>
+__device__ __forceinline__ void restrict_leaf(const Geo& g, const StageArgs& a, int leaf, int tid) {
+  constexpr int NB = 16;
+  if (tid >= 128) return;
+  const size_t vs = (size_t)g.n * g.ncell;
+  const double* src = a.Uout + (size_t)leaf * g.ncell;
+  const int lay = tid >> 6, c1 = tid & 7, c2 = (tid >> 3) & 7;
+  for (int f = 0; f < 6; f++) {
+    if (g.kind[leaf * 6 + f] != NB_COARSER) continue;
+    const int d = f >> 1, e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;
+    const int rs = g.slot[g.nbr[leaf * 6 + f] * 6 + (f ^ 1)];
+    if (rs < 0) continue;
+    int cc[3];
+    cc[d] = (f & 1) ? NB / 2 - 1 - lay : lay;
+    cc[e1] = c1;
+    cc[e2] = c2;
+    const int tt = 8 * (g.ijk[leaf * 3 + e1] & 1) + NB * 8 * (g.ijk[leaf * 3 + e2] & 1) + c1 + NB * c2;
+    double* o = a.Gw + (size_t)rs * NV * 2 * g.T + (size_t)lay * g.T + tt;
+    const double* p0 = src + 2 * cc[0] + NB * (2 * cc[1] + NB * 2 * cc[2]);
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+      const double* p = p0 + v * vs;
+      const double2 q0 = *reinterpret_cast<const double2*>(p);
+      const double2 q1 = *reinterpret_cast<const double2*>(p + NB);
+      const double2 q2 = *reinterpret_cast<const double2*>(p + NB * NB);
+      const double2 q3 = *reinterpret_cast<const double2*>(p + NB * NB + NB);
+      o[(size_t)v * 2 * g.T] = (((q0.x + q0.y) + (q1.x + q1.y)) + ((q2.x + q2.y) + (q3.x + q3.y))) * 0.125;
+    }
+  }
+}
+
 // Stage update of 16^2 / 16^3 leaves.  One 256-thread workgroup owns a leaf;
 // thread (tx, ty) owns the z-column of cells (tx, ty, *).  Per z-plane:
 //   (1) z direction in registers: slope of cell k+1, flux of face k+1/2;
@@ -859,6 +895,16 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
       if (a.cflred) {
         const double rd[3] = {rdx, rdy, rdz};
         cfl_cell<ND, PH>(Ui, P, rd, csmax, ccmax, cbad);
+      }
+    }
+    if constexpr (ND == 3 && !SPLIT && PH != PH_MHD) {
+      bool rany = false;
+#pragma unroll
+      for (int f = 0; f < 6; f++) rany = rany || (a.Gw && kinds[f] == NB_COARSER);
+      if (rany) {
+        __threadfence_block();
+        __syncthreads();
+        restrict_leaf<NV>(g, a, leaf, tid);
       }
     }
   }
