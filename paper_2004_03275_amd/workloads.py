@@ -580,3 +580,34 @@ def mlp_random_features(seed: int, n: int) -> np.ndarray:
     bits = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
     y = (rng.uniform(size=n) < 0.3).astype(np.float32)
     return bits, y
+
+
+# -- reaction-diffusion on uniform grids (Sec. 3.4) -------------------------
+
+def rd_cell_centres(ndim: int, n: int, length: float) -> list:
+    """Cell-centre coordinates (x, y[, z]) of an n^ndim grid on [0, L]^ndim,
+    arrays indexed [z][y][x]."""
+    c = (np.arange(n) + 0.5) * (length / n)
+    grids = np.meshgrid(*([c] * ndim), indexing="ij")  # [x][y][z] order
+    return [np.ascontiguousarray(np.transpose(g)) for g in grids]
+
+
+def schnakenberg_initial(ndim: int = 2, n: int = 256, a: float = 0.1305, b: float = 0.7695):
+    """Sec. 3.4: v = b/(a+b)^2, u = a + b + exp(-100 |r - r0|^2) on the unit
+    square/cube, r0 = (1/3, 1/2[, 1/2]).  Returns (u, v, L = 1)."""
+    xs = rd_cell_centres(ndim, n, 1.0)
+    r0 = (1.0 / 3.0, 0.5, 0.5)
+    r2 = sum((x - r0[d]) ** 2 for d, x in enumerate(xs))
+    u = a + b + np.exp(-100.0 * r2)
+    v = np.full_like(u, b / (a + b) ** 2)
+    return u, v, 1.0
+
+
+def gray_scott_initial(n: int = 256):
+    """Sec. 3.4: the steady state u = 1, v = 0 with two Gaussians
+    0.5 exp(-25 |r - r_i|^2), r_1 = (0.5, 0.5), r_2 = (0.55, 0.6),
+    subtracted from u and added to v, on the periodic square of side 2.
+    Returns (u, v, L = 2)."""
+    x, y = rd_cell_centres(2, n, 2.0)
+    g = sum(0.5 * np.exp(-25.0 * ((x - cx) ** 2 + (y - cy) ** 2)) for cx, cy in ((0.5, 0.5), (0.55, 0.6)))
+    return 1.0 - g, g.copy(), 2.0

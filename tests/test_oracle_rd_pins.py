@@ -1,0 +1,230 @@
+"""Pins of the oracle's elliptic solve and reaction-diffusion schemes
+(Sec. 2.3 multigrid, Sec. 3.4 reaction-diffusion; oracle/rd.py).
+
+* The discrete Laplacian is pinned on a whole basis: every Fourier mode
+  (periodic) and every cosine mode (Neumann) of small grids is an
+  eigenvector with the closed-form eigenvalue, and quadratics are
+  differentiated exactly in the interior.
+* The exact Helmholtz solve is checked against a dense solve of a matrix
+  assembled from the stencil by index loops written here, against a
+  manufactured continuum solution at second order, and by the mass
+  identity lambda sum(phi) = -sum(f).
+* The time schemes: Table 1's printed explicit limits; fixed points of both
+  models; the steps against an accurate stiff integration (scipy Radau) of
+  the semi-discrete system: Euler and split at first order, midpoint and
+  IMEX at second order, matching the paper's IMEX-versus-split finding;
+  conservation of each species' mass by the diffusion (Neumann) in the
+  split and IMEX solves with the reaction switched off; and the mirror
+  symmetry of the 2D Schnakenberg initial condition.
+"""
+import os
+
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+
+from oracle import rd as R
+from paper_2004_03275_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "rd_table1_dt_limits.txt")
+
+
+def _modes(nd, n, bc):
+    """Eigenvectors (real arrays) and closed-form eigenvalues of the
+    unit-spacing-free second difference, h = 1 (L = n)."""
+    ks = np.array(np.meshgrid(*([np.arange(n)] * nd), indexing="ij")).reshape(nd, -1).T
+    idx = np.arange(n)
+    for k in ks:
+        vec = np.ones([n] * nd)
+        lam = 0.0
+        for d in range(nd):
+            kd = k[d]
+            if bc == R.PERIODIC:
+                lam += 2.0 * np.cos(2.0 * np.pi * kd / n) - 2.0
+            else:
+                lam += 2.0 * np.cos(np.pi * kd / n) - 2.0
+            sh = [1] * nd
+            sh[nd - 1 - d] = n
+            vec = vec * (np.cos(2.0 * np.pi * kd * idx / n) if bc == R.PERIODIC
+                         else np.cos(np.pi * kd * (idx + 0.5) / n)).reshape(sh)
+        yield vec, lam
+        if bc == R.PERIODIC:
+            # the sine partner of each direction's cosine (one at a time)
+            for d in range(nd):
+                if k[d] == 0:
+                    continue
+                v2 = np.ones([n] * nd)
+                for e in range(nd):
+                    sh = [1] * nd
+                    sh[nd - 1 - e] = n
+                    fn = np.sin if e == d else np.cos
+                    v2 = v2 * fn(2.0 * np.pi * k[e] * idx / n).reshape(sh)
+                yield v2, lam
+
+
+@pytest.mark.parametrize("nd,n", [(2, 8), (3, 4)])
+@pytest.mark.parametrize("bc", [R.PERIODIC, R.NEUMANN])
+def test_laplacian_on_every_eigenmode(nd, n, bc):
+    count = 0
+    for vec, lam in _modes(nd, n, bc):
+        got = R.laplacian(vec, float(n), bc)  # h = 1
+        assert np.abs(got - lam * vec).max() <= 1e-12 * max(1.0, np.abs(vec).max()), lam
+        count += 1
+    assert count >= n ** nd
+
+
+def test_laplacian_of_quadratics_is_exact_inside():
+    n, L = 16, 2.0
+    x, y, z = W.rd_cell_centres(3, n, L)
+    w = 3.0 * x * x - y * y + 0.5 * z * z + x * y
+    lap = R.laplacian(w, L, R.NEUMANN)
+    inner = lap[1:-1, 1:-1, 1:-1]
+    assert np.abs(inner - (6.0 - 2.0 + 1.0)).max() < 1e-11
+
+
+def _dense_matrix(nd, n, length, bc, lam):
+    """A = lap - lambda I assembled cell by cell (index loops)."""
+    N = n ** nd
+    A = np.zeros((N, N))
+    ih2 = (n / length) ** 2
+    for c in range(N):
+        ijk = [(c // n ** d) % n for d in range(nd)]  # x, y, z
+        A[c, c] -= lam
+        for d in range(nd):
+            for s in (-1, 1):
+                m = list(ijk)
+                t = m[d] + s
+                if bc == R.PERIODIC:
+                    t %= n
+                else:
+                    t = min(max(t, 0), n - 1)
+                m[d] = t
+                A[c, sum(m[e] * n ** e for e in range(nd))] += ih2
+                A[c, c] -= ih2
+    return A
+
+
+@pytest.mark.parametrize("nd,n", [(2, 8), (3, 4)])
+@pytest.mark.parametrize("bc", [R.PERIODIC, R.NEUMANN])
+@pytest.mark.parametrize("lam", [0.3, 50.0])
+def test_exact_solve_matches_a_dense_solve(nd, n, bc, lam):
+    rng = np.random.default_rng(7 + nd + 10 * bc)
+    f = rng.standard_normal([n] * nd)
+    phi = R.helmholtz_solve(f, lam, 1.7, bc)
+    ref = np.linalg.solve(_dense_matrix(nd, n, 1.7, bc, lam), f.ravel()).reshape(f.shape)
+    assert np.abs(phi - ref).max() <= 1e-12 * np.abs(ref).max()
+    # and the residual through the stencil code
+    r = f - R.helmholtz_apply(phi, lam, 1.7, bc)
+    assert np.abs(r).max() <= 1e-10 * np.abs(f).max()
+    # mass: every row of lap sums to zero
+    assert lam * phi.sum() == pytest.approx(-f.sum(), abs=1e-11 * np.abs(f).sum())
+
+
+@pytest.mark.parametrize("bc", [R.PERIODIC, R.NEUMANN])
+def test_manufactured_solution_converges_at_second_order(bc):
+    """phi = cos(2 pi x) cos(2 pi y) (periodic) or cos(pi x) cos(pi y)
+    (Neumann) on the unit square solves the continuum equation with
+    f = (-(k^2 + k^2) - lambda) phi."""
+    lam = 10.0
+    k = 2.0 * np.pi if bc == R.PERIODIC else np.pi
+    errs = []
+    for n in (32, 64, 128):
+        x, y = W.rd_cell_centres(2, n, 1.0)
+        exact = np.cos(k * x) * np.cos(k * y)
+        f = (-2.0 * k * k - lam) * exact
+        errs.append(np.abs(R.helmholtz_solve(f, lam, 1.0, bc) - exact).max())
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders > 1.95) and np.all(orders < 2.05), (errs, orders)
+
+
+def test_table1_explicit_limits():
+    rows = [l.split() for l in open(GOLDEN) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 2
+    for name, dmax, *vals in rows:
+        for h, printed in zip((1 / 128, 1 / 256, 1 / 512), vals):
+            got = R.explicit_dt_limit(h, 2, float(dmax))
+            p = float(printed)
+            # two printed significant digits
+            assert abs(got - p) <= 0.05 * p, (name, h, got, p)
+
+
+@pytest.mark.parametrize("scheme", [R.EULER, R.MIDPOINT, R.SPLIT, R.IMEX])
+def test_fixed_points(scheme):
+    p = R.SCHNAKENBERG_PARAMS
+    a, b = p["p2"], p["p3"]
+    u = np.full((8, 8), a + b)
+    v = np.full((8, 8), b / (a + b) ** 2)
+    u1, v1 = R.run(u, v, 1e-3, 5, scheme, p, 1.0, R.NEUMANN)
+    assert np.abs(u1 - u).max() < 1e-12 and np.abs(v1 - v).max() < 1e-12
+    g = R.GRAY_SCOTT_PARAMS
+    u, v = np.ones((8, 8)), np.zeros((8, 8))
+    u1, v1 = R.run(u, v, 0.5, 3, scheme, g, 2.0, R.PERIODIC)
+    if scheme in (R.EULER, R.MIDPOINT):
+        assert np.array_equal(u1, u) and np.array_equal(v1, v)
+    else:
+        assert np.abs(u1 - 1.0).max() < 1e-13 and np.abs(v1).max() < 1e-13
+
+
+def _semi_discrete_reference(u0, v0, p, L, bc, t):
+    shape = u0.shape
+    N = u0.size
+
+    def F(_, y):
+        fu, fv = R.rhs_full(y[:N].reshape(shape), y[N:].reshape(shape), p, L, bc)
+        return np.concatenate([fu.ravel(), fv.ravel()])
+
+    sol = solve_ivp(F, (0.0, t), np.concatenate([u0.ravel(), v0.ravel()]), method="Radau", rtol=1e-11,
+                    atol=1e-13)
+    assert sol.success
+    y = sol.y[:, -1]
+    return y[:N].reshape(shape), y[N:].reshape(shape)
+
+
+@pytest.fixture(scope="module")
+def schnakenberg_16():
+    u0, v0, L = W.schnakenberg_initial(2, 16)
+    p = R.SCHNAKENBERG_PARAMS
+    t = 0.02
+    return u0, v0, L, p, t, _semi_discrete_reference(u0, v0, p, L, R.NEUMANN, t)
+
+
+@pytest.mark.parametrize("scheme,dts,lo,hi", [
+    (R.IMEX, (2e-3, 1e-3, 5e-4), 1.8, 2.2),
+    (R.SPLIT, (2e-3, 1e-3, 5e-4), 0.7, 1.15),
+    (R.MIDPOINT, (4e-5, 2e-5, 1e-5), 1.8, 2.2),
+    (R.EULER, (4e-5, 2e-5, 1e-5), 0.9, 1.1),
+])
+def test_time_order_against_a_stiff_integrator(schnakenberg_16, scheme, dts, lo, hi):
+    """The paper's comparison (Sec. 3.4, Fig. schnakenberg-conv): IMEX
+    second order, the split scheme at most first order."""
+    u0, v0, L, p, t, (ur, vr) = schnakenberg_16
+    errs = []
+    for dt in dts:
+        n = int(round(t / dt))
+        u, v = R.run(u0, v0, dt, n, scheme, p, L, R.NEUMANN)
+        errs.append(np.sqrt(np.mean((u - ur) ** 2) + np.mean((v - vr) ** 2)))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders > lo) and np.all(orders < hi), (errs, orders)
+
+
+@pytest.mark.parametrize("scheme", [R.SPLIT, R.IMEX])
+def test_diffusion_conserves_mass(scheme):
+    p = dict(R.SCHNAKENBERG_PARAMS, p1=0.0)  # kappa = 0: pure diffusion
+    u0, v0, L = W.schnakenberg_initial(2, 32)
+    u, v = R.run(u0, v0, 1e-2, 4, scheme, p, L, R.NEUMANN)
+    assert u.sum() == pytest.approx(u0.sum(), rel=1e-13)
+    assert v.sum() == pytest.approx(v0.sum(), rel=1e-13)
+    assert np.abs(u - u0).max() > 1e-3  # it did diffuse
+
+
+def test_schnakenberg_2d_keeps_its_mirror_symmetry():
+    u0, v0, L = W.schnakenberg_initial(2, 32)
+    u, v = R.run(u0, v0, 1e-3, 10, R.IMEX, R.SCHNAKENBERG_PARAMS, L, R.NEUMANN)
+    assert np.abs(u - u[::-1, :]).max() < 1e-12
+    assert np.abs(v - v[::-1, :]).max() < 1e-12
+    assert np.abs(u - u[:, ::-1]).max() > 1e-3
+
+
+def test_rejects_nonpositive_lambda():
+    with pytest.raises(ValueError):
+        R.helmholtz_solve(np.zeros((4, 4)), 0.0, 1.0, R.PERIODIC)
