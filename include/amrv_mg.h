@@ -1,0 +1,124 @@
+/* amrv_mg.h -- C-ABI of libamrv's geometric multigrid Helmholtz solver and
+ * the reaction-diffusion time steps built on it.
+ *
+ * Method (arXiv 2004.03275): the multigrid functionality of Sec. 2.3 solves
+ * Poisson/Helmholtz problems; Sec. 3.4 uses it for the reaction-diffusion
+ * models (Eqs. gray-scott and schnakenberg): the split scheme's backward-
+ * Euler diffusion step leads to the Helmholtz problem of Eq. diff-helmholtz,
+ * and the first stage of the IMEX scheme (Eq. imex, the trapezoidal pair) to
+ * another one.  This library solves them on one uniform cell-centred grid.
+ *
+ * Grid and layout: n cells per side (a power of two), ndim = 2 or 3, on
+ * [0, L]^ndim, h = L / n.  A field is n^ndim binary64 values in device
+ * memory, x fastest: index x + n (y + n z).  Boundaries: periodic, or zero
+ * Neumann (the ghost value beyond a face equals the adjacent interior cell).
+ * Discrete Laplacian: per direction ((w_minus + w_plus) - 2 w) / h^2, the
+ * directions summed in the order x, y, z.
+ *
+ * Helmholtz problem: lap(phi) - lambda phi = f with lambda > 0.  The solver
+ * runs V-cycles (red-black Gauss-Seidel smoothing with `pre` and `post`
+ * sweeps, residual restriction by averaging the 2^ndim children, correction
+ * prolongation by bi/trilinear interpolation, coarse grids rediscretised
+ * down to 2 cells per side and solved exactly there) until the maximum
+ * residual |f - (lap(phi) - lambda phi)| is at most tol times max |f| -- the
+ * paper's stopping rule, Sec. 3.4, with tol = 1e-7 there.  Since lambda I - lap is an M-matrix
+ * whose rows sum to lambda, the returned solution differs from the exact
+ * discrete one by at most (max residual) / lambda in every cell.
+ *
+ * Conventions: as in amrv.h (0 on success, negative AMRV_E* codes,
+ * amrv_last_error() for the message).  All device pointers belong to the
+ * caller; the handle keeps only its workspace and stream.  Calls enqueue on
+ * the handle's stream and return after it has completed (the solver reads
+ * the residual after every cycle).
+ */
+#ifndef AMRV_MG_H
+#define AMRV_MG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "amrv.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AMRV_ENOTCONVERGED (-7) /* the residual did not reach tol within max_cycles */
+
+#define AMRV_MG_PERIODIC 0
+#define AMRV_MG_NEUMANN 1
+
+#define AMRV_RD_SCHNAKENBERG 0 /* F0 = (kappa (a - u + u^2 v), kappa (b - u^2 v)) */
+#define AMRV_RD_GRAY_SCOTT 1   /* F0 = (-u v^2 + F (1 - u), u v^2 - (F + k) v) */
+
+#define AMRV_RD_EULER 0    /* w1 = w + dt F(w), F = F0 + D lap: explicit */
+#define AMRV_RD_MIDPOINT 1 /* explicit midpoint: w + dt F(w + dt/2 F(w)) */
+#define AMRV_RD_SPLIT 2    /* w* = w + dt F0(w); w1 = w* + dt D lap(w1) (Helmholtz, lambda = 1/(dt D)) */
+#define AMRV_RD_IMEX 3     /* Eq. imex: w* - dt/2 D lap(w*) = w + dt F0(w) + dt/2 D lap(w)
+                              (Helmholtz, lambda = 2/(dt D)); w1 = w + dt/2 (F(w) + F(w*)) */
+
+typedef struct amrv_mg amrv_mg;
+
+typedef struct {
+  int32_t ndim;          /* 2 or 3 */
+  int32_t n;             /* cells per side: power of two, 4..8192 (2D), 4..512 (3D) */
+  int32_t bc;            /* AMRV_MG_PERIODIC or AMRV_MG_NEUMANN */
+  int32_t nfields;       /* 1 or 2 fields solved together (2 for the RD steps) */
+  int32_t pre_sweeps;    /* red-black sweeps before restriction (1..8) */
+  int32_t post_sweeps;   /* red-black sweeps after prolongation (1..8) */
+  int32_t use_graph;     /* replay each V-cycle from a captured HIP graph (needs a stream) */
+  int32_t pad;
+  double length;         /* L > 0 */
+} amrv_mg_config;
+
+typedef struct {
+  int32_t model; /* AMRV_RD_SCHNAKENBERG or AMRV_RD_GRAY_SCOTT */
+  int32_t pad;
+  double Du, Dv; /* diffusion coefficients, > 0 */
+  double p1, p2, p3; /* Schnakenberg: kappa, a, b; Gray-Scott: F, k, unused */
+} amrv_rd_params;
+
+/* Bytes of device workspace for this configuration (256-byte aligned
+ * start), or 0 with amrv_last_error() set for an invalid one. */
+size_t amrv_mg_workspace_bytes(const amrv_mg_config* cfg);
+
+/* Creates a solver in the caller's workspace (device memory of at least
+ * amrv_mg_workspace_bytes, owned by the caller, alive until destroy) on the
+ * given HIP stream (NULL: the null stream).  Allocates only pinned host
+ * memory for the residual read-back. */
+int amrv_mg_create(const amrv_mg_config* cfg, void* workspace, size_t bytes, void* stream, amrv_mg** out);
+int amrv_mg_destroy(amrv_mg* m);
+
+/* Solves lap(phi) - lambda phi = f (Sec. 2.3, Eq. diff-helmholtz) for
+ * nfields fields stored one after another (f and phi: nfields * n^ndim
+ * doubles each, device; phi holds the initial guess on entry and the
+ * solution on return; lambda: nfields host values, each > 0).  Stops when
+ * every field's max residual <= tol * its max |f| (tol > 0), or after
+ * max_cycles V-cycles (then AMRV_ENOTCONVERGED, phi holding the last
+ * iterate).  cycles, res_max and f_max (host, may be NULL) receive the
+ * cycle count and, per field, the final max residual and max |f|. */
+int amrv_mg_solve(amrv_mg* m, const double* f, double* phi, const double* lambda, double tol, int32_t max_cycles,
+                  int32_t* cycles, double* res_max, double* f_max);
+
+/* nsteps time steps of the reaction-diffusion model (Sec. 3.4) on the
+ * device fields u, v (n^ndim doubles each, updated in place) with step dt
+ * and the given scheme.  SPLIT and IMEX need a solver created with
+ * nfields = 2: both species' Helmholtz problems are solved together, each
+ * to tol (initial guess: the current state), at most max_cycles V-cycles
+ * per step.  cycles_total (may be NULL) receives the V-cycles summed over
+ * the steps; res_max (may be NULL, 2 doubles) the last solve's residuals. */
+int amrv_rd_step(amrv_mg* m, const amrv_rd_params* p, int32_t scheme, double dt, int32_t nsteps, double* u, double* v,
+                 double tol, int32_t max_cycles, int32_t* cycles_total, double* res_max);
+
+/* V-cycle timing: with enable != 0, every V-cycle of amrv_mg_solve and
+ * amrv_rd_step (graph replay or direct launches, residual read-back
+ * included) is bracketed by HIP events on the handle's stream;
+ * amrv_mg_profile_read returns the summed time (ms) and the cycle count
+ * since the last read, and resets both. */
+int amrv_mg_profile(amrv_mg* m, int32_t enable);
+int amrv_mg_profile_read(amrv_mg* m, double* ms_total, int64_t* cycles);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

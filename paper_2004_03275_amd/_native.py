@@ -19,6 +19,7 @@ ENONPHYSICAL = -3
 ENOMEM = -4
 EDEVICE = -5
 ENOTSUP = -6
+ENOTCONVERGED = -7
 
 SCHED_PER_BLOCK = 0
 SCHED_GRID = 1
@@ -64,6 +65,21 @@ class Config(ctypes.Structure):
 class TrainCfg(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float), ("pos_weight", ctypes.c_float), ("t0", ctypes.c_int32)]
+
+
+class MgConfig(ctypes.Structure):
+    """amrv_mg_config (include/amrv_mg.h)."""
+
+    _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int32), ("bc", ctypes.c_int32), ("nfields", ctypes.c_int32),
+                ("pre_sweeps", ctypes.c_int32), ("post_sweeps", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("length", ctypes.c_double)]
+
+
+class RdParams(ctypes.Structure):
+    """amrv_rd_params (include/amrv_mg.h)."""
+
+    _fields_ = [("model", ctypes.c_int32), ("pad", ctypes.c_int32), ("Du", ctypes.c_double), ("Dv", ctypes.c_double),
+                ("p1", ctypes.c_double), ("p2", ctypes.c_double), ("p3", ctypes.c_double)]
 
 
 class AmrvError(RuntimeError):
@@ -113,6 +129,15 @@ SIGNATURES = {
                                  ctypes.POINTER(ctypes.c_int64), P, P], ctypes.c_int),
     "amrv_regrid_transfer": ([P, P], ctypes.c_int),
     "amrv_synchronize": ([P], ctypes.c_int),
+    "amrv_mg_workspace_bytes": ([ctypes.POINTER(MgConfig)], ctypes.c_size_t),
+    "amrv_mg_create": ([ctypes.POINTER(MgConfig), P, ctypes.c_size_t, P, ctypes.POINTER(P)], ctypes.c_int),
+    "amrv_mg_destroy": ([P], ctypes.c_int),
+    "amrv_mg_solve": ([P, P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), P, P],
+                      ctypes.c_int),
+    "amrv_rd_step": ([P, ctypes.POINTER(RdParams), ctypes.c_int32, ctypes.c_double, ctypes.c_int32, P, P,
+                      ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), P], ctypes.c_int),
+    "amrv_mg_profile": ([P, ctypes.c_int32], ctypes.c_int),
+    "amrv_mg_profile_read": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "amrv_last_error": ([], ctypes.c_char_p),
 }
 

@@ -88,6 +88,11 @@ Layout plan(const Tables& t) {
 
 }  // namespace
 
+namespace amrv {
+// the error channel shared with the multigrid entry points (amrv_last_error)
+int set_error(int code, const char* msg) { return fail(code, msg); }
+}  // namespace amrv
+
 struct amrv_forest {
   amrv_config cfg{};
   Tables tab;

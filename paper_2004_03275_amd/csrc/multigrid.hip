@@ -1,0 +1,840 @@
+// multigrid.hip -- geometric multigrid Helmholtz solver on one uniform
+// cell-centred grid and the reaction-diffusion time steps built on it
+// (declared in include/amrv_mg.h; the method's multigrid of Sec. 2.3 and the
+// reaction-diffusion schemes of Sec. 3.4).
+//
+// Layout in the caller's workspace (every array 256-byte aligned):
+//   phi[field][level], f[field][level]   n_l^d doubles each, n_l = n >> l,
+//                                         x fastest; level 0 is the grid
+//   tmp[4]                                n^d doubles (reaction-diffusion
+//                                         temporaries)
+//   par                                   lambda per field, 1/diagonal per
+//                                         field and level, 1/h^2 per level
+//   red                                   per field: max residual and max |f|
+//                                         as binary64 bit patterns (uint64)
+//
+// A V-cycle: on each level above the tail, `pre` red-black sweeps, then one
+// launch that forms the residual on the 2^d children of every coarse cell,
+// averages it into the coarse right-hand side and zeroes the coarse
+// correction; the coarse levels of at most 4,096 cells are solved by one
+// workgroup per field with every level resident in LDS (the whole descent,
+// the exact solve on the 2-per-side grid and the ascent in one launch); back
+// up, one
+// launch adds the bi/trilinear interpolation of the coarse correction, then
+// `post` sweeps.  Fields (u and v of the reaction-diffusion steps) are solved
+// by the same launches (grid y = field).  These grids are small (a 256^2
+// field is 512 KiB), so the cycle is bound by launch and synchronisation
+// latency, not by HBM: it is replayed from a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "../../include/amrv_mg.h"
+#include "internal.hpp"
+
+namespace {
+
+constexpr int MG_MAXL = 14;   // n <= 8192: 13 levels down to 2 cells per side
+constexpr int NFMAX = 2;
+constexpr int TAIL_CELLS = 4096;
+constexpr int TAIL_THREADS = 1024;
+constexpr int PAR_LAM = 0;
+constexpr int PAR_IDIAG = NFMAX;                       // + field * MG_MAXL + level
+constexpr int PAR_IH2 = NFMAX + NFMAX * MG_MAXL;       // + level
+constexpr int PAR_COUNT = PAR_IH2 + MG_MAXL;
+
+struct MgDev {
+  int nd, bc, nlev, nf;
+  int n[MG_MAXL];
+  int cells[MG_MAXL];
+  int loff[MG_MAXL];            // LDS offset (doubles) of the tail's phi_l; f_l follows it
+  double* phi[NFMAX][MG_MAXL];
+  double* f[NFMAX][MG_MAXL];
+  const double* par;
+  unsigned long long* red;
+};
+
+struct MgPar {
+  double v[PAR_COUNT];
+};
+
+struct RdK {
+  int model;
+  double Du, Dv, p1, p2, p3;
+};
+
+// neighbours with the boundary rule: periodic wrap, or (Neumann) the cell
+// itself, whose value is the mirrored ghost
+__device__ __forceinline__ int im(int i, int n, int bc) { return i > 0 ? i - 1 : (bc == AMRV_MG_PERIODIC ? n - 1 : 0); }
+__device__ __forceinline__ int ip(int i, int n, int bc) { return i < n - 1 ? i + 1 : (bc == AMRV_MG_PERIODIC ? 0 : n - 1); }
+
+template <int ND>
+__device__ __forceinline__ void decode(int t, int n, int& x, int& y, int& z) {
+  x = t % n;
+  const int r = t / n;
+  y = ND == 3 ? r % n : r;
+  z = ND == 3 ? r / n : 0;
+}
+
+// Laplacian: per direction ((w- + w+) - 2 w) * (1/h^2), added x, y, z
+template <int ND>
+__device__ __forceinline__ double lap_at(const double* a, int x, int y, int z, int n, int bc, double ih2) {
+  const int row = (z * n + y) * n;
+  const double w = a[row + x];
+  double out = ((a[row + im(x, n, bc)] + a[row + ip(x, n, bc)]) - 2.0 * w) * ih2;
+  out = out + ((a[(z * n + im(y, n, bc)) * n + x] + a[(z * n + ip(y, n, bc)) * n + x]) - 2.0 * w) * ih2;
+  if constexpr (ND == 3)
+    out = out + ((a[(im(z, n, bc) * n + y) * n + x] + a[(ip(z, n, bc) * n + y) * n + x]) - 2.0 * w) * ih2;
+  return out;
+}
+
+// Gauss-Seidel update of one cell: phi = (sum of neighbours / h^2 - f) / (2 d / h^2 + lambda)
+template <int ND>
+__device__ __forceinline__ void gs_cell(double* p, const double* rhs, int x, int y, int z, int n, int bc, double ih2,
+                                        double idiag) {
+  const int row = (z * n + y) * n;
+  double s = (p[row + im(x, n, bc)] + p[row + ip(x, n, bc)]) +
+             (p[(z * n + im(y, n, bc)) * n + x] + p[(z * n + ip(y, n, bc)) * n + x]);
+  if constexpr (ND == 3) s = s + (p[(im(z, n, bc) * n + y) * n + x] + p[(ip(z, n, bc) * n + y) * n + x]);
+  p[row + x] = (s * ih2 - rhs[row + x]) * idiag;
+}
+
+// cell t of colour c among the cells with (x + y + z) % 2 == c
+template <int ND>
+__device__ __forceinline__ void colour_cell(int t, int n, int c, int& x, int& y, int& z) {
+  const int half = n >> 1;
+  const int xh = t % half;
+  const int r = t / half;
+  y = ND == 3 ? r % n : r;
+  z = ND == 3 ? r / n : 0;
+  x = 2 * xh + ((y + z + c) & 1);
+}
+
+// residual f - (lap(phi) - lambda phi) of one fine cell
+template <int ND>
+__device__ __forceinline__ double resid(const double* p, const double* rhs, int x, int y, int z, int n, int bc,
+                                        double ih2, double lam) {
+  const int i = (z * n + y) * n + x;
+  return rhs[i] - (lap_at<ND>(p, x, y, z, n, bc, ih2) - lam * p[i]);
+}
+
+// coarse cell (xc, yc, zc): mean of the children's residuals
+template <int ND>
+__device__ __forceinline__ double restrict_cell(const double* p, const double* rhs, int xc, int yc, int zc, int n,
+                                                int bc, double ih2, double lam) {
+  double s = 0.0;
+#pragma unroll
+  for (int dz = 0; dz < (ND == 3 ? 2 : 1); dz++)
+#pragma unroll
+    for (int dy = 0; dy < 2; dy++)
+#pragma unroll
+      for (int dx = 0; dx < 2; dx++) s += resid<ND>(p, rhs, 2 * xc + dx, 2 * yc + dy, 2 * zc + dz, n, bc, ih2, lam);
+  return s * (ND == 3 ? 0.125 : 0.25);
+}
+
+// bi/trilinear interpolation of the coarse correction at fine cell (x, y, z):
+// weight 3/4 on the parent and 1/4 on the parent's neighbour on the side of
+// the fine cell, per direction (boundary rule as for the stencil)
+template <int ND>
+__device__ __forceinline__ double prolong_cell(const double* e, int x, int y, int z, int nc, int bc) {
+  const int xc = x >> 1, yc = y >> 1, zc = z >> 1;
+  const int xn = (x & 1) ? ip(xc, nc, bc) : im(xc, nc, bc);
+  const int yn = (y & 1) ? ip(yc, nc, bc) : im(yc, nc, bc);
+  auto plane = [&](int zz) {
+    const double a = 0.75 * e[(zz * nc + yc) * nc + xc] + 0.25 * e[(zz * nc + yc) * nc + xn];
+    const double b = 0.75 * e[(zz * nc + yn) * nc + xc] + 0.25 * e[(zz * nc + yn) * nc + xn];
+    return 0.75 * a + 0.25 * b;
+  };
+  if constexpr (ND == 2) {
+    return plane(0);
+  } else {
+    const int zn = (z & 1) ? ip(zc, nc, bc) : im(zc, nc, bc);
+    return 0.75 * plane(zc) + 0.25 * plane(zn);
+  }
+}
+
+__device__ __forceinline__ double par_ih2(const MgDev& g, int l) { return g.par[PAR_IH2 + l]; }
+__device__ __forceinline__ double par_idiag(const MgDev& g, int f, int l) { return g.par[PAR_IDIAG + f * MG_MAXL + l]; }
+__device__ __forceinline__ double par_lam(const MgDev& g, int f) { return g.par[PAR_LAM + f]; }
+
+// ---- level kernels (HBM levels above the tail) ---------------------------
+
+template <int ND>
+__global__ void __launch_bounds__(256) k_mg_smooth(MgDev g, int l, int c) {
+  const int f = blockIdx.y;
+  const int n = g.n[l];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (g.cells[l] >> 1)) return;
+  int x, y, z;
+  colour_cell<ND>(t, n, c, x, y, z);
+  gs_cell<ND>(g.phi[f][l], g.f[f][l], x, y, z, n, g.bc, par_ih2(g, l), par_idiag(g, f, l));
+}
+
+template <int ND>
+__global__ void __launch_bounds__(256) k_mg_restrict(MgDev g, int l) {
+  const int f = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.cells[l + 1]) return;
+  int x, y, z;
+  decode<ND>(t, g.n[l + 1], x, y, z);
+  g.f[f][l + 1][t] = restrict_cell<ND>(g.phi[f][l], g.f[f][l], x, y, z, g.n[l], g.bc, par_ih2(g, l), par_lam(g, f));
+  g.phi[f][l + 1][t] = 0.0;
+}
+
+template <int ND>
+__global__ void __launch_bounds__(256) k_mg_prolong(MgDev g, int l) {
+  const int f = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.cells[l]) return;
+  int x, y, z;
+  decode<ND>(t, g.n[l], x, y, z);
+  g.phi[f][l][t] += prolong_cell<ND>(g.phi[f][l + 1], x, y, z, g.n[l + 1], g.bc);
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+// max |residual| (and with with_f, max |f|) of level 0 per field, folded as
+// bit patterns of non-negative doubles (NaN sorts above every number)
+template <int ND>
+__global__ void __launch_bounds__(256) k_mg_resnorm(MgDev g, int with_f) {
+  __shared__ unsigned long long sr[4], sf[4];
+  const int f = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long br = 0, bf = 0;
+  if (t < g.cells[0]) {
+    int x, y, z;
+    decode<ND>(t, g.n[0], x, y, z);
+    const double r = resid<ND>(g.phi[f][0], g.f[f][0], x, y, z, g.n[0], g.bc, par_ih2(g, 0), par_lam(g, f));
+    br = (unsigned long long)__double_as_longlong(fabs(r));
+    bf = (unsigned long long)__double_as_longlong(fabs(g.f[f][0][t]));
+  }
+  br = wave_max_u64(br);
+  bf = wave_max_u64(bf);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sr[w] = br;
+    sf[w] = bf;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long a = sr[0], b = sf[0];
+    for (int i = 1; i < 4; i++) {
+      a = sr[i] > a ? sr[i] : a;
+      b = sf[i] > b ? sf[i] : b;
+    }
+    atomicMax(&g.red[2 * f], a);
+    if (with_f) atomicMax(&g.red[2 * f + 1], b);
+  }
+}
+
+__global__ void k_mg_fill_u64(unsigned long long* p, int n, unsigned long long v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_mg_set(double* dst, MgPar v) {
+  const int i = threadIdx.x;
+  if (i < PAR_COUNT) dst[i] = v.v[i];
+}
+
+// ---- the coarse tail: every level from `top` down, one workgroup per field,
+// all levels in LDS -------------------------------------------------------
+
+template <int ND>
+__device__ void tail_sweeps(const MgDev& g, double* P, const double* F, int l, int f, int sweeps) {
+  const int n = g.n[l], half = g.cells[l] >> 1;
+  const double ih2 = par_ih2(g, l), idg = par_idiag(g, f, l);
+  for (int s = 0; s < sweeps; s++)
+    for (int c = 0; c < 2; c++) {
+      for (int t = threadIdx.x; t < half; t += blockDim.x) {
+        int x, y, z;
+        colour_cell<ND>(t, n, c, x, y, z);
+        gs_cell<ND>(P, F, x, y, z, n, g.bc, ih2, idg);
+      }
+      __syncthreads();
+    }
+}
+
+// exact solve on the coarsest grid (2 cells per side): per direction the
+// operator couples the two cells as c [[-1, 1], [1, -1]] (c = 1/h^2 with the
+// mirrored Neumann ghost, 2/h^2 with the periodic wrap), so the 2^d Walsh
+// patterns (-1)^popcount(k & cell) are its eigenvectors, with eigenvalue
+// -2c per set bit of k, minus lambda.
+template <int ND>
+__device__ void coarse_exact(const MgDev& g, double* P, const double* F, int l, int f) {
+  constexpr int C = 1 << ND;
+  if (threadIdx.x == 0) {
+    const double c2 = 2.0 * (g.bc == AMRV_MG_PERIODIC ? 2.0 : 1.0) * par_ih2(g, l);
+    const double lam = par_lam(g, f);
+    double hat[C];
+#pragma unroll
+    for (int k = 0; k < C; k++) {
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < C; c++) s += (__popc(k & c) & 1) ? -F[c] : F[c];
+      double mu = -lam;
+#pragma unroll
+      for (int d = 0; d < ND; d++)
+        if ((k >> d) & 1) mu -= c2;
+      hat[k] = s / (mu * C);
+    }
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < C; k++) s += (__popc(k & c) & 1) ? -hat[k] : hat[k];
+      P[c] = s;
+    }
+  }
+  __syncthreads();
+}
+
+template <int ND>
+__global__ void __launch_bounds__(TAIL_THREADS) k_mg_tail(MgDev g, int top, int pre, int post) {
+  extern __shared__ double lds[];
+  const int f = blockIdx.x;
+  auto P = [&](int l) { return lds + g.loff[l]; };
+  auto F = [&](int l) { return lds + g.loff[l] + g.cells[l]; };
+  for (int i = threadIdx.x; i < g.cells[top]; i += blockDim.x) {
+    P(top)[i] = g.phi[f][top][i];
+    F(top)[i] = g.f[f][top][i];
+  }
+  __syncthreads();
+  const int last = g.nlev - 1;
+  for (int l = top; l < last; l++) {
+    tail_sweeps<ND>(g, P(l), F(l), l, f, pre);
+    const double ih2 = par_ih2(g, l), lam = par_lam(g, f);
+    for (int t = threadIdx.x; t < g.cells[l + 1]; t += blockDim.x) {
+      int x, y, z;
+      decode<ND>(t, g.n[l + 1], x, y, z);
+      F(l + 1)[t] = restrict_cell<ND>(P(l), F(l), x, y, z, g.n[l], g.bc, ih2, lam);
+      P(l + 1)[t] = 0.0;
+    }
+    __syncthreads();
+  }
+  coarse_exact<ND>(g, P(last), F(last), last, f);
+  for (int l = last - 1; l >= top; l--) {
+    for (int t = threadIdx.x; t < g.cells[l]; t += blockDim.x) {
+      int x, y, z;
+      decode<ND>(t, g.n[l], x, y, z);
+      P(l)[t] += prolong_cell<ND>(P(l + 1), x, y, z, g.n[l + 1], g.bc);
+    }
+    __syncthreads();
+    tail_sweeps<ND>(g, P(l), F(l), l, f, post);
+  }
+  for (int i = threadIdx.x; i < g.cells[top]; i += blockDim.x) g.phi[f][top][i] = P(top)[i];
+}
+
+// ---- reaction-diffusion (Sec. 3.4) ---------------------------------------
+
+__device__ __forceinline__ void react(const RdK& p, double u, double v, double& ru, double& rv) {
+  if (p.model == AMRV_RD_SCHNAKENBERG) {
+    const double uuv = (u * u) * v;
+    ru = p.p1 * ((p.p2 - u) + uuv);
+    rv = p.p1 * (p.p3 - uuv);
+  } else {
+    const double uvv = u * (v * v);
+    ru = p.p1 * (1.0 - u) - uvv;
+    rv = uvv - (p.p1 + p.p2) * v;
+  }
+}
+
+// out = base + c F(src), F = F0 + D lap (explicit Euler and midpoint stages)
+template <int ND>
+__global__ void __launch_bounds__(256) k_rd_explicit(MgDev g, RdK p, const double* bu, const double* bv,
+                                                     const double* su, const double* sv, double* ou, double* ov,
+                                                     double c) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.cells[0]) return;
+  int x, y, z;
+  decode<ND>(t, g.n[0], x, y, z);
+  const double ih2 = par_ih2(g, 0);
+  double ru, rv;
+  react(p, su[t], sv[t], ru, rv);
+  const double fu = ru + p.Du * lap_at<ND>(su, x, y, z, g.n[0], g.bc, ih2);
+  const double fv = rv + p.Dv * lap_at<ND>(sv, x, y, z, g.n[0], g.bc, ih2);
+  ou[t] = bu[t] + c * fu;
+  ov[t] = bv[t] + c * fv;
+}
+
+// split scheme: f = -lambda (w + dt F0(w)), initial guess w
+template <int ND>
+__global__ void __launch_bounds__(256) k_rd_split_rhs(MgDev g, RdK p, const double* u, const double* v, double dt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.cells[0]) return;
+  double ru, rv;
+  react(p, u[t], v[t], ru, rv);
+  g.f[0][0][t] = -par_lam(g, 0) * (u[t] + dt * ru);
+  g.f[1][0][t] = -par_lam(g, 1) * (v[t] + dt * rv);
+  g.phi[0][0][t] = u[t];
+  g.phi[1][0][t] = v[t];
+}
+
+// IMEX first stage: f = -lambda ((w + dt F0(w)) + (dt/2) D lap(w)), and
+// F(w) kept for the second stage
+template <int ND>
+__global__ void __launch_bounds__(256) k_rd_imex_rhs(MgDev g, RdK p, const double* u, const double* v, double* Eu,
+                                                     double* Ev, double dt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.cells[0]) return;
+  int x, y, z;
+  decode<ND>(t, g.n[0], x, y, z);
+  const double ih2 = par_ih2(g, 0);
+  double ru, rv;
+  react(p, u[t], v[t], ru, rv);
+  const double du = p.Du * lap_at<ND>(u, x, y, z, g.n[0], g.bc, ih2);
+  const double dv = p.Dv * lap_at<ND>(v, x, y, z, g.n[0], g.bc, ih2);
+  Eu[t] = ru + du;
+  Ev[t] = rv + dv;
+  const double hdt = 0.5 * dt;
+  g.f[0][0][t] = -par_lam(g, 0) * ((u[t] + dt * ru) + hdt * du);
+  g.f[1][0][t] = -par_lam(g, 1) * ((v[t] + dt * rv) + hdt * dv);
+  g.phi[0][0][t] = u[t];
+  g.phi[1][0][t] = v[t];
+}
+
+// IMEX second stage: w1 = w + (dt/2) (F(w) + F(w*)), w* = the solve's phi
+template <int ND>
+__global__ void __launch_bounds__(256) k_rd_imex_final(MgDev g, RdK p, double* u, double* v, const double* Eu,
+                                                       const double* Ev, double dt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.cells[0]) return;
+  int x, y, z;
+  decode<ND>(t, g.n[0], x, y, z);
+  const double ih2 = par_ih2(g, 0);
+  const double* su = g.phi[0][0];
+  const double* sv = g.phi[1][0];
+  double ru, rv;
+  react(p, su[t], sv[t], ru, rv);
+  const double fu = ru + p.Du * lap_at<ND>(su, x, y, z, g.n[0], g.bc, ih2);
+  const double fv = rv + p.Dv * lap_at<ND>(sv, x, y, z, g.n[0], g.bc, ih2);
+  const double hdt = 0.5 * dt;
+  u[t] = u[t] + hdt * (Eu[t] + fu);
+  v[t] = v[t] + hdt * (Ev[t] + fv);
+}
+
+int blocks_of(int n) { return (n + 255) / 256; }
+
+}  // namespace
+
+struct amrv_mg {
+  amrv_mg_config cfg{};
+  MgDev g{};
+  hipStream_t st = nullptr;
+  double* par = nullptr;
+  unsigned long long* red = nullptr;
+  unsigned long long* hred = nullptr;  // pinned copy of red
+  double* tmp[4] = {nullptr, nullptr, nullptr, nullptr};
+  int tail = 0;
+  size_t tail_lds = 0;
+  hipGraphExec_t gexec = nullptr;
+  bool profile = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double prof_ms = 0.0;
+  int64_t prof_cycles = 0;
+  double par_lam[NFMAX] = {-1.0, -1.0};
+};
+
+namespace {
+
+using amrv::set_error;
+
+int hip_err(hipError_t e, const char* where) {
+  return set_error(AMRV_EDEVICE, (std::string(where) + ": " + hipGetErrorString(e)).c_str());
+}
+
+#define MGCHK(expr)                                \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) return hip_err(e_, #expr); \
+  } while (0)
+
+constexpr size_t ALIGN = 256;
+size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+int validate(const amrv_mg_config* c) {
+  if (!c) return set_error(AMRV_EINVAL, "null config");
+  if (c->ndim != 2 && c->ndim != 3) return set_error(AMRV_EINVAL, "ndim must be 2 or 3");
+  const int nmax = c->ndim == 2 ? 8192 : 512;
+  if (!is_pow2(c->n) || c->n < 4 || c->n > nmax)
+    return set_error(AMRV_EINVAL, "n must be a power of two in 4..8192 (2D) or 4..512 (3D)");
+  if (c->bc != AMRV_MG_PERIODIC && c->bc != AMRV_MG_NEUMANN) return set_error(AMRV_EINVAL, "unknown boundary");
+  if (c->nfields < 1 || c->nfields > NFMAX) return set_error(AMRV_EINVAL, "nfields must be 1 or 2");
+  if (c->pre_sweeps < 1 || c->pre_sweeps > 8 || c->post_sweeps < 1 || c->post_sweeps > 8)
+    return set_error(AMRV_EINVAL, "pre and post sweeps must be in 1..8");
+  if (!(c->length > 0.0) || !std::isfinite(c->length)) return set_error(AMRV_EINVAL, "length must be positive");
+  return 0;
+}
+
+struct MgLayout {
+  int nlev = 0;
+  size_t off_phi[NFMAX][MG_MAXL]{}, off_f[NFMAX][MG_MAXL]{}, off_tmp[4]{}, off_par = 0, off_red = 0, total = 0;
+};
+
+MgLayout layout(const amrv_mg_config* c) {
+  MgLayout L;
+  int lv = 0;
+  for (int n = c->n; n >= 2; n >>= 1) lv++;
+  L.nlev = lv;
+  size_t o = 0;
+  for (int f = 0; f < c->nfields; f++)
+    for (int l = 0; l < lv; l++) {
+      size_t cells = 1;
+      for (int d = 0; d < c->ndim; d++) cells *= (size_t)(c->n >> l);
+      L.off_phi[f][l] = o;
+      o += up(cells * 8);
+      L.off_f[f][l] = o;
+      o += up(cells * 8);
+    }
+  size_t c0 = 1;
+  for (int d = 0; d < c->ndim; d++) c0 *= (size_t)c->n;
+  for (int i = 0; i < 4; i++) {
+    L.off_tmp[i] = o;
+    o += up(c0 * 8);
+  }
+  L.off_par = o;
+  o += up(PAR_COUNT * 8);
+  L.off_red = o;
+  o += up(2 * NFMAX * 8);
+  L.total = o;
+  return L;
+}
+
+template <int ND>
+void enqueue_vcycle_nd(amrv_mg* m) {
+  const MgDev& g = m->g;
+  const int nf = g.nf;
+  const int pre = m->cfg.pre_sweeps, post = m->cfg.post_sweeps;
+  for (int l = 0; l < m->tail; l++) {
+    for (int s = 0; s < pre; s++)
+      for (int c = 0; c < 2; c++)
+        hipLaunchKernelGGL(k_mg_smooth<ND>, dim3(blocks_of(g.cells[l] >> 1), nf), dim3(256), 0, m->st, g, l, c);
+    hipLaunchKernelGGL(k_mg_restrict<ND>, dim3(blocks_of(g.cells[l + 1]), nf), dim3(256), 0, m->st, g, l);
+  }
+  hipLaunchKernelGGL(k_mg_tail<ND>, dim3(nf), dim3(TAIL_THREADS), m->tail_lds, m->st, g, m->tail, pre, post);
+  for (int l = m->tail - 1; l >= 0; l--) {
+    hipLaunchKernelGGL(k_mg_prolong<ND>, dim3(blocks_of(g.cells[l]), nf), dim3(256), 0, m->st, g, l);
+    for (int s = 0; s < post; s++)
+      for (int c = 0; c < 2; c++)
+        hipLaunchKernelGGL(k_mg_smooth<ND>, dim3(blocks_of(g.cells[l] >> 1), nf), dim3(256), 0, m->st, g, l, c);
+  }
+}
+
+// residual norms of level 0 into the pinned host copy (with_f: also max |f|)
+template <int ND>
+void enqueue_norms_nd(amrv_mg* m, int with_f) {
+  const MgDev& g = m->g;
+  if (with_f) {
+    hipLaunchKernelGGL(k_mg_fill_u64, dim3(1), dim3(64), 0, m->st, m->red, 2 * NFMAX, 0ull);
+  } else {
+    for (int f = 0; f < g.nf; f++) hipLaunchKernelGGL(k_mg_fill_u64, dim3(1), dim3(64), 0, m->st, m->red + 2 * f, 1, 0ull);
+  }
+  hipLaunchKernelGGL(k_mg_resnorm<ND>, dim3(blocks_of(g.cells[0]), g.nf), dim3(256), 0, m->st, g, with_f);
+  (void)hipMemcpyAsync(m->hred, m->red, 2 * NFMAX * sizeof(unsigned long long), hipMemcpyDeviceToHost, m->st);
+}
+
+void enqueue_vcycle(amrv_mg* m) {
+  if (m->g.nd == 2) {
+    enqueue_vcycle_nd<2>(m);
+    enqueue_norms_nd<2>(m, 0);
+  } else {
+    enqueue_vcycle_nd<3>(m);
+    enqueue_norms_nd<3>(m, 0);
+  }
+}
+
+int set_params(amrv_mg* m, const double* lam) {
+  MgPar P{};
+  const double L = m->cfg.length;
+  for (int l = 0; l < m->g.nlev; l++) {
+    const double r = m->g.n[l] / L;
+    P.v[PAR_IH2 + l] = r * r;
+  }
+  for (int f = 0; f < m->g.nf; f++) {
+    P.v[PAR_LAM + f] = lam[f];
+    for (int l = 0; l < m->g.nlev; l++)
+      P.v[PAR_IDIAG + f * MG_MAXL + l] = 1.0 / (2.0 * m->g.nd * P.v[PAR_IH2 + l] + lam[f]);
+    m->par_lam[f] = lam[f];
+  }
+  hipLaunchKernelGGL(k_mg_set, dim3(1), dim3(64), 0, m->st, m->par, P);
+  MGCHK(hipGetLastError());
+  return 0;
+}
+
+double bits_to_double(unsigned long long b) {
+  double d;
+  std::memcpy(&d, &b, 8);
+  return d;
+}
+
+// the V-cycle loop on level-0 buffers already filled; returns 0, or
+// AMRV_ENOTCONVERGED / AMRV_ENONPHYSICAL
+int run_cycles(amrv_mg* m, double tol, int max_cycles, int* cycles, double* res_out, double* f_out) {
+  const int nf = m->g.nf;
+  if (m->g.nd == 2)
+    enqueue_norms_nd<2>(m, 1);
+  else
+    enqueue_norms_nd<3>(m, 1);
+  MGCHK(hipGetLastError());
+  MGCHK(hipStreamSynchronize(m->st));
+  double fmax[NFMAX] = {0, 0}, res[NFMAX] = {0, 0};
+  for (int f = 0; f < nf; f++) fmax[f] = bits_to_double(m->hred[2 * f + 1]);
+  auto done = [&]() {
+    bool ok = true;
+    for (int f = 0; f < nf; f++) {
+      res[f] = bits_to_double(m->hred[2 * f]);
+      ok = ok && (res[f] <= tol * fmax[f]);
+    }
+    return ok;
+  };
+  int c = 0;
+  bool ok = done();
+  for (int f = 0; f < nf; f++)
+    if (std::isnan(res[f]) || std::isnan(fmax[f])) {
+      if (cycles) *cycles = 0;
+      return set_error(AMRV_ENONPHYSICAL, "NaN in the multigrid right-hand side or initial guess");
+    }
+  while (!ok && c < max_cycles) {
+    if (m->profile) MGCHK(hipEventRecord(m->e0, m->st));
+    if (m->cfg.use_graph) {
+      if (!m->gexec) {
+        hipGraph_t gr;
+        MGCHK(hipStreamBeginCapture(m->st, hipStreamCaptureModeThreadLocal));
+        enqueue_vcycle(m);
+        MGCHK(hipStreamEndCapture(m->st, &gr));
+        hipError_t e = hipGraphInstantiate(&m->gexec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        MGCHK(e);
+      }
+      MGCHK(hipGraphLaunch(m->gexec, m->st));
+    } else {
+      enqueue_vcycle(m);
+      MGCHK(hipGetLastError());
+    }
+    if (m->profile) MGCHK(hipEventRecord(m->e1, m->st));
+    MGCHK(hipStreamSynchronize(m->st));
+    if (m->profile) {
+      float ms = 0.0f;
+      MGCHK(hipEventElapsedTime(&ms, m->e0, m->e1));
+      m->prof_ms += ms;
+      m->prof_cycles++;
+    }
+    c++;
+    ok = done();
+    for (int f = 0; f < nf; f++)
+      if (std::isnan(res[f])) {
+        if (cycles) *cycles = c;
+        return set_error(AMRV_ENONPHYSICAL, "NaN in the multigrid residual");
+      }
+  }
+  if (cycles) *cycles = c;
+  for (int f = 0; f < nf; f++) {
+    if (res_out) res_out[f] = res[f];
+    if (f_out) f_out[f] = fmax[f];
+  }
+  if (!ok) return set_error(AMRV_ENOTCONVERGED, "multigrid residual above tol after max_cycles V-cycles");
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t amrv_mg_workspace_bytes(const amrv_mg_config* cfg) {
+  if (validate(cfg)) return 0;
+  return layout(cfg).total;
+}
+
+int amrv_mg_create(const amrv_mg_config* cfg, void* workspace, size_t bytes, void* stream, amrv_mg** out) {
+  if (!out) return set_error(AMRV_EINVAL, "null argument");
+  *out = nullptr;
+  if (int rc = validate(cfg)) return rc;
+  if (!workspace) return set_error(AMRV_EINVAL, "null workspace");
+  if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) return set_error(AMRV_EINVAL, "workspace must be 256-byte aligned");
+  const MgLayout L = layout(cfg);
+  if (bytes < L.total) return set_error(AMRV_ENOMEM, ("workspace too small: need " + std::to_string(L.total)).c_str());
+  if (cfg->use_graph && !stream) return set_error(AMRV_EINVAL, "graph replay needs a stream other than the null stream");
+  amrv_mg* m = new amrv_mg;
+  m->cfg = *cfg;
+  m->st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(workspace);
+  MgDev& g = m->g;
+  g.nd = cfg->ndim;
+  g.bc = cfg->bc;
+  g.nlev = L.nlev;
+  g.nf = cfg->nfields;
+  for (int l = 0; l < L.nlev; l++) {
+    g.n[l] = cfg->n >> l;
+    long long c = 1;
+    for (int d = 0; d < cfg->ndim; d++) c *= g.n[l];
+    g.cells[l] = (int)c;
+    for (int f = 0; f < cfg->nfields; f++) {
+      g.phi[f][l] = reinterpret_cast<double*>(base + L.off_phi[f][l]);
+      g.f[f][l] = reinterpret_cast<double*>(base + L.off_f[f][l]);
+    }
+  }
+  for (int i = 0; i < 4; i++) m->tmp[i] = reinterpret_cast<double*>(base + L.off_tmp[i]);
+  m->par = reinterpret_cast<double*>(base + L.off_par);
+  m->red = reinterpret_cast<unsigned long long*>(base + L.off_red);
+  g.par = m->par;
+  g.red = m->red;
+  // the tail: the first level of at most TAIL_CELLS cells, and every level below
+  int tail = 0;
+  while (g.cells[tail] > TAIL_CELLS) tail++;
+  m->tail = tail;
+  int off = 0;
+  for (int l = tail; l < L.nlev; l++) {
+    g.loff[l] = off;
+    off += 2 * g.cells[l];
+  }
+  m->tail_lds = (size_t)off * sizeof(double);
+  hipError_t e = cfg->ndim == 2
+                     ? hipFuncSetAttribute(reinterpret_cast<const void*>(k_mg_tail<2>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->tail_lds)
+                     : hipFuncSetAttribute(reinterpret_cast<const void*>(k_mg_tail<3>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->tail_lds);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&m->hred), 2 * NFMAX * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipEventCreate(&m->e0);
+  if (e == hipSuccess) e = hipEventCreate(&m->e1);
+  if (e != hipSuccess) {
+    int rc = hip_err(e, "amrv_mg_create");
+    amrv_mg_destroy(m);
+    return rc;
+  }
+  std::memset(m->hred, 0, 2 * NFMAX * sizeof(unsigned long long));
+  *out = m;
+  return 0;
+}
+
+int amrv_mg_destroy(amrv_mg* m) {
+  if (!m) return 0;
+  if (m->st) (void)hipStreamSynchronize(m->st);
+  if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+  if (m->hred) (void)hipHostFree(m->hred);
+  if (m->e0) (void)hipEventDestroy(m->e0);
+  if (m->e1) (void)hipEventDestroy(m->e1);
+  delete m;
+  return 0;
+}
+
+int amrv_mg_solve(amrv_mg* m, const double* f, double* phi, const double* lambda, double tol, int32_t max_cycles,
+                  int32_t* cycles, double* res_max, double* f_max) {
+  if (!m || !f || !phi || !lambda) return set_error(AMRV_EINVAL, "null argument");
+  if (!(tol > 0.0)) return set_error(AMRV_EINVAL, "tol must be positive");
+  if (max_cycles < 0) return set_error(AMRV_EINVAL, "max_cycles must be >= 0");
+  for (int i = 0; i < m->g.nf; i++)
+    if (!(lambda[i] > 0.0) || !std::isfinite(lambda[i])) return set_error(AMRV_EINVAL, "lambda must be positive and finite");
+  if (int rc = set_params(m, lambda)) return rc;
+  const size_t bytes = (size_t)m->g.cells[0] * sizeof(double);
+  for (int i = 0; i < m->g.nf; i++) {
+    MGCHK(hipMemcpyAsync(m->g.f[i][0], f + (size_t)i * m->g.cells[0], bytes, hipMemcpyDeviceToDevice, m->st));
+    MGCHK(hipMemcpyAsync(m->g.phi[i][0], phi + (size_t)i * m->g.cells[0], bytes, hipMemcpyDeviceToDevice, m->st));
+  }
+  int c = 0;
+  const int rc = run_cycles(m, tol, max_cycles, &c, res_max, f_max);
+  if (cycles) *cycles = c;
+  for (int i = 0; i < m->g.nf; i++)
+    MGCHK(hipMemcpyAsync(phi + (size_t)i * m->g.cells[0], m->g.phi[i][0], bytes, hipMemcpyDeviceToDevice, m->st));
+  MGCHK(hipStreamSynchronize(m->st));
+  return rc;
+}
+
+int amrv_rd_step(amrv_mg* m, const amrv_rd_params* p, int32_t scheme, double dt, int32_t nsteps, double* u, double* v,
+                 double tol, int32_t max_cycles, int32_t* cycles_total, double* res_max) {
+  if (!m || !p || !u || !v) return set_error(AMRV_EINVAL, "null argument");
+  if (p->model != AMRV_RD_SCHNAKENBERG && p->model != AMRV_RD_GRAY_SCOTT) return set_error(AMRV_EINVAL, "unknown model");
+  if (!(p->Du > 0.0) || !(p->Dv > 0.0)) return set_error(AMRV_EINVAL, "diffusion coefficients must be positive");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(AMRV_EINVAL, "dt must be positive and finite");
+  if (nsteps < 0) return set_error(AMRV_EINVAL, "nsteps must be >= 0");
+  if (scheme < AMRV_RD_EULER || scheme > AMRV_RD_IMEX) return set_error(AMRV_EINVAL, "unknown scheme");
+  const bool implicit = scheme == AMRV_RD_SPLIT || scheme == AMRV_RD_IMEX;
+  if (implicit && m->g.nf != 2) return set_error(AMRV_EINVAL, "split and IMEX steps need a solver with nfields = 2");
+  if (implicit && (!(tol > 0.0) || max_cycles < 0)) return set_error(AMRV_EINVAL, "bad tol or max_cycles");
+  RdK k{p->model, p->Du, p->Dv, p->p1, p->p2, p->p3};
+  const MgDev& g = m->g;
+  const int nb = blocks_of(g.cells[0]);
+  const size_t bytes = (size_t)g.cells[0] * sizeof(double);
+  double lam[2] = {1.0, 1.0};
+  if (scheme == AMRV_RD_SPLIT) {
+    lam[0] = 1.0 / (dt * p->Du);
+    lam[1] = 1.0 / (dt * p->Dv);
+  } else if (scheme == AMRV_RD_IMEX) {
+    lam[0] = 2.0 / (dt * p->Du);
+    lam[1] = 2.0 / (dt * p->Dv);
+  }
+  if (int rc = set_params(m, lam)) return rc;
+  int total = 0;
+  const bool d2 = g.nd == 2;
+  for (int s = 0; s < nsteps; s++) {
+    if (scheme == AMRV_RD_EULER || scheme == AMRV_RD_MIDPOINT) {
+      double *tu = m->tmp[0], *tv = m->tmp[1];
+      if (scheme == AMRV_RD_EULER) {
+        hipLaunchKernelGGL(d2 ? k_rd_explicit<2> : k_rd_explicit<3>, dim3(nb), dim3(256), 0, m->st, g, k, u, v, u, v,
+                           tu, tv, dt);
+      } else {
+        double *hu = m->tmp[2], *hv = m->tmp[3];
+        hipLaunchKernelGGL(d2 ? k_rd_explicit<2> : k_rd_explicit<3>, dim3(nb), dim3(256), 0, m->st, g, k, u, v, u, v,
+                           hu, hv, 0.5 * dt);
+        hipLaunchKernelGGL(d2 ? k_rd_explicit<2> : k_rd_explicit<3>, dim3(nb), dim3(256), 0, m->st, g, k, u, v, hu,
+                           hv, tu, tv, dt);
+      }
+      MGCHK(hipGetLastError());
+      MGCHK(hipMemcpyAsync(u, tu, bytes, hipMemcpyDeviceToDevice, m->st));
+      MGCHK(hipMemcpyAsync(v, tv, bytes, hipMemcpyDeviceToDevice, m->st));
+      continue;
+    }
+    if (scheme == AMRV_RD_SPLIT)
+      hipLaunchKernelGGL(d2 ? k_rd_split_rhs<2> : k_rd_split_rhs<3>, dim3(nb), dim3(256), 0, m->st, g, k, u, v, dt);
+    else
+      hipLaunchKernelGGL(d2 ? k_rd_imex_rhs<2> : k_rd_imex_rhs<3>, dim3(nb), dim3(256), 0, m->st, g, k, u, v,
+                         m->tmp[0], m->tmp[1], dt);
+    MGCHK(hipGetLastError());
+    int c = 0;
+    const int rc = run_cycles(m, tol, max_cycles, &c, res_max, nullptr);
+    total += c;
+    if (rc) {
+      if (cycles_total) *cycles_total = total;
+      return rc;
+    }
+    if (scheme == AMRV_RD_SPLIT) {
+      MGCHK(hipMemcpyAsync(u, g.phi[0][0], bytes, hipMemcpyDeviceToDevice, m->st));
+      MGCHK(hipMemcpyAsync(v, g.phi[1][0], bytes, hipMemcpyDeviceToDevice, m->st));
+    } else {
+      hipLaunchKernelGGL(d2 ? k_rd_imex_final<2> : k_rd_imex_final<3>, dim3(nb), dim3(256), 0, m->st, g, k, u, v,
+                         m->tmp[0], m->tmp[1], dt);
+      MGCHK(hipGetLastError());
+    }
+  }
+  if (cycles_total) *cycles_total = total;
+  MGCHK(hipStreamSynchronize(m->st));
+  return 0;
+}
+
+int amrv_mg_profile(amrv_mg* m, int32_t enable) {
+  if (!m) return set_error(AMRV_EINVAL, "null argument");
+  m->profile = enable != 0;
+  return 0;
+}
+
+int amrv_mg_profile_read(amrv_mg* m, double* ms_total, int64_t* cycles) {
+  if (!m || !ms_total || !cycles) return set_error(AMRV_EINVAL, "null argument");
+  *ms_total = m->prof_ms;
+  *cycles = m->prof_cycles;
+  m->prof_ms = 0.0;
+  m->prof_cycles = 0;
+  return 0;
+}
+
+}  // extern "C"

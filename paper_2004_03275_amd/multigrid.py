@@ -1,0 +1,107 @@
+"""Python face of libamrv's multigrid Helmholtz solver and reaction-diffusion
+steps (include/amrv_mg.h): argument marshalling only; every step runs in the
+HIP kernels.  Fields are float64 device tensors of shape [n]*ndim (index
+[z][y][x], x fastest)."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+PERIODIC, NEUMANN = 0, 1
+SCHNAKENBERG, GRAY_SCOTT = 0, 1
+EULER, MIDPOINT, SPLIT, IMEX = 0, 1, 2, 3
+
+
+def rd_params(model: int, Du: float, Dv: float, p1: float, p2: float, p3: float = 0.0) -> N.RdParams:
+    return N.RdParams(model=model, pad=0, Du=Du, Dv=Dv, p1=p1, p2=p2, p3=p3)
+
+
+class GpuMultigrid:
+    """A solver for one grid shape on one GPU (workspace from torch)."""
+
+    def __init__(self, ndim: int, n: int, bc: int, length: float, nfields: int = 2, pre: int = 2, post: int = 2,
+                 graph: bool = True, device: str | torch.device = "cuda:0",
+                 stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("GpuMultigrid needs a ROCm GPU (torch.cuda.is_available() is False)")
+        L = N.lib()
+        self.cfg = N.MgConfig(ndim=ndim, n=n, bc=bc, nfields=nfields, pre_sweeps=pre, post_sweeps=post,
+                              use_graph=1 if graph else 0, pad=0, length=length)
+        nbytes = L.amrv_mg_workspace_bytes(ctypes.byref(self.cfg))
+        if nbytes == 0:
+            raise N.AmrvError(N.EINVAL, L.amrv_last_error().decode())
+        self.device = torch.device(device)
+        self.ndim, self.n, self.nfields = ndim, n, nfields
+        self.shape = (n,) * ndim
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+            self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self._h = ctypes.c_void_p()
+        N.check(L.amrv_mg_create(ctypes.byref(self.cfg), ctypes.c_void_p(self.workspace.data_ptr()), int(nbytes),
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._h)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            N.lib().amrv_mg_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, t: torch.Tensor, count: int) -> torch.Tensor:
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError("expected a contiguous float64 device tensor")
+        if t.numel() != count:
+            raise ValueError(f"expected {count} values, got {t.numel()}")
+        return t
+
+    def solve(self, f: torch.Tensor, phi: torch.Tensor, lam, tol: float = 1e-7, max_cycles: int = 50):
+        """lap(phi) - lam phi = f for the nfields fields stacked in f and phi
+        (phi: initial guess in, solution out).  Returns (cycles, max
+        residual per field, max |f| per field)."""
+        cells = self.n ** self.ndim
+        self._dev(f, cells * self.nfields)
+        self._dev(phi, cells * self.nfields)
+        lam = np.ascontiguousarray(np.broadcast_to(np.asarray(lam, dtype=np.float64), (self.nfields,)))
+        cyc = ctypes.c_int32()
+        res = np.zeros(self.nfields)
+        fmax = np.zeros(self.nfields)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        N.check(N.lib().amrv_mg_solve(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(phi.data_ptr()),
+                                      lam.ctypes.data, float(tol), int(max_cycles), ctypes.byref(cyc),
+                                      res.ctypes.data, fmax.ctypes.data))
+        return cyc.value, res, fmax
+
+    def rd_step(self, u: torch.Tensor, v: torch.Tensor, dt: float, scheme: int, params: dict, nsteps: int = 1,
+                tol: float = 1e-7, max_cycles: int = 50):
+        """nsteps reaction-diffusion steps on u, v in place.  params: dict
+        with model, Du, Dv, p1, p2, p3 (the oracle's parameter dicts).
+        Returns (V-cycles summed over the steps, last residuals)."""
+        cells = self.n ** self.ndim
+        self._dev(u, cells)
+        self._dev(v, cells)
+        p = rd_params(int(params["model"]), params["Du"], params["Dv"], params["p1"], params["p2"],
+                      params.get("p3", 0.0))
+        cyc = ctypes.c_int32()
+        res = np.zeros(2)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        N.check(N.lib().amrv_rd_step(self._h, ctypes.byref(p), int(scheme), float(dt), int(nsteps),
+                                     ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(v.data_ptr()), float(tol),
+                                     int(max_cycles), ctypes.byref(cyc), res.ctypes.data))
+        return cyc.value, res
+
+    def profile(self, enable: bool = True):
+        N.check(N.lib().amrv_mg_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(summed V-cycle ms, cycles) since the last read."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        N.check(N.lib().amrv_mg_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

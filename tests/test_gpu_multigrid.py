@@ -1,0 +1,196 @@
+"""GPU (HIP, gfx950) multigrid Helmholtz solver and reaction-diffusion steps
+against the CPU oracle (oracle/rd.py), through the C-ABI (include/amrv_mg.h).
+
+Bars:
+* Helmholtz solve: lambda I - lap is an M-matrix whose rows sum to lambda,
+  so max |phi_gpu - phi_exact| <= r / lambda, r the true max residual of the
+  GPU's answer.  The GPU reports r computed in binary64; the test allows
+  twice that plus 1e-12 of max |phi| for the rounding of both sides.
+* Explicit Euler and midpoint steps: bitwise (same operation order, no
+  contraction on either side).
+* Split and IMEX steps: the solves run to tol = 1e-12, so w* is within
+  1e-12 max|f| / lambda of the exact one; IMEX's second stage multiplies that
+  by at most 1 + dt/2 (D 4 d / h^2 + reaction Lipschitz), a few hundred
+  here; over a few steps the relative difference stays below 1e-8.
+"""
+import numpy as np
+import pytest
+
+from oracle import rd as R
+from paper_2004_03275_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _mg():
+    import torch
+
+    from paper_2004_03275_amd import multigrid as M
+
+    return torch, M
+
+
+def _seeded(shape, seed):
+    return W.uniform01(seed, int(np.prod(shape))).reshape(shape) * 2.0 - 1.0
+
+
+@pytest.mark.parametrize("nd,n", [(2, 16), (2, 64), (2, 256), (3, 8), (3, 16), (3, 64)])
+@pytest.mark.parametrize("bc", [R.PERIODIC, R.NEUMANN])
+@pytest.mark.parametrize("lam", [1.0, 4000.0])
+def test_helmholtz_solve_within_the_residual_bound(nd, n, bc, lam):
+    torch, M = _mg()
+    L = 1.0
+    shape = (n,) * nd
+    f = _seeded(shape, 11 + n + nd) + np.cos(2 * np.pi * W.rd_cell_centres(nd, n, L)[0])
+    exact = R.helmholtz_solve(f, lam, L, bc)
+    mg = M.GpuMultigrid(nd, n, bc, L, nfields=1)
+    ft = torch.tensor(f, device="cuda:0").contiguous()
+    phi = torch.zeros_like(ft)
+    cycles, res, fmax = mg.solve(ft, phi, lam, tol=1e-10, max_cycles=40)
+    got = phi.cpu().numpy()
+    err = np.abs(got - exact).max()
+    bound = 2.0 * res[0] / lam + 1e-12 * np.abs(exact).max()
+    print(f"[mg] {nd}D n={n} bc={bc} lam={lam}: {cycles} cycles, res {res[0]:.2e}, err {err:.2e}, "
+          f"bound {bound:.2e}", flush=True)
+    assert fmax[0] == np.abs(f).max()
+    assert res[0] <= 1e-10 * fmax[0]
+    assert err <= bound
+    assert cycles <= 20  # V(2,2) reduces the max residual >= 3x per cycle (about 0.1 in 2D, 0.25 in 3D)
+    mg.close()
+
+
+@pytest.mark.parametrize("nd,n", [(2, 128), (3, 32)])
+def test_two_fields_graph_and_direct_launches_agree(nd, n):
+    """Both fields of one solve match separate one-field solves, and graph
+    replay matches direct launches bit for bit."""
+    torch, M = _mg()
+    shape = (n,) * nd
+    f = np.stack([_seeded(shape, 5), _seeded(shape, 6)])
+    lam = np.array([30.0, 700.0])
+    out = []
+    for graph in (True, False):
+        mg = M.GpuMultigrid(nd, n, R.NEUMANN, 2.0, nfields=2, graph=graph)
+        ft = torch.tensor(f, device="cuda:0").contiguous()
+        phi = torch.zeros_like(ft)
+        c, res, _ = mg.solve(ft, phi, lam, tol=1e-9)
+        out.append(phi.cpu().numpy())
+        mg.close()
+    assert np.array_equal(out[0], out[1])
+    for k in range(2):
+        exact = R.helmholtz_solve(f[k], lam[k], 2.0, R.NEUMANN)
+        assert np.abs(out[0][k] - exact).max() <= 2e-9 * np.abs(f[k]).max() / lam[k] + 1e-12
+
+
+def test_initial_guess_that_solves_takes_no_cycle():
+    torch, M = _mg()
+    n = 32
+    exact = R.helmholtz_solve(_seeded((n, n), 3), 50.0, 1.0, R.PERIODIC)
+    f = R.helmholtz_apply(exact, 50.0, 1.0, R.PERIODIC)
+    mg = M.GpuMultigrid(2, n, R.PERIODIC, 1.0, nfields=1)
+    phi = torch.tensor(exact, device="cuda:0").contiguous()
+    c, res, _ = mg.solve(torch.tensor(f, device="cuda:0").contiguous(), phi, 50.0, tol=1e-7)
+    assert c == 0
+    assert np.array_equal(phi.cpu().numpy(), exact)
+
+
+def _rd_case(model, nd, n):
+    if model == R.SCHNAKENBERG:
+        u, v, L = W.schnakenberg_initial(nd, n)
+        return u, v, L, R.NEUMANN, R.SCHNAKENBERG_PARAMS
+    u, v, L = W.gray_scott_initial(n)
+    return u, v, L, R.PERIODIC, R.GRAY_SCOTT_PARAMS
+
+
+@pytest.mark.parametrize("model,nd,n,dt,steps", [
+    (R.SCHNAKENBERG, 2, 64, 5e-5, 8), (R.SCHNAKENBERG, 3, 16, 2e-4, 5), (R.GRAY_SCOTT, 2, 64, 0.5, 6)])
+@pytest.mark.parametrize("scheme", [R.EULER, R.MIDPOINT])
+def test_explicit_steps_bitwise(model, nd, n, dt, steps, scheme):
+    torch, M = _mg()
+    u0, v0, L, bc, p = _rd_case(model, nd, n)
+    ru, rv = R.run(u0, v0, dt, steps, scheme, p, L, bc)
+    mg = M.GpuMultigrid(nd, n, bc, L, nfields=2)
+    u = torch.tensor(u0, device="cuda:0").contiguous()
+    v = torch.tensor(v0, device="cuda:0").contiguous()
+    mg.rd_step(u, v, dt, scheme, p, nsteps=steps)
+    gu, gv = u.cpu().numpy(), v.cpu().numpy()
+    print(f"[rd] explicit model={model} {nd}D n={n} scheme={scheme}: differing "
+          f"{int(np.count_nonzero(gu != ru) + np.count_nonzero(gv != rv))}", flush=True)
+    assert np.array_equal(gu, ru) and np.array_equal(gv, rv)
+    mg.close()
+
+
+@pytest.mark.parametrize("model,nd,n,dt,steps", [
+    (R.SCHNAKENBERG, 2, 64, 1e-3, 4), (R.SCHNAKENBERG, 2, 256, 1e-3, 3), (R.SCHNAKENBERG, 3, 32, 1e-3, 3),
+    (R.GRAY_SCOTT, 2, 128, 0.5, 4)])
+@pytest.mark.parametrize("scheme", [R.SPLIT, R.IMEX])
+def test_implicit_steps_match_the_exact_solves(model, nd, n, dt, steps, scheme):
+    torch, M = _mg()
+    u0, v0, L, bc, p = _rd_case(model, nd, n)
+    ru, rv = R.run(u0, v0, dt, steps, scheme, p, L, bc)
+    mg = M.GpuMultigrid(nd, n, bc, L, nfields=2)
+    u = torch.tensor(u0, device="cuda:0").contiguous()
+    v = torch.tensor(v0, device="cuda:0").contiguous()
+    cycles, res = mg.rd_step(u, v, dt, scheme, p, nsteps=steps, tol=1e-12, max_cycles=60)
+    gu, gv = u.cpu().numpy(), v.cpu().numpy()
+    eu = np.abs(gu - ru).max() / np.abs(ru).max()
+    ev = np.abs(gv - rv).max() / max(np.abs(rv).max(), 1e-300)
+    print(f"[rd] model={model} {nd}D n={n} scheme={scheme}: {cycles} cycles over {steps} steps, "
+          f"rel max diff u {eu:.2e} v {ev:.2e}", flush=True)
+    assert eu <= 1e-8 and ev <= 1e-8
+    assert np.abs(gu - u0).max() > 1e-6  # it moved
+    mg.close()
+
+
+def test_paper_tolerance_step_is_close_to_the_exact_step():
+    """At the paper's tol = 1e-7 (Sec. 3.4) one IMEX step of the 256^2
+    Schnakenberg run stays within the residual bound propagated through the
+    second stage."""
+    torch, M = _mg()
+    u0, v0, L, bc, p = _rd_case(R.SCHNAKENBERG, 2, 256)
+    dt = 1e-3
+    ru, rv = R.step(u0, v0, dt, R.IMEX, p, L, bc)
+    mg = M.GpuMultigrid(2, 256, bc, L, nfields=2)
+    u = torch.tensor(u0, device="cuda:0").contiguous()
+    v = torch.tensor(v0, device="cuda:0").contiguous()
+    cycles, res = mg.rd_step(u, v, dt, R.IMEX, p, nsteps=1, tol=1e-7)
+    lam = np.array([2.0 / (dt * p["Du"]), 2.0 / (dt * p["Dv"])])
+    # w* is off by at most delta = max_k res_k / lambda_k in every cell; the
+    # second stage adds dt/2 (F(w*) - F(w*_exact)), F's max-norm Lipschitz
+    # constant being at most D_max 8/h^2 plus the reaction Jacobian's row
+    # sums, kappa (1 + 2 u v + u^2) with u <= 2, v <= 1 here
+    ih2 = 256.0 ** 2
+    delta = max(res[0] / lam[0], res[1] / lam[1])
+    amp = 0.5 * dt * (max(p["Du"], p["Dv"]) * 8.0 * ih2 + p["p1"] * (1.0 + 4.0 + 4.0))
+    assert u0.max() < 2.0 and v0.max() < 1.0
+    for k, (g, r) in enumerate(((u, ru), (v, rv))):
+        err = np.abs(g.cpu().numpy() - r).max()
+        assert err <= 2.0 * amp * delta + 1e-12, (k, err, res)
+    print(f"[rd] paper tol: {cycles} cycles, residuals {res}", flush=True)
+    mg.close()
+
+
+def test_errors():
+    torch, M = _mg()
+    from paper_2004_03275_amd import _native as N
+
+    mg = M.GpuMultigrid(2, 32, R.NEUMANN, 1.0, nfields=1)
+    f = torch.ones(32 * 32, dtype=torch.float64, device="cuda:0")
+    phi = torch.zeros_like(f)
+    with pytest.raises(N.AmrvError) as e:
+        mg.solve(f, phi, 0.0)
+    assert e.value.code == N.EINVAL
+    with pytest.raises(N.AmrvError) as e:
+        mg.solve(torch.tensor(_seeded((32, 32), 9), device="cuda:0").contiguous(), phi, 1.0, tol=1e-15,
+                 max_cycles=1)
+    assert e.value.code == N.ENOTCONVERGED
+    u = torch.ones(32 * 32, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(N.AmrvError) as e:
+        mg.rd_step(u, u.clone(), 1e-3, R.IMEX, R.SCHNAKENBERG_PARAMS)
+    assert e.value.code == N.EINVAL  # implicit steps need two fields
+    mg.close()
+    mg = M.GpuMultigrid(2, 32, R.NEUMANN, 1.0, nfields=1)
+    bad = torch.full((32 * 32,), float("nan"), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(N.AmrvError) as e:
+        mg.solve(bad, torch.zeros_like(bad), 1.0)
+    assert e.value.code == N.ENONPHYSICAL
+    mg.close()
