@@ -48,6 +48,15 @@ extern "C" {
 #define AMRV_MG_PERIODIC 0
 #define AMRV_MG_NEUMANN 1
 
+/* Smoother launches of the levels above the LDS-resident coarse tail.  In 2D
+ * TILED stages 32x32 tiles with a halo in LDS and repeats the red-black
+ * sweeps over the halo, so one launch per level smooths and restricts (and
+ * one prolongs and smooths); PER_COLOUR launches every colour sweep over the
+ * whole level.  Both compute every cell from the same neighbour values in
+ * the same order and agree bit for bit; 3D always uses PER_COLOUR. */
+#define AMRV_MG_TILED 0
+#define AMRV_MG_PER_COLOUR 1
+
 #define AMRV_RD_SCHNAKENBERG 0 /* F0 = (kappa (a - u + u^2 v), kappa (b - u^2 v)) */
 #define AMRV_RD_GRAY_SCOTT 1   /* F0 = (-u v^2 + F (1 - u), u v^2 - (F + k) v) */
 
@@ -67,7 +76,7 @@ typedef struct {
   int32_t pre_sweeps;    /* red-black sweeps before restriction (1..8) */
   int32_t post_sweeps;   /* red-black sweeps after prolongation (1..8) */
   int32_t use_graph;     /* replay each V-cycle from a captured HIP graph (needs a stream) */
-  int32_t pad;
+  int32_t smoother;      /* AMRV_MG_TILED or AMRV_MG_PER_COLOUR (same results, bit for bit) */
   double length;         /* L > 0 */
 } amrv_mg_config;
 

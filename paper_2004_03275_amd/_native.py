@@ -72,7 +72,7 @@ class MgConfig(ctypes.Structure):
 
     _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int32), ("bc", ctypes.c_int32), ("nfields", ctypes.c_int32),
                 ("pre_sweeps", ctypes.c_int32), ("post_sweeps", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("length", ctypes.c_double)]
+                ("smoother", ctypes.c_int32), ("length", ctypes.c_double)]
 
 
 class RdParams(ctypes.Structure):

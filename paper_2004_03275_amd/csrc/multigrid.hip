@@ -13,9 +13,10 @@
 //   red                                   per field: max residual and max |f|
 //                                         as binary64 bit patterns (uint64)
 //
-// A V-cycle: on each level above the tail, `pre` red-black sweeps, then one
-// launch that forms the residual on the 2^d children of every coarse cell,
-// averages it into the coarse right-hand side and zeroes the coarse
+// A V-cycle: on each level above the tail, `pre` red-black sweeps (in 2D one
+// tiled launch that also restricts, see k_mg_down2d), then one launch that
+// forms the residual on the 2^d children of every coarse cell, averages it
+// into the coarse right-hand side and zeroes the coarse
 // correction; the coarse levels of at most 4,096 cells are solved by one
 // workgroup per field with every level resident in LDS (the whole descent,
 // the exact solve on the 2-per-side grid and the ascent in one launch); back
@@ -54,7 +55,8 @@ struct MgDev {
   double* phi[NFMAX][MG_MAXL];
   double* f[NFMAX][MG_MAXL];
   const double* par;
-  unsigned long long* red;
+  unsigned long long* red;    // [2 NFMAX] maxima, then the block counter
+  unsigned long long* hred;   // pinned host copy, written by the last block
 };
 
 struct MgPar {
@@ -203,38 +205,55 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
   return v;
 }
 
-// max |residual| (and with with_f, max |f|) of level 0 per field, folded as
-// bit patterns of non-negative doubles (NaN sorts above every number)
-template <int ND>
-__global__ void __launch_bounds__(256) k_mg_resnorm(MgDev g, int with_f) {
-  __shared__ unsigned long long sr[4], sf[4];
-  const int f = blockIdx.y;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long br = 0, bf = 0;
-  if (t < g.cells[0]) {
-    int x, y, z;
-    decode<ND>(t, g.n[0], x, y, z);
-    const double r = resid<ND>(g.phi[f][0], g.f[f][0], x, y, z, g.n[0], g.bc, par_ih2(g, 0), par_lam(g, f));
-    br = (unsigned long long)__double_as_longlong(fabs(r));
-    bf = (unsigned long long)__double_as_longlong(fabs(g.f[f][0][t]));
-  }
-  br = wave_max_u64(br);
-  bf = wave_max_u64(bf);
+// Block maxima of non-negative doubles as bit patterns (NaN sorts above every
+// number) folded into red with one atomic per block; the launch's last
+// block copies red to the pinned host buffer and clears red and the block
+// counter, so the next launch starts from zero without a fill.
+__device__ void fold_norms(const MgDev& g, int f, unsigned long long a, unsigned long long b, int with_f) {
+  __shared__ unsigned long long sr[16], sf[16];
+  __shared__ int last;
+  a = wave_max_u64(a);
+  b = wave_max_u64(b);
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    sr[w] = br;
-    sf[w] = bf;
+    sr[w] = a;
+    sf[w] = b;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long a = sr[0], b = sf[0];
-    for (int i = 1; i < 4; i++) {
+    for (int i = 1; i < (int)(blockDim.x >> 6); i++) {
       a = sr[i] > a ? sr[i] : a;
       b = sf[i] > b ? sf[i] : b;
     }
     atomicMax(&g.red[2 * f], a);
     if (with_f) atomicMax(&g.red[2 * f + 1], b);
+    __threadfence();
+    const unsigned long long nb = (unsigned long long)gridDim.x * gridDim.y;
+    last = atomicAdd(&g.red[2 * NFMAX], 1ull) == nb - 1;
   }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();
+    for (int i = 0; i < 2 * NFMAX; i++) g.hred[i] = atomicExch(&g.red[i], 0ull);
+    atomicExch(&g.red[2 * NFMAX], 0ull);
+  }
+}
+
+// max |residual| (and with with_f, max |f|) of level 0 per field
+template <int ND>
+__global__ void __launch_bounds__(256) k_mg_resnorm(MgDev g, int with_f) {
+  const int f = blockIdx.y;
+  unsigned long long br = 0, bf = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.cells[0]; t += gridDim.x * blockDim.x) {
+    int x, y, z;
+    decode<ND>(t, g.n[0], x, y, z);
+    const double r = resid<ND>(g.phi[f][0], g.f[f][0], x, y, z, g.n[0], g.bc, par_ih2(g, 0), par_lam(g, f));
+    const unsigned long long a = (unsigned long long)__double_as_longlong(fabs(r));
+    const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(g.f[f][0][t]));
+    br = a > br ? a : br;
+    bf = b > bf ? b : bf;
+  }
+  fold_norms(g, f, br, bf, with_f);
 }
 
 __global__ void k_mg_fill_u64(unsigned long long* p, int n, unsigned long long v) {
@@ -245,6 +264,179 @@ __global__ void k_mg_fill_u64(unsigned long long* p, int n, unsigned long long v
 __global__ void k_mg_set(double* dst, MgPar v) {
   const int i = threadIdx.x;
   if (i < PAR_COUNT) dst[i] = v.v[i];
+}
+
+// ---- tiled 2D level kernels ---------------------------------------------
+// One workgroup per 32x32 tile of a level above the tail: the tile and a halo
+// ring of H cells (clipped at Neumann domain faces, wrapped on periodic ones)
+// are staged in LDS and the red-black sweeps are repeated over the whole
+// staged region; a cell whose neighbours are not all staged (the open edge
+// of the halo) is never updated, so after k half-sweeps every cell at least
+// k cells from the open edge holds exactly the value the global sweeps give
+// it (same neighbours, same arithmetic).  `down` sweeps pre times, forms the
+// residual on the tile, restricts it and clears the coarse correction (H =
+// 2 pre + 1); `up` adds the interpolated coarse correction over the region,
+// sweeps post times (H = 2 post, + 1 when it also folds the residual norm
+// of the finest level).
+
+constexpr int TS = 32;
+
+struct Region {
+  int gx0, gy0, w, h;
+  bool open[4];  // x-, x+, y-, y+ edges that cut the domain (not a Neumann face)
+};
+
+__device__ __forceinline__ Region region2d(int x0, int y0, int n, int H, int bc) {
+  Region r;
+  if (bc == AMRV_MG_PERIODIC) {
+    r.gx0 = x0 - H;
+    r.gy0 = y0 - H;
+    r.w = r.h = TS + 2 * H;
+    r.open[0] = r.open[1] = r.open[2] = r.open[3] = true;
+  } else {
+    r.gx0 = max(x0 - H, 0);
+    r.gy0 = max(y0 - H, 0);
+    const int x1 = min(x0 + TS + H, n), y1 = min(y0 + TS + H, n);
+    r.w = x1 - r.gx0;
+    r.h = y1 - r.gy0;
+    r.open[0] = r.gx0 > 0;
+    r.open[1] = x1 < n;
+    r.open[2] = r.gy0 > 0;
+    r.open[3] = y1 < n;
+  }
+  return r;
+}
+
+__device__ __forceinline__ int wrapn(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// the staged region's cells: LDS index i <-> global (wrapped) index
+__device__ __forceinline__ int region_global(const Region& r, int i, int n, int& gx, int& gy) {
+  const int lx = i % r.w, ly = i / r.w;
+  gx = wrapn(r.gx0 + lx, n);
+  gy = wrapn(r.gy0 + ly, n);
+  return gy * n + gx;
+}
+
+// one half-sweep of colour c over the staged region
+__device__ __forceinline__ void tile_halfsweep(double* P, const double* F, const Region& r, int n, int c, double ih2,
+                                               double idiag) {
+  const int cells = r.w * r.h;
+  for (int i = threadIdx.x; i < cells; i += blockDim.x) {
+    const int lx = i % r.w, ly = i / r.w;
+    const int gx = wrapn(r.gx0 + lx, n), gy = wrapn(r.gy0 + ly, n);
+    if (((gx + gy) & 1) != c) continue;
+    int xm = i - 1, xp = i + 1, ym = i - r.w, yp = i + r.w;
+    if (lx == 0) {
+      if (r.open[0]) continue;
+      xm = i;
+    }
+    if (lx == r.w - 1) {
+      if (r.open[1]) continue;
+      xp = i;
+    }
+    if (ly == 0) {
+      if (r.open[2]) continue;
+      ym = i;
+    }
+    if (ly == r.h - 1) {
+      if (r.open[3]) continue;
+      yp = i;
+    }
+    const double s = (P[xm] + P[xp]) + (P[ym] + P[yp]);
+    P[i] = (s * ih2 - F[i]) * idiag;
+  }
+}
+
+// residual at a staged cell whose neighbours are all staged
+__device__ __forceinline__ double tile_resid(const double* P, const double* F, const Region& r, int lx, int ly,
+                                             double ih2, double lam) {
+  const int i = ly * r.w + lx;
+  const int xm = lx == 0 ? i : i - 1, xp = lx == r.w - 1 ? i : i + 1;
+  const int ym = ly == 0 ? i : i - r.w, yp = ly == r.h - 1 ? i : i + r.w;
+  const double w = P[i];
+  double lap = ((P[xm] + P[xp]) - 2.0 * w) * ih2;
+  lap = lap + ((P[ym] + P[yp]) - 2.0 * w) * ih2;
+  return F[i] - (lap - lam * w);
+}
+
+__global__ void __launch_bounds__(256) k_mg_down2d(MgDev g, int l, int pre) {
+  extern __shared__ double lds[];
+  const int f = blockIdx.y, n = g.n[l], nt = n / TS;
+  const int x0 = (blockIdx.x % nt) * TS, y0 = (blockIdx.x / nt) * TS;
+  const Region r = region2d(x0, y0, n, 2 * pre + 1, g.bc);
+  double* P = lds;
+  double* F = lds + r.w * r.h;
+  const double* phi = g.phi[f][l];
+  const double* rhs = g.f[f][l];
+  for (int i = threadIdx.x; i < r.w * r.h; i += blockDim.x) {
+    int gx, gy;
+    const int gi = region_global(r, i, n, gx, gy);
+    P[i] = phi[gi];
+    F[i] = rhs[gi];
+  }
+  __syncthreads();
+  const double ih2 = par_ih2(g, l), idg = par_idiag(g, f, l), lam = par_lam(g, f);
+  for (int s = 0; s < pre; s++)
+    for (int c = 0; c < 2; c++) {
+      tile_halfsweep(P, F, r, n, c, ih2, idg);
+      __syncthreads();
+    }
+  {
+    const int cx = threadIdx.x % (TS / 2), cy = threadIdx.x / (TS / 2);
+    const int bx = x0 - r.gx0 + 2 * cx, by = y0 - r.gy0 + 2 * cy;
+    double sum = 0.0;
+#pragma unroll
+    for (int dy = 0; dy < 2; dy++)
+#pragma unroll
+      for (int dx = 0; dx < 2; dx++) sum += tile_resid(P, F, r, bx + dx, by + dy, ih2, lam);
+    const int nc = n >> 1;
+    const int ci = (y0 / 2 + cy) * nc + (x0 / 2 + cx);
+    g.f[f][l + 1][ci] = sum * 0.25;
+    g.phi[f][l + 1][ci] = 0.0;
+  }
+  double* out = g.phi[f][l];
+  for (int i = threadIdx.x; i < TS * TS; i += blockDim.x) {
+    const int tx = i % TS, ty = i / TS;
+    out[(y0 + ty) * n + x0 + tx] = P[(y0 + ty - r.gy0) * r.w + (x0 + tx - r.gx0)];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_mg_up2d(MgDev g, int l, int post, int norm) {
+  extern __shared__ double lds[];
+  const int f = blockIdx.y, n = g.n[l], nt = n / TS;
+  const int x0 = (blockIdx.x % nt) * TS, y0 = (blockIdx.x / nt) * TS;
+  const Region r = region2d(x0, y0, n, 2 * post + (norm ? 1 : 0), g.bc);
+  double* P = lds;
+  double* F = lds + r.w * r.h;
+  const double* phi = g.phi[f][l];
+  const double* rhs = g.f[f][l];
+  const double* e = g.phi[f][l + 1];
+  for (int i = threadIdx.x; i < r.w * r.h; i += blockDim.x) {
+    int gx, gy;
+    const int gi = region_global(r, i, n, gx, gy);
+    P[i] = phi[gi] + prolong_cell<2>(e, gx, gy, 0, n >> 1, g.bc);
+    F[i] = rhs[gi];
+  }
+  __syncthreads();
+  const double ih2 = par_ih2(g, l), idg = par_idiag(g, f, l), lam = par_lam(g, f);
+  for (int s = 0; s < post; s++)
+    for (int c = 0; c < 2; c++) {
+      tile_halfsweep(P, F, r, n, c, ih2, idg);
+      __syncthreads();
+    }
+  double* out = g.phi[f][l];
+  unsigned long long br = 0;
+  for (int i = threadIdx.x; i < TS * TS; i += blockDim.x) {
+    const int tx = i % TS, ty = i / TS;
+    const int lx = x0 + tx - r.gx0, ly = y0 + ty - r.gy0;
+    out[(y0 + ty) * n + x0 + tx] = P[ly * r.w + lx];
+    if (norm) {
+      const unsigned long long a =
+          (unsigned long long)__double_as_longlong(fabs(tile_resid(P, F, r, lx, ly, ih2, lam)));
+      br = a > br ? a : br;
+    }
+  }
+  if (norm) fold_norms(g, f, br, 0ull, 0);
 }
 
 // ---- the coarse tail: every level from `top` down, one workgroup per field,
@@ -474,6 +666,7 @@ int validate(const amrv_mg_config* c) {
   if (c->nfields < 1 || c->nfields > NFMAX) return set_error(AMRV_EINVAL, "nfields must be 1 or 2");
   if (c->pre_sweeps < 1 || c->pre_sweeps > 8 || c->post_sweeps < 1 || c->post_sweeps > 8)
     return set_error(AMRV_EINVAL, "pre and post sweeps must be in 1..8");
+  if (c->smoother != AMRV_MG_TILED && c->smoother != AMRV_MG_PER_COLOUR) return set_error(AMRV_EINVAL, "unknown smoother");
   if (!(c->length > 0.0) || !std::isfinite(c->length)) return set_error(AMRV_EINVAL, "length must be positive");
   return 0;
 }
@@ -507,52 +700,63 @@ MgLayout layout(const amrv_mg_config* c) {
   L.off_par = o;
   o += up(PAR_COUNT * 8);
   L.off_red = o;
-  o += up(2 * NFMAX * 8);
+  o += up((2 * NFMAX + 1) * 8);
   L.total = o;
   return L;
 }
 
+bool tiled(const amrv_mg* m) { return m->g.nd == 2 && m->cfg.smoother == AMRV_MG_TILED && m->tail > 0; }
+
+size_t tile_lds(int H) { return (size_t)(TS + 2 * H) * (TS + 2 * H) * 2 * sizeof(double); }
+
+// residual norms of level 0 (with_f: also max |f|), published to the pinned
+// host copy by the launch's last block
+template <int ND>
+void enqueue_norms_nd(amrv_mg* m, int with_f) {
+  const MgDev& g = m->g;
+  hipLaunchKernelGGL(k_mg_resnorm<ND>, dim3(std::min(blocks_of(g.cells[0]), 256), g.nf), dim3(256), 0, m->st, g,
+                     with_f);
+}
+
+// one V-cycle, ending with the residual norms of its result
 template <int ND>
 void enqueue_vcycle_nd(amrv_mg* m) {
   const MgDev& g = m->g;
   const int nf = g.nf;
   const int pre = m->cfg.pre_sweeps, post = m->cfg.post_sweeps;
-  for (int l = 0; l < m->tail; l++) {
-    for (int s = 0; s < pre; s++)
-      for (int c = 0; c < 2; c++)
-        hipLaunchKernelGGL(k_mg_smooth<ND>, dim3(blocks_of(g.cells[l] >> 1), nf), dim3(256), 0, m->st, g, l, c);
-    hipLaunchKernelGGL(k_mg_restrict<ND>, dim3(blocks_of(g.cells[l + 1]), nf), dim3(256), 0, m->st, g, l);
+  if (tiled(m)) {
+    for (int l = 0; l < m->tail; l++)
+      hipLaunchKernelGGL(k_mg_down2d, dim3((g.n[l] / TS) * (g.n[l] / TS), nf), dim3(256), tile_lds(2 * pre + 1),
+                         m->st, g, l, pre);
+  } else {
+    for (int l = 0; l < m->tail; l++) {
+      for (int s = 0; s < pre; s++)
+        for (int c = 0; c < 2; c++)
+          hipLaunchKernelGGL(k_mg_smooth<ND>, dim3(blocks_of(g.cells[l] >> 1), nf), dim3(256), 0, m->st, g, l, c);
+      hipLaunchKernelGGL(k_mg_restrict<ND>, dim3(blocks_of(g.cells[l + 1]), nf), dim3(256), 0, m->st, g, l);
+    }
   }
   hipLaunchKernelGGL(k_mg_tail<ND>, dim3(nf), dim3(TAIL_THREADS), m->tail_lds, m->st, g, m->tail, pre, post);
+  if (tiled(m)) {
+    for (int l = m->tail - 1; l >= 0; l--)
+      hipLaunchKernelGGL(k_mg_up2d, dim3((g.n[l] / TS) * (g.n[l] / TS), nf), dim3(256),
+                         tile_lds(2 * post + (l == 0 ? 1 : 0)), m->st, g, l, post, l == 0 ? 1 : 0);
+    return;  // the finest level's up launch folded the norms
+  }
   for (int l = m->tail - 1; l >= 0; l--) {
     hipLaunchKernelGGL(k_mg_prolong<ND>, dim3(blocks_of(g.cells[l]), nf), dim3(256), 0, m->st, g, l);
     for (int s = 0; s < post; s++)
       for (int c = 0; c < 2; c++)
         hipLaunchKernelGGL(k_mg_smooth<ND>, dim3(blocks_of(g.cells[l] >> 1), nf), dim3(256), 0, m->st, g, l, c);
   }
-}
-
-// residual norms of level 0 into the pinned host copy (with_f: also max |f|)
-template <int ND>
-void enqueue_norms_nd(amrv_mg* m, int with_f) {
-  const MgDev& g = m->g;
-  if (with_f) {
-    hipLaunchKernelGGL(k_mg_fill_u64, dim3(1), dim3(64), 0, m->st, m->red, 2 * NFMAX, 0ull);
-  } else {
-    for (int f = 0; f < g.nf; f++) hipLaunchKernelGGL(k_mg_fill_u64, dim3(1), dim3(64), 0, m->st, m->red + 2 * f, 1, 0ull);
-  }
-  hipLaunchKernelGGL(k_mg_resnorm<ND>, dim3(blocks_of(g.cells[0]), g.nf), dim3(256), 0, m->st, g, with_f);
-  (void)hipMemcpyAsync(m->hred, m->red, 2 * NFMAX * sizeof(unsigned long long), hipMemcpyDeviceToHost, m->st);
+  enqueue_norms_nd<ND>(m, 0);
 }
 
 void enqueue_vcycle(amrv_mg* m) {
-  if (m->g.nd == 2) {
+  if (m->g.nd == 2)
     enqueue_vcycle_nd<2>(m);
-    enqueue_norms_nd<2>(m, 0);
-  } else {
+  else
     enqueue_vcycle_nd<3>(m);
-    enqueue_norms_nd<3>(m, 0);
-  }
 }
 
 int set_params(amrv_mg* m, const double* lam) {
@@ -583,6 +787,9 @@ double bits_to_double(unsigned long long b) {
 // AMRV_ENOTCONVERGED / AMRV_ENONPHYSICAL
 int run_cycles(amrv_mg* m, double tol, int max_cycles, int* cycles, double* res_out, double* f_out) {
   const int nf = m->g.nf;
+  // clear the maxima and the block counter (a launch that failed earlier may
+  // have left them set), then the norms of the initial guess
+  hipLaunchKernelGGL(k_mg_fill_u64, dim3(1), dim3(64), 0, m->st, m->red, 2 * NFMAX + 1, 0ull);
   if (m->g.nd == 2)
     enqueue_norms_nd<2>(m, 1);
   else
@@ -705,7 +912,16 @@ int amrv_mg_create(const amrv_mg_config* cfg, void* workspace, size_t bytes, voi
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->tail_lds)
                      : hipFuncSetAttribute(reinterpret_cast<const void*>(k_mg_tail<3>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->tail_lds);
+  if (e == hipSuccess && cfg->ndim == 2) {
+    const int H = 2 * std::max(cfg->pre_sweeps, cfg->post_sweeps) + 1;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_mg_down2d), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)tile_lds(H));
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_mg_up2d), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)tile_lds(H));
+  }
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&m->hred), 2 * NFMAX * sizeof(unsigned long long));
+  if (e == hipSuccess) m->g.hred = m->hred;
   if (e == hipSuccess) e = hipEventCreate(&m->e0);
   if (e == hipSuccess) e = hipEventCreate(&m->e1);
   if (e != hipSuccess) {

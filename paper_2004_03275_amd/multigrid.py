@@ -14,6 +14,7 @@ from . import _native as N
 PERIODIC, NEUMANN = 0, 1
 SCHNAKENBERG, GRAY_SCOTT = 0, 1
 EULER, MIDPOINT, SPLIT, IMEX = 0, 1, 2, 3
+TILED, PER_COLOUR = 0, 1
 
 
 def rd_params(model: int, Du: float, Dv: float, p1: float, p2: float, p3: float = 0.0) -> N.RdParams:
@@ -24,13 +25,13 @@ class GpuMultigrid:
     """A solver for one grid shape on one GPU (workspace from torch)."""
 
     def __init__(self, ndim: int, n: int, bc: int, length: float, nfields: int = 2, pre: int = 2, post: int = 2,
-                 graph: bool = True, device: str | torch.device = "cuda:0",
+                 graph: bool = True, smoother: int = TILED, device: str | torch.device = "cuda:0",
                  stream: torch.cuda.Stream | None = None):
         if not torch.cuda.is_available():
             raise RuntimeError("GpuMultigrid needs a ROCm GPU (torch.cuda.is_available() is False)")
         L = N.lib()
         self.cfg = N.MgConfig(ndim=ndim, n=n, bc=bc, nfields=nfields, pre_sweeps=pre, post_sweeps=post,
-                              use_graph=1 if graph else 0, pad=0, length=length)
+                              use_graph=1 if graph else 0, smoother=smoother, length=length)
         nbytes = L.amrv_mg_workspace_bytes(ctypes.byref(self.cfg))
         if nbytes == 0:
             raise N.AmrvError(N.EINVAL, L.amrv_last_error().decode())

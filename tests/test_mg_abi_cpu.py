@@ -9,7 +9,7 @@ from paper_2004_03275_amd import _native as N
 
 
 def _cfg(**kw):
-    base = dict(ndim=2, n=64, bc=1, nfields=2, pre_sweeps=2, post_sweeps=2, use_graph=1, pad=0, length=1.0)
+    base = dict(ndim=2, n=64, bc=1, nfields=2, pre_sweeps=2, post_sweeps=2, use_graph=1, smoother=0, length=1.0)
     base.update(kw)
     return N.MgConfig(**base)
 
@@ -25,7 +25,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(N.LIB_PATH), reason="libamrv.
     ({"ndim": 1}, "ndim"), ({"ndim": 4}, "ndim"), ({"n": 48}, "power of two"), ({"n": 2}, "power of two"),
     ({"n": 16384}, "power of two"), ({"ndim": 3, "n": 1024}, "power of two"), ({"bc": 2}, "boundary"),
     ({"nfields": 0}, "nfields"), ({"nfields": 3}, "nfields"), ({"pre_sweeps": 0}, "sweeps"),
-    ({"post_sweeps": 9}, "sweeps"), ({"length": 0.0}, "length"), ({"length": float("inf")}, "length"),
+    ({"post_sweeps": 9}, "sweeps"), ({"smoother": 2}, "smoother"), ({"length": 0.0}, "length"), ({"length": float("inf")}, "length"),
 ])
 def test_rejects_bad_configurations(change, msg):
     n, err = _bytes(_cfg(**change))
@@ -41,7 +41,7 @@ def test_workspace_size():
     for nd, n, nf in [(2, 256, 2), (3, 32, 1), (2, 4, 1)]:
         got, _ = _bytes(_cfg(ndim=nd, n=n, nfields=nf))
         levels = [n >> l for l in range(n.bit_length() - 1)]
-        want = nf * sum(2 * up(8 * m ** nd) for m in levels) + 4 * up(8 * n ** nd) + up(8 * 44) + up(32)
+        want = nf * sum(2 * up(8 * m ** nd) for m in levels) + 4 * up(8 * n ** nd) + up(8 * 44) + up(40)
         assert got == want, (nd, n, nf, got, want)
 
 
