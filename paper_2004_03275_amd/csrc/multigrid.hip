@@ -10,22 +10,22 @@
 //                                         temporaries)
 //   par                                   lambda per field, 1/diagonal per
 //                                         field and level, 1/h^2 per level
-//   red                                   per field: max residual and max |f|
-//                                         as binary64 bit patterns (uint64)
+// plus pinned host memory for the per-block residual maxima, folded on the
+// host after each cycle.
 //
-// A V-cycle: on each level above the tail, `pre` red-black sweeps (in 2D one
-// tiled launch that also restricts, see k_mg_down2d), then one launch that
-// forms the residual on the 2^d children of every coarse cell, averages it
-// into the coarse right-hand side and zeroes the coarse
-// correction; the coarse levels of at most 4,096 cells are solved by one
-// workgroup per field with every level resident in LDS (the whole descent,
-// the exact solve on the 2-per-side grid and the ascent in one launch); back
-// up, one
-// launch adds the bi/trilinear interpolation of the coarse correction, then
-// `post` sweeps.  Fields (u and v of the reaction-diffusion steps) are solved
-// by the same launches (grid y = field).  These grids are small (a 256^2
-// field is 512 KiB), so the cycle is bound by launch and synchronisation
-// latency, not by HBM: it is replayed from a HIP graph.
+// A V-cycle: on each level above the tail, `pre` red-black sweeps and a
+// launch that forms the residual on the 2^d children of every coarse cell,
+// averages it into the coarse right-hand side and zeroes the coarse
+// correction (in 2D both in one tiled launch, k_mg_down2d); the coarse
+// levels of at most 4,096 cells are solved by one workgroup per field with
+// every level resident in LDS (the whole descent, the exact solve on the
+// 2-per-side grid and the ascent in one launch); back up, a launch adds the
+// bi/trilinear interpolation of the coarse correction, then `post` sweeps
+// (again one tiled launch in 2D, the finest one also folding the residual
+// norms).  Fields (u and v of the reaction-diffusion steps) are solved by the
+// same launches (grid y = field).  These grids are small (a 256^2 field is
+// 512 KiB), so the cycle is bound by launch and synchronisation latency, not
+// by HBM: it is replayed from a HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,6 +42,7 @@ constexpr int MG_MAXL = 14;   // n <= 8192: 13 levels down to 2 cells per side
 constexpr int NFMAX = 2;
 constexpr int TAIL_CELLS = 4096;
 constexpr int TAIL_THREADS = 1024;
+constexpr int TK = TAIL_CELLS / 2 / TAIL_THREADS;  // colour cells per tail thread on its top level
 constexpr int PAR_LAM = 0;
 constexpr int PAR_IDIAG = NFMAX;                       // + field * MG_MAXL + level
 constexpr int PAR_IH2 = NFMAX + NFMAX * MG_MAXL;       // + level
@@ -50,13 +51,16 @@ constexpr int PAR_COUNT = PAR_IH2 + MG_MAXL;
 struct MgDev {
   int nd, bc, nlev, nf;
   int n[MG_MAXL];
+  int lg[MG_MAXL];              // log2(n[l])
   int cells[MG_MAXL];
   int loff[MG_MAXL];            // LDS offset (doubles) of the tail's phi_l; f_l follows it
   double* phi[NFMAX][MG_MAXL];
   double* f[NFMAX][MG_MAXL];
+  double* phi2[NFMAX][MG_MAXL]; // 2D levels above the tail: the tiled launches'
+                                // second buffer (down writes it, up reads it)
   const double* par;
-  unsigned long long* red;    // [2 NFMAX] maxima, then the block counter
-  unsigned long long* hred;   // pinned host copy, written by the last block
+  unsigned long long* hpart;  // pinned host slots of per-block maxima: [2][NFMAX][maxb]
+  int maxb;
 };
 
 struct MgPar {
@@ -73,12 +77,13 @@ struct RdK {
 __device__ __forceinline__ int im(int i, int n, int bc) { return i > 0 ? i - 1 : (bc == AMRV_MG_PERIODIC ? n - 1 : 0); }
 __device__ __forceinline__ int ip(int i, int n, int bc) { return i < n - 1 ? i + 1 : (bc == AMRV_MG_PERIODIC ? 0 : n - 1); }
 
+// cell t of a level with n = 2^lg cells per side
 template <int ND>
-__device__ __forceinline__ void decode(int t, int n, int& x, int& y, int& z) {
-  x = t % n;
-  const int r = t / n;
-  y = ND == 3 ? r % n : r;
-  z = ND == 3 ? r / n : 0;
+__device__ __forceinline__ void decode(int t, int n, int lg, int& x, int& y, int& z) {
+  x = t & (n - 1);
+  const int r = t >> lg;
+  y = ND == 3 ? (r & (n - 1)) : r;
+  z = ND == 3 ? (r >> lg) : 0;
 }
 
 // Laplacian: per direction ((w- + w+) - 2 w) * (1/h^2), added x, y, z
@@ -106,12 +111,11 @@ __device__ __forceinline__ void gs_cell(double* p, const double* rhs, int x, int
 
 // cell t of colour c among the cells with (x + y + z) % 2 == c
 template <int ND>
-__device__ __forceinline__ void colour_cell(int t, int n, int c, int& x, int& y, int& z) {
-  const int half = n >> 1;
-  const int xh = t % half;
-  const int r = t / half;
-  y = ND == 3 ? r % n : r;
-  z = ND == 3 ? r / n : 0;
+__device__ __forceinline__ void colour_cell(int t, int n, int lg, int c, int& x, int& y, int& z) {
+  const int xh = t & ((n >> 1) - 1);
+  const int r = t >> (lg - 1);
+  y = ND == 3 ? (r & (n - 1)) : r;
+  z = ND == 3 ? (r >> lg) : 0;
   x = 2 * xh + ((y + z + c) & 1);
 }
 
@@ -171,7 +175,7 @@ __global__ void __launch_bounds__(256) k_mg_smooth(MgDev g, int l, int c) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (g.cells[l] >> 1)) return;
   int x, y, z;
-  colour_cell<ND>(t, n, c, x, y, z);
+  colour_cell<ND>(t, n, g.lg[l], c, x, y, z);
   gs_cell<ND>(g.phi[f][l], g.f[f][l], x, y, z, n, g.bc, par_ih2(g, l), par_idiag(g, f, l));
 }
 
@@ -181,7 +185,7 @@ __global__ void __launch_bounds__(256) k_mg_restrict(MgDev g, int l) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.cells[l + 1]) return;
   int x, y, z;
-  decode<ND>(t, g.n[l + 1], x, y, z);
+  decode<ND>(t, g.n[l + 1], g.lg[l + 1], x, y, z);
   g.f[f][l + 1][t] = restrict_cell<ND>(g.phi[f][l], g.f[f][l], x, y, z, g.n[l], g.bc, par_ih2(g, l), par_lam(g, f));
   g.phi[f][l + 1][t] = 0.0;
 }
@@ -192,7 +196,7 @@ __global__ void __launch_bounds__(256) k_mg_prolong(MgDev g, int l) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.cells[l]) return;
   int x, y, z;
-  decode<ND>(t, g.n[l], x, y, z);
+  decode<ND>(t, g.n[l], g.lg[l], x, y, z);
   g.phi[f][l][t] += prolong_cell<ND>(g.phi[f][l + 1], x, y, z, g.n[l + 1], g.bc);
 }
 
@@ -206,12 +210,12 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 }
 
 // Block maxima of non-negative doubles as bit patterns (NaN sorts above every
-// number) folded into red with one atomic per block; the launch's last
-// block copies red to the pinned host buffer and clears red and the block
-// counter, so the next launch starts from zero without a fill.
+// number), written by each block into its own slot of the pinned host buffer
+// (the residual maxima of field f in row f, the |f| maxima in row NFMAX + f);
+// the host folds the launch's slots once it has completed.  No atomics: many
+// blocks folding into one address serialise.
 __device__ void fold_norms(const MgDev& g, int f, unsigned long long a, unsigned long long b, int with_f) {
   __shared__ unsigned long long sr[16], sf[16];
-  __shared__ int last;
   a = wave_max_u64(a);
   b = wave_max_u64(b);
   const int w = threadIdx.x >> 6;
@@ -225,17 +229,8 @@ __device__ void fold_norms(const MgDev& g, int f, unsigned long long a, unsigned
       a = sr[i] > a ? sr[i] : a;
       b = sf[i] > b ? sf[i] : b;
     }
-    atomicMax(&g.red[2 * f], a);
-    if (with_f) atomicMax(&g.red[2 * f + 1], b);
-    __threadfence();
-    const unsigned long long nb = (unsigned long long)gridDim.x * gridDim.y;
-    last = atomicAdd(&g.red[2 * NFMAX], 1ull) == nb - 1;
-  }
-  __syncthreads();
-  if (last && threadIdx.x == 0) {
-    __threadfence();
-    for (int i = 0; i < 2 * NFMAX; i++) g.hred[i] = atomicExch(&g.red[i], 0ull);
-    atomicExch(&g.red[2 * NFMAX], 0ull);
+    g.hpart[(size_t)f * g.maxb + blockIdx.x] = a;
+    if (with_f) g.hpart[(size_t)(NFMAX + f) * g.maxb + blockIdx.x] = b;
   }
 }
 
@@ -246,7 +241,7 @@ __global__ void __launch_bounds__(256) k_mg_resnorm(MgDev g, int with_f) {
   unsigned long long br = 0, bf = 0;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.cells[0]; t += gridDim.x * blockDim.x) {
     int x, y, z;
-    decode<ND>(t, g.n[0], x, y, z);
+    decode<ND>(t, g.n[0], g.lg[0], x, y, z);
     const double r = resid<ND>(g.phi[f][0], g.f[f][0], x, y, z, g.n[0], g.bc, par_ih2(g, 0), par_lam(g, f));
     const unsigned long long a = (unsigned long long)__double_as_longlong(fabs(r));
     const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(g.f[f][0][t]));
@@ -256,10 +251,6 @@ __global__ void __launch_bounds__(256) k_mg_resnorm(MgDev g, int with_f) {
   fold_norms(g, f, br, bf, with_f);
 }
 
-__global__ void k_mg_fill_u64(unsigned long long* p, int n, unsigned long long v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
 
 __global__ void k_mg_set(double* dst, MgPar v) {
   const int i = threadIdx.x;
@@ -277,9 +268,14 @@ __global__ void k_mg_set(double* dst, MgPar v) {
 // residual on the tile, restricts it and clears the coarse correction (H =
 // 2 pre + 1); `up` adds the interpolated coarse correction over the region,
 // sweeps post times (H = 2 post, + 1 when it also folds the residual norm
-// of the finest level).
+// of the finest level).  A launch never writes the array it stages from
+// (blocks that start late would read a neighbour's new tile): down reads phi
+// and writes phi2, up reads phi2 and writes phi.
 
-constexpr int TS = 32;
+constexpr int TS = 32;                 // tile side
+constexpr int RP = 64;                 // LDS row pitch of a staged region
+constexpr int HMAX = 9;                // largest halo: pre, post <= 4
+constexpr int RMAX = TS + 2 * HMAX;    // largest staged rows and columns
 
 struct Region {
   int gx0, gy0, w, h;
@@ -309,50 +305,138 @@ __device__ __forceinline__ Region region2d(int x0, int y0, int n, int H, int bc)
 
 __device__ __forceinline__ int wrapn(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// the staged region's cells: LDS index i <-> global (wrapped) index
-__device__ __forceinline__ int region_global(const Region& r, int i, int n, int& gx, int& gy) {
-  const int lx = i % r.w, ly = i / r.w;
-  gx = wrapn(r.gx0 + lx, n);
-  gy = wrapn(r.gy0 + ly, n);
-  return gy * n + gx;
+// The coarse cells a region's interpolation reads: parents (gx >> 1 of the
+// unwrapped fine coordinate) and their neighbours, staged with the boundary
+// rule applied (wrap, or the mirrored cell at a Neumann face) in an
+// EP-pitched LDS block, so each fine cell interpolates from LDS with the
+// weights and order of prolong_cell.
+constexpr int EP = 32;
+constexpr int EMAX = RMAX / 2 + 3;
+
+struct CoarseWin {
+  int cx0, cy0;
+};
+
+__device__ __forceinline__ CoarseWin stage_coarse(double* E, const Region& r, int nc, const double* e, int bc) {
+  CoarseWin c;
+  c.cx0 = (r.gx0 >> 1) - 1;
+  c.cy0 = (r.gy0 >> 1) - 1;
+  const int cw = ((r.gx0 + r.w - 1) >> 1) - c.cx0 + 2, ch = ((r.gy0 + r.h - 1) >> 1) - c.cy0 + 2;
+  constexpr int K = (EMAX * EP + 255) / 256;
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const int i = threadIdx.x + 256 * k;
+    const int lx = i & (EP - 1), ly = i >> 5;
+    v[k] = 0.0;
+    if (lx < cw && ly < ch) {
+      int gx = c.cx0 + lx, gy = c.cy0 + ly;
+      if (bc == AMRV_MG_PERIODIC) {
+        gx = wrapn(gx, nc);
+        gy = wrapn(gy, nc);
+      } else {
+        gx = min(max(gx, 0), nc - 1);
+        gy = min(max(gy, 0), nc - 1);
+      }
+      v[k] = e[gy * nc + gx];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const int i = threadIdx.x + 256 * k;
+    const int lx = i & (EP - 1), ly = i >> 5;
+    if (lx < cw && ly < ch) E[ly * EP + lx] = v[k];
+  }
+  return c;
 }
 
-// one half-sweep of colour c over the staged region
-__device__ __forceinline__ void tile_halfsweep(double* P, const double* F, const Region& r, int n, int c, double ih2,
+// prolong_cell's interpolation at the unwrapped fine cell (ux, uy) from the
+// staged coarse block
+__device__ __forceinline__ double prolong_lds(const double* E, const CoarseWin& c, int ux, int uy) {
+  const int xc = (ux >> 1) - c.cx0, yc = (uy >> 1) - c.cy0;
+  const int xn = (ux & 1) ? xc + 1 : xc - 1, yn = (uy & 1) ? yc + 1 : yc - 1;
+  const double a = 0.75 * E[yc * EP + xc] + 0.25 * E[yc * EP + xn];
+  const double b = 0.75 * E[yn * EP + xc] + 0.25 * E[yn * EP + xn];
+  return 0.75 * a + 0.25 * b;
+}
+
+// stage phi (+ the interpolated coarse correction when E != null) and f of
+// the region into LDS (row pitch RP); every global load is issued before the
+// first one is waited for
+__device__ __forceinline__ void stage_region(double* P, double* F, const Region& r, int n, const double* phi,
+                                             const double* rhs, const double* E, const CoarseWin& cw) {
+  constexpr int K = (RMAX * RP + 255) / 256;
+  double pv[K], fv[K];
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const int i = threadIdx.x + 256 * k;
+    const int lx = i & (RP - 1), ly = i >> 6;
+    pv[k] = fv[k] = 0.0;
+    if (lx < r.w && ly < r.h) {
+      const int gx = wrapn(r.gx0 + lx, n), gy = wrapn(r.gy0 + ly, n);
+      pv[k] = phi[gy * n + gx];
+      fv[k] = rhs[gy * n + gx];
+    }
+  }
+  if (E) {
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const int i = threadIdx.x + 256 * k;
+      const int lx = i & (RP - 1), ly = i >> 6;
+      if (lx < r.w && ly < r.h) pv[k] = pv[k] + prolong_lds(E, cw, r.gx0 + lx, r.gy0 + ly);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const int i = threadIdx.x + 256 * k;
+    const int lx = i & (RP - 1), ly = i >> 6;
+    if (lx < r.w && ly < r.h) {
+      P[i] = pv[k];
+      F[i] = fv[k];
+    }
+  }
+}
+
+// one half-sweep of colour c over the staged region: 32 lanes per row take
+// the row's cells of that colour; every new value is computed before any is
+// stored (a half-sweep reads only the other colour, so no barrier is needed
+// between the two passes).  A cell with a neighbour beyond an open edge is
+// left alone.
+__device__ __forceinline__ void tile_halfsweep(double* P, const double* F, const Region& r, int c, double ih2,
                                                double idiag) {
-  const int cells = r.w * r.h;
-  for (int i = threadIdx.x; i < cells; i += blockDim.x) {
-    const int lx = i % r.w, ly = i / r.w;
-    const int gx = wrapn(r.gx0 + lx, n), gy = wrapn(r.gy0 + ly, n);
-    if (((gx + gy) & 1) != c) continue;
-    int xm = i - 1, xp = i + 1, ym = i - r.w, yp = i + r.w;
-    if (lx == 0) {
-      if (r.open[0]) continue;
-      xm = i;
+  constexpr int K = (RMAX + 7) / 8;
+  const int j = threadIdx.x & 31, r0 = threadIdx.x >> 5;
+  double nv[K];
+  bool ok[K];
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const int ly = r0 + 8 * k;
+    const int lx = 2 * j + ((c + r.gx0 + r.gy0 + ly) & 1);
+    const int i = ly * RP + lx;
+    ok[k] = ly < r.h && lx < r.w && !(lx == 0 && r.open[0]) && !(lx == r.w - 1 && r.open[1]) &&
+            !(ly == 0 && r.open[2]) && !(ly == r.h - 1 && r.open[3]);
+    nv[k] = 0.0;
+    if (ok[k]) {
+      const int xm = lx == 0 ? i : i - 1, xp = lx == r.w - 1 ? i : i + 1;
+      const int ym = ly == 0 ? i : i - RP, yp = ly == r.h - 1 ? i : i + RP;
+      const double sum = (P[xm] + P[xp]) + (P[ym] + P[yp]);
+      nv[k] = (sum * ih2 - F[i]) * idiag;
     }
-    if (lx == r.w - 1) {
-      if (r.open[1]) continue;
-      xp = i;
-    }
-    if (ly == 0) {
-      if (r.open[2]) continue;
-      ym = i;
-    }
-    if (ly == r.h - 1) {
-      if (r.open[3]) continue;
-      yp = i;
-    }
-    const double s = (P[xm] + P[xp]) + (P[ym] + P[yp]);
-    P[i] = (s * ih2 - F[i]) * idiag;
+  }
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const int ly = r0 + 8 * k;
+    const int lx = 2 * j + ((c + r.gx0 + r.gy0 + ly) & 1);
+    if (ok[k]) P[ly * RP + lx] = nv[k];
   }
 }
 
 // residual at a staged cell whose neighbours are all staged
 __device__ __forceinline__ double tile_resid(const double* P, const double* F, const Region& r, int lx, int ly,
                                              double ih2, double lam) {
-  const int i = ly * r.w + lx;
+  const int i = ly * RP + lx;
   const int xm = lx == 0 ? i : i - 1, xp = lx == r.w - 1 ? i : i + 1;
-  const int ym = ly == 0 ? i : i - r.w, yp = ly == r.h - 1 ? i : i + r.w;
+  const int ym = ly == 0 ? i : i - RP, yp = ly == r.h - 1 ? i : i + RP;
   const double w = P[i];
   double lap = ((P[xm] + P[xp]) - 2.0 * w) * ih2;
   lap = lap + ((P[ym] + P[yp]) - 2.0 * w) * ih2;
@@ -360,29 +444,20 @@ __device__ __forceinline__ double tile_resid(const double* P, const double* F, c
 }
 
 __global__ void __launch_bounds__(256) k_mg_down2d(MgDev g, int l, int pre) {
-  extern __shared__ double lds[];
+  __shared__ double P[RMAX * RP], F[RMAX * RP];
   const int f = blockIdx.y, n = g.n[l], nt = n / TS;
   const int x0 = (blockIdx.x % nt) * TS, y0 = (blockIdx.x / nt) * TS;
   const Region r = region2d(x0, y0, n, 2 * pre + 1, g.bc);
-  double* P = lds;
-  double* F = lds + r.w * r.h;
-  const double* phi = g.phi[f][l];
-  const double* rhs = g.f[f][l];
-  for (int i = threadIdx.x; i < r.w * r.h; i += blockDim.x) {
-    int gx, gy;
-    const int gi = region_global(r, i, n, gx, gy);
-    P[i] = phi[gi];
-    F[i] = rhs[gi];
-  }
+  stage_region(P, F, r, n, g.phi[f][l], g.f[f][l], nullptr, CoarseWin{0, 0});
   __syncthreads();
   const double ih2 = par_ih2(g, l), idg = par_idiag(g, f, l), lam = par_lam(g, f);
   for (int s = 0; s < pre; s++)
     for (int c = 0; c < 2; c++) {
-      tile_halfsweep(P, F, r, n, c, ih2, idg);
+      tile_halfsweep(P, F, r, c, ih2, idg);
       __syncthreads();
     }
   {
-    const int cx = threadIdx.x % (TS / 2), cy = threadIdx.x / (TS / 2);
+    const int cx = threadIdx.x & (TS / 2 - 1), cy = threadIdx.x >> 4;
     const int bx = x0 - r.gx0 + 2 * cx, by = y0 - r.gy0 + 2 * cy;
     double sum = 0.0;
 #pragma unroll
@@ -394,42 +469,36 @@ __global__ void __launch_bounds__(256) k_mg_down2d(MgDev g, int l, int pre) {
     g.f[f][l + 1][ci] = sum * 0.25;
     g.phi[f][l + 1][ci] = 0.0;
   }
-  double* out = g.phi[f][l];
-  for (int i = threadIdx.x; i < TS * TS; i += blockDim.x) {
-    const int tx = i % TS, ty = i / TS;
-    out[(y0 + ty) * n + x0 + tx] = P[(y0 + ty - r.gy0) * r.w + (x0 + tx - r.gx0)];
+  double* out = g.phi2[f][l];  // other blocks of this launch still stage phi
+#pragma unroll
+  for (int k = 0; k < TS * TS / 256; k++) {
+    const int tx = threadIdx.x & (TS - 1), ty = (threadIdx.x >> 5) + 8 * k;
+    out[(y0 + ty) * n + x0 + tx] = P[(y0 + ty - r.gy0) * RP + (x0 + tx - r.gx0)];
   }
 }
 
 __global__ void __launch_bounds__(256) k_mg_up2d(MgDev g, int l, int post, int norm) {
-  extern __shared__ double lds[];
+  __shared__ double P[RMAX * RP], F[RMAX * RP], E[EMAX * EP];
   const int f = blockIdx.y, n = g.n[l], nt = n / TS;
   const int x0 = (blockIdx.x % nt) * TS, y0 = (blockIdx.x / nt) * TS;
   const Region r = region2d(x0, y0, n, 2 * post + (norm ? 1 : 0), g.bc);
-  double* P = lds;
-  double* F = lds + r.w * r.h;
-  const double* phi = g.phi[f][l];
-  const double* rhs = g.f[f][l];
-  const double* e = g.phi[f][l + 1];
-  for (int i = threadIdx.x; i < r.w * r.h; i += blockDim.x) {
-    int gx, gy;
-    const int gi = region_global(r, i, n, gx, gy);
-    P[i] = phi[gi] + prolong_cell<2>(e, gx, gy, 0, n >> 1, g.bc);
-    F[i] = rhs[gi];
-  }
+  const CoarseWin cw = stage_coarse(E, r, n >> 1, g.phi[f][l + 1], g.bc);
+  __syncthreads();
+  stage_region(P, F, r, n, g.phi2[f][l], g.f[f][l], E, cw);
   __syncthreads();
   const double ih2 = par_ih2(g, l), idg = par_idiag(g, f, l), lam = par_lam(g, f);
   for (int s = 0; s < post; s++)
     for (int c = 0; c < 2; c++) {
-      tile_halfsweep(P, F, r, n, c, ih2, idg);
+      tile_halfsweep(P, F, r, c, ih2, idg);
       __syncthreads();
     }
   double* out = g.phi[f][l];
   unsigned long long br = 0;
-  for (int i = threadIdx.x; i < TS * TS; i += blockDim.x) {
-    const int tx = i % TS, ty = i / TS;
+#pragma unroll
+  for (int k = 0; k < TS * TS / 256; k++) {
+    const int tx = threadIdx.x & (TS - 1), ty = (threadIdx.x >> 5) + 8 * k;
     const int lx = x0 + tx - r.gx0, ly = y0 + ty - r.gy0;
-    out[(y0 + ty) * n + x0 + tx] = P[ly * r.w + lx];
+    out[(y0 + ty) * n + x0 + tx] = P[ly * RP + lx];
     if (norm) {
       const unsigned long long a =
           (unsigned long long)__double_as_longlong(fabs(tile_resid(P, F, r, lx, ly, ih2, lam)));
@@ -443,31 +512,43 @@ __global__ void __launch_bounds__(256) k_mg_up2d(MgDev g, int l, int post, int n
 // all levels in LDS -------------------------------------------------------
 
 template <int ND>
-__device__ void tail_sweeps(const MgDev& g, double* P, const double* F, int l, int f, int sweeps) {
-  const int n = g.n[l], half = g.cells[l] >> 1;
-  const double ih2 = par_ih2(g, l), idg = par_idiag(g, f, l);
+__device__ void tail_sweeps(const MgDev& g, double* P, const double* F, int l, int sweeps, double ih2, double idg) {
+  const int n = g.n[l], lg = g.lg[l], half = g.cells[l] >> 1;
   for (int s = 0; s < sweeps; s++)
     for (int c = 0; c < 2; c++) {
-      for (int t = threadIdx.x; t < half; t += blockDim.x) {
-        int x, y, z;
-        colour_cell<ND>(t, n, c, x, y, z);
-        gs_cell<ND>(P, F, x, y, z, n, g.bc, ih2, idg);
+      // TK cells per thread per pass: every new value before any store
+      for (int t0 = threadIdx.x; t0 < half; t0 += TK * blockDim.x) {
+        double nv[TK];
+        int idx[TK];
+#pragma unroll
+        for (int k = 0; k < TK; k++) {
+          const int t = t0 + k * blockDim.x;
+          idx[k] = -1;
+          if (t < half) {
+            int x, y, z;
+            colour_cell<ND>(t, n, lg, c, x, y, z);
+            const int row = (z * n + y) * n;
+            double sum = (P[row + im(x, n, g.bc)] + P[row + ip(x, n, g.bc)]) +
+                         (P[(z * n + im(y, n, g.bc)) * n + x] + P[(z * n + ip(y, n, g.bc)) * n + x]);
+            if constexpr (ND == 3)
+              sum = sum + (P[(im(z, n, g.bc) * n + y) * n + x] + P[(ip(z, n, g.bc) * n + y) * n + x]);
+            idx[k] = row + x;
+            nv[k] = (sum * ih2 - F[row + x]) * idg;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < TK; k++)
+          if (idx[k] >= 0) P[idx[k]] = nv[k];
       }
       __syncthreads();
     }
 }
 
-// exact solve on the coarsest grid (2 cells per side): per direction the
-// operator couples the two cells as c [[-1, 1], [1, -1]] (c = 1/h^2 with the
-// mirrored Neumann ghost, 2/h^2 with the periodic wrap), so the 2^d Walsh
-// patterns (-1)^popcount(k & cell) are its eigenvectors, with eigenvalue
-// -2c per set bit of k, minus lambda.
 template <int ND>
-__device__ void coarse_exact(const MgDev& g, double* P, const double* F, int l, int f) {
+__device__ void coarse_exact(const MgDev& g, double* P, const double* F, double ih2, double lam) {
   constexpr int C = 1 << ND;
   if (threadIdx.x == 0) {
-    const double c2 = 2.0 * (g.bc == AMRV_MG_PERIODIC ? 2.0 : 1.0) * par_ih2(g, l);
-    const double lam = par_lam(g, f);
+    const double c2 = 2.0 * (g.bc == AMRV_MG_PERIODIC ? 2.0 : 1.0) * ih2;
     double hat[C];
 #pragma unroll
     for (int k = 0; k < C; k++) {
@@ -494,7 +575,13 @@ __device__ void coarse_exact(const MgDev& g, double* P, const double* F, int l, 
 template <int ND>
 __global__ void __launch_bounds__(TAIL_THREADS) k_mg_tail(MgDev g, int top, int pre, int post) {
   extern __shared__ double lds[];
+  __shared__ double s_ih2[MG_MAXL], s_idg[MG_MAXL];
   const int f = blockIdx.x;
+  if (threadIdx.x < MG_MAXL) {
+    s_ih2[threadIdx.x] = par_ih2(g, threadIdx.x);
+    s_idg[threadIdx.x] = par_idiag(g, f, threadIdx.x);
+  }
+  const double lam = par_lam(g, f);
   auto P = [&](int l) { return lds + g.loff[l]; };
   auto F = [&](int l) { return lds + g.loff[l] + g.cells[l]; };
   for (int i = threadIdx.x; i < g.cells[top]; i += blockDim.x) {
@@ -504,25 +591,25 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_mg_tail(MgDev g, int top, int 
   __syncthreads();
   const int last = g.nlev - 1;
   for (int l = top; l < last; l++) {
-    tail_sweeps<ND>(g, P(l), F(l), l, f, pre);
-    const double ih2 = par_ih2(g, l), lam = par_lam(g, f);
+    tail_sweeps<ND>(g, P(l), F(l), l, pre, s_ih2[l], s_idg[l]);
+    const double ih2 = s_ih2[l];
     for (int t = threadIdx.x; t < g.cells[l + 1]; t += blockDim.x) {
       int x, y, z;
-      decode<ND>(t, g.n[l + 1], x, y, z);
+      decode<ND>(t, g.n[l + 1], g.lg[l + 1], x, y, z);
       F(l + 1)[t] = restrict_cell<ND>(P(l), F(l), x, y, z, g.n[l], g.bc, ih2, lam);
       P(l + 1)[t] = 0.0;
     }
     __syncthreads();
   }
-  coarse_exact<ND>(g, P(last), F(last), last, f);
+  coarse_exact<ND>(g, P(last), F(last), s_ih2[last], lam);
   for (int l = last - 1; l >= top; l--) {
     for (int t = threadIdx.x; t < g.cells[l]; t += blockDim.x) {
       int x, y, z;
-      decode<ND>(t, g.n[l], x, y, z);
+      decode<ND>(t, g.n[l], g.lg[l], x, y, z);
       P(l)[t] += prolong_cell<ND>(P(l + 1), x, y, z, g.n[l + 1], g.bc);
     }
     __syncthreads();
-    tail_sweeps<ND>(g, P(l), F(l), l, f, post);
+    tail_sweeps<ND>(g, P(l), F(l), l, post, s_ih2[l], s_idg[l]);
   }
   for (int i = threadIdx.x; i < g.cells[top]; i += blockDim.x) g.phi[f][top][i] = P(top)[i];
 }
@@ -549,7 +636,7 @@ __global__ void __launch_bounds__(256) k_rd_explicit(MgDev g, RdK p, const doubl
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.cells[0]) return;
   int x, y, z;
-  decode<ND>(t, g.n[0], x, y, z);
+  decode<ND>(t, g.n[0], g.lg[0], x, y, z);
   const double ih2 = par_ih2(g, 0);
   double ru, rv;
   react(p, su[t], sv[t], ru, rv);
@@ -572,15 +659,16 @@ __global__ void __launch_bounds__(256) k_rd_split_rhs(MgDev g, RdK p, const doub
   g.phi[1][0][t] = v[t];
 }
 
-// IMEX first stage: f = -lambda ((w + dt F0(w)) + (dt/2) D lap(w)), and
-// F(w) kept for the second stage
+// IMEX first stage: f = -lambda ((w + dt F0(w)) + (dt/2) D lap(w)), initial
+// guess the explicit Euler predictor w + dt F(w); F(w) kept for the second
+// stage
 template <int ND>
 __global__ void __launch_bounds__(256) k_rd_imex_rhs(MgDev g, RdK p, const double* u, const double* v, double* Eu,
                                                      double* Ev, double dt) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.cells[0]) return;
   int x, y, z;
-  decode<ND>(t, g.n[0], x, y, z);
+  decode<ND>(t, g.n[0], g.lg[0], x, y, z);
   const double ih2 = par_ih2(g, 0);
   double ru, rv;
   react(p, u[t], v[t], ru, rv);
@@ -591,8 +679,8 @@ __global__ void __launch_bounds__(256) k_rd_imex_rhs(MgDev g, RdK p, const doubl
   const double hdt = 0.5 * dt;
   g.f[0][0][t] = -par_lam(g, 0) * ((u[t] + dt * ru) + hdt * du);
   g.f[1][0][t] = -par_lam(g, 1) * ((v[t] + dt * rv) + hdt * dv);
-  g.phi[0][0][t] = u[t];
-  g.phi[1][0][t] = v[t];
+  g.phi[0][0][t] = u[t] + dt * (ru + du);
+  g.phi[1][0][t] = v[t] + dt * (rv + dv);
 }
 
 // IMEX second stage: w1 = w + (dt/2) (F(w) + F(w*)), w* = the solve's phi
@@ -602,7 +690,7 @@ __global__ void __launch_bounds__(256) k_rd_imex_final(MgDev g, RdK p, double* u
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.cells[0]) return;
   int x, y, z;
-  decode<ND>(t, g.n[0], x, y, z);
+  decode<ND>(t, g.n[0], g.lg[0], x, y, z);
   const double ih2 = par_ih2(g, 0);
   const double* su = g.phi[0][0];
   const double* sv = g.phi[1][0];
@@ -624,8 +712,8 @@ struct amrv_mg {
   MgDev g{};
   hipStream_t st = nullptr;
   double* par = nullptr;
-  unsigned long long* red = nullptr;
-  unsigned long long* hred = nullptr;  // pinned copy of red
+  unsigned long long* hpart = nullptr;  // pinned slots of per-block maxima
+  int nb_cycle = 0, nb_init = 0;        // blocks folding norms: a V-cycle's last launch, the initial norms
   double* tmp[4] = {nullptr, nullptr, nullptr, nullptr};
   int tail = 0;
   size_t tail_lds = 0;
@@ -673,7 +761,8 @@ int validate(const amrv_mg_config* c) {
 
 struct MgLayout {
   int nlev = 0;
-  size_t off_phi[NFMAX][MG_MAXL]{}, off_f[NFMAX][MG_MAXL]{}, off_tmp[4]{}, off_par = 0, off_red = 0, total = 0;
+  size_t off_phi[NFMAX][MG_MAXL]{}, off_f[NFMAX][MG_MAXL]{}, off_phi2[NFMAX][MG_MAXL]{}, off_tmp[4]{}, off_par = 0,
+      total = 0;
 };
 
 MgLayout layout(const amrv_mg_config* c) {
@@ -690,6 +779,10 @@ MgLayout layout(const amrv_mg_config* c) {
       o += up(cells * 8);
       L.off_f[f][l] = o;
       o += up(cells * 8);
+      if (c->ndim == 2 && cells > (size_t)TAIL_CELLS) {
+        L.off_phi2[f][l] = o;
+        o += up(cells * 8);
+      }
     }
   size_t c0 = 1;
   for (int d = 0; d < c->ndim; d++) c0 *= (size_t)c->n;
@@ -699,23 +792,21 @@ MgLayout layout(const amrv_mg_config* c) {
   }
   L.off_par = o;
   o += up(PAR_COUNT * 8);
-  L.off_red = o;
-  o += up((2 * NFMAX + 1) * 8);
   L.total = o;
   return L;
 }
 
-bool tiled(const amrv_mg* m) { return m->g.nd == 2 && m->cfg.smoother == AMRV_MG_TILED && m->tail > 0; }
-
-size_t tile_lds(int H) { return (size_t)(TS + 2 * H) * (TS + 2 * H) * 2 * sizeof(double); }
+bool tiled(const amrv_mg* m) {
+  return m->g.nd == 2 && m->cfg.smoother == AMRV_MG_TILED && m->tail > 0 &&
+         2 * std::max(m->cfg.pre_sweeps, m->cfg.post_sweeps) + 1 <= HMAX;
+}
 
 // residual norms of level 0 (with_f: also max |f|), published to the pinned
 // host copy by the launch's last block
 template <int ND>
 void enqueue_norms_nd(amrv_mg* m, int with_f) {
   const MgDev& g = m->g;
-  hipLaunchKernelGGL(k_mg_resnorm<ND>, dim3(std::min(blocks_of(g.cells[0]), 256), g.nf), dim3(256), 0, m->st, g,
-                     with_f);
+  hipLaunchKernelGGL(k_mg_resnorm<ND>, dim3(m->nb_init, g.nf), dim3(256), 0, m->st, g, with_f);
 }
 
 // one V-cycle, ending with the residual norms of its result
@@ -726,8 +817,7 @@ void enqueue_vcycle_nd(amrv_mg* m) {
   const int pre = m->cfg.pre_sweeps, post = m->cfg.post_sweeps;
   if (tiled(m)) {
     for (int l = 0; l < m->tail; l++)
-      hipLaunchKernelGGL(k_mg_down2d, dim3((g.n[l] / TS) * (g.n[l] / TS), nf), dim3(256), tile_lds(2 * pre + 1),
-                         m->st, g, l, pre);
+      hipLaunchKernelGGL(k_mg_down2d, dim3((g.n[l] / TS) * (g.n[l] / TS), nf), dim3(256), 0, m->st, g, l, pre);
   } else {
     for (int l = 0; l < m->tail; l++) {
       for (int s = 0; s < pre; s++)
@@ -739,8 +829,8 @@ void enqueue_vcycle_nd(amrv_mg* m) {
   hipLaunchKernelGGL(k_mg_tail<ND>, dim3(nf), dim3(TAIL_THREADS), m->tail_lds, m->st, g, m->tail, pre, post);
   if (tiled(m)) {
     for (int l = m->tail - 1; l >= 0; l--)
-      hipLaunchKernelGGL(k_mg_up2d, dim3((g.n[l] / TS) * (g.n[l] / TS), nf), dim3(256),
-                         tile_lds(2 * post + (l == 0 ? 1 : 0)), m->st, g, l, post, l == 0 ? 1 : 0);
+      hipLaunchKernelGGL(k_mg_up2d, dim3((g.n[l] / TS) * (g.n[l] / TS), nf), dim3(256), 0, m->st, g, l, post,
+                         l == 0 ? 1 : 0);
     return;  // the finest level's up launch folded the norms
   }
   for (int l = m->tail - 1; l >= 0; l--) {
@@ -787,9 +877,7 @@ double bits_to_double(unsigned long long b) {
 // AMRV_ENOTCONVERGED / AMRV_ENONPHYSICAL
 int run_cycles(amrv_mg* m, double tol, int max_cycles, int* cycles, double* res_out, double* f_out) {
   const int nf = m->g.nf;
-  // clear the maxima and the block counter (a launch that failed earlier may
-  // have left them set), then the norms of the initial guess
-  hipLaunchKernelGGL(k_mg_fill_u64, dim3(1), dim3(64), 0, m->st, m->red, 2 * NFMAX + 1, 0ull);
+  // the norms of the initial guess
   if (m->g.nd == 2)
     enqueue_norms_nd<2>(m, 1);
   else
@@ -797,11 +885,18 @@ int run_cycles(amrv_mg* m, double tol, int max_cycles, int* cycles, double* res_
   MGCHK(hipGetLastError());
   MGCHK(hipStreamSynchronize(m->st));
   double fmax[NFMAX] = {0, 0}, res[NFMAX] = {0, 0};
-  for (int f = 0; f < nf; f++) fmax[f] = bits_to_double(m->hred[2 * f + 1]);
+  auto fold = [&](int row, int nb) {
+    unsigned long long v = 0;
+    const unsigned long long* p = m->hpart + (size_t)row * m->g.maxb;
+    for (int b = 0; b < nb; b++) v = p[b] > v ? p[b] : v;
+    return bits_to_double(v);
+  };
+  for (int f = 0; f < nf; f++) fmax[f] = fold(NFMAX + f, m->nb_init);
+  int nb = m->nb_init;
   auto done = [&]() {
     bool ok = true;
     for (int f = 0; f < nf; f++) {
-      res[f] = bits_to_double(m->hred[2 * f]);
+      res[f] = fold(f, nb);
       ok = ok && (res[f] <= tol * fmax[f]);
     }
     return ok;
@@ -839,6 +934,7 @@ int run_cycles(amrv_mg* m, double tol, int max_cycles, int* cycles, double* res_
       m->prof_cycles++;
     }
     c++;
+    nb = m->nb_cycle;
     ok = done();
     for (int f = 0; f < nf; f++)
       if (std::isnan(res[f])) {
@@ -887,16 +983,17 @@ int amrv_mg_create(const amrv_mg_config* cfg, void* workspace, size_t bytes, voi
     long long c = 1;
     for (int d = 0; d < cfg->ndim; d++) c *= g.n[l];
     g.cells[l] = (int)c;
+    g.lg[l] = 0;
+    while ((1 << g.lg[l]) < g.n[l]) g.lg[l]++;
     for (int f = 0; f < cfg->nfields; f++) {
       g.phi[f][l] = reinterpret_cast<double*>(base + L.off_phi[f][l]);
       g.f[f][l] = reinterpret_cast<double*>(base + L.off_f[f][l]);
+      g.phi2[f][l] = L.off_phi2[f][l] ? reinterpret_cast<double*>(base + L.off_phi2[f][l]) : nullptr;
     }
   }
   for (int i = 0; i < 4; i++) m->tmp[i] = reinterpret_cast<double*>(base + L.off_tmp[i]);
   m->par = reinterpret_cast<double*>(base + L.off_par);
-  m->red = reinterpret_cast<unsigned long long*>(base + L.off_red);
   g.par = m->par;
-  g.red = m->red;
   // the tail: the first level of at most TAIL_CELLS cells, and every level below
   int tail = 0;
   while (g.cells[tail] > TAIL_CELLS) tail++;
@@ -912,16 +1009,15 @@ int amrv_mg_create(const amrv_mg_config* cfg, void* workspace, size_t bytes, voi
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->tail_lds)
                      : hipFuncSetAttribute(reinterpret_cast<const void*>(k_mg_tail<3>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->tail_lds);
-  if (e == hipSuccess && cfg->ndim == 2) {
-    const int H = 2 * std::max(cfg->pre_sweeps, cfg->post_sweeps) + 1;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_mg_down2d), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)tile_lds(H));
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_mg_up2d), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)tile_lds(H));
+  m->nb_init = std::min(blocks_of(g.cells[0]), 256);
+  m->nb_cycle = tiled(m) ? (g.n[0] / TS) * (g.n[0] / TS) : m->nb_init;
+  g.maxb = std::max(m->nb_init, m->nb_cycle);
+  const size_t hbytes = (size_t)2 * NFMAX * g.maxb * sizeof(unsigned long long);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&m->hpart), hbytes);
+  if (e == hipSuccess) {
+    std::memset(m->hpart, 0, hbytes);
+    g.hpart = m->hpart;
   }
-  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&m->hred), 2 * NFMAX * sizeof(unsigned long long));
-  if (e == hipSuccess) m->g.hred = m->hred;
   if (e == hipSuccess) e = hipEventCreate(&m->e0);
   if (e == hipSuccess) e = hipEventCreate(&m->e1);
   if (e != hipSuccess) {
@@ -929,7 +1025,6 @@ int amrv_mg_create(const amrv_mg_config* cfg, void* workspace, size_t bytes, voi
     amrv_mg_destroy(m);
     return rc;
   }
-  std::memset(m->hred, 0, 2 * NFMAX * sizeof(unsigned long long));
   *out = m;
   return 0;
 }
@@ -938,7 +1033,7 @@ int amrv_mg_destroy(amrv_mg* m) {
   if (!m) return 0;
   if (m->st) (void)hipStreamSynchronize(m->st);
   if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
-  if (m->hred) (void)hipHostFree(m->hred);
+  if (m->hpart) (void)hipHostFree(m->hpart);
   if (m->e0) (void)hipEventDestroy(m->e0);
   if (m->e1) (void)hipEventDestroy(m->e1);
   delete m;
