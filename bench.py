@@ -10,7 +10,11 @@ full SSP-RK3 step (coarse-fine ghost slabs, stage kernels) and, every
 Prints ONE JSON line: MCUPS of the batched path (interior cells x steps / s),
 the stage kernel's HBM roofline fraction (algorithmic bytes / event-timed
 launch duration), the one-launch-per-block path, full-size parity of one step
-against the CPU oracle, and the oracle's own throughput on the host cores.
+against the CPU oracle, the oracle's own throughput on the host cores, and
+(object "reaction_diffusion") the paper's timed reaction-diffusion workload:
+Schnakenberg on 256^2 with IMEX, split and explicit steps through the
+multigrid solver.  --workload rd2d / rd3d print that workload's own line
+(ms per IMEX step on 256^2 / 128^3).
 """
 from __future__ import annotations
 
@@ -82,13 +86,136 @@ def make_workload(name: str):
     return desc, f, U
 
 
+RD_PAPER_MS = {"imex": 7.7, "split": 7.2, "explicit": 1.1}  # Sec. 3.4: 256^2 Schnakenberg, 4 CPU cores
+
+
+def rd_vcycle_bytes(nd: int, n: int, nfields: int = 2) -> float:
+    """Algorithmic HBM bytes of one V-cycle: per field and level above the
+    LDS-resident tail (levels of more than 4,096 cells), the down launch reads
+    phi and f and writes phi and the coarse f and phi (24 + 16/2^d bytes per
+    cell), the up launch reads phi, f and the coarse correction and writes
+    phi (24 + 8/2^d bytes per cell); the tail's own levels never leave LDS."""
+    total = 0.0
+    m = n
+    while m ** nd > 4096:
+        c = m ** nd
+        total += c * (24 + 16 / 2 ** nd) + c * (24 + 8 / 2 ** nd)
+        m //= 2
+    return nfields * total
+
+
+def rd_measure(nd: int, n: int, steps: int, warmup: int, log, cpu: bool = True, dt: float = 1e-3,
+               tol: float = 1e-7) -> dict:
+    """The paper's reaction-diffusion workload (Sec. 3.4): Schnakenberg on an
+    n^nd uniform grid with zero Neumann boundaries, dt = 1e-3, multigrid to
+    max residual <= tol max|f|; IMEX, split and explicit Euler steps timed
+    with the state resident in HBM, one IMEX step checked against the oracle
+    (exact solves), the oracle's IMEX step timed on the host."""
+    import numpy as np
+    import torch
+
+    from paper_2004_03275_amd import multigrid as M
+    from paper_2004_03275_amd import workloads as W
+
+    params = {"model": M.SCHNAKENBERG, "Du": 0.05, "Dv": 1.0, "p1": 100.0, "p2": 0.1305, "p3": 0.7695}
+    u0, v0, L = W.schnakenberg_initial(nd, n)
+    mg = M.GpuMultigrid(nd, n, M.NEUMANN, L, nfields=2)
+    res = {}
+    for name, scheme, sdt, k in (("imex", M.IMEX, dt, steps), ("split", M.SPLIT, dt, steps),
+                                 ("explicit", M.EULER, 1e-6, steps * 10)):
+        u = torch.tensor(u0, device="cuda:0").contiguous()
+        v = torch.tensor(v0, device="cuda:0").contiguous()
+        mg.rd_step(u, v, sdt, scheme, params, nsteps=warmup, tol=tol)
+        torch.cuda.synchronize()
+        mg.profile(True)
+        mg.profile_read()
+        mg.profile(False)
+        t0 = time.perf_counter()
+        cyc, _ = mg.rd_step(u, v, sdt, scheme, params, nsteps=k, tol=tol)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[name] = {"ms_per_step": 1e3 * el / k, "steps": k, "vcycles_per_step": cyc / k}
+    # V-cycle time from HIP events (separate run, same work)
+    u = torch.tensor(u0, device="cuda:0").contiguous()
+    v = torch.tensor(v0, device="cuda:0").contiguous()
+    mg.profile(True)
+    mg.rd_step(u, v, dt, M.IMEX, params, nsteps=steps, tol=tol)
+    vms, vcyc = mg.profile_read()
+    mg.profile(False)
+    vcycle_us = 1e3 * vms / max(vcyc, 1)
+    vbytes = rd_vcycle_bytes(nd, n)
+    achieved = vbytes / (vcycle_us * 1e-6) / 1e9
+    out = {"workload": f"schnakenberg_{nd}d_{n}", "cells": n ** nd, "dt": dt, "tol": tol,
+           "imex_ms_per_step": res["imex"]["ms_per_step"], "split_ms_per_step": res["split"]["ms_per_step"],
+           "explicit_euler_ms_per_step": res["explicit"]["ms_per_step"],
+           "imex_vcycles_per_step": res["imex"]["vcycles_per_step"],
+           "split_vcycles_per_step": res["split"]["vcycles_per_step"],
+           "vcycle_us": vcycle_us,
+           "roofline": {"bound": "hbm", "kernel": "one V-cycle (all its launches)", "achieved": achieved,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "algorithmic_bytes_per_vcycle": vbytes,
+                        "note": "latency-bound: the levels are cache-resident and each V-cycle is a chain of "
+                                "dependent launches"},
+           "paper_cpu_ms_per_step": dict(RD_PAPER_MS) if (nd, n) == (2, 256) else None}
+    log(f"rd {nd}D {n}: IMEX {out['imex_ms_per_step']:.3f} ms/step ({out['imex_vcycles_per_step']:.2f} cycles), "
+        f"split {out['split_ms_per_step']:.3f} ms, explicit {out['explicit_euler_ms_per_step']:.4f} ms, "
+        f"V-cycle {vcycle_us:.1f} us")
+    if cpu:
+        from oracle import rd as R
+
+        u = torch.tensor(u0, device="cuda:0").contiguous()
+        v = torch.tensor(v0, device="cuda:0").contiguous()
+        mg.rd_step(u, v, dt, M.IMEX, params, nsteps=1, tol=1e-12, max_cycles=80)
+        t0 = time.perf_counter()
+        ru, rv = R.step(u0, v0, dt, R.IMEX, R.SCHNAKENBERG_PARAMS, L, R.NEUMANN)
+        ocpu = time.perf_counter() - t0
+        diff = max(np.abs(u.cpu().numpy() - ru).max() / np.abs(ru).max(),
+                   np.abs(v.cpu().numpy() - rv).max() / np.abs(rv).max())
+        out["parity"] = {"steps": 1, "scheme": "imex", "tol": 1e-12, "rel_max_diff": float(diff),
+                         "bar": 1e-8}
+        out["cpu_baseline"] = {"value": 1e3 * ocpu, "unit": "ms per IMEX step", "cores": 1, "kind": "oracle",
+                               "sample": "one IMEX step of the same grid with exact (FFT/DCT) solves"}
+        log(f"rd parity: rel max diff {diff:.2e}; oracle {1e3 * ocpu:.1f} ms per IMEX step")
+    mg.close()
+    return out
+
+
+def rd_main(args, log):
+    nd, n = (2, 256) if args.workload == "rd2d" else (3, 128)
+    r = rd_measure(nd, n, args.steps, args.warmup, log, cpu=not args.no_cpu_baseline)
+    ms = r["imex_ms_per_step"]
+    paper = RD_PAPER_MS["imex"] if (nd, n) == (2, 256) else None
+    out = {
+        "metric": "ms per IMEX reaction-diffusion step (multigrid to max residual <= 1e-7 max|f|)",
+        "value": ms,
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": ms / paper if paper else None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": r["workload"], "cells": r["cells"], "dt": r["dt"], "tol": r["tol"],
+                   "model": "schnakenberg", "bc": "neumann", "smoother": "tiled 2D" if nd == 2 else "per-colour",
+                   "cycle": "V(2,2)"},
+        "roofline": r["roofline"],
+        "cpu_baseline": r.get("cpu_baseline"),
+        "parity": r.get("parity"),
+        "reaction_diffusion": r,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="blast", choices=["blast", "kh", "ot", "sod", "mhdblast2d", "mhdblast3d",
-                                                             "dambreak2d"])
+                                                             "dambreak2d", "rd2d", "rd3d"])
     ap.add_argument("--flag-every", type=int, default=10)
     ap.add_argument("--per-block-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -111,6 +238,8 @@ def main():
     ap.add_argument("--adaptive-flagger", default="lohner", choices=["lohner", "mlp"],
                     help="flags of the adaptive run: Loehner, or the learned flagger with Loehner fallback "
                          "(judged against full Loehner flags every second regrid)")
+    ap.add_argument("--no-rd", action="store_true",
+                    help="skip the reaction-diffusion measurement that the default run adds")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -128,6 +257,10 @@ def main():
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.workload in ("rd2d", "rd3d"):
+        rd_main(args, log)
+        return
 
     desc, f, U0 = make_workload(args.workload)
     s = f.scheme
@@ -370,6 +503,10 @@ def main():
         if ga is not g:
             ga.close()
 
+    rd = None
+    if args.workload == "blast" and not args.no_rd:
+        rd = rd_measure(2, 256, 20, 3, log, cpu=not args.no_cpu_baseline)
+
     counters = measured_counters(args.workload)
     names = {0: "per_block", 1: "grid", 2: "persistent"}
     bytes_per_cell_step = (2 + 3 * (s.rk_stages - 1)) * s.nvar * 8
@@ -428,6 +565,7 @@ def main():
         "parity": parity,
         "learned_flagger": flagger,
         "adaptive": adaptive,
+        "reaction_diffusion": rd,
     }
     print(json.dumps(out), flush=True)
 
