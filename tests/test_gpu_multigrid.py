@@ -220,3 +220,64 @@ def test_tiled_and_per_colour_smoothers_agree_bitwise(n, bc):
     a, b = out
     assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
     assert a[3] == b[3] and np.array_equal(a[4], b[4]) and np.array_equal(a[5], b[5])
+
+
+@pytest.mark.parametrize("nd,n", [(2, 4), (3, 4), (2, 8)])
+@pytest.mark.parametrize("bc", [R.PERIODIC, R.NEUMANN])
+def test_smallest_grids(nd, n, bc):
+    """n = 4: one level above the exact 2-per-side solve, all in the tail."""
+    torch, M = _mg()
+    f = _seeded((n,) * nd, 40 + n)
+    lam = 7.0
+    exact = R.helmholtz_solve(f, lam, 1.0, bc)
+    mg = M.GpuMultigrid(nd, n, bc, 1.0, nfields=1)
+    phi = torch.zeros(f.size, dtype=torch.float64, device="cuda:0")
+    c, res, _ = mg.solve(torch.tensor(f.ravel(), device="cuda:0"), phi, lam, tol=1e-13, max_cycles=60)
+    assert np.abs(phi.cpu().numpy().reshape(f.shape) - exact).max() <= 2.0 * res[0] / lam + 1e-14
+    mg.close()
+
+
+@pytest.mark.parametrize("pre,post", [(1, 1), (4, 4), (1, 3), (5, 5)])
+def test_sweep_counts_tiled_and_fallback(pre, post):
+    """Tiled halos for 1..4 sweeps; 5 sweeps exceed the largest halo and run
+    per colour.  Either way the two smoother settings agree bit for bit and
+    the answer meets the residual bound."""
+    torch, M = _mg()
+    n, lam = 256, 2.0
+    f = _seeded((n, n), 50 + pre)
+    exact = R.helmholtz_solve(f, lam, 1.0, R.NEUMANN)
+    out = []
+    for sm in (M.TILED, M.PER_COLOUR):
+        mg = M.GpuMultigrid(2, n, R.NEUMANN, 1.0, nfields=1, pre=pre, post=post, smoother=sm)
+        phi = torch.zeros(n * n, dtype=torch.float64, device="cuda:0")
+        c, res, _ = mg.solve(torch.tensor(f.ravel(), device="cuda:0"), phi, lam, tol=1e-10, max_cycles=60)
+        out.append((c, phi.cpu().numpy()))
+        assert np.abs(out[-1][1].reshape(n, n) - exact).max() <= 2.0 * res[0] / lam + 1e-13
+        mg.close()
+    assert out[0][0] == out[1][0] and np.array_equal(out[0][1], out[1][1])
+
+
+def test_periodic_3d_and_gray_scott_512():
+    torch, M = _mg()
+    # 3D periodic IMEX on a Schnakenberg state (periodic faces instead of Neumann)
+    u0, v0, L = W.schnakenberg_initial(3, 32)
+    p = R.SCHNAKENBERG_PARAMS
+    ru, rv = R.run(u0, v0, 1e-3, 2, R.IMEX, p, L, R.PERIODIC)
+    mg = M.GpuMultigrid(3, 32, R.PERIODIC, L, nfields=2)
+    u = torch.tensor(u0, device="cuda:0").contiguous()
+    v = torch.tensor(v0, device="cuda:0").contiguous()
+    mg.rd_step(u, v, 1e-3, R.IMEX, p, nsteps=2, tol=1e-12, max_cycles=60)
+    assert np.abs(u.cpu().numpy() - ru).max() / np.abs(ru).max() <= 1e-8
+    assert np.abs(v.cpu().numpy() - rv).max() / np.abs(rv).max() <= 1e-8
+    mg.close()
+    # Gray-Scott split steps on 512^2 (the paper's finest Gray-Scott level)
+    u0, v0, L = W.gray_scott_initial(512)
+    g = R.GRAY_SCOTT_PARAMS
+    ru, rv = R.run(u0, v0, 0.5, 2, R.SPLIT, g, L, R.PERIODIC)
+    mg = M.GpuMultigrid(2, 512, R.PERIODIC, L, nfields=2)
+    u = torch.tensor(u0, device="cuda:0").contiguous()
+    v = torch.tensor(v0, device="cuda:0").contiguous()
+    mg.rd_step(u, v, 0.5, R.SPLIT, g, nsteps=2, tol=1e-12, max_cycles=60)
+    assert np.abs(u.cpu().numpy() - ru).max() / np.abs(ru).max() <= 1e-8
+    assert np.abs(v.cpu().numpy() - rv).max() / np.abs(rv).max() <= 1e-8
+    mg.close()
