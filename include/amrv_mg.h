@@ -114,8 +114,11 @@ int amrv_mg_solve(amrv_mg* m, const double* f, double* phi, const double* lambda
  * and the given scheme.  SPLIT and IMEX need a solver created with
  * nfields = 2: both species' Helmholtz problems are solved together, each
  * to tol, at most max_cycles V-cycles per step (initial guess: the current
- * state for SPLIT, the explicit Euler predictor w + dt F(w) for IMEX).  cycles_total (may be NULL) receives the V-cycles summed over
- * the steps; res_max (may be NULL, 2 doubles) the last solve's residuals. */
+ * state for SPLIT, the explicit Euler predictor w + dt F(w) for IMEX).  If
+ * a solve does not converge (AMRV_ENOTCONVERGED) or meets a NaN
+ * (AMRV_ENONPHYSICAL), u and v hold the state after the last completed
+ * step.  cycles_total (may be NULL) receives the V-cycles summed over the
+ * steps; res_max (may be NULL, 2 doubles) the last solve's residuals. */
 int amrv_rd_step(amrv_mg* m, const amrv_rd_params* p, int32_t scheme, double dt, int32_t nsteps, double* u, double* v,
                  double tol, int32_t max_cycles, int32_t* cycles_total, double* res_max);
 
