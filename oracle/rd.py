@@ -2,8 +2,9 @@
 
 TEST INFRASTRUCTURE ONLY (tests/, smoke, bench's CPU leg).  Written from the
 paper's multigrid and reaction-diffusion sections (Sec. 2.3 on multigrid,
-Sec. 3.4: Eqs. gray-scott, schnakenberg, diff-helmholtz and imex, Table 1),
-sharing nothing with the HIP path.
+Sec. 2.4 on its divergence control of the MHD runs, Sec. 3.4: Eqs.
+gray-scott, schnakenberg, diff-helmholtz and imex, Table 1), sharing nothing
+with the HIP path.
 
 Grid: a uniform cell-centred grid of n cells per side on [0, L]^d (d = 2, 3),
 h = L / n, arrays indexed [z][y][x] with x fastest.  Boundaries: periodic, or
@@ -14,7 +15,9 @@ Discrete Laplacian (the standard second-order discretisation the paper
 names): per direction ((w_minus + w_plus) - 2 w) * (1/h^2), the directions
 added in the order x, y, z, with 1/h^2 formed as (n/L) * (n/L).
 
-Helmholtz problem (Eq. diff-helmholtz): lap(phi) - lambda phi = f, lambda > 0.
+Helmholtz problem (Eq. diff-helmholtz): lap(phi) - lambda phi = f, lambda > 0;
+Poisson (lambda = 0) for the divergence control of the MHD runs (Sec. 2.4),
+whose solution is fixed up to a constant (the zero-mean one here).
 This module solves it exactly (to rounding): the operator is diagonalised by
 the discrete Fourier transform (periodic) or the type-II cosine transform
 (Neumann), with eigenvalue sum_d (2 cos(theta_d) - 2) / h^2 - lambda,
@@ -109,6 +112,47 @@ def helmholtz_solve(f, lam: float, length: float, bc: int):
     if bc == PERIODIC:
         return np.real(np.fft.ifftn(np.fft.fftn(f) / mu))
     return sfft.idctn(sfft.dctn(f, type=2, norm="ortho") / mu, type=2, norm="ortho")
+
+
+def poisson_solve(f, length: float, bc: int):
+    """The zero-mean solution of lap(phi) = f - mean(f) (periodic or Neumann
+    faces, where lap is singular: constants are its null space and a right-
+    hand side is admissible when it sums to zero; the mean is the part no
+    phi can produce)."""
+    mu = _eigenvalues(f.shape, length, bc, 0.0)
+    mu.flat[0] = 1.0  # the constant mode: dropped below
+    if bc == PERIODIC:
+        hat = np.fft.fftn(f)
+        hat.flat[0] = 0.0
+        return np.real(np.fft.ifftn(hat / mu))
+    hat = sfft.dctn(f, type=2, norm="ortho")
+    hat.flat[0] = 0.0
+    return sfft.idctn(hat / mu, type=2, norm="ortho")
+
+
+def central_diff(w, d: int, length: float, bc: int):
+    """(w(+1) - w(-1)) * (n / (2L)) along direction d (0 = x)."""
+    n = w.shape[-1]
+    ax = w.ndim - 1 - d
+    return (_shift(w, ax, +1, bc) - _shift(w, ax, -1, bc)) * (0.5 * n / length)
+
+
+def central_div(B, length: float, bc: int):
+    """sum_d of the central differences of B[d], added x, y, z."""
+    out = central_diff(B[0], 0, length, bc)
+    for d in range(1, len(B)):
+        out = out + central_diff(B[d], d, length, bc)
+    return out
+
+
+def divb_project(B, length: float, bc: int):
+    """The multigrid divergence control of the MHD runs (Sec. 2.4): solve
+    lap(phi) = div B* and set B = B* - grad phi (central differences for div
+    and grad, the 5/7-point Laplacian for lap: an approximate projection,
+    which removes the divergence up to the difference between lap and
+    div(grad)).  Returns (B, phi)."""
+    phi = poisson_solve(central_div(B, length, bc), length, bc)
+    return [B[d] - central_diff(phi, d, length, bc) for d in range(len(B))], phi
 
 
 def reaction(u, v, p: dict):

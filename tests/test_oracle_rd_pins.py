@@ -228,3 +228,82 @@ def test_schnakenberg_2d_keeps_its_mirror_symmetry():
 def test_rejects_nonpositive_lambda():
     with pytest.raises(ValueError):
         R.helmholtz_solve(np.zeros((4, 4)), 0.0, 1.0, R.PERIODIC)
+
+
+# -- Poisson (lambda = 0) and the divergence control of Sec. 2.4 -------------
+
+@pytest.mark.parametrize("bc", [R.PERIODIC, R.NEUMANN])
+def test_poisson_solve_is_the_minimum_norm_solution(bc):
+    """The dense singular system solved by least squares (numpy lstsq gives
+    the minimum-norm solution, which for a symmetric matrix with the
+    constants as null space is the zero-mean one)."""
+    n = 8
+    rng = np.random.default_rng(3 + bc)
+    f = rng.standard_normal((n, n))
+    f -= f.mean()
+    phi = R.poisson_solve(f, 1.3, bc)
+    A = _dense_matrix(2, n, 1.3, bc, 0.0)
+    ref = np.linalg.lstsq(A, f.ravel(), rcond=None)[0].reshape(n, n)
+    assert np.abs(phi - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert abs(phi.mean()) < 1e-14 * np.abs(phi).max()
+    r = f - R.laplacian(phi, 1.3, bc)
+    assert np.abs(r).max() <= 1e-10 * np.abs(f).max()
+
+
+def test_poisson_manufactured_second_order():
+    errs = []
+    for n in (32, 64, 128):
+        x, y = W.rd_cell_centres(2, n, 1.0)
+        exact = np.cos(2 * np.pi * x) * np.sin(4 * np.pi * y)
+        f = -(4 + 16) * np.pi ** 2 * exact
+        got = R.poisson_solve(f, 1.0, R.PERIODIC)
+        errs.append(np.abs(got - exact).max())
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders > 1.95) and np.all(orders < 2.05), (errs, orders)
+
+
+def _curl_field(n, L=1.0, nd=2):
+    """A field that is divergence-free under central differences: the
+    central-difference curl of a smooth potential (central differences in
+    different directions commute)."""
+    xs = W.rd_cell_centres(nd, n, L)
+    if nd == 2:
+        x, y = xs
+        A = np.sin(2 * np.pi * x / L) * np.cos(2 * np.pi * y / L) + 0.3 * np.cos(4 * np.pi * x / L)
+        return [R.central_diff(A, 1, L, R.PERIODIC), -R.central_diff(A, 0, L, R.PERIODIC)]
+    x, y, z = xs
+    Ax = np.sin(2 * np.pi * y / L) * np.cos(2 * np.pi * z / L)
+    Ay = np.cos(2 * np.pi * x / L) * np.sin(4 * np.pi * z / L)
+    Az = np.sin(2 * np.pi * (x + y) / L)
+    cd = lambda w, d: R.central_diff(w, d, L, R.PERIODIC)
+    return [cd(Az, 1) - cd(Ay, 2), cd(Ax, 2) - cd(Az, 0), cd(Ay, 0) - cd(Ax, 1)]
+
+
+@pytest.mark.parametrize("nd", [2, 3])
+def test_projection_leaves_a_discretely_solenoidal_field_alone(nd):
+    n = 32 if nd == 2 else 16
+    B = _curl_field(n, nd=nd)
+    assert np.abs(R.central_div(B, 1.0, R.PERIODIC)).max() < 1e-11
+    P, phi = R.divb_project(B, 1.0, R.PERIODIC)
+    for d in range(nd):
+        assert np.abs(P[d] - B[d]).max() < 1e-11
+
+
+def test_projection_removes_a_smooth_gradient_at_second_order():
+    """B* = B_sol + grad(psi) with psi smooth: the projection returns B_sol
+    up to O(h^2), and the central divergence drops by orders of magnitude."""
+    errs, ratios = [], []
+    for n in (32, 64, 128):
+        x, y = W.rd_cell_centres(2, n, 1.0)
+        Bs = _curl_field(n)
+        psi = np.cos(2 * np.pi * x) * np.cos(2 * np.pi * y)
+        gx = -2 * np.pi * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y)
+        gy = -2 * np.pi * np.cos(2 * np.pi * x) * np.sin(2 * np.pi * y)
+        B = [Bs[0] + gx, Bs[1] + gy]
+        P, _ = R.divb_project(B, 1.0, R.PERIODIC)
+        errs.append(max(np.abs(P[0] - Bs[0]).max(), np.abs(P[1] - Bs[1]).max()))
+        ratios.append(np.abs(R.central_div(P, 1.0, R.PERIODIC)).max() /
+                      np.abs(R.central_div(B, 1.0, R.PERIODIC)).max())
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders > 1.9), (errs, orders)
+    assert max(ratios) < 1e-2, ratios
