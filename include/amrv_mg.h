@@ -15,7 +15,9 @@
  * Discrete Laplacian: per direction ((w_minus + w_plus) - 2 w) / h^2, the
  * directions summed in the order x, y, z.
  *
- * Helmholtz problem: lap(phi) - lambda phi = f with lambda > 0.  The solver
+ * Helmholtz problem: lap(phi) - lambda phi = f with lambda > 0, or the
+ * Poisson problem (lambda = 0) of the divergence control of the paper's MHD
+ * runs (Sec. 2.4), whose solution is fixed up to a constant.  The solver
  * runs V-cycles (red-black Gauss-Seidel smoothing with `pre` and `post`
  * sweeps, residual restriction by averaging the 2^ndim children, correction
  * prolongation by bi/trilinear interpolation, coarse grids rediscretised
@@ -23,7 +25,9 @@
  * residual |f - (lap(phi) - lambda phi)| is at most tol times max |f| -- the
  * paper's stopping rule, Sec. 3.4, with tol = 1e-7 there.  Since lambda I - lap is an M-matrix
  * whose rows sum to lambda, the returned solution differs from the exact
- * discrete one by at most (max residual) / lambda in every cell.
+ * discrete one by at most (max residual) / lambda in every cell (lambda = 0:
+ * up to a constant, by at most sqrt(cells) (max residual) / mu_1 with mu_1
+ * the smallest non-zero eigenvalue magnitude of lap).
  *
  * Conventions: as in amrv.h (0 on success, negative AMRV_E* codes,
  * amrv_last_error() for the message).  All device pointers belong to the
@@ -101,13 +105,28 @@ int amrv_mg_destroy(amrv_mg* m);
 /* Solves lap(phi) - lambda phi = f (Sec. 2.3, Eq. diff-helmholtz) for
  * nfields fields stored one after another (f and phi: nfields * n^ndim
  * doubles each, device; phi holds the initial guess on entry and the
- * solution on return; lambda: nfields host values, each > 0).  Stops when
+ * solution on return; lambda: nfields host values, each >= 0; with
+ * lambda = 0 the right-hand side must sum to zero, or the residual cannot
+ * fall below |mean f| and the call ends with AMRV_ENOTCONVERGED).  Stops when
  * every field's max residual <= tol * its max |f| (tol > 0), or after
  * max_cycles V-cycles (then AMRV_ENOTCONVERGED, phi holding the last
  * iterate).  cycles, res_max and f_max (host, may be NULL) receive the
  * cycle count and, per field, the final max residual and max |f|. */
 int amrv_mg_solve(amrv_mg* m, const double* f, double* phi, const double* lambda, double tol, int32_t max_cycles,
                   int32_t* cycles, double* res_max, double* f_max);
+
+/* Divergence control of the MHD runs (Sec. 2.4) on one uniform periodic
+ * grid: solves lap(phi) = div B* (central differences (w(+1) - w(-1)) n/(2L),
+ * directions added x, y, z) to tol, then sets B = B* - grad phi with the
+ * same differences -- an approximate projection: it removes the divergence
+ * up to the difference between the 5/7-point lap and div(grad).  bx, by, bz:
+ * device arrays of n^ndim doubles (bz unused in 2D), updated in place.  Needs
+ * a solver with nfields = 1 and periodic faces (the central divergence of a
+ * field with mirrored Neumann faces does not sum to zero).  div_before and
+ * div_after (host, may be NULL) receive max |div B| before and after;
+ * cycles the V-cycle count. */
+int amrv_mg_divb_project(amrv_mg* m, double* bx, double* by, double* bz, double tol, int32_t max_cycles,
+                         int32_t* cycles, double* div_before, double* div_after);
 
 /* nsteps time steps of the reaction-diffusion model (Sec. 3.4) on the
  * device fields u, v (n^ndim doubles each, updated in place) with step dt

@@ -136,6 +136,8 @@ SIGNATURES = {
                       ctypes.c_int),
     "amrv_rd_step": ([P, ctypes.POINTER(RdParams), ctypes.c_int32, ctypes.c_double, ctypes.c_int32, P, P,
                       ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), P], ctypes.c_int),
+    "amrv_mg_divb_project": ([P, P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "amrv_mg_profile": ([P, ctypes.c_int32], ctypes.c_int),
     "amrv_mg_profile_read": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "amrv_last_error": ([], ctypes.c_char_p),

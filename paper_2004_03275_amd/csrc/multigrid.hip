@@ -544,6 +544,12 @@ __device__ void tail_sweeps(const MgDev& g, double* P, const double* F, int l, i
     }
 }
 
+// exact solve on the coarsest grid (2 cells per side): per direction the
+// operator couples the two cells as c [[-1, 1], [1, -1]] (c = 1/h^2 with the
+// mirrored Neumann ghost, 2/h^2 with the periodic wrap), so the 2^d Walsh
+// patterns (-1)^popcount(k & cell) are its eigenvectors, with eigenvalue
+// -2c per set bit of k, minus lambda.  For lambda = 0 the constant pattern
+// has eigenvalue 0 and the correction gets no constant part.
 template <int ND>
 __device__ void coarse_exact(const MgDev& g, double* P, const double* F, double ih2, double lam) {
   constexpr int C = 1 << ND;
@@ -559,7 +565,7 @@ __device__ void coarse_exact(const MgDev& g, double* P, const double* F, double 
 #pragma unroll
       for (int d = 0; d < ND; d++)
         if ((k >> d) & 1) mu -= c2;
-      hat[k] = s / (mu * C);
+      hat[k] = mu == 0.0 ? 0.0 : s / (mu * C);
     }
 #pragma unroll
     for (int c = 0; c < C; c++) {
@@ -612,6 +618,64 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_mg_tail(MgDev g, int top, int 
     tail_sweeps<ND>(g, P(l), F(l), l, post, s_ih2[l], s_idg[l]);
   }
   for (int i = threadIdx.x; i < g.cells[top]; i += blockDim.x) g.phi[f][top][i] = P(top)[i];
+}
+
+// ---- divergence control of the MHD runs (Sec. 2.4): lap(phi) = div B*,
+// B = B* - grad phi, central differences (w(+1) - w(-1)) * (n / 2L) ---------
+
+template <int ND>
+__device__ __forceinline__ double cdiff(const double* w, int x, int y, int z, int n, int bc, int d, double c) {
+  if (d == 0) return (w[(z * n + y) * n + ip(x, n, bc)] - w[(z * n + y) * n + im(x, n, bc)]) * c;
+  if (d == 1) return (w[(z * n + ip(y, n, bc)) * n + x] - w[(z * n + im(y, n, bc)) * n + x]) * c;
+  return (w[(ip(z, n, bc) * n + y) * n + x] - w[(im(z, n, bc) * n + y) * n + x]) * c;
+}
+
+template <int ND>
+__device__ __forceinline__ double cdiv(const double* b0, const double* b1, const double* b2, int x, int y, int z,
+                                       int n, int bc, double c) {
+  double d = cdiff<ND>(b0, x, y, z, n, bc, 0, c);
+  d = d + cdiff<ND>(b1, x, y, z, n, bc, 1, c);
+  if constexpr (ND == 3) d = d + cdiff<ND>(b2, x, y, z, n, bc, 2, c);
+  return d;
+}
+
+// right-hand side div B*, initial guess 0
+template <int ND>
+__global__ void __launch_bounds__(256) k_mg_divb(MgDev g, const double* b0, const double* b1, const double* b2,
+                                                 double c) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.cells[0]) return;
+  int x, y, z;
+  decode<ND>(t, g.n[0], g.lg[0], x, y, z);
+  g.f[0][0][t] = cdiv<ND>(b0, b1, b2, x, y, z, g.n[0], g.bc, c);
+  g.phi[0][0][t] = 0.0;
+}
+
+template <int ND>
+__global__ void __launch_bounds__(256) k_mg_gradsub(MgDev g, double* b0, double* b1, double* b2, double c) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.cells[0]) return;
+  int x, y, z;
+  decode<ND>(t, g.n[0], g.lg[0], x, y, z);
+  const double* phi = g.phi[0][0];
+  b0[t] = b0[t] - cdiff<ND>(phi, x, y, z, g.n[0], g.bc, 0, c);
+  b1[t] = b1[t] - cdiff<ND>(phi, x, y, z, g.n[0], g.bc, 1, c);
+  if constexpr (ND == 3) b2[t] = b2[t] - cdiff<ND>(phi, x, y, z, g.n[0], g.bc, 2, c);
+}
+
+// max |div B| into the host slots of row 0
+template <int ND>
+__global__ void __launch_bounds__(256) k_mg_divnorm(MgDev g, const double* b0, const double* b1, const double* b2,
+                                                    double c) {
+  unsigned long long m = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.cells[0]; t += gridDim.x * blockDim.x) {
+    int x, y, z;
+    decode<ND>(t, g.n[0], g.lg[0], x, y, z);
+    const unsigned long long a =
+        (unsigned long long)__double_as_longlong(fabs(cdiv<ND>(b0, b1, b2, x, y, z, g.n[0], g.bc, c)));
+    m = a > m ? a : m;
+  }
+  fold_norms(g, 0, m, 0ull, 0);
 }
 
 // ---- reaction-diffusion (Sec. 3.4) ---------------------------------------
@@ -1046,7 +1110,8 @@ int amrv_mg_solve(amrv_mg* m, const double* f, double* phi, const double* lambda
   if (!(tol > 0.0)) return set_error(AMRV_EINVAL, "tol must be positive");
   if (max_cycles < 0) return set_error(AMRV_EINVAL, "max_cycles must be >= 0");
   for (int i = 0; i < m->g.nf; i++)
-    if (!(lambda[i] > 0.0) || !std::isfinite(lambda[i])) return set_error(AMRV_EINVAL, "lambda must be positive and finite");
+    if (!(lambda[i] >= 0.0) || !std::isfinite(lambda[i]))
+      return set_error(AMRV_EINVAL, "lambda must be non-negative and finite");
   if (int rc = set_params(m, lambda)) return rc;
   const size_t bytes = (size_t)m->g.cells[0] * sizeof(double);
   for (int i = 0; i < m->g.nf; i++) {
@@ -1060,6 +1125,41 @@ int amrv_mg_solve(amrv_mg* m, const double* f, double* phi, const double* lambda
     MGCHK(hipMemcpyAsync(phi + (size_t)i * m->g.cells[0], m->g.phi[i][0], bytes, hipMemcpyDeviceToDevice, m->st));
   MGCHK(hipStreamSynchronize(m->st));
   return rc;
+}
+
+int amrv_mg_divb_project(amrv_mg* m, double* bx, double* by, double* bz, double tol, int32_t max_cycles,
+                         int32_t* cycles, double* div_before, double* div_after) {
+  if (!m || !bx || !by || (m->g.nd == 3 && !bz)) return set_error(AMRV_EINVAL, "null argument");
+  if (m->g.nf != 1) return set_error(AMRV_EINVAL, "the projection needs a solver created with nfields = 1");
+  if (m->g.bc != AMRV_MG_PERIODIC) return set_error(AMRV_EINVAL, "the projection needs periodic faces");
+  if (!(tol > 0.0) || max_cycles < 0) return set_error(AMRV_EINVAL, "bad tol or max_cycles");
+  const double lam0 = 0.0;
+  if (int rc = set_params(m, &lam0)) return rc;
+  const MgDev& g = m->g;
+  const double c = 0.5 * g.n[0] / m->cfg.length;
+  const bool d2 = g.nd == 2;
+  const int nb = blocks_of(g.cells[0]);
+  double* b2 = d2 ? bx : bz;  // not read in 2D
+  auto divmax = [&](double* out) -> int {
+    hipLaunchKernelGGL(d2 ? k_mg_divnorm<2> : k_mg_divnorm<3>, dim3(m->nb_init), dim3(256), 0, m->st, g, bx, by, b2,
+                       c);
+    MGCHK(hipGetLastError());
+    MGCHK(hipStreamSynchronize(m->st));
+    unsigned long long v = 0;
+    for (int b = 0; b < m->nb_init; b++) v = m->hpart[b] > v ? m->hpart[b] : v;
+    if (out) *out = bits_to_double(v);
+    return 0;
+  };
+  if (int rc = divmax(div_before)) return rc;
+  hipLaunchKernelGGL(d2 ? k_mg_divb<2> : k_mg_divb<3>, dim3(nb), dim3(256), 0, m->st, g, bx, by, b2, c);
+  MGCHK(hipGetLastError());
+  int cyc = 0;
+  const int rc = run_cycles(m, tol, max_cycles, &cyc, nullptr, nullptr);
+  if (cycles) *cycles = cyc;
+  if (rc) return rc;
+  hipLaunchKernelGGL(d2 ? k_mg_gradsub<2> : k_mg_gradsub<3>, dim3(nb), dim3(256), 0, m->st, g, bx, by, b2, c);
+  MGCHK(hipGetLastError());
+  return divmax(div_after);
 }
 
 int amrv_rd_step(amrv_mg* m, const amrv_rd_params* p, int32_t scheme, double dt, int32_t nsteps, double* u, double* v,

@@ -98,6 +98,22 @@ class GpuMultigrid:
                                      int(max_cycles), ctypes.byref(cyc), res.ctypes.data))
         return cyc.value, res
 
+    def divb_project(self, B, tol: float = 1e-10, max_cycles: int = 50):
+        """The divergence control of Sec. 2.4 on the ndim device arrays B
+        (updated in place).  Returns (cycles, max |div B| before, after)."""
+        cells = self.n ** self.ndim
+        if len(B) != self.ndim:
+            raise ValueError("one array per dimension")
+        for b in B:
+            self._dev(b, cells)
+        ptr = [ctypes.c_void_p(b.data_ptr()) for b in B] + ([ctypes.c_void_p(0)] if self.ndim == 2 else [])
+        cyc = ctypes.c_int32()
+        before, after = ctypes.c_double(), ctypes.c_double()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        N.check(N.lib().amrv_mg_divb_project(self._h, ptr[0], ptr[1], ptr[2], float(tol), int(max_cycles),
+                                             ctypes.byref(cyc), ctypes.byref(before), ctypes.byref(after)))
+        return cyc.value, before.value, after.value
+
     def profile(self, enable: bool = True):
         N.check(N.lib().amrv_mg_profile(self._h, 1 if enable else 0))
 

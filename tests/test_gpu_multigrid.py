@@ -177,8 +177,11 @@ def test_errors():
     f = torch.ones(32 * 32, dtype=torch.float64, device="cuda:0")
     phi = torch.zeros_like(f)
     with pytest.raises(N.AmrvError) as e:
-        mg.solve(f, phi, 0.0)
+        mg.solve(f, phi, -1.0)
     assert e.value.code == N.EINVAL
+    with pytest.raises(N.AmrvError) as e:  # lambda = 0 with a right-hand side that does not sum to zero
+        mg.solve(f, phi, 0.0, tol=1e-9, max_cycles=20)
+    assert e.value.code == N.ENOTCONVERGED
     with pytest.raises(N.AmrvError) as e:
         mg.solve(torch.tensor(_seeded((32, 32), 9), device="cuda:0").contiguous(), phi, 1.0, tol=1e-15,
                  max_cycles=1)
@@ -281,3 +284,86 @@ def test_periodic_3d_and_gray_scott_512():
     assert np.abs(u.cpu().numpy() - ru).max() / np.abs(ru).max() <= 1e-8
     assert np.abs(v.cpu().numpy() - rv).max() / np.abs(rv).max() <= 1e-8
     mg.close()
+
+
+# -- Poisson (lambda = 0) and the divergence control of Sec. 2.4 -------------
+
+def _mu1(n, L, bc):
+    """Smallest non-zero eigenvalue magnitude of the discrete Laplacian."""
+    theta = 2 * np.pi / n if bc == R.PERIODIC else np.pi / n
+    return (2.0 - 2.0 * np.cos(theta)) * (n / L) ** 2
+
+
+@pytest.mark.parametrize("nd,n", [(2, 64), (2, 256), (3, 32)])
+@pytest.mark.parametrize("bc", [R.PERIODIC, R.NEUMANN])
+def test_poisson_solve_up_to_a_constant(nd, n, bc):
+    """lambda = 0 with a right-hand side that sums to zero: the GPU answer
+    minus its mean equals the oracle's zero-mean solution within
+    sqrt(cells) max|r| / mu_1 (2-norm bound of the error orthogonal to the
+    constants)."""
+    torch, M = _mg()
+    f = _seeded((n,) * nd, 70 + n) + np.cos(2 * np.pi * W.rd_cell_centres(nd, n, 1.0)[1])
+    f -= f.mean()
+    exact = R.poisson_solve(f, 1.0, bc)
+    mg = M.GpuMultigrid(nd, n, bc, 1.0, nfields=1)
+    phi = torch.zeros(f.size, dtype=torch.float64, device="cuda:0")
+    c, res, fmax = mg.solve(torch.tensor(f.ravel(), device="cuda:0"), phi, 0.0, tol=1e-11, max_cycles=60)
+    got = phi.cpu().numpy().reshape(f.shape)
+    got -= got.mean()
+    err = np.abs(got - exact).max()
+    bound = 2.0 * np.sqrt(f.size) * (res[0] + abs(f.mean())) / _mu1(n, 1.0, bc) + 1e-12 * np.abs(exact).max()
+    print(f"[mg] poisson {nd}D n={n} bc={bc}: {c} cycles, res {res[0]:.2e}, err {err:.2e}, bound {bound:.2e}",
+          flush=True)
+    assert err <= bound
+    mg.close()
+
+
+def _solenoidal_plus_gradient(nd, n):
+    xs = W.rd_cell_centres(nd, n, 1.0)
+    cd = lambda w, d: R.central_diff(w, d, 1.0, R.PERIODIC)
+    if nd == 2:
+        x, y = xs
+        A = np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y) + 0.3 * np.cos(4 * np.pi * x)
+        psi = np.cos(2 * np.pi * x) * np.cos(4 * np.pi * y)
+        B = [cd(A, 1), -cd(A, 0)]
+    else:
+        x, y, z = xs
+        Ax = np.sin(2 * np.pi * y) * np.cos(2 * np.pi * z)
+        Ay = np.cos(2 * np.pi * x) * np.sin(4 * np.pi * z)
+        Az = np.sin(2 * np.pi * (x + y))
+        psi = np.cos(2 * np.pi * x) * np.sin(2 * np.pi * y) * np.cos(2 * np.pi * z)
+        B = [cd(Az, 1) - cd(Ay, 2), cd(Ax, 2) - cd(Az, 0), cd(Ay, 0) - cd(Ax, 1)]
+    noise = [0.01 * _seeded((n,) * nd, 90 + d) for d in range(nd)]
+    return [B[d] + cd(psi, d) + noise[d] for d in range(nd)]
+
+
+@pytest.mark.parametrize("nd,n", [(2, 128), (3, 32)])
+def test_divb_projection_matches_the_oracle(nd, n):
+    torch, M = _mg()
+    B = _solenoidal_plus_gradient(nd, n)
+    ref, _ = R.divb_project(B, 1.0, R.PERIODIC)
+    mg = M.GpuMultigrid(nd, n, M.PERIODIC, 1.0, nfields=1)
+    Bt = [torch.tensor(b, device="cuda:0").contiguous() for b in B]
+    c, before, after = mg.divb_project(Bt, tol=1e-12, max_cycles=80)
+    assert before == np.abs(R.central_div(B, 1.0, R.PERIODIC)).max()  # same arithmetic, bit for bit
+    assert after == np.abs(R.central_div([b.cpu().numpy() for b in Bt], 1.0, R.PERIODIC)).max()
+    err = max(np.abs(Bt[d].cpu().numpy() - ref[d]).max() for d in range(nd))
+    scale = max(np.abs(b).max() for b in B)
+    print(f"[mg] divB {nd}D n={n}: {c} cycles, max|div| {before:.3e} -> {after:.3e}, vs oracle {err:.2e}",
+          flush=True)
+    assert err <= 1e-9 * scale
+    assert after < 0.1 * before
+    mg.close()
+
+
+def test_divb_projection_rejects_unsupported_setups():
+    torch, M = _mg()
+    from paper_2004_03275_amd import _native as N
+
+    B = [torch.zeros(64 * 64, dtype=torch.float64, device="cuda:0") for _ in range(2)]
+    for kw in ({"nfields": 2, "bc": M.PERIODIC}, {"nfields": 1, "bc": M.NEUMANN}):
+        mg = M.GpuMultigrid(2, 64, kw["bc"], 1.0, nfields=kw["nfields"])
+        with pytest.raises(N.AmrvError) as e:
+            mg.divb_project(B)
+        assert e.value.code == N.EINVAL
+        mg.close()
