@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/amrv.h"
+#include "errors.hpp"
 #include "forest.hpp"
 #include "regrid.hpp"
 #include "internal.hpp"

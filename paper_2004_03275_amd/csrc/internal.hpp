@@ -18,9 +18,6 @@
 
 namespace amrv {
 
-// records msg for amrv_last_error() and returns code
-int set_error(int code, const char* msg);
-
 enum { NB_SAME = 0, NB_COARSER = 1, NB_FINER = 2, NB_BND = 3 };
 constexpr int MAXLEV = 16;
 

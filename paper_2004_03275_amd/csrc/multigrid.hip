@@ -34,7 +34,7 @@
 #include <string>
 
 #include "../../include/amrv_mg.h"
-#include "internal.hpp"
+#include "errors.hpp"
 
 namespace {
 
