@@ -133,7 +133,10 @@ int amrv_mg_divb_project(amrv_mg* m, double* bx, double* by, double* bz, double 
  * and the given scheme.  SPLIT and IMEX need a solver created with
  * nfields = 2: both species' Helmholtz problems are solved together, each
  * to tol, at most max_cycles V-cycles per step (initial guess: the current
- * state for SPLIT, the explicit Euler predictor w + dt F(w) for IMEX).  If
+ * state for SPLIT, the explicit Euler predictor w + dt F(w) for IMEX).  To
+ * save host synchronisations a solve runs the previous solve's cycle count
+ * less one before its first residual check, so it may run a cycle or two
+ * more than tol demands (never fewer).  If
  * a solve does not converge (AMRV_ENOTCONVERGED) or meets a NaN
  * (AMRV_ENONPHYSICAL), u and v hold the state after the last completed
  * step.  cycles_total (may be NULL) receives the V-cycles summed over the

@@ -787,6 +787,7 @@ struct amrv_mg {
   double prof_ms = 0.0;
   int64_t prof_cycles = 0;
   double par_lam[NFMAX] = {-1.0, -1.0};
+  int last_cycles = 0;  // V-cycles of the last reaction-diffusion solve
 };
 
 namespace {
@@ -937,16 +938,42 @@ double bits_to_double(unsigned long long b) {
   return d;
 }
 
-// the V-cycle loop on level-0 buffers already filled; returns 0, or
-// AMRV_ENOTCONVERGED / AMRV_ENONPHYSICAL
-int run_cycles(amrv_mg* m, double tol, int max_cycles, int* cycles, double* res_out, double* f_out) {
+int launch_cycle(amrv_mg* m) {
+  if (m->cfg.use_graph) {
+    if (!m->gexec) {
+      hipGraph_t gr;
+      MGCHK(hipStreamBeginCapture(m->st, hipStreamCaptureModeThreadLocal));
+      enqueue_vcycle(m);
+      MGCHK(hipStreamEndCapture(m->st, &gr));
+      hipError_t e = hipGraphInstantiate(&m->gexec, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      MGCHK(e);
+    }
+    MGCHK(hipGraphLaunch(m->gexec, m->st));
+  } else {
+    enqueue_vcycle(m);
+    MGCHK(hipGetLastError());
+  }
+  return 0;
+}
+
+// the V-cycle loop on level-0 buffers already filled: `unchecked` cycles
+// are enqueued behind the initial norms before the host first waits (each
+// host check is a synchronisation), then the residual is checked after every
+// cycle.  Returns 0, or AMRV_ENOTCONVERGED / AMRV_ENONPHYSICAL.
+int run_cycles(amrv_mg* m, double tol, int max_cycles, int unchecked, int* cycles, double* res_out,
+               double* f_out) {
   const int nf = m->g.nf;
-  // the norms of the initial guess
+  if (m->profile) unchecked = 0;  // profiling times each cycle on its own
+  unchecked = std::max(0, std::min(unchecked, max_cycles));
+  // the norms of the initial guess (max |f| is taken from these)
   if (m->g.nd == 2)
     enqueue_norms_nd<2>(m, 1);
   else
     enqueue_norms_nd<3>(m, 1);
   MGCHK(hipGetLastError());
+  for (int i = 0; i < unchecked; i++)
+    if (int rc = launch_cycle(m)) return rc;
   MGCHK(hipStreamSynchronize(m->st));
   double fmax[NFMAX] = {0, 0}, res[NFMAX] = {0, 0};
   auto fold = [&](int row, int nb) {
@@ -956,7 +983,7 @@ int run_cycles(amrv_mg* m, double tol, int max_cycles, int* cycles, double* res_
     return bits_to_double(v);
   };
   for (int f = 0; f < nf; f++) fmax[f] = fold(NFMAX + f, m->nb_init);
-  int nb = m->nb_init;
+  int nb = unchecked ? m->nb_cycle : m->nb_init;
   auto done = [&]() {
     bool ok = true;
     for (int f = 0; f < nf; f++) {
@@ -965,30 +992,16 @@ int run_cycles(amrv_mg* m, double tol, int max_cycles, int* cycles, double* res_
     }
     return ok;
   };
-  int c = 0;
+  int c = unchecked;
   bool ok = done();
   for (int f = 0; f < nf; f++)
     if (std::isnan(res[f]) || std::isnan(fmax[f])) {
-      if (cycles) *cycles = 0;
-      return set_error(AMRV_ENONPHYSICAL, "NaN in the multigrid right-hand side or initial guess");
+      if (cycles) *cycles = c;
+      return set_error(AMRV_ENONPHYSICAL, "NaN in the multigrid right-hand side, initial guess or residual");
     }
   while (!ok && c < max_cycles) {
     if (m->profile) MGCHK(hipEventRecord(m->e0, m->st));
-    if (m->cfg.use_graph) {
-      if (!m->gexec) {
-        hipGraph_t gr;
-        MGCHK(hipStreamBeginCapture(m->st, hipStreamCaptureModeThreadLocal));
-        enqueue_vcycle(m);
-        MGCHK(hipStreamEndCapture(m->st, &gr));
-        hipError_t e = hipGraphInstantiate(&m->gexec, gr, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(gr);
-        MGCHK(e);
-      }
-      MGCHK(hipGraphLaunch(m->gexec, m->st));
-    } else {
-      enqueue_vcycle(m);
-      MGCHK(hipGetLastError());
-    }
+    if (int rc = launch_cycle(m)) return rc;
     if (m->profile) MGCHK(hipEventRecord(m->e1, m->st));
     MGCHK(hipStreamSynchronize(m->st));
     if (m->profile) {
@@ -1119,7 +1132,7 @@ int amrv_mg_solve(amrv_mg* m, const double* f, double* phi, const double* lambda
     MGCHK(hipMemcpyAsync(m->g.phi[i][0], phi + (size_t)i * m->g.cells[0], bytes, hipMemcpyDeviceToDevice, m->st));
   }
   int c = 0;
-  const int rc = run_cycles(m, tol, max_cycles, &c, res_max, f_max);
+  const int rc = run_cycles(m, tol, max_cycles, 0, &c, res_max, f_max);
   if (cycles) *cycles = c;
   for (int i = 0; i < m->g.nf; i++)
     MGCHK(hipMemcpyAsync(phi + (size_t)i * m->g.cells[0], m->g.phi[i][0], bytes, hipMemcpyDeviceToDevice, m->st));
@@ -1154,7 +1167,7 @@ int amrv_mg_divb_project(amrv_mg* m, double* bx, double* by, double* bz, double 
   hipLaunchKernelGGL(d2 ? k_mg_divb<2> : k_mg_divb<3>, dim3(nb), dim3(256), 0, m->st, g, bx, by, b2, c);
   MGCHK(hipGetLastError());
   int cyc = 0;
-  const int rc = run_cycles(m, tol, max_cycles, &cyc, nullptr, nullptr);
+  const int rc = run_cycles(m, tol, max_cycles, 0, &cyc, nullptr, nullptr);
   if (cycles) *cycles = cyc;
   if (rc) return rc;
   hipLaunchKernelGGL(d2 ? k_mg_gradsub<2> : k_mg_gradsub<3>, dim3(nb), dim3(256), 0, m->st, g, bx, by, b2, c);
@@ -1213,7 +1226,9 @@ int amrv_rd_step(amrv_mg* m, const amrv_rd_params* p, int32_t scheme, double dt,
                          m->tmp[0], m->tmp[1], dt);
     MGCHK(hipGetLastError());
     int c = 0;
-    const int rc = run_cycles(m, tol, max_cycles, &c, res_max, nullptr);
+    // the previous solve's cycle count, less one, runs before the first check
+    const int rc = run_cycles(m, tol, max_cycles, m->last_cycles - 1, &c, res_max, nullptr);
+    m->last_cycles = c;
     total += c;
     if (rc) {
       if (cycles_total) *cycles_total = total;
