@@ -200,7 +200,7 @@ def rd_main(args, log):
         "data": "synthetic",
         "config": {"workload": r["workload"], "cells": r["cells"], "dt": r["dt"], "tol": r["tol"],
                    "model": "schnakenberg", "bc": "neumann", "smoother": "tiled 2D" if nd == 2 else "per-colour",
-                   "cycle": "V(2,2)"},
+                   "cycle": "V(2,2)", "launch": "direct (no graph)"},
         "roofline": r["roofline"],
         "cpu_baseline": r.get("cpu_baseline"),
         "parity": r.get("parity"),

@@ -25,7 +25,8 @@
 // norms).  Fields (u and v of the reaction-diffusion steps) are solved by the
 // same launches (grid y = field).  These grids are small (a 256^2 field is
 // 512 KiB), so the cycle is bound by launch and synchronisation latency, not
-// by HBM: it is replayed from a HIP graph.
+// by HBM: a solve enqueues several cycles before its first host check, and
+// each cycle can be replayed from a captured HIP graph (use_graph).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
