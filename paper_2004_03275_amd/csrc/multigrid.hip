@@ -787,7 +787,6 @@ struct amrv_mg {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   double prof_ms = 0.0;
   int64_t prof_cycles = 0;
-  double par_lam[NFMAX] = {-1.0, -1.0};
   int last_cycles = 0;  // V-cycles of the last reaction-diffusion solve
 };
 
@@ -926,7 +925,6 @@ int set_params(amrv_mg* m, const double* lam) {
     P.v[PAR_LAM + f] = lam[f];
     for (int l = 0; l < m->g.nlev; l++)
       P.v[PAR_IDIAG + f * MG_MAXL + l] = 1.0 / (2.0 * m->g.nd * P.v[PAR_IH2 + l] + lam[f]);
-    m->par_lam[f] = lam[f];
   }
   hipLaunchKernelGGL(k_mg_set, dim3(1), dim3(64), 0, m->st, m->par, P);
   MGCHK(hipGetLastError());
