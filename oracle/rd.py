@@ -17,7 +17,10 @@ added in the order x, y, z, with 1/h^2 formed as (n/L) * (n/L).
 
 Helmholtz problem (Eq. diff-helmholtz): lap(phi) - lambda phi = f, lambda > 0;
 Poisson (lambda = 0) for the divergence control of the MHD runs (Sec. 2.4),
-whose solution is fixed up to a constant (the zero-mean one here).
+whose solution is fixed up to a constant (the zero-mean one here).  With a
+variable coefficient (Sec. 2.3): div(eps grad phi) - lambda phi = f, eps > 0
+per cell, face coefficients the arithmetic mean of the two cells, solved by
+a sparse direct solve; still an M-matrix with row sums lambda.
 This module solves it exactly (to rounding): the operator is diagonalised by
 the discrete Fourier transform (periodic) or the type-II cosine transform
 (Neumann), with eigenvalue sum_d (2 cos(theta_d) - 2) / h^2 - lambda,
@@ -112,6 +115,64 @@ def helmholtz_solve(f, lam: float, length: float, bc: int):
     if bc == PERIODIC:
         return np.real(np.fft.ifftn(np.fft.fftn(f) / mu))
     return sfft.idctn(sfft.dctn(f, type=2, norm="ortho") / mu, type=2, norm="ortho")
+
+
+def _face_sums(phi, eps, length: float, bc: int):
+    """sum_d (e+ (phi+ - phi) - e- (phi - phi-)) / h^2 with face coefficients
+    e+- the arithmetic means of the two cells' eps (a face beyond a Neumann
+    boundary mirrors the cell, so its difference vanishes)."""
+    nd = phi.ndim
+    ih2 = inv_h2(phi.shape[-1], length)
+    out = None
+    for d in range(nd):
+        ax = nd - 1 - d
+        ep = 0.5 * (eps + _shift(eps, ax, +1, bc))
+        em = 0.5 * (eps + _shift(eps, ax, -1, bc))
+        term = (ep * (_shift(phi, ax, +1, bc) - phi) - em * (phi - _shift(phi, ax, -1, bc))) * ih2
+        out = term if out is None else out + term
+    return out
+
+
+def helmholtz_var_apply(phi, eps, lam: float, length: float, bc: int):
+    """div(eps grad phi) - lambda phi, the variable-coefficient Helmholtz
+    operator of the multigrid (Sec. 2.3)."""
+    return _face_sums(phi, eps, length, bc) - lam * phi
+
+
+def helmholtz_var_matrix(eps, lam: float, length: float, bc: int):
+    """The operator as a sparse matrix on the flattened [z][y][x] grid,
+    assembled column by column from unit vectors' stencil neighbourhoods."""
+    import scipy.sparse as sp
+
+    shape = eps.shape
+    N = eps.size
+    nd = eps.ndim
+    n = shape[-1]
+    ih2 = inv_h2(n, length)
+    idx = np.arange(N).reshape(shape)
+    rows, cols, vals = [idx.ravel()], [idx.ravel()], [-lam * np.ones(N)]
+    for d in range(nd):
+        ax = nd - 1 - d
+        for step in (+1, -1):
+            nb_idx = _shift(idx, ax, step, bc)
+            e = 0.5 * (eps + _shift(eps, ax, step, bc)) * ih2
+            same = nb_idx == idx  # a Neumann face: the mirrored difference is zero
+            e = np.where(same, 0.0, e)
+            rows += [idx.ravel(), idx.ravel()]
+            cols += [nb_idx.ravel(), idx.ravel()]
+            vals += [e.ravel(), -e.ravel()]
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, N))
+
+
+def helmholtz_var_solve(f, eps, lam: float, length: float, bc: int):
+    """Exact (sparse direct) solution of div(eps grad phi) - lambda phi = f,
+    lambda > 0, eps > 0."""
+    import scipy.sparse.linalg as spl
+
+    if not lam > 0.0:
+        raise ValueError("lambda must be positive")
+    A = helmholtz_var_matrix(eps, lam, length, bc).tocsc()
+    return spl.spsolve(A, f.ravel()).reshape(f.shape)
 
 
 def poisson_solve(f, length: float, bc: int):

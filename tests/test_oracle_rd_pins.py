@@ -307,3 +307,60 @@ def test_projection_removes_a_smooth_gradient_at_second_order():
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(orders > 1.9), (errs, orders)
     assert max(ratios) < 1e-2, ratios
+
+
+# -- variable coefficient (Sec. 2.3) ------------------------------------------
+
+def test_variable_coefficient_reduces_to_the_constant_one():
+    rng = np.random.default_rng(11)
+    for nd, n, bc in [(2, 16, R.PERIODIC), (2, 16, R.NEUMANN), (3, 8, R.NEUMANN)]:
+        f = rng.standard_normal((n,) * nd)
+        eps = np.ones_like(f)
+        a = R.helmholtz_var_solve(f, eps, 3.0, 1.0, bc)
+        b = R.helmholtz_solve(f, 3.0, 1.0, bc)
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
+        phi = rng.standard_normal(f.shape)
+        assert np.abs(R.helmholtz_var_apply(phi, eps, 3.0, 1.0, bc) - R.helmholtz_apply(phi, 3.0, 1.0, bc)).max() \
+            < 1e-9
+
+
+@pytest.mark.parametrize("bc", [R.PERIODIC, R.NEUMANN])
+def test_variable_coefficient_matrix_properties(bc):
+    """Symmetric, an M-matrix (off-diagonals >= 0 in lap - lambda form, i.e.
+    lambda I - A has non-positive off-diagonals) with row sums -lambda, so
+    the residual bound |e| <= |r| / lambda holds as in the constant case;
+    and the matrix applied to a vector equals the stencil code."""
+    rng = np.random.default_rng(12)
+    n = 8
+    eps = 0.2 + rng.random((n, n))
+    A = R.helmholtz_var_matrix(eps, 2.5, 1.0, bc).toarray()
+    assert np.abs(A - A.T).max() < 1e-12 * np.abs(A).max()
+    off = A - np.diag(np.diag(A))
+    assert off.min() >= 0.0
+    assert np.abs(A.sum(axis=1) + 2.5).max() < 1e-9 * np.abs(A).max()
+    phi = rng.standard_normal((n, n))
+    assert np.abs(A @ phi.ravel() - R.helmholtz_var_apply(phi, eps, 2.5, 1.0, bc).ravel()).max() \
+        < 1e-12 * np.abs(A).max()
+
+
+def test_variable_coefficient_manufactured_second_order():
+    """phi = cos(pi x) cos(pi y) (zero normal derivative on the unit square),
+    eps = 1 + 0.5 sin(pi x) sin(pi y)... with f = div(eps grad phi) - lambda phi
+    computed from the continuum formulas."""
+    lam = 5.0
+    errs = []
+    for n in (32, 64, 128):
+        x, y = W.rd_cell_centres(2, n, 1.0)
+        c, s_ = np.cos, np.sin
+        phi = c(np.pi * x) * c(np.pi * y)
+        eps = 1.0 + 0.5 * c(np.pi * x) ** 2 * c(np.pi * y) ** 2
+        px = -np.pi * s_(np.pi * x) * c(np.pi * y)
+        py = -np.pi * c(np.pi * x) * s_(np.pi * y)
+        ex = 0.5 * 2 * c(np.pi * x) * (-np.pi * s_(np.pi * x)) * c(np.pi * y) ** 2
+        ey = 0.5 * 2 * c(np.pi * y) * (-np.pi * s_(np.pi * y)) * c(np.pi * x) ** 2
+        lap = -2 * np.pi ** 2 * phi
+        f = ex * px + ey * py + eps * lap - lam * phi
+        got = R.helmholtz_var_solve(f, eps, lam, 1.0, R.NEUMANN)
+        errs.append(np.abs(got - phi).max())
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders > 1.8), (errs, orders)
