@@ -115,6 +115,17 @@ int amrv_mg_destroy(amrv_mg* m);
 int amrv_mg_solve(amrv_mg* m, const double* f, double* phi, const double* lambda, double tol, int32_t max_cycles,
                   int32_t* cycles, double* res_max, double* f_max);
 
+/* Variable coefficient (Sec. 2.3: Helmholtz problems with variable
+ * coefficients): with eps != NULL (device, n^ndim doubles, each > 0; copied)
+ * later amrv_mg_solve calls solve div(eps grad phi) - lambda phi = f, the
+ * coefficient of a face the arithmetic mean of its two cells (none across a
+ * Neumann face), coarse levels carrying the mean of their children's eps, the
+ * 2-per-side grid solved by elimination; lambda must be > 0 (the operator
+ * stays an M-matrix with row sums lambda, so the residual bound above
+ * holds).  These solves use the per-colour launches.  eps = NULL returns to
+ * eps = 1.  amrv_rd_step and amrv_mg_divb_project need eps = 1. */
+int amrv_mg_set_coefficient(amrv_mg* m, const double* eps);
+
 /* Divergence control of the MHD runs (Sec. 2.4) on one uniform periodic
  * grid: solves lap(phi) = div B* (central differences (w(+1) - w(-1)) n/(2L),
  * directions added x, y, z) to tol, then sets B = B* - grad phi with the

@@ -138,6 +138,7 @@ SIGNATURES = {
                       ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), P], ctypes.c_int),
     "amrv_mg_divb_project": ([P, P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "amrv_mg_set_coefficient": ([P, P], ctypes.c_int),
     "amrv_mg_profile": ([P, ctypes.c_int32], ctypes.c_int),
     "amrv_mg_profile_read": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "amrv_last_error": ([], ctypes.c_char_p),

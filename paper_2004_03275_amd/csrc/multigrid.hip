@@ -55,6 +55,8 @@ struct MgDev {
   int lg[MG_MAXL];              // log2(n[l])
   int cells[MG_MAXL];
   int loff[MG_MAXL];            // LDS offset (doubles) of the tail's phi_l; f_l follows it
+  int loffv[MG_MAXL];           // the same with a coefficient: phi_l, f_l, eps_l
+  const double* eps[MG_MAXL];   // cell coefficient per level (variable-coefficient solves)
   double* phi[NFMAX][MG_MAXL];
   double* f[NFMAX][MG_MAXL];
   double* phi2[NFMAX][MG_MAXL]; // 2D levels above the tail: the tiled launches'
@@ -142,6 +144,67 @@ __device__ __forceinline__ double restrict_cell(const double* p, const double* r
   return s * (ND == 3 ? 0.125 : 0.25);
 }
 
+// ---- variable coefficient: div(eps grad phi) - lambda phi, face coefficient
+// the mean of the two cells; a neighbour that is the cell itself (a Neumann
+// face) contributes no flux -----------------------------------------------
+
+template <int ND>
+__device__ __forceinline__ void nbr_list(int x, int y, int z, int n, int bc, int* j) {
+  const int row = (z * n + y) * n;
+  j[0] = row + im(x, n, bc);
+  j[1] = row + ip(x, n, bc);
+  j[2] = (z * n + im(y, n, bc)) * n + x;
+  j[3] = (z * n + ip(y, n, bc)) * n + x;
+  if constexpr (ND == 3) {
+    j[4] = (im(z, n, bc) * n + y) * n + x;
+    j[5] = (ip(z, n, bc) * n + y) * n + x;
+  }
+}
+
+template <int ND>
+__device__ __forceinline__ void gs_cell_var(double* p, const double* rhs, const double* e, int x, int y, int z, int n,
+                                            int bc, double ih2, double lam) {
+  const int i = (z * n + y) * n + x;
+  int j[2 * ND];
+  nbr_list<ND>(x, y, z, n, bc, j);
+  double num = 0.0, den = 0.0;
+#pragma unroll
+  for (int k = 0; k < 2 * ND; k++)
+    if (j[k] != i) {
+      const double ef = 0.5 * (e[i] + e[j[k]]);
+      num += ef * p[j[k]];
+      den += ef;
+    }
+  p[i] = (num * ih2 - rhs[i]) / (den * ih2 + lam);
+}
+
+template <int ND>
+__device__ __forceinline__ double resid_var(const double* p, const double* rhs, const double* e, int x, int y, int z,
+                                            int n, int bc, double ih2, double lam) {
+  const int i = (z * n + y) * n + x;
+  int j[2 * ND];
+  nbr_list<ND>(x, y, z, n, bc, j);
+  double a = 0.0;
+#pragma unroll
+  for (int k = 0; k < 2 * ND; k++)
+    if (j[k] != i) a += 0.5 * (e[i] + e[j[k]]) * (p[j[k]] - p[i]);
+  return rhs[i] - (a * ih2 - lam * p[i]);
+}
+
+template <int ND>
+__device__ __forceinline__ double restrict_cell_var(const double* p, const double* rhs, const double* e, int xc, int yc,
+                                                    int zc, int n, int bc, double ih2, double lam) {
+  double s = 0.0;
+#pragma unroll
+  for (int dz = 0; dz < (ND == 3 ? 2 : 1); dz++)
+#pragma unroll
+    for (int dy = 0; dy < 2; dy++)
+#pragma unroll
+      for (int dx = 0; dx < 2; dx++)
+        s += resid_var<ND>(p, rhs, e, 2 * xc + dx, 2 * yc + dy, 2 * zc + dz, n, bc, ih2, lam);
+  return s * (ND == 3 ? 0.125 : 0.25);
+}
+
 // bi/trilinear interpolation of the coarse correction at fine cell (x, y, z):
 // weight 3/4 on the parent and 1/4 on the parent's neighbour on the side of
 // the fine cell, per direction (boundary rule as for the stencil)
@@ -169,7 +232,7 @@ __device__ __forceinline__ double par_lam(const MgDev& g, int f) { return g.par[
 
 // ---- level kernels (HBM levels above the tail) ---------------------------
 
-template <int ND>
+template <int ND, bool VAR>
 __global__ void __launch_bounds__(256) k_mg_smooth(MgDev g, int l, int c) {
   const int f = blockIdx.y;
   const int n = g.n[l];
@@ -177,18 +240,42 @@ __global__ void __launch_bounds__(256) k_mg_smooth(MgDev g, int l, int c) {
   if (t >= (g.cells[l] >> 1)) return;
   int x, y, z;
   colour_cell<ND>(t, n, g.lg[l], c, x, y, z);
-  gs_cell<ND>(g.phi[f][l], g.f[f][l], x, y, z, n, g.bc, par_ih2(g, l), par_idiag(g, f, l));
+  if constexpr (VAR)
+    gs_cell_var<ND>(g.phi[f][l], g.f[f][l], g.eps[l], x, y, z, n, g.bc, par_ih2(g, l), par_lam(g, f));
+  else
+    gs_cell<ND>(g.phi[f][l], g.f[f][l], x, y, z, n, g.bc, par_ih2(g, l), par_idiag(g, f, l));
 }
 
-template <int ND>
+template <int ND, bool VAR>
 __global__ void __launch_bounds__(256) k_mg_restrict(MgDev g, int l) {
   const int f = blockIdx.y;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.cells[l + 1]) return;
   int x, y, z;
   decode<ND>(t, g.n[l + 1], g.lg[l + 1], x, y, z);
-  g.f[f][l + 1][t] = restrict_cell<ND>(g.phi[f][l], g.f[f][l], x, y, z, g.n[l], g.bc, par_ih2(g, l), par_lam(g, f));
+  if constexpr (VAR)
+    g.f[f][l + 1][t] = restrict_cell_var<ND>(g.phi[f][l], g.f[f][l], g.eps[l], x, y, z, g.n[l], g.bc, par_ih2(g, l),
+                                             par_lam(g, f));
+  else
+    g.f[f][l + 1][t] =
+        restrict_cell<ND>(g.phi[f][l], g.f[f][l], x, y, z, g.n[l], g.bc, par_ih2(g, l), par_lam(g, f));
   g.phi[f][l + 1][t] = 0.0;
+}
+
+// coefficient of level l + 1: the mean of the 2^d children
+template <int ND>
+__global__ void __launch_bounds__(256) k_mg_eps_restrict(MgDev g, int l, double* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.cells[l + 1]) return;
+  int x, y, z;
+  decode<ND>(t, g.n[l + 1], g.lg[l + 1], x, y, z);
+  const int n = g.n[l];
+  const double* e = g.eps[l];
+  double s = 0.0;
+  for (int dz = 0; dz < (ND == 3 ? 2 : 1); dz++)
+    for (int dy = 0; dy < 2; dy++)
+      for (int dx = 0; dx < 2; dx++) s += e[((2 * z + dz) * n + 2 * y + dy) * n + 2 * x + dx];
+  out[t] = s * (ND == 3 ? 0.125 : 0.25);
 }
 
 template <int ND>
@@ -236,14 +323,18 @@ __device__ void fold_norms(const MgDev& g, int f, unsigned long long a, unsigned
 }
 
 // max |residual| (and with with_f, max |f|) of level 0 per field
-template <int ND>
+template <int ND, bool VAR>
 __global__ void __launch_bounds__(256) k_mg_resnorm(MgDev g, int with_f) {
   const int f = blockIdx.y;
   unsigned long long br = 0, bf = 0;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.cells[0]; t += gridDim.x * blockDim.x) {
     int x, y, z;
     decode<ND>(t, g.n[0], g.lg[0], x, y, z);
-    const double r = resid<ND>(g.phi[f][0], g.f[f][0], x, y, z, g.n[0], g.bc, par_ih2(g, 0), par_lam(g, f));
+    double r;
+    if constexpr (VAR)
+      r = resid_var<ND>(g.phi[f][0], g.f[f][0], g.eps[0], x, y, z, g.n[0], g.bc, par_ih2(g, 0), par_lam(g, f));
+    else
+      r = resid<ND>(g.phi[f][0], g.f[f][0], x, y, z, g.n[0], g.bc, par_ih2(g, 0), par_lam(g, f));
     const unsigned long long a = (unsigned long long)__double_as_longlong(fabs(r));
     const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(g.f[f][0][t]));
     br = a > br ? a : br;
@@ -580,6 +671,58 @@ __device__ void coarse_exact(const MgDev& g, double* P, const double* F, double 
 }
 
 template <int ND>
+__device__ void tail_sweeps_var(const MgDev& g, double* P, const double* F, const double* E, int l, int sweeps,
+                                double ih2, double lam) {
+  const int n = g.n[l], lg = g.lg[l], half = g.cells[l] >> 1;
+  for (int s = 0; s < sweeps; s++)
+    for (int c = 0; c < 2; c++) {
+      for (int t = threadIdx.x; t < half; t += blockDim.x) {
+        int x, y, z;
+        colour_cell<ND>(t, n, lg, c, x, y, z);
+        gs_cell_var<ND>(P, F, E, x, y, z, n, g.bc, ih2, lam);
+      }
+      __syncthreads();
+    }
+}
+
+// exact solve on the 2-per-side grid with a coefficient: the 2^d x 2^d
+// system of the operator, strictly diagonally dominant (lambda > 0), by
+// Gaussian elimination without pivoting in one thread
+template <int ND>
+__device__ void coarse_exact_var(const MgDev& g, double* P, const double* F, const double* E, double ih2, double lam) {
+  constexpr int C = 1 << ND;
+  if (threadIdx.x == 0) {
+    double A[C][C + 1];
+    for (int r = 0; r < C; r++) {
+      for (int c = 0; c <= C; c++) A[r][c] = 0.0;
+      const int x = r & 1, y = (r >> 1) & 1, z = ND == 3 ? (r >> 2) & 1 : 0;
+      int j[2 * ND];
+      nbr_list<ND>(x, y, z, 2, g.bc, j);
+      double diag = -lam;
+      for (int k = 0; k < 2 * ND; k++)
+        if (j[k] != r) {
+          const double ef = 0.5 * (E[r] + E[j[k]]) * ih2;
+          A[r][j[k]] += ef;
+          diag -= ef;
+        }
+      A[r][r] += diag;
+      A[r][C] = F[r];
+    }
+    for (int k = 0; k < C; k++)
+      for (int r = k + 1; r < C; r++) {
+        const double m = A[r][k] / A[k][k];
+        for (int c = k; c <= C; c++) A[r][c] -= m * A[k][c];
+      }
+    for (int r = C - 1; r >= 0; r--) {
+      double s = A[r][C];
+      for (int c = r + 1; c < C; c++) s -= A[r][c] * P[c];
+      P[r] = s / A[r][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int ND, bool VAR>
 __global__ void __launch_bounds__(TAIL_THREADS) k_mg_tail(MgDev g, int top, int pre, int post) {
   extern __shared__ double lds[];
   __shared__ double s_ih2[MG_MAXL], s_idg[MG_MAXL];
@@ -589,26 +732,39 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_mg_tail(MgDev g, int top, int 
     s_idg[threadIdx.x] = par_idiag(g, f, threadIdx.x);
   }
   const double lam = par_lam(g, f);
-  auto P = [&](int l) { return lds + g.loff[l]; };
-  auto F = [&](int l) { return lds + g.loff[l] + g.cells[l]; };
+  auto P = [&](int l) { return lds + (VAR ? g.loffv[l] : g.loff[l]); };
+  auto F = [&](int l) { return P(l) + g.cells[l]; };
+  auto E = [&](int l) { return P(l) + 2 * g.cells[l]; };  // with a coefficient only
+  const int last = g.nlev - 1;
   for (int i = threadIdx.x; i < g.cells[top]; i += blockDim.x) {
     P(top)[i] = g.phi[f][top][i];
     F(top)[i] = g.f[f][top][i];
   }
+  if constexpr (VAR)
+    for (int l = top; l <= last; l++)
+      for (int i = threadIdx.x; i < g.cells[l]; i += blockDim.x) E(l)[i] = g.eps[l][i];
   __syncthreads();
-  const int last = g.nlev - 1;
   for (int l = top; l < last; l++) {
-    tail_sweeps<ND>(g, P(l), F(l), l, pre, s_ih2[l], s_idg[l]);
+    if constexpr (VAR)
+      tail_sweeps_var<ND>(g, P(l), F(l), E(l), l, pre, s_ih2[l], lam);
+    else
+      tail_sweeps<ND>(g, P(l), F(l), l, pre, s_ih2[l], s_idg[l]);
     const double ih2 = s_ih2[l];
     for (int t = threadIdx.x; t < g.cells[l + 1]; t += blockDim.x) {
       int x, y, z;
       decode<ND>(t, g.n[l + 1], g.lg[l + 1], x, y, z);
-      F(l + 1)[t] = restrict_cell<ND>(P(l), F(l), x, y, z, g.n[l], g.bc, ih2, lam);
+      if constexpr (VAR)
+        F(l + 1)[t] = restrict_cell_var<ND>(P(l), F(l), E(l), x, y, z, g.n[l], g.bc, ih2, lam);
+      else
+        F(l + 1)[t] = restrict_cell<ND>(P(l), F(l), x, y, z, g.n[l], g.bc, ih2, lam);
       P(l + 1)[t] = 0.0;
     }
     __syncthreads();
   }
-  coarse_exact<ND>(g, P(last), F(last), s_ih2[last], lam);
+  if constexpr (VAR)
+    coarse_exact_var<ND>(g, P(last), F(last), E(last), s_ih2[last], lam);
+  else
+    coarse_exact<ND>(g, P(last), F(last), s_ih2[last], lam);
   for (int l = last - 1; l >= top; l--) {
     for (int t = threadIdx.x; t < g.cells[l]; t += blockDim.x) {
       int x, y, z;
@@ -616,7 +772,10 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_mg_tail(MgDev g, int top, int 
       P(l)[t] += prolong_cell<ND>(P(l + 1), x, y, z, g.n[l + 1], g.bc);
     }
     __syncthreads();
-    tail_sweeps<ND>(g, P(l), F(l), l, post, s_ih2[l], s_idg[l]);
+    if constexpr (VAR)
+      tail_sweeps_var<ND>(g, P(l), F(l), E(l), l, post, s_ih2[l], lam);
+    else
+      tail_sweeps<ND>(g, P(l), F(l), l, post, s_ih2[l], s_idg[l]);
   }
   for (int i = threadIdx.x; i < g.cells[top]; i += blockDim.x) g.phi[f][top][i] = P(top)[i];
 }
@@ -788,6 +947,9 @@ struct amrv_mg {
   double prof_ms = 0.0;
   int64_t prof_cycles = 0;
   int last_cycles = 0;  // V-cycles of the last reaction-diffusion solve
+  bool var = false;     // a cell coefficient is set (div(eps grad phi) - lambda phi)
+  size_t tail_lds_var = 0;
+  double* eps[MG_MAXL] = {};
 };
 
 namespace {
@@ -826,8 +988,8 @@ int validate(const amrv_mg_config* c) {
 
 struct MgLayout {
   int nlev = 0;
-  size_t off_phi[NFMAX][MG_MAXL]{}, off_f[NFMAX][MG_MAXL]{}, off_phi2[NFMAX][MG_MAXL]{}, off_tmp[4]{}, off_par = 0,
-      total = 0;
+  size_t off_phi[NFMAX][MG_MAXL]{}, off_f[NFMAX][MG_MAXL]{}, off_phi2[NFMAX][MG_MAXL]{}, off_eps[MG_MAXL]{},
+      off_tmp[4]{}, off_par = 0, total = 0;
 };
 
 MgLayout layout(const amrv_mg_config* c) {
@@ -849,6 +1011,12 @@ MgLayout layout(const amrv_mg_config* c) {
         o += up(cells * 8);
       }
     }
+  for (int l = 0; l < lv; l++) {
+    size_t cells = 1;
+    for (int d = 0; d < c->ndim; d++) cells *= (size_t)(c->n >> l);
+    L.off_eps[l] = o;
+    o += up(cells * 8);
+  }
   size_t c0 = 1;
   for (int d = 0; d < c->ndim; d++) c0 *= (size_t)c->n;
   for (int i = 0; i < 4; i++) {
@@ -862,7 +1030,7 @@ MgLayout layout(const amrv_mg_config* c) {
 }
 
 bool tiled(const amrv_mg* m) {
-  return m->g.nd == 2 && m->cfg.smoother == AMRV_MG_TILED && m->tail > 0 &&
+  return !m->var && m->g.nd == 2 && m->cfg.smoother == AMRV_MG_TILED && m->tail > 0 &&
          2 * std::max(m->cfg.pre_sweeps, m->cfg.post_sweeps) + 1 <= HMAX;
 }
 
@@ -871,7 +1039,10 @@ bool tiled(const amrv_mg* m) {
 template <int ND>
 void enqueue_norms_nd(amrv_mg* m, int with_f) {
   const MgDev& g = m->g;
-  hipLaunchKernelGGL(k_mg_resnorm<ND>, dim3(m->nb_init, g.nf), dim3(256), 0, m->st, g, with_f);
+  if (m->var)
+    hipLaunchKernelGGL((k_mg_resnorm<ND, true>), dim3(m->nb_init, g.nf), dim3(256), 0, m->st, g, with_f);
+  else
+    hipLaunchKernelGGL((k_mg_resnorm<ND, false>), dim3(m->nb_init, g.nf), dim3(256), 0, m->st, g, with_f);
 }
 
 // one V-cycle, ending with the residual norms of its result
@@ -887,11 +1058,25 @@ void enqueue_vcycle_nd(amrv_mg* m) {
     for (int l = 0; l < m->tail; l++) {
       for (int s = 0; s < pre; s++)
         for (int c = 0; c < 2; c++)
-          hipLaunchKernelGGL(k_mg_smooth<ND>, dim3(blocks_of(g.cells[l] >> 1), nf), dim3(256), 0, m->st, g, l, c);
-      hipLaunchKernelGGL(k_mg_restrict<ND>, dim3(blocks_of(g.cells[l + 1]), nf), dim3(256), 0, m->st, g, l);
+          if (m->var)
+            hipLaunchKernelGGL((k_mg_smooth<ND, true>), dim3(blocks_of(g.cells[l] >> 1), nf), dim3(256), 0, m->st, g,
+                               l, c);
+          else
+            hipLaunchKernelGGL((k_mg_smooth<ND, false>), dim3(blocks_of(g.cells[l] >> 1), nf), dim3(256), 0, m->st,
+                               g, l, c);
+      if (m->var)
+        hipLaunchKernelGGL((k_mg_restrict<ND, true>), dim3(blocks_of(g.cells[l + 1]), nf), dim3(256), 0, m->st, g, l);
+      else
+        hipLaunchKernelGGL((k_mg_restrict<ND, false>), dim3(blocks_of(g.cells[l + 1]), nf), dim3(256), 0, m->st, g,
+                           l);
     }
   }
-  hipLaunchKernelGGL(k_mg_tail<ND>, dim3(nf), dim3(TAIL_THREADS), m->tail_lds, m->st, g, m->tail, pre, post);
+  if (m->var)
+    hipLaunchKernelGGL((k_mg_tail<ND, true>), dim3(nf), dim3(TAIL_THREADS), m->tail_lds_var, m->st, g, m->tail, pre,
+                       post);
+  else
+    hipLaunchKernelGGL((k_mg_tail<ND, false>), dim3(nf), dim3(TAIL_THREADS), m->tail_lds, m->st, g, m->tail, pre,
+                       post);
   if (tiled(m)) {
     for (int l = m->tail - 1; l >= 0; l--)
       hipLaunchKernelGGL(k_mg_up2d, dim3((g.n[l] / TS) * (g.n[l] / TS), nf), dim3(256), 0, m->st, g, l, post,
@@ -902,7 +1087,12 @@ void enqueue_vcycle_nd(amrv_mg* m) {
     hipLaunchKernelGGL(k_mg_prolong<ND>, dim3(blocks_of(g.cells[l]), nf), dim3(256), 0, m->st, g, l);
     for (int s = 0; s < post; s++)
       for (int c = 0; c < 2; c++)
-        hipLaunchKernelGGL(k_mg_smooth<ND>, dim3(blocks_of(g.cells[l] >> 1), nf), dim3(256), 0, m->st, g, l, c);
+        if (m->var)
+          hipLaunchKernelGGL((k_mg_smooth<ND, true>), dim3(blocks_of(g.cells[l] >> 1), nf), dim3(256), 0, m->st, g,
+                             l, c);
+        else
+          hipLaunchKernelGGL((k_mg_smooth<ND, false>), dim3(blocks_of(g.cells[l] >> 1), nf), dim3(256), 0, m->st, g,
+                             l, c);
   }
   enqueue_norms_nd<ND>(m, 0);
 }
@@ -1068,6 +1258,10 @@ int amrv_mg_create(const amrv_mg_config* cfg, void* workspace, size_t bytes, voi
     }
   }
   for (int i = 0; i < 4; i++) m->tmp[i] = reinterpret_cast<double*>(base + L.off_tmp[i]);
+  for (int l = 0; l < L.nlev; l++) {
+    m->eps[l] = reinterpret_cast<double*>(base + L.off_eps[l]);
+    g.eps[l] = m->eps[l];
+  }
   m->par = reinterpret_cast<double*>(base + L.off_par);
   g.par = m->par;
   // the tail: the first level of at most TAIL_CELLS cells, and every level below
@@ -1080,11 +1274,22 @@ int amrv_mg_create(const amrv_mg_config* cfg, void* workspace, size_t bytes, voi
     off += 2 * g.cells[l];
   }
   m->tail_lds = (size_t)off * sizeof(double);
+  int offv = 0;
+  for (int l = tail; l < L.nlev; l++) {
+    g.loffv[l] = offv;
+    offv += 3 * g.cells[l];
+  }
+  m->tail_lds_var = (size_t)offv * sizeof(double);
   hipError_t e = cfg->ndim == 2
-                     ? hipFuncSetAttribute(reinterpret_cast<const void*>(k_mg_tail<2>),
+                     ? hipFuncSetAttribute(reinterpret_cast<const void*>(k_mg_tail<2, false>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->tail_lds)
-                     : hipFuncSetAttribute(reinterpret_cast<const void*>(k_mg_tail<3>),
+                     : hipFuncSetAttribute(reinterpret_cast<const void*>(k_mg_tail<3, false>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->tail_lds);
+  if (e == hipSuccess)
+    e = cfg->ndim == 2 ? hipFuncSetAttribute(reinterpret_cast<const void*>(k_mg_tail<2, true>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->tail_lds_var)
+                       : hipFuncSetAttribute(reinterpret_cast<const void*>(k_mg_tail<3, true>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->tail_lds_var);
   m->nb_init = std::min(blocks_of(g.cells[0]), 256);
   m->nb_cycle = tiled(m) ? (g.n[0] / TS) * (g.n[0] / TS) : m->nb_init;
   g.maxb = std::max(m->nb_init, m->nb_cycle);
@@ -1124,6 +1329,8 @@ int amrv_mg_solve(amrv_mg* m, const double* f, double* phi, const double* lambda
   for (int i = 0; i < m->g.nf; i++)
     if (!(lambda[i] >= 0.0) || !std::isfinite(lambda[i]))
       return set_error(AMRV_EINVAL, "lambda must be non-negative and finite");
+  for (int i = 0; i < m->g.nf; i++)
+    if (m->var && !(lambda[i] > 0.0)) return set_error(AMRV_EINVAL, "a solve with a coefficient needs lambda > 0");
   if (int rc = set_params(m, lambda)) return rc;
   const size_t bytes = (size_t)m->g.cells[0] * sizeof(double);
   for (int i = 0; i < m->g.nf; i++) {
@@ -1143,6 +1350,7 @@ int amrv_mg_divb_project(amrv_mg* m, double* bx, double* by, double* bz, double 
                          int32_t* cycles, double* div_before, double* div_after) {
   if (!m || !bx || !by || (m->g.nd == 3 && !bz)) return set_error(AMRV_EINVAL, "null argument");
   if (m->g.nf != 1) return set_error(AMRV_EINVAL, "the projection needs a solver created with nfields = 1");
+  if (m->var) return set_error(AMRV_EINVAL, "the projection needs the constant coefficient");
   if (m->g.bc != AMRV_MG_PERIODIC) return set_error(AMRV_EINVAL, "the projection needs periodic faces");
   if (!(tol > 0.0) || max_cycles < 0) return set_error(AMRV_EINVAL, "bad tol or max_cycles");
   const double lam0 = 0.0;
@@ -1182,6 +1390,7 @@ int amrv_rd_step(amrv_mg* m, const amrv_rd_params* p, int32_t scheme, double dt,
   if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(AMRV_EINVAL, "dt must be positive and finite");
   if (nsteps < 0) return set_error(AMRV_EINVAL, "nsteps must be >= 0");
   if (scheme < AMRV_RD_EULER || scheme > AMRV_RD_IMEX) return set_error(AMRV_EINVAL, "unknown scheme");
+  if (m->var) return set_error(AMRV_EINVAL, "reaction-diffusion steps need the constant coefficient");
   const bool implicit = scheme == AMRV_RD_SPLIT || scheme == AMRV_RD_IMEX;
   if (implicit && m->g.nf != 2) return set_error(AMRV_EINVAL, "split and IMEX steps need a solver with nfields = 2");
   if (implicit && (!(tol > 0.0) || max_cycles < 0)) return set_error(AMRV_EINVAL, "bad tol or max_cycles");
@@ -1244,6 +1453,33 @@ int amrv_rd_step(amrv_mg* m, const amrv_rd_params* p, int32_t scheme, double dt,
   }
   if (cycles_total) *cycles_total = total;
   MGCHK(hipStreamSynchronize(m->st));
+  return 0;
+}
+
+int amrv_mg_set_coefficient(amrv_mg* m, const double* eps) {
+  if (!m) return set_error(AMRV_EINVAL, "null argument");
+  if (m->gexec) {  // the captured cycle belongs to the other operator
+    MGCHK(hipGraphExecDestroy(m->gexec));
+    m->gexec = nullptr;
+  }
+  if (!eps) {
+    m->var = false;
+    m->g.eps[0] = m->eps[0];
+    return 0;
+  }
+  const MgDev& g = m->g;
+  MGCHK(hipMemcpyAsync(m->eps[0], eps, (size_t)g.cells[0] * sizeof(double), hipMemcpyDeviceToDevice, m->st));
+  for (int l = 0; l + 1 < g.nlev; l++) {
+    if (g.nd == 2)
+      hipLaunchKernelGGL(k_mg_eps_restrict<2>, dim3(blocks_of(g.cells[l + 1])), dim3(256), 0, m->st, g, l,
+                         m->eps[l + 1]);
+    else
+      hipLaunchKernelGGL(k_mg_eps_restrict<3>, dim3(blocks_of(g.cells[l + 1])), dim3(256), 0, m->st, g, l,
+                         m->eps[l + 1]);
+    MGCHK(hipGetLastError());
+  }
+  MGCHK(hipStreamSynchronize(m->st));
+  m->var = true;
   return 0;
 }
 

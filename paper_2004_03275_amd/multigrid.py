@@ -101,6 +101,17 @@ class GpuMultigrid:
                                      int(max_cycles), ctypes.byref(cyc), res.ctypes.data))
         return cyc.value, res
 
+    def set_coefficient(self, eps: torch.Tensor | None):
+        """Solve div(eps grad phi) - lambda phi = f from now on (eps: float64
+        device tensor of the grid's size, > 0), or return to eps = 1 (None)."""
+        if eps is None:
+            N.check(N.lib().amrv_mg_set_coefficient(self._h, None))
+            self._eps = None
+            return
+        self._eps = self._dev(eps, self.n ** self.ndim)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        N.check(N.lib().amrv_mg_set_coefficient(self._h, ctypes.c_void_p(eps.data_ptr())))
+
     def divb_project(self, B, tol: float = 1e-10, max_cycles: int = 50):
         """The divergence control of Sec. 2.4 on the ndim device arrays B
         (updated in place).  Returns (cycles, max |div B| before, after)."""

@@ -367,3 +367,69 @@ def test_divb_projection_rejects_unsupported_setups():
             mg.divb_project(B)
         assert e.value.code == N.EINVAL
         mg.close()
+
+
+# -- variable coefficient (Sec. 2.3) ------------------------------------------
+
+def _eps_field(nd, n, kind):
+    xs = W.rd_cell_centres(nd, n, 1.0)
+    if kind == "smooth":
+        e = 1.0 + 0.5 * np.cos(2 * np.pi * xs[0]) * np.sin(2 * np.pi * xs[1])
+    else:  # a jump of 10x across x = 1/2
+        e = np.where(xs[0] < 0.5, 1.0, 10.0)
+    return np.ascontiguousarray(e)
+
+
+@pytest.mark.parametrize("nd,n", [(2, 64), (2, 256), (3, 16), (3, 32)])
+@pytest.mark.parametrize("bc", [R.PERIODIC, R.NEUMANN])
+@pytest.mark.parametrize("kind", ["smooth", "jump"])
+def test_variable_coefficient_solve_within_the_residual_bound(nd, n, bc, kind):
+    """div(eps grad phi) - lambda phi = f against the oracle's sparse direct
+    solve: still an M-matrix with row sums lambda, so max |phi - exact| <=
+    max |r| / lambda."""
+    torch, M = _mg()
+    lam = 20.0
+    f = _seeded((n,) * nd, 60 + n)
+    eps = _eps_field(nd, n, kind)
+    exact = R.helmholtz_var_solve(f, eps, lam, 1.0, bc)
+    mg = M.GpuMultigrid(nd, n, bc, 1.0, nfields=1)
+    mg.set_coefficient(torch.tensor(eps.ravel(), device="cuda:0"))
+    phi = torch.zeros(f.size, dtype=torch.float64, device="cuda:0")
+    c, res, _ = mg.solve(torch.tensor(f.ravel(), device="cuda:0"), phi, lam, tol=1e-11, max_cycles=80)
+    err = np.abs(phi.cpu().numpy().reshape(f.shape) - exact).max()
+    print(f"[mg] var {kind} {nd}D n={n} bc={bc}: {c} cycles, res {res[0]:.2e}, err {err:.2e}", flush=True)
+    assert err <= 2.0 * res[0] / lam + 1e-12 * np.abs(exact).max()
+    mg.close()
+
+
+def test_coefficient_reset_and_rejections():
+    torch, M = _mg()
+    from paper_2004_03275_amd import _native as N
+
+    n = 64
+    f = torch.tensor(_seeded((n, n), 3).ravel(), device="cuda:0")
+    ref = M.GpuMultigrid(2, n, R.NEUMANN, 1.0, nfields=1)
+    p0 = torch.zeros_like(f)
+    ref.solve(f, p0, 4.0, tol=1e-10)
+    mg = M.GpuMultigrid(2, n, R.NEUMANN, 1.0, nfields=1)
+    mg.set_coefficient(torch.full((n * n,), 2.0, dtype=torch.float64, device="cuda:0"))
+    p1 = torch.zeros_like(f)
+    with pytest.raises(N.AmrvError) as e:
+        mg.solve(f, p1, 0.0)
+    assert e.value.code == N.EINVAL
+    mg.solve(f, p1, 4.0, tol=1e-10)
+    exact2 = R.helmholtz_var_solve(f.cpu().numpy().reshape(n, n), np.full((n, n), 2.0), 4.0, 1.0, R.NEUMANN)
+    assert np.abs(p1.cpu().numpy().reshape(n, n) - exact2).max() < 1e-9
+    mg.set_coefficient(None)  # back to eps = 1: bit for bit the fresh solver's answer
+    p2 = torch.zeros_like(f)
+    mg.solve(f, p2, 4.0, tol=1e-10)
+    assert torch.equal(p2, p0)
+    mg.close()
+    ref.close()
+    m2 = M.GpuMultigrid(2, n, R.PERIODIC, 1.0, nfields=2)
+    m2.set_coefficient(torch.ones(n * n, dtype=torch.float64, device="cuda:0"))
+    u = torch.ones(n * n, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(N.AmrvError) as e:
+        m2.rd_step(u, u.clone(), 1e-3, M.IMEX, R.SCHNAKENBERG_PARAMS)
+    assert e.value.code == N.EINVAL
+    m2.close()

@@ -36,15 +36,15 @@ def test_rejects_bad_configurations(change, msg):
 def test_workspace_size():
     """Per field and level a solution and a right-hand side of (n >> l)^d
     doubles (256-byte aligned; 2D levels above the LDS-resident tail also a
-    second solution buffer), four temporaries of n^d doubles, and the
-    parameter block."""
+    second solution buffer), a cell coefficient per level, four temporaries
+    of n^d doubles, and the parameter block."""
     up = lambda b: (b + 255) // 256 * 256
     for nd, n, nf in [(2, 256, 2), (3, 32, 1), (2, 4, 1)]:
         got, _ = _bytes(_cfg(ndim=nd, n=n, nfields=nf))
         levels = [n >> l for l in range(n.bit_length() - 1)]
         # 2D levels above the 4,096-cell tail carry a second solution buffer
         per = [(3 if nd == 2 and m ** nd > 4096 else 2) * up(8 * m ** nd) for m in levels]
-        want = nf * sum(per) + 4 * up(8 * n ** nd) + up(8 * 44)
+        want = nf * sum(per) + sum(up(8 * m ** nd) for m in levels) + 4 * up(8 * n ** nd) + up(8 * 44)
         assert got == want, (nd, n, nf, got, want)
 
 
