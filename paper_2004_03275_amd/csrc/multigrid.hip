@@ -1409,22 +1409,28 @@ int amrv_rd_step(amrv_mg* m, const amrv_rd_params* p, int32_t scheme, double dt,
   if (int rc = set_params(m, lam)) return rc;
   int total = 0;
   const bool d2 = g.nd == 2;
+  double *cu = u, *cv = v, *au = m->tmp[0], *av = m->tmp[1];  // explicit schemes: current and other buffer
   for (int s = 0; s < nsteps; s++) {
     if (scheme == AMRV_RD_EULER || scheme == AMRV_RD_MIDPOINT) {
-      double *tu = m->tmp[0], *tv = m->tmp[1];
+      // the new state goes to the other buffer of the pair (the caller's
+      // arrays and tmp[0..1] alternate); one copy at the end if needed
       if (scheme == AMRV_RD_EULER) {
-        hipLaunchKernelGGL(d2 ? k_rd_explicit<2> : k_rd_explicit<3>, dim3(nb), dim3(256), 0, m->st, g, k, u, v, u, v,
-                           tu, tv, dt);
+        hipLaunchKernelGGL(d2 ? k_rd_explicit<2> : k_rd_explicit<3>, dim3(nb), dim3(256), 0, m->st, g, k, cu, cv, cu,
+                           cv, au, av, dt);
       } else {
         double *hu = m->tmp[2], *hv = m->tmp[3];
-        hipLaunchKernelGGL(d2 ? k_rd_explicit<2> : k_rd_explicit<3>, dim3(nb), dim3(256), 0, m->st, g, k, u, v, u, v,
-                           hu, hv, 0.5 * dt);
-        hipLaunchKernelGGL(d2 ? k_rd_explicit<2> : k_rd_explicit<3>, dim3(nb), dim3(256), 0, m->st, g, k, u, v, hu,
-                           hv, tu, tv, dt);
+        hipLaunchKernelGGL(d2 ? k_rd_explicit<2> : k_rd_explicit<3>, dim3(nb), dim3(256), 0, m->st, g, k, cu, cv, cu,
+                           cv, hu, hv, 0.5 * dt);
+        hipLaunchKernelGGL(d2 ? k_rd_explicit<2> : k_rd_explicit<3>, dim3(nb), dim3(256), 0, m->st, g, k, cu, cv, hu,
+                           hv, au, av, dt);
       }
       MGCHK(hipGetLastError());
-      MGCHK(hipMemcpyAsync(u, tu, bytes, hipMemcpyDeviceToDevice, m->st));
-      MGCHK(hipMemcpyAsync(v, tv, bytes, hipMemcpyDeviceToDevice, m->st));
+      std::swap(cu, au);
+      std::swap(cv, av);
+      if (s + 1 == nsteps && cu != u) {
+        MGCHK(hipMemcpyAsync(u, cu, bytes, hipMemcpyDeviceToDevice, m->st));
+        MGCHK(hipMemcpyAsync(v, cv, bytes, hipMemcpyDeviceToDevice, m->st));
+      }
       continue;
     }
     if (scheme == AMRV_RD_SPLIT)
