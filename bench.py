@@ -245,7 +245,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design, not an implementation)", file=sys.stderr)
         sys.exit(2)
 

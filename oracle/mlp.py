@@ -1,8 +1,8 @@
 """CPU reference of the learned refinement flagger.
 
 TEST INFRASTRUCTURE ONLY (tests/, smoke, bench's CPU leg).  The paper refines
-blocks with the Loehner estimator (Sec. 1.3); the learned flagger is an
-addition of this build: a 128-64-64-1 multilayer perceptron that predicts,
+blocks with the Loehner estimator (Sec. 1.3); the learned flagger is not
+in the paper: a 128-64-64-1 multilayer perceptron that predicts,
 from pooled block features, whether Loehner would flag the block for
 refinement.  This module is written from the definitions below, not from the
 HIP code, and shares nothing with it.
