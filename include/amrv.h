@@ -280,6 +280,17 @@ int amrv_use_graph(amrv_forest* f, int32_t enable);
 int amrv_profile(amrv_forest* f, int32_t enable);
 int amrv_profile_read(amrv_forest* f, double* ms_total, int64_t* launches, double* bytes);
 
+/* Uniform forests (every leaf on one level, so the leaves tile the domain
+ * as one grid): copies state variable var (0 <= var < nvar) between the
+ * forest's current state and a device grid array of
+ * (base_blocks[d] * 2^(level-1) * block_nx) cells per dimension, x fastest
+ * (to_grid != 0: forest -> grid; else grid -> forest, which then counts as
+ * a new state).  This lets grid solvers act on forest states, e.g. the
+ * multigrid divergence control of the MHD runs (Sec. 2.4, amrv_mg.h) on the
+ * magnetic field of a uniform MHD forest.  Synchronises.  EINVAL for a
+ * forest with leaves on several levels. */
+int amrv_uniform_grid_copy(amrv_forest* f, int32_t var, double* grid, int32_t to_grid);
+
 int amrv_synchronize(amrv_forest* f);
 const char* amrv_last_error(void);
 

@@ -129,6 +129,7 @@ SIGNATURES = {
                                  ctypes.POINTER(ctypes.c_int64), P, P], ctypes.c_int),
     "amrv_regrid_transfer": ([P, P], ctypes.c_int),
     "amrv_synchronize": ([P], ctypes.c_int),
+    "amrv_uniform_grid_copy": ([P, ctypes.c_int32, P, ctypes.c_int32], ctypes.c_int),
     "amrv_mg_workspace_bytes": ([ctypes.POINTER(MgConfig)], ctypes.c_size_t),
     "amrv_mg_create": ([ctypes.POINTER(MgConfig), P, ctypes.c_size_t, P, ctypes.POINTER(P)], ctypes.c_int),
     "amrv_mg_destroy": ([P], ctypes.c_int),

@@ -14,6 +14,7 @@
 #include "../../include/amrv.h"
 #include "errors.hpp"
 #include "forest.hpp"
+#include "gridcopy.hpp"
 #include "regrid.hpp"
 #include "internal.hpp"
 #include "mlp.hpp"
@@ -500,6 +501,25 @@ int amrv_set_state(amrv_forest* f, const double* U, int64_t nd, int32_t on_devic
   if (!on_device) HIPCHK(hipStreamSynchronize(f->st));
   f->fold_valid = false;
   f->rvalid = false;
+  return AMRV_OK;
+}
+
+int amrv_uniform_grid_copy(amrv_forest* f, int32_t var, double* grid, int32_t to_grid) {
+  if (!f || !grid) return fail(AMRV_EINVAL, "null argument");
+  if (var < 0 || var >= f->tab.nvar) return fail(AMRV_EINVAL, "variable out of range");
+  const int nd = f->tab.nd, l0 = f->tab.lvl[0];
+  for (int64_t b = 0; b < f->tab.n; b++)
+    if (f->tab.lvl[b] != l0) return fail(AMRV_EINVAL, "the forest is not uniform (leaves on several levels)");
+  int ext[3] = {1, 1, 1};
+  for (int d = 0; d < nd; d++) ext[d] = (f->cfg.base_blocks[d] << (l0 - 1)) * f->tab.nx;
+  double* Uvar = f->U[0] + (size_t)var * f->tab.n * f->tab.ncell;
+  HIPCHK(launch_grid_copy(Uvar, grid, f->geo.ijk, (int)f->tab.n, nd, f->tab.nx, f->tab.ncell, ext[0], ext[1],
+                          to_grid ? 1 : 0, f->st));
+  if (!to_grid) {
+    f->fold_valid = false;
+    f->rvalid = false;
+  }
+  HIPCHK(hipStreamSynchronize(f->st));
   return AMRV_OK;
 }
 

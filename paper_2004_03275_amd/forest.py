@@ -202,6 +202,27 @@ class GpuForest:
         N.check(N.lib().amrv_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
         return ms.value, n.value, b.value
 
+    def grid_shape(self) -> tuple:
+        """[z][y][x] extents of the uniform grid the leaves tile (uniform forests)."""
+        s = self.scheme
+        lev = int(self.forest.level[0])
+        ext = [s.base_blocks[d] * (1 << (lev - 1)) * s.block_nx[d] for d in range(s.ndim)]
+        return tuple(reversed(ext))
+
+    def to_grid(self, var: int) -> torch.Tensor:
+        """State variable var of a uniform forest as a device grid array."""
+        t = torch.empty(self.grid_shape(), dtype=torch.float64, device=self.device)
+        N.check(N.lib().amrv_uniform_grid_copy(self._h, int(var), ctypes.c_void_p(t.data_ptr()), 1))
+        return t
+
+    def from_grid(self, var: int, grid: torch.Tensor):
+        """Write state variable var of a uniform forest from a device grid array."""
+        if not (grid.is_cuda and grid.dtype == torch.float64 and grid.is_contiguous()
+                and tuple(grid.shape) == self.grid_shape()):
+            raise ValueError(f"expected a contiguous float64 device tensor of shape {self.grid_shape()}")
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        N.check(N.lib().amrv_uniform_grid_copy(self._h, int(var), ctypes.c_void_p(grid.data_ptr()), 0))
+
     def synchronize(self):
         N.check(N.lib().amrv_synchronize(self._h))
 
