@@ -433,3 +433,21 @@ def test_coefficient_reset_and_rejections():
         m2.rd_step(u, u.clone(), 1e-3, M.IMEX, R.SCHNAKENBERG_PARAMS)
     assert e.value.code == N.EINVAL
     m2.close()
+
+
+@pytest.mark.parametrize("nd,sizes", [(2, (64, 256, 1024)), (3, (16, 32, 64, 128))])
+def test_cycle_count_does_not_grow_with_the_grid(nd, sizes):
+    """Multigrid's defining property: the V-cycles needed for a fixed
+    relative residual stay (nearly) constant as the grid is refined, where a
+    smoother alone would need O(n^2) sweeps."""
+    torch, M = _mg()
+    counts = []
+    for n in sizes:
+        f = _seeded((n,) * nd, 80 + n)
+        mg = M.GpuMultigrid(nd, n, R.NEUMANN, 1.0, nfields=1)
+        phi = torch.zeros(f.size, dtype=torch.float64, device="cuda:0")
+        c, res, fmax = mg.solve(torch.tensor(f.ravel(), device="cuda:0"), phi, 1.0, tol=1e-9, max_cycles=60)
+        counts.append(c)
+        mg.close()
+    print(f"[mg] {nd}D cycles to 1e-9 for n = {sizes}: {counts}", flush=True)
+    assert max(counts) - min(counts) <= 3, counts
