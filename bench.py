@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 def measured_counters(workload: str) -> dict:
     """HBM bytes per stage-kernel launch and the VALU / FP64 issue fractions
     from the committed counter summary, if it was taken on this workload with
-    the current kernel sources (else an empty dict)."""
+    the current kernel sources and build flags (else an empty dict)."""
     import hashlib
     if workload != "blast":
         return {}
@@ -45,8 +45,9 @@ def measured_counters(workload: str) -> dict:
     csrc = os.path.join(ROOT, "paper_2004_03275_amd", "csrc")
     try:
         text = open(prof).read()
+        # the kernel sources and the build (its compile flags)
         h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
-                                    for f in ("kernels.hip", "physics.hpp", "internal.hpp"))).hexdigest()
+                                    for f in ("kernels.hip", "physics.hpp", "internal.hpp", "../build.py"))).hexdigest()
     except OSError:
         return {}
     keys = ("kernel_source_sha256", "traffic_bytes_per_launch", "valu_issue_frac", "fp64_issue_frac")

@@ -18,6 +18,9 @@ HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-but-set-variable",
+    # the stage kernel runs two waves per SIMD (register-bound): the
+    # ILP-maximising scheduler hides more latency there (-3% per launch)
+    "-mllvm", "-amdgpu-sched-strategy=max-ilp",
 ]
 
 
