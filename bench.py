@@ -47,7 +47,7 @@ def measured_counters(workload: str) -> dict:
         text = open(prof).read()
         # the kernel sources and the build (its compile flags)
         h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
-                                    for f in ("kernels.hip", "physics.hpp", "internal.hpp", "../build.py"))).hexdigest()
+                                    for f in ("kernels.hip", "stage_ilp.hip", "physics.hpp", "internal.hpp", "../build.py"))).hexdigest()
     except OSError:
         return {}
     keys = ("kernel_source_sha256", "traffic_bytes_per_launch", "valu_issue_frac", "fp64_issue_frac")

@@ -18,20 +18,36 @@ HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-but-set-variable",
-    # the stage kernel runs two waves per SIMD (register-bound): the
-    # ILP-maximising scheduler hides more latency there (-3% per launch)
-    "-mllvm", "-amdgpu-sched-strategy=max-ilp",
 ]
+
+# compiled separately with extra flags and linked in: the combined-variant
+# stage kernels, which run two waves per SIMD (register-bound), gain ~3% per
+# launch from the ILP-maximising scheduler (the other stage kernels lose)
+UNITS = {"stage_ilp.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 
 
 def build(verbose: bool = False, extra: list | None = None) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", *HIPFLAGS, *(extra or []), "-x", "hip", *srcs, "-o", tmp]
+    t0 = time.time()
+    objs = []
+    for unit, flags in UNITS.items():
+        obj = os.path.join(HERE, unit + ".o.tmp")
+        cflags = [f for f in HIPFLAGS if f != "-shared"]
+        cmd = ["hipcc", *cflags, *flags, *(extra or []), "-c", "-x", "hip", os.path.join(CSRC, unit), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    cmd = ["hipcc", *HIPFLAGS, *(extra or []), "-x", "hip", *srcs, "-x", "none", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
-    t0 = time.time()
-    subprocess.run(cmd, check=True)
+    try:
+        subprocess.run(cmd, check=True)
+    finally:
+        for obj in objs:
+            if os.path.exists(obj):
+                os.remove(obj)
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB} in {time.time() - t0:.1f}s", flush=True)

@@ -1140,6 +1140,7 @@ __global__ void __launch_bounds__(WGS) k_lohner(Geo g, const double* __restrict_
   }
 }
 
+#ifndef AMRV_STAGE_ILP_UNIT
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
@@ -1164,6 +1165,8 @@ __global__ void k_scale(double* U, const double* __restrict__ facp, long long co
 // ---------------------------------------------------------------------------
 // launchers: dispatch runtime configuration onto template instances
 // ---------------------------------------------------------------------------
+
+#endif  // AMRV_STAGE_ILP_UNIT
 
 template <int V>
 using IC = std::integral_constant<int, V>;
@@ -1215,6 +1218,30 @@ static void dispatch(const LaunchCfg& c, Fn&& fn) {
 }
 
 static inline unsigned blocks_for(long long work) { return (unsigned)((work + WGS - 1) / WGS); }
+
+// The combined-variant stage kernels of 2D/3D non-MHD physics are compiled
+// in a unit of their own (stage_ilp.hip) with LLVM's ILP-maximising
+// scheduler, which helps them at two waves per SIMD and slows the others;
+// each instantiation exists in one unit only.
+hipError_t launch_stage_combined(const Geo& g, const LaunchCfg& c, const StageArgs& a, const double* physp,
+                                 const Sched& s, int grid, hipStream_t st);
+template <int ND, int PH, int LM>
+constexpr bool in_ilp_unit() {
+  return ND >= 2 && PH != PH_MHD && !lim_asym<LM>();
+}
+
+#ifdef AMRV_STAGE_ILP_UNIT
+hipError_t launch_stage_combined(const Geo& g, const LaunchCfg& c, const StageArgs& a, const double* physp,
+                                 const Sched& s, int grid, hipStream_t st) {
+  dispatch(c, [&](auto nd, auto ph, auto fl, auto lm) {
+    constexpr int ND = decltype(nd)::value, FL = decltype(fl)::value, LM = decltype(lm)::value;
+    constexpr int PH = decltype(ph)::value;
+    if constexpr (in_ilp_unit<ND, PH, LM>())
+      hipLaunchKernelGGL((k_stage_tile<ND, PH, FL, LM, false>), dim3(grid), dim3(WGS), 0, st, g, a, physp, s);
+  });
+  return hipGetLastError();
+}
+#else
 
 hipError_t launch_restrict(const Geo& g, const LaunchCfg& c, const double* U, const int32_t* list, int nlist,
                            hipStream_t st) {
@@ -1282,6 +1309,7 @@ hipError_t launch_prolong(const Geo& g, const LaunchCfg& c, const double* U, con
 
 hipError_t launch_stage(const Geo& g, const LaunchCfg& c, const StageArgs& a, const double* physp, const Sched& s,
                         int grid, hipStream_t st) {
+  bool combined = false;
   dispatch(c, [&](auto nd, auto ph, auto fl, auto lm) {
     constexpr int ND = decltype(nd)::value, FL = decltype(fl)::value, LM = decltype(lm)::value;
     constexpr int PH = decltype(ph)::value;
@@ -1289,9 +1317,12 @@ hipError_t launch_stage(const Geo& g, const LaunchCfg& c, const StageArgs& a, co
       hipLaunchKernelGGL((k_stage_line<PH, FL, LM>), dim3(grid), dim3(WGS), 0, st, g, a, physp, s);
     else if (c.variant == 1 || lim_asym<LM>())
       hipLaunchKernelGGL((k_stage_tile<ND, PH, FL, LM, true>), dim3(grid), dim3(WGS), 0, st, g, a, physp, s);
+    else if constexpr (in_ilp_unit<ND, PH, LM>())
+      combined = true;
     else if constexpr (!lim_asym<LM>())
       hipLaunchKernelGGL((k_stage_tile<ND, PH, FL, LM, false>), dim3(grid), dim3(WGS), 0, st, g, a, physp, s);
   });
+  if (combined) return launch_stage_combined(g, c, a, physp, s, grid, st);
   return hipGetLastError();
 }
 
@@ -1390,5 +1421,7 @@ hipError_t launch_scale_var(double* U, const double* facp, long long count, hipS
   hipLaunchKernelGGL(k_scale, dim3((unsigned)nb), dim3(256), 0, st, U, facp, count);
   return hipGetLastError();
 }
+
+#endif  // AMRV_STAGE_ILP_UNIT
 
 }  // namespace amrv
