@@ -238,7 +238,7 @@ def main():
     ap.add_argument("--regrid-every", type=int, default=5)
     ap.add_argument("--adaptive-flagger", default="lohner", choices=["lohner", "mlp"],
                     help="flags of the adaptive run: Loehner, or the learned flagger with Loehner fallback "
-                         "(judged against full Loehner flags every second regrid)")
+                         "(compared with full Loehner flags every second regrid)")
     ap.add_argument("--no-rd", action="store_true",
                     help="skip the reaction-diffusion measurement that the default run adds")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -455,7 +455,7 @@ def main():
         ga = g
         t_ad, done, updates, regrid_ms, regrids, counts = 0.0, 0, 0, 0.0, 0, []
         use_mlp = args.adaptive_flagger == "mlp" and s.ndim > 1
-        judge = []
+        vs_lohner = []
         if use_mlp:
             from paper_2004_03275_amd import mlp as MLP
 
@@ -476,7 +476,7 @@ def main():
                     flags = ga.flag_blocks(mode=N.FLAG_MLP_FALLBACK)
                     if regrids % 2 == 1:
                         ref = ga.flag_blocks()
-                        judge.append(float(np.mean((flags == 1) != (ref == 1))))
+                        vs_lohner.append(float(np.mean((flags == 1) != (ref == 1))))
                 else:
                     flags = ga.flag_blocks()
                 nxt = ga.regrid(flags)
@@ -496,7 +496,7 @@ def main():
                      "leaves_after_each_regrid": counts, "final_levels": {str(k): v for k, v in
                                                                            ga.forest.level_counts().items()},
                      "flagger": "mlp_fallback" if use_mlp else "lohner",
-                     "judge_refine_disagreement": judge if use_mlp else None,
+                     "refine_disagreement_vs_lohner": vs_lohner if use_mlp else None,
                      "note": "cell updates of the current forest per step; regrid = flags, plan, new "
                              "forest (workspace, tables), transfer"}
         log(f"adaptive: {adaptive['value']:.1f} MCUPS over {nad} steps, {regrids} regrids of "

@@ -5,7 +5,7 @@ flagger predicts the same refine decision (block maximum of the estimator
 above the tolerance) from 128 pooled features per leaf with a 128-64-64-1
 perceptron whose forward and backward passes are the library's bfloat16 MFMA
 kernels (amrv_mlp_train, AMRV_FLAG_MLP); Loehner stays as the fallback for
-low-confidence leaves and as the judge of the disagreement rate.
+low-confidence leaves and as the reference its disagreement rate is measured against.
 """
 from __future__ import annotations
 
