@@ -34,12 +34,13 @@ METRIC = "MCUPS (cell-updates/s) per full RK step, batched vs per-block, at 1e-1
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-def measured_counters(workload: str) -> dict:
+def measured_counters(workload: str, limiter: str = "vanleer", variant: int = 0) -> dict:
     """HBM bytes per stage-kernel launch and the VALU / FP64 issue fractions
-    from the committed counter summary, if it was taken on this workload with
-    the current kernel sources and build flags (else an empty dict)."""
+    from the committed counter summary, if it was taken on this workload and
+    stage kernel (van Leer slopes, combined variant) with the current kernel
+    sources and build flags (else an empty dict)."""
     import hashlib
-    if workload != "blast":
+    if workload != "blast" or limiter != "vanleer" or variant != 0:
         return {}
     prof = os.path.join(ROOT, "profiles", "hbm_counters_3d_amr_blast.md")
     csrc = os.path.join(ROOT, "paper_2004_03275_amd", "csrc")
@@ -508,7 +509,7 @@ def main():
     if args.workload == "blast" and not args.no_rd:
         rd = rd_measure(2, 256, 20, 3, log, cpu=not args.no_cpu_baseline)
 
-    counters = measured_counters(args.workload)
+    counters = measured_counters(args.workload, ["minmod", "vanleer", "mc", "koren", "cada"][s.limiter], sched[3])
     names = {0: "per_block", 1: "grid", 2: "persistent"}
     bytes_per_cell_step = (2 + 3 * (s.rk_stages - 1)) * s.nvar * 8
     out = {

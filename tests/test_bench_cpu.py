@@ -37,3 +37,7 @@ def test_counter_summary_is_tied_to_the_kernel_sources(tmp_path, monkeypatch):
         assert set(got) == {"traffic_bytes_per_launch", "valu_issue_frac", "fp64_issue_frac"}
         assert got["traffic_bytes_per_launch"] > 8e9  # above the 8.47 GB algorithmic bytes
     assert bench.measured_counters("kh") == {}
+    # counters of the van Leer combined-variant kernel belong to no other stage kernel
+    assert bench.measured_counters("blast", "koren", 1) == {}
+    assert bench.measured_counters("blast", "vanleer", 1) == {}
+    assert bench.measured_counters("blast", "mc", 0) == {}
