@@ -59,7 +59,7 @@ def measured_counters(workload: str, limiter: str = "vanleer", variant: int = 0)
 
 
 def make_workload(name: str):
-    from paper_2004_03275_amd import workloads as W
+    import workloads as W
 
     if name == "blast":
         s = W.blast_scheme()
@@ -117,7 +117,7 @@ def rd_measure(nd: int, n: int, steps: int, warmup: int, log, cpu: bool = True, 
     import torch
 
     from paper_2004_03275_amd import multigrid as M
-    from paper_2004_03275_amd import workloads as W
+    import workloads as W
 
     params = {"model": M.SCHNAKENBERG, "Du": 0.05, "Dv": 1.0, "p1": 100.0, "p2": 0.1305, "p3": 0.7695}
     u0, v0, L = W.schnakenberg_initial(nd, n)
@@ -255,7 +255,7 @@ def main():
 
     from paper_2004_03275_amd import _native as N
     from paper_2004_03275_amd import forest as F
-    from paper_2004_03275_amd import workloads as W
+    import workloads as W
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)

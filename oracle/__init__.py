@@ -45,35 +45,41 @@ class _Config(ctypes.Structure):
     ]
 
 
+def bind(path: str) -> ctypes.CDLL:
+    """Load an oracle library build at `path` and declare its functions."""
+    L = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    L.orc_forest_create.argtypes = [ctypes.POINTER(_Config), ctypes.c_int64, P, P, ctypes.POINTER(P)]
+    L.orc_forest_destroy.argtypes = [P]
+    L.orc_nvar.argtypes = [P]
+    L.orc_set_state.argtypes = [P, P, ctypes.c_int64]
+    L.orc_get_state.argtypes = [P, P, ctypes.c_int64]
+    L.orc_max_dt.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+    L.orc_glm_ch.argtypes = [P]
+    L.orc_glm_ch.restype = ctypes.c_double
+    L.orc_advance.argtypes = [P, ctypes.c_double]
+    L.orc_flag_blocks.argtypes = [P, P, P]
+    L.orc_padded_block.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64]
+    L.orc_face_kinds.argtypes = [P, ctypes.c_int64, P]
+    L.orc_lohner_cells.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64]
+    L.orc_face_flux.argtypes = [P, P, P, ctypes.c_int, P]
+    L.orc_regrid_plan.argtypes = [P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P, P]
+    L.orc_regrid_transfer.argtypes = [P, P]
+    L.orc_limiter_value.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    L.orc_limiter_value.restype = ctypes.c_double
+    L.orc_set_threads.argtypes = [ctypes.c_int]
+    L.orc_set_threads.restype = None
+    L.orc_get_threads.restype = ctypes.c_int
+    L.orc_last_error.restype = ctypes.c_char_p
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_build.LIB):
             _build.build()
-        L = ctypes.CDLL(_build.LIB)
-        P = ctypes.c_void_p
-        L.orc_forest_create.argtypes = [ctypes.POINTER(_Config), ctypes.c_int64, P, P, ctypes.POINTER(P)]
-        L.orc_forest_destroy.argtypes = [P]
-        L.orc_nvar.argtypes = [P]
-        L.orc_set_state.argtypes = [P, P, ctypes.c_int64]
-        L.orc_get_state.argtypes = [P, P, ctypes.c_int64]
-        L.orc_max_dt.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
-        L.orc_glm_ch.argtypes = [P]
-        L.orc_glm_ch.restype = ctypes.c_double
-        L.orc_advance.argtypes = [P, ctypes.c_double]
-        L.orc_flag_blocks.argtypes = [P, P, P]
-        L.orc_padded_block.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64]
-        L.orc_face_kinds.argtypes = [P, ctypes.c_int64, P]
-        L.orc_lohner_cells.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64]
-        L.orc_regrid_plan.argtypes = [P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P, P]
-        L.orc_regrid_transfer.argtypes = [P, P]
-        L.orc_limiter_value.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
-        L.orc_limiter_value.restype = ctypes.c_double
-        L.orc_set_threads.argtypes = [ctypes.c_int]
-        L.orc_set_threads.restype = None
-        L.orc_get_threads.restype = ctypes.c_int
-        L.orc_last_error.restype = ctypes.c_char_p
-        _lib = L
+        _lib = bind(_build.LIB)
     return _lib
 
 
@@ -199,6 +205,16 @@ class OracleForest:
         _check(lib().orc_lohner_cells(self._h, int(leaf), out.ctypes.data, out.size))
         return out
 
+    def face_flux(self, vl, vr, direction: int = 0) -> np.ndarray:
+        """The scheme's Riemann flux across a face normal to `direction` for
+        primitive face states vl, vr."""
+        vl = np.ascontiguousarray(vl, dtype=np.float64)
+        vr = np.ascontiguousarray(vr, dtype=np.float64)
+        assert vl.shape == vr.shape == (self.nvar,)
+        F = np.empty(self.nvar, dtype=np.float64)
+        _check(lib().orc_face_flux(self._h, vl.ctypes.data, vr.ctypes.data, int(direction), F.ctypes.data))
+        return F
+
     def face_kinds(self, leaf: int) -> np.ndarray:
         k = np.empty(2 * self.scheme.ndim, dtype=np.int32)
         _check(lib().orc_face_kinds(self._h, int(leaf), k.ctypes.data))
@@ -219,10 +235,8 @@ class OracleForest:
 
     def regrid(self, flags) -> "OracleForest":
         """A new oracle forest on the regridded leaves, holding the transferred state."""
-        from paper_2004_03275_amd import workloads as W
-
         lev, ijk = self.regrid_plan(flags)
-        g = OracleForest(W.Forest(self.scheme, lev, ijk))
+        g = OracleForest(type(self.forest)(self.scheme, lev, ijk))
         _check(lib().orc_regrid_transfer(self._h, g._h))
         return g
 
@@ -231,13 +245,21 @@ class OracleForest:
         _check(lib().orc_regrid_transfer(self._h, other._h))
 
 
+def courant_factor(n: int, nramp: int) -> float:
+    """The reduced Courant step of the MHD blast's start (Sec. 2.4: the
+    first 10 steps are lowered gradually; the paper gives no formula).
+    Reading: step n (from 0) of the first nramp steps takes the fraction
+    (n + 1) / nramp of the Courant step, later steps all of it."""
+    if nramp > 0 and n < nramp:
+        return (n + 1) / nramp
+    return 1.0
+
+
 def run(forest, U0: np.ndarray, *, t_end: float | None = None, steps: int | None = None,
         dts=None, ramp_steps: int = 0):
     """Drive the oracle: free Courant steps to t_end, a fixed step count, or a
     given dt sequence (lockstep runs); ramp_steps > 0 scales the Courant step
-    of the first steps by workloads.courant_ramp.  Returns (state, dts used)."""
-    from paper_2004_03275_amd.workloads import courant_ramp
-
+    of the first steps by courant_factor.  Returns (state, dts used)."""
     o = OracleForest(forest)
     o.set_state(U0)
     used = []
@@ -252,7 +274,7 @@ def run(forest, U0: np.ndarray, *, t_end: float | None = None, steps: int | None
         while True:
             if steps is not None and n >= steps:
                 break
-            dt = o.max_dt() * courant_ramp(n, ramp_steps)
+            dt = o.max_dt() * courant_factor(n, ramp_steps)
             if t_end is not None:
                 if t >= t_end:
                     break

@@ -13,15 +13,19 @@ FLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "
          "-Wall", "-Wextra"]
 
 
-def build(verbose: bool = False) -> str:
-    src = os.path.join(HERE, "orc.c")
-    tmp = LIB + ".tmp"
-    cmd = ["gcc", *FLAGS, "-o", tmp, src, "-lm"]
+SRC = os.path.join(HERE, "orc.c")
+
+
+def build(verbose: bool = False, src: str = SRC, out: str = LIB) -> str:
+    """Compile `src` (the oracle's source, or a test's edited copy of it)
+    into the shared library `out`."""
+    tmp = out + ".tmp"
+    cmd = ["gcc", *FLAGS, "-I", HERE, "-o", tmp, src, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

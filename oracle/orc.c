@@ -1342,6 +1342,12 @@ int orc_padded_block(orc_forest* f, int64_t leaf, double* out, int64_t n_doubles
   return ORC_OK;
 }
 
+int orc_face_flux(orc_forest* f, const double* vl, const double* vr, int dir, double* F) {
+  if (!f || !vl || !vr || !F || dir < 0 || dir >= f->nd) return fail(ORC_EINVAL, "bad argument");
+  riemann(f, vl, vr, dir, F);
+  return ORC_OK;
+}
+
 int orc_lohner_cells(orc_forest* f, int64_t leaf, double* out, int64_t n_doubles) {
   if (!f || !out || leaf < 0 || leaf >= f->n) return fail(ORC_EINVAL, "bad argument");
   if (n_doubles != f->ncell) return fail(ORC_EINVAL, "size mismatch");

@@ -83,6 +83,10 @@ int orc_padded_block(orc_forest* f, int64_t leaf, double* out, int64_t n_doubles
  * 2 finer, 3 physical boundary. faces = 2*ndim entries (-x,+x,-y,+y,-z,+z). */
 int orc_face_kinds(const orc_forest* f, int64_t leaf, int32_t* kinds);
 /* Test hook: per-cell weighted Loehner estimator of one leaf, [cell]. */
+/* The forest's Riemann flux across a face normal to dir (0..ndim-1) for the
+ * primitive face states vl, vr (nvar values each; MHD uses the GLM speed of
+ * the last orc_max_dt) into F (nvar). */
+int orc_face_flux(orc_forest* f, const double* vl, const double* vr, int dir, double* F);
 int orc_lohner_cells(orc_forest* f, int64_t leaf, double* out, int64_t n_doubles);
 /* Regrid plan (Sec. 1.3, refinement ratio 2): leaves flagged +1 (below
  * max_level) are split into 2^ndim children; a complete group of 2^ndim

@@ -14,8 +14,8 @@ from . import _native as N
 
 
 class GpuForest:
-    """A forest on one GPU.  ``forest`` is a workloads.Forest (leaf list and
-    scheme); ``stream`` a torch.cuda.Stream (a new one by default)."""
+    """A forest on one GPU.  ``forest`` is a leaf list with its scheme (e.g.
+    a workloads.Forest); ``stream`` a torch.cuda.Stream (a new one by default)."""
 
     def __init__(self, forest, device: str | torch.device = "cuda:0", stream: torch.cuda.Stream | None = None,
                  config: N.Config | None = None):
@@ -120,10 +120,9 @@ class GpuForest:
     def regrid(self, flags) -> "GpuForest":
         """A new forest on the regridded leaves (same device and stream,
         schedule and variant), holding this forest's transferred state."""
-        from . import workloads as W
-
         lev, ijk = self.regrid_plan(flags)
-        g = GpuForest(W.Forest(self.scheme, lev, ijk), device=self.device, stream=self.stream, config=self.cfg)
+        g = GpuForest(type(self.forest)(self.scheme, lev, ijk), device=self.device, stream=self.stream,
+                      config=self.cfg)
         g.set_schedule(*self.get_schedule())
         g.set_variant(self.get_variant())
         N.check(N.lib().amrv_regrid_transfer(self._h, g._h))
@@ -227,14 +226,22 @@ class GpuForest:
         N.check(N.lib().amrv_synchronize(self._h))
 
 
+def courant_ramp(step: int, ramp_steps: int) -> float:
+    """Factor on the Courant time step of step ``step`` (counted from 0):
+    the paper lowers the first 10 time steps of its MHD blast gradually
+    (Sec. 2.4) without a formula; read as the linear ramp (step + 1) /
+    ramp_steps over the first ramp_steps steps, 1 after them."""
+    if ramp_steps <= 0 or step >= ramp_steps:
+        return 1.0
+    return (step + 1) / ramp_steps
+
+
 def run(forest, U0, *, t_end=None, steps=None, dts=None, schedule=None, graph=False, device="cuda:0",
         variant=None, device_dt=False, chunk=50, ramp_steps=0):
     """Drive the GPU forest like oracle.run: free Courant steps to t_end, a
     fixed step count, or a given dt sequence; ramp_steps > 0 scales the first
-    Courant steps by workloads.courant_ramp (host-chosen steps only).
+    Courant steps by courant_ramp (host-chosen steps only).
     Returns (state, dts used)."""
-    from .workloads import courant_ramp
-
     g = GpuForest(forest, device=device)
     if schedule is not None:
         g.set_schedule(*schedule)

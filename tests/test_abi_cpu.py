@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 from paper_2004_03275_amd import _native as N
-from paper_2004_03275_amd import workloads as W
+import workloads as W
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from oracle import mlp as M
-from paper_2004_03275_amd import workloads as W
+import workloads as W
 
 pytestmark = pytest.mark.gpu
 

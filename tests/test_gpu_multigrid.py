@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 from oracle import rd as R
-from paper_2004_03275_amd import workloads as W
+import workloads as W
 
 pytestmark = pytest.mark.gpu
 

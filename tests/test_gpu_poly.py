@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from oracle import mlp as M
-from paper_2004_03275_amd import workloads as W
+import workloads as W
 
 pytestmark = pytest.mark.gpu
 

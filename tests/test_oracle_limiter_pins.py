@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2004_03275_amd import workloads as W
+import workloads as W
 
 MM, VL, MC, KO, CA = W.MINMOD, W.VANLEER, W.MC, W.KOREN, W.CADA
 

@@ -19,7 +19,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2004_03275_amd import workloads as W
+import workloads as W
 
 
 def _line_mhd(n, cr=0.18, flux=W.HLL):
@@ -172,9 +172,16 @@ def test_mhd_blast_point_and_diagonal_symmetry():
     assert np.abs(G[1]).max() > 0.1
 
 
-def test_courant_ramp():
-    assert [W.courant_ramp(n, 10) for n in range(12)] == [(n + 1) / 10 for n in range(10)] + [1.0, 1.0]
-    assert W.courant_ramp(0, 0) == 1.0
+def test_courant_ramp_reading():
+    """The reading of the lowered first steps (Sec. 2.4 gives no formula):
+    the oracle's run takes (n + 1)/10 of each of the first 10 Courant steps."""
+    assert [oracle.courant_factor(n, 10) for n in range(12)] == [(n + 1) / 10 for n in range(10)] + [1.0, 1.0]
+    assert oracle.courant_factor(0, 0) == 1.0
+    f, U = W.mhd_blast(2, base=2, max_level=2)
+    o = oracle.OracleForest(f)
+    o.set_state(U)
+    _, dts = oracle.run(f, U, steps=3, ramp_steps=10)
+    assert dts[0] == o.max_dt() * 0.1
 
 
 # ---------------------------------------------------------------------------

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from oracle import mlp as M
-from paper_2004_03275_amd import workloads as W
+import workloads as W
 
 
 def test_bf16_rounding_bit_patterns():

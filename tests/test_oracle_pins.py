@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 from oracle import exact_riemann as ER
-from paper_2004_03275_amd import workloads as W
+import workloads as W
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 

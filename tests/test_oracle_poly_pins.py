@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 from oracle import exact_riemann as E
-from paper_2004_03275_amd import workloads as W
+import workloads as W
 
 
 def _scheme_1d(n, nb=8, g=2.0, cad=0.5, flux=W.HLL, lim=W.KOREN, bc=W.ZERO_GRADIENT, x=(-10.0, 10.0)):

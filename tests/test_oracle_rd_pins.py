@@ -24,7 +24,7 @@ import pytest
 from scipy.integrate import solve_ivp
 
 from oracle import rd as R
-from paper_2004_03275_amd import workloads as W
+import workloads as W
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "rd_table1_dt_limits.txt")
 

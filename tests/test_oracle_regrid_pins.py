@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2004_03275_amd import workloads as W
+import workloads as W
 
 
 # ---------------------------------------------------------------------------

@@ -1,10 +1,11 @@
 """Seeded synthetic inputs shared by the HIP path's callers and the oracle.
 
-This module holds no step of the finite-volume method: it builds block forests
-(leaf lists with 2:1 balance, Morton order) and initial conditions in
-conserved variables, plus the scheme parameters of each workload.  Both the
-product binding and the oracle consume what it returns; neither imports the
-other.
+This package holds no step of the finite-volume method: it builds block
+forests (leaf lists with 2:1 balance, Morton order) and initial conditions in
+conserved variables, the scheme parameters of each workload, and the relative
+L1 difference used to compare two states.  It imports neither the product
+package nor the oracle, and neither of those imports it: tests, the smoke
+check and the bench hand its forests and states to both.
 
 Workloads (the paper's MPI-AMRVAC, arXiv 2004.03275, runs the solver it names
 on block forests, Sec. 1.3; the configurations below are synthetic stand-ins
@@ -509,15 +510,6 @@ def mhd_blast(ndim: int = 2, base: int = 4, max_level: int = 4, radius: float = 
     b0 = 1.0 / math.sqrt(s.ndim)
     B = [np.full_like(r2, b0) for _ in range(s.ndim)]
     return f, state_from_primitive(f, rho, vel, p, B)
-
-
-def courant_ramp(step: int, ramp_steps: int) -> float:
-    """Factor on the Courant time step of step ``step`` (from 0): the paper
-    reduces the first 10 steps of its MHD blast gradually (Sec. 2.4); read
-    here as a linear ramp (step + 1) / ramp_steps."""
-    if ramp_steps <= 0 or step >= ramp_steps:
-        return 1.0
-    return (step + 1) / ramp_steps
 
 
 def relative_l1(U: np.ndarray, R: np.ndarray, forest: Forest) -> np.ndarray:
