@@ -16,7 +16,7 @@ import numpy as np
 import torch
 
 from . import _native as N
-from . import workloads as W
+import workloads as W
 from .forest import GpuForest
 
 
