@@ -6,9 +6,12 @@
 * Orszag-Tang: 1024 leaves of 16^2, MHD + GLM, to t = 0.5, compared every
   200 steps and at the end;
 * 3D AMR blast: 19,384 leaves of 16^3 on 4 levels, 2 steps, then identical
-  Loehner flags.
+  Loehner flags and regrid;
+* 3D AMR blast on the path bench.py times: autotuned schedule, HIP-graph
+  replay, 20 steps of amrv_advance_cfl (device-computed dt) in chunks of 5,
+  Loehner flags after steps 10 and 20 as in the timed region.
 The bar is relative L1 <= 1e-10 per variable; the runs are in fact equal
-bit for bit.
+bit for bit, which is asserted too.
 """
 import time
 
@@ -98,3 +101,43 @@ def test_blast_full_size_two_steps_and_flags():
     print(f"[full] blast regrid: {f.n} -> {g2.forest.n} leaves {g2.forest.level_counts()}, differing values {nbad}",
           flush=True)
     assert nbad == 0
+
+
+def test_blast_timed_path_20_steps():
+    """The configuration the headline MCUPS is measured in, against the oracle."""
+    from paper_2004_03275_amd.forest import GpuForest
+
+    f, U = W.blast(W.blast_scheme())
+    g = GpuForest(f)
+    g.set_state(U)
+    sched = g.autotune(5)
+    g.use_graph(True)
+    print(f"[full] timed path: {f.n} leaves, schedule {sched}", flush=True)
+    o = oracle.OracleForest(f)
+    o.set_state(U)
+    tg = to = 0.0
+    t0 = time.time()
+    for chunk in range(1, 5):
+        tg, taken = g.advance_cfl(5, float("inf"), tg)
+        assert taken == 5
+        for _ in range(5):
+            dt = o.max_dt()
+            o.advance(dt)
+            to += dt
+        step = 5 * chunk
+        assert tg == to, (step, tg, to)
+        G, R = g.get_state(), o.get_state()
+        e = W.relative_l1(G, R, f).max()
+        same = bool(np.array_equal(G, R))
+        print(f"[full] timed path step {step}: t {tg:.6e}, rel L1 {e:.3e}, bitwise {same} "
+              f"({time.time() - t0:.0f} s)", flush=True)
+        assert e <= TOL and same, (step, e)
+        del G, R
+        if step % 10 == 0:
+            fg, eg = g.flag_blocks(with_emax=True)
+            fo, eo = o.flag_blocks(with_emax=True)
+            print(f"[full] timed path flags at step {step}: refine {int(np.sum(fo == 1))}, "
+                  f"coarsen {int(np.sum(fo == -1))}; identical {np.array_equal(fg, fo)}", flush=True)
+            assert np.array_equal(fg, fo) and np.array_equal(eg, eo)
+    g.close()
+    o.close()

@@ -110,7 +110,7 @@ def test_training_step_gradient_matches_reference(n):
     gr, lr = M.grad_bf16(w0, X, y, 2.0)
     rel = np.linalg.norm(g - gr) / np.linalg.norm(gr)
     print(f"[mlp] n={n} grad rel err {rel:.2e}, loss {loss[0]:.5f} vs {lr:.5f}", flush=True)
-    assert rel <= 2e-2
+    assert rel <= 1e-3  # measured 2e-7 (FP32 accumulation order only)
     assert abs(loss[0] - lr) <= 1e-4 * max(1.0, lr)
     assert np.array_equal(w1, w0)  # lr = 0 leaves the weights
 

@@ -113,6 +113,7 @@ def test_kh_small_matches_oracle(flux, lim):
     G, _ = F.run(f, U, steps=30)
     e = _report(f"kh 4x4 flux={flux} lim={lim}", G, R, f)
     assert e.max() <= TOL
+    assert np.array_equal(G, R)
 
 
 def test_orszag_tang_small_matches_oracle():
@@ -122,6 +123,7 @@ def test_orszag_tang_small_matches_oracle():
     G, _ = F.run(f, U, steps=30)
     e = _report("ot 4x4", G, R, f)
     assert e.max() <= TOL
+    assert np.array_equal(G, R)
 
 
 @pytest.mark.parametrize("flux", [W.HLLC, W.HLL])
@@ -138,6 +140,7 @@ def test_amr2d_matches_oracle(flux):
     G, _ = F.run(f, U, dts=dts)
     e = _report(f"amr2d flux={flux} ({f.level_counts()})", G, R, f)
     assert e.max() <= TOL
+    assert np.array_equal(G, R)
 
 
 def test_blast_small_amr_matches_oracle():
@@ -147,6 +150,7 @@ def test_blast_small_amr_matches_oracle():
     G, _ = F.run(f, U, dts=dts)
     e = _report(f"blast small ({f.level_counts()})", G, R, f)
     assert e.max() <= TOL
+    assert np.array_equal(G, R)
 
 
 @pytest.mark.parametrize("lim", [W.MC, W.MINMOD, W.KOREN, W.CADA])
