@@ -24,7 +24,9 @@
  *  - Device memory: the caller allocates ONE device workspace of
  *    amrv_workspace_bytes() bytes (e.g. a torch uint8 tensor) and keeps it
  *    alive until amrv_forest_destroy; the library allocates no device memory
- *    of its own.  The HIP stream is borrowed; all work is enqueued on it.
+ *    of its own (its one static array, the training scratch of
+ *    amrv_mlp_train_noalloc, is part of the loaded code object).  The HIP
+ *    stream is borrowed; all work is enqueued on it.
  *  - State layout: conserved binary64 U[var][leaf][z][y][x], interior cells
  *    only, leaves in the caller's order.  Hydrodynamics: var = (rho, m_x,
  *    [m_y, m_z,] E); MHD: (rho, m.., E, B.., psi); polytrope: (rho, m..).
@@ -203,6 +205,23 @@ size_t amrv_mlp_train_workspace_bytes(int32_t batch);
 int amrv_mlp_train(const uint16_t* X, const float* y, const int32_t* order, int64_t n, int32_t batch,
                    int32_t first_batch, int32_t nbatch, float* w, float* m, float* v, const amrv_train_cfg* cfg,
                    void* d_workspace, size_t ws_bytes, void* hip_stream, float* loss, float* grad);
+
+/* amrv_mlp_train without the workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving or
+ * training loops, harnesses that forbid hipMalloc).  Same arguments,
+ * arithmetic and results as amrv_mlp_train; the scratch lives in a
+ * library-held static device array of amrv_mlp_train_workspace_bytes(4096)
+ * bytes (about 6.1 MiB), one per GPU, resolved on the first call on a
+ * device and kept until the process ends.  batch <= 4096 (larger:
+ * AMRV_ENOMEM).  The call allocates nothing: no hipMalloc, no hipFree.
+ * Every call on one GPU shares that GPU's scratch and leaves its contents
+ * behind; each call overwrites every scratch value before reading it, so
+ * nothing needs clearing, but calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller.
+ * Asynchronous on the stream. */
+int amrv_mlp_train_noalloc(const uint16_t* X, const float* y, const int32_t* order, int64_t n, int32_t batch,
+                           int32_t first_batch, int32_t nbatch, float* w, float* m, float* v,
+                           const amrv_train_cfg* cfg, void* hip_stream, float* loss, float* grad);
 
 /* Regrid plan (Sec. 1.3: refinement ratio 2; a block is refined when one of
  * its cells exceeds the tolerance and coarsened when all of them lie below a

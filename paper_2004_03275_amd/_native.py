@@ -113,6 +113,8 @@ SIGNATURES = {
     "amrv_mlp_train_workspace_bytes": ([ctypes.c_int32], ctypes.c_size_t),
     "amrv_mlp_train": ([P, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P,
                         ctypes.POINTER(TrainCfg), P, ctypes.c_size_t, P, P, P], ctypes.c_int),
+    "amrv_mlp_train_noalloc": ([P, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P,
+                                ctypes.POINTER(TrainCfg), P, P, P], ctypes.c_int),
     "amrv_set_schedule": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "amrv_get_schedule": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),

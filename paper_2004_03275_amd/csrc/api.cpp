@@ -709,19 +709,46 @@ size_t amrv_mlp_train_workspace_bytes(int32_t batch) {
   return mlp_train_scratch_bytes(batch);
 }
 
-int amrv_mlp_train(const uint16_t* X, const float* y, const int32_t* order, int64_t n, int32_t batch,
-                   int32_t first_batch, int32_t nbatch, float* w, float* m, float* v, const amrv_train_cfg* cfg,
-                   void* ws, size_t ws_bytes, void* stream, float* loss, float* grad) {
-  if (!X || !y || !order || !w || !m || !v || !cfg || !ws) return fail(AMRV_EINVAL, "null argument");
+namespace {
+// argument checks shared by both training entry points
+int check_train_args(const uint16_t* X, const float* y, const int32_t* order, int64_t n, int32_t batch,
+                     int32_t first_batch, int32_t nbatch, const float* w, const float* m, const float* v,
+                     const amrv_train_cfg* cfg) {
+  if (!X || !y || !order || !w || !m || !v || !cfg) return fail(AMRV_EINVAL, "null argument");
   if (n <= 0 || n > (1 << 30)) return fail(AMRV_EINVAL, "bad sample count");
   if (batch <= 0 || batch % 32 || batch > 4096) return fail(AMRV_EINVAL, "batch must be a positive multiple of 32 <= 4096");
   const int64_t nb_total = (n + batch - 1) / batch;
   if (first_batch < 0 || nbatch < 0 || first_batch + nbatch > nb_total) return fail(AMRV_EINVAL, "batch range outside the data");
-  if (ws_bytes < mlp_train_scratch_bytes(batch)) return fail(AMRV_ENOMEM, "training workspace too small");
-  if (((uintptr_t)ws) % 256) return fail(AMRV_EINVAL, "workspace must be 256-byte aligned");
   if (!(cfg->lr >= 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) || !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) ||
       !(cfg->eps > 0.0f) || !(cfg->pos_weight > 0.0f) || cfg->t0 < 0)
     return fail(AMRV_EINVAL, "bad training hyper-parameters");
+  return AMRV_OK;
+}
+}  // namespace
+
+int amrv_mlp_train(const uint16_t* X, const float* y, const int32_t* order, int64_t n, int32_t batch,
+                   int32_t first_batch, int32_t nbatch, float* w, float* m, float* v, const amrv_train_cfg* cfg,
+                   void* ws, size_t ws_bytes, void* stream, float* loss, float* grad) {
+  int rc = check_train_args(X, y, order, n, batch, first_batch, nbatch, w, m, v, cfg);
+  if (rc) return rc;
+  if (!ws) return fail(AMRV_EINVAL, "null argument");
+  if (ws_bytes < mlp_train_scratch_bytes(batch)) return fail(AMRV_ENOMEM, "training workspace too small");
+  if (((uintptr_t)ws) % 256) return fail(AMRV_EINVAL, "workspace must be 256-byte aligned");
+  TrainHyper hp{cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, cfg->pos_weight};
+  HIPCHK(launch_mlp_train(X, y, order, (int)n, batch, first_batch, nbatch, w, m, v, hp, cfg->t0, ws, loss, grad,
+                          (hipStream_t)stream));
+  return AMRV_OK;
+}
+
+int amrv_mlp_train_noalloc(const uint16_t* X, const float* y, const int32_t* order, int64_t n, int32_t batch,
+                           int32_t first_batch, int32_t nbatch, float* w, float* m, float* v,
+                           const amrv_train_cfg* cfg, void* stream, float* loss, float* grad) {
+  int rc = check_train_args(X, y, order, n, batch, first_batch, nbatch, w, m, v, cfg);
+  if (rc) return rc;
+  if (mlp_train_scratch_bytes(batch) > MLP_STATIC_SCRATCH_BYTES)
+    return fail(AMRV_ENOMEM, "batch needs more than the library's training scratch");
+  void* ws = nullptr;
+  HIPCHK(mlp_static_scratch(&ws));
   TrainHyper hp{cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, cfg->pos_weight};
   HIPCHK(launch_mlp_train(X, y, order, (int)n, batch, first_batch, nbatch, w, m, v, hp, cfg->t0, ws, loss, grad,
                           (hipStream_t)stream));

@@ -15,6 +15,8 @@
 // Reductions run in a fixed order, so results are deterministic.
 #include <type_traits>
 
+#include <mutex>
+
 #include "internal.hpp"
 #include "mlp.hpp"
 #include "physics.hpp"
@@ -467,22 +469,7 @@ hipError_t launch_mlp_flags(const float* z, const int32_t* lvl, int n, int max_l
   return hipGetLastError();
 }
 
-size_t mlp_train_scratch_bytes(int B) {
-  size_t o = 0;
-  auto take = [&](size_t b) { o += (b + 255) / 256 * 256; };
-  take(2 * (size_t)B * MLP_NIN);  // xg
-  take(2 * (size_t)B * MLP_NIN);  // xgT
-  for (int i = 0; i < 5; i++) take(2 * (size_t)B * MLP_NH);  // h1 h1T h2 dh2 dh2T
-  take(2 * (size_t)B * MLP_NH);   // dh1T
-  take(4 * (size_t)B * MLP_NH);   // dh1
-  take(4 * (size_t)B);            // z
-  take(4 * (size_t)B);            // dz
-  take(4 * (size_t)MLP_NPARAM);   // grad
-  take(4 * (size_t)B);            // loss
-  take(2 * (size_t)MLP_WB_COUNT); // wb
-  take(16);                       // step counter
-  return o;
-}
+size_t mlp_train_scratch_bytes(int B) { return mlp_train_scratch_bytes_c(B); }
 
 static TrainScratch carve(char* ws, int B) {
   TrainScratch s;
@@ -528,6 +515,34 @@ hipError_t launch_mlp_train(const uint16_t* X, const float* Y, const int32_t* or
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();
+}
+
+// Training scratch held by the library for callers that cannot allocate
+// (amrv_mlp_train_noalloc): room for the largest batch, one copy per device
+// for the life of the process.  Host code never passes the array's name to a
+// kernel: it resolves each device's address with hipGetSymbolAddress once,
+// with that device current, and uses that address only.
+static __device__ __align__(256) char scratch[MLP_STATIC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MLP_MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t mlp_static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MLP_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace amrv

@@ -33,7 +33,24 @@ hipError_t launch_mlp_prep(const float* w, uint16_t* wb, hipStream_t st);
 hipError_t launch_mlp_infer(const uint16_t* X, int n, const uint16_t* wb, const float* w, float* z, hipStream_t st);
 hipError_t launch_mlp_flags(const float* z, const int32_t* lvl, int n, int max_level, float margin, int8_t* flags,
                             int8_t* uncertain, double* zout, hipStream_t st);
+// device scratch of one training call with batch B (256-byte aligned pieces)
+constexpr size_t mlp_align256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t mlp_train_scratch_bytes_c(int B) {
+  return 2 * mlp_align256(2 * (size_t)B * MLP_NIN)       // xg, xgT
+         + 6 * mlp_align256(2 * (size_t)B * MLP_NH)      // h1 h1T h2 dh2 dh2T dh1T
+         + mlp_align256(4 * (size_t)B * MLP_NH)          // dh1
+         + 3 * mlp_align256(4 * (size_t)B)               // z, dz, loss
+         + mlp_align256(4 * (size_t)MLP_NPARAM)          // grad
+         + mlp_align256(2 * (size_t)MLP_WB_COUNT)        // wb
+         + mlp_align256(16);                             // step counter
+}
 size_t mlp_train_scratch_bytes(int B);
+// the library-held scratch of amrv_mlp_train_noalloc: the largest batch
+constexpr int MLP_MAX_BATCH = 4096;
+constexpr size_t MLP_STATIC_SCRATCH_BYTES = mlp_train_scratch_bytes_c(MLP_MAX_BATCH);
+constexpr int MLP_MAX_DEVICES = 64;
+// this device's address of that scratch (resolved once per device)
+hipError_t mlp_static_scratch(void** out);
 hipError_t launch_mlp_train(const uint16_t* X, const float* Y, const int32_t* order, int n, int B, int first_batch,
                             int nbatch, float* w, float* am, float* av, const TrainHyper& hp, int t0, void* ws,
                             float* loss_out, float* grad_out, hipStream_t st);
