@@ -226,6 +226,9 @@ def main():
     ap.add_argument("--schedule", default=None,
                     help="fixed schedule instead of autotuning: grid, grid-noremap or persistent:<workgroups>")
     ap.add_argument("--variant", type=int, default=None, help="force the stage-kernel variant (0 or 1)")
+    ap.add_argument("--arithmetic", default="fast", choices=["fast", "exact"],
+                    help="stage-kernel arithmetic: fast (FMA, refined reciprocal estimates; within the 1e-10 bar) "
+                         "or exact (correctly rounded, bit for bit with the oracle)")
     ap.add_argument("--tune-reps", type=int, default=5)
     ap.add_argument("--host-dt", action="store_true",
                     help="time steps as amrv_max_dt + amrv_advance (host-side dt) instead of amrv_advance_cfl")
@@ -275,6 +278,7 @@ def main():
     log(f"workload {desc}: {f.n} leaves {f.level_counts()}, {cells} cells")
 
     g = F.GpuForest(f, device="cuda:0")
+    g.set_arithmetic(N.ARITH_FAST if args.arithmetic == "fast" else N.ARITH_EXACT)
     g.set_state(U0)
     dt0 = g.max_dt()
 
@@ -542,6 +546,7 @@ def main():
             "flag_every": args.flag_every,
             "schedule": {"mode": names[sched[0]], "xcd_remap": sched[1], "persistent_wgs": sched[2],
                          "stage_kernel_variant": ["combined_xy", "split_xy"][sched[3]]},
+            "arithmetic": args.arithmetic,
             "graph": bool(args.graph) or not args.host_dt,
             "time_step": "host (amrv_max_dt + amrv_advance)" if args.host_dt else "device (amrv_advance_cfl)",
         },

@@ -278,6 +278,23 @@ int amrv_get_schedule(const amrv_forest* f, int32_t* sched, int32_t* xcd_remap, 
 int amrv_set_variant(amrv_forest* f, int32_t variant);
 int amrv_get_variant(const amrv_forest* f, int32_t* variant);
 
+/* Arithmetic of the stage update.  AMRV_ARITH_EXACT (the default): every
+ * operation correctly rounded, no contraction, in the oracle's order, so
+ * results equal the oracle's bit for bit.  AMRV_ARITH_FAST: the combined-
+ * variant stage kernels of the 2D/3D hydrodynamic systems (Euler, polytrope;
+ * minmod, van Leer, MC) with multiply-adds contracted into FMAs, and
+ * division, reciprocal, square root and the sound speed sqrt(gamma p/rho)
+ * from the hardware reciprocal (square root) estimates refined by Newton
+ * steps: each within a few ulp of the correctly rounded value, the stage
+ * results within the 1e-10 relative-L1 bar of the oracle, not bit for bit.
+ * Other configurations (1D, MHD, Koren, Cada, the split variant) run exact
+ * in either mode.  Ghost prolongation, Courant reduction outside the stage
+ * kernel and Loehner flags are always exact. */
+#define AMRV_ARITH_EXACT 0
+#define AMRV_ARITH_FAST 1
+int amrv_set_arithmetic(amrv_forest* f, int32_t mode);
+int amrv_get_arithmetic(const amrv_forest* f, int32_t* mode);
+
 /* Time the candidate schedules and kernel variants on the current state
  * (first-stage kernel, state unchanged) and keep the fastest.  Synchronises. */
 int amrv_autotune(amrv_forest* f, int32_t reps);

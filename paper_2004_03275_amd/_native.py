@@ -25,6 +25,9 @@ SCHED_PER_BLOCK = 0
 SCHED_GRID = 1
 SCHED_PERSISTENT = 2
 
+ARITH_EXACT = 0
+ARITH_FAST = 1
+
 FLAG_LOHNER = 0
 FLAG_MLP = 1
 FLAG_MLP_FALLBACK = 2
@@ -119,6 +122,8 @@ SIGNATURES = {
     "amrv_get_schedule": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "amrv_set_variant": ([P, ctypes.c_int32], ctypes.c_int),
+    "amrv_set_arithmetic": ([P, ctypes.c_int32], ctypes.c_int),
+    "amrv_get_arithmetic": ([P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "amrv_get_variant": ([P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "amrv_autotune": ([P, ctypes.c_int32], ctypes.c_int),
     "amrv_autotune_report": ([P], ctypes.c_char_p),

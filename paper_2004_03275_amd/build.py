@@ -30,7 +30,10 @@ HIPFLAGS = [
 # extra flags per unit: the combined-variant stage kernels, which run two
 # waves per SIMD (register-bound), gain ~3% per launch from the
 # ILP-maximising scheduler (the other stage kernels lose)
-UNITS = {"stage_ilp.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
+UNITS = {"stage_ilp.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+         # the same kernels in fast arithmetic: contraction on (the flag after
+         # the common -ffp-contract=off wins)
+         "stage_fast.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp", "-ffp-contract=fast"]}
 
 
 def _jobs() -> int:

@@ -433,6 +433,7 @@ int amrv_forest_create(const amrv_config* cfg, int64_t n, const int32_t* lev, co
   f->lc.flux = cfg->flux;
   f->lc.lim = cfg->limiter;
   f->lc.variant = 0;
+  f->lc.arith = AMRV_ARITH_EXACT;
 
   auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
     if (!bytes) return hipSuccess;
@@ -846,6 +847,20 @@ int amrv_set_variant(amrv_forest* f, int32_t variant) {
   return AMRV_OK;
 }
 
+int amrv_set_arithmetic(amrv_forest* f, int32_t mode) {
+  if (!f) return fail(AMRV_EINVAL, "null forest");
+  if (mode != AMRV_ARITH_EXACT && mode != AMRV_ARITH_FAST) return fail(AMRV_EINVAL, "unknown arithmetic mode");
+  f->lc.arith = mode;
+  drop_graph(f);
+  return AMRV_OK;
+}
+
+int amrv_get_arithmetic(const amrv_forest* f, int32_t* mode) {
+  if (!f || !mode) return fail(AMRV_EINVAL, "null argument");
+  *mode = f->lc.arith;
+  return AMRV_OK;
+}
+
 int amrv_get_variant(const amrv_forest* f, int32_t* variant) {
   if (!f || !variant) return fail(AMRV_EINVAL, "null argument");
   *variant = f->lc.variant;
@@ -870,8 +885,12 @@ int amrv_autotune(amrv_forest* f, int32_t reps) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  // time the first-stage pass U^n -> U^(1): it writes only the stage buffer,
-  // so the state is untouched (dt must be > 0: dt = 0 marks a finished run)
+  // time the first stage U^n -> U^(1) as a step runs it (coarse-fine
+  // pre-pass, with the separate restriction where the kernel does not fuse
+  // it, and the stage update, writing the fused restriction into ghost-slab
+  // buffer 1 as stage 1 does); it writes only the stage buffer and ghost
+  // slabs, so the state is untouched (dt must be > 0: dt = 0 marks a
+  // finished run)
   int rc = set_scalars(f, PP_DT, {1.0e-12, 1.0});
   double best = 1e300;
   std::string report;
@@ -882,6 +901,7 @@ int amrv_autotune(amrv_forest* f, int32_t reps) {
     f->xcd = c.xcd;
     f->pwgs = c.pwgs;
     f->lc.variant = c.var;
+    const bool fused = fused_restriction(f);
     StageArgs a{};
     a.Uin = f->U[0];
     a.Un = f->U[0];
@@ -889,6 +909,7 @@ int amrv_autotune(amrv_forest* f, int32_t reps) {
     a.dtp = f->pp + PP_DT;
     a.stage = 1;
     a.rk = f->cfg.rk_stages;
+    a.Gw = fused ? f->Gb[1] : nullptr;
     std::vector<float> ts;
     for (int r = 0; r < reps + 1 && !rc; r++) {
       if (c.sched == AMRV_SCHED_PERSISTENT) {
@@ -896,6 +917,7 @@ int amrv_autotune(amrv_forest* f, int32_t reps) {
         if (e != hipSuccess) rc = hip_fail(e, "reset");
       }
       (void)hipEventRecord(e0, f->st);
+      if (!rc) rc = enqueue_ghosts(f, f->geo, f->U[0], true, !fused);
       if (!rc) rc = enqueue_stage_update(f, f->geo, a, c.sched);
       (void)hipEventRecord(e1, f->st);
       (void)hipEventSynchronize(e1);

@@ -75,6 +75,7 @@ enum { PH_EULER = 0, PH_MHD = 1, PH_POLY = 2 };
 struct LaunchCfg {
   int ndim, phys, flux, lim;  // phys: PH_EULER, PH_MHD or PH_POLY
   int variant;  // stage kernel: 0 combined x/y phases, 1 split x then y
+  int arith;    // 0 correctly rounded (default), 1 fast arithmetic where the stage kernel has that form
 };
 
 hipError_t launch_restrict(const Geo& g, const LaunchCfg& c, const double* U, const int32_t* list, int nlist,

@@ -6,6 +6,13 @@
 // GLM scalar psi.  Fluxes: TVDLF (Rusanov), HLL, HLLC (Sec. 1.2, Sec. 2.4),
 // all with the textbook formulas; the expression order below is fixed so that
 // every result is reproducible bit for bit (built with -ffp-contract=off).
+//
+// Division, reciprocal, square root and the sound speed of the hydrodynamic
+// systems go through ddiv, drcp, dsqrt and dsound.  They are the correctly
+// rounded operations, except in the fast-arithmetic unit (AMRV_FAST_MATH,
+// stage_fast.hip, built with contraction on), where they come from the
+// hardware reciprocal and reciprocal square root refined by Newton steps:
+// each result within a few ulp of the correctly rounded one.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -38,6 +45,46 @@ struct Sys {
   static constexpr int IB = 2 + ND;   // first magnetic component
   static constexpr int IP = 2 + 2 * ND;  // psi
 };
+
+#ifdef AMRV_FAST_MATH
+// 1/b: hardware reciprocal, then two Newton steps y += y (1 - b y)
+__device__ __forceinline__ double drcp(double b) {
+  double y = __builtin_amdgcn_rcp(b);
+  y = __builtin_fma(y, __builtin_fma(-b, y, 1.0), y);
+  y = __builtin_fma(y, __builtin_fma(-b, y, 1.0), y);
+  return y;
+}
+// a/b: a times the refined reciprocal, then one residual correction
+// q += y (a - b q) (Markstein's final step)
+__device__ __forceinline__ double ddiv(double a, double b) {
+  const double y = drcp(b);
+  const double q = a * y;
+  return __builtin_fma(y, __builtin_fma(-b, q, a), q);
+}
+// x^(-1/2) for x > 0: hardware estimate, then two Newton steps
+// y += (y/2)(1 - x y^2)
+__device__ __forceinline__ double drsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = __builtin_fma(0.5 * y, __builtin_fma(-x * y, y, 1.0), y);
+  y = __builtin_fma(0.5 * y, __builtin_fma(-x * y, y, 1.0), y);
+  return y;
+}
+// sqrt(x) for x > 0: g = x y with y ~ x^(-1/2), then the residual
+// correction g += (y/2)(x - g^2)
+__device__ __forceinline__ double dsqrt(double x) {
+  const double y = drsq(x);
+  const double g = x * y;
+  return __builtin_fma(0.5 * y, __builtin_fma(-g, g, x), g);
+}
+// sqrt(gp / rho) = gp (gp rho)^(-1/2): one reciprocal square root instead of
+// a division and a square root
+__device__ __forceinline__ double dsound(double gp, double rho) { return gp * drsq(gp * rho); }
+#else
+__device__ __forceinline__ double drcp(double b) { return 1.0 / b; }
+__device__ __forceinline__ double ddiv(double a, double b) { return a / b; }
+__device__ __forceinline__ double dsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ double dsound(double gp, double rho) { return sqrt(gp / rho); }
+#endif
 
 __device__ __forceinline__ double dmin(double a, double b) { return a < b ? a : b; }
 __device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
@@ -76,7 +123,7 @@ template <int ND, int PH>
 __device__ __forceinline__ void cons2prim(const double* u, double* v, const PhysParams& P) {
   using S = Sys<ND, PH>;
   const double rho = u[0];
-  const double inv = 1.0 / rho;
+  const double inv = drcp(rho);
   double mm = u[1] * u[1];
   v[0] = rho;
   v[1] = u[1] * inv;
@@ -180,9 +227,9 @@ template <int ND, int PH, int N>
 __device__ __forceinline__ double wave_speed(const double* v, const PhysParams& P) {
   using S = Sys<ND, PH>;
   if constexpr (PH == PH_POLY) {
-    return sqrt(P.gcad * rpow(v[0], P.gm1));
+    return dsqrt(P.gcad * rpow(v[0], P.gm1));
   } else if constexpr (PH == PH_EULER) {
-    return sqrt(P.gamma * v[S::IE] / v[0]);
+    return dsound(P.gamma * v[S::IE], v[0]);
   } else {
     const double irho = 1.0 / v[0];
     double bb = v[S::IB] * v[S::IB];
@@ -243,11 +290,11 @@ __device__ __forceinline__ double limiter(double a, double b, double thr2 = 0.0)
     return fabs(a) < fabs(b) ? a : b;
   } else if constexpr (LIM == LIM_MC || LIM == LIM_KOREN) {
     const double ta = 2.0 * a, tb = 2.0 * b;
-    const double c = LIM == LIM_MC ? 0.5 * (a + b) : (a + 2.0 * b) / 3.0;
+    const double c = LIM == LIM_MC ? 0.5 * (a + b) : ddiv(a + 2.0 * b, 3.0);
     const double m = fabs(ta) < fabs(tb) ? ta : tb;
     return fabs(c) < fabs(m) ? c : m;
   } else {
-    return 2.0 * a * b / (a + b);
+    return ddiv(2.0 * a * b, a + b);
   }
 }
 
@@ -273,7 +320,7 @@ __device__ __forceinline__ void hllc_flux(const double* vl, const double* vr, do
   const double pl = vl[ie], pr = vr[ie];
   const double rl = vl[0] * (sl - unl);
   const double rr = vr[0] * (sr - unr);
-  const double sm = ((pr - pl) + unl * rl - unr * rr) / (rl - rr);
+  const double sm = ddiv((pr - pl) + unl * rl - unr * rr, rl - rr);
   const bool left = sl >= 0.0 || sm >= 0.0;
   const bool star = !(sl >= 0.0) && (sm >= 0.0 || sr > 0.0);
   double vk[NV];
@@ -289,7 +336,7 @@ __device__ __forceinline__ void hllc_flux(const double* vl, const double* vr, do
     const double sk = left ? sl : sr;
     const double rk = left ? rl : rr;
     const double unk = vk[1 + N], pk = vk[ie];
-    const double inv = 1.0 / (sk - sm);
+    const double inv = drcp(sk - sm);
     const double coef = rk * inv;
     const double ps = pk + rk * (sm - unk);
     double us[NV];
@@ -436,7 +483,7 @@ __device__ __forceinline__ void riemann(double* vl, double* vr, double* F, const
 #pragma unroll
         for (int k = 0; k < NV; k++) F[k] = fr[k];
       } else {
-        const double ids = 1.0 / (sr - sl);
+        const double ids = drcp(sr - sl);
 #pragma unroll
         for (int k = 0; k < NV; k++) F[k] = ((sr * fl[k] - sl * fr[k]) + (sl * sr) * (ur[k] - ul[k])) * ids;
       }

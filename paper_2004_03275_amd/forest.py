@@ -180,6 +180,15 @@ class GpuForest:
         N.check(N.lib().amrv_get_variant(self._h, ctypes.byref(v)))
         return v.value
 
+    def set_arithmetic(self, mode: int):
+        """N.ARITH_EXACT (bit-for-bit with the oracle) or N.ARITH_FAST."""
+        N.check(N.lib().amrv_set_arithmetic(self._h, int(mode)))
+
+    def get_arithmetic(self) -> int:
+        v = ctypes.c_int32()
+        N.check(N.lib().amrv_get_arithmetic(self._h, ctypes.byref(v)))
+        return v.value
+
     def autotune(self, reps: int = 3):
         """Pick the fastest schedule and stage-kernel variant; returns
         (schedule, xcd_remap, persistent_wgs, variant)."""
@@ -237,12 +246,14 @@ def courant_ramp(step: int, ramp_steps: int) -> float:
 
 
 def run(forest, U0, *, t_end=None, steps=None, dts=None, schedule=None, graph=False, device="cuda:0",
-        variant=None, device_dt=False, chunk=50, ramp_steps=0):
+        variant=None, device_dt=False, chunk=50, ramp_steps=0, arithmetic=None):
     """Drive the GPU forest like oracle.run: free Courant steps to t_end, a
     fixed step count, or a given dt sequence; ramp_steps > 0 scales the first
     Courant steps by courant_ramp (host-chosen steps only).
     Returns (state, dts used)."""
     g = GpuForest(forest, device=device)
+    if arithmetic is not None:
+        g.set_arithmetic(arithmetic)
     if schedule is not None:
         g.set_schedule(*schedule)
     if variant is not None:

@@ -104,40 +104,62 @@ def test_blast_full_size_two_steps_and_flags():
 
 
 def test_blast_timed_path_20_steps():
-    """The configuration the headline MCUPS is measured in, against the oracle."""
+    """The configuration the headline MCUPS is measured in, against the oracle,
+    in both arithmetic modes: exact (bit for bit) and fast (the bench's mode,
+    relative L1 <= 1e-10, identical flags)."""
+    from paper_2004_03275_amd import _native as N
     from paper_2004_03275_amd.forest import GpuForest
 
     f, U = W.blast(W.blast_scheme())
-    g = GpuForest(f)
-    g.set_state(U)
-    sched = g.autotune(5)
-    g.use_graph(True)
-    print(f"[full] timed path: {f.n} leaves, schedule {sched}", flush=True)
+    gs = {}
+    for mode in (N.ARITH_EXACT, N.ARITH_FAST):
+        g = GpuForest(f)
+        g.set_arithmetic(mode)
+        g.set_state(U)
+        sched = g.autotune(5)
+        g.use_graph(True)
+        gs[mode] = [g, 0.0]
+        print(f"[full] timed path arithmetic {mode}: {f.n} leaves, schedule {sched}", flush=True)
     o = oracle.OracleForest(f)
     o.set_state(U)
-    tg = to = 0.0
+    to = 0.0
     t0 = time.time()
     for chunk in range(1, 5):
-        tg, taken = g.advance_cfl(5, float("inf"), tg)
-        assert taken == 5
+        for mode, gt in gs.items():
+            gt[1], taken = gt[0].advance_cfl(5, float("inf"), gt[1])
+            assert taken == 5
         for _ in range(5):
             dt = o.max_dt()
             o.advance(dt)
             to += dt
         step = 5 * chunk
-        assert tg == to, (step, tg, to)
-        G, R = g.get_state(), o.get_state()
-        e = W.relative_l1(G, R, f).max()
-        same = bool(np.array_equal(G, R))
-        print(f"[full] timed path step {step}: t {tg:.6e}, rel L1 {e:.3e}, bitwise {same} "
-              f"({time.time() - t0:.0f} s)", flush=True)
-        assert e <= TOL and same, (step, e)
-        del G, R
+        R = o.get_state()
+        for mode, (g, tg) in gs.items():
+            G = g.get_state()
+            e = W.relative_l1(G, R, f).max()
+            same = bool(np.array_equal(G, R))
+            print(f"[full] timed path arithmetic {mode} step {step}: t {tg:.15e} (oracle {to:.15e}), rel L1 {e:.3e}, "
+                  f"bitwise {same} ({time.time() - t0:.0f} s)", flush=True)
+            assert e <= TOL, (mode, step, e)
+            if mode == N.ARITH_EXACT:
+                assert tg == to and same, (step, e)
+            else:
+                assert abs(tg - to) <= 1e-12 * to
+            del G
+        del R
         if step % 10 == 0:
-            fg, eg = g.flag_blocks(with_emax=True)
             fo, eo = o.flag_blocks(with_emax=True)
-            print(f"[full] timed path flags at step {step}: refine {int(np.sum(fo == 1))}, "
-                  f"coarsen {int(np.sum(fo == -1))}; identical {np.array_equal(fg, fo)}", flush=True)
-            assert np.array_equal(fg, fo) and np.array_equal(eg, eo)
-    g.close()
+            for mode, (g, _) in gs.items():
+                fg, eg = g.flag_blocks(with_emax=True)
+                de = float(np.max(np.abs(eg - eo)))
+                print(f"[full] timed path arithmetic {mode} flags at step {step}: refine {int(np.sum(fo == 1))}, "
+                      f"coarsen {int(np.sum(fo == -1))}; identical {np.array_equal(fg, fo)}, max |emax diff| {de:.2e}",
+                      flush=True)
+                assert np.array_equal(fg, fo)
+                if mode == N.ARITH_EXACT:
+                    assert np.array_equal(eg, eo)
+                else:
+                    assert de <= 1e-10
+    for g, _ in gs.values():
+        g.close()
     o.close()
