@@ -88,7 +88,7 @@ def make_workload(name: str):
     return desc, f, U
 
 
-RD_PAPER_MS = {"imex": 7.7, "split": 7.2, "explicit": 1.1}  # Sec. 3.4: 256^2 Schnakenberg, 4 CPU cores
+RD_PAPER_MS = {"imex": 7.7, "split": 7.2, "explicit": 1.1}  # Sec. 2.5.2: 256^2 Schnakenberg, 4 CPU cores
 
 
 def rd_vcycle_bytes(nd: int, n: int, nfields: int = 2) -> float:
@@ -108,7 +108,7 @@ def rd_vcycle_bytes(nd: int, n: int, nfields: int = 2) -> float:
 
 def rd_measure(nd: int, n: int, steps: int, warmup: int, log, cpu: bool = True, dt: float = 1e-3,
                tol: float = 1e-7) -> dict:
-    """The paper's reaction-diffusion workload (Sec. 3.4): Schnakenberg on an
+    """The paper's reaction-diffusion workload (Sec. 2.5.2): Schnakenberg on an
     n^nd uniform grid with zero Neumann boundaries, dt = 1e-3, multigrid to
     max residual <= tol max|f|; IMEX, split and explicit Euler steps timed
     with the state resident in HBM, one IMEX step checked against the oracle

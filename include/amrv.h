@@ -61,8 +61,8 @@ extern "C" {
 #define AMRV_VANLEER 1
 #define AMRV_MC 2 /* monotonized central ('woodward', Sec. 2.3.1) */
 #define AMRV_KOREN 3 /* Koren (Sec. 2.2, 2.3.2); runs the split stage-kernel variant */
-#define AMRV_CADA 4  /* Cada's third order (Sec. 2.4 blast runs; LimO3 of Cada and Torrilhon 2009,
-                        without its smoothness switch); split variant */
+#define AMRV_CADA 4  /* Cada's third order (Sec. 2.4 blast runs; LimO3 of Cada and Torrilhon 2009;
+                        its smoothness switch with cada_radius > 0); split variant */
 #define AMRV_BC_PERIODIC 0
 #define AMRV_BC_ZERO_GRADIENT 1
 

@@ -1,8 +1,8 @@
 /* amrv_mg.h -- C-ABI of libamrv's geometric multigrid Helmholtz solver and
  * the reaction-diffusion time steps built on it.
  *
- * Method (arXiv 2004.03275): the multigrid functionality of Sec. 2.3 solves
- * Poisson/Helmholtz problems; Sec. 3.4 uses it for the reaction-diffusion
+ * Method (arXiv 2004.03275): the multigrid functionality of Sec. 1.4 solves
+ * Poisson/Helmholtz problems; Sec. 2.5 uses it for the reaction-diffusion
  * models (Eqs. gray-scott and schnakenberg): the split scheme's backward-
  * Euler diffusion step leads to the Helmholtz problem of Eq. diff-helmholtz,
  * and the first stage of the IMEX scheme (Eq. imex, the trapezoidal pair) to
@@ -23,7 +23,7 @@
  * prolongation by bi/trilinear interpolation, coarse grids rediscretised
  * down to 2 cells per side and solved exactly there) until the maximum
  * residual |f - (lap(phi) - lambda phi)| is at most tol times max |f| -- the
- * paper's stopping rule, Sec. 3.4, with tol = 1e-7 there.  Since lambda I - lap is an M-matrix
+ * paper's stopping rule, Sec. 2.5.2, with tol = 1e-7 there.  Since lambda I - lap is an M-matrix
  * whose rows sum to lambda, the returned solution differs from the exact
  * discrete one by at most (max residual) / lambda in every cell (lambda = 0:
  * up to a constant, by at most sqrt(cells) (max residual) / mu_1 with mu_1
@@ -102,7 +102,7 @@ size_t amrv_mg_workspace_bytes(const amrv_mg_config* cfg);
 int amrv_mg_create(const amrv_mg_config* cfg, void* workspace, size_t bytes, void* stream, amrv_mg** out);
 int amrv_mg_destroy(amrv_mg* m);
 
-/* Solves lap(phi) - lambda phi = f (Sec. 2.3, Eq. diff-helmholtz) for
+/* Solves lap(phi) - lambda phi = f (Sec. 1.4; Sec. 2.5.1, Eq. diff-helmholtz) for
  * nfields fields stored one after another (f and phi: nfields * n^ndim
  * doubles each, device; phi holds the initial guess on entry and the
  * solution on return; lambda: nfields host values, each >= 0; with
@@ -115,7 +115,7 @@ int amrv_mg_destroy(amrv_mg* m);
 int amrv_mg_solve(amrv_mg* m, const double* f, double* phi, const double* lambda, double tol, int32_t max_cycles,
                   int32_t* cycles, double* res_max, double* f_max);
 
-/* Variable coefficient (Sec. 2.3: Helmholtz problems with variable
+/* Variable coefficient (Sec. 1.4: Helmholtz problems with variable
  * coefficients): with eps != NULL (device, n^ndim doubles, each > 0; copied)
  * later amrv_mg_solve calls solve div(eps grad phi) - lambda phi = f, the
  * coefficient of a face the arithmetic mean of its two cells (none across a
@@ -139,7 +139,7 @@ int amrv_mg_set_coefficient(amrv_mg* m, const double* eps);
 int amrv_mg_divb_project(amrv_mg* m, double* bx, double* by, double* bz, double tol, int32_t max_cycles,
                          int32_t* cycles, double* div_before, double* div_after);
 
-/* nsteps time steps of the reaction-diffusion model (Sec. 3.4) on the
+/* nsteps time steps of the reaction-diffusion model (Sec. 2.5) on the
  * device fields u, v (n^ndim doubles each, updated in place) with step dt
  * and the given scheme.  SPLIT and IMEX need a solver created with
  * nfields = 2: both species' Helmholtz problems are solved together, each

@@ -460,9 +460,8 @@ static void riemann(const orc_forest* f, const double* vl_in, const double* vr_i
  * without the division: for b > 0 every candidate of H times b is a
  * candidate in a and b (p3 b = (a + 2b)/3), and b < 0 follows from
  * s(-a, -b) = -s(a, b); b = 0 gives 0 (H is bounded), and so does a = 0
- * (H(0) = 0).  The smoothness switch
- * of that paper (unlimited p3 where the differences are small against a
- * radius times the cell size) is not applied: the radius -> 0 case. */
+ * (H(0) = 0).  The smoothness switch above applies only for thr2 > 0
+ * (cada_radius > 0); with thr2 = 0 the limited function is used alone. */
 static double smaller(double x, double y) { return y < x ? y : x; }
 static double larger(double x, double y) { return y > x ? y : x; }
 

@@ -1,8 +1,8 @@
 """CPU reference of the elliptic solve and the reaction-diffusion schemes.
 
 TEST INFRASTRUCTURE ONLY (tests/, smoke, bench's CPU leg).  Written from the
-paper's multigrid and reaction-diffusion sections (Sec. 2.3 on multigrid,
-Sec. 2.4 on its divergence control of the MHD runs, Sec. 3.4: Eqs.
+paper's multigrid and reaction-diffusion sections (Sec. 1.4 on multigrid,
+Sec. 2.4 on its divergence control of the MHD runs, Sec. 2.5 and 2.5.1: Eqs.
 gray-scott, schnakenberg, diff-helmholtz and imex, Table 1), sharing nothing
 with the HIP path.
 
@@ -18,7 +18,7 @@ added in the order x, y, z, with 1/h^2 formed as (n/L) * (n/L).
 Helmholtz problem (Eq. diff-helmholtz): lap(phi) - lambda phi = f, lambda > 0;
 Poisson (lambda = 0) for the divergence control of the MHD runs (Sec. 2.4),
 whose solution is fixed up to a constant (the zero-mean one here).  With a
-variable coefficient (Sec. 2.3): div(eps grad phi) - lambda phi = f, eps > 0
+variable coefficient (Sec. 1.4): div(eps grad phi) - lambda phi = f, eps > 0
 per cell, face coefficients the arithmetic mean of the two cells, solved by
 a sparse direct solve; still an M-matrix with row sums lambda.
 This module solves it exactly (to rounding): the operator is diagonalised by
@@ -54,7 +54,7 @@ PERIODIC, NEUMANN = 0, 1
 SCHNAKENBERG, GRAY_SCOTT = 0, 1
 EULER, MIDPOINT, SPLIT, IMEX = 0, 1, 2, 3
 
-# Sec. 3.4: Schnakenberg parameters (Du, Dv, kappa, a, b) and Gray-Scott
+# Sec. 2.5: Schnakenberg parameters (Du, Dv, kappa, a, b) and Gray-Scott
 # (Du, Dv, F, k)
 SCHNAKENBERG_PARAMS = dict(model=SCHNAKENBERG, Du=0.05, Dv=1.0, p1=100.0, p2=0.1305, p3=0.7695)
 GRAY_SCOTT_PARAMS = dict(model=GRAY_SCOTT, Du=2e-5, Dv=1e-5, p1=0.046, p2=0.063, p3=0.0)
@@ -135,7 +135,7 @@ def _face_sums(phi, eps, length: float, bc: int):
 
 def helmholtz_var_apply(phi, eps, lam: float, length: float, bc: int):
     """div(eps grad phi) - lambda phi, the variable-coefficient Helmholtz
-    operator of the multigrid (Sec. 2.3)."""
+    operator of the multigrid (Sec. 1.4)."""
     return _face_sums(phi, eps, length, bc) - lam * phi
 
 
@@ -276,5 +276,5 @@ def run(u, v, dt: float, nsteps: int, scheme: int, p: dict, length: float, bc: i
 
 
 def explicit_dt_limit(h: float, ndim: int, d_max: float) -> float:
-    """Stability bound of explicit diffusion (Sec. 3.4): h^2 / (2 N_dim D_max)."""
+    """Stability bound of explicit diffusion (Sec. 2.5.1, Table 1): h^2 / (2 N_dim D_max)."""
     return h * h / (2.0 * ndim * d_max)

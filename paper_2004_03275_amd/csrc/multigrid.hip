@@ -1,7 +1,7 @@
 // multigrid.hip -- geometric multigrid Helmholtz solver on one uniform
 // cell-centred grid and the reaction-diffusion time steps built on it
-// (declared in include/amrv_mg.h; the method's multigrid of Sec. 2.3 and the
-// reaction-diffusion schemes of Sec. 3.4).
+// (declared in include/amrv_mg.h; the method's multigrid of Sec. 1.4 and the
+// reaction-diffusion schemes of Sec. 2.5).
 //
 // Layout in the caller's workspace (every array 256-byte aligned):
 //   phi[field][level], f[field][level]   n_l^d doubles each, n_l = n >> l,
@@ -838,7 +838,7 @@ __global__ void __launch_bounds__(256) k_mg_divnorm(MgDev g, const double* b0, c
   fold_norms(g, 0, m, 0ull, 0);
 }
 
-// ---- reaction-diffusion (Sec. 3.4) ---------------------------------------
+// ---- reaction-diffusion (Sec. 2.5) ---------------------------------------
 
 __device__ __forceinline__ void react(const RdK& p, double u, double v, double& ru, double& rv) {
   if (p.model == AMRV_RD_SCHNAKENBERG) {

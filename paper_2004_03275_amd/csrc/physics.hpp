@@ -261,7 +261,7 @@ __device__ __forceinline__ double wave_speed_dir(const double* v, int n, const P
 // 2ab/(a+b)), monotonized central (smallest magnitude of 2a, (a+b)/2, 2b),
 // Koren (smallest of 2a, (a+2b)/3, 2b); zero at extrema.  All but Koren are
 // symmetric in a and b, bit for bit.  Cada's third-order limiter (LimO3 of
-// Cada and Torrilhon 2009, without its smoothness switch) is b H(a/b) with
+// Cada and Torrilhon 2009) is b H(a/b) with
 // H(t) = max(0, min(p3, max(-t/2, min(2t, p3, 1.6)))), p3 = (2 + t)/3: for
 // b > 0 the candidates scale by b exactly, b < 0 is the odd mirror, b = 0
 // gives 0, as does a = 0; it keeps a slope at extrema (-2 < a/b < 0).  With

@@ -142,7 +142,7 @@ def test_implicit_steps_match_the_exact_solves(model, nd, n, dt, steps, scheme):
 
 
 def test_paper_tolerance_step_is_close_to_the_exact_step():
-    """At the paper's tol = 1e-7 (Sec. 3.4) one IMEX step of the 256^2
+    """At the paper's tol = 1e-7 (Sec. 2.5.2) one IMEX step of the 256^2
     Schnakenberg run stays within the residual bound propagated through the
     second stage."""
     torch, M = _mg()
@@ -369,7 +369,7 @@ def test_divb_projection_rejects_unsupported_setups():
         mg.close()
 
 
-# -- variable coefficient (Sec. 2.3) ------------------------------------------
+# -- variable coefficient (Sec. 1.4) ------------------------------------------
 
 def _eps_field(nd, n, kind):
     xs = W.rd_cell_centres(nd, n, 1.0)

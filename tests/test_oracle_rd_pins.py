@@ -1,5 +1,5 @@
 """Pins of the oracle's elliptic solve and reaction-diffusion schemes
-(Sec. 2.3 multigrid, Sec. 3.4 reaction-diffusion; oracle/rd.py).
+(Sec. 1.4 multigrid, Sec. 2.5 reaction-diffusion; oracle/rd.py).
 
 * The discrete Laplacian is pinned on a whole basis: every Fourier mode
   (periodic) and every cosine mode (Neumann) of small grids is an
@@ -195,7 +195,7 @@ def schnakenberg_16():
     (R.EULER, (4e-5, 2e-5, 1e-5), 0.9, 1.1),
 ])
 def test_time_order_against_a_stiff_integrator(schnakenberg_16, scheme, dts, lo, hi):
-    """The paper's comparison (Sec. 3.4, Fig. schnakenberg-conv): IMEX
+    """The paper's comparison (Sec. 2.5.2, Fig. schnakenberg-conv): IMEX
     second order, the split scheme at most first order."""
     u0, v0, L, p, t, (ur, vr) = schnakenberg_16
     errs = []
@@ -309,7 +309,7 @@ def test_projection_removes_a_smooth_gradient_at_second_order():
     assert max(ratios) < 1e-2, ratios
 
 
-# -- variable coefficient (Sec. 2.3) ------------------------------------------
+# -- variable coefficient (Sec. 1.4) ------------------------------------------
 
 def test_variable_coefficient_reduces_to_the_constant_one():
     rng = np.random.default_rng(11)

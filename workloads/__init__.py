@@ -574,7 +574,7 @@ def mlp_random_features(seed: int, n: int) -> np.ndarray:
     return bits, y
 
 
-# -- reaction-diffusion on uniform grids (Sec. 3.4) -------------------------
+# -- reaction-diffusion on uniform grids (Sec. 2.5) -------------------------
 
 def rd_cell_centres(ndim: int, n: int, length: float) -> list:
     """Cell-centre coordinates (x, y[, z]) of an n^ndim grid on [0, L]^ndim,
@@ -585,7 +585,7 @@ def rd_cell_centres(ndim: int, n: int, length: float) -> list:
 
 
 def schnakenberg_initial(ndim: int = 2, n: int = 256, a: float = 0.1305, b: float = 0.7695):
-    """Sec. 3.4: v = b/(a+b)^2, u = a + b + exp(-100 |r - r0|^2) on the unit
+    """Sec. 2.5.2: v = b/(a+b)^2, u = a + b + exp(-100 |r - r0|^2) on the unit
     square/cube, r0 = (1/3, 1/2[, 1/2]).  Returns (u, v, L = 1)."""
     xs = rd_cell_centres(ndim, n, 1.0)
     r0 = (1.0 / 3.0, 0.5, 0.5)
@@ -596,7 +596,7 @@ def schnakenberg_initial(ndim: int = 2, n: int = 256, a: float = 0.1305, b: floa
 
 
 def gray_scott_initial(n: int = 256):
-    """Sec. 3.4: the steady state u = 1, v = 0 with two Gaussians
+    """Sec. 2.5.2: the steady state u = 1, v = 0 with two Gaussians
     0.5 exp(-25 |r - r_i|^2), r_1 = (0.5, 0.5), r_2 = (0.55, 0.6),
     subtracted from u and added to v, on the periodic square of side 2.
     Returns (u, v, L = 2)."""
