@@ -63,7 +63,7 @@ def make_workload(name: str):
 
     if name == "blast":
         s = W.blast_scheme()
-        f, U = W.blast(s)
+        f, U = W.blast(s, forest=W.blast_lohner_forest(s))
         desc = "3d_amr_blast"
     elif name == "kh":
         f, U = W.kh(16)

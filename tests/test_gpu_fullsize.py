@@ -80,7 +80,8 @@ def test_orszag_tang_full_to_t05():
 
 
 def test_blast_full_size_two_steps_and_flags():
-    f, U = W.blast(W.blast_scheme())
+    s = W.blast_scheme()
+    f, U = W.blast(s, forest=W.blast_lohner_forest(s))
     g, o = _pair(f, U)
     for step in (1, 2):
         dg, do = g.max_dt(), o.max_dt()
@@ -110,7 +111,8 @@ def test_blast_timed_path_20_steps():
     from paper_2004_03275_amd import _native as N
     from paper_2004_03275_amd.forest import GpuForest
 
-    f, U = W.blast(W.blast_scheme())
+    s = W.blast_scheme()
+    f, U = W.blast(s, forest=W.blast_lohner_forest(s))
     gs = {}
     for mode in (N.ARITH_EXACT, N.ARITH_FAST):
         g = GpuForest(f)

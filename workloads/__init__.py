@@ -4,8 +4,10 @@ This package holds no step of the finite-volume method: it builds block
 forests (leaf lists with 2:1 balance, Morton order) and initial conditions in
 conserved variables, the scheme parameters of each workload, and the relative
 L1 difference used to compare two states.  It imports neither the product
-package nor the oracle, and neither of those imports it: tests, the smoke
-check and the bench hand its forests and states to both.
+package nor the oracle: tests, the smoke check and the bench hand its forests
+and states to both.  One stored input, the leaf list of the 3D AMR blast
+refined by the Loehner estimator (data/blast_lohner_forest.npz), was written
+by oracle/lohner_forest.py.
 
 Workloads (the paper's MPI-AMRVAC, arXiv 2004.03275, runs the solver it names
 on block forests, Sec. 1.3; the configurations below are synthetic stand-ins
@@ -435,6 +437,21 @@ def blast_forest(scheme: Scheme, radius: float = 0.1, centre=(0.0, 0.0, 0.0), bu
         return _box_shell_hit(lo, lo + h, centre[:nd], radius, float(buffer_cells * dx.max()))
 
     return refined_forest(s, refine)
+
+
+DATA = __import__("os").path.join(__import__("os").path.dirname(__file__), "data")
+
+
+def blast_lohner_forest(scheme: Scheme | None = None) -> Forest:
+    """The 3D AMR blast's forest (16^3 base blocks of 16^3 cells, 4 levels)
+    refined where the Loehner estimator flags its initial state, with an
+    8-cell buffer and 2:1 balance: the stored leaf list written by
+    oracle/lohner_forest.py (19,384 leaves)."""
+    s = scheme or blast_scheme()
+    if s.ndim != 3 or s.base_blocks != (16, 16, 16) or s.max_level != 4 or s.block_nx != (16, 16, 16):
+        raise ValueError("the stored Loehner forest is the 16^3-base, 4-level blast")
+    with np.load(__import__("os").path.join(DATA, "blast_lohner_forest.npz")) as d:
+        return Forest(s, d["level"].astype(np.int32), d["ijk"].astype(np.int32))
 
 
 def blast(scheme: Scheme | None = None, radius: float = 0.1, p_in: float = 100.0, p_out: float = 0.1,
