@@ -422,15 +422,17 @@ def main():
 
         try:
             wts = MLP.trained_weights()
-        except (OSError, ValueError):
+            margin = MLP.trained_margin()
+        except (OSError, ValueError, KeyError):
             wts = None
         if wts is not None:
             g.set_schedule(*sched[:3])
             g.mlp_set_weights(wts)
-            g.mlp_set_margin(2.0)
+            g.mlp_set_margin(margin)
             fl, emax = g.flag_blocks(with_emax=True)
-            fm, z = g.flag_blocks(with_emax=True, mode=N.FLAG_MLP)
+            fm = g.flag_blocks(mode=N.FLAG_MLP)
             ff = g.flag_blocks(mode=N.FLAG_MLP_FALLBACK)
+            z = g.mlp_logits()
 
             def tflag(mode, reps=5):
                 g.synchronize()
@@ -440,13 +442,34 @@ def main():
                 return (time.perf_counter() - t0) / reps * 1e3
 
             tl, tm, tf = tflag(N.FLAG_LOHNER), tflag(N.FLAG_MLP), tflag(N.FLAG_MLP_FALLBACK)
+            conf = np.zeros((3, 3), dtype=np.int64)
+            np.add.at(conf, (fl.astype(np.int64) + 1, fm.astype(np.int64) + 1), 1)
             flagger = {"lohner_ms": tl, "mlp_ms": tm, "mlp_fallback_ms": tf,
-                       "flag_disagreement": float(np.mean((fm == 1) != (fl == 1))),
-                       "fallback_flag_disagreement": float(np.mean((ff == 1) != (fl == 1))),
-                       "fallback_fraction": float(np.mean(np.abs(z) < 2.0)),
-                       "refine_flags_lohner": int(np.sum(fl == 1))}
-            log(f"flagger: Loehner {tl:.2f} ms, MLP {tm:.2f} ms, fallback {tf:.2f} ms; "
-                f"disagreement {flagger['flag_disagreement']:.4f} (fallback {flagger['fallback_flag_disagreement']:.4f})")
+                       "flag_disagreement": float(np.mean(fm != fl)),
+                       "fallback_flag_disagreement": float(np.mean(ff != fl)),
+                       "fallback_fraction": float(np.mean((np.abs(z[:, 0]) < margin) | (np.abs(z[:, 1]) < margin))),
+                       "margin": margin, "refine_flags_lohner": int(np.sum(fl == 1)),
+                       "coarsen_flags_lohner": int(np.sum(fl == -1)), "confusion_lohner_by_mlp": conf.tolist()}
+            # features pooled in the last stage of the step (amrv_mlp_fuse_features):
+            # the flagging that follows runs the network only
+            if s.ndim == 3:
+                g.mlp_fuse_features(True)
+                g.synchronize()
+                t0 = time.perf_counter()
+                t_sim, _ = g.advance_cfl(1, float("inf"), t_sim)
+                step_fused_ms = (time.perf_counter() - t0) * 1e3
+                g.synchronize()
+                t0 = time.perf_counter()
+                fused = g.flag_blocks(mode=N.FLAG_MLP)
+                tfz = (time.perf_counter() - t0) * 1e3
+                g.mlp_fuse_features(False)
+                fsep = g.flag_blocks(mode=N.FLAG_MLP)
+                flagger.update({"mlp_fused_ms": tfz, "fused_equal_separate": bool(np.array_equal(fused, fsep)),
+                                "step_with_fused_features_ms": step_fused_ms})
+            log(f"flagger: Loehner {tl:.2f} ms, MLP {tm:.2f} ms, fallback {tf:.2f} ms, fused "
+                f"{flagger.get('mlp_fused_ms', float('nan')):.3f} ms; disagreement {flagger['flag_disagreement']:.4f} "
+                f"(fallback {flagger['fallback_flag_disagreement']:.4f}); Loehner +1/-1: "
+                f"{flagger['refine_flags_lohner']}/{flagger['coarsen_flags_lohner']}")
 
     # adaptive run: Loehner flags and a regrid (plan, new forest, transfer)
     # every regrid_every steps, from the initial state, timed as a whole

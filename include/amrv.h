@@ -164,40 +164,56 @@ int amrv_advance_cfl(amrv_forest* f, int32_t nsteps, double t_end, double* t, in
  * AMRV_FLAG_LOHNER (Sec. 1.3): +1 refine (level < max_level and block max
  * estimator > tol), -1 coarsen (level > 1 and max < frac * tol), else 0;
  * emax_out (host, may be NULL) receives each leaf's max estimator.
- * AMRV_FLAG_MLP: +1 where the learned flagger's logit is > 0 (and level <
- * max_level), else 0; emax_out receives the logits.  Needs
- * amrv_mlp_set_weights.  AMRV_FLAG_MLP_FALLBACK: as AMRV_FLAG_MLP, but leaves
- * with |logit| < margin (amrv_mlp_set_margin) get the Loehner flag, and
- * emax_out the Loehner maximum for them.  Synchronises. */
+ * AMRV_FLAG_MLP: the learned flagger's two logits (z_r, z_c): +1 where
+ * z_r > 0 (and level < max_level), -1 where z_r <= 0 and z_c > 0 (and
+ * level > 1), else 0; emax_out receives z_r (amrv_mlp_logits gives both).
+ * Needs amrv_mlp_set_weights.  AMRV_FLAG_MLP_FALLBACK: as AMRV_FLAG_MLP, but
+ * leaves with |z_r| < margin or |z_c| < margin (amrv_mlp_set_margin) get the
+ * Loehner flag, and emax_out the Loehner maximum for them.  Synchronises. */
 int amrv_flag_blocks(amrv_forest* f, int32_t mode, int8_t* flags_out, double* emax_out);
 
-/* ---- learned refinement flagger (a 128-64-64-1 perceptron, bfloat16 MFMA
+/* ---- learned refinement flagger (a 128-64-64-2 perceptron, bfloat16 MFMA
  * products with binary32 accumulation; not part of the paper, which flags
  * with the Loehner estimator of Sec. 1.3) ----
- * Parameters: 12,481 binary32 values, W1 [64][128], b1 [64], W2 [64][64],
- * b2 [64], w3 [64], b3.  Features of a leaf: the means of rho and p over 64
+ * Parameters: 12,546 binary32 values, W1 [64][128], b1 [64], W2 [64][64],
+ * b2 [64], W3 [2][64], b3 [2]; output 0 is the refine logit (trained on
+ * Loehner's block maximum > tol), output 1 the coarsen logit (maximum <
+ * frac * tol).  Features of a leaf: the means of rho and p over 64
  * sub-blocks (4^3 cells in 3D, 2^2 in 2D), each divided by the leaf's mean of
  * them minus one, as bfloat16 bit patterns [128] (rho first). */
-#define AMRV_MLP_NPARAM 12481
+#define AMRV_MLP_NPARAM 12546
 #define AMRV_MLP_NIN 128
 int amrv_mlp_set_weights(amrv_forest* f, const float* w_host, int64_t n);
 int amrv_mlp_set_margin(amrv_forest* f, float margin);
 /* Features of the current state, [nleaves][128] bfloat16 bits; out is host
  * (on_device = 0, synchronises) or device memory. */
 int amrv_mlp_features(amrv_forest* f, uint16_t* out, int32_t on_device);
+/* enable != 0: the last stage of every step also pools the flagger's
+ * features of its result (the same sums, in the same order, as
+ * amrv_mlp_features), so that the next AMRV_FLAG_MLP / AMRV_FLAG_MLP_FALLBACK
+ * flagging of that state runs only the network.  3D hydrodynamic forests on
+ * the combined stage-kernel variant with minmod, van Leer or MC; elsewhere
+ * the flaggings compute the features as before.  Disabled by default. */
+int amrv_mlp_fuse_features(amrv_forest* f, int32_t enable);
+/* The logits of the last AMRV_FLAG_MLP / AMRV_FLAG_MLP_FALLBACK flagging,
+ * [nleaves][2] binary32 (refine, coarsen) into host memory.  Synchronises. */
+int amrv_mlp_logits(amrv_forest* f, float* out);
 
 typedef struct {
   float lr, beta1, beta2, eps;  /* Adam (binary32) */
-  float pos_weight;             /* weight of positive samples in the loss */
+  float pos_weight;             /* weight of the refine output's positive samples in its loss */
+  float pos_weight_c;           /* weight of the coarsen output's positive samples in its loss */
   int32_t t0;                   /* Adam steps already taken */
 } amrv_train_cfg;
 /* Device scratch bytes of amrv_mlp_train for batch size `batch`. */
 size_t amrv_mlp_train_workspace_bytes(int32_t batch);
 /* nbatch optimisation steps on device data, all pointers device memory:
- * X [n][128] bfloat16 features, y [n] labels (0 or 1), order [n] sample
- * order (batch b uses order[b*batch .. b*batch+batch-1]; the caller draws the
- * permutation), w [12,481] binary32 master weights updated in place, m and v
- * [12,481] Adam moments.  Steps first_batch .. first_batch+nbatch-1; a last
+ * X [n][128] bfloat16 features, y [n] labels (Loehner's class: +1 refine,
+ * -1 coarsen, 0 keep; the targets of the refine and coarsen outputs), order
+ * [n] sample order (batch b uses order[b*batch .. b*batch+batch-1]; the
+ * caller draws the permutation), w [12,546] binary32 master weights updated
+ * in place, m and v [12,546] Adam moments.  The loss of a sample is the sum
+ * of both outputs' class-weighted binary cross-entropies.  Steps first_batch .. first_batch+nbatch-1; a last
  * partial batch is padded with zero-weight rows.  loss (may be NULL):
  * per-batch mean loss, indexed by batch number.  grad (may be NULL): the last
  * step's gradient.  batch must be a positive multiple of 32 <= 4096.

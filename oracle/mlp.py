@@ -2,9 +2,10 @@
 
 TEST INFRASTRUCTURE ONLY (tests/, smoke, bench's CPU leg).  The paper refines
 blocks with the Loehner estimator (Sec. 1.3); the learned flagger is not
-in the paper: a 128-64-64-1 multilayer perceptron that predicts,
-from pooled block features, whether Loehner would flag the block for
-refinement.  This module is written from the definitions below, not from the
+in the paper: a 128-64-64-2 multilayer perceptron that predicts, from pooled
+block features, whether Loehner's block maximum exceeds the refinement
+tolerance (output 0) and whether it lies below the coarsening fraction of it
+(output 1).  This module is written from the definitions below, not from the
 HIP code, and shares nothing with it.
 
 Features of a leaf (3D, 16^3 cells): the means of rho and of p over the 64
@@ -16,17 +17,20 @@ binary32 and then to bfloat16 (round to nearest even).  2D leaves (16^2) use
 p features.  p follows the solver's primitive conversion
 p = (gamma-1) ((E - (0.5 m.m) (1/rho)) [- 0.5 B.B]).
 
-Network: h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), z = w3 . h2 + b3.
-Parameter vector (12,481 binary32): W1 [64][128], b1 [64], W2 [64][64],
-b2 [64], w3 [64], b3.  Loss: mean over the batch of the class-weighted binary
-cross-entropy with logits, -(pw y log s(z) + (1-y) log(1-s(z))).
+Network: h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), z = W3 h2 + b3 (two
+logits).  Parameter vector (12,546 binary32): W1 [64][128], b1 [64],
+W2 [64][64], b2 [64], W3 [2][64], b3 [2].  Labels are Loehner's classes
+(+1 refine, -1 coarsen, 0 keep); the targets are y_r = [label = +1] for
+output 0 and y_c = [label = -1] for output 1.  Loss: mean over the batch of
+the sum of both outputs' class-weighted binary cross-entropies with logits,
+-(pw y log s(z) + (1-y) log(1-s(z))), with weights pw_r and pw_c.
 """
 from __future__ import annotations
 
 import numpy as np
 
-NIN, NH = 128, 64
-NPARAM = NH * NIN + NH + NH * NH + NH + NH + 1  # 12,481
+NIN, NH, NOUT = 128, 64, 2
+NPARAM = NH * NIN + NH + NH * NH + NH + NOUT * NH + NOUT  # 12,546
 
 # ---------------------------------------------------------------------------
 # bfloat16
@@ -139,14 +143,14 @@ def unpack(params: np.ndarray):
     o += NH * NH
     b2 = p[o:o + NH]
     o += NH
-    w3 = p[o:o + NH]
-    o += NH
-    b3 = p[o]
-    return W1, b1, W2, b2, w3, b3
+    W3 = p[o:o + NOUT * NH].reshape(NOUT, NH)
+    o += NOUT * NH
+    b3 = p[o:o + NOUT]
+    return W1, b1, W2, b2, W3, b3
 
 
-def pack(W1, b1, W2, b2, w3, b3) -> np.ndarray:
-    return np.concatenate([np.ravel(W1), b1, np.ravel(W2), b2, w3, [b3]])
+def pack(W1, b1, W2, b2, W3, b3) -> np.ndarray:
+    return np.concatenate([np.ravel(W1), b1, np.ravel(W2), b2, np.ravel(W3), b3])
 
 
 def he_uniform_init(seed: int) -> np.ndarray:
@@ -154,53 +158,68 @@ def he_uniform_init(seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     W1 = rng.uniform(-1, 1, (NH, NIN)) * np.sqrt(6.0 / NIN)
     W2 = rng.uniform(-1, 1, (NH, NH)) * np.sqrt(6.0 / NH)
-    w3 = rng.uniform(-1, 1, NH) * np.sqrt(6.0 / NH)
-    return pack(W1, np.zeros(NH), W2, np.zeros(NH), w3, 0.0).astype(np.float32)
+    W3 = rng.uniform(-1, 1, (NOUT, NH)) * np.sqrt(6.0 / NH)
+    return pack(W1, np.zeros(NH), W2, np.zeros(NH), W3, np.zeros(NOUT)).astype(np.float32)
+
+
+def targets(labels) -> np.ndarray:
+    """[B, 2] targets (y_r, y_c) of Loehner class labels (+1, -1, 0)."""
+    lab = np.asarray(labels, dtype=np.float64)
+    return np.stack([(lab > 0.5).astype(np.float64), (lab < -0.5).astype(np.float64)], axis=1)
+
+
+def decide(z: np.ndarray) -> np.ndarray:
+    """Predicted class of logits [B, 2]: +1 where z_r > 0, else -1 where
+    z_c > 0, else 0 (before the level limits of a flag)."""
+    z = np.asarray(z)
+    return np.where(z[:, 0] > 0, 1, np.where(z[:, 1] > 0, -1, 0)).astype(np.int8)
 
 
 def forward64(params: np.ndarray, X: np.ndarray):
-    """binary64 forward pass; X [B, 128] values.  Returns (z, cache)."""
-    W1, b1, W2, b2, w3, b3 = (np.asarray(a, dtype=np.float64) for a in unpack(np.asarray(params, np.float64)))
+    """binary64 forward pass; X [B, 128] values.  Returns (z [B, 2], cache)."""
+    W1, b1, W2, b2, W3, b3 = (np.asarray(a, dtype=np.float64) for a in unpack(np.asarray(params, np.float64)))
     X = np.asarray(X, dtype=np.float64)
     a1 = X @ W1.T + b1
     h1 = np.maximum(a1, 0.0)
     a2 = h1 @ W2.T + b2
     h2 = np.maximum(a2, 0.0)
-    z = h2 @ w3 + b3
+    z = h2 @ W3.T + b3
     return z, (X, a1, h1, a2, h2)
 
 
-def bce_loss64(z, y, pw):
-    """mean of -(pw y log s(z) + (1-y) log(1-s(z))), in a stable form."""
+def bce_loss64(z, labels, pw, pw_c):
+    """mean over rows of the two outputs' -(pw y log s(z) + (1-y) log(1-s(z)))."""
     z = np.asarray(z, dtype=np.float64)
-    y = np.asarray(y, dtype=np.float64)
+    y = targets(labels)
+    w = np.array([pw, pw_c], dtype=np.float64)
     log_s = -np.logaddexp(0.0, -z)
     log_1ms = -np.logaddexp(0.0, z)
-    return float(np.mean(-(pw * y * log_s + (1.0 - y) * log_1ms)))
+    return float(np.mean(np.sum(-(w * y * log_s + (1.0 - y) * log_1ms), axis=1)))
 
 
-def loss64(params, X, y, pw):
+def loss64(params, X, labels, pw, pw_c):
     z, _ = forward64(params, X)
-    return bce_loss64(z, y, pw)
+    return bce_loss64(z, labels, pw, pw_c)
 
 
-def grad64(params, X, y, pw) -> np.ndarray:
+def grad64(params, X, labels, pw, pw_c) -> np.ndarray:
     """binary64 gradient of loss64 by backpropagation."""
-    W1, b1, W2, b2, w3, b3 = (np.asarray(a, dtype=np.float64) for a in unpack(np.asarray(params, np.float64)))
+    W1, b1, W2, b2, W3, b3 = (np.asarray(a, dtype=np.float64) for a in unpack(np.asarray(params, np.float64)))
     z, (X, a1, h1, a2, h2) = forward64(params, X)
-    y = np.asarray(y, dtype=np.float64)
+    y = targets(labels)
+    w = np.array([pw, pw_c], dtype=np.float64)
     B = len(z)
     s = 1.0 / (1.0 + np.exp(-z))
-    dz = ((1.0 - y) * s - pw * y * (1.0 - s)) / B
-    dw3 = h2.T @ dz
-    db3 = dz.sum()
-    dh2 = np.outer(dz, w3) * (a2 > 0)
+    dz = ((1.0 - y) * s - w * y * (1.0 - s)) / B
+    dW3 = dz.T @ h2
+    db3 = dz.sum(axis=0)
+    dh2 = (dz @ W3) * (a2 > 0)
     dW2 = dh2.T @ h1
     db2 = dh2.sum(axis=0)
     dh1 = (dh2 @ W2) * (a1 > 0)
     dW1 = dh1.T @ X
     db1 = dh1.sum(axis=0)
-    return pack(dW1, db1, dW2, db2, dw3, db3)
+    return pack(dW1, db1, dW2, db2, dW3, db3)
 
 
 # ---------------------------------------------------------------------------
@@ -211,30 +230,33 @@ def grad64(params, X, y, pw) -> np.ndarray:
 
 
 def forward_bf16(params: np.ndarray, Xbits: np.ndarray):
-    W1, b1, W2, b2, w3, b3 = unpack(np.asarray(params, np.float32))
+    W1, b1, W2, b2, W3, b3 = unpack(np.asarray(params, np.float32))
     Xb = bf16_value(Xbits)
     a1 = Xb @ bf16(W1).T + b1.astype(np.float32)
     h1b = bf16(np.maximum(a1, 0.0).astype(np.float32))
     a2 = h1b @ bf16(W2).T + b2.astype(np.float32)
     h2b = bf16(np.maximum(a2, 0.0).astype(np.float32))
-    z = (h2b @ bf16(w3)).astype(np.float32) + np.float32(b3)
+    z = (h2b @ bf16(W3).T).astype(np.float32) + b3.astype(np.float32)
     return z.astype(np.float32), (Xb, a1, h1b, a2, h2b)
 
 
-def grad_bf16(params: np.ndarray, Xbits: np.ndarray, y: np.ndarray, pw: float, weight=None):
-    """Gradient with the GPU's rounding points: dz in binary32; dh2 and dh1
-    rounded to bfloat16 as operands of the weight-gradient products; bias and
-    w3 gradients summed in binary32.  weight: per-sample 0/1 mask (padding)."""
-    W1, b1, W2, b2, w3, b3 = unpack(np.asarray(params, np.float32))
+def grad_bf16(params: np.ndarray, Xbits: np.ndarray, labels: np.ndarray, pw: float, pw_c: float, weight=None):
+    """Gradient with the GPU's rounding points: dz in binary32; dh2 (the sum
+    dz_r w3_r + dz_c w3_c in that order) and dh1 rounded to bfloat16 as
+    operands of the weight-gradient products; bias and W3 gradients summed in
+    binary32.  weight: per-sample 0/1 mask (padding)."""
+    W1, b1, W2, b2, W3, b3 = unpack(np.asarray(params, np.float32))
     z, (Xb, a1, h1b, a2, h2b) = forward_bf16(params, Xbits)
-    y = np.asarray(y, dtype=np.float32)
-    wmask = np.ones_like(y) if weight is None else np.asarray(weight, np.float32)
+    y = targets(labels).astype(np.float32)
+    wmask = np.ones(len(z), np.float32) if weight is None else np.asarray(weight, np.float32)
     B = np.float32(wmask.sum())
+    wcls = np.array([pw, pw_c], dtype=np.float32)
     s = (1.0 / (1.0 + np.exp(-z.astype(np.float64)))).astype(np.float32)
-    dz = (((1.0 - y) * s - np.float32(pw) * y * (1.0 - s)) / B * wmask).astype(np.float32)
-    dw3 = (h2b.T @ dz).astype(np.float32)
-    db3 = np.float32(dz.sum(dtype=np.float32))
-    dh2 = (np.outer(dz, bf16(w3)) * (a2 > 0)).astype(np.float32)
+    dz = (((1.0 - y) * s - wcls * y * (1.0 - s)) / B * wmask[:, None]).astype(np.float32)
+    dW3 = (dz.T @ h2b).astype(np.float32)
+    db3 = dz.sum(axis=0, dtype=np.float32)
+    W3b = bf16(W3)
+    dh2 = ((dz[:, :1] * W3b[0][None, :] + dz[:, 1:] * W3b[1][None, :]) * (a2 > 0)).astype(np.float32)
     dh2b = bf16(dh2)
     dW2 = (dh2b.T @ h1b).astype(np.float32)
     db2 = dh2.sum(axis=0, dtype=np.float32)
@@ -242,8 +264,8 @@ def grad_bf16(params: np.ndarray, Xbits: np.ndarray, y: np.ndarray, pw: float, w
     dh1b = bf16(dh1)
     dW1 = (dh1b.T @ Xb).astype(np.float32)
     db1 = dh1.sum(axis=0, dtype=np.float32)
-    loss = bce_loss64(z, y, pw)
-    return pack(dW1, db1, dW2, db2, dw3, db3).astype(np.float32), loss
+    loss = bce_loss64(z, labels, pw, pw_c)
+    return pack(dW1, db1, dW2, db2, dW3, db3).astype(np.float32), loss
 
 
 def adam(params, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

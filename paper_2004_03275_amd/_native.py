@@ -31,7 +31,7 @@ ARITH_FAST = 1
 FLAG_LOHNER = 0
 FLAG_MLP = 1
 FLAG_MLP_FALLBACK = 2
-MLP_NPARAM = 12481
+MLP_NPARAM = 12546
 MLP_NIN = 128
 
 
@@ -67,7 +67,8 @@ class Config(ctypes.Structure):
 
 class TrainCfg(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
-                ("eps", ctypes.c_float), ("pos_weight", ctypes.c_float), ("t0", ctypes.c_int32)]
+                ("eps", ctypes.c_float), ("pos_weight", ctypes.c_float), ("pos_weight_c", ctypes.c_float),
+                ("t0", ctypes.c_int32)]
 
 
 class MgConfig(ctypes.Structure):
@@ -113,6 +114,8 @@ SIGNATURES = {
     "amrv_mlp_set_weights": ([P, P, ctypes.c_int64], ctypes.c_int),
     "amrv_mlp_set_margin": ([P, ctypes.c_float], ctypes.c_int),
     "amrv_mlp_features": ([P, P, ctypes.c_int32], ctypes.c_int),
+    "amrv_mlp_logits": ([P, P], ctypes.c_int),
+    "amrv_mlp_fuse_features": ([P, ctypes.c_int32], ctypes.c_int),
     "amrv_mlp_train_workspace_bytes": ([ctypes.c_int32], ctypes.c_size_t),
     "amrv_mlp_train": ([P, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P,
                         ctypes.POINTER(TrainCfg), P, ctypes.c_size_t, P, P, P], ctypes.c_int),

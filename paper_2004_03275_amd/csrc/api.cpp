@@ -81,7 +81,7 @@ Layout plan(const Tables& t) {
   L.off_mw = take(sizeof(float) * MLP_NPARAM);
   L.off_mwb = take(sizeof(uint16_t) * MLP_WB_COUNT);
   L.off_mx = take(sizeof(uint16_t) * MLP_NIN * t.n);
-  L.off_mz = take(sizeof(float) * t.n);
+  L.off_mz = take(sizeof(float) * MLP_NOUT * t.n);
   L.off_munc = take(sizeof(int8_t) * t.n);
   L.off_xfer = take(sizeof(int32_t) * XFER_STRIDE * t.n);
   L.total = o;
@@ -131,6 +131,8 @@ struct amrv_forest {
   bool fold_valid = false;         // the reduction words hold the Courant fold of U^n
   double* Gb[3] = {nullptr, nullptr, nullptr};  // ghost-slab buffers (geo.G = Gb[0])
   bool rvalid = false;             // Gb[0]'s coarse-side slots hold the restriction of U^n
+  bool fuse_feat = false;          // the last stage writes the flagger's features (amrv_mlp_fuse_features)
+  bool fvalid = false;             // the feature buffer holds the features of U^n
 };
 
 namespace {
@@ -175,6 +177,13 @@ int enqueue_ghosts(amrv_forest* f, const Geo& geo, const double* U, bool fluxes,
 bool fused_restriction(const amrv_forest* f) {
   return f->tab.nd == 3 && f->lc.variant == 0 && f->lc.phys != PH_MHD && f->lc.lim != AMRV_KOREN &&
          f->lc.lim != AMRV_CADA && !f->tab.rlist.empty();
+}
+
+// the last stage writes the learned flagger's features of its result (3D
+// combined variant of the hydrodynamic systems, symmetric limiters)
+bool fused_features(const amrv_forest* f) {
+  return f->fuse_feat && f->tab.nd == 3 && f->lc.variant == 0 && f->lc.phys != PH_MHD &&
+         f->lc.lim != AMRV_KOREN && f->lc.lim != AMRV_CADA;
 }
 
 int enqueue_stage_update(amrv_forest* f, const Geo& geo, const StageArgs& a, int mode) {
@@ -223,7 +232,7 @@ int enqueue_stage_update(amrv_forest* f, const Geo& geo, const StageArgs& a, int
 // a captured step).
 int enqueue_step(amrv_forest* f, unsigned long long* fold = nullptr, bool assume_valid = false) {
   const int S = f->cfg.rk_stages;
-  const bool fused = fused_restriction(f);
+  const bool fused = fused_restriction(f), feat = fused_features(f);
   if (f->sched == AMRV_SCHED_PERSISTENT && f->tab.nd > 1) HIPCHK(launch_reset_u32(f->cnt, CNT_QUEUES, f->st));
   for (int s = 1; s <= S; s++) {
     const double* in = s == 1 ? f->U[0] : (s == 2 ? f->U[1] : f->U[2]);
@@ -242,10 +251,12 @@ int enqueue_step(amrv_forest* f, unsigned long long* fold = nullptr, bool assume
     a.rk = S;
     a.cflred = s == S ? fold : nullptr;
     a.Gw = fused ? f->Gb[s % S] : nullptr;
+    a.Xout = feat && s == S ? (uint16_t*)(f->ws + f->lay.off_mx) : nullptr;
     rc = enqueue_stage_update(f, geo, a, f->sched);
     if (rc) return rc;
   }
   f->rvalid = fused;
+  f->fvalid = feat;
   if (f->cfg.physics == AMRV_MHD_GLM) {
     const int ip = 2 + 2 * f->tab.nd;
     double* psi = f->U[0] + (size_t)ip * f->tab.n * f->tab.ncell;
@@ -502,6 +513,7 @@ int amrv_set_state(amrv_forest* f, const double* U, int64_t nd, int32_t on_devic
   if (!on_device) HIPCHK(hipStreamSynchronize(f->st));
   f->fold_valid = false;
   f->rvalid = false;
+  f->fvalid = false;
   return AMRV_OK;
 }
 
@@ -519,6 +531,7 @@ int amrv_uniform_grid_copy(amrv_forest* f, int32_t var, double* grid, int32_t to
   if (!to_grid) {
     f->fold_valid = false;
     f->rvalid = false;
+    f->fvalid = false;
   }
   HIPCHK(hipStreamSynchronize(f->st));
   return AMRV_OK;
@@ -572,6 +585,7 @@ int amrv_advance(amrv_forest* f, double dt) {
     }
     HIPCHK(hipGraphLaunch(f->gexec, f->st));
     f->rvalid = fused_restriction(f);
+    f->fvalid = fused_features(f);
     return AMRV_OK;
   }
   return enqueue_step(f);
@@ -618,6 +632,7 @@ int amrv_advance_cfl(amrv_forest* f, int32_t nsteps, double t_end, double* t, in
     if (graph) {
       HIPCHK(hipGraphLaunch(f->dexec, f->st));
       f->rvalid = fused_restriction(f);
+      f->fvalid = fused_features(f);
     } else {
       rc = enqueue_device_step(f, t_end);
       if (rc) return rc;
@@ -654,7 +669,7 @@ int amrv_flag_blocks(amrv_forest* f, int32_t mode, int8_t* flags_out, double* em
     uint16_t* X = (uint16_t*)(f->ws + f->lay.off_mx);
     float* z = (float*)(f->ws + f->lay.off_mz);
     int8_t* unc = (int8_t*)(f->ws + f->lay.off_munc);
-    HIPCHK(launch_mlp_features(f->geo, f->lc, f->U[0], f->pp, X, f->st));
+    if (!(f->fvalid && fused_features(f))) HIPCHK(launch_mlp_features(f->geo, f->lc, f->U[0], f->pp, X, f->st));
     HIPCHK(launch_mlp_infer(X, n, (const uint16_t*)(f->ws + f->lay.off_mwb), (const float*)(f->ws + f->lay.off_mw), z,
                             f->st));
     HIPCHK(launch_mlp_flags(z, f->geo.lvl, n, f->cfg.max_level, f->margin, f->flags,
@@ -675,7 +690,7 @@ int amrv_flag_blocks(amrv_forest* f, int32_t mode, int8_t* flags_out, double* em
 
 int amrv_mlp_set_weights(amrv_forest* f, const float* w, int64_t n) {
   if (!f || !w) return fail(AMRV_EINVAL, "null argument");
-  if (n != MLP_NPARAM) return fail(AMRV_EINVAL, "expected 12481 parameters");
+  if (n != MLP_NPARAM) return fail(AMRV_EINVAL, "expected 12546 parameters");
   float* dw = (float*)(f->ws + f->lay.off_mw);
   HIPCHK(hipMemcpyAsync(dw, w, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, f->st));
   HIPCHK(launch_mlp_prep(dw, (uint16_t*)(f->ws + f->lay.off_mwb), f->st));
@@ -702,6 +717,22 @@ int amrv_mlp_features(amrv_forest* f, uint16_t* out, int32_t on_device) {
   return AMRV_OK;
 }
 
+int amrv_mlp_fuse_features(amrv_forest* f, int32_t enable) {
+  if (!f) return fail(AMRV_EINVAL, "null forest");
+  f->fuse_feat = enable != 0;
+  f->fvalid = false;
+  drop_graph(f);
+  return AMRV_OK;
+}
+
+int amrv_mlp_logits(amrv_forest* f, float* out) {
+  if (!f || !out) return fail(AMRV_EINVAL, "null argument");
+  HIPCHK(hipMemcpyAsync(out, f->ws + f->lay.off_mz, sizeof(float) * MLP_NOUT * f->tab.n, hipMemcpyDeviceToHost,
+                        f->st));
+  HIPCHK(hipStreamSynchronize(f->st));
+  return AMRV_OK;
+}
+
 size_t amrv_mlp_train_workspace_bytes(int32_t batch) {
   if (batch <= 0 || batch % 32 || batch > 4096) {
     g_err = "batch must be a positive multiple of 32 <= 4096";
@@ -721,7 +752,7 @@ int check_train_args(const uint16_t* X, const float* y, const int32_t* order, in
   const int64_t nb_total = (n + batch - 1) / batch;
   if (first_batch < 0 || nbatch < 0 || first_batch + nbatch > nb_total) return fail(AMRV_EINVAL, "batch range outside the data");
   if (!(cfg->lr >= 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) || !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) ||
-      !(cfg->eps > 0.0f) || !(cfg->pos_weight > 0.0f) || cfg->t0 < 0)
+      !(cfg->eps > 0.0f) || !(cfg->pos_weight > 0.0f) || !(cfg->pos_weight_c > 0.0f) || cfg->t0 < 0)
     return fail(AMRV_EINVAL, "bad training hyper-parameters");
   return AMRV_OK;
 }
@@ -735,7 +766,7 @@ int amrv_mlp_train(const uint16_t* X, const float* y, const int32_t* order, int6
   if (!ws) return fail(AMRV_EINVAL, "null argument");
   if (ws_bytes < mlp_train_scratch_bytes(batch)) return fail(AMRV_ENOMEM, "training workspace too small");
   if (((uintptr_t)ws) % 256) return fail(AMRV_EINVAL, "workspace must be 256-byte aligned");
-  TrainHyper hp{cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, cfg->pos_weight};
+  TrainHyper hp{cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, cfg->pos_weight, cfg->pos_weight_c};
   HIPCHK(launch_mlp_train(X, y, order, (int)n, batch, first_batch, nbatch, w, m, v, hp, cfg->t0, ws, loss, grad,
                           (hipStream_t)stream));
   return AMRV_OK;
@@ -750,7 +781,7 @@ int amrv_mlp_train_noalloc(const uint16_t* X, const float* y, const int32_t* ord
     return fail(AMRV_ENOMEM, "batch needs more than the library's training scratch");
   void* ws = nullptr;
   HIPCHK(mlp_static_scratch(&ws));
-  TrainHyper hp{cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, cfg->pos_weight};
+  TrainHyper hp{cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, cfg->pos_weight, cfg->pos_weight_c};
   HIPCHK(launch_mlp_train(X, y, order, (int)n, batch, first_batch, nbatch, w, m, v, hp, cfg->t0, ws, loss, grad,
                           (hipStream_t)stream));
   return AMRV_OK;
@@ -809,6 +840,7 @@ int amrv_regrid_transfer(amrv_forest* from, amrv_forest* to) {
   rc = enqueue_ghosts(from, from->geo, from->U[0], false);
   from->rvalid = true;
   to->rvalid = false;
+  to->fvalid = false;
   if (rc) return rc;
   if (from->st != to->st) HIPCHK(hipStreamSynchronize(from->st));
   HIPCHK(hipMemcpyAsync(xf, to->xfer_host.data(), sizeof(int32_t) * to->xfer_host.size(), hipMemcpyHostToDevice,

@@ -61,6 +61,8 @@ struct StageArgs {
   unsigned long long* cflred;  // last stage: fold the Courant reduction of the new state here (or null)
   double* Gw;          // 3D combined variant: restrict the stage output onto the coarse neighbours'
                        // ghost slabs of this buffer (the G layout), or null
+  uint16_t* Xout;      // 3D combined variant, last stage: the learned flagger's features of the
+                       // stage output [n][128] bfloat16 bits, or null
 };
 
 struct Kernels;  // forward

@@ -24,6 +24,7 @@
 
 #include "internal.hpp"
 #include "physics.hpp"
+#include "bf16.hpp"
 #include "stage_common.hpp"
 
 namespace amrv {
@@ -319,6 +320,27 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
   auto& sFy = sF[NSB - 1];
   __shared__ double sZF[ND == 3 ? NV : 1][ND == 3 ? NB * NB : 1];  // +z coarse-fine face flux of the own column
   __shared__ int sLeaf;
+  // fused features of the learned flagger (3D combined hydrodynamics, last
+  // stage): rho and p of the output plane, and the running sums of the 16
+  // sub-blocks (4^3 cells) of the current layer of sub-blocks, then their sums
+  constexpr bool FEAT = ND == 3 && !SPLIT && PH != PH_MHD;
+  __shared__ double sQ[FEAT ? 2 : 1][FEAT ? NB * NB : 1];
+  __shared__ double sAcc[FEAT ? 2 : 1][FEAT ? 64 : 1];
+  // add the output plane kp (in sQ) to its sub-blocks' sums, cells in y, x
+  // order (planes arrive in z order): 32 threads, one per (variable, sub-block
+  // column)
+  auto pool_plane = [&](int kp) {
+    if constexpr (FEAT) {
+      const int t = threadIdx.x;
+      if (t >= 32) return;
+      const int var = t >> 4, bx = t & 3, by = (t >> 2) & 3;
+      const int sb = bx + 4 * by + 16 * (kp >> 2);
+      double acc = (kp & 3) == 0 ? 0.0 : sAcc[var][sb];
+      for (int j = 0; j < 4; j++)
+        for (int i = 0; i < 4; i++) acc = acc + sQ[var][(4 * by + j) * NB + 4 * bx + i];
+      sAcc[var][sb] = acc;
+    }
+  };
 
   const PhysParams P = load_phys(pp);
   const double dt = pp[PP_DT];
@@ -516,6 +538,9 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
         if (a.stage > 1) load_strided<NV>(ownn + k * NB * NB, vs, Uo);
       }
       __syncthreads();
+      if constexpr (FEAT) {
+        if (a.Xout && k > 0) pool_plane(k - 1);
+      }
 
       // (3) limited slopes of the plane's cells (and the first ghost layer)
       auto slopes = [&](int t0, int t1) {
@@ -639,6 +664,31 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
       if (a.cflred) {
         const double rd[3] = {rdx, rdy, rdz};
         cfl_cell<ND, PH>(Ui, P, rd, csmax, ccmax, cbad);
+      }
+      if constexpr (FEAT) {
+        if (a.Xout) {
+          double w[NV];
+          cons2prim<ND, PH>(Ui, w, P);
+          sQ[0][tid] = Ui[0];
+          sQ[1][tid] = pressure<ND, PH>(w, P);
+        }
+      }
+    }
+    if constexpr (FEAT) {
+      // the last plane's sums, then the 128 features of the leaf: sub-block
+      // means over their leaf mean (summed in sub-block order), minus one
+      if (a.Xout) {
+        __syncthreads();
+        pool_plane(NB - 1);
+        __syncthreads();
+        if (tid < 128) {
+          const int var = tid >> 6, sb = tid & 63;
+          double m = 0.0;
+          for (int i = 0; i < 64; i++) m = m + sAcc[var][i] / 64.0;
+          const double mtot = m / 64.0;
+          const float fv = (float)(sAcc[var][sb] / 64.0 / mtot - 1.0);
+          a.Xout[(size_t)leaf * 128 + 64 * var + sb] = to_bf16(fv);
+        }
       }
     }
     if constexpr (ND == 3 && !SPLIT && PH != PH_MHD) {

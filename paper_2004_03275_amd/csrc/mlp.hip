@@ -2,13 +2,13 @@
 //
 // The paper refines blocks where the Loehner estimator exceeds a tolerance
 // (arXiv 2004.03275, Sec. 1.3).  This file adds a small multilayer perceptron
-// (128-64-64-1) that predicts that decision from pooled block features, so
+// (128-64-64-2) that predicts those decisions from pooled block features, so
 // most blocks can be flagged without the estimator's ghost fill and
 // second-derivative pass:
 //   k_mlp_features  per leaf: means of rho and p over 64 sub-blocks (4^3 cells
 //                   in 3D, 2^2 in 2D), normalised by the leaf mean, to bfloat16
-//   k_mlp_infer     logits of all leaves: bfloat16 MFMA products
-//                   (v_mfma_f32_16x16x32_bf16), binary32 accumulation
+//   k_mlp_infer     refine and coarsen logits of all leaves: bfloat16 MFMA
+//                   products (v_mfma_f32_16x16x32_bf16), binary32 accumulation
 //   k_mlp_train     one optimisation step on a batch: forward, class-weighted
 //                   binary cross-entropy, backward (weight gradients again as
 //                   bfloat16 MFMA products with binary32 accumulation), Adam
@@ -17,6 +17,7 @@
 
 #include <mutex>
 
+#include "bf16.hpp"
 #include "internal.hpp"
 #include "mlp.hpp"
 #include "physics.hpp"
@@ -25,12 +26,6 @@ namespace amrv {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
-
-__device__ __forceinline__ uint16_t to_bf16(float x) {
-  const uint32_t u = __float_as_uint(x);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
-  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
 
 __device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
@@ -142,7 +137,7 @@ __global__ void __launch_bounds__(128) k_mlp_features(Geo g, const double* __res
 // parameters: binary32 master vector -> bfloat16 operand copies
 // ---------------------------------------------------------------------------
 
-// W1b [64][128], W2b [64][64], W2bT [64][64] (transposed), w3b [64]
+// W1b [64][128], W2b [64][64], W2bT [64][64] (transposed), W3b [2][64]
 __global__ void k_mlp_prep(const float* __restrict__ w, uint16_t* __restrict__ wb) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < MLP_NH * MLP_NIN; i += gridDim.x * blockDim.x)
     wb[MLP_WB_W1 + i] = to_bf16(w[MLP_W1 + i]);
@@ -152,7 +147,7 @@ __global__ void k_mlp_prep(const float* __restrict__ w, uint16_t* __restrict__ w
     const int n2 = i / MLP_NH, n1 = i % MLP_NH;  // W2[n2][n1]
     wb[MLP_WB_W2T + n1 * MLP_NH + n2] = b;
   }
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < MLP_NH; i += gridDim.x * blockDim.x)
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < MLP_NOUT * MLP_NH; i += gridDim.x * blockDim.x)
     wb[MLP_WB_W3 + i] = to_bf16(w[MLP_W3 + i]);
 }
 
@@ -161,9 +156,9 @@ __global__ void k_mlp_prep(const float* __restrict__ w, uint16_t* __restrict__ w
 // ---------------------------------------------------------------------------
 
 // rows of X: xrow(r) -> pointer to 128 bfloat16 features, or nullptr (zeros)
-// h1t, h2t: the wave's LDS tiles [16][64] bfloat16.  Returns the logit of row
-// (lane < 16 ? lane : undefined).  If keep != nullptr the binary32
-// pre-activation signs are not needed: ReLU outputs > 0 mark them.
+// h1t, h2t: the wave's LDS tiles [16][64] bfloat16.  Returns, in lane l < 16,
+// the refine logit of row l and, in lane 16 + l, the coarsen logit of row l
+// (other lanes: undefined).
 template <class XRow>
 __device__ __forceinline__ float tile_forward(XRow xrow, const uint16_t* __restrict__ wb, const float* __restrict__ w,
                                               uint16_t* h1t, uint16_t* h2t) {
@@ -207,14 +202,16 @@ __device__ __forceinline__ float tile_forward(XRow xrow, const uint16_t* __restr
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
   float z = 0.f;
-  if (l < 16) {
-    for (int k = 0; k < MLP_NH; k++) z = z + from_bf16(h2t[l * MLP_NH + k]) * from_bf16(wb[MLP_WB_W3 + k]);
-    z = z + w[MLP_B3];
+  if (l < 32) {
+    const int o = l >> 4, r = l & 15;
+    for (int k = 0; k < MLP_NH; k++)
+      z = z + from_bf16(h2t[r * MLP_NH + k]) * from_bf16(wb[MLP_WB_W3 + o * MLP_NH + k]);
+    z = z + w[MLP_B3 + o];
   }
   return z;
 }
 
-// logits of n rows of X [n][128]; 256 threads = 4 waves x 16 rows
+// logits of n rows of X [n][128] into z [n][2]; 256 threads = 4 waves x 16 rows
 __global__ void __launch_bounds__(256) k_mlp_infer(const uint16_t* __restrict__ X, int n, const uint16_t* __restrict__ wb,
                                                    const float* __restrict__ w, float* __restrict__ z) {
   __shared__ __attribute__((aligned(16))) uint16_t h1[4][16 * MLP_NH];
@@ -223,19 +220,22 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const uint16_t* __restrict__ 
   const int r0 = blockIdx.x * 64 + wave * 16;
   auto xrow = [&](int m) -> const uint16_t* { return r0 + m < n ? X + (size_t)(r0 + m) * MLP_NIN : nullptr; };
   const float zz = tile_forward(xrow, wb, w, h1[wave], h2[wave]);
-  if (l < 16 && r0 + l < n) z[r0 + l] = zz;
+  const int r = l & 15, o = l >> 4;
+  if (l < 32 && r0 + r < n) z[(size_t)(r0 + r) * MLP_NOUT + o] = zz;
 }
 
-// flags from logits: MLP mode +1 where z > 0 below the finest level, else 0;
-// `uncertain` marks |z| < margin (fallback mode)
+// flags from logits (z_r, z_c): +1 where z_r > 0 below the finest level, -1
+// where z_r <= 0 and z_c > 0 above level 1, else 0; `uncertain` marks
+// leaves with |z_r| < margin or |z_c| < margin (fallback mode)
 __global__ void k_mlp_flags(const float* __restrict__ z, const int32_t* __restrict__ lvl, int n, int max_level,
                             float margin, int8_t* __restrict__ flags, int8_t* __restrict__ uncertain, double* zout) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float zi = z[i];
-  flags[i] = (zi > 0.f && lvl[i] < max_level) ? 1 : 0;
-  if (uncertain) uncertain[i] = fabsf(zi) < margin ? 1 : 0;
-  if (zout) zout[i] = (double)zi;
+  const float zr = z[(size_t)i * MLP_NOUT], zc = z[(size_t)i * MLP_NOUT + 1];
+  const int l = lvl[i];
+  flags[i] = (zr > 0.f && l < max_level) ? 1 : ((!(zr > 0.f) && zc > 0.f && l > 1) ? -1 : 0);
+  if (uncertain) uncertain[i] = (fabsf(zr) < margin || fabsf(zc) < margin) ? 1 : 0;
+  if (zout) zout[i] = (double)zr;
 }
 
 // ---------------------------------------------------------------------------
@@ -253,8 +253,8 @@ struct TrainScratch {
   uint16_t* dh2T;  // [64][B]
   uint16_t* dh1T;  // [64][B]
   float* dh1;      // [B][64] binary32 (bias gradient)
-  float* z;        // [B]
-  float* dz;       // [B]
+  float* z;        // [B][2]
+  float* dz;       // [B][2]
   float* grad;     // [NPARAM]
   float* loss;     // [B] per-row loss
   uint16_t* wb;    // bfloat16 operand copies
@@ -296,51 +296,72 @@ __global__ void __launch_bounds__(256) k_mlp_train(const uint16_t* __restrict__ 
       s.h1T[(size_t)c * B + r0 + m] = h1t[wave][i];
       s.h2[(size_t)(r0 + m) * MLP_NH + c] = h2t[wave][i];
     }
-    if (l < 16) s.z[r0 + l] = z;
+    if (l < 32) s.z[(size_t)(r0 + (l & 15)) * MLP_NOUT + (l >> 4)] = z;
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
   }
   __threadfence_block();
   __syncthreads();
 
-  // P2: logit gradient and loss per row
+  // P2: logit gradients and loss per row.  The label is Loehner's class
+  // (+1 refine, -1 coarsen, 0 keep): target 1 of the refine output for +1,
+  // of the coarsen output for -1; each output's class-weighted binary
+  // cross-entropy, summed
   const float Bv = (float)nvalid;
   for (int r = tid; r < B; r += 256) {
-    float dz = 0.f, lr = 0.f;
+    float dzr = 0.f, dzc = 0.f, lr = 0.f;
     if (r < nvalid) {
-      const float z = s.z[r];
-      const float y = Y[order[b0 + r]];
-      const float sg = 1.f / (1.f + expf(-z));
-      dz = ((1.f - y) * sg - hp.pos_weight * y * (1.f - sg)) / Bv;
-      // -(pw y log s + (1-y) log(1-s)) with log s = -softplus(-z)
-      const float sp_neg = fmaxf(-z, 0.f) + log1pf(expf(-fabsf(z)));
-      const float sp_pos = fmaxf(z, 0.f) + log1pf(expf(-fabsf(z)));
-      lr = hp.pos_weight * y * sp_neg + (1.f - y) * sp_pos;
+      const float lab = Y[order[b0 + r]];
+#pragma unroll
+      for (int o = 0; o < MLP_NOUT; o++) {
+        const float z = s.z[(size_t)r * MLP_NOUT + o];
+        const float y = o == 0 ? (lab > 0.5f ? 1.f : 0.f) : (lab < -0.5f ? 1.f : 0.f);
+        const float pw = o == 0 ? hp.pos_weight : hp.pos_weight_c;
+        const float sg = 1.f / (1.f + expf(-z));
+        const float dz = ((1.f - y) * sg - pw * y * (1.f - sg)) / Bv;
+        // -(pw y log s + (1-y) log(1-s)) with log s = -softplus(-z)
+        const float sp_neg = fmaxf(-z, 0.f) + log1pf(expf(-fabsf(z)));
+        const float sp_pos = fmaxf(z, 0.f) + log1pf(expf(-fabsf(z)));
+        lr = lr + (pw * y * sp_neg + (1.f - y) * sp_pos);
+        if (o == 0)
+          dzr = dz;
+        else
+          dzc = dz;
+      }
     }
-    s.dz[r] = dz;
+    s.dz[(size_t)r * MLP_NOUT] = dzr;
+    s.dz[(size_t)r * MLP_NOUT + 1] = dzc;
     s.loss[r] = lr;
   }
   __threadfence_block();
   __syncthreads();
 
-  // P3: w3, b3, b2 gradients; dh2 = dz w3 * [h2 > 0] (binary32, then bfloat16)
-  if (tid < MLP_NH) {
+  // P3: W3, b3, b2 gradients; dh2 = (dz_r w3_r + dz_c w3_c) * [h2 > 0]
+  // (binary32, then bfloat16)
+  if (tid < MLP_NOUT * MLP_NH) {
+    const int o = tid / MLP_NH, c = tid % MLP_NH;
     float g3 = 0.f;
-    for (int r = 0; r < B; r++) g3 = g3 + s.dz[r] * from_bf16(s.h2[(size_t)r * MLP_NH + tid]);
+    for (int r = 0; r < B; r++) g3 = g3 + s.dz[(size_t)r * MLP_NOUT + o] * from_bf16(s.h2[(size_t)r * MLP_NH + c]);
     s.grad[MLP_W3 + tid] = g3;
-  } else if (tid == MLP_NH) {
+  } else if (tid < MLP_NOUT * MLP_NH + MLP_NOUT) {
+    const int o = tid - MLP_NOUT * MLP_NH;
     float g = 0.f, L = 0.f;
     for (int r = 0; r < B; r++) {
-      g = g + s.dz[r];
+      g = g + s.dz[(size_t)r * MLP_NOUT + o];
       L = L + s.loss[r];
     }
-    s.grad[MLP_B3] = g;
-    if (loss_out) loss_out[batch] = L / Bv;
+    s.grad[MLP_B3 + o] = g;
+    if (loss_out && o == 0) loss_out[batch] = L / Bv;
   }
+  auto dh2_of = [&](int r, int c) -> float {
+    return from_bf16(s.h2[(size_t)r * MLP_NH + c]) > 0.f
+               ? s.dz[(size_t)r * MLP_NOUT] * from_bf16(s.wb[MLP_WB_W3 + c]) +
+                     s.dz[(size_t)r * MLP_NOUT + 1] * from_bf16(s.wb[MLP_WB_W3 + MLP_NH + c])
+               : 0.f;
+  };
   for (int i = tid; i < B * MLP_NH; i += 256) {
     const int r = i / MLP_NH, c = i % MLP_NH;
-    const float d = from_bf16(s.h2[i]) > 0.f ? s.dz[r] * from_bf16(s.wb[MLP_WB_W3 + c]) : 0.f;
-    const uint16_t db = to_bf16(d);
+    const uint16_t db = to_bf16(dh2_of(r, c));
     s.dh2[i] = db;
     s.dh2T[(size_t)c * B + r] = db;
   }
@@ -348,10 +369,7 @@ __global__ void __launch_bounds__(256) k_mlp_train(const uint16_t* __restrict__ 
   __syncthreads();
   if (tid < MLP_NH) {
     float g = 0.f;
-    for (int r = 0; r < B; r++) {
-      const float d = from_bf16(s.h2[(size_t)r * MLP_NH + tid]) > 0.f ? s.dz[r] * from_bf16(s.wb[MLP_WB_W3 + tid]) : 0.f;
-      g = g + d;
-    }
+    for (int r = 0; r < B; r++) g = g + dh2_of(r, tid);
     s.grad[MLP_B2 + tid] = g;
   }
 
@@ -422,7 +440,7 @@ __global__ void __launch_bounds__(256) k_mlp_train(const uint16_t* __restrict__ 
     s.wb[MLP_WB_W2 + i] = b;
     s.wb[MLP_WB_W2T + (i % MLP_NH) * MLP_NH + i / MLP_NH] = b;
   }
-  if (tid < MLP_NH) s.wb[MLP_WB_W3 + tid] = to_bf16(w[MLP_W3 + tid]);
+  if (tid < MLP_NOUT * MLP_NH) s.wb[MLP_WB_W3 + tid] = to_bf16(w[MLP_W3 + tid]);
   if (tid == 0) *s.tstep = t;
 }
 
@@ -488,8 +506,8 @@ static TrainScratch carve(char* ws, int B) {
   s.dh2T = (uint16_t*)take(2 * (size_t)B * MLP_NH);
   s.dh1T = (uint16_t*)take(2 * (size_t)B * MLP_NH);
   s.dh1 = (float*)take(4 * (size_t)B * MLP_NH);
-  s.z = (float*)take(4 * (size_t)B);
-  s.dz = (float*)take(4 * (size_t)B);
+  s.z = (float*)take(4 * (size_t)MLP_NOUT * B);
+  s.dz = (float*)take(4 * (size_t)MLP_NOUT * B);
   s.grad = (float*)take(4 * (size_t)MLP_NPARAM);
   s.loss = (float*)take(4 * (size_t)B);
   s.wb = (uint16_t*)take(2 * (size_t)MLP_WB_COUNT);

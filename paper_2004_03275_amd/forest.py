@@ -163,6 +163,16 @@ class GpuForest:
         N.check(N.lib().amrv_mlp_features(self._h, X.ctypes.data, 0))
         return X
 
+    def mlp_fuse_features(self, enable: bool = True):
+        """Pool the flagger's features in the last stage of every step."""
+        N.check(N.lib().amrv_mlp_fuse_features(self._h, 1 if enable else 0))
+
+    def mlp_logits(self) -> np.ndarray:
+        """[n, 2] binary32 refine and coarsen logits of the last MLP flagging."""
+        z = np.empty((self.forest.n, 2), dtype=np.float32)
+        N.check(N.lib().amrv_mlp_logits(self._h, z.ctypes.data))
+        return z
+
     # -- scheduling ---------------------------------------------------------
     def set_schedule(self, sched: int, xcd_remap: int = 1, persistent_wgs: int = 0):
         N.check(N.lib().amrv_set_schedule(self._h, int(sched), int(xcd_remap), int(persistent_wgs)))

@@ -66,25 +66,48 @@ def test_backprop_matches_finite_differences():
     w = W.mlp_init(3).astype(np.float64)
     w[M.NH * M.NIN:M.NH * M.NIN + M.NH] = rng.uniform(0.05, 0.2, M.NH)  # positive b1: active units
     X = rng.standard_normal((32, M.NIN)) * 0.5
-    y = (rng.uniform(size=32) < 0.4).astype(np.float64)
-    g = M.grad64(w, X, y, 2.5)
+    r = rng.uniform(size=32)
+    y = np.where(r < 0.4, 1.0, np.where(r < 0.7, -1.0, 0.0))
+    g = M.grad64(w, X, y, 2.5, 1.5)
     idx = rng.choice(M.NPARAM, 60, replace=False)
-    idx = np.concatenate([idx, [M.NPARAM - 1, M.NH * M.NIN + 3]])
+    # the last parameters: b3 of both outputs, a W3 entry of each output, a b1 entry
+    o3 = M.NH * M.NIN + M.NH + M.NH * M.NH + M.NH
+    idx = np.concatenate([idx, [M.NPARAM - 1, M.NPARAM - 2, o3 + 5, o3 + M.NH + 7, M.NH * M.NIN + 3]])
     h = 1e-6
     for k in idx:
         wp = w.copy()
         wm = w.copy()
         wp[k] += h
         wm[k] -= h
-        fd = (M.loss64(wp, X, y, 2.5) - M.loss64(wm, X, y, 2.5)) / (2 * h)
+        fd = (M.loss64(wp, X, y, 2.5, 1.5) - M.loss64(wm, X, y, 2.5, 1.5)) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])) + 1e-8, (k, fd, g[k])
+
+
+def test_outputs_train_on_their_own_class():
+    """The refine output's gradient ignores coarsen labels and vice versa: with
+    every label +1 the coarsen output is pushed down only, with every label -1
+    the refine output is."""
+    X, _ = W.mlp_random_features(9, 64)
+    w = W.mlp_init(2).astype(np.float64)
+    Xv = M.bf16_value(X).astype(np.float64)
+    ob3 = M.NPARAM - 2
+    g_up = M.grad64(w, Xv, np.ones(64), 2.0, 3.0)
+    g_dn = M.grad64(w, Xv, -np.ones(64), 2.0, 3.0)
+    z, _ = M.forward64(w, Xv)
+    s = 1.0 / (1.0 + np.exp(-z))
+    # db3 closed forms: mean of ((1 - y) s - pw y (1 - s)) per output
+    assert np.isclose(g_up[ob3], np.mean(-2.0 * (1.0 - s[:, 0])), rtol=1e-12)
+    assert np.isclose(g_up[ob3 + 1], np.mean(s[:, 1]), rtol=1e-12)
+    assert np.isclose(g_dn[ob3], np.mean(s[:, 0]), rtol=1e-12)
+    assert np.isclose(g_dn[ob3 + 1], np.mean(-3.0 * (1.0 - s[:, 1])), rtol=1e-12)
+    assert list(M.decide(np.array([[1.0, 1.0], [-1.0, 2.0], [-1.0, -2.0], [0.0, 0.5]]))) == [1, -1, 0, -1]
 
 
 def test_bf16_emulated_gradient_is_close_to_binary64():
     X, y = W.mlp_random_features(5, 256)
     w = W.mlp_init(7)
-    g32, _ = M.grad_bf16(w, X, y, 2.0)
-    g64 = M.grad64(w.astype(np.float64), M.bf16_value(X).astype(np.float64), y, 2.0)
+    g32, _ = M.grad_bf16(w, X, y, 2.0, 1.0)
+    g64 = M.grad64(w.astype(np.float64), M.bf16_value(X).astype(np.float64), y, 2.0, 1.0)
     rel = np.linalg.norm(g32 - g64) / np.linalg.norm(g64)
     assert rel < 3e-2, rel
 

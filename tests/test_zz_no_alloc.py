@@ -60,7 +60,7 @@ def _run(noalloc, Xd, yd, od, n, batch, nbatch, w0, cfg):
 def test_noalloc_training_matches_workspace_training(calls):
     from paper_2004_03275_amd import _native as N
 
-    cfg = N.TrainCfg(1e-3, 0.9, 0.999, 1e-8, 2.0, 0)
+    cfg = N.TrainCfg(1e-3, 0.9, 0.999, 1e-8, 2.0, 1.5, 0)
     w0 = W.mlp_init(11)
     for i, (n, batch, nbatch) in enumerate(calls):
         Xd, yd, od = _inputs(31 + i, n)
@@ -76,7 +76,7 @@ def test_noalloc_training_matches_workspace_training(calls):
 def test_noalloc_rejects_batches_beyond_its_scratch():
     from paper_2004_03275_amd import _native as N
 
-    cfg = N.TrainCfg(1e-3, 0.9, 0.999, 1e-8, 2.0, 0)
+    cfg = N.TrainCfg(1e-3, 0.9, 0.999, 1e-8, 2.0, 1.5, 0)
     Xd, yd, od = _inputs(41, 256)
     w, m, v, loss, grad = _state(W.mlp_init(1), 1)
     rc = N.lib().amrv_mlp_train_noalloc(_p(Xd), _p(yd), _p(od), 256, 8192, 0, 1, _p(w), _p(m), _p(v),

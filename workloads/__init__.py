@@ -553,41 +553,45 @@ def relative_l1(U: np.ndarray, R: np.ndarray, forest: Forest) -> np.ndarray:
 # learned flagger: seeded initial weights and jittered blast parameters
 # ---------------------------------------------------------------------------
 
-MLP_NIN, MLP_NH = 128, 64
-MLP_NPARAM = MLP_NH * MLP_NIN + MLP_NH + MLP_NH * MLP_NH + MLP_NH + MLP_NH + 1
+MLP_NIN, MLP_NH, MLP_NOUT = 128, 64, 2
+MLP_NPARAM = MLP_NH * MLP_NIN + MLP_NH + MLP_NH * MLP_NH + MLP_NH + MLP_NOUT * MLP_NH + MLP_NOUT
 
 
 def mlp_init(seed: int) -> np.ndarray:
     """He-uniform initial weights (bound sqrt(6 / fan_in)), zero biases, as the
-    binary32 parameter vector W1 [64][128], b1, W2 [64][64], b2, w3, b3."""
+    binary32 parameter vector W1 [64][128], b1, W2 [64][64], b2, W3 [2][64], b3 [2]."""
     rng = np.random.default_rng(seed)
     W1 = rng.uniform(-1, 1, (MLP_NH, MLP_NIN)) * np.sqrt(6.0 / MLP_NIN)
     W2 = rng.uniform(-1, 1, (MLP_NH, MLP_NH)) * np.sqrt(6.0 / MLP_NH)
-    w3 = rng.uniform(-1, 1, MLP_NH) * np.sqrt(6.0 / MLP_NH)
+    W3 = rng.uniform(-1, 1, (MLP_NOUT, MLP_NH)) * np.sqrt(6.0 / MLP_NH)
     z = np.zeros(MLP_NH)
-    return np.concatenate([W1.ravel(), z, W2.ravel(), z, w3, [0.0]]).astype(np.float32)
+    return np.concatenate([W1.ravel(), z, W2.ravel(), z, W3.ravel(), np.zeros(MLP_NOUT)]).astype(np.float32)
 
 
-def jittered_blast(seed: int, base: int = 8, max_level: int = 3):
+def jittered_blast(seed: int, base: int = 8, max_level: int = 3, coarse: bool = False):
     """A blast with seeded centre (|c_i| <= 0.1), radius in [0.08, 0.12] and
-    inner pressure in [50, 200] on its own refined forest."""
+    inner pressure in [50, 200] on its own refined forest, or with coarse=True
+    on the uniform level-1 forest (every leaf below the top level, so the
+    blocks the blast crosses are ones a flagger would refine)."""
     rng = np.random.default_rng(seed)
     radius = float(rng.uniform(0.08, 0.12))
     centre = tuple(float(c) for c in rng.uniform(-0.1, 0.1, 3))
     p_in = float(rng.uniform(50.0, 200.0))
     s = blast_scheme(base=base, max_level=max_level)
-    f = blast_forest(s, radius=radius, centre=centre, buffer_cells=4.0)
+    f = uniform_forest(s) if coarse else blast_forest(s, radius=radius, centre=centre, buffer_cells=4.0)
     return blast(s, radius=radius, p_in=p_in, centre=centre, forest=f)
 
 
 def mlp_random_features(seed: int, n: int) -> np.ndarray:
     """Seeded synthetic feature rows [n, 128] (bfloat16 bit patterns of
-    values in about [-1, 1]) and labels, for kernel parity checks."""
+    values in about [-1, 1]) and class labels (+1 with probability 0.3, -1
+    with 0.3, else 0), for kernel parity checks."""
     rng = np.random.default_rng(seed)
     x = (rng.standard_normal((n, MLP_NIN)) * 0.5).astype(np.float32)
     u = x.view(np.uint32).astype(np.uint64)
     bits = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
-    y = (rng.uniform(size=n) < 0.3).astype(np.float32)
+    r = rng.uniform(size=n)
+    y = np.where(r < 0.3, 1.0, np.where(r < 0.6, -1.0, 0.0)).astype(np.float32)
     return bits, y
 
 
