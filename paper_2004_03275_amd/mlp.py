@@ -182,41 +182,46 @@ def evaluate(w: np.ndarray, seeds, tol=0.1, frac=0.125, base=8, max_level=3, ste
     return out
 
 
-def flags_from_logits(z: np.ndarray, level: np.ndarray, max_level: int, dr: float = 0.0, dc: float = 0.0):
+C4_STEPS = (0, 5, 10, 15, 20, 25)
+
+
+def flags_from_logits(z: np.ndarray, level: np.ndarray, max_level, dr: float = 0.0, dc: float = 0.0):
     """The flag rule of AMRV_FLAG_MLP on logits shifted by (dr, dc)."""
     zr, zc = z[:, 0] - dr, z[:, 1] - dc
     return np.where((zr > 0) & (level < max_level), 1, np.where(~(zr > 0) & (zc > 0) & (level > 1), -1, 0))
 
 
 def calibrate(w: np.ndarray, seeds, base=8, max_level=3, steps=(0, 4, 8, 14, 20, 28), coarse_steps=(0, 3, 6, 10, 14),
-              device="cuda:0", grid=np.arange(-4.0, 4.0001, 0.05), max_fallback=0.05):
+              device="cuda:0", grid=np.arange(-4.0, 4.0001, 0.05), max_fallback=0.05, c4_seeds=()):
     """Decision thresholds of the two outputs, fitted on training seeds: the
     shifts (dr, dc) of the refine and coarsen logits that minimise the flag
     disagreement with Loehner over the seeds' snapshots (refined and level-1
     forests), folded into the output biases, and the fallback margin that
     sends max_fallback of those leaves to Loehner.  Returns (weights, dr, dc,
     disagreement before, after, margin)."""
-    Z, FL, LV = [], [], []
-    runs = [(sd, False, steps) for sd in seeds] + [(sd, True, coarse_steps) for sd in seeds]
-    for sd, coarse, stp in runs:
-        f, U = W.jittered_blast(sd, base=base, max_level=max_level, coarse=coarse)
+    Z, FL, LV, MX = [], [], [], []
+    runs = [(sd, False, steps, base, max_level) for sd in seeds] + \
+        [(sd, True, coarse_steps, base, max_level) for sd in seeds] + [(sd, False, C4_STEPS, 16, 4) for sd in c4_seeds]
+    for sd, coarse, stp, bs, ml in runs:
+        f, U = W.jittered_blast(sd, base=bs, max_level=ml, coarse=coarse)
         for _, g in snapshots(f, U, stp, device):
             g.mlp_set_weights(w)
             FL.append(g.flag_blocks())
             g.flag_blocks(mode=N.FLAG_MLP)
             Z.append(g.mlp_logits())
             LV.append(np.asarray(f.level))
-    Z, FL, LV = np.concatenate(Z), np.concatenate(FL), np.concatenate(LV)
-    before = float(np.mean(flags_from_logits(Z, LV, max_level) != FL))
+            MX.append(np.full(f.n, ml))
+    Z, FL, LV, MX = np.concatenate(Z), np.concatenate(FL), np.concatenate(LV), np.concatenate(MX)
+    before = float(np.mean(flags_from_logits(Z, LV, MX) != FL))
     best = (before, 0.0, 0.0)
     # the refine threshold first (the coarsen flag depends on it), then the coarsen one
     for dr in grid:
-        d = float(np.mean(flags_from_logits(Z, LV, max_level, dr, 0.0) != FL))
+        d = float(np.mean(flags_from_logits(Z, LV, MX, dr, 0.0) != FL))
         if d < best[0] - 1e-12:
             best = (d, float(dr), 0.0)
     dr = best[1]
     for dc in grid:
-        d = float(np.mean(flags_from_logits(Z, LV, max_level, dr, dc) != FL))
+        d = float(np.mean(flags_from_logits(Z, LV, MX, dr, dc) != FL))
         if d < best[0] - 1e-12:
             best = (d, dr, float(dc))
     _, dr, dc = best
@@ -274,6 +279,8 @@ def main(argv=None):
     ap.add_argument("--kh-seeds", default="1-8")
     ap.add_argument("--test-seeds", default="101-103")
     ap.add_argument("--calib-seeds", default="1-12", help="training seeds the decision thresholds are fitted on")
+X
+    ap.add_argument("--c4-test-seed", type=int, default=101)
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -290,8 +297,11 @@ def main(argv=None):
     t0 = time.perf_counter()
     X1, e1, l1 = blast_dataset(_seeds(args.blast_seeds))
     X0, e0, l0 = blast_dataset(_seeds(args.blast_seeds), steps=(0, 3, 6, 10, 14), coarse=True)
-    X1, e1, l1 = np.concatenate([X1, X0]), np.concatenate([e1, e0]), np.concatenate([l1, l0])
-    log(f"blast data (refined and level-1 forests): {len(e1)} leaves ({time.perf_counter() - t0:.1f} s)")
+    parts = [(X1, e1, l1), (X0, e0, l0)]
+    if args.c4_seeds:
+        parts.append(blast_dataset(_seeds(args.c4_seeds), base=16, max_level=4, steps=C4_STEPS))
+    X1, e1, l1 = (np.concatenate([p[i] for p in parts]) for i in range(3))
+    log(f"blast data (refined, level-1 and 16^3-base forests): {len(e1)} leaves ({time.perf_counter() - t0:.1f} s)")
     X2, e2, l2 = kh_dataset(_seeds(args.kh_seeds))
     log(f"kh data: {len(e2)} leaves ({time.perf_counter() - t0:.1f} s)")
     X = np.concatenate([X1, X2])
@@ -302,10 +312,13 @@ def main(argv=None):
     hist = tr.fit(args.epochs, log)
     train_s = time.perf_counter() - t1
     w0 = tr.weights()
-    w, dr, dc, d0, d1, margin = calibrate(w0, _seeds(args.calib_seeds))
+    w, dr, dc, d0, d1, margin = calibrate(w0, _seeds(args.calib_seeds), c4_seeds=_seeds(args.c4_seeds))
     log(f"calibration on seeds {args.calib_seeds}: logit shifts refine {dr:+.2f}, coarsen {dc:+.2f}; "
         f"flag disagreement {d0:.4f} -> {d1:.4f}; fallback margin {margin:.3f}")
     res = evaluate(w, _seeds(args.test_seeds), tol=args.tol, margin=margin if args.margin is None else args.margin)
+    res_c4 = evaluate(w, [args.c4_test_seed], tol=args.tol, base=16, max_level=4, steps=C4_STEPS, coarse_steps=(),
+                      margin=margin if args.margin is None else args.margin)
+    res["c4_size"] = res_c4
     rec = {"samples": int(len(y)), "refine_labels": int(np.sum(y > 0)), "coarsen_labels": int(np.sum(y < 0)),
            "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "train_seconds": train_s,
            "final_loss": hist[-1], "pos_weight": tr.pos_weight, "pos_weight_c": tr.pos_weight_c,
