@@ -279,7 +279,8 @@ def main(argv=None):
     ap.add_argument("--kh-seeds", default="1-8")
     ap.add_argument("--test-seeds", default="101-103")
     ap.add_argument("--calib-seeds", default="1-12", help="training seeds the decision thresholds are fitted on")
-X
+    ap.add_argument("--c4-seeds", default="",
+                    help="also train and calibrate on blasts on 16^3-base, 4-level forests (the 3D AMR blast's size)")
     ap.add_argument("--c4-test-seed", type=int, default=101)
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--batch", type=int, default=1024)
