@@ -34,21 +34,29 @@ METRIC = "MCUPS (cell-updates/s) per full RK step, batched vs per-block, at 1e-1
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-def measured_counters(workload: str, limiter: str = "vanleer", variant: int = 0) -> dict:
+COUNTER_SOURCES = ("kernels.hip", "stage_ilp.hip", "stage_fast.hip", "stage_common.hpp", "bf16.hpp", "physics.hpp",
+                   "internal.hpp", "../build.py")
+
+
+def counter_sources_sha256() -> str:
+    """sha256 of the stage kernel's sources and the build (its compile flags)."""
+    import hashlib
+
+    csrc = os.path.join(ROOT, "paper_2004_03275_amd", "csrc")
+    return hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read() for f in COUNTER_SOURCES)).hexdigest()
+
+
+def measured_counters(workload: str, limiter: str = "vanleer", variant: int = 0, arithmetic: str = "fast") -> dict:
     """HBM bytes per stage-kernel launch and the VALU / FP64 issue fractions
     from the committed counter summary, if it was taken on this workload and
-    stage kernel (van Leer slopes, combined variant) with the current kernel
-    sources and build flags (else an empty dict)."""
-    import hashlib
-    if workload != "blast" or limiter != "vanleer" or variant != 0:
+    stage kernel (van Leer slopes, combined variant, fast arithmetic) with the
+    current kernel sources and build flags (else an empty dict)."""
+    if workload != "blast" or limiter != "vanleer" or variant != 0 or arithmetic != "fast":
         return {}
     prof = os.path.join(ROOT, "profiles", "hbm_counters_3d_amr_blast.md")
-    csrc = os.path.join(ROOT, "paper_2004_03275_amd", "csrc")
     try:
         text = open(prof).read()
-        # the kernel sources and the build (its compile flags)
-        h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
-                                    for f in ("kernels.hip", "stage_ilp.hip", "physics.hpp", "internal.hpp", "../build.py"))).hexdigest()
+        h = counter_sources_sha256()
     except OSError:
         return {}
     keys = ("kernel_source_sha256", "traffic_bytes_per_launch", "valu_issue_frac", "fp64_issue_frac")
@@ -310,6 +318,27 @@ def main():
             f"MCUPS on {threads} threads")
         del G1, R1
         g.set_state(U0)
+        if args.workload == "blast":
+            # the oracle on one thread, on a bounded sample of the same workload:
+            # one step of the blast on the 8^3-base forest (the same sphere and levels)
+            s8 = W.blast_scheme(base=8, max_level=s.max_level)
+            f8, U8 = W.blast(s8)
+            c8 = f8.n * s8.cells_per_block
+            oracle.set_threads(1)
+            try:
+                o = oracle.OracleForest(f8)
+                o.set_state(U8)
+                dt8 = o.max_dt()
+                t0 = time.perf_counter()
+                o.advance(dt8)
+                el1 = time.perf_counter() - t0
+                o.close()
+            finally:
+                oracle.set_threads(threads)
+            cpu["one_thread"] = {"value": c8 / el1 / 1e6, "unit": "MCUPS", "cores": 1,
+                                 "sample": f"one full SSP-RK step of the 3d_amr_blast on the 8^3-base forest "
+                                           f"({f8.n} leaves, {c8} cells) from its initial state, {el1:.1f} s"}
+            log(f"oracle on 1 thread: {cpu['one_thread']['value']:.2f} MCUPS ({el1:.1f} s, {f8.n} leaves)")
 
     if args.copy_calibration_mib > 0:
         nel = args.copy_calibration_mib * (1 << 20) // 8
@@ -536,7 +565,8 @@ def main():
     if args.workload == "blast" and not args.no_rd:
         rd = rd_measure(2, 256, 20, 3, log, cpu=not args.no_cpu_baseline)
 
-    counters = measured_counters(args.workload, ["minmod", "vanleer", "mc", "koren", "cada"][s.limiter], sched[3])
+    counters = measured_counters(args.workload, ["minmod", "vanleer", "mc", "koren", "cada"][s.limiter], sched[3],
+                                 args.arithmetic)
     names = {0: "per_block", 1: "grid", 2: "persistent"}
     bytes_per_cell_step = (2 + 3 * (s.rk_stages - 1)) * s.nvar * 8
     out = {
@@ -572,6 +602,16 @@ def main():
             "arithmetic": args.arithmetic,
             "graph": bool(args.graph) or not args.host_dt,
             "time_step": "host (amrv_max_dt + amrv_advance)" if args.host_dt else "device (amrv_advance_cfl)",
+        },
+        "step_roofline": {
+            "bound": "hbm",
+            "achieved": bytes_per_cell_step * cells / (ms_step / 1e3) / 1e9,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": bytes_per_cell_step * cells / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_step": bytes_per_cell_step * cells,
+            "note": "whole step (all launches, the timed region's flaggings included) against the interior-state "
+                    "passes of the SSP stages",
         },
         "roofline": {
             "bound": "hbm",
