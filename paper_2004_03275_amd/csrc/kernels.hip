@@ -542,9 +542,19 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
         if (a.Xout && k > 0) pool_plane(k - 1);
       }
 
+      // The items of the slope and flux phases do not divide evenly over the
+      // four waves (576 and 544 per plane); the remainder goes to the threads
+      // of one wave, which changes from plane to plane (and leaf to leaf), so
+      // that it is spread over the SIMDs instead of always falling on the
+      // first wave's.  Each item is computed the same way by any thread.
+      const int rs = (tid + 64 * (k + leaf)) & (WGS - 1);
+      const int rf = (tid + 64 * (k + leaf + 2)) & (WGS - 1);
       // (3) limited slopes of the plane's cells (and the first ghost layer)
       auto slopes = [&](int t0, int t1) {
-        for (int t = t0 + tid; t < t1; t += WGS) {
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+          const int t = t0 + rs + j * WGS;
+          if (t >= t1) break;
           const bool yd = t >= NSX;
           const int u = yd ? t - NSX : t;
           int b, st;
@@ -583,7 +593,7 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
       // commutative, so the results are identical while a wave holding both
       // x and y faces runs one Riemann solver instead of two.
       auto fluxes = [&](int t0, int t1) {
-        for (int t = t0 + tid; t < t1; t += WGS) {
+        for (int t = t0 + rf; t < t1; t += WGS) {
           const bool yd = t >= NFX;
           const int u = yd ? t - NFX : t;
           int r, m, bl, st, s0, s1;
