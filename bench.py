@@ -482,11 +482,17 @@ def main():
             # features pooled in the last stage of the step (amrv_mlp_fuse_features):
             # the flagging that follows runs the network only
             if s.ndim == 3:
-                g.mlp_fuse_features(True)
-                g.synchronize()
-                t0 = time.perf_counter()
-                t_sim, _ = g.advance_cfl(1, float("inf"), t_sim)
-                step_fused_ms = (time.perf_counter() - t0) * 1e3
+                # the cost of pooling: 5 device-timed steps (graph replay) with
+                # and without it, each after one step that captures its graph
+                step_ms = {}
+                for fuse in (False, True):
+                    g.mlp_fuse_features(fuse)
+                    t_sim, _ = g.advance_cfl(1, float("inf"), t_sim)
+                    g.synchronize()
+                    t0 = time.perf_counter()
+                    t_sim, _ = g.advance_cfl(5, float("inf"), t_sim)
+                    g.synchronize()
+                    step_ms[fuse] = (time.perf_counter() - t0) * 1e3 / 5
                 g.synchronize()
                 t0 = time.perf_counter()
                 fused = g.flag_blocks(mode=N.FLAG_MLP)
@@ -494,7 +500,8 @@ def main():
                 g.mlp_fuse_features(False)
                 fsep = g.flag_blocks(mode=N.FLAG_MLP)
                 flagger.update({"mlp_fused_ms": tfz, "fused_equal_separate": bool(np.array_equal(fused, fsep)),
-                                "step_with_fused_features_ms": step_fused_ms})
+                                "step_ms_with_fused_features": step_ms[True],
+                                "step_ms_without_features": step_ms[False]})
             log(f"flagger: Loehner {tl:.2f} ms, MLP {tm:.2f} ms, fallback {tf:.2f} ms, fused "
                 f"{flagger.get('mlp_fused_ms', float('nan')):.3f} ms; disagreement {flagger['flag_disagreement']:.4f} "
                 f"(fallback {flagger['fallback_flag_disagreement']:.4f}); Loehner +1/-1: "
