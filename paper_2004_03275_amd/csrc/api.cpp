@@ -671,8 +671,7 @@ int amrv_flag_blocks(amrv_forest* f, int32_t mode, int8_t* flags_out, double* em
     int8_t* unc = (int8_t*)(f->ws + f->lay.off_munc);
     if (!(f->fvalid && fused_features(f))) HIPCHK(launch_mlp_features(f->geo, f->lc, f->U[0], f->pp, X, f->st));
     HIPCHK(launch_mlp_infer(X, n, (const uint16_t*)(f->ws + f->lay.off_mwb), (const float*)(f->ws + f->lay.off_mw), z,
-                            f->st));
-    HIPCHK(launch_mlp_flags(z, f->geo.lvl, n, f->cfg.max_level, f->margin, f->flags,
+                            f->geo.lvl, f->cfg.max_level, f->margin, f->flags,
                             mode == AMRV_FLAG_MLP_FALLBACK ? unc : nullptr, f->emax, f->st));
     if (mode == AMRV_FLAG_MLP_FALLBACK) only = unc;
   }

@@ -8,7 +8,8 @@
 //   k_mlp_features  per leaf: means of rho and p over 64 sub-blocks (4^3 cells
 //                   in 3D, 2^2 in 2D), normalised by the leaf mean, to bfloat16
 //   k_mlp_infer     refine and coarsen logits of all leaves: bfloat16 MFMA
-//                   products (v_mfma_f32_16x16x32_bf16), binary32 accumulation
+//                   products (v_mfma_f32_16x16x32_bf16), binary32 accumulation,
+//                   and each leaf's three-way flag from its two logits
 //   k_mlp_train     one optimisation step on a batch: forward, class-weighted
 //                   binary cross-entropy, backward (weight gradients again as
 //                   bfloat16 MFMA products with binary32 accumulation), Adam
@@ -211,9 +212,16 @@ __device__ __forceinline__ float tile_forward(XRow xrow, const uint16_t* __restr
   return z;
 }
 
-// logits of n rows of X [n][128] into z [n][2]; 256 threads = 4 waves x 16 rows
+// logits of n rows of X [n][128] into z [n][2], and each leaf's flag from
+// its logits (z_r, z_c): +1 where z_r > 0 below the finest level, -1 where
+// z_r <= 0 and z_c > 0 above level 1, else 0; `uncertain` (optional) marks
+// leaves with |z_r| < margin or |z_c| < margin (fallback mode), `zout`
+// (optional) receives z_r.  256 threads = 4 waves x 16 rows.
 __global__ void __launch_bounds__(256) k_mlp_infer(const uint16_t* __restrict__ X, int n, const uint16_t* __restrict__ wb,
-                                                   const float* __restrict__ w, float* __restrict__ z) {
+                                                   const float* __restrict__ w, float* __restrict__ z,
+                                                   const int32_t* __restrict__ lvl, int max_level, float margin,
+                                                   int8_t* __restrict__ flags, int8_t* __restrict__ uncertain,
+                                                   double* __restrict__ zout) {
   __shared__ __attribute__((aligned(16))) uint16_t h1[4][16 * MLP_NH];
   __shared__ __attribute__((aligned(16))) uint16_t h2[4][16 * MLP_NH];
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -221,21 +229,16 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const uint16_t* __restrict__ 
   auto xrow = [&](int m) -> const uint16_t* { return r0 + m < n ? X + (size_t)(r0 + m) * MLP_NIN : nullptr; };
   const float zz = tile_forward(xrow, wb, w, h1[wave], h2[wave]);
   const int r = l & 15, o = l >> 4;
+  const float zc = __shfl(zz, r + 16, 64);  // lane r (< 16) gets the coarsen logit of its row
   if (l < 32 && r0 + r < n) z[(size_t)(r0 + r) * MLP_NOUT + o] = zz;
-}
-
-// flags from logits (z_r, z_c): +1 where z_r > 0 below the finest level, -1
-// where z_r <= 0 and z_c > 0 above level 1, else 0; `uncertain` marks
-// leaves with |z_r| < margin or |z_c| < margin (fallback mode)
-__global__ void k_mlp_flags(const float* __restrict__ z, const int32_t* __restrict__ lvl, int n, int max_level,
-                            float margin, int8_t* __restrict__ flags, int8_t* __restrict__ uncertain, double* zout) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float zr = z[(size_t)i * MLP_NOUT], zc = z[(size_t)i * MLP_NOUT + 1];
-  const int l = lvl[i];
-  flags[i] = (zr > 0.f && l < max_level) ? 1 : ((!(zr > 0.f) && zc > 0.f && l > 1) ? -1 : 0);
-  if (uncertain) uncertain[i] = (fabsf(zr) < margin || fabsf(zc) < margin) ? 1 : 0;
-  if (zout) zout[i] = (double)zr;
+  if (l < 16 && r0 + r < n) {
+    const int i = r0 + r;
+    const float zr = zz;
+    const int lv = lvl[i];
+    flags[i] = (zr > 0.f && lv < max_level) ? 1 : ((!(zr > 0.f) && zc > 0.f && lv > 1) ? -1 : 0);
+    if (uncertain) uncertain[i] = (fabsf(zr) < margin || fabsf(zc) < margin) ? 1 : 0;
+    if (zout) zout[i] = (double)zr;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -474,15 +477,11 @@ hipError_t launch_mlp_prep(const float* w, uint16_t* wb, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_infer(const uint16_t* X, int n, const uint16_t* wb, const float* w, float* z, hipStream_t st) {
+hipError_t launch_mlp_infer(const uint16_t* X, int n, const uint16_t* wb, const float* w, float* z, const int32_t* lvl,
+                            int max_level, float margin, int8_t* flags, int8_t* uncertain, double* zout,
+                            hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mlp_infer, dim3((n + 63) / 64), dim3(256), 0, st, X, n, wb, w, z);
-  return hipGetLastError();
-}
-
-hipError_t launch_mlp_flags(const float* z, const int32_t* lvl, int n, int max_level, float margin, int8_t* flags,
-                            int8_t* uncertain, double* zout, hipStream_t st) {
-  hipLaunchKernelGGL(k_mlp_flags, dim3((n + 255) / 256), dim3(256), 0, st, z, lvl, n, max_level, margin, flags,
+  hipLaunchKernelGGL(k_mlp_infer, dim3((n + 63) / 64), dim3(256), 0, st, X, n, wb, w, z, lvl, max_level, margin, flags,
                      uncertain, zout);
   return hipGetLastError();
 }

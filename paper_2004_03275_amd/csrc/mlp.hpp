@@ -31,10 +31,11 @@ struct TrainHyper {
 hipError_t launch_mlp_features(const Geo& g, const LaunchCfg& c, const double* U, const double* physp, uint16_t* X,
                                hipStream_t st);
 hipError_t launch_mlp_prep(const float* w, uint16_t* wb, hipStream_t st);
-hipError_t launch_mlp_infer(const uint16_t* X, int n, const uint16_t* wb, const float* w, float* z, hipStream_t st);
-// z [n][2]: refine and coarsen logits; zout (may be null): the refine logits
-hipError_t launch_mlp_flags(const float* z, const int32_t* lvl, int n, int max_level, float margin, int8_t* flags,
-                            int8_t* uncertain, double* zout, hipStream_t st);
+// z [n][2]: refine and coarsen logits; flags [n]: the three-way decision;
+// uncertain, zout (may be null): the fallback marks and the refine logits
+hipError_t launch_mlp_infer(const uint16_t* X, int n, const uint16_t* wb, const float* w, float* z, const int32_t* lvl,
+                            int max_level, float margin, int8_t* flags, int8_t* uncertain, double* zout,
+                            hipStream_t st);
 // device scratch of one training call with batch B (256-byte aligned pieces)
 constexpr size_t mlp_align256(size_t b) { return (b + 255) / 256 * 256; }
 constexpr size_t mlp_train_scratch_bytes_c(int B) {

@@ -137,8 +137,9 @@ class GpuForest:
         Loehner maximum (LOHNER mode) or the learned flagger's logit (MLP
         modes; Loehner maximum on the fallback leaves)."""
         flags = np.empty(self.forest.n, dtype=np.int8)
-        emax = np.empty(self.forest.n, dtype=np.float64)
-        N.check(N.lib().amrv_flag_blocks(self._h, int(mode), flags.ctypes.data, emax.ctypes.data))
+        emax = np.empty(self.forest.n, dtype=np.float64) if with_emax else None
+        N.check(N.lib().amrv_flag_blocks(self._h, int(mode), flags.ctypes.data,
+                                         emax.ctypes.data if with_emax else None))
         return (flags, emax) if with_emax else flags
 
     # -- learned flagger ----------------------------------------------------
