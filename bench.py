@@ -233,7 +233,7 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay each step as a HIP graph")
     ap.add_argument("--schedule", default=None,
                     help="fixed schedule instead of autotuning: grid, grid-noremap or persistent:<workgroups>")
-    ap.add_argument("--variant", type=int, default=None, help="force the stage-kernel variant (0 or 1)")
+    ap.add_argument("--variant", type=int, default=None, help="force the stage-kernel variant (0, 1, or 2 for 3D MHD)")
     ap.add_argument("--arithmetic", default="fast", choices=["fast", "exact"],
                     help="stage-kernel arithmetic: fast (FMA, refined reciprocal estimates; within the 1e-10 bar) "
                          "or exact (correctly rounded, bit for bit with the oracle)")
@@ -605,7 +605,7 @@ def main():
             "cfl": s.cfl,
             "flag_every": args.flag_every,
             "schedule": {"mode": names[sched[0]], "xcd_remap": sched[1], "persistent_wgs": sched[2],
-                         "stage_kernel_variant": ["combined_xy", "split_xy"][sched[3]]},
+                         "stage_kernel_variant": ["combined_xy", "split_xy", "z_then_xy"][sched[3]]},
             "arithmetic": args.arithmetic,
             "graph": bool(args.graph) or not args.host_dt,
             "time_step": "host (amrv_max_dt + amrv_advance)" if args.host_dt else "device (amrv_advance_cfl)",

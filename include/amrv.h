@@ -289,8 +289,13 @@ int amrv_get_schedule(const amrv_forest* f, int32_t* sched, int32_t* xcd_remap, 
 
 /* Stage-kernel variant for 2D/3D leaves: 0 = x and y share the slope and
  * flux phases (fewer barriers, more LDS), 1 = x then y through one set of
- * LDS arrays (less LDS, more workgroups per compute unit).  Both give
- * identical results. */
+ * LDS arrays (less LDS, more workgroups per compute unit), 2 = (3D MHD
+ * forests only; others get AMRV_EINVAL) two launches per stage: the z
+ * direction of every column, whose flux divergence goes to a workspace
+ * buffer that amrv_workspace_bytes includes for these forests, then the x/y
+ * planes with the face states formed in place (no stored slopes), so that
+ * each launch fits two workgroups per compute unit.  All give identical
+ * results. */
 int amrv_set_variant(amrv_forest* f, int32_t variant);
 int amrv_get_variant(const amrv_forest* f, int32_t* variant);
 

@@ -33,7 +33,10 @@ HIPFLAGS = [
 UNITS = {"stage_ilp.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
          # the same kernels in fast arithmetic: contraction on (the flag after
          # the common -ffp-contract=off wins)
-         "stage_fast.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp", "-ffp-contract=fast"]}
+         "stage_fast.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp", "-ffp-contract=fast"],
+         # the two-launch 3D MHD stage update (default scheduler), exact and fast
+         "stage_zsplit.hip": [],
+         "stage_zsplit_fast.hip": ["-ffp-contract=fast"]}
 
 
 def _jobs() -> int:

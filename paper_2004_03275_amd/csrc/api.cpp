@@ -45,10 +45,14 @@ constexpr size_t ALIGN = 256;
 struct Layout {
   size_t off_U[3], off_G, off_FF, off_lvl, off_ijk, off_nbr, off_slot, off_kind, off_fslot, off_sleaf, off_sface,
       off_rlist, off_plist, off_pp, off_lp, off_red, off_cnt, off_emax, off_flags, off_mw, off_mwb, off_mx, off_mz,
-      off_munc, off_xfer, total;
+      off_munc, off_xfer, off_zd, total;
 };
 
-Layout plan(const Tables& t) {
+// 3D MHD forests carry a buffer for the z flux divergence of stage-kernel
+// variant 2 (one state-sized array)
+bool zsplit_capable(const amrv_config& c, const Tables& t) { return c.physics == AMRV_MHD_GLM && t.nd == 3; }
+
+Layout plan(const amrv_config& c, const Tables& t) {
   Layout L;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -84,6 +88,7 @@ Layout plan(const Tables& t) {
   L.off_mz = take(sizeof(float) * MLP_NOUT * t.n);
   L.off_munc = take(sizeof(int8_t) * t.n);
   L.off_xfer = take(sizeof(int32_t) * XFER_STRIDE * t.n);
+  L.off_zd = take(zsplit_capable(c, t) ? state : 1);
   L.total = o;
   return L;
 }
@@ -252,6 +257,7 @@ int enqueue_step(amrv_forest* f, unsigned long long* fold = nullptr, bool assume
     a.cflred = s == S ? fold : nullptr;
     a.Gw = fused ? f->Gb[s % S] : nullptr;
     a.Xout = feat && s == S ? (uint16_t*)(f->ws + f->lay.off_mx) : nullptr;
+    a.Zd = zsplit_capable(f->cfg, f->tab) ? (double*)(f->ws + f->lay.off_zd) : nullptr;
     rc = enqueue_stage_update(f, geo, a, f->sched);
     if (rc) return rc;
   }
@@ -348,7 +354,7 @@ size_t amrv_workspace_bytes(const amrv_config* cfg, int64_t n, const int32_t* le
     g_err = t.err;
     return 0;
   }
-  const size_t total = plan(t).total;
+  const size_t total = plan(*cfg, t).total;
   g_tables.cfg = *cfg;
   g_tables.lev.assign(lev, lev + n);
   g_tables.ijk.assign(ijk, ijk + 3 * n);
@@ -375,7 +381,7 @@ int amrv_forest_create(const amrv_config* cfg, int64_t n, const int32_t* lev, co
     delete f;
     return fail(rc, m);
   }
-  f->lay = plan(f->tab);
+  f->lay = plan(f->cfg, f->tab);
   if (!d_ws) {
     delete f;
     return fail(AMRV_EINVAL, "null workspace");
@@ -872,7 +878,9 @@ int amrv_get_schedule(const amrv_forest* f, int32_t* sched, int32_t* xcd, int32_
 
 int amrv_set_variant(amrv_forest* f, int32_t variant) {
   if (!f) return fail(AMRV_EINVAL, "null forest");
-  if (variant < 0 || variant > 1) return fail(AMRV_EINVAL, "unknown stage-kernel variant");
+  if (variant < 0 || variant > 2) return fail(AMRV_EINVAL, "unknown stage-kernel variant");
+  if (variant == 2 && !zsplit_capable(f->cfg, f->tab))
+    return fail(AMRV_EINVAL, "stage-kernel variant 2 is the two-launch update of 3D MHD forests");
   f->lc.variant = variant;
   drop_graph(f);
   return AMRV_OK;
@@ -905,7 +913,9 @@ int amrv_autotune(amrv_forest* f, int32_t reps) {
     int sched, xcd, pwgs, var;
   };
   std::vector<Cand> cands;
-  for (int var : f->tab.nd > 1 ? std::vector<int>{0, 1} : std::vector<int>{0}) {
+  std::vector<int> vars = f->tab.nd > 1 ? std::vector<int>{0, 1} : std::vector<int>{0};
+  if (zsplit_capable(f->cfg, f->tab)) vars.push_back(2);
+  for (int var : vars) {
     cands.push_back({AMRV_SCHED_GRID, 0, 0, var});
     cands.push_back({AMRV_SCHED_GRID, 1, 0, var});
     if (f->tab.nd > 1)
@@ -941,6 +951,7 @@ int amrv_autotune(amrv_forest* f, int32_t reps) {
     a.stage = 1;
     a.rk = f->cfg.rk_stages;
     a.Gw = fused ? f->Gb[1] : nullptr;
+    a.Zd = zsplit_capable(f->cfg, f->tab) ? (double*)(f->ws + f->lay.off_zd) : nullptr;
     std::vector<float> ts;
     for (int r = 0; r < reps + 1 && !rc; r++) {
       if (c.sched == AMRV_SCHED_PERSISTENT) {

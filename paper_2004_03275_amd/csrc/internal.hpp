@@ -63,6 +63,8 @@ struct StageArgs {
                        // ghost slabs of this buffer (the G layout), or null
   uint16_t* Xout;      // 3D combined variant, last stage: the learned flagger's features of the
                        // stage output [n][128] bfloat16 bits, or null
+  double* Zd;          // variant 2 (3D MHD): the z flux divergence of every cell (the state
+                       // layout), written by the z-column launch and read by the x/y launch
 };
 
 struct Kernels;  // forward
@@ -76,7 +78,7 @@ enum { PH_EULER = 0, PH_MHD = 1, PH_POLY = 2 };
 // launchers (kernels.hip)
 struct LaunchCfg {
   int ndim, phys, flux, lim;  // phys: PH_EULER, PH_MHD or PH_POLY
-  int variant;  // stage kernel: 0 combined x/y phases, 1 split x then y
+  int variant;  // stage kernel: 0 combined x/y phases, 1 split x then y, 2 (3D MHD) z columns, then x/y
   int arith;    // 0 correctly rounded (default), 1 fast arithmetic where the stage kernel has that form
 };
 

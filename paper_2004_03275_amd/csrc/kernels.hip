@@ -716,6 +716,292 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
 }
 
 // ---------------------------------------------------------------------------
+// stage update of 16^3 leaves in two launches (variant 2, 3D MHD): the z
+// direction of every column first (k_stage_zcol), then the x/y planes with
+// the z flux divergence read back (k_stage_xy).  The 9-variable z queue of
+// the one-launch kernel keeps it at one workgroup per CU; split, each launch
+// fits two.  Same expressions in the same order as k_stage_tile, so the
+// results are identical bit for bit.  AR names the arithmetic of the unit
+// that instantiates them (0: correctly rounded, stage_zsplit.hip; 1: fast,
+// stage_zsplit_fast.hip), as for k_stage_tile.
+// ---------------------------------------------------------------------------
+
+// (1) of the stage update for whole columns: thread (tx, ty) streams its
+// column through the planes, with the z slope of cell k+1 and the flux of face
+// k+1/2 in registers, and writes (F_{k+1/2} - F_{k-1/2}) * rdz of every cell
+// to a.Zd (the state layout).  No LDS, no barrier.
+template <int PH, int FLUX, int LIM, int AR>
+__global__ void __launch_bounds__(WGS, 2) k_stage_zcol(Geo g, StageArgs a, const double* __restrict__ pp, Sched sc) {
+  constexpr int ND = 3;
+  constexpr int NV = Sys<ND, PH>::NV;
+  const PhysParams P = load_phys(pp);
+  if (pp[PP_DT] == 0.0) return;  // a device-timed run that has reached its end time
+  const int leaf = pick_leaf(sc, blockIdx.x);
+  if (leaf >= g.n) return;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const size_t vs = (size_t)g.n * g.ncell;
+  const int lvl = g.lvl[leaf];
+  const double rdz = g.rdx[lvl][2];
+  const double thz = pp[PP_CTHR + 3 * lvl + 2];
+  const int kd4 = g.kind[leaf * 6 + 4], kd5 = g.kind[leaf * 6 + 5];
+  const size_t col = (size_t)leaf * g.ncell + tx + NB * ty;
+  const double* own = a.Uin + col;
+  double* zo = a.Zd + col;
+
+  // +z face source of this thread's column (ghost planes 16, 17)
+  const double* zptr = a.Uin;
+  int zls = 0;
+  size_t zvs = vs;
+  if (kd5 == NB_SAME) {
+    zptr = a.Uin + (size_t)g.nbr[leaf * 6 + 5] * g.ncell + tx + NB * ty;
+    zls = NB * NB;
+  } else if (kd5 == NB_BND) {
+    zptr = own + (NB - 1) * NB * NB;
+    zls = 0;
+  } else {
+    zptr = g.G + (size_t)g.slot[leaf * 6 + 5] * NV * 2 * g.T + tx + NB * ty;
+    zls = g.T;
+    zvs = 2 * (size_t)g.T;
+  }
+
+  double V0[NV], V1[NV], C2[NV], VLz[NV], Flo[NV];
+  {
+    double vm2[NV], vm1[NV], c[NV], lo[NV], hi[NV], vlm1[NV];
+    own_prim<ND, PH>(g, a.Uin, leaf, tx, ty, -2, vm2, P);
+    own_prim<ND, PH>(g, a.Uin, leaf, tx, ty, -1, vm1, P);
+    load_strided<NV>(own, vs, c);
+    cons2prim<ND, PH>(c, V0, P);
+    load_strided<NV>(own + NB * NB, vs, c);
+    cons2prim<ND, PH>(c, V1, P);
+    load_strided<NV>(own + 2 * NB * NB, vs, C2);
+    muscl<NV, LIM>(vm2, vm1, V0, lo, vlm1, thz);
+    muscl<NV, LIM>(vm1, V0, V1, lo, hi, thz);
+    if (kd4 == NB_SAME || kd4 == NB_BND) {
+      riemann<ND, PH, FLUX, 2>(vlm1, lo, Flo, P);
+    } else {
+      cf_flux<NV, ND>(g, leaf, 4, kd4, tx, ty, Flo);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; v++) VLz[v] = hi[v];
+  }
+  for (int k = 0; k < NB; k++) {
+    double V2[NV], VR1[NV], VL1[NV], Fhi[NV];
+    cons2prim<ND, PH>(C2, V2, P);
+    const int pn = k + 3;
+    if (pn < NB)
+      load_strided<NV>(own + pn * NB * NB, vs, C2);
+    else if (pn < NB + 2)
+      load_strided<NV>(zptr + (pn - NB) * zls, zvs, C2);
+    muscl<NV, LIM>(V0, V1, V2, VR1, VL1, thz);
+    if (k == NB - 1 && !(kd5 == NB_SAME || kd5 == NB_BND)) {
+      cf_flux<NV, ND>(g, leaf, 5, kd5, tx, ty, Fhi);
+    } else {
+      riemann<ND, PH, FLUX, 2>(VLz, VR1, Fhi, P);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+      zo[v * vs + (size_t)k * NB * NB] = (Fhi[v] - Flo[v]) * rdz;
+      Flo[v] = Fhi[v];
+      VLz[v] = VL1[v];
+      V0[v] = V1[v];
+      V1[v] = V2[v];
+    }
+  }
+}
+
+// (2)-(5) of the stage update on x/y planes, the z divergence from a.Zd: per
+// plane the primitives (with the 2-cell x/y ghost ring) to LDS, then every x
+// and y face flux with the face's two limited states formed in place from
+// four primitives (the half slope of the lower cell toward the face and of the
+// upper cell toward it: each is needed by that one face only, so no slope is
+// stored and no slope phase or barrier is needed), then the divergence and
+// the SSP combination.  Two barriers per plane, 68 KB of LDS for MHD.
+template <int PH, int FLUX, int LIM, int AR>
+__global__ void __launch_bounds__(WGS, 2) k_stage_xy(Geo g, StageArgs a, const double* __restrict__ pp, Sched sc) {
+  constexpr int ND = 3;
+  using S = Sys<ND, PH>;
+  constexpr int NV = S::NV;
+  constexpr int PW = NB + 4;
+  constexpr int NFX = NB * 17;  // x faces: 16 rows x faces 0..16, [row][face]
+  __shared__ double sP[NV][PW * PW];  // primitive plane incl. x/y ghost ring, (y+2)*PW + x+2
+  __shared__ double sF[2][NV][NFX];   // fluxes: x [row][face]; y [face][column]
+  __shared__ int sLeaf;
+
+  const PhysParams P = load_phys(pp);
+  const double dt = pp[PP_DT];
+  if (dt == 0.0) return;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const size_t vs = (size_t)g.n * g.ncell;
+  unsigned long long csmax = 0, ccmax = 0;
+  int cbad = 0;
+
+  // ring cell of this thread (tid < 128): x ring then y ring
+  int rx = 0, ry = 0, rface = 0, rlayer = 0, ra1 = 0;
+  if (tid < 64) {
+    const int c = tid >> 4;
+    ry = tid & 15;
+    rx = c < 2 ? c - 2 : 14 + c;
+    rface = rx < 0 ? 0 : 1;
+    rlayer = rx < 0 ? -1 - rx : rx - NB;
+    ra1 = ry;
+  } else if (tid < 128) {
+    const int u = tid - 64, c = u >> 4;
+    rx = u & 15;
+    ry = c < 2 ? c - 2 : 14 + c;
+    rface = ry < 0 ? 2 : 3;
+    rlayer = ry < 0 ? -1 - ry : ry - NB;
+    ra1 = rx;
+  }
+  const bool ring = tid < 128;
+  const int rdst = (ry + 2) * PW + rx + 2;
+
+  for (int iter = 0;; iter++) {
+    int leaf;
+    if (sc.mode == 2) {
+      if (tid == 0) sLeaf = queue_next(sc, g.n);
+      __syncthreads();
+      leaf = sLeaf;
+      __syncthreads();
+    } else {
+      if (iter) break;
+      leaf = pick_leaf(sc, blockIdx.x);
+    }
+    if (leaf >= g.n) break;
+
+    const int lvl = g.lvl[leaf];
+    const double rdx = g.rdx[lvl][0], rdy = g.rdx[lvl][1], rdz = g.rdx[lvl][2];
+    const double thx = pp[PP_CTHR + 3 * lvl], thy = pp[PP_CTHR + 3 * lvl + 1];
+    int kinds[4];
+#pragma unroll
+    for (int f = 0; f < 4; f++) kinds[f] = g.kind[leaf * 6 + f];
+
+    const size_t col = (size_t)leaf * g.ncell + tx + NB * ty;
+    const double* own = a.Uin + col;
+    const double* ownn = a.Un + col;
+    const double* zdp = a.Zd + col;
+    double* out = a.Uout + col;
+
+    // source of this thread's ring cell: var 0 at plane 0, plane and var strides
+    const double* rptr = a.Uin;
+    int rks = 0;
+    size_t rvs = vs;
+    if (ring) {
+      const int kd = kinds[rface];
+      const int d = rface >> 1, hi = rface & 1;
+      if (kd == NB_SAME || kd == NB_BND) {
+        const int src = g.nbr[leaf * 6 + rface];
+        const int along = kd == NB_SAME ? (hi ? rlayer : NB - 1 - rlayer) : (hi ? NB - 1 : 0);
+        const int cell0 = d == 0 ? along + NB * ra1 : ra1 + NB * along;
+        rptr = a.Uin + (size_t)src * g.ncell + cell0;
+        rks = NB * NB;
+        rvs = vs;
+      } else {
+        const int sl = g.slot[leaf * 6 + rface];
+        rptr = g.G + (size_t)sl * NV * 2 * g.T + (size_t)rlayer * g.T + ra1;
+        rks = NB;
+        rvs = 2 * (size_t)g.T;
+      }
+    }
+
+    double Cq[NV], Cr[NV], Ui[NV], Uo[NV], Zk[NV];
+    load_strided<NV>(own, vs, Cq);
+    if (ring) load_strided<NV>(rptr, rvs, Cr);
+
+    for (int k = 0; k < NB; k++) {
+      // (2) plane k (own cell and ring cell) to LDS; the next plane's loads,
+      // U^n and the z divergence of this plane issued for phase 5
+      {
+        double w[NV];
+        cons2prim<ND, PH>(Cq, w, P);
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+          sP[v][(ty + 2) * PW + tx + 2] = w[v];
+          Ui[v] = Cq[v];
+        }
+      }
+      if (k + 1 < NB) load_strided<NV>(own + (k + 1) * NB * NB, vs, Cq);
+      if (ring) {
+        double w[NV];
+        cons2prim<ND, PH>(Cr, w, P);
+#pragma unroll
+        for (int v = 0; v < NV; v++) sP[v][rdst] = w[v];
+        if (k + 1 < NB) load_strided<NV>(rptr + (k + 1) * rks, rvs, Cr);
+      }
+      if (a.stage > 1) load_strided<NV>(ownn + k * NB * NB, vs, Uo);
+      load_strided<NV>(zdp + k * NB * NB, vs, Zk);
+      __syncthreads();
+
+      // (3)+(4) face fluxes; a y face is solved as an x face of the state
+      // with its x and y components exchanged (as in k_stage_tile)
+      for (int t = tid; t < 2 * NFX; t += WGS) {
+        const bool yd = t >= NFX;
+        const int u = yd ? t - NFX : t;
+        int r, m, bl, st;
+        if (!yd) {
+          r = u / 17;
+          m = u % 17;
+          bl = (r + 2) * PW + m + 1;
+          st = 1;
+        } else {
+          m = u / NB;
+          r = u % NB;
+          bl = (m + 1) * PW + r + 2;
+          st = PW;
+        }
+        const int bf = m == 0 ? 2 * yd : (m == NB ? 2 * yd + 1 : -1);
+        double F[NV];
+        if (bf >= 0 && !(kinds[bf] == NB_SAME || kinds[bf] == NB_BND)) {
+          cf_flux<NV, ND>(g, leaf, bf, kinds[bf], r, k, F);
+        } else {
+          const double th = yd ? thy : thx;
+          double vl[NV], vr[NV];
+#pragma unroll
+          for (int v = 0; v < NV; v++) {
+            // cells a (lower) and b (upper) of the face and their outer neighbours
+            const double pa0 = sP[v][bl - st], pa = sP[v][bl], pb = sP[v][bl + st], pb1 = sP[v][bl + 2 * st];
+            // the half slopes as the slope phase of k_stage_tile forms them: a
+            // toward its upper face phi(a - a0, b - a), b toward its lower face
+            // phi(b1 - b, b - a) (asymmetric limiters) or phi(b - a, b1 - b)
+            const double da = pa - pa0, dab = pb - pa, db = pb1 - pb;
+            const double su = 0.5 * limiter<LIM>(da, dab, th);
+            const double sl = lim_asym<LIM>() ? 0.5 * limiter<LIM>(db, dab, th) : 0.5 * limiter<LIM>(dab, db, th);
+            vl[v] = pa + su;
+            vr[v] = pb - sl;
+          }
+          if (yd) {
+            swap_xy<ND, PH>(vl);
+            swap_xy<ND, PH>(vr);
+          }
+          riemann<ND, PH, FLUX, 0>(vl, vr, F, P);
+          if (yd) swap_xy<ND, PH>(F);
+        }
+        double* fo = &sF[yd ? 1 : 0][0][0];
+#pragma unroll
+        for (int v = 0; v < NV; v++) fo[v * NFX + u] = F[v];
+      }
+      __syncthreads();
+
+      // (5) divergence (x, then y, then z) and the SSP combination
+#pragma unroll
+      for (int v = 0; v < NV; v++) {
+        double acc = (sF[0][v][ty * 17 + tx + 1] - sF[0][v][ty * 17 + tx]) * rdx;
+        acc = acc + (sF[1][v][(ty + 1) * NB + tx] - sF[1][v][ty * NB + tx]) * rdy;
+        acc = acc + Zk[v];
+        const double tmp = Ui[v] - dt * acc;
+        const double res = combine<NV>(a.stage, a.rk, a.stage > 1 ? Uo[v] : 0.0, tmp);
+        out[v * vs + (size_t)k * NB * NB] = res;
+        Ui[v] = res;
+      }
+      if (a.cflred) {
+        const double rd[3] = {rdx, rdy, rdz};
+        cfl_cell<ND, PH>(Ui, P, rd, csmax, ccmax, cbad);
+      }
+    }
+  }
+  if (a.cflred) cfl_fold(a.cflred, csmax, ccmax, cbad);
+}
+
+// ---------------------------------------------------------------------------
 // stage update, 1D: a leaf of nx cells in chunks of 256, one workgroup each
 // ---------------------------------------------------------------------------
 
@@ -1024,12 +1310,49 @@ hipError_t launch_stage_combined(const Geo& g, const LaunchCfg& c, const StageAr
                                  const Sched& s, int grid, hipStream_t st);
 hipError_t launch_stage_combined_fast(const Geo& g, const LaunchCfg& c, const StageArgs& a, const double* physp,
                                       const Sched& s, int grid, hipStream_t st);
+// the two-launch stage update of the 3D MHD forests (variant 2), in units of
+// their own (stage_zsplit.hip, and stage_zsplit_fast.hip in fast arithmetic)
+hipError_t launch_stage_zsplit(const Geo& g, const LaunchCfg& c, const StageArgs& a, const double* physp,
+                               const Sched& s, int grid, hipStream_t st);
+hipError_t launch_stage_zsplit_fast(const Geo& g, const LaunchCfg& c, const StageArgs& a, const double* physp,
+                                    const Sched& s, int grid, hipStream_t st);
 template <int ND, int PH, int LM>
 constexpr bool in_ilp_unit() {
   return ND >= 2 && PH != PH_MHD && !lim_asym<LM>();
 }
 
 #ifdef AMRV_STAGE_UNIT
+#if AMRV_STAGE_UNIT >= 2
+#if AMRV_STAGE_UNIT == 3
+#define AMRV_ZSPLIT_LAUNCHER launch_stage_zsplit_fast
+#define AMRV_ZSPLIT_AR 1
+#else
+#define AMRV_ZSPLIT_LAUNCHER launch_stage_zsplit
+#define AMRV_ZSPLIT_AR 0
+#endif
+// z columns over every leaf (one workgroup per leaf, XCD remap as the
+// schedule's), then the x/y planes in the schedule the forest uses
+hipError_t AMRV_ZSPLIT_LAUNCHER(const Geo& g, const LaunchCfg& c, const StageArgs& a, const double* physp,
+                                const Sched& s, int grid, hipStream_t st) {
+  Sched zs = s;
+  int zgrid = 1;
+  if (s.mode != 0) {
+    zs.mode = 1;
+    zgrid = s.xcd_remap ? 8 * ((g.n + 7) / 8) : g.n;
+  }
+  dispatch(c, [&](auto nd, auto ph, auto fl, auto lm) {
+    constexpr int ND = decltype(nd)::value, FL = decltype(fl)::value, LM = decltype(lm)::value;
+    constexpr int PH = decltype(ph)::value;
+    if constexpr (ND == 3 && PH == PH_MHD) {
+      hipLaunchKernelGGL((k_stage_zcol<PH, FL, LM, AMRV_ZSPLIT_AR>), dim3(zgrid), dim3(WGS), 0, st, g, a, physp, zs);
+      hipLaunchKernelGGL((k_stage_xy<PH, FL, LM, AMRV_ZSPLIT_AR>), dim3(grid), dim3(WGS), 0, st, g, a, physp, s);
+    }
+  });
+  return hipGetLastError();
+}
+#undef AMRV_ZSPLIT_LAUNCHER
+#undef AMRV_ZSPLIT_AR
+#else
 #if AMRV_STAGE_UNIT == 1
 #define AMRV_UNIT_LAUNCHER launch_stage_combined_fast
 #else
@@ -1047,6 +1370,7 @@ hipError_t AMRV_UNIT_LAUNCHER(const Geo& g, const LaunchCfg& c, const StageArgs&
   return hipGetLastError();
 }
 #undef AMRV_UNIT_LAUNCHER
+#endif  // AMRV_STAGE_UNIT >= 2
 #else
 
 hipError_t launch_restrict(const Geo& g, const LaunchCfg& c, const double* U, const int32_t* list, int nlist,
@@ -1116,6 +1440,11 @@ hipError_t launch_prolong(const Geo& g, const LaunchCfg& c, const double* U, con
 hipError_t launch_stage(const Geo& g, const LaunchCfg& c, const StageArgs& a, const double* physp, const Sched& s,
                         int grid, hipStream_t st) {
   bool combined = false;
+  if (c.variant == 2) {
+    if (c.ndim != 3 || c.phys != PH_MHD || a.Zd == nullptr) return hipErrorInvalidValue;
+    return c.arith == 1 ? launch_stage_zsplit_fast(g, c, a, physp, s, grid, st)
+                        : launch_stage_zsplit(g, c, a, physp, s, grid, st);
+  }
   dispatch(c, [&](auto nd, auto ph, auto fl, auto lm) {
     constexpr int ND = decltype(nd)::value, FL = decltype(fl)::value, LM = decltype(lm)::value;
     constexpr int PH = decltype(ph)::value;

@@ -79,11 +79,14 @@ __device__ __forceinline__ double dsqrt(double x) {
 // sqrt(gp / rho) = gp (gp rho)^(-1/2): one reciprocal square root instead of
 // a division and a square root
 __device__ __forceinline__ double dsound(double gp, double rho) { return gp * drsq(gp * rho); }
+// sqrt(x) for x >= 0 (the estimate alone would give 0 * inf at 0)
+__device__ __forceinline__ double dsqrt0(double x) { return x == 0.0 ? x : dsqrt(x); }
 #else
 __device__ __forceinline__ double drcp(double b) { return 1.0 / b; }
 __device__ __forceinline__ double ddiv(double a, double b) { return a / b; }
 __device__ __forceinline__ double dsqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ double dsound(double gp, double rho) { return sqrt(gp / rho); }
+__device__ __forceinline__ double dsqrt0(double x) { return sqrt(x); }
 #endif
 
 __device__ __forceinline__ double dmin(double a, double b) { return a < b ? a : b; }
@@ -231,7 +234,7 @@ __device__ __forceinline__ double wave_speed(const double* v, const PhysParams& 
   } else if constexpr (PH == PH_EULER) {
     return dsound(P.gamma * v[S::IE], v[0]);
   } else {
-    const double irho = 1.0 / v[0];
+    const double irho = drcp(v[0]);
     double bb = v[S::IB] * v[S::IB];
 #pragma unroll
     for (int d = 1; d < ND; d++) bb = bb + v[S::IB + d] * v[S::IB + d];
@@ -241,7 +244,7 @@ __device__ __forceinline__ double wave_speed(const double* v, const PhysParams& 
     const double s = a2 + b2;
     double disc = s * s - 4.0 * a2 * bn2;
     if (!(disc > 0.0)) disc = 0.0;
-    return sqrt(0.5 * (s + sqrt(disc)));
+    return dsqrt0(0.5 * (s + dsqrt0(disc)));
   }
 }
 
@@ -271,11 +274,11 @@ template <int LIM>
 __device__ __forceinline__ double limiter(double a, double b, double thr2 = 0.0) {
   if constexpr (LIM == LIM_CADA) {
     if (a == 0.0 && b == 0.0) return 0.0;  // flat: every branch gives 0
-    if (thr2 > 0.0 && a * a + b * b <= thr2) return (a + 2.0 * b) / 3.0;
+    if (thr2 > 0.0 && a * a + b * b <= thr2) return ddiv(a + 2.0 * b, 3.0);
     if (a == 0.0 || b == 0.0) return 0.0;  // H bounded, H(0) = 0
     const double sg = b > 0.0 ? 1.0 : -1.0;
     const double ap = sg * a, bp = sg * b;
-    const double p3 = (ap + 2.0 * bp) / 3.0;
+    const double p3 = ddiv(ap + 2.0 * bp, 3.0);
     double in = 2.0 * ap;
     in = p3 < in ? p3 : in;
     in = 1.6 * bp < in ? 1.6 * bp : in;
@@ -385,8 +388,8 @@ __device__ __forceinline__ void hllc_mhd(const double* vl, const double* vr, con
   const double ptl = vl[ie] + 0.5 * bbl, ptr = vr[ie] + 0.5 * bbr;
   const double rl = vl[0] * (sl - unl);
   const double rr = vr[0] * (sr - unr);
-  const double sm = ((ptr - ptl) + unl * rl - unr * rr) / (rl - rr);
-  const double ids = 1.0 / (sr - sl);
+  const double sm = ddiv((ptr - ptl) + unl * rl - unr * rr, rl - rr);
+  const double ids = drcp(sr - sl);
   double uh[NV];  // HLL state of density, momenta and field
 #pragma unroll
   for (int k = 0; k <= ND; k++) uh[k] = ((sr * ur[k] - sl * ul[k]) - (fr[k] - fl[k])) * ids;
@@ -403,7 +406,7 @@ __device__ __forceinline__ void hllc_mhd(const double* vl, const double* vr, con
   const double sk = left ? sl : sr;
   const double rk = left ? rl : rr;
   const double unk = vk[1 + N], ptk = left ? ptl : ptr;
-  const double inv = 1.0 / (sk - sm);
+  const double inv = drcp(sk - sm);
   const double coef = rk * inv;
   const double pts = ptk + rk * (sm - unk);
   const double bn = vk[ib + N];
@@ -417,7 +420,7 @@ __device__ __forceinline__ void hllc_mhd(const double* vl, const double* vr, con
       vs[d] = vk[1 + d];
       bs[d] = vk[ib + d] * ((sk - unk) * inv);
     } else {
-      vs[d] = uh[1 + d] / uh[0];
+      vs[d] = ddiv(uh[1 + d], uh[0]);
       bs[d] = uh[ib + d];
     }
   }
@@ -454,7 +457,7 @@ __device__ __forceinline__ void riemann(double* vl, double* vr, double* F, const
     double bns = 0.0, psis = 0.0;
     if constexpr (PH == PH_MHD) {
       constexpr int ib = S::IB + N, ip = S::IP;
-      bns = 0.5 * (vl[ib] + vr[ib]) - 0.5 * (vr[ip] - vl[ip]) / P.ch;
+      bns = 0.5 * (vl[ib] + vr[ib]) - ddiv(0.5 * (vr[ip] - vl[ip]), P.ch);
       psis = 0.5 * (vl[ip] + vr[ip]) - 0.5 * P.ch * (vr[ib] - vl[ib]);
       vl[ib] = bns;
       vr[ib] = bns;

@@ -87,3 +87,14 @@ def test_dam_break_poly_fast():
     R, dts = oracle.run(f, U, steps=10)
     G, E = _run_both(f, U, dts=dts)
     _check(f"dam break poly MC ({f.level_counts()})", f, G, E, R)
+
+
+@pytest.mark.parametrize("flux,lim", [(W.HLLC, W.CADA), (W.HLL, W.VANLEER)])
+def test_mhd_3d_two_launch_fast(flux, lim):
+    """The 3D MHD blast through stage-kernel variant 2 (z columns, then x/y
+    planes) in fast arithmetic: MHD-HLLC / HLL with the GLM sub-solve, the
+    fast magnetosonic speed and Cada's limiter from the refined estimates."""
+    f, U = W.mhd_blast(3, scheme=W.mhd_blast_scheme(3, base=2, max_level=3, flux=flux, limiter=lim))
+    R, dts = oracle.run(f, U, steps=6, ramp_steps=10)
+    G, E = _run_both(f, U, dts=dts, variant=2)
+    _check(f"mhd blast 3D variant 2 flux={flux} lim={lim} ({f.level_counts()})", f, G, E, R)

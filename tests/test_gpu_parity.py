@@ -250,6 +250,34 @@ def test_mhd_blast_matches_oracle(nd, flux):
     assert np.array_equal(G, R)
 
 
+@pytest.mark.parametrize("flux,lim", [(W.HLLC, W.CADA), (W.HLL, W.CADA), (W.HLLC, W.VANLEER), (W.TVDLF, W.MINMOD)])
+def test_mhd_3d_two_launch_variant_matches_oracle(flux, lim):
+    """Stage-kernel variant 2 of the 3D MHD forests (the z direction of every
+    column in one launch, then the x/y planes with the face states formed in
+    place) on the paper's MHD blast: bit for bit the oracle's under the grid
+    (XCD remap), persistent and per-block schedules and with graph replay,
+    and with a symmetric and an asymmetric limiter."""
+    F = _gpu()
+    f, U = W.mhd_blast(3, scheme=W.mhd_blast_scheme(3, base=2, max_level=3, flux=flux, limiter=lim))
+    R, dts = oracle.run(f, U, steps=4, ramp_steps=10)
+    for sched, graph in [((1, 1, 0), False), ((2, 0, 0), True), ((2, 1, 24), False), ((0, 0, 0), False)]:
+        G, gdts = F.run(f, U, steps=4, ramp_steps=10, schedule=sched, graph=graph, variant=2)
+        assert gdts == dts
+        _report(f"mhd blast 3D variant 2 flux={flux} lim={lim} sched={sched} graph={graph}", G, R, f)
+        assert np.array_equal(G, R)
+
+
+def test_two_launch_variant_is_3d_mhd_only():
+    from paper_2004_03275_amd import _native as N
+
+    F = _gpu()
+    for f, _ in (W.mhd_blast(2, scheme=W.mhd_blast_scheme(2, base=2, max_level=2)), _blast_small()):
+        g = F.GpuForest(f)
+        with pytest.raises(N.AmrvError):
+            g.set_variant(2)
+        g.close()
+
+
 def test_flags_identical():
     F = _gpu()
     for name, (f, U) in {"kh": W.kh(4), "blast": _blast_small(), "ot": W.orszag_tang(4)}.items():
