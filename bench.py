@@ -622,7 +622,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_stage_tile (stage update)",
+            "kernel": ("k_stage_zcol + k_stage_xy (stage update, two launches)" if sched[3] == 2
+                       else "k_stage_tile (stage update)"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
