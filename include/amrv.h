@@ -307,9 +307,10 @@ int amrv_get_variant(const amrv_forest* f, int32_t* variant);
  * division, reciprocal, square root and the sound speed sqrt(gamma p/rho)
  * from the hardware reciprocal (square root) estimates refined by Newton
  * steps: each within a few ulp of the correctly rounded value, the stage
- * results within the 1e-10 relative-L1 bar of the oracle, not bit for bit.
- * Other configurations (1D, MHD, Koren, Cada, the split variant) run exact
- * in either mode.  Ghost prolongation, Courant reduction outside the stage
+ * results within the 1e-10 relative-L1 bar of the oracle, not bit for bit;
+ * likewise the two-launch update of 3D MHD forests (variant 2).  Other
+ * configurations (1D, 2D MHD, the one-launch MHD kernels, Koren, Cada outside
+ * variant 2, the split variant) run exact in either mode.  Ghost prolongation, Courant reduction outside the stage
  * kernel and Loehner flags are always exact. */
 #define AMRV_ARITH_EXACT 0
 #define AMRV_ARITH_FAST 1
