@@ -83,3 +83,19 @@ def test_blast_forest_tables_build():
     assert len(f.level_counts()) == 3
     n, err = _ws(f)
     assert n > 0, err
+
+
+def test_workspace_holds_the_z_buffer_of_3d_mhd_only():
+    """3D MHD forests carry one more state-sized buffer (the z flux divergence
+    of the two-launch stage update); the same leaves with Euler do not."""
+    if not os.path.exists(N.LIB_PATH):
+        pytest.skip("libamrv.so not built")
+    f, _ = W.mhd_blast(3, scheme=W.mhd_blast_scheme(3, base=2, max_level=2))
+    n_mhd, err = _ws(f)
+    assert n_mhd > 0, err
+    state = f.scheme.nvar * f.n * f.scheme.cells_per_block * 8
+    assert n_mhd >= 4 * state
+    f2, _ = W.mhd_blast(2, scheme=W.mhd_blast_scheme(2, base=2, max_level=2))
+    n2, err = _ws(f2)
+    state2 = f2.scheme.nvar * f2.n * f2.scheme.cells_per_block * 8
+    assert 3 * state2 <= n2 < 4 * state2, err
