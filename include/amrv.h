@@ -60,9 +60,9 @@ extern "C" {
 #define AMRV_MINMOD 0
 #define AMRV_VANLEER 1
 #define AMRV_MC 2 /* monotonized central ('woodward', Sec. 2.3.1) */
-#define AMRV_KOREN 3 /* Koren (Sec. 2.2, 2.3.2); runs the split stage-kernel variant */
+#define AMRV_KOREN 3 /* Koren (Sec. 2.2, 2.3.2); asymmetric: two half slopes per cell */
 #define AMRV_CADA 4  /* Cada's third order (Sec. 2.4 blast runs; LimO3 of Cada and Torrilhon 2009;
-                        its smoothness switch with cada_radius > 0); split variant */
+                        its smoothness switch with cada_radius > 0); asymmetric */
 #define AMRV_BC_PERIODIC 0
 #define AMRV_BC_ZERO_GRADIENT 1
 
@@ -303,15 +303,15 @@ int amrv_get_variant(const amrv_forest* f, int32_t* variant);
  * operation correctly rounded, no contraction, in the oracle's order, so
  * results equal the oracle's bit for bit.  AMRV_ARITH_FAST: the combined-
  * variant stage kernels of the 2D/3D hydrodynamic systems (Euler, polytrope;
- * minmod, van Leer, MC) with multiply-adds contracted into FMAs, and
+ * every limiter) with multiply-adds contracted into FMAs, and
  * division, reciprocal, square root and the sound speed sqrt(gamma p/rho)
  * from the hardware reciprocal (square root) estimates refined by Newton
  * steps: each within a few ulp of the correctly rounded value, the stage
  * results within the 1e-10 relative-L1 bar of the oracle, not bit for bit;
  * likewise the two-launch update of 3D MHD forests (variant 2).  Other
- * configurations (1D, 2D MHD, the one-launch MHD kernels, Koren, Cada outside
- * variant 2, the split variant) run exact in either mode.  Ghost prolongation, Courant reduction outside the stage
- * kernel and Loehner flags are always exact. */
+ * configurations (1D, 2D MHD, the one-launch MHD kernels, the split variant)
+ * run exact in either mode.  Ghost prolongation, the Courant reduction outside
+ * the stage kernel and Loehner flags are always exact. */
 #define AMRV_ARITH_EXACT 0
 #define AMRV_ARITH_FAST 1
 int amrv_set_arithmetic(amrv_forest* f, int32_t mode);

@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(WGS) k_transfer(Geo gf, const double* __restri
 // rounded, no contraction; 1: the fast-arithmetic unit, stage_fast.hip); the
 // body is the same text.
 template <int ND, int PH, int FLUX, int LIM, bool SPLIT, int AR>
-__global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>::NV <= 5) ? 3 : 1) k_stage_tile(Geo g, StageArgs a, const double* __restrict__ pp,
+__global__ void __launch_bounds__(WGS, (Sys<ND, PH>::NV > 5) ? 1 : (SPLIT ? (lim_asym<LIM>() ? 1 : 3) : (lim_asym<LIM>() && AR == 0 ? 2 : 1))) k_stage_tile(Geo g, StageArgs a, const double* __restrict__ pp,
                                                                   Sched sc) {
   using S = Sys<ND, PH>;
   constexpr int NV = S::NV;
@@ -308,14 +308,17 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
   // an asymmetric limiter keeps two half slopes per cell (toward the upper
   // and toward the lower face) and runs the split variant only
   constexpr bool ASYM = lim_asym<LIM>();
-  static_assert(!ASYM || SPLIT, "asymmetric limiters use the split variant");
+  // the combined variant with an asymmetric limiter forms each face's two
+  // states in the flux phase from four primitives (each half slope serves that
+  // one face only, so nothing is computed twice), with no slope phase
+  constexpr bool RCF = ASYM && !SPLIT;
   constexpr int NSS = (SPLIT && !ASYM) ? 1 : 2;
   __shared__ double sP[NV][PW * PW];  // primitive plane incl. x/y ghost ring, (y+2)*PW + x+2
-  __shared__ double sS[NSS][NV][NSX]; // half slopes 0.5*phi: x [row][cell+1]; y [cell+1][column]
+  __shared__ double sS[RCF ? 1 : NSS][NV][RCF ? 1 : NSX]; // half slopes 0.5*phi: x [row][cell+1]; y [cell+1][column]
                                       // (asymmetric: [0] toward the upper, [1] toward the lower face)
   __shared__ double sF[NSB][NV][NFX]; // fluxes: x [row][face]; y [face][column]
   auto& sSx = sS[0];
-  auto& sSy = sS[NSS - 1];
+  auto& sSy = sS[RCF ? 0 : NSS - 1];
   auto& sFx = sF[0];
   auto& sFy = sF[NSB - 1];
   __shared__ double sZF[ND == 3 ? NV : 1][ND == 3 ? NB * NB : 1];  // +z coarse-fine face flux of the own column
@@ -551,6 +554,7 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
       const int rf = (tid + 64 * (k + leaf + 2)) & (WGS - 1);
       // (3) limited slopes of the plane's cells (and the first ghost layer)
       auto slopes = [&](int t0, int t1) {
+        if constexpr (RCF) return;  // no slope phase (above)
 #pragma unroll
         for (int j = 0; j < 3; j++) {
           const int t = t0 + rs + j * WGS;
@@ -575,7 +579,7 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
             const double sa = v0 - vm, sb = vp - v0;
             const double th = yd ? thy : thx;
             const double sl = 0.5 * limiter<LIM>(sa, sb, th);
-            if constexpr (ASYM) {
+            if constexpr (ASYM && !RCF) {
               sS[0][v][u] = sl;
               sS[1][v][u] = 0.5 * limiter<LIM>(sb, sa, th);
             } else if (!yd) {
@@ -617,13 +621,28 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
           if (bf >= 0 && !(kinds[bf] == NB_SAME || kinds[bf] == NB_BND)) {
             cf_flux<NV, ND>(g, leaf, bf, kinds[bf], r, k, F);
           } else {
-            const double* slu = &sS[ASYM ? 0 : (yd ? NSS - 1 : 0)][0][0];  // toward the upper face
-            const double* sll = &sS[ASYM ? 1 : (yd ? NSS - 1 : 0)][0][0];  // toward the lower face
             double vl[NV], vr[NV];
+            if constexpr (RCF) {
+              // cells a (lower) and b (upper) of the face and their outer
+              // neighbours: a's half slope toward its upper face phi(a - a0,
+              // b - a), b's toward its lower face phi(b1 - b, b - a), as the
+              // slope phase forms them
+              const double th = yd ? thy : thx;
 #pragma unroll
-            for (int v = 0; v < NV; v++) {
-              vl[v] = sP[v][bl] + slu[v * NSX + s0];
-              vr[v] = sP[v][bl + st] - sll[v * NSX + s1];
+              for (int v = 0; v < NV; v++) {
+                const double pa0 = sP[v][bl - st], pa = sP[v][bl], pb = sP[v][bl + st], pb1 = sP[v][bl + 2 * st];
+                const double da = pa - pa0, dab = pb - pa, db = pb1 - pb;
+                vl[v] = pa + 0.5 * limiter<LIM>(da, dab, th);
+                vr[v] = pb - 0.5 * limiter<LIM>(db, dab, th);
+              }
+            } else {
+              const double* slu = &sS[ASYM ? 0 : (yd ? NSS - 1 : 0)][0][0];  // toward the upper face
+              const double* sll = &sS[ASYM ? 1 : (yd ? NSS - 1 : 0)][0][0];  // toward the lower face
+#pragma unroll
+              for (int v = 0; v < NV; v++) {
+                vl[v] = sP[v][bl] + slu[v * NSX + s0];
+                vr[v] = sP[v][bl + st] - sll[v * NSX + s1];
+              }
             }
             if (yd) {
               swap_xy<ND, PH>(vl);
@@ -639,8 +658,10 @@ __global__ void __launch_bounds__(WGS, (SPLIT && !lim_asym<LIM>() && Sys<ND, PH>
       };
       double accx[NV];
       if constexpr (!SPLIT) {
-        slopes(0, 2 * NSX);
-        __syncthreads();
+        if constexpr (!RCF) {
+          slopes(0, 2 * NSX);
+          __syncthreads();
+        }
         fluxes(0, 2 * NFX);
         __syncthreads();
 #pragma unroll
@@ -1318,7 +1339,7 @@ hipError_t launch_stage_zsplit_fast(const Geo& g, const LaunchCfg& c, const Stag
                                     const Sched& s, int grid, hipStream_t st);
 template <int ND, int PH, int LM>
 constexpr bool in_ilp_unit() {
-  return ND >= 2 && PH != PH_MHD && !lim_asym<LM>();
+  return ND >= 2 && PH != PH_MHD;
 }
 
 #ifdef AMRV_STAGE_UNIT
@@ -1450,7 +1471,7 @@ hipError_t launch_stage(const Geo& g, const LaunchCfg& c, const StageArgs& a, co
     constexpr int PH = decltype(ph)::value;
     if constexpr (ND == 1)
       hipLaunchKernelGGL((k_stage_line<PH, FL, LM>), dim3(grid), dim3(WGS), 0, st, g, a, physp, s);
-    else if (c.variant == 1 || lim_asym<LM>())
+    else if (c.variant == 1 || (lim_asym<LM>() && !in_ilp_unit<ND, PH, LM>()))
       hipLaunchKernelGGL((k_stage_tile<ND, PH, FL, LM, true, 0>), dim3(grid), dim3(WGS), 0, st, g, a, physp, s);
     else if constexpr (in_ilp_unit<ND, PH, LM>())
       combined = true;

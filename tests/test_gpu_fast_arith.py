@@ -46,7 +46,8 @@ def test_blast_small_amr_fast():
     _check(f"blast small ({f.level_counts()})", f, G, E, R)
 
 
-@pytest.mark.parametrize("flux,lim", [(W.HLLC, W.VANLEER), (W.HLL, W.MINMOD), (W.TVDLF, W.MC)])
+@pytest.mark.parametrize("flux,lim", [(W.HLLC, W.VANLEER), (W.HLL, W.MINMOD), (W.TVDLF, W.MC), (W.HLLC, W.KOREN),
+                                      (W.HLL, W.CADA)])
 def test_kh_small_fast(flux, lim):
     s = W.kh_scheme(4)
     s.flux, s.limiter = flux, lim
@@ -98,3 +99,16 @@ def test_mhd_3d_two_launch_fast(flux, lim):
     R, dts = oracle.run(f, U, steps=6, ramp_steps=10)
     G, E = _run_both(f, U, dts=dts, variant=2)
     _check(f"mhd blast 3D variant 2 flux={flux} lim={lim} ({f.level_counts()})", f, G, E, R)
+
+
+@pytest.mark.parametrize("lim", [W.KOREN, W.CADA])
+def test_blast_3d_asymmetric_limiters_fast(lim):
+    """The combined 3D kernel with an asymmetric limiter (face states formed
+    in the flux phase) in fast arithmetic."""
+    s = W.blast_scheme(base=2, max_level=3)
+    s.limiter = lim
+    f = W.blast_forest(s, radius=0.2, buffer_cells=2.0)
+    _, U = W.blast(s, radius=0.2, forest=f)
+    R, dts = oracle.run(f, U, steps=4)
+    G, E = _run_both(f, U, dts=dts, variant=0)
+    _check(f"blast small lim={lim}", f, G, E, R)
