@@ -180,15 +180,13 @@ int enqueue_ghosts(amrv_forest* f, const Geo& geo, const double* U, bool fluxes,
 // the stage kernel restricts its own result (3D combined variant, not MHD,
 // whose damping of psi after the step would make the restriction stale)
 bool fused_restriction(const amrv_forest* f) {
-  return f->tab.nd == 3 && f->lc.variant == 0 && f->lc.phys != PH_MHD && f->lc.lim != AMRV_KOREN &&
-         f->lc.lim != AMRV_CADA && !f->tab.rlist.empty();
+  return f->tab.nd == 3 && f->lc.variant == 0 && f->lc.phys != PH_MHD && !f->tab.rlist.empty();
 }
 
 // the last stage writes the learned flagger's features of its result (3D
-// combined variant of the hydrodynamic systems, symmetric limiters)
+// combined variant of the hydrodynamic systems)
 bool fused_features(const amrv_forest* f) {
-  return f->fuse_feat && f->tab.nd == 3 && f->lc.variant == 0 && f->lc.phys != PH_MHD &&
-         f->lc.lim != AMRV_KOREN && f->lc.lim != AMRV_CADA;
+  return f->fuse_feat && f->tab.nd == 3 && f->lc.variant == 0 && f->lc.phys != PH_MHD;
 }
 
 int enqueue_stage_update(amrv_forest* f, const Geo& geo, const StageArgs& a, int mode) {
