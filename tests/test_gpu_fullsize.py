@@ -9,7 +9,10 @@
   Loehner flags and regrid;
 * 3D AMR blast on the path bench.py times: autotuned schedule, HIP-graph
   replay, 20 steps of amrv_advance_cfl (device-computed dt) in chunks of 5,
-  Loehner flags after steps 10 and 20 as in the timed region.
+  Loehner flags after steps 10 and 20 as in the timed region;
+* the paper's 3D MHD blast (512 leaves of 16^3, 9 variables) through the
+  two-launch stage update (variant 2), exact and fast arithmetic, 8 steps with
+  the Courant ramp.
 The bar is relative L1 <= 1e-10 per variable; the runs are in fact equal
 bit for bit, which is asserted too.
 """
@@ -165,3 +168,26 @@ def test_blast_timed_path_20_steps():
     for g, _ in gs.values():
         g.close()
     o.close()
+
+
+@pytest.mark.parametrize("arith", [0, 1])
+def test_mhd_blast_3d_full_size_two_launch(arith):
+    """The bench's 3D MHD workload through stage-kernel variant 2 with the
+    grid schedule and graph replay, 8 steps with the host-chosen ramped dt:
+    bit for bit in exact arithmetic, within the bar in fast arithmetic."""
+    from paper_2004_03275_amd import _native as N
+    from paper_2004_03275_amd import forest as F
+
+    f, U = W.mhd_blast(3, base=4, max_level=3)
+    t0 = time.time()
+    R, dts = oracle.run(f, U, steps=8, ramp_steps=10)
+    G, gdts = F.run(f, U, steps=8, ramp_steps=10, schedule=(N.SCHED_GRID, 1, 0), graph=True, variant=2,
+                    arithmetic=N.ARITH_FAST if arith else N.ARITH_EXACT)
+    e = W.relative_l1(G, R, f).max()
+    print(f"[full] mhd blast 3D ({f.n} leaves) variant 2 arithmetic {arith}: rel L1 {e:.3e}, "
+          f"bitwise {np.array_equal(G, R)}, dt equal {gdts == dts} ({time.time() - t0:.1f} s)", flush=True)
+    if arith == 0:
+        assert gdts == dts
+        assert np.array_equal(G, R)
+    else:
+        assert e <= TOL
