@@ -1,0 +1,128 @@
+"""Pins of the forest Helmholtz oracle (oracle/fmg.py) against what fixes it
+from outside: the uniform-grid exact solve (oracle/rd.py, spectral), exact
+reproduction of constants and linear functions by every ghost rule, mirror
+and transposition symmetry, and second-order convergence to a smooth
+solution across coarse-fine faces (Sec. 1.4)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fmg, rd
+
+
+def _uniform_to_grid(forest, u):
+    """Leaf layout [leaf][y][x] of a uniform forest -> [y][x] of the grid."""
+    s = forest.scheme
+    nb = s.block_nx[0]
+    n = (s.base_blocks[0] << (int(forest.level[0]) - 1)) * nb
+    out = np.zeros((n, n))
+    for k in range(forest.n):
+        i, j = forest.ijk[k, :2]
+        out[j * nb:(j + 1) * nb, i * nb:(i + 1) * nb] = u[k]
+    return out
+
+
+@pytest.mark.parametrize("bc", [fmg.PERIODIC, fmg.NEUMANN])
+def test_uniform_forest_is_the_uniform_grid(bc):
+    """Every leaf at level 2: the composite problem is the 5-point problem on
+    the 64^2 grid, which oracle/rd.py solves spectrally."""
+    s = W.fmg_scheme(base=2, max_level=2, bc=bc)
+    f = W.uniform_forest(s, level=2)
+    x, y = fmg.cell_centres(f, 1.0)
+    rhs = np.sin(2 * np.pi * x) * np.cos(4 * np.pi * y) + x * y
+    lam = 37.0
+    u = fmg.solve(f, rhs, lam, 1.0, bc)
+    ref = rd.helmholtz_solve(_uniform_to_grid(f, rhs), lam, 1.0, bc)
+    assert np.max(np.abs(_uniform_to_grid(f, u) - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def _refined(bc, base=4, max_level=3):
+    """A circle off the centre: levels 1, 2 and 3 for base >= 4."""
+    return W.fmg_forest(W.fmg_scheme(base=base, max_level=max_level, bc=bc), centre=(0.27, 0.3), radius=0.15)
+
+
+@pytest.mark.parametrize("bc", [fmg.PERIODIC, fmg.NEUMANN])
+def test_constants_are_reproduced(bc):
+    f = _refined(bc)
+    assert len(np.unique(f.level)) == 3
+    lam = 5.0
+    u = fmg.solve(f, np.full((f.n, 16, 16), -lam * 2.5), lam, 1.0, bc)
+    assert np.max(np.abs(u - 2.5)) <= 1e-12
+
+
+def test_linear_functions_have_zero_laplacian_off_the_boundary():
+    """Rules (1) and (3) interpolate linear data exactly, so lap(a x + b y +
+    c) vanishes at every cell whose stencil stays inside the domain -- a wrong
+    weight, offset sign, tangential half or restriction shows up here."""
+    f = _refined(fmg.NEUMANN)
+    x, y = fmg.cell_centres(f, 1.0)
+    u = 0.7 * x - 1.3 * y + 0.2
+    lap = fmg.apply(f, u, 0.0, 1.0, fmg.NEUMANN)
+    n = (4 << (f.level.astype(np.int64) - 1)) * 16
+    h = 1.0 / n[:, None, None]
+    interior = (x > h) & (x < 1 - h) & (y > h) & (y < 1 - h)
+    assert interior.sum() > 0.9 * u.size
+    # lap is O(1/h^2) * rounding of O(1) values
+    assert np.max(np.abs(lap[interior])) <= 1e-9 * np.max(1.0 / h ** 2)
+    assert np.max(np.abs(lap[~interior])) > 1.0  # the Neumann faces do see the slope
+
+
+def test_mirror_and_transpose_symmetry():
+    """A forest symmetric under x -> 1 - x and x <-> y, with the data mirrored
+    or transposed, has the mirrored or transposed solution."""
+    s = W.fmg_scheme(base=8, max_level=3, bc=fmg.NEUMANN)
+    f = W.fmg_forest(s, centre=(0.5, 0.5), radius=0.15)
+    assert len(np.unique(f.level)) == 3
+    x, y = fmg.cell_centres(f, 1.0)
+    lam = 11.0
+
+    def field(a, b):
+        return np.exp(-30 * ((a - 0.3) ** 2 + (b - 0.6) ** 2)) + 0.3 * a
+
+    u = fmg.solve(f, field(x, y), lam, 1.0, fmg.NEUMANN)
+    key = {(int(l), int(i), int(j)): k for k, (l, (i, j, _)) in enumerate(zip(f.level, f.ijk))}
+    um = fmg.solve(f, field(1 - x, y), lam, 1.0, fmg.NEUMANN)
+    ut = fmg.solve(f, field(y, x), lam, 1.0, fmg.NEUMANN)
+    for k in range(f.n):
+        l, i, j = int(f.level[k]), int(f.ijk[k, 0]), int(f.ijk[k, 1])
+        nbl = 8 << (l - 1)
+        km = key[(l, nbl - 1 - i, j)]
+        kt = key[(l, j, i)]
+        assert np.allclose(um[km][:, ::-1], u[k], rtol=0, atol=1e-12)
+        assert np.allclose(ut[kt].T, u[k], rtol=0, atol=1e-12)
+
+
+def test_second_order_convergence_across_coarse_fine_faces():
+    """A smooth Neumann-compatible solution u = cos(2 pi x) cos(4 pi y), f =
+    -(20 pi^2 + lambda) u, on one three-level block forest with 8, 16, 32 and
+    64 cells per block side: the maximum error falls at second order (a
+    non-conservative coarse side, the mean of the children as its ghost,
+    falls at first order on the same forests)."""
+    lam = 3.0
+    f0 = _refined(fmg.NEUMANN)
+    assert len(np.unique(f0.level)) == 3
+    errs = []
+    for nb in (8, 16, 32, 64):
+        s = W.fmg_scheme(base=4, max_level=3, bc=fmg.NEUMANN)
+        s.block_nx = (nb, nb, 1)
+        f = W.Forest(s, f0.level, f0.ijk)
+        x, y = fmg.cell_centres(f, 1.0)
+        ue = np.cos(2 * np.pi * x) * np.cos(4 * np.pi * y)
+        u = fmg.solve(f, -(20 * np.pi ** 2 + lam) * ue, lam, 1.0, fmg.NEUMANN)
+        errs.append(np.max(np.abs(u - ue)))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders >= 1.9), (errs, orders)
+    assert errs[1] < 5e-3
+
+
+@pytest.mark.parametrize("bc", [fmg.PERIODIC, fmg.NEUMANN])
+def test_discrete_conservation(bc):
+    """Rule (4) makes the coarse flux through a coarse-fine face the mean of
+    the fine fluxes: the area-weighted sum of lap(u) over all leaf cells is
+    zero for any u on a periodic or Neumann domain."""
+    f = _refined(bc)
+    u = W.uniform01(7, f.n * 256).reshape(f.n, 16, 16)
+    lap = fmg.apply(f, u, 0.0, 1.0, bc)
+    area = (1.0 / ((4 << (f.level.astype(np.int64) - 1)) * 16)) ** 2
+    total = np.sum(lap * area[:, None, None])
+    assert abs(total) <= 1e-12 * np.sum(np.abs(lap) * area[:, None, None])
