@@ -163,6 +163,81 @@ int amrv_rd_step(amrv_mg* m, const amrv_rd_params* p, int32_t scheme, double dt,
 int amrv_mg_profile(amrv_mg* m, int32_t enable);
 int amrv_mg_profile_read(amrv_mg* m, double* ms_total, int64_t* cycles);
 
+/* ---------------------------------------------------------------------------
+ * Helmholtz problem on a 2D block-adaptive forest (Sec. 1.4: the geometric
+ * multigrid on the block-adaptive quadtree grid).
+ *
+ * Grid: the leaves of a quadtree forest of 16 x 16-cell blocks on the square
+ * [0, L]^2, base x base blocks at level 1 (base a power of two), leaf k at
+ * level leaf_level[k] (1..max_level) with block coordinates leaf_ijk[3k],
+ * leaf_ijk[3k + 1] at that level (leaf_ijk[3k + 2] = 0), the leaves covering
+ * the square without overlap and 2:1 balanced across faces.  A field is one
+ * binary64 value per leaf cell, [leaf][y][x] with x fastest (the forest's
+ * state layout of one variable), in device memory.
+ *
+ * Problem: lap(u) - lambda u = f, lambda > 0, lap of a cell the 5-point sum
+ * at the cell's own level, (u_W + u_E + u_S + u_N - 4 u) / h_l^2, h_l =
+ * L / (16 base 2^(l-1)).  The value across a face is the same-level leaf's
+ * cell; at a domain face the periodic image or the zero-Neumann mirror (the
+ * cell itself); on the fine side of a coarse-fine face (u + 2 u_c) / 3, u_c
+ * the coarse cell across the face moved a quarter coarse cell along the face
+ * with the coarse block's own tangential difference (central, one-sided at
+ * its edges); on the coarse side u + (4/3) (m - u), m the mean of the two
+ * fine cells touching the face (the mean of the two fine fluxes: the scheme
+ * is conservative and second order).  The coarse-fine stencils are this
+ * library's reading: the paper defers them to its multigrid library.
+ *
+ * Solver: V-cycles of the full approximation scheme over the block tree
+ * (every ancestor of a leaf is a 16 x 16 block holding the mean of its
+ * children), red-black Gauss-Seidel with pre_sweeps / post_sweeps sweeps per
+ * level, bilinear interpolation of the coarse change within each parent, and
+ * the uniform solver above on the complete level-1 grid.  Stops when the
+ * maximum residual of the problem over the leaf cells is at most tol times
+ * max |f|, or after max_cycles cycles (AMRV_ENOTCONVERGED, phi holding the
+ * last iterate).  Host-synchronous: every cycle reads its residual back. */
+
+typedef struct amrv_fmg amrv_fmg;
+
+typedef struct {
+  int64_t nleaves;     /* leaves, >= 1 */
+  int32_t base;        /* level-1 blocks per side: a power of two, 1..512 */
+  int32_t max_level;   /* 1..16 */
+  int32_t bc;          /* AMRV_MG_PERIODIC or AMRV_MG_NEUMANN */
+  int32_t pre_sweeps;  /* red-black sweeps per level on the way down (1..8) */
+  int32_t post_sweeps; /* and on the way up (1..8) */
+  int32_t pad;
+  double length;       /* L > 0 */
+} amrv_fmg_config;
+
+/* Bytes of device workspace for this forest (256-byte aligned start), or 0
+ * with amrv_last_error() set (AMRV_EINVAL for a bad configuration,
+ * AMRV_EUNBALANCED for leaves that overlap, leave gaps or break 2:1
+ * balance).  leaf_level [nleaves], leaf_ijk [nleaves][3]: host. */
+size_t amrv_fmg_workspace_bytes(const amrv_fmg_config* cfg, const int32_t* leaf_level, const int32_t* leaf_ijk);
+
+/* Builds the block tree and its tables in the caller's workspace (device
+ * memory of at least amrv_fmg_workspace_bytes, owned by the caller, alive
+ * until destroy), on the given HIP stream (NULL: the null stream).
+ * Allocates only pinned host memory for the residual read-back (and the
+ * level-1 solver's).  Returns 0 or a negative AMRV_E* code. */
+int amrv_fmg_create(const amrv_fmg_config* cfg, const int32_t* leaf_level, const int32_t* leaf_ijk,
+                    void* workspace, size_t bytes, void* stream, amrv_fmg** out);
+int amrv_fmg_destroy(amrv_fmg* m);
+
+/* Blocks per level of the tree (levels 1..16; 0 beyond the finest), host
+ * array of 16. */
+int amrv_fmg_levels(const amrv_fmg* m, int32_t* nblocks_per_level);
+
+/* Solves lap(phi) - lambda phi = f on the leaf cells (f, phi: device fields
+ * of nleaves * 256 doubles; phi holds the initial guess on entry and the
+ * solution on return).  cycles, res_max, f_max (host, may be NULL) receive
+ * the V-cycle count, the final maximum residual and max |f|.  Returns 0,
+ * AMRV_ENOTCONVERGED, AMRV_ENONPHYSICAL (NaN or infinity in f, phi or the
+ * residual), AMRV_EINVAL (lambda <= 0, tol <= 0, max_cycles < 0) or
+ * AMRV_EDEVICE. */
+int amrv_fmg_solve(amrv_fmg* m, const double* f, double* phi, double lambda, double tol, int32_t max_cycles,
+                   int32_t* cycles, double* res_max, double* f_max);
+
 #ifdef __cplusplus
 }
 #endif

@@ -79,6 +79,14 @@ class MgConfig(ctypes.Structure):
                 ("smoother", ctypes.c_int32), ("length", ctypes.c_double)]
 
 
+class FmgConfig(ctypes.Structure):
+    """amrv_fmg_config (include/amrv_mg.h)."""
+
+    _fields_ = [("nleaves", ctypes.c_int64), ("base", ctypes.c_int32), ("max_level", ctypes.c_int32),
+                ("bc", ctypes.c_int32), ("pre_sweeps", ctypes.c_int32), ("post_sweeps", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("length", ctypes.c_double)]
+
+
 class RdParams(ctypes.Structure):
     """amrv_rd_params (include/amrv_mg.h)."""
 
@@ -152,6 +160,12 @@ SIGNATURES = {
     "amrv_mg_set_coefficient": ([P, P], ctypes.c_int),
     "amrv_mg_profile": ([P, ctypes.c_int32], ctypes.c_int),
     "amrv_mg_profile_read": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "amrv_fmg_workspace_bytes": ([ctypes.POINTER(FmgConfig), P, P], ctypes.c_size_t),
+    "amrv_fmg_create": ([ctypes.POINTER(FmgConfig), P, P, P, ctypes.c_size_t, P, ctypes.POINTER(P)], ctypes.c_int),
+    "amrv_fmg_destroy": ([P], ctypes.c_int),
+    "amrv_fmg_levels": ([P, P], ctypes.c_int),
+    "amrv_fmg_solve": ([P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "amrv_last_error": ([], ctypes.c_char_p),
 }
 

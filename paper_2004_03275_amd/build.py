@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libamrv.so")
 
-SOURCES = ["kernels.hip", "mlp.hip", "multigrid.hip", "gridcopy.hip", "forest.cpp", "regrid.cpp", "api.cpp"]
+SOURCES = ["kernels.hip", "mlp.hip", "multigrid.hip", "fmg.hip", "gridcopy.hip", "forest.cpp", "regrid.cpp", "api.cpp"]
 
 # binary64 results are reproducible bit for bit only without contraction;
 # packed-FP32 instructions are kept out of every HIP build

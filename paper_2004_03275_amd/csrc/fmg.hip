@@ -1,0 +1,759 @@
+// fmg.hip -- Helmholtz solver on a 2D block-adaptive quadtree forest
+// (declared in include/amrv_mg.h; the multigrid of Sec. 1.4 on the block-
+// adaptive grid), by full-approximation-scheme V-cycles over the block tree.
+//
+// The problem on the leaf cells: lap(u) - lambda u = f, the 5-point lap of a
+// cell at its own level, the value across a face from
+//   a leaf cell at the same level;
+//   the zero-Neumann mirror at a non-periodic domain face (periodic faces
+//     wrap through the neighbour table);
+//   the fine side of a coarse-fine face: (u + 2 u_c) / 3, u_c the coarse
+//     leaf's cell across the face moved a quarter coarse cell along it with
+//     the coarse block's own tangential difference (central, one-sided at
+//     its edges);
+//   the coarse side: u + (4/3) (m - u), m the mean of the two fine cells
+//     touching the face -- the mean of the two fine fluxes, so the scheme is
+//     conservative.
+//
+// The tree: every leaf and every ancestor of a leaf is a block of 16 x 16
+// cells, the blocks of a level stored one after another (level 1 first).  A
+// parent holds the mean of its children's 2 x 2 cells.  The grid of level l
+// is every block of that level, relaxed with the plain stencil (a refined
+// neighbour's own cells in place of the coarse side of a coarse-fine face;
+// on the finest level this is the problem's stencil) and the right-hand
+// side of the full approximation scheme L(u) + r: r the restricted residual
+// of a parent, the problem's residual of a leaf (f itself where the plain
+// stencil is the problem's).  So a coarse leaf and the refined block beside
+// it relax one operator, and the fixed point is the problem's solution.
+//
+// A V-cycle: from the finest level down to level 2, `pre` red-black sweeps,
+// the residual, its restriction with the state's into the parents, and the
+// parents' coarse right-hand side; on level 1 (complete: base x base blocks)
+// `pre` sweeps, then the uniform-grid solver of multigrid.hip on the level-1
+// grid for the correction L(e) = r (from e = 0, to 1e-4 of r), then `post`
+// sweeps; back up, every block adds the bilinear interpolation (within its
+// parent) of the parent's change since restriction, then `post` sweeps.
+// After each cycle the problem's residual over the leaves is reduced and
+// read back for the stopping rule max |r| <= tol max |f|.
+//
+// Layout in the caller's workspace (256-byte aligned arrays):
+//   tables   lvl, ij[2], nbr[4], chi[4], cnb[4], par per block; leaf -> block
+//   u, f, fu, r, uo  [block][256] doubles (state, relaxation right-hand
+//                 side, the problem's f, residual or restricted residual,
+//                 restricted state)
+//   fgrid, vgrid  the level-1 grid (n = 16 base cells per side) for the
+//                 uniform solver, and that solver's own workspace
+//   red           two 64-bit maxima
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/amrv_mg.h"
+#include "errors.hpp"
+
+namespace {
+
+using amrv::set_error;
+
+constexpr int NB = 16;
+constexpr int NC = NB * NB;
+constexpr int FMG_MAXL = 16;
+constexpr int NBR_NONE = -1;  // no block of the same level across the face (a coarser leaf is)
+constexpr int NBR_WALL = -2;  // a non-periodic domain face
+constexpr size_t ALIGN = 256;
+
+struct FmgDev {
+  const int* lvl;
+  const int* ij;   // [block][2]
+  const int* nbr;  // [block][4]: -x, +x, -y, +y; a block index, NBR_NONE or NBR_WALL
+  const int* chi;  // [block][4]: children (x fastest), -1 for a leaf
+  const int* cnb;  // [block][4]: the coarser leaf across a face whose nbr is NBR_NONE
+  const int* par;  // [block]: parent, -1 on level 1
+  double* u;
+  double* f;   // right-hand side of the relaxation: the problem's f on the finest level, else L(u) + r
+  double* fu;  // the problem's f on the leaves
+  double* r;
+  double* uo;
+  double lam;
+  double ih2[FMG_MAXL + 1];  // 1/h^2 per level (1-based)
+};
+
+// the value across face `face` of cell (x, y) of block b, as c + w u(x, y)
+// (host-callable too, for checks of the tables on the CPU)
+__host__ __device__ inline void across(const FmgDev& g, int b, bool leaf, int x, int y, int face, double& c,
+                                       double& w) {
+  const int nb = g.nbr[4 * b + face];
+  if (nb == NBR_WALL) {
+    c = 0.0;
+    w = 1.0;
+    return;
+  }
+  int X = x, Y = y;  // the neighbouring cell in the neighbouring block
+  if (face == 0) X = NB - 1;
+  if (face == 1) X = 0;
+  if (face == 2) Y = NB - 1;
+  if (face == 3) Y = 0;
+  if (nb >= 0) {
+    const int* ch = g.chi + 4 * nb;
+    if (!leaf || ch[0] < 0) {
+      c = g.u[(size_t)nb * NC + X + NB * Y];
+      w = 0.0;
+      return;
+    }
+    // the coarse side: the two fine cells of the neighbour's children that
+    // touch the face, in its 32 x 32 grid of child cells
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < 2; t++) {
+      const int fx = face < 2 ? 2 * X + (face == 0 ? 1 : 0) : 2 * X + t;
+      const int fy = face < 2 ? 2 * Y + t : 2 * Y + (face == 2 ? 1 : 0);
+      const int fb = ch[(fx >> 4) + 2 * (fy >> 4)];
+      s += g.u[(size_t)fb * NC + (fx & (NB - 1)) + NB * (fy & (NB - 1))];
+    }
+    c = (2.0 / 3.0) * s;
+    w = -1.0 / 3.0;
+    return;
+  }
+  // the fine side: the coarser leaf across the face
+  const int C = g.cnb[4 * b + face];
+  const int gx = g.ij[2 * b] * NB + x, gy = g.ij[2 * b + 1] * NB + y;
+  const double* uc = g.u + (size_t)C * NC;
+  int cx, cy, t, st;
+  double o;
+  if (face < 2) {
+    cx = face == 0 ? NB - 1 : 0;
+    cy = (gy >> 1) - g.ij[2 * C + 1] * NB;
+    t = cy;
+    st = NB;
+    o = (gy & 1) ? 0.25 : -0.25;
+  } else {
+    cy = face == 2 ? NB - 1 : 0;
+    cx = (gx >> 1) - g.ij[2 * C] * NB;
+    t = cx;
+    st = 1;
+    o = (gx & 1) ? 0.25 : -0.25;
+  }
+  const double* p = uc + cx + NB * cy;  // the coarse cell; st steps along the face
+  double slope;
+  if (t == 0)
+    slope = p[st] - p[0];
+  else if (t == NB - 1)
+    slope = p[0] - p[-st];
+  else
+    slope = 0.5 * p[st] - 0.5 * p[-st];
+  c = (2.0 / 3.0) * (p[0] + o * slope);
+  w = 1.0 / 3.0;
+}
+
+// the neighbour sums of cell (x, y) of block b: sum of the four values as
+// sc + sw u(x, y)
+__host__ __device__ inline void stencil(const FmgDev& g, int b, bool leaf, int x, int y, double& sc, double& sw) {
+  const double* ub = g.u + (size_t)b * NC;
+  sc = 0.0;
+  sw = 0.0;
+#pragma unroll
+  for (int face = 0; face < 4; face++) {
+    const int xn = x + (face == 0 ? -1 : (face == 1 ? 1 : 0));
+    const int yn = y + (face == 2 ? -1 : (face == 3 ? 1 : 0));
+    if (xn >= 0 && xn < NB && yn >= 0 && yn < NB) {
+      sc += ub[xn + NB * yn];
+    } else {
+      double c, w;
+      across(g, b, leaf, x, y, face, c, w);
+      sc += c;
+      sw += w;
+    }
+  }
+}
+
+// Every kernel below applies one per-cell function (host-callable too, so a
+// host loop over the same functions checks a cycle on the CPU); cell t of a
+// block is (x, y) = (t & 15, t >> 4).
+
+// lap(u) - lambda u at cell (x, y) of block b: the problem's rules (leaf),
+// or the plain stencil, the refined neighbours' own (restricted) cells in
+// place of the coarse side of a coarse-fine face
+__host__ __device__ inline double apply_cell(const FmgDev& g, int b, bool leaf, int x, int y) {
+  double sc, sw;
+  stencil(g, b, leaf, x, y, sc, sw);
+  const double u = g.u[(size_t)b * NC + x + NB * y];
+  return g.ih2[g.lvl[b]] * (sc + sw * u - 4.0 * u) - g.lam * u;
+}
+
+// red-black relaxation of cell (x, y) of block b with the plain stencil
+// (the problem's rules on the finest level, which has no refined
+// neighbour): a cell of colour (x + y) & 1 reads cells of the other colour
+// only (the block edge is even, so the colour is global) and coarser
+// levels, none of which a sweep of one level writes
+__host__ __device__ inline void smooth_cell(const FmgDev& g, int b, int x, int y) {
+  const double ih2 = g.ih2[g.lvl[b]];
+  double sc, sw;
+  stencil(g, b, false, x, y, sc, sw);
+  const size_t i = (size_t)b * NC + x + NB * y;
+  g.u[i] = (g.f[i] - ih2 * sc) / (ih2 * (sw - 4.0) - g.lam);
+}
+
+// the residual of the relaxation (plain stencil)
+__host__ __device__ inline void resid_cell(const FmgDev& g, int b, int x, int y) {
+  const size_t i = (size_t)b * NC + x + NB * y;
+  g.r[i] = g.f[i] - apply_cell(g, b, false, x, y);
+}
+
+// the problem's residual at a leaf cell
+__host__ __device__ inline double residual(const FmgDev& g, int b, int x, int y) {
+  return g.fu[(size_t)b * NC + x + NB * y] - apply_cell(g, b, true, x, y);
+}
+
+// child b into its parent: parent cell t (0..63) of the child's quadrant gets
+// the mean of u and of r over its 2 x 2 cells (r into the parent's r, u into
+// its u and uo)
+__host__ __device__ inline void restrict_cell(const FmgDev& g, int b, int t) {
+  const int p = g.par[b];
+  const int qx = g.ij[2 * b] & 1, qy = g.ij[2 * b + 1] & 1;
+  const int xx = t & 7, yy = t >> 3;
+  const size_t c0 = (size_t)b * NC + 2 * xx + NB * 2 * yy;
+  const size_t pc = (size_t)p * NC + qx * 8 + xx + NB * (qy * 8 + yy);
+  const double um = 0.25 * ((g.u[c0] + g.u[c0 + 1]) + (g.u[c0 + NB] + g.u[c0 + NB + 1]));
+  const double rm = 0.25 * ((g.r[c0] + g.r[c0 + 1]) + (g.r[c0 + NB] + g.r[c0 + NB + 1]));
+  g.u[pc] = um;
+  g.uo[pc] = um;
+  g.r[pc] = rm;
+}
+
+// the right-hand side of a level below the finest: L(u) + r with L the plain
+// stencil, r the restricted residual (a parent) or the problem's residual (a
+// leaf; where the plain stencil is the problem's, exactly f).  A leaf next to
+// a refined block thereby relaxes with the same stencil as that block's
+// cells, and is left unchanged once the problem's residual vanishes.
+__host__ __device__ inline void fas_cell(const FmgDev& g, int b, int x, int y) {
+  const size_t i = (size_t)b * NC + x + NB * y;
+  const double lp = apply_cell(g, b, false, x, y);
+  if (g.chi[4 * b] >= 0) {
+    g.f[i] = lp + g.r[i];
+    return;
+  }
+  const double lc = apply_cell(g, b, true, x, y);
+  g.f[i] = lp == lc ? g.fu[i] : lp + (g.fu[i] - lc);
+}
+
+// a block of level >= 2 adds the bilinear interpolation of its parent's
+// change e = u - uo: weights 9, 3, 3, 1 (/16) from the parent cell and its
+// neighbours toward the fine cell, the parent's own cell where that
+// neighbour lies outside the parent
+__host__ __device__ inline void prolong_cell(const FmgDev& g, int b, int x, int y) {
+  const int p = g.par[b];
+  const int I = (g.ij[2 * b] & 1) * 8 + (x >> 1), J = (g.ij[2 * b + 1] & 1) * 8 + (y >> 1);
+  const int I2n = I + ((x & 1) ? 1 : -1), J2n = J + ((y & 1) ? 1 : -1);
+  const int I2 = I2n < 0 ? 0 : (I2n > NB - 1 ? NB - 1 : I2n);
+  const int J2 = J2n < 0 ? 0 : (J2n > NB - 1 ? NB - 1 : J2n);
+  const double* up = g.u + (size_t)p * NC;
+  const double* uq = g.uo + (size_t)p * NC;
+  const double e00 = up[I + NB * J] - uq[I + NB * J], e10 = up[I2 + NB * J] - uq[I2 + NB * J];
+  const double e01 = up[I + NB * J2] - uq[I + NB * J2], e11 = up[I2 + NB * J2] - uq[I2 + NB * J2];
+  g.u[(size_t)b * NC + x + NB * y] += (9.0 * e00 + 3.0 * e10 + 3.0 * e01 + e11) * (1.0 / 16.0);
+}
+
+// a level-1 cell to the n x n grid: the correction problem L(e) = r, from e = 0
+__host__ __device__ inline void to_grid_cell(const FmgDev& g, int b, int x, int y, int n, double* fgrid,
+                                             double* vgrid) {
+  const size_t i = (size_t)b * NC + x + NB * y;
+  const size_t gi = (size_t)(g.ij[2 * b + 1] * NB + y) * n + g.ij[2 * b] * NB + x;
+  fgrid[gi] = g.r[i];
+  vgrid[gi] = 0.0;
+}
+
+__global__ void __launch_bounds__(NC) k_fmg_smooth(FmgDev g, int b0, int colour) {
+  const int x = threadIdx.x & (NB - 1), y = threadIdx.x >> 4;
+  if (((x + y) & 1) == colour) smooth_cell(g, b0 + blockIdx.x, x, y);
+}
+
+__global__ void __launch_bounds__(NC) k_fmg_resid(FmgDev g, int b0) {
+  resid_cell(g, b0 + blockIdx.x, threadIdx.x & (NB - 1), threadIdx.x >> 4);
+}
+
+__global__ void __launch_bounds__(64) k_fmg_restrict(FmgDev g, int b0) { restrict_cell(g, b0 + blockIdx.x, threadIdx.x); }
+
+__global__ void __launch_bounds__(NC) k_fmg_fas(FmgDev g, int b0) {
+  fas_cell(g, b0 + blockIdx.x, threadIdx.x & (NB - 1), threadIdx.x >> 4);
+}
+
+__global__ void __launch_bounds__(NC) k_fmg_prolong(FmgDev g, int b0) {
+  prolong_cell(g, b0 + blockIdx.x, threadIdx.x & (NB - 1), threadIdx.x >> 4);
+}
+
+__global__ void __launch_bounds__(NC) k_fmg_to_grid(FmgDev g, int b0, int n, double* fgrid, double* vgrid) {
+  to_grid_cell(g, b0 + blockIdx.x, threadIdx.x & (NB - 1), threadIdx.x >> 4, n, fgrid, vgrid);
+}
+
+__global__ void __launch_bounds__(NC) k_fmg_from_grid(FmgDev g, int b0, int n, const double* vgrid) {
+  const int b = b0 + blockIdx.x;
+  const int x = threadIdx.x & (NB - 1), y = threadIdx.x >> 4;
+  g.u[(size_t)b * NC + threadIdx.x] += vgrid[(size_t)(g.ij[2 * b + 1] * NB + y) * n + g.ij[2 * b] * NB + x];
+}
+
+// block maximum of v >= 0 into *out (the bits of non-negative doubles order
+// as the values)
+__device__ __forceinline__ void fold_max(double v, unsigned long long* out) {
+  __shared__ double sm[NC / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = sm[0];
+    for (int i = 1; i < NC / 64; i++) m = fmax(m, sm[i]);
+    atomicMax(out, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// max |r| of the problem over the leaves (every block launched; parents skip)
+__global__ void __launch_bounds__(NC) k_fmg_resmax(FmgDev g, unsigned long long* out) {
+  const int b = blockIdx.x;
+  if (g.chi[4 * b] >= 0) return;  // uniform per workgroup
+  const double r = residual(g, b, threadIdx.x & (NB - 1), threadIdx.x >> 4);
+  fold_max(isnan(r) ? INFINITY : fabs(r), out);
+}
+
+// leaf fields <-> block arrays; dir 0: f and phi in, 1: phi out
+__global__ void __launch_bounds__(NC) k_fmg_leaves(FmgDev g, const int* leafblk, const double* f, double* phi,
+                                                  int dir) {
+  const int k = blockIdx.x;
+  const size_t i = (size_t)leafblk[k] * NC + threadIdx.x, o = (size_t)k * NC + threadIdx.x;
+  if (dir == 0) {
+    g.f[i] = f[o];
+    g.fu[i] = f[o];
+    g.u[i] = phi[o];
+  } else {
+    phi[o] = g.u[i];
+  }
+}
+
+__global__ void k_fmg_maxabs(const double* v, long long count, unsigned long long* out) {
+  double m = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+    m = fmax(m, isnan(v[i]) ? INFINITY : fabs(v[i]));
+  fold_max(m, out);
+}
+
+__global__ void k_fmg_zero2(unsigned long long* p) {
+  if (threadIdx.x < 2) p[threadIdx.x] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// host: the block tree
+// ---------------------------------------------------------------------------
+
+struct Tree {
+  int nblk = 0, nlev = 0;
+  int lstart[FMG_MAXL + 2] = {};
+  std::vector<int> lvl, ij, nbr, chi, cnb, par, leafblk;
+};
+
+int validate(const amrv_fmg_config* c) {
+  if (!c) return set_error(AMRV_EINVAL, "null config");
+  if (c->nleaves < 1) return set_error(AMRV_EINVAL, "nleaves must be >= 1");
+  if (c->base < 1 || c->base > 512 || (c->base & (c->base - 1)))
+    return set_error(AMRV_EINVAL, "base must be a power of two in 1..512");
+  if (c->max_level < 1 || c->max_level > FMG_MAXL) return set_error(AMRV_EINVAL, "max_level must be in 1..16");
+  if ((long long)c->base * NB > 8192) return set_error(AMRV_EINVAL, "base * 16 must be <= 8192");
+  if (c->bc != AMRV_MG_PERIODIC && c->bc != AMRV_MG_NEUMANN) return set_error(AMRV_EINVAL, "bc must be periodic or Neumann");
+  if (c->pre_sweeps < 1 || c->pre_sweeps > 8 || c->post_sweeps < 1 || c->post_sweeps > 8)
+    return set_error(AMRV_EINVAL, "pre_sweeps and post_sweeps must be in 1..8");
+  if (!(c->length > 0.0) || !std::isfinite(c->length)) return set_error(AMRV_EINVAL, "length must be > 0");
+  return 0;
+}
+
+int build_tree(const amrv_fmg_config* c, const int32_t* level, const int32_t* ijk, Tree& T) {
+  if (!level || !ijk) return set_error(AMRV_EINVAL, "null leaf arrays");
+  using Key = std::tuple<int, int, int>;
+  std::map<Key, int> leaf;
+  std::map<Key, int> blocks;  // value: 1 for a leaf
+  for (long long k = 0; k < c->nleaves; k++) {
+    const int l = level[k], i = ijk[3 * k], j = ijk[3 * k + 1];
+    const long long nl = (long long)c->base << (l - 1);
+    if (l < 1 || l > c->max_level || i < 0 || j < 0 || i >= nl || j >= nl || ijk[3 * k + 2] != 0)
+      return set_error(AMRV_EINVAL, "leaf level or block coordinates out of range");
+    if (!leaf.emplace(Key(l, i, j), (int)k).second) return set_error(AMRV_EUNBALANCED, "leaves overlap (a leaf appears twice)");
+  }
+  for (const auto& kv : leaf) blocks[kv.first] = 1;
+  for (const auto& kv : leaf) {
+    int l, i, j;
+    std::tie(l, i, j) = kv.first;
+    while (l > 1) {
+      l--;
+      i >>= 1;
+      j >>= 1;
+      auto it = blocks.find(Key(l, i, j));
+      if (it != blocks.end()) {
+        if (it->second == 1) return set_error(AMRV_EUNBALANCED, "leaves overlap");
+        break;  // its ancestors are in already
+      }
+      blocks[Key(l, i, j)] = 0;
+    }
+  }
+  // blocks ordered by level, then row-major
+  std::vector<Key> keys;
+  for (const auto& kv : blocks) keys.push_back(kv.first);
+  std::sort(keys.begin(), keys.end(), [](const Key& a, const Key& b) {
+    return std::make_tuple(std::get<0>(a), std::get<2>(a), std::get<1>(a)) <
+           std::make_tuple(std::get<0>(b), std::get<2>(b), std::get<1>(b));
+  });
+  std::map<Key, int> index;
+  for (size_t b = 0; b < keys.size(); b++) index[keys[b]] = (int)b;
+  const int nblk = (int)keys.size();
+  T.nblk = nblk;
+  T.lvl.assign(nblk, 0);
+  T.ij.assign(2 * nblk, 0);
+  T.nbr.assign(4 * nblk, NBR_NONE);
+  T.chi.assign(4 * nblk, -1);
+  T.cnb.assign(4 * nblk, -1);
+  T.par.assign(nblk, -1);
+  T.leafblk.assign(c->nleaves, -1);
+  T.nlev = 0;
+  for (int b = 0; b < nblk; b++) T.nlev = std::max(T.nlev, std::get<0>(keys[b]));
+  // blocks of level l: [lstart[l], lstart[l + 1])
+  for (int l = 0; l <= FMG_MAXL + 1; l++) T.lstart[l] = 0;
+  for (int b = 0; b < nblk; b++) T.lstart[std::get<0>(keys[b]) + 1]++;
+  for (int l = 1; l <= FMG_MAXL + 1; l++) T.lstart[l] += T.lstart[l - 1];
+  if (T.lstart[2] - T.lstart[1] != c->base * c->base)
+    return set_error(AMRV_EUNBALANCED, "the leaves do not cover the base grid");
+  auto find = [&](int l, long long i, long long j) {
+    auto it = index.find(Key(l, (int)i, (int)j));
+    return it == index.end() ? -1 : it->second;
+  };
+  for (int b = 0; b < nblk; b++) {
+    int l, i, j;
+    std::tie(l, i, j) = keys[b];
+    T.lvl[b] = l;
+    T.ij[2 * b] = i;
+    T.ij[2 * b + 1] = j;
+    if (l > 1) T.par[b] = find(l - 1, i >> 1, j >> 1);
+    const long long nl = (long long)c->base << (l - 1);
+    const bool isleaf = blocks[keys[b]] == 1;
+    int nch = 0;
+    for (int q = 0; q < 4; q++) {
+      T.chi[4 * b + q] = find(l + 1, 2 * i + (q & 1), 2 * j + (q >> 1));
+      nch += T.chi[4 * b + q] >= 0;
+    }
+    if (isleaf ? nch != 0 : nch != 4) return set_error(AMRV_EUNBALANCED, "leaves overlap or leave gaps");
+    for (int f = 0; f < 4; f++) {
+      long long ni = i + (f == 0 ? -1 : (f == 1 ? 1 : 0)), nj = j + (f == 2 ? -1 : (f == 3 ? 1 : 0));
+      if (ni < 0 || nj < 0 || ni >= nl || nj >= nl) {
+        if (c->bc == AMRV_MG_NEUMANN) {
+          T.nbr[4 * b + f] = NBR_WALL;
+          continue;
+        }
+        ni = (ni + nl) % nl;
+        nj = (nj + nl) % nl;
+      }
+      const int nb = find(l, ni, nj);
+      T.nbr[4 * b + f] = nb;
+      if (nb >= 0) {
+        // a refined neighbour of a leaf: its two children along the face must be leaves
+        if (isleaf && blocks[keys[nb]] == 0)
+          for (int q = 0; q < 4; q++) {
+            const bool touches = f < 2 ? (q & 1) == (f == 0 ? 1 : 0) : (q >> 1) == (f == 2 ? 1 : 0);
+            if (!touches) continue;
+            const int cq = find(l + 1, 2 * ni + (q & 1), 2 * nj + (q >> 1));
+            if (cq < 0 || blocks[keys[cq]] != 1) return set_error(AMRV_EUNBALANCED, "2:1 balance across a face broken");
+          }
+        continue;
+      }
+      // no block of this level across the face: only a leaf may see a coarser leaf there
+      const long long nl1 = nl >> 1;
+      long long ci = ni >> 1, cj = nj >> 1;
+      ci = (ci + nl1) % nl1;
+      cj = (cj + nl1) % nl1;
+      const int C = l > 1 ? find(l - 1, ci, cj) : -1;
+      if (!isleaf || C < 0 || blocks[keys[C]] != 1)
+        return set_error(AMRV_EUNBALANCED, "2:1 balance across a face broken");
+      T.cnb[4 * b + f] = C;
+    }
+  }
+  for (const auto& kv : leaf) T.leafblk[kv.second] = index[kv.first];
+  return 0;
+}
+
+// the uniform solver of the level-1 grid: one field, the forest's boundary,
+// per-colour sweeps (its smoother choice does not change its result)
+amrv_mg_config base_config(const amrv_fmg_config* c) {
+  amrv_mg_config mc{};
+  mc.ndim = 2;
+  mc.n = c->base * NB;
+  mc.bc = c->bc;
+  mc.nfields = 1;
+  mc.pre_sweeps = 2;
+  mc.post_sweeps = 2;
+  mc.use_graph = 0;
+  mc.smoother = AMRV_MG_PER_COLOUR;
+  mc.length = c->length;
+  return mc;
+}
+
+struct FmgLayout {
+  size_t off_tab[7], off_u, off_f, off_fu, off_r, off_uo, off_fg, off_vg, off_red, off_mg, total;
+  size_t mg_bytes;
+};
+
+FmgLayout layout(const amrv_fmg_config* c, const Tree& T) {
+  FmgLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += (bytes + ALIGN - 1) / ALIGN * ALIGN;
+    return at;
+  };
+  const size_t nb = (size_t)T.nblk;
+  L.off_tab[0] = take(sizeof(int) * nb);        // lvl
+  L.off_tab[1] = take(sizeof(int) * 2 * nb);    // ij
+  L.off_tab[2] = take(sizeof(int) * 4 * nb);    // nbr
+  L.off_tab[3] = take(sizeof(int) * 4 * nb);    // chi
+  L.off_tab[4] = take(sizeof(int) * 4 * nb);    // cnb
+  L.off_tab[5] = take(sizeof(int) * nb);        // par
+  L.off_tab[6] = take(sizeof(int) * (size_t)c->nleaves);  // leaf -> block
+  L.off_u = take(sizeof(double) * NC * nb);
+  L.off_f = take(sizeof(double) * NC * nb);
+  L.off_fu = take(sizeof(double) * NC * nb);
+  L.off_r = take(sizeof(double) * NC * nb);
+  L.off_uo = take(sizeof(double) * NC * nb);
+  const size_t n = (size_t)c->base * NB;
+  L.off_fg = take(sizeof(double) * n * n);
+  L.off_vg = take(sizeof(double) * n * n);
+  L.off_red = take(sizeof(unsigned long long) * 2);
+  amrv_mg_config mc = base_config(c);
+  L.mg_bytes = amrv_mg_workspace_bytes(&mc);
+  L.off_mg = take(L.mg_bytes);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+
+struct amrv_fmg {
+  amrv_fmg_config cfg{};
+  hipStream_t st = nullptr;
+  Tree T;
+  FmgLayout L{};
+  FmgDev g{};
+  int* leafblk = nullptr;
+  double* fgrid = nullptr;
+  double* vgrid = nullptr;
+  unsigned long long* red = nullptr;
+  unsigned long long* hred = nullptr;  // pinned
+  amrv_mg* base = nullptr;
+};
+
+namespace {
+
+int hip_fail(hipError_t e, const char* what) {
+  return set_error(AMRV_EDEVICE, (std::string(what) + ": " + hipGetErrorString(e)).c_str());
+}
+
+#define FMGCHK(expr)                                   \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr);  \
+  } while (0)
+
+double bits_to_double(unsigned long long b) {
+  double d;
+  std::memcpy(&d, &b, 8);
+  return d;
+}
+
+int nblocks(const amrv_fmg* m, int l) { return m->T.lstart[l + 1] - m->T.lstart[l]; }
+
+int sweeps(amrv_fmg* m, int l, int count) {
+  for (int s = 0; s < count; s++)
+    for (int c = 0; c < 2; c++)
+      hipLaunchKernelGGL(k_fmg_smooth, dim3(nblocks(m, l)), dim3(NC), 0, m->st, m->g, m->T.lstart[l], c);
+  FMGCHK(hipGetLastError());
+  return 0;
+}
+
+// one V-cycle (enqueued; the level-1 solve synchronises inside)
+int vcycle(amrv_fmg* m) {
+  const int L = m->T.nlev;
+  const int pre = m->cfg.pre_sweeps, post = m->cfg.post_sweeps;
+  for (int l = L; l >= 2; l--) {
+    if (int rc = sweeps(m, l, pre)) return rc;
+    hipLaunchKernelGGL(k_fmg_resid, dim3(nblocks(m, l)), dim3(NC), 0, m->st, m->g, m->T.lstart[l]);
+    hipLaunchKernelGGL(k_fmg_restrict, dim3(nblocks(m, l)), dim3(64), 0, m->st, m->g, m->T.lstart[l]);
+    hipLaunchKernelGGL(k_fmg_fas, dim3(nblocks(m, l - 1)), dim3(NC), 0, m->st, m->g, m->T.lstart[l - 1]);
+    FMGCHK(hipGetLastError());
+  }
+  if (int rc = sweeps(m, 1, pre)) return rc;
+  const int n = m->cfg.base * NB;
+  hipLaunchKernelGGL(k_fmg_resid, dim3(nblocks(m, 1)), dim3(NC), 0, m->st, m->g, m->T.lstart[1]);
+  hipLaunchKernelGGL(k_fmg_to_grid, dim3(nblocks(m, 1)), dim3(NC), 0, m->st, m->g, m->T.lstart[1], n, m->fgrid,
+                     m->vgrid);
+  FMGCHK(hipGetLastError());
+  // the level-1 correction to 1e-4 of its right-hand side (at most 8 of the
+  // uniform solver's cycles): solved as a correction, its error shrinks with
+  // the residual from cycle to cycle
+  const double lam = m->g.lam;
+  int cyc = 0;
+  const int rc = amrv_mg_solve(m->base, m->fgrid, m->vgrid, &lam, 1e-4, 8, &cyc, nullptr, nullptr);
+  if (rc != 0 && rc != AMRV_ENOTCONVERGED) return rc;
+  hipLaunchKernelGGL(k_fmg_from_grid, dim3(nblocks(m, 1)), dim3(NC), 0, m->st, m->g, m->T.lstart[1], n, m->vgrid);
+  FMGCHK(hipGetLastError());
+  if (int rc2 = sweeps(m, 1, post)) return rc2;
+  for (int l = 2; l <= L; l++) {
+    hipLaunchKernelGGL(k_fmg_prolong, dim3(nblocks(m, l)), dim3(NC), 0, m->st, m->g, m->T.lstart[l]);
+    FMGCHK(hipGetLastError());
+    if (int rc2 = sweeps(m, l, post)) return rc2;
+  }
+  return 0;
+}
+
+// max |r| over the leaves (and, with fmax, max |f| of the leaf field)
+int norms(amrv_fmg* m, const double* f, double* res, double* fmax) {
+  hipLaunchKernelGGL(k_fmg_zero2, dim3(1), dim3(64), 0, m->st, m->red);
+  hipLaunchKernelGGL(k_fmg_resmax, dim3(m->T.nblk), dim3(NC), 0, m->st, m->g, m->red);
+  if (fmax)
+    hipLaunchKernelGGL(k_fmg_maxabs, dim3(std::min<long long>(1024, m->cfg.nleaves)), dim3(NC), 0, m->st, f,
+                       (long long)m->cfg.nleaves * NC, m->red + 1);
+  FMGCHK(hipGetLastError());
+  FMGCHK(hipMemcpyAsync(m->hred, m->red, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, m->st));
+  FMGCHK(hipStreamSynchronize(m->st));
+  *res = bits_to_double(m->hred[0]);
+  if (fmax) *fmax = bits_to_double(m->hred[1]);
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t amrv_fmg_workspace_bytes(const amrv_fmg_config* cfg, const int32_t* leaf_level, const int32_t* leaf_ijk) {
+  if (validate(cfg)) return 0;
+  Tree T;
+  if (build_tree(cfg, leaf_level, leaf_ijk, T)) return 0;
+  return layout(cfg, T).total;
+}
+
+int amrv_fmg_create(const amrv_fmg_config* cfg, const int32_t* leaf_level, const int32_t* leaf_ijk,
+                    void* workspace, size_t bytes, void* stream, amrv_fmg** out) {
+  if (!out) return set_error(AMRV_EINVAL, "null argument");
+  *out = nullptr;
+  if (int rc = validate(cfg)) return rc;
+  if (!workspace) return set_error(AMRV_EINVAL, "null workspace");
+  if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) return set_error(AMRV_EINVAL, "workspace must be 256-byte aligned");
+  amrv_fmg* m = new amrv_fmg;
+  m->cfg = *cfg;
+  m->st = static_cast<hipStream_t>(stream);
+  if (int rc = build_tree(cfg, leaf_level, leaf_ijk, m->T)) {
+    delete m;
+    return rc;
+  }
+  m->L = layout(cfg, m->T);
+  if (bytes < m->L.total) {
+    delete m;
+    return set_error(AMRV_ENOMEM, ("workspace too small: need " + std::to_string(m->L.total)).c_str());
+  }
+  char* base = static_cast<char*>(workspace);
+  const Tree& T = m->T;
+  const std::vector<int>* tabs[7] = {&T.lvl, &T.ij, &T.nbr, &T.chi, &T.cnb, &T.par, &T.leafblk};
+  int* dtab[7];
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 7 && e == hipSuccess; i++) {
+    dtab[i] = reinterpret_cast<int*>(base + m->L.off_tab[i]);
+    e = hipMemcpyAsync(dtab[i], tabs[i]->data(), sizeof(int) * tabs[i]->size(), hipMemcpyHostToDevice, m->st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(m->st);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&m->hred), 2 * sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    delete m;
+    return hip_fail(e, "amrv_fmg_create");
+  }
+  FmgDev& g = m->g;
+  g.lvl = dtab[0];
+  g.ij = dtab[1];
+  g.nbr = dtab[2];
+  g.chi = dtab[3];
+  g.cnb = dtab[4];
+  g.par = dtab[5];
+  m->leafblk = dtab[6];
+  g.u = reinterpret_cast<double*>(base + m->L.off_u);
+  g.f = reinterpret_cast<double*>(base + m->L.off_f);
+  g.fu = reinterpret_cast<double*>(base + m->L.off_fu);
+  g.r = reinterpret_cast<double*>(base + m->L.off_r);
+  g.uo = reinterpret_cast<double*>(base + m->L.off_uo);
+  for (int l = 1; l <= FMG_MAXL; l++) {
+    const double q = (double)((long long)cfg->base * NB << (l - 1)) / cfg->length;
+    g.ih2[l] = q * q;
+  }
+  m->fgrid = reinterpret_cast<double*>(base + m->L.off_fg);
+  m->vgrid = reinterpret_cast<double*>(base + m->L.off_vg);
+  m->red = reinterpret_cast<unsigned long long*>(base + m->L.off_red);
+  const amrv_mg_config mc = base_config(cfg);
+  if (int rc = amrv_mg_create(&mc, base + m->L.off_mg, m->L.mg_bytes, stream, &m->base)) {
+    (void)hipHostFree(m->hred);
+    delete m;
+    return rc;
+  }
+  // parents start from zero (every parent is restricted before it is read)
+  e = hipMemsetAsync(g.u, 0, sizeof(double) * NC * (size_t)T.nblk, m->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->st);
+  if (e != hipSuccess) {
+    amrv_mg_destroy(m->base);
+    (void)hipHostFree(m->hred);
+    delete m;
+    return hip_fail(e, "amrv_fmg_create");
+  }
+  *out = m;
+  return 0;
+}
+
+int amrv_fmg_destroy(amrv_fmg* m) {
+  if (!m) return 0;
+  int rc = amrv_mg_destroy(m->base);
+  if (m->hred) (void)hipHostFree(m->hred);
+  delete m;
+  return rc;
+}
+
+int amrv_fmg_levels(const amrv_fmg* m, int32_t* nblocks_per_level) {
+  if (!m || !nblocks_per_level) return set_error(AMRV_EINVAL, "null argument");
+  for (int l = 1; l <= FMG_MAXL; l++) nblocks_per_level[l - 1] = l <= m->T.nlev ? nblocks(m, l) : 0;
+  return 0;
+}
+
+int amrv_fmg_solve(amrv_fmg* m, const double* f, double* phi, double lambda, double tol, int32_t max_cycles,
+                   int32_t* cycles, double* res_max, double* f_max) {
+  if (!m || !f || !phi) return set_error(AMRV_EINVAL, "null argument");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return set_error(AMRV_EINVAL, "lambda must be > 0");
+  if (!(tol > 0.0) || max_cycles < 0) return set_error(AMRV_EINVAL, "tol must be > 0 and max_cycles >= 0");
+  m->g.lam = lambda;
+  hipLaunchKernelGGL(k_fmg_leaves, dim3(m->cfg.nleaves), dim3(NC), 0, m->st, m->g, m->leafblk, f, phi, 0);
+  FMGCHK(hipGetLastError());
+  double res = 0.0, fmax = 0.0;
+  if (int rc = norms(m, f, &res, &fmax)) return rc;
+  int c = 0;
+  bool ok = res <= tol * fmax;
+  while (!ok && c < max_cycles && !std::isnan(res)) {
+    if (int rc = vcycle(m)) return rc;
+    c++;
+    if (int rc = norms(m, f, &res, nullptr)) return rc;
+    ok = res <= tol * fmax;
+  }
+  hipLaunchKernelGGL(k_fmg_leaves, dim3(m->cfg.nleaves), dim3(NC), 0, m->st, m->g, m->leafblk, f, phi, 1);
+  FMGCHK(hipGetLastError());
+  FMGCHK(hipStreamSynchronize(m->st));
+  if (cycles) *cycles = c;
+  if (res_max) *res_max = res;
+  if (f_max) *f_max = fmax;
+  if (std::isnan(res) || std::isinf(res) || std::isinf(fmax))
+    return set_error(AMRV_ENONPHYSICAL, "NaN or infinity in the forest multigrid right-hand side or residual");
+  if (!ok) return set_error(AMRV_ENOTCONVERGED, "forest multigrid residual above tol after max_cycles V-cycles");
+  return 0;
+}
+
+}  // extern "C"

@@ -136,3 +136,86 @@ class GpuMultigrid:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         N.check(N.lib().amrv_mg_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+def fmg_config(forest, length: float, bc: int, pre: int = 2, post: int = 2) -> N.FmgConfig:
+    """amrv_fmg_config of a 2D forest (workloads.Forest: square 16^2 blocks,
+    base x base blocks at level 1)."""
+    s = forest.scheme
+    if s.ndim != 2 or s.base_blocks[0] != s.base_blocks[1] or tuple(s.block_nx[:2]) != (16, 16):
+        raise ValueError("a 2D forest of 16 x 16 blocks on a square base grid")
+    return N.FmgConfig(nleaves=forest.n, base=s.base_blocks[0], max_level=s.max_level, bc=bc, pre_sweeps=pre,
+                       post_sweeps=post, pad=0, length=length)
+
+
+def fmg_workspace_bytes(forest, length: float, bc: int) -> int:
+    """Workspace bytes of the forest solver (host only; raises AmrvError for a
+    bad configuration or leaf list)."""
+    L = N.lib()
+    cfg = fmg_config(forest, length, bc)
+    lev = np.ascontiguousarray(forest.level, dtype=np.int32)
+    ijk = np.ascontiguousarray(forest.ijk, dtype=np.int32)
+    nbytes = L.amrv_fmg_workspace_bytes(ctypes.byref(cfg), lev.ctypes.data, ijk.ctypes.data)
+    if nbytes == 0:
+        err = L.amrv_last_error().decode()
+        raise N.AmrvError(N.EUNBALANCED if "balance" in err or "overlap" in err or "cover" in err or "gap" in err
+                          else N.EINVAL, err)
+    return int(nbytes)
+
+
+class GpuForestMultigrid:
+    """The Helmholtz solver on a 2D block-adaptive forest (amrv_fmg_*):
+    fields are float64 device tensors of shape [nleaves, 16, 16] (the
+    forest's layout of one variable)."""
+
+    def __init__(self, forest, length: float, bc: int, pre: int = 2, post: int = 2,
+                 device: str | torch.device = "cuda:0", stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("GpuForestMultigrid needs a ROCm GPU (torch.cuda.is_available() is False)")
+        L = N.lib()
+        self.cfg = fmg_config(forest, length, bc, pre, post)
+        lev = np.ascontiguousarray(forest.level, dtype=np.int32)
+        ijk = np.ascontiguousarray(forest.ijk, dtype=np.int32)
+        nbytes = fmg_workspace_bytes(forest, length, bc)
+        self.device = torch.device(device)
+        self.nleaves = forest.n
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._h = ctypes.c_void_p()
+        N.check(L.amrv_fmg_create(ctypes.byref(self.cfg), lev.ctypes.data, ijk.ctypes.data,
+                                  ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._h)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            N.lib().amrv_fmg_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def levels(self) -> list:
+        out = np.zeros(16, dtype=np.int32)
+        N.check(N.lib().amrv_fmg_levels(self._h, out.ctypes.data))
+        return [int(v) for v in out if v]
+
+    def solve(self, f: torch.Tensor, phi: torch.Tensor, lam: float, tol: float = 1e-10, max_cycles: int = 50):
+        """lap(phi) - lam phi = f on the leaf cells (phi: initial guess in,
+        solution out).  Returns (cycles, max residual, max |f|)."""
+        for t in (f, phi):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError("expected contiguous float64 device tensors")
+            if t.numel() != self.nleaves * 256:
+                raise ValueError(f"expected {self.nleaves * 256} values, got {t.numel()}")
+        cyc = ctypes.c_int32()
+        res, fmax = ctypes.c_double(), ctypes.c_double()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        N.check(N.lib().amrv_fmg_solve(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(phi.data_ptr()),
+                                       float(lam), float(tol), int(max_cycles), ctypes.byref(cyc),
+                                       ctypes.byref(res), ctypes.byref(fmax)))
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return cyc.value, res.value, fmax.value
