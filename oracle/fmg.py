@@ -178,3 +178,45 @@ def cell_centres(forest, length: float):
     x = (forest.ijk[:, 0, None, None] * nb + loc[None, None, :] + 0.5) * h[:, None, None]
     y = (forest.ijk[:, 1, None, None] * nb + loc[None, :, None] + 0.5) * h[:, None, None]
     return np.broadcast_to(x, (forest.n, nb, nb)).copy(), np.broadcast_to(y, (forest.n, nb, nb)).copy()
+
+
+# -- reaction-diffusion on the forest (Sec. 2.5: Eqs. gray-scott, schnakenberg,
+# diff-helmholtz and imex; the schemes as oracle/rd.py writes them on a
+# uniform grid, with this module's lap and solve) ----------------------------
+
+def rd_step(forest, u, v, dt: float, scheme: int, p: dict, length: float, bc: int):
+    """One step of a reaction-diffusion scheme on the leaf cells ([leaf][y][x]
+    fields); scheme and parameters as in oracle/rd.py.  Returns (u1, v1)."""
+    from . import rd
+
+    def lap(w):
+        return apply(forest, w, 0.0, length, bc)
+
+    def full(a, b):
+        ra, rb = rd.reaction(a, b, p)
+        return ra + p["Du"] * lap(a), rb + p["Dv"] * lap(b)
+
+    if scheme == rd.EULER:
+        fu, fv = full(u, v)
+        return u + dt * fu, v + dt * fv
+    if scheme == rd.MIDPOINT:
+        fu, fv = full(u, v)
+        uh, vh = u + (0.5 * dt) * fu, v + (0.5 * dt) * fv
+        gu, gv = full(uh, vh)
+        return u + dt * gu, v + dt * gv
+    ru, rv = rd.reaction(u, v, p)
+    if scheme == rd.SPLIT:
+        out = []
+        for w, r, D in ((u, ru, p["Du"]), (v, rv, p["Dv"])):
+            lam = 1.0 / (dt * D)
+            out.append(solve(forest, -lam * (w + dt * r), lam, length, bc))
+        return out[0], out[1]
+    if scheme == rd.IMEX:
+        star = []
+        for w, r, D in ((u, ru, p["Du"]), (v, rv, p["Dv"])):
+            lam = 2.0 / (dt * D)
+            star.append(solve(forest, -lam * (w + dt * r + (0.5 * dt) * (D * lap(w))), lam, length, bc))
+        fu, fv = full(u, v)
+        su, sv = full(star[0], star[1])
+        return u + (0.5 * dt) * (fu + su), v + (0.5 * dt) * (fv + sv)
+    raise ValueError(f"unknown scheme {scheme}")

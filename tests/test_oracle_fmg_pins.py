@@ -126,3 +126,38 @@ def test_discrete_conservation(bc):
     area = (1.0 / ((4 << (f.level.astype(np.int64) - 1)) * 16)) ** 2
     total = np.sum(lap * area[:, None, None])
     assert abs(total) <= 1e-12 * np.sum(np.abs(lap) * area[:, None, None])
+
+
+@pytest.mark.parametrize("scheme", [rd.EULER, rd.MIDPOINT, rd.SPLIT, rd.IMEX])
+def test_rd_step_on_a_uniform_forest_is_the_grid_step(scheme):
+    """Every leaf at level 2: one step of each scheme equals oracle/rd.py's
+    step on the 64^2 grid (spectral solves, its own Laplacian)."""
+    s = W.fmg_scheme(base=4, max_level=2, bc=fmg.PERIODIC, length=2.0)
+    f = W.uniform_forest(s, level=2)
+    x, y = fmg.cell_centres(f, 2.0)
+    g = sum(0.5 * np.exp(-25.0 * ((x - cx) ** 2 + (y - cy) ** 2)) for cx, cy in ((0.5, 0.5), (0.55, 0.6)))
+    u, v = 1.0 - g, g.copy()
+    p = rd.GRAY_SCOTT_PARAMS
+    dt = 0.5 if scheme in (rd.SPLIT, rd.IMEX) else 0.05
+    u1, v1 = fmg.rd_step(f, u, v, dt, scheme, p, 2.0, fmg.PERIODIC)
+    gu, gv = rd.step(_uniform_to_grid(f, u), _uniform_to_grid(f, v), dt, scheme, p, 2.0, rd.PERIODIC)
+    for a, b in ((u1, gu), (v1, gv)):
+        assert np.max(np.abs(_uniform_to_grid(f, a) - b)) <= 1e-12 * np.max(np.abs(b))
+
+
+def test_split_diffusion_conserves_mass_on_a_refined_forest():
+    """The split scheme's diffusion solve (I - dt D lap) w1 = w* keeps the
+    area integral of w* (the conservative coarse-fine faces): the change of
+    the integral over a step is dt times the integral of the reaction."""
+    f = _refined(fmg.PERIODIC)
+    x, y = fmg.cell_centres(f, 1.0)
+    u = 1.0 - 0.5 * np.exp(-60 * ((x - 0.3) ** 2 + (y - 0.35) ** 2))
+    v = 1.0 - u
+    p = rd.GRAY_SCOTT_PARAMS
+    dt = 0.5
+    u1, v1 = fmg.rd_step(f, u, v, dt, rd.SPLIT, p, 1.0, fmg.PERIODIC)
+    ru, rv = rd.reaction(u, v, p)
+    area = ((1.0 / ((4 << (f.level.astype(np.int64) - 1)) * 16)) ** 2)[:, None, None]
+    for w, w1, r in ((u, u1, ru), (v, v1, rv)):
+        expect = np.sum(area * (w + dt * r))
+        assert abs(np.sum(area * w1) - expect) <= 1e-12 * abs(expect)
