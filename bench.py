@@ -13,8 +13,10 @@ launch duration), the one-launch-per-block path, full-size parity of one step
 against the CPU oracle, the oracle's own throughput on the host cores, and
 (object "reaction_diffusion") the paper's timed reaction-diffusion workload:
 Schnakenberg on 256^2 with IMEX, split and explicit steps through the
-multigrid solver.  --workload rd2d / rd3d print that workload's own line
-(ms per IMEX step on 256^2 / 128^3).
+multigrid solver; (object "reaction_diffusion_amr") Gray-Scott on the
+paper's three-level AMR setup through the forest multigrid.  --workload rd2d
+/ rd3d / gsamr2d print that workload's own line (ms per IMEX step on 256^2 /
+128^3 / the 128^2-512^2 forest).
 """
 from __future__ import annotations
 
@@ -190,6 +192,119 @@ def rd_measure(nd: int, n: int, steps: int, warmup: int, log, cpu: bool = True, 
     return out
 
 
+def fmg_vcycle_bytes(levels: list, base_cells: int) -> float:
+    """Algorithmic HBM bytes of one forest V-cycle: on every level above the
+    base, each block's 256 cells are read and written once on the way down
+    (state and right-hand side in, state, parent state and right-hand side
+    out: 24 + 16/4 bytes per cell) and once on the way up (state, right-hand
+    side and parent change in, state out: 24 + 8/4), as rd_vcycle_bytes
+    counts a uniform level; plus the level-1 correction's uniform V-cycles
+    (one field), counted once."""
+    total = 0.0
+    for nblk in levels[1:]:
+        c = 256 * nblk
+        total += c * (24 + 16 / 4) + c * (24 + 8 / 4)
+    return total + rd_vcycle_bytes(2, base_cells, nfields=1)
+
+
+def gsamr_measure(steps: int, warmup: int, log, cpu: bool = True, tol: float = 1e-7) -> dict:
+    """Gray-Scott on the paper's three-level AMR setup (Sec. 2.5.2; periodic
+    side 2, 128^2 to 512^2, a static forest refined around the initial
+    perturbations): IMEX and split steps (dt = 0.5, the forest multigrid to
+    max residual <= tol max|f|) and explicit midpoint steps (dt = 0.05, within
+    the explicit limit of the finest level), state resident in HBM; one IMEX
+    step checked against the oracle (exact composite solves), the oracle's
+    IMEX step timed on the host."""
+    import numpy as np
+    import torch
+
+    from paper_2004_03275_amd import multigrid as M
+    import workloads as W
+
+    params = {"model": M.GRAY_SCOTT, "Du": 2e-5, "Dv": 1e-5, "p1": 0.046, "p2": 0.063, "p3": 0.0}
+    f, u0, v0, L = W.gray_scott_amr()
+    mg = M.GpuForestMultigrid(f, L, M.PERIODIC)
+    levels = mg.levels()
+    res = {}
+    for name, scheme, sdt in (("imex", M.IMEX, 0.5), ("split", M.SPLIT, 0.5), ("midpoint", M.MIDPOINT, 0.05)):
+        u = torch.tensor(u0, device="cuda:0").contiguous()
+        v = torch.tensor(v0, device="cuda:0").contiguous()
+        mg.rd_step(u, v, sdt, scheme, params, nsteps=warmup, tol=tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cyc, _ = mg.rd_step(u, v, sdt, scheme, params, nsteps=steps, tol=tol)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[name] = {"ms_per_step": 1e3 * el / steps, "vcycles_per_step": cyc / steps}
+    # the V-cycle's share: the IMEX step time over its cycles (each cycle ends
+    # in a host read of its residual, which this includes)
+    vcycle_us = 1e3 * res["imex"]["ms_per_step"] / max(res["imex"]["vcycles_per_step"], 1e-9)
+    vbytes = fmg_vcycle_bytes(levels, 16 * f.scheme.base_blocks[0])
+    achieved = vbytes / (vcycle_us * 1e-6) / 1e9
+    cells = f.n * 256
+    out = {"workload": "gray_scott_amr_2d", "leaves": f.n, "cells": cells,
+           "levels": {str(k): v for k, v in f.level_counts().items()}, "blocks_per_tree_level": levels,
+           "dt": {"imex": 0.5, "split": 0.5, "midpoint": 0.05}, "tol": tol,
+           "imex_ms_per_step": res["imex"]["ms_per_step"], "split_ms_per_step": res["split"]["ms_per_step"],
+           "midpoint_ms_per_step": res["midpoint"]["ms_per_step"],
+           "imex_vcycles_per_step": res["imex"]["vcycles_per_step"],
+           "split_vcycles_per_step": res["split"]["vcycles_per_step"],
+           "vcycle_us": vcycle_us,
+           "roofline": {"bound": "hbm", "kernel": "one forest V-cycle (all its launches)", "achieved": achieved,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "algorithmic_bytes_per_vcycle": vbytes,
+                        "note": "latency-bound: about 50 dependent launches per cycle over cache-resident "
+                                "levels, and a host read of the residual after each cycle"}}
+    log(f"gray-scott AMR {f.level_counts()}: IMEX {out['imex_ms_per_step']:.2f} ms/step "
+        f"({out['imex_vcycles_per_step']:.2f} cycles per step, both species), split {out['split_ms_per_step']:.2f} ms, "
+        f"midpoint {out['midpoint_ms_per_step']:.3f} ms, V-cycle {vcycle_us:.0f} us")
+    if cpu:
+        from oracle import fmg as O
+        from oracle import rd as R
+
+        u = torch.tensor(u0, device="cuda:0").contiguous()
+        v = torch.tensor(v0, device="cuda:0").contiguous()
+        mg.rd_step(u, v, 0.5, M.IMEX, params, nsteps=1, tol=1e-12, max_cycles=80)
+        t0 = time.perf_counter()
+        ru, rv = O.rd_step(f, u0, v0, 0.5, R.IMEX, R.GRAY_SCOTT_PARAMS, L, O.PERIODIC)
+        ocpu = time.perf_counter() - t0
+        diff = max(np.abs(u.cpu().numpy() - ru).max() / np.abs(ru).max(),
+                   np.abs(v.cpu().numpy() - rv).max() / np.abs(rv).max())
+        out["parity"] = {"steps": 1, "scheme": "imex", "tol": 1e-12, "rel_max_diff": float(diff), "bar": 1e-8}
+        out["cpu_baseline"] = {"value": 1e3 * ocpu, "unit": "ms per IMEX step", "cores": 1, "kind": "oracle",
+                               "sample": "one IMEX step of the same forest with exact (sparse LU) composite solves"}
+        log(f"gray-scott AMR parity: rel max diff {diff:.2e}; oracle {1e3 * ocpu:.0f} ms per IMEX step")
+    mg.close()
+    return out
+
+
+def gsamr_main(args, log):
+    r = gsamr_measure(args.steps, args.warmup, log, cpu=not args.no_cpu_baseline)
+    ms = r["imex_ms_per_step"]
+    out = {
+        "metric": "ms per IMEX Gray-Scott step on the three-level forest (multigrid to max residual <= 1e-7 max|f|)",
+        "value": ms,
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": r["workload"], "leaves": r["leaves"], "cells": r["cells"], "levels": r["levels"],
+                   "dt": r["dt"]["imex"], "tol": r["tol"], "model": "gray_scott", "bc": "periodic",
+                   "cycle": "FAS V(2,2) over the block tree, uniform V-cycles on level 1"},
+        "roofline": r["roofline"],
+        "cpu_baseline": r.get("cpu_baseline"),
+        "parity": r.get("parity"),
+        "reaction_diffusion_amr": r,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def rd_main(args, log):
     nd, n = (2, 256) if args.workload == "rd2d" else (3, 128)
     r = rd_measure(nd, n, args.steps, args.warmup, log, cpu=not args.no_cpu_baseline)
@@ -225,7 +340,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="blast", choices=["blast", "kh", "ot", "sod", "mhdblast2d", "mhdblast3d",
-                                                             "dambreak2d", "rd2d", "rd3d"])
+                                                             "dambreak2d", "rd2d", "rd3d", "gsamr2d"])
     ap.add_argument("--flag-every", type=int, default=10)
     ap.add_argument("--per-block-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -273,6 +388,9 @@ def main():
 
     if args.workload in ("rd2d", "rd3d"):
         rd_main(args, log)
+        return
+    if args.workload == "gsamr2d":
+        gsamr_main(args, log)
         return
 
     desc, f, U0 = make_workload(args.workload)
@@ -573,9 +691,10 @@ def main():
         if ga is not g:
             ga.close()
 
-    rd = None
+    rd = rd_amr = None
     if args.workload == "blast" and not args.no_rd:
         rd = rd_measure(2, 256, 20, 3, log, cpu=not args.no_cpu_baseline)
+        rd_amr = gsamr_measure(10, 2, log, cpu=not args.no_cpu_baseline)
 
     counters = measured_counters(args.workload, ["minmod", "vanleer", "mc", "koren", "cada"][s.limiter], sched[3],
                                  args.arithmetic)
@@ -649,6 +768,7 @@ def main():
         "learned_flagger": flagger,
         "adaptive": adaptive,
         "reaction_diffusion": rd,
+        "reaction_diffusion_amr": rd_amr,
     }
     print(json.dumps(out), flush=True)
 

@@ -238,6 +238,17 @@ int amrv_fmg_levels(const amrv_fmg* m, int32_t* nblocks_per_level);
 int amrv_fmg_solve(amrv_fmg* m, const double* f, double* phi, double lambda, double tol, int32_t max_cycles,
                    int32_t* cycles, double* res_max, double* f_max);
 
+/* nsteps reaction-diffusion steps on the forest's leaf fields u, v (device,
+ * nleaves * 256 doubles each, updated in place), the schemes and models of
+ * amrv_rd_step with this forest's Laplacian (the rules above, lambda = 0):
+ * EULER and MIDPOINT explicit (the paper's Gray-Scott AMR run uses
+ * MIDPOINT), SPLIT and IMEX through amrv_fmg_solve per species (tol,
+ * max_cycles as there).  cycles_total and res_max (host, may be NULL)
+ * receive the V-cycles summed over the solves and the largest final
+ * residual.  Returns 0 or the first failing solve's code. */
+int amrv_fmg_rd_step(amrv_fmg* m, const amrv_rd_params* p, int32_t scheme, double dt, int32_t nsteps, double* u,
+                     double* v, double tol, int32_t max_cycles, int32_t* cycles_total, double* res_max);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,12 +29,14 @@
 // A V-cycle: from the finest level down to level 2, `pre` red-black sweeps,
 // the residual, its restriction with the state's into the parents, and the
 // parents' coarse right-hand side; on level 1 (complete: base x base blocks)
-// `pre` sweeps, then the uniform-grid solver of multigrid.hip on the level-1
-// grid for the correction L(e) = r (from e = 0, to 1e-4 of r), then `post`
+// `pre` sweeps, then one V-cycle of the uniform-grid solver of multigrid.hip
+// on the level-1 grid for the correction L(e) = r (from e = 0), then `post`
 // sweeps; back up, every block adds the bilinear interpolation (within its
 // parent) of the parent's change since restriction, then `post` sweeps.
-// After each cycle the problem's residual over the leaves is reduced and
-// read back for the stopping rule max |r| <= tol max |f|.
+// A cycle has no host wait: a solve enqueues as many cycles as the previous
+// solve needed, less one, before it first reads back the problem's residual
+// over the leaves, then checks after every cycle (the stopping rule max |r|
+// <= tol max |f|).
 //
 // Layout in the caller's workspace (256-byte aligned arrays):
 //   tables   lvl, ij[2], nbr[4], chi[4], cnb[4], par per block; leaf -> block
@@ -56,6 +58,7 @@
 
 #include "../../include/amrv_mg.h"
 #include "errors.hpp"
+#include "mg_internal.hpp"
 
 namespace {
 
@@ -345,6 +348,92 @@ __global__ void k_fmg_zero2(unsigned long long* p) {
   if (threadIdx.x < 2) p[threadIdx.x] = 0ull;
 }
 
+// ---- reaction-diffusion on the leaves (Sec. 2.5) ---------------------------
+
+struct RdF {
+  int model;
+  double Du, Dv, p1, p2, p3;
+};
+
+// (F0_u, F0_v) of Eqs. schnakenberg / gray-scott
+__device__ __forceinline__ void react(const RdF& p, double u, double v, double& ru, double& rv) {
+  if (p.model == AMRV_RD_SCHNAKENBERG) {
+    const double uuv = (u * u) * v;
+    ru = p.p1 * ((p.p2 - u) + uuv);
+    rv = p.p1 * (p.p3 - uuv);
+  } else {
+    const double uvv = u * (v * v);
+    ru = p.p1 * (1.0 - u) - uvv;
+    rv = uvv - (p.p1 + p.p2) * v;
+  }
+}
+
+// a leaf field into the state of the leaf blocks
+__global__ void __launch_bounds__(NC) k_fmg_load(FmgDev g, const int* leafblk, const double* w) {
+  g.u[(size_t)leafblk[blockIdx.x] * NC + threadIdx.x] = w[(size_t)blockIdx.x * NC + threadIdx.x];
+}
+
+// D lap(w) at the leaf cells of the loaded field (the problem's rules; g.lam = 0)
+__global__ void __launch_bounds__(NC) k_fmg_lap(FmgDev g, const int* leafblk, double D, double* out) {
+  out[(size_t)blockIdx.x * NC + threadIdx.x] =
+      D * apply_cell(g, leafblk[blockIdx.x], true, threadIdx.x & (NB - 1), threadIdx.x >> 4);
+}
+
+// o = b + c (F0(s) + l), l = D lap(s) (explicit Euler and midpoint stages)
+__global__ void k_fmg_rd_explicit(RdF p, long long n, const double* bu, const double* bv, const double* su,
+                                  const double* sv, const double* lu, const double* lv, double* ou, double* ov,
+                                  double c) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double ru, rv;
+  react(p, su[t], sv[t], ru, rv);
+  const double fu = ru + lu[t], fv = rv + lv[t];
+  ou[t] = bu[t] + c * fu;
+  ov[t] = bv[t] + c * fv;
+}
+
+// split: f = -lambda (w + dt F0(w)) per species
+__global__ void k_fmg_rd_split_rhs(RdF p, long long n, const double* u, const double* v, double lu_, double lv_,
+                                   double dt, double* fu, double* fv) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double ru, rv;
+  react(p, u[t], v[t], ru, rv);
+  fu[t] = -lu_ * (u[t] + dt * ru);
+  fv[t] = -lv_ * (v[t] + dt * rv);
+}
+
+// IMEX first stage: E = F(w), f = -lambda ((w + dt F0(w)) + (dt/2) D lap(w)),
+// initial guess w + dt F(w)
+__global__ void k_fmg_rd_imex_rhs(RdF p, long long n, const double* u, const double* v, const double* du,
+                                  const double* dv, double lu_, double lv_, double dt, double* Eu, double* Ev,
+                                  double* fu, double* fv, double* su, double* sv) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double ru, rv;
+  react(p, u[t], v[t], ru, rv);
+  Eu[t] = ru + du[t];
+  Ev[t] = rv + dv[t];
+  const double hdt = 0.5 * dt;
+  fu[t] = -lu_ * ((u[t] + dt * ru) + hdt * du[t]);
+  fv[t] = -lv_ * ((v[t] + dt * rv) + hdt * dv[t]);
+  su[t] = u[t] + dt * (ru + du[t]);
+  sv[t] = v[t] + dt * (rv + dv[t]);
+}
+
+// IMEX second stage: w1 = w + (dt/2) (E + F(w*)), l = D lap(w*)
+__global__ void k_fmg_rd_imex_final(RdF p, long long n, double* u, double* v, const double* Eu, const double* Ev,
+                                    const double* su, const double* sv, const double* lu, const double* lv,
+                                    double dt) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double ru, rv;
+  react(p, su[t], sv[t], ru, rv);
+  const double hdt = 0.5 * dt;
+  u[t] = u[t] + hdt * (Eu[t] + (ru + lu[t]));
+  v[t] = v[t] + hdt * (Ev[t] + (rv + lv[t]));
+}
+
 // ---------------------------------------------------------------------------
 // host: the block tree
 // ---------------------------------------------------------------------------
@@ -497,7 +586,7 @@ amrv_mg_config base_config(const amrv_fmg_config* c) {
 }
 
 struct FmgLayout {
-  size_t off_tab[7], off_u, off_f, off_fu, off_r, off_uo, off_fg, off_vg, off_red, off_mg, total;
+  size_t off_tab[7], off_u, off_f, off_fu, off_r, off_uo, off_fg, off_vg, off_red, off_tmp[8], off_mg, total;
   size_t mg_bytes;
 };
 
@@ -526,6 +615,7 @@ FmgLayout layout(const amrv_fmg_config* c, const Tree& T) {
   L.off_fg = take(sizeof(double) * n * n);
   L.off_vg = take(sizeof(double) * n * n);
   L.off_red = take(sizeof(unsigned long long) * 2);
+  for (int i = 0; i < 8; i++) L.off_tmp[i] = take(sizeof(double) * NC * (size_t)c->nleaves);  // RD temporaries
   amrv_mg_config mc = base_config(c);
   L.mg_bytes = amrv_mg_workspace_bytes(&mc);
   L.off_mg = take(L.mg_bytes);
@@ -545,9 +635,11 @@ struct amrv_fmg {
   int* leafblk = nullptr;
   double* fgrid = nullptr;
   double* vgrid = nullptr;
+  double* tmp[8] = {};  // leaf fields of the reaction-diffusion steps
   unsigned long long* red = nullptr;
   unsigned long long* hred = nullptr;  // pinned
   amrv_mg* base = nullptr;
+  int last_cycles = 0;  // cycles of the previous solve
 };
 
 namespace {
@@ -595,13 +687,11 @@ int vcycle(amrv_fmg* m) {
   hipLaunchKernelGGL(k_fmg_to_grid, dim3(nblocks(m, 1)), dim3(NC), 0, m->st, m->g, m->T.lstart[1], n, m->fgrid,
                      m->vgrid);
   FMGCHK(hipGetLastError());
-  // the level-1 correction to 1e-4 of its right-hand side (at most 8 of the
-  // uniform solver's cycles): solved as a correction, its error shrinks with
-  // the residual from cycle to cycle
-  const double lam = m->g.lam;
-  int cyc = 0;
-  const int rc = amrv_mg_solve(m->base, m->fgrid, m->vgrid, &lam, 1e-4, 8, &cyc, nullptr, nullptr);
-  if (rc != 0 && rc != AMRV_ENOTCONVERGED) return rc;
+  // the level-1 correction: one of the uniform solver's V-cycles from zero
+  // (it cuts the error by 20 or more; solved as a correction, what is left
+  // shrinks with the residual from cycle to cycle), enqueued without a host
+  // wait
+  if (int rc = amrv::mg_enqueue_correction(m->base, m->fgrid, m->vgrid, m->g.lam, 1)) return rc;
   hipLaunchKernelGGL(k_fmg_from_grid, dim3(nblocks(m, 1)), dim3(NC), 0, m->st, m->g, m->T.lstart[1], n, m->vgrid);
   FMGCHK(hipGetLastError());
   if (int rc2 = sweeps(m, 1, post)) return rc2;
@@ -693,6 +783,7 @@ int amrv_fmg_create(const amrv_fmg_config* cfg, const int32_t* leaf_level, const
   m->fgrid = reinterpret_cast<double*>(base + m->L.off_fg);
   m->vgrid = reinterpret_cast<double*>(base + m->L.off_vg);
   m->red = reinterpret_cast<unsigned long long*>(base + m->L.off_red);
+  for (int i = 0; i < 8; i++) m->tmp[i] = reinterpret_cast<double*>(base + m->L.off_tmp[i]);
   const amrv_mg_config mc = base_config(cfg);
   if (int rc = amrv_mg_create(&mc, base + m->L.off_mg, m->L.mg_bytes, stream, &m->base)) {
     (void)hipHostFree(m->hred);
@@ -738,12 +829,22 @@ int amrv_fmg_solve(amrv_fmg* m, const double* f, double* phi, double lambda, dou
   if (int rc = norms(m, f, &res, &fmax)) return rc;
   int c = 0;
   bool ok = res <= tol * fmax;
+  // cycles the previous solve needed, less one, before the next host check
+  for (int i = 0; !ok && i < std::min(max_cycles, m->last_cycles - 1) && !std::isnan(res); i++) {
+    if (int rc = vcycle(m)) return rc;
+    c++;
+  }
+  if (c > 0) {
+    if (int rc = norms(m, f, &res, nullptr)) return rc;
+    ok = res <= tol * fmax;
+  }
   while (!ok && c < max_cycles && !std::isnan(res)) {
     if (int rc = vcycle(m)) return rc;
     c++;
     if (int rc = norms(m, f, &res, nullptr)) return rc;
     ok = res <= tol * fmax;
   }
+  m->last_cycles = c;
   hipLaunchKernelGGL(k_fmg_leaves, dim3(m->cfg.nleaves), dim3(NC), 0, m->st, m->g, m->leafblk, f, phi, 1);
   FMGCHK(hipGetLastError());
   FMGCHK(hipStreamSynchronize(m->st));
@@ -753,6 +854,83 @@ int amrv_fmg_solve(amrv_fmg* m, const double* f, double* phi, double lambda, dou
   if (std::isnan(res) || std::isinf(res) || std::isinf(fmax))
     return set_error(AMRV_ENONPHYSICAL, "NaN or infinity in the forest multigrid right-hand side or residual");
   if (!ok) return set_error(AMRV_ENOTCONVERGED, "forest multigrid residual above tol after max_cycles V-cycles");
+  return 0;
+}
+
+int amrv_fmg_rd_step(amrv_fmg* m, const amrv_rd_params* p, int32_t scheme, double dt, int32_t nsteps, double* u,
+                     double* v, double tol, int32_t max_cycles, int32_t* cycles_total, double* res_max) {
+  if (!m || !p || !u || !v) return set_error(AMRV_EINVAL, "null argument");
+  if (p->model != AMRV_RD_SCHNAKENBERG && p->model != AMRV_RD_GRAY_SCOTT) return set_error(AMRV_EINVAL, "unknown model");
+  if (!(p->Du > 0.0) || !(p->Dv > 0.0)) return set_error(AMRV_EINVAL, "diffusion coefficients must be positive");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(AMRV_EINVAL, "dt must be positive and finite");
+  if (nsteps < 0) return set_error(AMRV_EINVAL, "nsteps must be >= 0");
+  if (scheme < AMRV_RD_EULER || scheme > AMRV_RD_IMEX) return set_error(AMRV_EINVAL, "unknown scheme");
+  const bool implicit = scheme == AMRV_RD_SPLIT || scheme == AMRV_RD_IMEX;
+  if (implicit && (!(tol > 0.0) || max_cycles < 0)) return set_error(AMRV_EINVAL, "bad tol or max_cycles");
+  const RdF k{p->model, p->Du, p->Dv, p->p1, p->p2, p->p3};
+  const long long n = (long long)m->cfg.nleaves * NC;
+  const int nb = (int)((n + 255) / 256);
+  const int nl = (int)m->cfg.nleaves;
+  FmgDev g0 = m->g;
+  g0.lam = 0.0;
+  double* const* T = m->tmp;
+  // D lap of a leaf field into out
+  auto lap = [&](const double* w, double D, double* out) {
+    hipLaunchKernelGGL(k_fmg_load, dim3(nl), dim3(NC), 0, m->st, g0, m->leafblk, w);
+    hipLaunchKernelGGL(k_fmg_lap, dim3(nl), dim3(NC), 0, m->st, g0, m->leafblk, D, out);
+  };
+  int total = 0;
+  double rmax = 0.0;
+  auto solve = [&](const double* f, double* phi, double lam) {
+    int32_t c = 0;
+    double r = 0.0;
+    const int rc = amrv_fmg_solve(m, f, phi, lam, tol, max_cycles, &c, &r, nullptr);
+    total += c;
+    rmax = std::max(rmax, r);
+    return rc;
+  };
+  for (int s = 0; s < nsteps; s++) {
+    if (scheme == AMRV_RD_EULER || scheme == AMRV_RD_MIDPOINT) {
+      lap(u, k.Du, T[0]);
+      lap(v, k.Dv, T[1]);
+      if (scheme == AMRV_RD_EULER) {
+        hipLaunchKernelGGL(k_fmg_rd_explicit, dim3(nb), dim3(256), 0, m->st, k, n, u, v, u, v, T[0], T[1], u, v, dt);
+      } else {
+        hipLaunchKernelGGL(k_fmg_rd_explicit, dim3(nb), dim3(256), 0, m->st, k, n, u, v, u, v, T[0], T[1], T[2], T[3],
+                           0.5 * dt);
+        lap(T[2], k.Du, T[0]);
+        lap(T[3], k.Dv, T[1]);
+        hipLaunchKernelGGL(k_fmg_rd_explicit, dim3(nb), dim3(256), 0, m->st, k, n, u, v, T[2], T[3], T[0], T[1], u, v,
+                           dt);
+      }
+      FMGCHK(hipGetLastError());
+      continue;
+    }
+    if (scheme == AMRV_RD_SPLIT) {
+      const double lu = 1.0 / (dt * k.Du), lv = 1.0 / (dt * k.Dv);
+      hipLaunchKernelGGL(k_fmg_rd_split_rhs, dim3(nb), dim3(256), 0, m->st, k, n, u, v, lu, lv, dt, T[0], T[1]);
+      FMGCHK(hipGetLastError());
+      if (int rc = solve(T[0], u, lu)) return rc;
+      if (int rc = solve(T[1], v, lv)) return rc;
+      continue;
+    }
+    const double lu = 2.0 / (dt * k.Du), lv = 2.0 / (dt * k.Dv);
+    lap(u, k.Du, T[0]);
+    lap(v, k.Dv, T[1]);
+    hipLaunchKernelGGL(k_fmg_rd_imex_rhs, dim3(nb), dim3(256), 0, m->st, k, n, u, v, T[0], T[1], lu, lv, dt, T[2],
+                       T[3], T[4], T[5], T[6], T[7]);
+    FMGCHK(hipGetLastError());
+    if (int rc = solve(T[4], T[6], lu)) return rc;
+    if (int rc = solve(T[5], T[7], lv)) return rc;
+    lap(T[6], k.Du, T[0]);
+    lap(T[7], k.Dv, T[1]);
+    hipLaunchKernelGGL(k_fmg_rd_imex_final, dim3(nb), dim3(256), 0, m->st, k, n, u, v, T[2], T[3], T[6], T[7], T[0],
+                       T[1], dt);
+    FMGCHK(hipGetLastError());
+  }
+  FMGCHK(hipStreamSynchronize(m->st));
+  if (cycles_total) *cycles_total = total;
+  if (res_max) *res_max = rmax;
   return 0;
 }
 

@@ -36,6 +36,7 @@
 
 #include "../../include/amrv_mg.h"
 #include "errors.hpp"
+#include "mg_internal.hpp"
 
 namespace {
 
@@ -1218,6 +1219,24 @@ int run_cycles(amrv_mg* m, double tol, int max_cycles, int unchecked, int* cycle
 }
 
 }  // namespace
+
+namespace amrv {
+
+int mg_enqueue_correction(amrv_mg* m, const double* f, double* out, double lambda, int cycles) {
+  if (!m || !f || !out) return set_error(AMRV_EINVAL, "null argument");
+  if (m->g.nf != 1 || m->var) return set_error(AMRV_EINVAL, "a correction solve needs one field and the constant coefficient");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return set_error(AMRV_EINVAL, "lambda must be non-negative and finite");
+  if (int rc = set_params(m, &lambda)) return rc;
+  const size_t bytes = (size_t)m->g.cells[0] * sizeof(double);
+  MGCHK(hipMemcpyAsync(m->g.f[0][0], f, bytes, hipMemcpyDeviceToDevice, m->st));
+  MGCHK(hipMemsetAsync(m->g.phi[0][0], 0, bytes, m->st));
+  for (int c = 0; c < cycles; c++)
+    if (int rc = launch_cycle(m)) return rc;
+  MGCHK(hipMemcpyAsync(out, m->g.phi[0][0], bytes, hipMemcpyDeviceToDevice, m->st));
+  return 0;
+}
+
+}  // namespace amrv
 
 extern "C" {
 

@@ -219,3 +219,24 @@ class GpuForestMultigrid:
                                        ctypes.byref(res), ctypes.byref(fmax)))
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
         return cyc.value, res.value, fmax.value
+
+    def rd_step(self, u: torch.Tensor, v: torch.Tensor, dt: float, scheme: int, params: dict, nsteps: int = 1,
+                tol: float = 1e-10, max_cycles: int = 50):
+        """nsteps reaction-diffusion steps on the leaf fields u, v in place
+        (params: dict with model, Du, Dv, p1, p2, p3).  Returns (V-cycles
+        summed over the solves, largest final residual)."""
+        for t in (u, v):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError("expected contiguous float64 device tensors")
+            if t.numel() != self.nleaves * 256:
+                raise ValueError(f"expected {self.nleaves * 256} values, got {t.numel()}")
+        p = rd_params(int(params["model"]), params["Du"], params["Dv"], params["p1"], params["p2"],
+                      params.get("p3", 0.0))
+        cyc = ctypes.c_int32()
+        res = ctypes.c_double()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        N.check(N.lib().amrv_fmg_rd_step(self._h, ctypes.byref(p), int(scheme), float(dt), int(nsteps),
+                                         ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(v.data_ptr()), float(tol),
+                                         int(max_cycles), ctypes.byref(cyc), ctypes.byref(res)))
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return cyc.value, res.value

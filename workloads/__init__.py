@@ -650,3 +650,32 @@ def fmg_forest(scheme: Scheme, centre=(0.5, 0.5), radius: float = 0.25, buffer_c
         return _box_shell_hit(lo, lo + h, c, radius * side, float(buffer_cells * h / s.block_nx[0]))
 
     return refined_forest(s, refine)
+
+
+def gray_scott_amr(base: int = 8, max_level: int = 3):
+    """Sec. 2.5.2's Gray-Scott AMR setup on a static forest: the periodic
+    square of side 2, base x base blocks of 16^2 cells at level 1 (128^2 for
+    base 8) and max_level 3 (512^2 effective); a block at level l <
+    max_level is refined while its box comes within 0.7 - 0.2 (l - 1) of a
+    perturbation centre (the paper refines as the pattern grows; here the
+    forest stays as it starts).  Initial state: u = 1, v = 0 with the two
+    Gaussians 0.5 exp(-25 |r - r_i|^2), r_1 = (0.5, 0.5), r_2 = (0.55, 0.6),
+    subtracted from u and added to v.  Returns (forest, u, v, L = 2), fields
+    [leaf][y][x]."""
+    s = fmg_scheme(base=base, max_level=max_level, bc=PERIODIC, length=2.0)
+    centres = ((0.5, 0.5), (0.55, 0.6))
+
+    def refine(l, ij):
+        h = 2.0 / (base << (l - 1))
+        lo = np.array([ij[0] * h, ij[1] * h])
+        reach = 0.7 - 0.2 * (l - 1)
+        for c in centres:
+            c = np.asarray(c)
+            if float(np.sqrt(np.sum((np.clip(c, lo, lo + h) - c) ** 2))) < reach:
+                return True
+        return False
+
+    f = refined_forest(s, refine)
+    x, y = cell_centres(f)
+    g = sum(0.5 * np.exp(-25.0 * ((x - cx) ** 2 + (y - cy) ** 2)) for cx, cy in centres)
+    return f, 1.0 - g, g.copy(), 2.0
