@@ -37,15 +37,19 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
 COUNTER_SOURCES = ("kernels.hip", "stage_ilp.hip", "stage_fast.hip", "stage_common.hpp", "bf16.hpp", "physics.hpp",
-                   "internal.hpp", "../build.py")
+                   "internal.hpp")
 
 
 def counter_sources_sha256() -> str:
-    """sha256 of the stage kernel's sources and the build (its compile flags)."""
+    """sha256 of the stage kernel's sources and its compile flags (the common
+    hipcc flags and the per-unit flags of paper_2004_03275_amd/build.py)."""
     import hashlib
 
+    from paper_2004_03275_amd import build as B
+
     csrc = os.path.join(ROOT, "paper_2004_03275_amd", "csrc")
-    return hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read() for f in COUNTER_SOURCES)).hexdigest()
+    data = b"".join(open(os.path.join(csrc, f), "rb").read() for f in COUNTER_SOURCES)
+    return hashlib.sha256(data + repr(B.HIPFLAGS).encode() + repr(sorted(B.UNITS.items())).encode()).hexdigest()
 
 
 def measured_counters(workload: str, limiter: str = "vanleer", variant: int = 0, arithmetic: str = "fast") -> dict:
