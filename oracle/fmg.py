@@ -220,3 +220,82 @@ def rd_step(forest, u, v, dt: float, scheme: int, p: dict, length: float, bc: in
         su, sv = full(star[0], star[1])
         return u + (0.5 * dt) * (fu + su), v + (0.5 * dt) * (fv + sv)
     raise ValueError(f"unknown scheme {scheme}")
+
+
+# -- Poisson and the divergence control on the forest (Sec. 2.4: solve
+# lap(phi) = div B*, set B = B* - grad phi; Sec. 1.4: the multigrid on the
+# block-adaptive grid) ---------------------------------------------------------
+
+def _value(g: ForestGrid, k: int, x: int, y: int, dx: int, dy: int) -> dict:
+    """{unknown: weight} of the value one cell over from leaf k's cell (x, y):
+    the cell itself inside the block, else the ghost rules (1)-(4), each of
+    which interpolates linear data exactly."""
+    if 0 <= x + dx < g.nb and 0 <= y + dy < g.nb:
+        return {g.index(k, x + dx, y + dy): 1.0}
+    return g.neighbour(k, x, y, dx, dy)
+
+
+def diff_matrix(g: ForestGrid, d: int) -> sp.csr_matrix:
+    """Central difference along d (0 = x): (w(+1) - w(-1)) * (n_l / (2L))."""
+    rows, cols, vals = [], [], []
+    dx, dy = (1, 0) if d == 0 else (0, 1)
+    for k in range(len(g.level)):
+        s = 0.5 * g.cells_per_side(int(g.level[k])) / g.length
+        for y in range(g.nb):
+            for x in range(g.nb):
+                r = g.index(k, x, y)
+                acc: dict = {}
+                for sgn in (1, -1):
+                    for q, w in _value(g, k, x, y, sgn * dx, sgn * dy).items():
+                        acc[q] = acc.get(q, 0.0) + sgn * w
+                for q, w in acc.items():
+                    rows.append(r)
+                    cols.append(q)
+                    vals.append(w * s)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(g.ncell, g.ncell))
+
+
+def cell_areas(forest, length: float) -> np.ndarray:
+    """Area of every leaf cell, [leaf][y][x]."""
+    s = forest.scheme
+    n = (s.base_blocks[0] << (forest.level.astype(np.int64) - 1)) * s.block_nx[0]
+    a = (length / n) ** 2
+    return np.broadcast_to(a[:, None, None], (forest.n, s.block_nx[0], s.block_nx[0])).copy()
+
+
+def divergence(forest, bx, by, length: float, bc: int) -> np.ndarray:
+    """Central-difference divergence at the leaf cells (x, then y)."""
+    g = grid(forest, length, bc)
+    shp = np.shape(bx)
+    return ((diff_matrix(g, 0) @ np.ravel(bx)) + (diff_matrix(g, 1) @ np.ravel(by))).reshape(shp)
+
+
+def gradient(forest, phi, length: float, bc: int):
+    g = grid(forest, length, bc)
+    shp = np.shape(phi)
+    return (diff_matrix(g, 0) @ np.ravel(phi)).reshape(shp), (diff_matrix(g, 1) @ np.ravel(phi)).reshape(shp)
+
+
+def poisson(forest, f, length: float, bc: int) -> np.ndarray:
+    """The zero-mean (area-weighted) solution of lap(phi) = f - mean(f), mean
+    area-weighted: lap is singular on a periodic or Neumann domain (constants
+    are its null space, and the area-weighted sum of lap(phi) vanishes), so
+    the bordered system [[lap, 1], [area^T, 0]] [phi; c] = [f; 0] is solved,
+    whose c is the area-weighted mean of f."""
+    g = grid(forest, length, bc)
+    A = matrix(g, 0.0)
+    a = cell_areas(forest, length).ravel()
+    n = g.ncell
+    M = sp.bmat([[A, sp.csr_matrix(np.ones((n, 1)))], [sp.csr_matrix(a.reshape(1, n)), None]]).tocsc()
+    sol = spla.spsolve(M, np.concatenate([np.ravel(f), [0.0]]))
+    return sol[:n].reshape(np.shape(f))
+
+
+def divb_project(forest, bx, by, length: float, bc: int):
+    """The divergence control of Sec. 2.4 on the leaf cells: phi = the
+    zero-mean solution of lap(phi) = div B*, B = B* - grad phi (central
+    differences for div and grad, the 5-point composite lap: an approximate
+    projection).  Returns (bx, by, phi)."""
+    phi = poisson(forest, divergence(forest, bx, by, length, bc), length, bc)
+    gx, gy = gradient(forest, phi, length, bc)
+    return bx - gx, by - gy, phi
