@@ -230,11 +230,15 @@ int amrv_fmg_levels(const amrv_fmg* m, int32_t* nblocks_per_level);
 
 /* Solves lap(phi) - lambda phi = f on the leaf cells (f, phi: device fields
  * of nleaves * 256 doubles; phi holds the initial guess on entry and the
- * solution on return).  cycles, res_max, f_max (host, may be NULL) receive
- * the V-cycle count, the final maximum residual and max |f|.  Returns 0,
- * AMRV_ENOTCONVERGED, AMRV_ENONPHYSICAL (NaN or infinity in f, phi or the
- * residual), AMRV_EINVAL (lambda <= 0, tol <= 0, max_cycles < 0) or
- * AMRV_EDEVICE. */
+ * solution on return).  lambda = 0 (Poisson, the divergence control of
+ * Sec. 2.4): lap is singular on a periodic or Neumann domain (constants are
+ * its null space, the area-weighted sum of lap(phi) vanishes), so the
+ * problem solved is lap(phi) = f - mean(f) and phi is returned with zero
+ * mean, means weighted by cell area.  cycles, res_max, f_max (host, may be
+ * NULL) receive the V-cycle count, the final maximum residual and max |f|
+ * of the problem solved.  Returns 0, AMRV_ENOTCONVERGED, AMRV_ENONPHYSICAL
+ * (NaN or infinity in f, phi or the residual), AMRV_EINVAL (lambda < 0,
+ * tol <= 0, max_cycles < 0) or AMRV_EDEVICE. */
 int amrv_fmg_solve(amrv_fmg* m, const double* f, double* phi, double lambda, double tol, int32_t max_cycles,
                    int32_t* cycles, double* res_max, double* f_max);
 
@@ -248,6 +252,19 @@ int amrv_fmg_solve(amrv_fmg* m, const double* f, double* phi, double lambda, dou
  * residual.  Returns 0 or the first failing solve's code. */
 int amrv_fmg_rd_step(amrv_fmg* m, const amrv_rd_params* p, int32_t scheme, double dt, int32_t nsteps, double* u,
                      double* v, double tol, int32_t max_cycles, int32_t* cycles_total, double* res_max);
+
+/* The divergence control of Sec. 2.4 on the forest's leaf fields bx, by
+ * (device, nleaves * 256 doubles each, updated in place): phi is the
+ * zero-mean solution of lap(phi) = div B* (amrv_fmg_solve with lambda = 0,
+ * tol and max_cycles as there), then B = B* - grad phi; div and grad are
+ * central differences (w(+1) - w(-1)) / (2 h_l) at each cell's level with
+ * the neighbour values of the rules above (exact for linear data), added x
+ * then y.  An approximate projection: it removes the divergence up to what
+ * the compact lap and div(grad) disagree on (O(h^2) away from coarse-fine
+ * faces, O(1) next to them).  div_before, div_after (host, may be NULL)
+ * receive max |div B| before and after; cycles the V-cycle count. */
+int amrv_fmg_divb_project(amrv_fmg* m, double* bx, double* by, double tol, int32_t max_cycles, int32_t* cycles,
+                          double* div_before, double* div_after);
 
 #ifdef __cplusplus
 }

@@ -85,6 +85,7 @@ struct FmgDev {
   double* uo;
   double lam;
   double ih2[FMG_MAXL + 1];  // 1/h^2 per level (1-based)
+  double rh[FMG_MAXL + 1];   // 1/h per level
 };
 
 // the value across face `face` of cell (x, y) of block b, as c + w u(x, y)
@@ -315,12 +316,18 @@ __device__ __forceinline__ void fold_max(double v, unsigned long long* out) {
   }
 }
 
-// max |r| of the problem over the leaves (every block launched; parents skip)
-__global__ void __launch_bounds__(NC) k_fmg_resmax(FmgDev g, unsigned long long* out) {
+// max |r| of the problem over the leaves into out[0] and, with fmax, max |f|
+// (the problem's f as solved) into out[1] (every block launched; parents skip)
+__global__ void __launch_bounds__(NC) k_fmg_resmax(FmgDev g, unsigned long long* out, int fmax) {
   const int b = blockIdx.x;
   if (g.chi[4 * b] >= 0) return;  // uniform per workgroup
   const double r = residual(g, b, threadIdx.x & (NB - 1), threadIdx.x >> 4);
   fold_max(isnan(r) ? INFINITY : fabs(r), out);
+  if (fmax) {
+    __syncthreads();
+    const double f = g.fu[(size_t)b * NC + threadIdx.x];
+    fold_max(isnan(f) ? INFINITY : fabs(f), out + 1);
+  }
 }
 
 // leaf fields <-> block arrays; dir 0: f and phi in, 1: phi out
@@ -346,6 +353,80 @@ __global__ void k_fmg_maxabs(const double* v, long long count, unsigned long lon
 
 __global__ void k_fmg_zero2(unsigned long long* p) {
   if (threadIdx.x < 2) p[threadIdx.x] = 0ull;
+}
+
+// ---- Poisson (lambda = 0) and the divergence control (Sec. 2.4) ------------
+
+// area-weighted sum of a leaf block's cells of `which` (0: g.f, 1: g.u) into
+// part[k] (a fixed reduction order: the same bits on every run)
+__global__ void __launch_bounds__(NC) k_fmg_wsum(FmgDev g, const int* leafblk, int which, double* part) {
+  __shared__ double sm[NC / 64];
+  const int b = leafblk[blockIdx.x];
+  const double* a = which ? g.u : g.f;
+  double v = a[(size_t)b * NC + threadIdx.x];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ((sm[0] + sm[1]) + (sm[2] + sm[3])) / g.ih2[g.lvl[b]];
+}
+
+// mean = sum(part) / area, one workgroup, a fixed order
+__global__ void __launch_bounds__(NC) k_fmg_wmean(const double* part, int n, double area, double* mean) {
+  __shared__ double sm[NC];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += NC) v += part[i];
+  sm[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = NC / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *mean = sm[0] / area;
+}
+
+// subtract *mean from the leaf blocks' g.f and g.fu (which 0) or g.u (which 1)
+__global__ void __launch_bounds__(NC) k_fmg_submean(FmgDev g, const int* leafblk, int which, const double* mean) {
+  const size_t i = (size_t)leafblk[blockIdx.x] * NC + threadIdx.x;
+  const double m = *mean;
+  if (which == 0) {
+    g.f[i] -= m;
+    g.fu[i] -= m;
+  } else {
+    g.u[i] -= m;
+  }
+}
+
+// the value one cell over from cell (x, y) of leaf block b along face `face`
+__host__ __device__ inline double face_value(const FmgDev& g, int b, int x, int y, int face) {
+  const int xn = x + (face == 0 ? -1 : (face == 1 ? 1 : 0));
+  const int yn = y + (face == 2 ? -1 : (face == 3 ? 1 : 0));
+  if (xn >= 0 && xn < NB && yn >= 0 && yn < NB) return g.u[(size_t)b * NC + xn + NB * yn];
+  double c, w;
+  across(g, b, true, x, y, face, c, w);
+  return c + w * g.u[(size_t)b * NC + x + NB * y];
+}
+
+// central difference along d of the loaded leaf field: (w(+1) - w(-1)) (n_l / 2L),
+// into out (acc 0) or added to it (acc 1)
+__global__ void __launch_bounds__(NC) k_fmg_diff(FmgDev g, const int* leafblk, int d, int acc, double* out) {
+  const int b = leafblk[blockIdx.x];
+  const int x = threadIdx.x & (NB - 1), y = threadIdx.x >> 4;
+  const double v = (face_value(g, b, x, y, 2 * d + 1) - face_value(g, b, x, y, 2 * d)) * (0.5 * g.rh[g.lvl[b]]);
+  const size_t o = (size_t)blockIdx.x * NC + threadIdx.x;
+  out[o] = acc ? out[o] + v : v;
+}
+
+__global__ void k_fmg_sub2(long long n, double* a, const double* da, double* b, const double* db) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  a[t] = a[t] - da[t];
+  b[t] = b[t] - db[t];
+}
+
+__global__ void k_fmg_zero(long long n, double* a) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t < n) a[t] = 0.0;
 }
 
 // ---- reaction-diffusion on the leaves (Sec. 2.5) ---------------------------
@@ -586,7 +667,7 @@ amrv_mg_config base_config(const amrv_fmg_config* c) {
 }
 
 struct FmgLayout {
-  size_t off_tab[7], off_u, off_f, off_fu, off_r, off_uo, off_fg, off_vg, off_red, off_tmp[8], off_mg, total;
+  size_t off_tab[7], off_u, off_f, off_fu, off_r, off_uo, off_fg, off_vg, off_red, off_tmp[8], off_part, off_mg, total;
   size_t mg_bytes;
 };
 
@@ -616,6 +697,7 @@ FmgLayout layout(const amrv_fmg_config* c, const Tree& T) {
   L.off_vg = take(sizeof(double) * n * n);
   L.off_red = take(sizeof(unsigned long long) * 2);
   for (int i = 0; i < 8; i++) L.off_tmp[i] = take(sizeof(double) * NC * (size_t)c->nleaves);  // RD temporaries
+  L.off_part = take(sizeof(double) * ((size_t)c->nleaves + 1));  // per-leaf sums and their mean
   amrv_mg_config mc = base_config(c);
   L.mg_bytes = amrv_mg_workspace_bytes(&mc);
   L.off_mg = take(L.mg_bytes);
@@ -636,6 +718,8 @@ struct amrv_fmg {
   double* fgrid = nullptr;
   double* vgrid = nullptr;
   double* tmp[8] = {};  // leaf fields of the reaction-diffusion steps
+  double* part = nullptr;  // per-leaf area-weighted sums, then [nleaves] = their mean
+  double area = 0.0;       // L^2
   unsigned long long* red = nullptr;
   unsigned long long* hred = nullptr;  // pinned
   amrv_mg* base = nullptr;
@@ -703,18 +787,25 @@ int vcycle(amrv_fmg* m) {
   return 0;
 }
 
-// max |r| over the leaves (and, with fmax, max |f| of the leaf field)
-int norms(amrv_fmg* m, const double* f, double* res, double* fmax) {
+// max |r| over the leaves (and, with fmax, max |f| of the problem as solved)
+int norms(amrv_fmg* m, double* res, double* fmax) {
   hipLaunchKernelGGL(k_fmg_zero2, dim3(1), dim3(64), 0, m->st, m->red);
-  hipLaunchKernelGGL(k_fmg_resmax, dim3(m->T.nblk), dim3(NC), 0, m->st, m->g, m->red);
-  if (fmax)
-    hipLaunchKernelGGL(k_fmg_maxabs, dim3(std::min<long long>(1024, m->cfg.nleaves)), dim3(NC), 0, m->st, f,
-                       (long long)m->cfg.nleaves * NC, m->red + 1);
+  hipLaunchKernelGGL(k_fmg_resmax, dim3(m->T.nblk), dim3(NC), 0, m->st, m->g, m->red, fmax ? 1 : 0);
   FMGCHK(hipGetLastError());
   FMGCHK(hipMemcpyAsync(m->hred, m->red, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, m->st));
   FMGCHK(hipStreamSynchronize(m->st));
   *res = bits_to_double(m->hred[0]);
   if (fmax) *fmax = bits_to_double(m->hred[1]);
+  return 0;
+}
+
+// subtract the area-weighted mean of the leaves' f (which 0: g.f and g.fu) or u (1)
+int remove_mean(amrv_fmg* m, int which) {
+  const int nl = (int)m->cfg.nleaves;
+  hipLaunchKernelGGL(k_fmg_wsum, dim3(nl), dim3(NC), 0, m->st, m->g, m->leafblk, which, m->part);
+  hipLaunchKernelGGL(k_fmg_wmean, dim3(1), dim3(NC), 0, m->st, m->part, nl, m->area, m->part + nl);
+  hipLaunchKernelGGL(k_fmg_submean, dim3(nl), dim3(NC), 0, m->st, m->g, m->leafblk, which, m->part + nl);
+  FMGCHK(hipGetLastError());
   return 0;
 }
 
@@ -779,11 +870,14 @@ int amrv_fmg_create(const amrv_fmg_config* cfg, const int32_t* leaf_level, const
   for (int l = 1; l <= FMG_MAXL; l++) {
     const double q = (double)((long long)cfg->base * NB << (l - 1)) / cfg->length;
     g.ih2[l] = q * q;
+    g.rh[l] = q;
   }
   m->fgrid = reinterpret_cast<double*>(base + m->L.off_fg);
   m->vgrid = reinterpret_cast<double*>(base + m->L.off_vg);
   m->red = reinterpret_cast<unsigned long long*>(base + m->L.off_red);
   for (int i = 0; i < 8; i++) m->tmp[i] = reinterpret_cast<double*>(base + m->L.off_tmp[i]);
+  m->part = reinterpret_cast<double*>(base + m->L.off_part);
+  m->area = cfg->length * cfg->length;
   const amrv_mg_config mc = base_config(cfg);
   if (int rc = amrv_mg_create(&mc, base + m->L.off_mg, m->L.mg_bytes, stream, &m->base)) {
     (void)hipHostFree(m->hred);
@@ -820,13 +914,19 @@ int amrv_fmg_levels(const amrv_fmg* m, int32_t* nblocks_per_level) {
 int amrv_fmg_solve(amrv_fmg* m, const double* f, double* phi, double lambda, double tol, int32_t max_cycles,
                    int32_t* cycles, double* res_max, double* f_max) {
   if (!m || !f || !phi) return set_error(AMRV_EINVAL, "null argument");
-  if (!(lambda > 0.0) || !std::isfinite(lambda)) return set_error(AMRV_EINVAL, "lambda must be > 0");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return set_error(AMRV_EINVAL, "lambda must be >= 0 and finite");
   if (!(tol > 0.0) || max_cycles < 0) return set_error(AMRV_EINVAL, "tol must be > 0 and max_cycles >= 0");
   m->g.lam = lambda;
   hipLaunchKernelGGL(k_fmg_leaves, dim3(m->cfg.nleaves), dim3(NC), 0, m->st, m->g, m->leafblk, f, phi, 0);
   FMGCHK(hipGetLastError());
+  // Poisson: lap has the constants as null space and its area-weighted sums
+  // vanish, so the problem solved is lap(phi) = f - mean(f), and phi is
+  // returned with zero mean (means area-weighted)
+  const bool poisson = lambda == 0.0;
+  if (poisson)
+    if (int rc = remove_mean(m, 0)) return rc;
   double res = 0.0, fmax = 0.0;
-  if (int rc = norms(m, f, &res, &fmax)) return rc;
+  if (int rc = norms(m, &res, &fmax)) return rc;
   int c = 0;
   bool ok = res <= tol * fmax;
   // cycles the previous solve needed, less one, before the next host check
@@ -835,16 +935,18 @@ int amrv_fmg_solve(amrv_fmg* m, const double* f, double* phi, double lambda, dou
     c++;
   }
   if (c > 0) {
-    if (int rc = norms(m, f, &res, nullptr)) return rc;
+    if (int rc = norms(m, &res, nullptr)) return rc;
     ok = res <= tol * fmax;
   }
   while (!ok && c < max_cycles && !std::isnan(res)) {
     if (int rc = vcycle(m)) return rc;
     c++;
-    if (int rc = norms(m, f, &res, nullptr)) return rc;
+    if (int rc = norms(m, &res, nullptr)) return rc;
     ok = res <= tol * fmax;
   }
   m->last_cycles = c;
+  if (poisson)
+    if (int rc = remove_mean(m, 1)) return rc;
   hipLaunchKernelGGL(k_fmg_leaves, dim3(m->cfg.nleaves), dim3(NC), 0, m->st, m->g, m->leafblk, f, phi, 1);
   FMGCHK(hipGetLastError());
   FMGCHK(hipStreamSynchronize(m->st));
@@ -931,6 +1033,51 @@ int amrv_fmg_rd_step(amrv_fmg* m, const amrv_rd_params* p, int32_t scheme, doubl
   FMGCHK(hipStreamSynchronize(m->st));
   if (cycles_total) *cycles_total = total;
   if (res_max) *res_max = rmax;
+  return 0;
+}
+
+int amrv_fmg_divb_project(amrv_fmg* m, double* bx, double* by, double tol, int32_t max_cycles, int32_t* cycles,
+                          double* div_before, double* div_after) {
+  if (!m || !bx || !by) return set_error(AMRV_EINVAL, "null argument");
+  if (!(tol > 0.0) || max_cycles < 0) return set_error(AMRV_EINVAL, "bad tol or max_cycles");
+  const long long n = (long long)m->cfg.nleaves * NC;
+  const int nb = (int)((n + 255) / 256);
+  const int nl = (int)m->cfg.nleaves;
+  double* const* T = m->tmp;
+  // the central divergence of (bx, by) into out
+  auto div = [&](double* out) {
+    hipLaunchKernelGGL(k_fmg_load, dim3(nl), dim3(NC), 0, m->st, m->g, m->leafblk, bx);
+    hipLaunchKernelGGL(k_fmg_diff, dim3(nl), dim3(NC), 0, m->st, m->g, m->leafblk, 0, 0, out);
+    hipLaunchKernelGGL(k_fmg_load, dim3(nl), dim3(NC), 0, m->st, m->g, m->leafblk, by);
+    hipLaunchKernelGGL(k_fmg_diff, dim3(nl), dim3(NC), 0, m->st, m->g, m->leafblk, 1, 1, out);
+  };
+  auto maxabs = [&](const double* v, double* out) -> int {
+    hipLaunchKernelGGL(k_fmg_zero2, dim3(1), dim3(64), 0, m->st, m->red);
+    hipLaunchKernelGGL(k_fmg_maxabs, dim3(std::min(1024, nb)), dim3(NC), 0, m->st, v, n, m->red);
+    FMGCHK(hipGetLastError());
+    FMGCHK(hipMemcpyAsync(m->hred, m->red, sizeof(unsigned long long), hipMemcpyDeviceToHost, m->st));
+    FMGCHK(hipStreamSynchronize(m->st));
+    *out = bits_to_double(m->hred[0]);
+    return 0;
+  };
+  div(T[0]);
+  if (div_before)
+    if (int rc = maxabs(T[0], div_before)) return rc;
+  hipLaunchKernelGGL(k_fmg_zero, dim3(nb), dim3(256), 0, m->st, n, T[1]);
+  FMGCHK(hipGetLastError());
+  // phi: the zero-mean solution of lap(phi) = div B* - mean
+  const int rc = amrv_fmg_solve(m, T[0], T[1], 0.0, tol, max_cycles, cycles, nullptr, nullptr);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_fmg_load, dim3(nl), dim3(NC), 0, m->st, m->g, m->leafblk, T[1]);
+  hipLaunchKernelGGL(k_fmg_diff, dim3(nl), dim3(NC), 0, m->st, m->g, m->leafblk, 0, 0, T[2]);
+  hipLaunchKernelGGL(k_fmg_diff, dim3(nl), dim3(NC), 0, m->st, m->g, m->leafblk, 1, 0, T[3]);
+  hipLaunchKernelGGL(k_fmg_sub2, dim3(nb), dim3(256), 0, m->st, n, bx, T[2], by, T[3]);
+  FMGCHK(hipGetLastError());
+  if (div_after) {
+    div(T[0]);
+    if (int rc2 = maxabs(T[0], div_after)) return rc2;
+  }
+  FMGCHK(hipStreamSynchronize(m->st));
   return 0;
 }
 

@@ -240,3 +240,20 @@ class GpuForestMultigrid:
                                          int(max_cycles), ctypes.byref(cyc), ctypes.byref(res)))
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
         return cyc.value, res.value
+
+    def divb_project(self, bx: torch.Tensor, by: torch.Tensor, tol: float = 1e-10, max_cycles: int = 50):
+        """The divergence control of Sec. 2.4 on the leaf fields bx, by
+        (updated in place).  Returns (cycles, max |div B| before, after)."""
+        for t in (bx, by):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError("expected contiguous float64 device tensors")
+            if t.numel() != self.nleaves * 256:
+                raise ValueError(f"expected {self.nleaves * 256} values, got {t.numel()}")
+        cyc = ctypes.c_int32()
+        before, after = ctypes.c_double(), ctypes.c_double()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        N.check(N.lib().amrv_fmg_divb_project(self._h, ctypes.c_void_p(bx.data_ptr()), ctypes.c_void_p(by.data_ptr()),
+                                              float(tol), int(max_cycles), ctypes.byref(cyc), ctypes.byref(before),
+                                              ctypes.byref(after)))
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return cyc.value, before.value, after.value
