@@ -257,3 +257,15 @@ class GpuForestMultigrid:
                                               ctypes.byref(after)))
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
         return cyc.value, before.value, after.value
+
+
+def project_forest_b(g, fm: GpuForestMultigrid, ib: int, tol: float = 1e-10, max_cycles: int = 50):
+    """The divergence control of Sec. 2.4 on a 2D forest's state: B (state
+    variables ib, ib + 1, each a [leaf][16][16] field) projected in place by
+    the forest solver fm built on the same leaves (g: forest.GpuForest).  The
+    state moves device to device only.  Returns (cycles, max |div B| before,
+    after)."""
+    U = g.state_tensor()
+    out = fm.divb_project(U[ib], U[ib + 1], tol=tol, max_cycles=max_cycles)
+    g.set_state(U)
+    return out
