@@ -231,3 +231,97 @@ def test_projection_reduces_the_divergence_on_a_refined_forest():
     bx1, by1, _ = fmg.divb_project(f, bx, by, 1.0, fmg.PERIODIC)
     d1 = np.max(np.abs(fmg.divergence(f, bx1, by1, 1.0, fmg.PERIODIC)))
     assert d1 <= 0.1 * d0, (d0, d1)
+
+
+# -- 3D (octree) ---------------------------------------------------------------
+
+def _forest3(bc, nb=4, base=2, max_level=3, centre=(0.3, 0.35, 0.4), radius=0.2):
+    s = W.fmg_scheme(base=base, max_level=max_level, bc=bc, ndim=3)
+    f = W.fmg_forest(s, centre=centre, radius=radius)
+    s.block_nx = (nb, nb, nb)
+    return f
+
+
+def test_3d_uniform_forest_is_the_uniform_grid():
+    """Every leaf at level 2 (4^3 cells per block, 16^3 grid): the composite
+    solve equals oracle/rd.py's spectral 3D solve, both boundary rules."""
+    for bc in (fmg.PERIODIC, fmg.NEUMANN):
+        s = W.fmg_scheme(base=2, max_level=2, bc=bc, ndim=3)
+        s.block_nx = (4, 4, 4)
+        f = W.uniform_forest(s, level=2)
+        x, y, z = fmg.cell_centres(f, 1.0)
+        rhs = np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y) * np.cos(4 * np.pi * z) + x * z
+        u = fmg.solve(f, rhs, 13.0, 1.0, bc)
+        grid = np.zeros((16, 16, 16))
+        ug = np.zeros((16, 16, 16))
+        for k in range(f.n):
+            i, j, l = f.ijk[k]
+            grid[4 * l:4 * l + 4, 4 * j:4 * j + 4, 4 * i:4 * i + 4] = rhs[k]
+            ug[4 * l:4 * l + 4, 4 * j:4 * j + 4, 4 * i:4 * i + 4] = u[k]
+        ref = rd.helmholtz_solve(grid, 13.0, 1.0, bc)
+        assert np.max(np.abs(ug - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_3d_constants_linear_fields_and_conservation():
+    for bc in (fmg.PERIODIC, fmg.NEUMANN):
+        f = _forest3(bc)
+        assert len(f.level_counts()) == 2 and min(f.level_counts()) == 2
+        x, y, z = fmg.cell_centres(f, 1.0)
+        # constants: lap(1) = 0
+        assert np.max(np.abs(fmg.apply(f, np.ones_like(x), 0.0, 1.0, bc))) <= 1e-9
+        # conservation: the volume-weighted sum of lap(u) vanishes for any u
+        u = W.uniform01(9, x.size).reshape(x.shape)
+        lap = fmg.apply(f, u, 0.0, 1.0, bc)
+        vol = fmg.cell_areas(f, 1.0)
+        assert abs(np.sum(vol * lap)) <= 1e-12 * np.sum(np.abs(lap) * vol)
+    # linear data: lap vanishes off the Neumann domain boundary
+    f = _forest3(fmg.NEUMANN)
+    x, y, z = fmg.cell_centres(f, 1.0)
+    lap = fmg.apply(f, 0.7 * x - 1.3 * y + 0.4 * z + 0.2, 0.0, 1.0, fmg.NEUMANN)
+    n = (2 << (f.level.astype(np.int64) - 1)) * 4
+    h = (1.0 / n).reshape(-1, 1, 1, 1)
+    interior = np.ones(x.shape, dtype=bool)
+    for c in (x, y, z):
+        interior &= (c > h) & (c < 1 - h)
+    assert interior.sum() > 0.3 * x.size
+    assert np.max(np.abs(lap[interior])) <= 1e-9 * np.max(1.0 / h ** 2)
+    assert np.max(np.abs(lap[~interior])) > 0.1
+
+
+def test_3d_symmetry_and_second_order():
+    """Mirror (x -> 1 - x) and axis-permutation symmetry on a forest symmetric
+    under both, and the order of the maximum error on one block forest with 4
+    and 6 cells per block side."""
+    s = W.fmg_scheme(base=2, max_level=3, bc=fmg.NEUMANN, ndim=3)
+    f = W.fmg_forest(s, centre=(0.5, 0.5, 0.5), radius=0.2)
+    s.block_nx = (4, 4, 4)
+    x, y, z = fmg.cell_centres(f, 1.0)
+
+    def field(a, b, c):
+        return np.exp(-30 * ((a - 0.3) ** 2 + (b - 0.6) ** 2 + (c - 0.45) ** 2)) + 0.3 * a
+
+    lam = 11.0
+    u = fmg.solve(f, field(x, y, z), lam, 1.0, fmg.NEUMANN)
+    um = fmg.solve(f, field(1 - x, y, z), lam, 1.0, fmg.NEUMANN)
+    up = fmg.solve(f, field(y, z, x), lam, 1.0, fmg.NEUMANN)
+    key = {(int(l), int(i), int(j), int(k)): n for n, (l, (i, j, k)) in enumerate(zip(f.level, f.ijk))}
+    for n in range(f.n):
+        l, i, j, k = int(f.level[n]), *(int(v) for v in f.ijk[n])
+        nbl = 2 << (l - 1)
+        assert np.allclose(um[key[(l, nbl - 1 - i, j, k)]][:, :, ::-1], u[n], rtol=0, atol=1e-12)
+        # up solves f(y, z, x), so up(x, y, z) = u(y, z, x): up's block
+        # (i, j, k) is u's block (j, k, i) with its axes cycled
+        assert np.allclose(up[n], u[key[(l, j, k, i)]].transpose(1, 2, 0), rtol=0, atol=1e-12)
+    lam = 3.0
+    f0 = _forest3(fmg.NEUMANN)
+    errs = []
+    for nb in (4, 6):
+        s = W.fmg_scheme(base=2, max_level=3, bc=fmg.NEUMANN, ndim=3)
+        s.block_nx = (nb, nb, nb)
+        g = W.Forest(s, f0.level, f0.ijk)
+        x, y, z = fmg.cell_centres(g, 1.0)
+        ue = np.cos(2 * np.pi * x) * np.cos(2 * np.pi * y) * np.cos(4 * np.pi * z)
+        uu = fmg.solve(g, -(24 * np.pi ** 2 + lam) * ue, lam, 1.0, fmg.NEUMANN)
+        errs.append(np.max(np.abs(uu - ue)))
+    order = np.log(errs[0] / errs[1]) / np.log(6 / 4)
+    assert order >= 1.7, (errs, order)

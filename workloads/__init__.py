@@ -628,25 +628,27 @@ def gray_scott_initial(n: int = 256):
 
 # -- elliptic problems on a 2D block-adaptive forest (Sec. 1.4) -------------
 
-def fmg_scheme(base: int = 2, max_level: int = 3, bc: int = PERIODIC, length: float = 1.0) -> Scheme:
-    """A 2D forest of 16^2 blocks on [0, L]^2 with base x base blocks at level 1."""
-    return Scheme(ndim=2, block_nx=(16, 16, 16), base_blocks=(base, base), max_level=max_level,
-                  xmin=(0.0, 0.0), xmax=(length, length), bc=bc)
+def fmg_scheme(base: int = 2, max_level: int = 3, bc: int = PERIODIC, length: float = 1.0, ndim: int = 2) -> Scheme:
+    """A forest of 16^d blocks on [0, L]^d (d = 2, 3) with base^d blocks at level 1."""
+    return Scheme(ndim=ndim, block_nx=(16, 16, 16), base_blocks=(base,) * ndim, max_level=max_level,
+                  xmin=(0.0,) * ndim, xmax=(length,) * ndim, bc=bc)
 
 
-def fmg_forest(scheme: Scheme, centre=(0.5, 0.5), radius: float = 0.25, buffer_cells: float = 2.0) -> Forest:
-    """Quadtree forest refined around a circle (centre and radius relative to
-    the side L): a block at level l is refined while l < max_level if its box,
-    grown by ``buffer_cells`` cells of that level, touches the circle -- rings
-    of levels whose coarse-fine faces run in every direction and orientation."""
+def fmg_forest(scheme: Scheme, centre=(0.5, 0.5, 0.5), radius: float = 0.25, buffer_cells: float = 2.0) -> Forest:
+    """Quadtree / octree forest refined around a circle / sphere (centre and
+    radius relative to the side L): a block at level l is refined while l <
+    max_level if its box, grown by ``buffer_cells`` cells of that level,
+    touches the circle -- shells of levels whose coarse-fine faces run in
+    every direction and orientation."""
     s = scheme
+    nd = s.ndim
     side = s.xmax[0] - s.xmin[0]
-    c = (centre[0] * side, centre[1] * side)
+    c = tuple(centre[d] * side for d in range(nd))
 
     def refine(l, ij):
         nb = s.base_blocks[0] << (l - 1)
         h = side / nb
-        lo = np.array([s.xmin[0] + ij[0] * h, s.xmin[1] + ij[1] * h])
+        lo = np.array([s.xmin[d] + ij[d] * h for d in range(nd)])
         return _box_shell_hit(lo, lo + h, c, radius * side, float(buffer_cells * h / s.block_nx[0]))
 
     return refined_forest(s, refine)
