@@ -164,34 +164,36 @@ int amrv_mg_profile(amrv_mg* m, int32_t enable);
 int amrv_mg_profile_read(amrv_mg* m, double* ms_total, int64_t* cycles);
 
 /* ---------------------------------------------------------------------------
- * Helmholtz problem on a 2D block-adaptive forest (Sec. 1.4: the geometric
- * multigrid on the block-adaptive quadtree grid).
+ * Helmholtz problem on a 2D or 3D block-adaptive forest (Sec. 1.4: the
+ * geometric multigrid on the block-adaptive quadtree / octree grid).
  *
- * Grid: the leaves of a quadtree forest of 16 x 16-cell blocks on the square
- * [0, L]^2, base x base blocks at level 1 (base a power of two), leaf k at
- * level leaf_level[k] (1..max_level) with block coordinates leaf_ijk[3k],
- * leaf_ijk[3k + 1] at that level (leaf_ijk[3k + 2] = 0), the leaves covering
- * the square without overlap and 2:1 balanced across faces.  A field is one
- * binary64 value per leaf cell, [leaf][y][x] with x fastest (the forest's
- * state layout of one variable), in device memory.
+ * Grid: the leaves of a quadtree (ndim 2) or octree (ndim 3) forest of
+ * 16^ndim-cell blocks on [0, L]^ndim, base^ndim blocks at level 1 (base a
+ * power of two), leaf k at level leaf_level[k] (1..max_level) with block
+ * coordinates leaf_ijk[3k .. 3k + 2] at that level (the third 0 in 2D), the
+ * leaves covering the domain without overlap and 2:1 balanced across faces.
+ * A field is one binary64 value per leaf cell, [leaf][(z)][y][x] with x
+ * fastest (the forest's state layout of one variable), in device memory.
  *
- * Problem: lap(u) - lambda u = f, lambda > 0, lap of a cell the 5-point sum
- * at the cell's own level, (u_W + u_E + u_S + u_N - 4 u) / h_l^2, h_l =
- * L / (16 base 2^(l-1)).  The value across a face is the same-level leaf's
- * cell; at a domain face the periodic image or the zero-Neumann mirror (the
- * cell itself); on the fine side of a coarse-fine face (u + 2 u_c) / 3, u_c
- * the coarse cell across the face moved a quarter coarse cell along the face
- * with the coarse block's own tangential difference (central, one-sided at
- * its edges); on the coarse side u + (4/3) (m - u), m the mean of the two
- * fine cells touching the face (the mean of the two fine fluxes: the scheme
- * is conservative and second order).  The coarse-fine stencils are this
+ * Problem: lap(u) - lambda u = f, lap of a cell the (2 ndim + 1)-point sum at
+ * the cell's own level, (sum of the 2 ndim values across its faces - 2 ndim
+ * u) / h_l^2, h_l = L / (16 base 2^(l-1)).  The value across a face is the
+ * same-level leaf's cell; at a domain face the periodic image or the
+ * zero-Neumann mirror (the cell itself); on the fine side of a coarse-fine
+ * face (u + 2 u_c) / 3, u_c the coarse cell across the face moved a quarter
+ * coarse cell along the face in each tangential direction with the coarse
+ * block's own difference there (central, one-sided at its edges); on the
+ * coarse side u + (4/3) (m - u), m the mean of the 2^(ndim-1) fine cells
+ * touching the face (the mean of the fine fluxes: the scheme is
+ * conservative and second order).  The coarse-fine stencils are this
  * library's reading: the paper defers them to its multigrid library.
  *
  * Solver: V-cycles of the full approximation scheme over the block tree
- * (every ancestor of a leaf is a 16 x 16 block holding the mean of its
- * children), red-black Gauss-Seidel with pre_sweeps / post_sweeps sweeps per
- * level, bilinear interpolation of the coarse change within each parent, and
- * the uniform solver above on the complete level-1 grid.  Stops when the
+ * (every ancestor of a leaf is a block holding the mean of its children),
+ * red-black Gauss-Seidel with pre_sweeps / post_sweeps sweeps per level,
+ * bi/trilinear interpolation of the coarse change within each parent, and
+ * the uniform solver above on the complete level-1 grid (base * 16 <= 8192
+ * in 2D, <= 512 in 3D).  Stops when the
  * maximum residual of the problem over the leaf cells is at most tol times
  * max |f|, or after max_cycles cycles (AMRV_ENOTCONVERGED, phi holding the
  * last iterate).  Host-synchronous: every cycle reads its residual back. */
@@ -205,7 +207,7 @@ typedef struct {
   int32_t bc;          /* AMRV_MG_PERIODIC or AMRV_MG_NEUMANN */
   int32_t pre_sweeps;  /* red-black sweeps per level on the way down (1..8) */
   int32_t post_sweeps; /* and on the way up (1..8) */
-  int32_t pad;
+  int32_t ndim;        /* 2 (quadtree, also for 0) or 3 (octree) */
   double length;       /* L > 0 */
 } amrv_fmg_config;
 
@@ -253,7 +255,7 @@ int amrv_fmg_solve(amrv_fmg* m, const double* f, double* phi, double lambda, dou
 int amrv_fmg_rd_step(amrv_fmg* m, const amrv_rd_params* p, int32_t scheme, double dt, int32_t nsteps, double* u,
                      double* v, double tol, int32_t max_cycles, int32_t* cycles_total, double* res_max);
 
-/* The divergence control of Sec. 2.4 on the forest's leaf fields bx, by
+/* The divergence control of Sec. 2.4 on a 2D forest's leaf fields bx, by
  * (device, nleaves * 256 doubles each, updated in place): phi is the
  * zero-mean solution of lap(phi) = div B* (amrv_fmg_solve with lambda = 0,
  * tol and max_cycles as there), then B = B* - grad phi; div and grad are
@@ -262,7 +264,8 @@ int amrv_fmg_rd_step(amrv_fmg* m, const amrv_rd_params* p, int32_t scheme, doubl
  * then y.  An approximate projection: it removes the divergence up to what
  * the compact lap and div(grad) disagree on (O(h^2) away from coarse-fine
  * faces, O(1) next to them).  div_before, div_after (host, may be NULL)
- * receive max |div B| before and after; cycles the V-cycle count. */
+ * receive max |div B| before and after; cycles the V-cycle count.
+ * AMRV_ENOTSUP on a 3D forest. */
 int amrv_fmg_divb_project(amrv_fmg* m, double* bx, double* by, double tol, int32_t max_cycles, int32_t* cycles,
                           double* div_before, double* div_after);
 

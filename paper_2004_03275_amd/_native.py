@@ -84,7 +84,7 @@ class FmgConfig(ctypes.Structure):
 
     _fields_ = [("nleaves", ctypes.c_int64), ("base", ctypes.c_int32), ("max_level", ctypes.c_int32),
                 ("bc", ctypes.c_int32), ("pre_sweeps", ctypes.c_int32), ("post_sweeps", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("length", ctypes.c_double)]
+                ("ndim", ctypes.c_int32), ("length", ctypes.c_double)]
 
 
 class RdParams(ctypes.Structure):

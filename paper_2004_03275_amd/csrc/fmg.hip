@@ -1,23 +1,24 @@
-// fmg.hip -- Helmholtz solver on a 2D block-adaptive quadtree forest
+// fmg.hip -- Helmholtz solver on a 2D or 3D block-adaptive forest
 // (declared in include/amrv_mg.h; the multigrid of Sec. 1.4 on the block-
-// adaptive grid), by full-approximation-scheme V-cycles over the block tree.
+// adaptive quadtree / octree grid), by full-approximation-scheme V-cycles
+// over the block tree.
 //
-// The problem on the leaf cells: lap(u) - lambda u = f, the 5-point lap of a
-// cell at its own level, the value across a face from
+// The problem on the leaf cells: lap(u) - lambda u = f, the (2d+1)-point lap
+// of a cell at its own level, the value across a face from
 //   a leaf cell at the same level;
 //   the zero-Neumann mirror at a non-periodic domain face (periodic faces
 //     wrap through the neighbour table);
 //   the fine side of a coarse-fine face: (u + 2 u_c) / 3, u_c the coarse
-//     leaf's cell across the face moved a quarter coarse cell along it with
-//     the coarse block's own tangential difference (central, one-sided at
-//     its edges);
-//   the coarse side: u + (4/3) (m - u), m the mean of the two fine cells
-//     touching the face -- the mean of the two fine fluxes, so the scheme is
+//     leaf's cell across the face moved a quarter coarse cell along it in
+//     each tangential direction with the coarse block's own difference there
+//     (central, one-sided at its edges);
+//   the coarse side: u + (4/3) (m - u), m the mean of the 2^(d-1) fine cells
+//     touching the face -- the mean of the fine fluxes, so the scheme is
 //     conservative.
 //
-// The tree: every leaf and every ancestor of a leaf is a block of 16 x 16
+// The tree: every leaf and every ancestor of a leaf is a block of 16^d
 // cells, the blocks of a level stored one after another (level 1 first).  A
-// parent holds the mean of its children's 2 x 2 cells.  The grid of level l
+// parent holds the mean of its children's 2^d cells.  The grid of level l
 // is every block of that level, relaxed with the plain stencil (a refined
 // neighbour's own cells in place of the coarse side of a coarse-fine face;
 // on the finest level this is the problem's stencil) and the right-hand
@@ -28,29 +29,33 @@
 //
 // A V-cycle: from the finest level down to level 2, `pre` red-black sweeps,
 // the residual, its restriction with the state's into the parents, and the
-// parents' coarse right-hand side; on level 1 (complete: base x base blocks)
+// parents' coarse right-hand side; on level 1 (complete: base^d blocks)
 // `pre` sweeps, then one V-cycle of the uniform-grid solver of multigrid.hip
 // on the level-1 grid for the correction L(e) = r (from e = 0), then `post`
-// sweeps; back up, every block adds the bilinear interpolation (within its
-// parent) of the parent's change since restriction, then `post` sweeps.
+// sweeps; back up, every block adds the bi/trilinear interpolation (within
+// its parent) of the parent's change since restriction, then `post` sweeps.
 // A cycle has no host wait: a solve enqueues as many cycles as the previous
 // solve needed, less one, before it first reads back the problem's residual
 // over the leaves, then checks after every cycle (the stopping rule max |r|
-// <= tol max |f|).
+// <= tol max |f|).  Kernels are templated on the dimension; a 256-thread
+// workgroup walks a block plane by plane.
 //
 // Layout in the caller's workspace (256-byte aligned arrays):
-//   tables   lvl, ij[2], nbr[4], chi[4], cnb[4], par per block; leaf -> block
-//   u, f, fu, r, uo  [block][256] doubles (state, relaxation right-hand
+//   tables   lvl, ij[3], nbr[6], chi[8], cnb[6], par per block (2D uses the
+//            first entries); leaf -> block
+//   u, f, fu, r, uo  [block][16^d] doubles (state, relaxation right-hand
 //                 side, the problem's f, residual or restricted residual,
 //                 restricted state)
-//   fgrid, vgrid  the level-1 grid (n = 16 base cells per side) for the
-//                 uniform solver, and that solver's own workspace
-//   red           two 64-bit maxima
+//   fgrid, vgrid  the level-1 grid ((16 base)^d cells) for the uniform
+//                 solver, and that solver's own workspace
+//   red, tmp, part  two 64-bit maxima, eight leaf fields (reaction-diffusion
+//                 and projection temporaries), per-leaf sums
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <array>
 #include <map>
 #include <string>
 #include <tuple>
@@ -65,18 +70,28 @@ namespace {
 using amrv::set_error;
 
 constexpr int NB = 16;
-constexpr int NC = NB * NB;
+constexpr int WG = 256;  // threads per workgroup: one 16 x 16 plane of a block at a time
 constexpr int FMG_MAXL = 16;
 constexpr int NBR_NONE = -1;  // no block of the same level across the face (a coarser leaf is)
 constexpr int NBR_WALL = -2;  // a non-periodic domain face
+constexpr int TS = 3, FS = 6, CS = 8;  // table strides per block: coordinates, faces, children (2D uses the first)
 constexpr size_t ALIGN = 256;
+
+template <int ND>
+constexpr int ncb() {  // cells per block
+  return ND == 3 ? NB * NB * NB : NB * NB;
+}
+template <int ND>
+constexpr int nplanes() {
+  return ND == 3 ? NB : 1;
+}
 
 struct FmgDev {
   const int* lvl;
-  const int* ij;   // [block][2]
-  const int* nbr;  // [block][4]: -x, +x, -y, +y; a block index, NBR_NONE or NBR_WALL
-  const int* chi;  // [block][4]: children (x fastest), -1 for a leaf
-  const int* cnb;  // [block][4]: the coarser leaf across a face whose nbr is NBR_NONE
+  const int* ij;   // [block][TS]: block coordinates at its level
+  const int* nbr;  // [block][FS]: -x, +x, -y, +y, -z, +z; a block index, NBR_NONE or NBR_WALL
+  const int* chi;  // [block][CS]: children (x fastest), -1 for a leaf
+  const int* cnb;  // [block][FS]: the coarser leaf across a face whose nbr is NBR_NONE
   const int* par;  // [block]: parent, -1 on level 1
   double* u;
   double* f;   // right-hand side of the relaxation: the problem's f on the finest level, else L(u) + r
@@ -88,146 +103,175 @@ struct FmgDev {
   double rh[FMG_MAXL + 1];   // 1/h per level
 };
 
-// the value across face `face` of cell (x, y) of block b, as c + w u(x, y)
-// (host-callable too, for checks of the tables on the CPU)
-__host__ __device__ inline void across(const FmgDev& g, int b, bool leaf, int x, int y, int face, double& c,
+// a cell's index in its block, (x, y, z) with x fastest (z = 0 in 2D)
+__host__ __device__ inline int cidx(const int* c) { return c[0] + NB * (c[1] + NB * c[2]); }
+
+// the value across face `face` (2d: -d, 2d + 1: +d) of cell c of block b, as
+// cv + w u(c) (host-callable too, for checks of the tables on the CPU)
+template <int ND>
+__host__ __device__ inline void across(const FmgDev& g, int b, bool leaf, const int* c, int face, double& cv,
                                        double& w) {
-  const int nb = g.nbr[4 * b + face];
+  constexpr int NCB = ncb<ND>();
+  const int nb = g.nbr[FS * b + face];
   if (nb == NBR_WALL) {
-    c = 0.0;
+    cv = 0.0;
     w = 1.0;
     return;
   }
-  int X = x, Y = y;  // the neighbouring cell in the neighbouring block
-  if (face == 0) X = NB - 1;
-  if (face == 1) X = 0;
-  if (face == 2) Y = NB - 1;
-  if (face == 3) Y = 0;
+  const int d = face >> 1;
+  const bool lo = (face & 1) == 0;
+  int C[3] = {c[0], c[1], c[2]};  // the neighbouring cell in the neighbouring block
+  C[d] = lo ? NB - 1 : 0;
   if (nb >= 0) {
-    const int* ch = g.chi + 4 * nb;
+    const int* ch = g.chi + CS * nb;
     if (!leaf || ch[0] < 0) {
-      c = g.u[(size_t)nb * NC + X + NB * Y];
+      cv = g.u[(size_t)nb * NCB + cidx(C)];
       w = 0.0;
       return;
     }
-    // the coarse side: the two fine cells of the neighbour's children that
-    // touch the face, in its 32 x 32 grid of child cells
+    // the coarse side: the 2^(ND-1) fine cells of the neighbour's children
+    // that touch the face, in its grid of 32^ND child cells
     double s = 0.0;
 #pragma unroll
-    for (int t = 0; t < 2; t++) {
-      const int fx = face < 2 ? 2 * X + (face == 0 ? 1 : 0) : 2 * X + t;
-      const int fy = face < 2 ? 2 * Y + t : 2 * Y + (face == 2 ? 1 : 0);
-      const int fb = ch[(fx >> 4) + 2 * (fy >> 4)];
-      s += g.u[(size_t)fb * NC + (fx & (NB - 1)) + NB * (fy & (NB - 1))];
+    for (int t = 0; t < (1 << (ND - 1)); t++) {
+      int F[3] = {0, 0, 0};
+      int bit = 0;
+#pragma unroll
+      for (int e = 0; e < ND; e++) {
+        if (e == d) {
+          F[e] = 2 * C[e] + (lo ? 1 : 0);
+        } else {
+          F[e] = 2 * C[e] + ((t >> bit) & 1);
+          bit++;
+        }
+      }
+      const int fb = ch[(F[0] >> 4) + 2 * (F[1] >> 4) + 4 * (F[2] >> 4)];
+      const int Fl[3] = {F[0] & (NB - 1), F[1] & (NB - 1), F[2] & (NB - 1)};
+      s += g.u[(size_t)fb * NCB + cidx(Fl)];
     }
-    c = (2.0 / 3.0) * s;
+    cv = ((4.0 / 3.0) / (1 << (ND - 1))) * s;
     w = -1.0 / 3.0;
     return;
   }
-  // the fine side: the coarser leaf across the face
-  const int C = g.cnb[4 * b + face];
-  const int gx = g.ij[2 * b] * NB + x, gy = g.ij[2 * b + 1] * NB + y;
-  const double* uc = g.u + (size_t)C * NC;
-  int cx, cy, t, st;
-  double o;
-  if (face < 2) {
-    cx = face == 0 ? NB - 1 : 0;
-    cy = (gy >> 1) - g.ij[2 * C + 1] * NB;
-    t = cy;
-    st = NB;
-    o = (gy & 1) ? 0.25 : -0.25;
-  } else {
-    cy = face == 2 ? NB - 1 : 0;
-    cx = (gx >> 1) - g.ij[2 * C] * NB;
-    t = cx;
-    st = 1;
-    o = (gx & 1) ? 0.25 : -0.25;
+  // the fine side: the coarser leaf across the face, its cell moved a quarter
+  // cell toward this one along each tangential direction
+  const int Cb = g.cnb[FS * b + face];
+  int gc[3] = {0, 0, 0}, K[3] = {0, 0, 0};
+#pragma unroll
+  for (int e = 0; e < ND; e++) {
+    gc[e] = g.ij[TS * b + e] * NB + c[e];
+    K[e] = (gc[e] >> 1) - g.ij[TS * Cb + e] * NB;
   }
-  const double* p = uc + cx + NB * cy;  // the coarse cell; st steps along the face
-  double slope;
-  if (t == 0)
-    slope = p[st] - p[0];
-  else if (t == NB - 1)
-    slope = p[0] - p[-st];
-  else
-    slope = 0.5 * p[st] - 0.5 * p[-st];
-  c = (2.0 / 3.0) * (p[0] + o * slope);
+  K[d] = lo ? NB - 1 : 0;
+  const double* p = g.u + (size_t)Cb * NCB + cidx(K);
+  double val = p[0];
+#pragma unroll
+  for (int e = 0; e < ND; e++) {
+    if (e == d) continue;
+    const int st = e == 0 ? 1 : (e == 1 ? NB : NB * NB);
+    const int t = K[e];
+    double slope;
+    if (t == 0)
+      slope = p[st] - p[0];
+    else if (t == NB - 1)
+      slope = p[0] - p[-st];
+    else
+      slope = 0.5 * p[st] - 0.5 * p[-st];
+    val += ((gc[e] & 1) ? 0.25 : -0.25) * slope;
+  }
+  cv = (2.0 / 3.0) * val;
   w = 1.0 / 3.0;
 }
 
-// the neighbour sums of cell (x, y) of block b: sum of the four values as
-// sc + sw u(x, y)
-__host__ __device__ inline void stencil(const FmgDev& g, int b, bool leaf, int x, int y, double& sc, double& sw) {
-  const double* ub = g.u + (size_t)b * NC;
+// the neighbour sums of cell c of block b: sum of the 2 ND values as sc + sw u(c)
+template <int ND>
+__host__ __device__ inline void stencil(const FmgDev& g, int b, bool leaf, const int* c, double& sc, double& sw) {
+  const double* ub = g.u + (size_t)b * ncb<ND>();
   sc = 0.0;
   sw = 0.0;
 #pragma unroll
-  for (int face = 0; face < 4; face++) {
-    const int xn = x + (face == 0 ? -1 : (face == 1 ? 1 : 0));
-    const int yn = y + (face == 2 ? -1 : (face == 3 ? 1 : 0));
-    if (xn >= 0 && xn < NB && yn >= 0 && yn < NB) {
-      sc += ub[xn + NB * yn];
+  for (int face = 0; face < 2 * ND; face++) {
+    int cn[3] = {c[0], c[1], c[2]};
+    cn[face >> 1] += (face & 1) ? 1 : -1;
+    if (cn[face >> 1] >= 0 && cn[face >> 1] < NB) {
+      sc += ub[cidx(cn)];
     } else {
-      double c, w;
-      across(g, b, leaf, x, y, face, c, w);
-      sc += c;
+      double cv, w;
+      across<ND>(g, b, leaf, c, face, cv, w);
+      sc += cv;
       sw += w;
     }
   }
 }
 
 // Every kernel below applies one per-cell function (host-callable too, so a
-// host loop over the same functions checks a cycle on the CPU); cell t of a
-// block is (x, y) = (t & 15, t >> 4).
+// host loop over the same functions checks a cycle on the CPU); a 256-thread
+// workgroup walks a block plane by plane, thread t at (t & 15, t >> 4).
 
-// lap(u) - lambda u at cell (x, y) of block b: the problem's rules (leaf),
-// or the plain stencil, the refined neighbours' own (restricted) cells in
-// place of the coarse side of a coarse-fine face
-__host__ __device__ inline double apply_cell(const FmgDev& g, int b, bool leaf, int x, int y) {
+// lap(u) - lambda u at cell c of block b: the problem's rules (leaf), or the
+// plain stencil, the refined neighbours' own (restricted) cells in place of
+// the coarse side of a coarse-fine face
+template <int ND>
+__host__ __device__ inline double apply_cell(const FmgDev& g, int b, bool leaf, const int* c) {
   double sc, sw;
-  stencil(g, b, leaf, x, y, sc, sw);
-  const double u = g.u[(size_t)b * NC + x + NB * y];
-  return g.ih2[g.lvl[b]] * (sc + sw * u - 4.0 * u) - g.lam * u;
+  stencil<ND>(g, b, leaf, c, sc, sw);
+  const double u = g.u[(size_t)b * ncb<ND>() + cidx(c)];
+  return g.ih2[g.lvl[b]] * (sc + sw * u - (2.0 * ND) * u) - g.lam * u;
 }
 
-// red-black relaxation of cell (x, y) of block b with the plain stencil
-// (the problem's rules on the finest level, which has no refined
-// neighbour): a cell of colour (x + y) & 1 reads cells of the other colour
-// only (the block edge is even, so the colour is global) and coarser
-// levels, none of which a sweep of one level writes
-__host__ __device__ inline void smooth_cell(const FmgDev& g, int b, int x, int y) {
+// red-black relaxation of cell c of block b with the plain stencil (the
+// problem's rules on the finest level, which has no refined neighbour): a
+// cell of colour (x + y + z) & 1 reads cells of the other colour only (the
+// block edge is even, so the colour is global) and coarser levels, none of
+// which a sweep of one level writes
+template <int ND>
+__host__ __device__ inline void smooth_cell(const FmgDev& g, int b, const int* c) {
   const double ih2 = g.ih2[g.lvl[b]];
   double sc, sw;
-  stencil(g, b, false, x, y, sc, sw);
-  const size_t i = (size_t)b * NC + x + NB * y;
-  g.u[i] = (g.f[i] - ih2 * sc) / (ih2 * (sw - 4.0) - g.lam);
+  stencil<ND>(g, b, false, c, sc, sw);
+  const size_t i = (size_t)b * ncb<ND>() + cidx(c);
+  g.u[i] = (g.f[i] - ih2 * sc) / (ih2 * (sw - 2.0 * ND) - g.lam);
 }
 
 // the residual of the relaxation (plain stencil)
-__host__ __device__ inline void resid_cell(const FmgDev& g, int b, int x, int y) {
-  const size_t i = (size_t)b * NC + x + NB * y;
-  g.r[i] = g.f[i] - apply_cell(g, b, false, x, y);
+template <int ND>
+__host__ __device__ inline void resid_cell(const FmgDev& g, int b, const int* c) {
+  const size_t i = (size_t)b * ncb<ND>() + cidx(c);
+  g.r[i] = g.f[i] - apply_cell<ND>(g, b, false, c);
 }
 
 // the problem's residual at a leaf cell
-__host__ __device__ inline double residual(const FmgDev& g, int b, int x, int y) {
-  return g.fu[(size_t)b * NC + x + NB * y] - apply_cell(g, b, true, x, y);
+template <int ND>
+__host__ __device__ inline double residual(const FmgDev& g, int b, const int* c) {
+  return g.fu[(size_t)b * ncb<ND>() + cidx(c)] - apply_cell<ND>(g, b, true, c);
 }
 
-// child b into its parent: parent cell t (0..63) of the child's quadrant gets
-// the mean of u and of r over its 2 x 2 cells (r into the parent's r, u into
-// its u and uo)
+// child b into its parent: parent cell t (0 .. 8^ND - 1) of the child's
+// quadrant / octant gets the mean of u and of r over its 2^ND cells (r into
+// the parent's r, u into its u and uo)
+template <int ND>
 __host__ __device__ inline void restrict_cell(const FmgDev& g, int b, int t) {
+  constexpr int NCB = ncb<ND>();
   const int p = g.par[b];
-  const int qx = g.ij[2 * b] & 1, qy = g.ij[2 * b + 1] & 1;
-  const int xx = t & 7, yy = t >> 3;
-  const size_t c0 = (size_t)b * NC + 2 * xx + NB * 2 * yy;
-  const size_t pc = (size_t)p * NC + qx * 8 + xx + NB * (qy * 8 + yy);
-  const double um = 0.25 * ((g.u[c0] + g.u[c0 + 1]) + (g.u[c0 + NB] + g.u[c0 + NB + 1]));
-  const double rm = 0.25 * ((g.r[c0] + g.r[c0 + 1]) + (g.r[c0 + NB] + g.r[c0 + NB + 1]));
-  g.u[pc] = um;
-  g.uo[pc] = um;
-  g.r[pc] = rm;
+  const int q[3] = {g.ij[TS * b] & 1, g.ij[TS * b + 1] & 1, ND == 3 ? (g.ij[TS * b + 2] & 1) : 0};
+  const int xx = t & 7, yy = (t >> 3) & 7, zz = ND == 3 ? t >> 6 : 0;
+  const int c0[3] = {2 * xx, 2 * yy, 2 * zz};
+  const int pc[3] = {q[0] * 8 + xx, q[1] * 8 + yy, q[2] * 8 + zz};
+  const size_t i0 = (size_t)b * NCB + cidx(c0), ip = (size_t)p * NCB + cidx(pc);
+  double um, rm;
+  if constexpr (ND == 2) {
+    um = 0.25 * ((g.u[i0] + g.u[i0 + 1]) + (g.u[i0 + NB] + g.u[i0 + NB + 1]));
+    rm = 0.25 * ((g.r[i0] + g.r[i0 + 1]) + (g.r[i0 + NB] + g.r[i0 + NB + 1]));
+  } else {
+    constexpr int P = NB * NB;
+    um = 0.125 * (((g.u[i0] + g.u[i0 + 1]) + (g.u[i0 + NB] + g.u[i0 + NB + 1])) +
+                  ((g.u[i0 + P] + g.u[i0 + P + 1]) + (g.u[i0 + P + NB] + g.u[i0 + P + NB + 1])));
+    rm = 0.125 * (((g.r[i0] + g.r[i0 + 1]) + (g.r[i0 + NB] + g.r[i0 + NB + 1])) +
+                  ((g.r[i0 + P] + g.r[i0 + P + 1]) + (g.r[i0 + P + NB] + g.r[i0 + P + NB + 1])));
+  }
+  g.u[ip] = um;
+  g.uo[ip] = um;
+  g.r[ip] = rm;
 }
 
 // the right-hand side of a level below the finest: L(u) + r with L the plain
@@ -235,112 +279,179 @@ __host__ __device__ inline void restrict_cell(const FmgDev& g, int b, int t) {
 // leaf; where the plain stencil is the problem's, exactly f).  A leaf next to
 // a refined block thereby relaxes with the same stencil as that block's
 // cells, and is left unchanged once the problem's residual vanishes.
-__host__ __device__ inline void fas_cell(const FmgDev& g, int b, int x, int y) {
-  const size_t i = (size_t)b * NC + x + NB * y;
-  const double lp = apply_cell(g, b, false, x, y);
-  if (g.chi[4 * b] >= 0) {
+template <int ND>
+__host__ __device__ inline void fas_cell(const FmgDev& g, int b, const int* c) {
+  const size_t i = (size_t)b * ncb<ND>() + cidx(c);
+  const double lp = apply_cell<ND>(g, b, false, c);
+  if (g.chi[CS * b] >= 0) {
     g.f[i] = lp + g.r[i];
     return;
   }
-  const double lc = apply_cell(g, b, true, x, y);
+  const double lc = apply_cell<ND>(g, b, true, c);
   g.f[i] = lp == lc ? g.fu[i] : lp + (g.fu[i] - lc);
 }
 
-// a block of level >= 2 adds the bilinear interpolation of its parent's
-// change e = u - uo: weights 9, 3, 3, 1 (/16) from the parent cell and its
-// neighbours toward the fine cell, the parent's own cell where that
-// neighbour lies outside the parent
-__host__ __device__ inline void prolong_cell(const FmgDev& g, int b, int x, int y) {
+// a block of level >= 2 adds the bi/trilinear interpolation of its parent's
+// change e = u - uo: weights 9, 3, 3, 1 (/16) in 2D, 27, 9, 3, 1 (/64) in 3D,
+// from the parent cell and its neighbours toward the fine cell, the parent's
+// own cell where that neighbour lies outside the parent
+template <int ND>
+__host__ __device__ inline void prolong_cell(const FmgDev& g, int b, const int* c) {
+  constexpr int NCB = ncb<ND>();
   const int p = g.par[b];
-  const int I = (g.ij[2 * b] & 1) * 8 + (x >> 1), J = (g.ij[2 * b + 1] & 1) * 8 + (y >> 1);
-  const int I2n = I + ((x & 1) ? 1 : -1), J2n = J + ((y & 1) ? 1 : -1);
-  const int I2 = I2n < 0 ? 0 : (I2n > NB - 1 ? NB - 1 : I2n);
-  const int J2 = J2n < 0 ? 0 : (J2n > NB - 1 ? NB - 1 : J2n);
-  const double* up = g.u + (size_t)p * NC;
-  const double* uq = g.uo + (size_t)p * NC;
-  const double e00 = up[I + NB * J] - uq[I + NB * J], e10 = up[I2 + NB * J] - uq[I2 + NB * J];
-  const double e01 = up[I + NB * J2] - uq[I + NB * J2], e11 = up[I2 + NB * J2] - uq[I2 + NB * J2];
-  g.u[(size_t)b * NC + x + NB * y] += (9.0 * e00 + 3.0 * e10 + 3.0 * e01 + e11) * (1.0 / 16.0);
+  int I[3] = {0, 0, 0}, I2[3] = {0, 0, 0};
+#pragma unroll
+  for (int e = 0; e < ND; e++) {
+    I[e] = (g.ij[TS * b + e] & 1) * 8 + (c[e] >> 1);
+    const int n2 = I[e] + ((c[e] & 1) ? 1 : -1);
+    I2[e] = n2 < 0 ? 0 : (n2 > NB - 1 ? NB - 1 : n2);
+  }
+  const double* up = g.u + (size_t)p * NCB;
+  const double* uq = g.uo + (size_t)p * NCB;
+  auto e = [&](int a, int bb, int cc) {
+    const int k[3] = {a ? I2[0] : I[0], bb ? I2[1] : I[1], cc ? I2[2] : I[2]};
+    const int i = cidx(k);
+    return up[i] - uq[i];
+  };
+  double d;
+  if constexpr (ND == 2) {
+    d = (9.0 * e(0, 0, 0) + 3.0 * e(1, 0, 0) + 3.0 * e(0, 1, 0) + e(1, 1, 0)) * (1.0 / 16.0);
+  } else {
+    d = (27.0 * e(0, 0, 0) + 9.0 * (e(1, 0, 0) + e(0, 1, 0) + e(0, 0, 1)) +
+         3.0 * (e(1, 1, 0) + e(1, 0, 1) + e(0, 1, 1)) + e(1, 1, 1)) *
+        (1.0 / 64.0);
+  }
+  g.u[(size_t)b * NCB + cidx(c)] += d;
 }
 
-// a level-1 cell to the n x n grid: the correction problem L(e) = r, from e = 0
-__host__ __device__ inline void to_grid_cell(const FmgDev& g, int b, int x, int y, int n, double* fgrid,
+// index of cell c of level-1 block b in the n^ND grid
+template <int ND>
+__host__ __device__ inline size_t grid_index(const FmgDev& g, int b, const int* c, int n) {
+  size_t i = 0;
+#pragma unroll
+  for (int e = ND - 1; e >= 0; e--) i = i * n + (size_t)(g.ij[TS * b + e] * NB + c[e]);
+  return i;
+}
+
+// a level-1 cell to the n^ND grid: the correction problem L(e) = r, from e = 0
+template <int ND>
+__host__ __device__ inline void to_grid_cell(const FmgDev& g, int b, const int* c, int n, double* fgrid,
                                              double* vgrid) {
-  const size_t i = (size_t)b * NC + x + NB * y;
-  const size_t gi = (size_t)(g.ij[2 * b + 1] * NB + y) * n + g.ij[2 * b] * NB + x;
+  const size_t i = (size_t)b * ncb<ND>() + cidx(c);
+  const size_t gi = grid_index<ND>(g, b, c, n);
   fgrid[gi] = g.r[i];
   vgrid[gi] = 0.0;
 }
 
-__global__ void __launch_bounds__(NC) k_fmg_smooth(FmgDev g, int b0, int colour) {
-  const int x = threadIdx.x & (NB - 1), y = threadIdx.x >> 4;
-  if (((x + y) & 1) == colour) smooth_cell(g, b0 + blockIdx.x, x, y);
+#define FMG_PLANES(ND)                                        \
+  const int tx = threadIdx.x & (NB - 1), ty = threadIdx.x >> 4; \
+  for (int tz = 0; tz < nplanes<ND>(); tz++)
+
+template <int ND>
+__global__ void __launch_bounds__(WG) k_fmg_smooth(FmgDev g, int b0, int colour) {
+  FMG_PLANES(ND) {
+    const int c[3] = {tx, ty, tz};
+    if (((tx + ty + tz) & 1) == colour) smooth_cell<ND>(g, b0 + blockIdx.x, c);
+  }
 }
 
-__global__ void __launch_bounds__(NC) k_fmg_resid(FmgDev g, int b0) {
-  resid_cell(g, b0 + blockIdx.x, threadIdx.x & (NB - 1), threadIdx.x >> 4);
+template <int ND>
+__global__ void __launch_bounds__(WG) k_fmg_resid(FmgDev g, int b0) {
+  FMG_PLANES(ND) {
+    const int c[3] = {tx, ty, tz};
+    resid_cell<ND>(g, b0 + blockIdx.x, c);
+  }
 }
 
-__global__ void __launch_bounds__(64) k_fmg_restrict(FmgDev g, int b0) { restrict_cell(g, b0 + blockIdx.x, threadIdx.x); }
-
-__global__ void __launch_bounds__(NC) k_fmg_fas(FmgDev g, int b0) {
-  fas_cell(g, b0 + blockIdx.x, threadIdx.x & (NB - 1), threadIdx.x >> 4);
+template <int ND>
+__global__ void __launch_bounds__(WG) k_fmg_restrict(FmgDev g, int b0) {
+  for (int t = threadIdx.x; t < (ND == 3 ? 512 : 64); t += blockDim.x) restrict_cell<ND>(g, b0 + blockIdx.x, t);
 }
 
-__global__ void __launch_bounds__(NC) k_fmg_prolong(FmgDev g, int b0) {
-  prolong_cell(g, b0 + blockIdx.x, threadIdx.x & (NB - 1), threadIdx.x >> 4);
+template <int ND>
+__global__ void __launch_bounds__(WG) k_fmg_fas(FmgDev g, int b0) {
+  FMG_PLANES(ND) {
+    const int c[3] = {tx, ty, tz};
+    fas_cell<ND>(g, b0 + blockIdx.x, c);
+  }
 }
 
-__global__ void __launch_bounds__(NC) k_fmg_to_grid(FmgDev g, int b0, int n, double* fgrid, double* vgrid) {
-  to_grid_cell(g, b0 + blockIdx.x, threadIdx.x & (NB - 1), threadIdx.x >> 4, n, fgrid, vgrid);
+template <int ND>
+__global__ void __launch_bounds__(WG) k_fmg_prolong(FmgDev g, int b0) {
+  FMG_PLANES(ND) {
+    const int c[3] = {tx, ty, tz};
+    prolong_cell<ND>(g, b0 + blockIdx.x, c);
+  }
 }
 
-__global__ void __launch_bounds__(NC) k_fmg_from_grid(FmgDev g, int b0, int n, const double* vgrid) {
+template <int ND>
+__global__ void __launch_bounds__(WG) k_fmg_to_grid(FmgDev g, int b0, int n, double* fgrid, double* vgrid) {
+  FMG_PLANES(ND) {
+    const int c[3] = {tx, ty, tz};
+    to_grid_cell<ND>(g, b0 + blockIdx.x, c, n, fgrid, vgrid);
+  }
+}
+
+template <int ND>
+__global__ void __launch_bounds__(WG) k_fmg_from_grid(FmgDev g, int b0, int n, const double* vgrid) {
   const int b = b0 + blockIdx.x;
-  const int x = threadIdx.x & (NB - 1), y = threadIdx.x >> 4;
-  g.u[(size_t)b * NC + threadIdx.x] += vgrid[(size_t)(g.ij[2 * b + 1] * NB + y) * n + g.ij[2 * b] * NB + x];
+  FMG_PLANES(ND) {
+    const int c[3] = {tx, ty, tz};
+    g.u[(size_t)b * ncb<ND>() + cidx(c)] += vgrid[grid_index<ND>(g, b, c, n)];
+  }
 }
 
 // block maximum of v >= 0 into *out (the bits of non-negative doubles order
 // as the values)
 __device__ __forceinline__ void fold_max(double v, unsigned long long* out) {
-  __shared__ double sm[NC / 64];
+  __shared__ double sm[WG / 64];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = sm[0];
-    for (int i = 1; i < NC / 64; i++) m = fmax(m, sm[i]);
+    for (int i = 1; i < WG / 64; i++) m = fmax(m, sm[i]);
     atomicMax(out, (unsigned long long)__double_as_longlong(m));
   }
 }
 
 // max |r| of the problem over the leaves into out[0] and, with fmax, max |f|
 // (the problem's f as solved) into out[1] (every block launched; parents skip)
-__global__ void __launch_bounds__(NC) k_fmg_resmax(FmgDev g, unsigned long long* out, int fmax) {
+template <int ND>
+__global__ void __launch_bounds__(WG) k_fmg_resmax(FmgDev g, unsigned long long* out, int with_f) {
   const int b = blockIdx.x;
-  if (g.chi[4 * b] >= 0) return;  // uniform per workgroup
-  const double r = residual(g, b, threadIdx.x & (NB - 1), threadIdx.x >> 4);
-  fold_max(isnan(r) ? INFINITY : fabs(r), out);
-  if (fmax) {
+  if (g.chi[CS * b] >= 0) return;  // uniform per workgroup
+  double mr = 0.0, mf = 0.0;
+  FMG_PLANES(ND) {
+    const int c[3] = {tx, ty, tz};
+    const double r = residual<ND>(g, b, c);
+    const double f = g.fu[(size_t)b * ncb<ND>() + cidx(c)];
+    mr = fmax(mr, isnan(r) ? INFINITY : fabs(r));
+    mf = fmax(mf, isnan(f) ? INFINITY : fabs(f));
+  }
+  fold_max(mr, out);
+  if (with_f) {
     __syncthreads();
-    const double f = g.fu[(size_t)b * NC + threadIdx.x];
-    fold_max(isnan(f) ? INFINITY : fabs(f), out + 1);
+    fold_max(mf, out + 1);
   }
 }
 
 // leaf fields <-> block arrays; dir 0: f and phi in, 1: phi out
-__global__ void __launch_bounds__(NC) k_fmg_leaves(FmgDev g, const int* leafblk, const double* f, double* phi,
+template <int ND>
+__global__ void __launch_bounds__(WG) k_fmg_leaves(FmgDev g, const int* leafblk, const double* f, double* phi,
                                                   int dir) {
+  constexpr int NCB = ncb<ND>();
   const int k = blockIdx.x;
-  const size_t i = (size_t)leafblk[k] * NC + threadIdx.x, o = (size_t)k * NC + threadIdx.x;
-  if (dir == 0) {
-    g.f[i] = f[o];
-    g.fu[i] = f[o];
-    g.u[i] = phi[o];
-  } else {
-    phi[o] = g.u[i];
+  for (int t = threadIdx.x; t < NCB; t += WG) {
+    const size_t i = (size_t)leafblk[k] * NCB + t, o = (size_t)k * NCB + t;
+    if (dir == 0) {
+      g.f[i] = f[o];
+      g.fu[i] = f[o];
+      g.u[i] = phi[o];
+    } else {
+      phi[o] = g.u[i];
+    }
   }
 }
 
@@ -357,64 +468,80 @@ __global__ void k_fmg_zero2(unsigned long long* p) {
 
 // ---- Poisson (lambda = 0) and the divergence control (Sec. 2.4) ------------
 
-// area-weighted sum of a leaf block's cells of `which` (0: g.f, 1: g.u) into
-// part[k] (a fixed reduction order: the same bits on every run)
-__global__ void __launch_bounds__(NC) k_fmg_wsum(FmgDev g, const int* leafblk, int which, double* part) {
-  __shared__ double sm[NC / 64];
+// volume-weighted sum of a leaf block's cells of `which` (0: g.f, 1: g.u)
+// into part[k] (a fixed reduction order: the same bits on every run)
+template <int ND>
+__global__ void __launch_bounds__(WG) k_fmg_wsum(FmgDev g, const int* leafblk, int which, double* part) {
+  constexpr int NCB = ncb<ND>();
+  __shared__ double sm[WG / 64];
   const int b = leafblk[blockIdx.x];
   const double* a = which ? g.u : g.f;
-  double v = a[(size_t)b * NC + threadIdx.x];
+  double v = 0.0;
+  for (int t = threadIdx.x; t < NCB; t += WG) v += a[(size_t)b * NCB + t];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
   __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = ((sm[0] + sm[1]) + (sm[2] + sm[3])) / g.ih2[g.lvl[b]];
+  const int l = g.lvl[b];
+  if (threadIdx.x == 0)
+    part[blockIdx.x] = ((sm[0] + sm[1]) + (sm[2] + sm[3])) / (ND == 3 ? g.ih2[l] * g.rh[l] : g.ih2[l]);
 }
 
-// mean = sum(part) / area, one workgroup, a fixed order
-__global__ void __launch_bounds__(NC) k_fmg_wmean(const double* part, int n, double area, double* mean) {
-  __shared__ double sm[NC];
+// mean = sum(part) / volume, one workgroup, a fixed order
+__global__ void __launch_bounds__(WG) k_fmg_wmean(const double* part, int n, double vol, double* mean) {
+  __shared__ double sm[WG];
   double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += NC) v += part[i];
+  for (int i = threadIdx.x; i < n; i += WG) v += part[i];
   sm[threadIdx.x] = v;
   __syncthreads();
-  for (int o = NC / 2; o > 0; o >>= 1) {
+  for (int o = WG / 2; o > 0; o >>= 1) {
     if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *mean = sm[0] / area;
+  if (threadIdx.x == 0) *mean = sm[0] / vol;
 }
 
 // subtract *mean from the leaf blocks' g.f and g.fu (which 0) or g.u (which 1)
-__global__ void __launch_bounds__(NC) k_fmg_submean(FmgDev g, const int* leafblk, int which, const double* mean) {
-  const size_t i = (size_t)leafblk[blockIdx.x] * NC + threadIdx.x;
+template <int ND>
+__global__ void __launch_bounds__(WG) k_fmg_submean(FmgDev g, const int* leafblk, int which, const double* mean) {
+  constexpr int NCB = ncb<ND>();
   const double m = *mean;
-  if (which == 0) {
-    g.f[i] -= m;
-    g.fu[i] -= m;
-  } else {
-    g.u[i] -= m;
+  for (int t = threadIdx.x; t < NCB; t += WG) {
+    const size_t i = (size_t)leafblk[blockIdx.x] * NCB + t;
+    if (which == 0) {
+      g.f[i] -= m;
+      g.fu[i] -= m;
+    } else {
+      g.u[i] -= m;
+    }
   }
 }
 
-// the value one cell over from cell (x, y) of leaf block b along face `face`
-__host__ __device__ inline double face_value(const FmgDev& g, int b, int x, int y, int face) {
-  const int xn = x + (face == 0 ? -1 : (face == 1 ? 1 : 0));
-  const int yn = y + (face == 2 ? -1 : (face == 3 ? 1 : 0));
-  if (xn >= 0 && xn < NB && yn >= 0 && yn < NB) return g.u[(size_t)b * NC + xn + NB * yn];
-  double c, w;
-  across(g, b, true, x, y, face, c, w);
-  return c + w * g.u[(size_t)b * NC + x + NB * y];
+// the value one cell over from cell c of leaf block b across face `face`
+template <int ND>
+__host__ __device__ inline double face_value(const FmgDev& g, int b, const int* c, int face) {
+  constexpr int NCB = ncb<ND>();
+  int cn[3] = {c[0], c[1], c[2]};
+  cn[face >> 1] += (face & 1) ? 1 : -1;
+  if (cn[face >> 1] >= 0 && cn[face >> 1] < NB) return g.u[(size_t)b * NCB + cidx(cn)];
+  double cv, w;
+  across<ND>(g, b, true, c, face, cv, w);
+  return cv + w * g.u[(size_t)b * NCB + cidx(c)];
 }
 
 // central difference along d of the loaded leaf field: (w(+1) - w(-1)) (n_l / 2L),
 // into out (acc 0) or added to it (acc 1)
-__global__ void __launch_bounds__(NC) k_fmg_diff(FmgDev g, const int* leafblk, int d, int acc, double* out) {
+template <int ND>
+__global__ void __launch_bounds__(WG) k_fmg_diff(FmgDev g, const int* leafblk, int d, int acc, double* out) {
+  constexpr int NCB = ncb<ND>();
   const int b = leafblk[blockIdx.x];
-  const int x = threadIdx.x & (NB - 1), y = threadIdx.x >> 4;
-  const double v = (face_value(g, b, x, y, 2 * d + 1) - face_value(g, b, x, y, 2 * d)) * (0.5 * g.rh[g.lvl[b]]);
-  const size_t o = (size_t)blockIdx.x * NC + threadIdx.x;
-  out[o] = acc ? out[o] + v : v;
+  FMG_PLANES(ND) {
+    const int c[3] = {tx, ty, tz};
+    const double v =
+        (face_value<ND>(g, b, c, 2 * d + 1) - face_value<ND>(g, b, c, 2 * d)) * (0.5 * g.rh[g.lvl[b]]);
+    const size_t o = (size_t)blockIdx.x * NCB + cidx(c);
+    out[o] = acc ? out[o] + v : v;
+  }
 }
 
 __global__ void k_fmg_sub2(long long n, double* a, const double* da, double* b, const double* db) {
@@ -450,14 +577,20 @@ __device__ __forceinline__ void react(const RdF& p, double u, double v, double& 
 }
 
 // a leaf field into the state of the leaf blocks
-__global__ void __launch_bounds__(NC) k_fmg_load(FmgDev g, const int* leafblk, const double* w) {
-  g.u[(size_t)leafblk[blockIdx.x] * NC + threadIdx.x] = w[(size_t)blockIdx.x * NC + threadIdx.x];
+template <int ND>
+__global__ void __launch_bounds__(WG) k_fmg_load(FmgDev g, const int* leafblk, const double* w) {
+  constexpr int NCB = ncb<ND>();
+  for (int t = threadIdx.x; t < NCB; t += WG)
+    g.u[(size_t)leafblk[blockIdx.x] * NCB + t] = w[(size_t)blockIdx.x * NCB + t];
 }
 
 // D lap(w) at the leaf cells of the loaded field (the problem's rules; g.lam = 0)
-__global__ void __launch_bounds__(NC) k_fmg_lap(FmgDev g, const int* leafblk, double D, double* out) {
-  out[(size_t)blockIdx.x * NC + threadIdx.x] =
-      D * apply_cell(g, leafblk[blockIdx.x], true, threadIdx.x & (NB - 1), threadIdx.x >> 4);
+template <int ND>
+__global__ void __launch_bounds__(WG) k_fmg_lap(FmgDev g, const int* leafblk, double D, double* out) {
+  FMG_PLANES(ND) {
+    const int c[3] = {tx, ty, tz};
+    out[(size_t)blockIdx.x * ncb<ND>() + cidx(c)] = D * apply_cell<ND>(g, leafblk[blockIdx.x], true, c);
+  }
 }
 
 // o = b + c (F0(s) + l), l = D lap(s) (explicit Euler and midpoint stages)
@@ -520,18 +653,23 @@ __global__ void k_fmg_rd_imex_final(RdF p, long long n, double* u, double* v, co
 // ---------------------------------------------------------------------------
 
 struct Tree {
-  int nblk = 0, nlev = 0;
+  int nd = 2, nblk = 0, nlev = 0;
   int lstart[FMG_MAXL + 2] = {};
   std::vector<int> lvl, ij, nbr, chi, cnb, par, leafblk;
 };
 
+int fmg_ndim(const amrv_fmg_config* c) { return c->ndim == 0 ? 2 : c->ndim; }
+
 int validate(const amrv_fmg_config* c) {
   if (!c) return set_error(AMRV_EINVAL, "null config");
+  const int nd = fmg_ndim(c);
+  if (nd != 2 && nd != 3) return set_error(AMRV_EINVAL, "ndim must be 2 or 3");
   if (c->nleaves < 1) return set_error(AMRV_EINVAL, "nleaves must be >= 1");
   if (c->base < 1 || c->base > 512 || (c->base & (c->base - 1)))
     return set_error(AMRV_EINVAL, "base must be a power of two in 1..512");
   if (c->max_level < 1 || c->max_level > FMG_MAXL) return set_error(AMRV_EINVAL, "max_level must be in 1..16");
-  if ((long long)c->base * NB > 8192) return set_error(AMRV_EINVAL, "base * 16 must be <= 8192");
+  if ((long long)c->base * NB > (nd == 2 ? 8192 : 512))
+    return set_error(AMRV_EINVAL, "base * 16 must be <= 8192 (2D) or 512 (3D)");
   if (c->bc != AMRV_MG_PERIODIC && c->bc != AMRV_MG_NEUMANN) return set_error(AMRV_EINVAL, "bc must be periodic or Neumann");
   if (c->pre_sweeps < 1 || c->pre_sweeps > 8 || c->post_sweeps < 1 || c->post_sweeps > 8)
     return set_error(AMRV_EINVAL, "pre_sweeps and post_sweeps must be in 1..8");
@@ -541,109 +679,111 @@ int validate(const amrv_fmg_config* c) {
 
 int build_tree(const amrv_fmg_config* c, const int32_t* level, const int32_t* ijk, Tree& T) {
   if (!level || !ijk) return set_error(AMRV_EINVAL, "null leaf arrays");
-  using Key = std::tuple<int, int, int>;
+  const int nd = fmg_ndim(c), nf = 2 * nd, nch = 1 << nd;
+  using Key = std::array<int, 4>;  // level, i, j, k
   std::map<Key, int> leaf;
   std::map<Key, int> blocks;  // value: 1 for a leaf
   for (long long k = 0; k < c->nleaves; k++) {
-    const int l = level[k], i = ijk[3 * k], j = ijk[3 * k + 1];
+    const int l = level[k];
     const long long nl = (long long)c->base << (l - 1);
-    if (l < 1 || l > c->max_level || i < 0 || j < 0 || i >= nl || j >= nl || ijk[3 * k + 2] != 0)
-      return set_error(AMRV_EINVAL, "leaf level or block coordinates out of range");
-    if (!leaf.emplace(Key(l, i, j), (int)k).second) return set_error(AMRV_EUNBALANCED, "leaves overlap (a leaf appears twice)");
+    bool ok = l >= 1 && l <= c->max_level;
+    for (int e = 0; e < 3 && ok; e++) {
+      const int v = ijk[3 * k + e];
+      ok = e < nd ? (v >= 0 && v < nl) : v == 0;
+    }
+    if (!ok) return set_error(AMRV_EINVAL, "leaf level or block coordinates out of range");
+    if (!leaf.emplace(Key{l, ijk[3 * k], ijk[3 * k + 1], ijk[3 * k + 2]}, (int)k).second)
+      return set_error(AMRV_EUNBALANCED, "leaves overlap (a leaf appears twice)");
   }
   for (const auto& kv : leaf) blocks[kv.first] = 1;
   for (const auto& kv : leaf) {
-    int l, i, j;
-    std::tie(l, i, j) = kv.first;
-    while (l > 1) {
-      l--;
-      i >>= 1;
-      j >>= 1;
-      auto it = blocks.find(Key(l, i, j));
+    Key a = kv.first;
+    while (a[0] > 1) {
+      a = Key{a[0] - 1, a[1] >> 1, a[2] >> 1, a[3] >> 1};
+      auto it = blocks.find(a);
       if (it != blocks.end()) {
         if (it->second == 1) return set_error(AMRV_EUNBALANCED, "leaves overlap");
         break;  // its ancestors are in already
       }
-      blocks[Key(l, i, j)] = 0;
+      blocks[a] = 0;
     }
   }
-  // blocks ordered by level, then row-major
+  // blocks ordered by level, then z, y, x
   std::vector<Key> keys;
   for (const auto& kv : blocks) keys.push_back(kv.first);
   std::sort(keys.begin(), keys.end(), [](const Key& a, const Key& b) {
-    return std::make_tuple(std::get<0>(a), std::get<2>(a), std::get<1>(a)) <
-           std::make_tuple(std::get<0>(b), std::get<2>(b), std::get<1>(b));
+    return std::make_tuple(a[0], a[3], a[2], a[1]) < std::make_tuple(b[0], b[3], b[2], b[1]);
   });
   std::map<Key, int> index;
   for (size_t b = 0; b < keys.size(); b++) index[keys[b]] = (int)b;
   const int nblk = (int)keys.size();
+  T.nd = nd;
   T.nblk = nblk;
   T.lvl.assign(nblk, 0);
-  T.ij.assign(2 * nblk, 0);
-  T.nbr.assign(4 * nblk, NBR_NONE);
-  T.chi.assign(4 * nblk, -1);
-  T.cnb.assign(4 * nblk, -1);
+  T.ij.assign(TS * nblk, 0);
+  T.nbr.assign(FS * nblk, NBR_NONE);
+  T.chi.assign(CS * nblk, -1);
+  T.cnb.assign(FS * nblk, -1);
   T.par.assign(nblk, -1);
   T.leafblk.assign(c->nleaves, -1);
   T.nlev = 0;
-  for (int b = 0; b < nblk; b++) T.nlev = std::max(T.nlev, std::get<0>(keys[b]));
+  for (int b = 0; b < nblk; b++) T.nlev = std::max(T.nlev, keys[b][0]);
   // blocks of level l: [lstart[l], lstart[l + 1])
   for (int l = 0; l <= FMG_MAXL + 1; l++) T.lstart[l] = 0;
-  for (int b = 0; b < nblk; b++) T.lstart[std::get<0>(keys[b]) + 1]++;
+  for (int b = 0; b < nblk; b++) T.lstart[keys[b][0] + 1]++;
   for (int l = 1; l <= FMG_MAXL + 1; l++) T.lstart[l] += T.lstart[l - 1];
-  if (T.lstart[2] - T.lstart[1] != c->base * c->base)
-    return set_error(AMRV_EUNBALANCED, "the leaves do not cover the base grid");
-  auto find = [&](int l, long long i, long long j) {
-    auto it = index.find(Key(l, (int)i, (int)j));
+  long long nbase = 1;
+  for (int e = 0; e < nd; e++) nbase *= c->base;
+  if (T.lstart[2] - T.lstart[1] != nbase) return set_error(AMRV_EUNBALANCED, "the leaves do not cover the base grid");
+  auto find = [&](int l, long long i, long long j, long long k) {
+    auto it = index.find(Key{l, (int)i, (int)j, (int)k});
     return it == index.end() ? -1 : it->second;
   };
   for (int b = 0; b < nblk; b++) {
-    int l, i, j;
-    std::tie(l, i, j) = keys[b];
+    const Key& K = keys[b];
+    const int l = K[0];
     T.lvl[b] = l;
-    T.ij[2 * b] = i;
-    T.ij[2 * b + 1] = j;
-    if (l > 1) T.par[b] = find(l - 1, i >> 1, j >> 1);
+    for (int e = 0; e < 3; e++) T.ij[TS * b + e] = K[1 + e];
+    if (l > 1) T.par[b] = find(l - 1, K[1] >> 1, K[2] >> 1, K[3] >> 1);
     const long long nl = (long long)c->base << (l - 1);
-    const bool isleaf = blocks[keys[b]] == 1;
-    int nch = 0;
-    for (int q = 0; q < 4; q++) {
-      T.chi[4 * b + q] = find(l + 1, 2 * i + (q & 1), 2 * j + (q >> 1));
-      nch += T.chi[4 * b + q] >= 0;
+    const bool isleaf = blocks[K] == 1;
+    int nchild = 0;
+    for (int q = 0; q < nch; q++) {
+      T.chi[CS * b + q] = find(l + 1, 2 * K[1] + (q & 1), 2 * K[2] + ((q >> 1) & 1), 2 * K[3] + ((q >> 2) & 1));
+      nchild += T.chi[CS * b + q] >= 0;
     }
-    if (isleaf ? nch != 0 : nch != 4) return set_error(AMRV_EUNBALANCED, "leaves overlap or leave gaps");
-    for (int f = 0; f < 4; f++) {
-      long long ni = i + (f == 0 ? -1 : (f == 1 ? 1 : 0)), nj = j + (f == 2 ? -1 : (f == 3 ? 1 : 0));
-      if (ni < 0 || nj < 0 || ni >= nl || nj >= nl) {
+    if (isleaf ? nchild != 0 : nchild != nch) return set_error(AMRV_EUNBALANCED, "leaves overlap or leave gaps");
+    for (int f = 0; f < nf; f++) {
+      const int d = f >> 1;
+      long long n3[3] = {K[1], K[2], K[3]};
+      n3[d] += (f & 1) ? 1 : -1;
+      if (n3[d] < 0 || n3[d] >= nl) {
         if (c->bc == AMRV_MG_NEUMANN) {
-          T.nbr[4 * b + f] = NBR_WALL;
+          T.nbr[FS * b + f] = NBR_WALL;
           continue;
         }
-        ni = (ni + nl) % nl;
-        nj = (nj + nl) % nl;
+        n3[d] = (n3[d] + nl) % nl;
       }
-      const int nb = find(l, ni, nj);
-      T.nbr[4 * b + f] = nb;
+      const int nb = find(l, n3[0], n3[1], n3[2]);
+      T.nbr[FS * b + f] = nb;
       if (nb >= 0) {
-        // a refined neighbour of a leaf: its two children along the face must be leaves
+        // a refined neighbour of a leaf: its children along the face must be leaves
         if (isleaf && blocks[keys[nb]] == 0)
-          for (int q = 0; q < 4; q++) {
-            const bool touches = f < 2 ? (q & 1) == (f == 0 ? 1 : 0) : (q >> 1) == (f == 2 ? 1 : 0);
-            if (!touches) continue;
-            const int cq = find(l + 1, 2 * ni + (q & 1), 2 * nj + (q >> 1));
+          for (int q = 0; q < nch; q++) {
+            if (((q >> d) & 1) != ((f & 1) ? 0 : 1)) continue;
+            const int cq = find(l + 1, 2 * n3[0] + (q & 1), 2 * n3[1] + ((q >> 1) & 1), 2 * n3[2] + ((q >> 2) & 1));
             if (cq < 0 || blocks[keys[cq]] != 1) return set_error(AMRV_EUNBALANCED, "2:1 balance across a face broken");
           }
         continue;
       }
       // no block of this level across the face: only a leaf may see a coarser leaf there
       const long long nl1 = nl >> 1;
-      long long ci = ni >> 1, cj = nj >> 1;
-      ci = (ci + nl1) % nl1;
-      cj = (cj + nl1) % nl1;
-      const int C = l > 1 ? find(l - 1, ci, cj) : -1;
+      long long cc[3] = {n3[0] >> 1, n3[1] >> 1, n3[2] >> 1};
+      for (int e = 0; e < nd; e++) cc[e] = (cc[e] + nl1) % nl1;
+      const int C = l > 1 ? find(l - 1, cc[0], cc[1], cc[2]) : -1;
       if (!isleaf || C < 0 || blocks[keys[C]] != 1)
         return set_error(AMRV_EUNBALANCED, "2:1 balance across a face broken");
-      T.cnb[4 * b + f] = C;
+      T.cnb[FS * b + f] = C;
     }
   }
   for (const auto& kv : leaf) T.leafblk[kv.second] = index[kv.first];
@@ -654,7 +794,7 @@ int build_tree(const amrv_fmg_config* c, const int32_t* level, const int32_t* ij
 // per-colour sweeps (its smoother choice does not change its result)
 amrv_mg_config base_config(const amrv_fmg_config* c) {
   amrv_mg_config mc{};
-  mc.ndim = 2;
+  mc.ndim = fmg_ndim(c);
   mc.n = c->base * NB;
   mc.bc = c->bc;
   mc.nfields = 1;
@@ -679,24 +819,26 @@ FmgLayout layout(const amrv_fmg_config* c, const Tree& T) {
     o += (bytes + ALIGN - 1) / ALIGN * ALIGN;
     return at;
   };
-  const size_t nb = (size_t)T.nblk;
+  const int nd = fmg_ndim(c);
+  const size_t nb = (size_t)T.nblk, cb = nd == 3 ? (size_t)NB * NB * NB : (size_t)NB * NB;
   L.off_tab[0] = take(sizeof(int) * nb);        // lvl
-  L.off_tab[1] = take(sizeof(int) * 2 * nb);    // ij
-  L.off_tab[2] = take(sizeof(int) * 4 * nb);    // nbr
-  L.off_tab[3] = take(sizeof(int) * 4 * nb);    // chi
-  L.off_tab[4] = take(sizeof(int) * 4 * nb);    // cnb
+  L.off_tab[1] = take(sizeof(int) * TS * nb);   // ij
+  L.off_tab[2] = take(sizeof(int) * FS * nb);   // nbr
+  L.off_tab[3] = take(sizeof(int) * CS * nb);   // chi
+  L.off_tab[4] = take(sizeof(int) * FS * nb);   // cnb
   L.off_tab[5] = take(sizeof(int) * nb);        // par
   L.off_tab[6] = take(sizeof(int) * (size_t)c->nleaves);  // leaf -> block
-  L.off_u = take(sizeof(double) * NC * nb);
-  L.off_f = take(sizeof(double) * NC * nb);
-  L.off_fu = take(sizeof(double) * NC * nb);
-  L.off_r = take(sizeof(double) * NC * nb);
-  L.off_uo = take(sizeof(double) * NC * nb);
-  const size_t n = (size_t)c->base * NB;
-  L.off_fg = take(sizeof(double) * n * n);
-  L.off_vg = take(sizeof(double) * n * n);
+  L.off_u = take(sizeof(double) * cb * nb);
+  L.off_f = take(sizeof(double) * cb * nb);
+  L.off_fu = take(sizeof(double) * cb * nb);
+  L.off_r = take(sizeof(double) * cb * nb);
+  L.off_uo = take(sizeof(double) * cb * nb);
+  size_t gcells = 1;
+  for (int e = 0; e < nd; e++) gcells *= (size_t)c->base * NB;
+  L.off_fg = take(sizeof(double) * gcells);
+  L.off_vg = take(sizeof(double) * gcells);
   L.off_red = take(sizeof(unsigned long long) * 2);
-  for (int i = 0; i < 8; i++) L.off_tmp[i] = take(sizeof(double) * NC * (size_t)c->nleaves);  // RD temporaries
+  for (int i = 0; i < 8; i++) L.off_tmp[i] = take(sizeof(double) * cb * (size_t)c->nleaves);  // RD temporaries
   L.off_part = take(sizeof(double) * ((size_t)c->nleaves + 1));  // per-leaf sums and their mean
   amrv_mg_config mc = base_config(c);
   L.mg_bytes = amrv_mg_workspace_bytes(&mc);
@@ -707,9 +849,10 @@ FmgLayout layout(const amrv_fmg_config* c, const Tree& T) {
 
 }  // namespace
 
-
 struct amrv_fmg {
   amrv_fmg_config cfg{};
+  int nd = 2;      // dimension
+  long long ncb = 0;  // cells per block
   hipStream_t st = nullptr;
   Tree T;
   FmgLayout L{};
@@ -719,7 +862,7 @@ struct amrv_fmg {
   double* vgrid = nullptr;
   double* tmp[8] = {};  // leaf fields of the reaction-diffusion steps
   double* part = nullptr;  // per-leaf area-weighted sums, then [nleaves] = their mean
-  double area = 0.0;       // L^2
+  double area = 0.0;       // L^nd (the domain's area or volume)
   unsigned long long* red = nullptr;
   unsigned long long* hred = nullptr;  // pinned
   amrv_mg* base = nullptr;
@@ -746,10 +889,19 @@ double bits_to_double(unsigned long long b) {
 
 int nblocks(const amrv_fmg* m, int l) { return m->T.lstart[l + 1] - m->T.lstart[l]; }
 
+// a launch of the ND = 2 or 3 instance of a kernel template on m's stream
+#define FMG_LAUNCH(kern, grid, block, ...)                                           \
+  do {                                                                               \
+    if (m->nd == 2)                                                                  \
+      hipLaunchKernelGGL((kern<2>), dim3(grid), dim3(block), 0, m->st, __VA_ARGS__); \
+    else                                                                             \
+      hipLaunchKernelGGL((kern<3>), dim3(grid), dim3(block), 0, m->st, __VA_ARGS__); \
+  } while (0)
+
 int sweeps(amrv_fmg* m, int l, int count) {
   for (int s = 0; s < count; s++)
     for (int c = 0; c < 2; c++)
-      hipLaunchKernelGGL(k_fmg_smooth, dim3(nblocks(m, l)), dim3(NC), 0, m->st, m->g, m->T.lstart[l], c);
+      FMG_LAUNCH(k_fmg_smooth, nblocks(m, l), WG, m->g, m->T.lstart[l], c);
   FMGCHK(hipGetLastError());
   return 0;
 }
@@ -760,27 +912,26 @@ int vcycle(amrv_fmg* m) {
   const int pre = m->cfg.pre_sweeps, post = m->cfg.post_sweeps;
   for (int l = L; l >= 2; l--) {
     if (int rc = sweeps(m, l, pre)) return rc;
-    hipLaunchKernelGGL(k_fmg_resid, dim3(nblocks(m, l)), dim3(NC), 0, m->st, m->g, m->T.lstart[l]);
-    hipLaunchKernelGGL(k_fmg_restrict, dim3(nblocks(m, l)), dim3(64), 0, m->st, m->g, m->T.lstart[l]);
-    hipLaunchKernelGGL(k_fmg_fas, dim3(nblocks(m, l - 1)), dim3(NC), 0, m->st, m->g, m->T.lstart[l - 1]);
+    FMG_LAUNCH(k_fmg_resid, nblocks(m, l), WG, m->g, m->T.lstart[l]);
+    FMG_LAUNCH(k_fmg_restrict, nblocks(m, l), m->nd == 3 ? WG : 64, m->g, m->T.lstart[l]);
+    FMG_LAUNCH(k_fmg_fas, nblocks(m, l - 1), WG, m->g, m->T.lstart[l - 1]);
     FMGCHK(hipGetLastError());
   }
   if (int rc = sweeps(m, 1, pre)) return rc;
   const int n = m->cfg.base * NB;
-  hipLaunchKernelGGL(k_fmg_resid, dim3(nblocks(m, 1)), dim3(NC), 0, m->st, m->g, m->T.lstart[1]);
-  hipLaunchKernelGGL(k_fmg_to_grid, dim3(nblocks(m, 1)), dim3(NC), 0, m->st, m->g, m->T.lstart[1], n, m->fgrid,
-                     m->vgrid);
+  FMG_LAUNCH(k_fmg_resid, nblocks(m, 1), WG, m->g, m->T.lstart[1]);
+  FMG_LAUNCH(k_fmg_to_grid, nblocks(m, 1), WG, m->g, m->T.lstart[1], n, m->fgrid, m->vgrid);
   FMGCHK(hipGetLastError());
   // the level-1 correction: one of the uniform solver's V-cycles from zero
   // (it cuts the error by 20 or more; solved as a correction, what is left
   // shrinks with the residual from cycle to cycle), enqueued without a host
   // wait
   if (int rc = amrv::mg_enqueue_correction(m->base, m->fgrid, m->vgrid, m->g.lam, 1)) return rc;
-  hipLaunchKernelGGL(k_fmg_from_grid, dim3(nblocks(m, 1)), dim3(NC), 0, m->st, m->g, m->T.lstart[1], n, m->vgrid);
+  FMG_LAUNCH(k_fmg_from_grid, nblocks(m, 1), WG, m->g, m->T.lstart[1], n, m->vgrid);
   FMGCHK(hipGetLastError());
   if (int rc2 = sweeps(m, 1, post)) return rc2;
   for (int l = 2; l <= L; l++) {
-    hipLaunchKernelGGL(k_fmg_prolong, dim3(nblocks(m, l)), dim3(NC), 0, m->st, m->g, m->T.lstart[l]);
+    FMG_LAUNCH(k_fmg_prolong, nblocks(m, l), WG, m->g, m->T.lstart[l]);
     FMGCHK(hipGetLastError());
     if (int rc2 = sweeps(m, l, post)) return rc2;
   }
@@ -790,7 +941,7 @@ int vcycle(amrv_fmg* m) {
 // max |r| over the leaves (and, with fmax, max |f| of the problem as solved)
 int norms(amrv_fmg* m, double* res, double* fmax) {
   hipLaunchKernelGGL(k_fmg_zero2, dim3(1), dim3(64), 0, m->st, m->red);
-  hipLaunchKernelGGL(k_fmg_resmax, dim3(m->T.nblk), dim3(NC), 0, m->st, m->g, m->red, fmax ? 1 : 0);
+  FMG_LAUNCH(k_fmg_resmax, m->T.nblk, WG, m->g, m->red, fmax ? 1 : 0);
   FMGCHK(hipGetLastError());
   FMGCHK(hipMemcpyAsync(m->hred, m->red, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, m->st));
   FMGCHK(hipStreamSynchronize(m->st));
@@ -802,9 +953,9 @@ int norms(amrv_fmg* m, double* res, double* fmax) {
 // subtract the area-weighted mean of the leaves' f (which 0: g.f and g.fu) or u (1)
 int remove_mean(amrv_fmg* m, int which) {
   const int nl = (int)m->cfg.nleaves;
-  hipLaunchKernelGGL(k_fmg_wsum, dim3(nl), dim3(NC), 0, m->st, m->g, m->leafblk, which, m->part);
-  hipLaunchKernelGGL(k_fmg_wmean, dim3(1), dim3(NC), 0, m->st, m->part, nl, m->area, m->part + nl);
-  hipLaunchKernelGGL(k_fmg_submean, dim3(nl), dim3(NC), 0, m->st, m->g, m->leafblk, which, m->part + nl);
+  FMG_LAUNCH(k_fmg_wsum, nl, WG, m->g, m->leafblk, which, m->part);
+  hipLaunchKernelGGL(k_fmg_wmean, dim3(1), dim3(WG), 0, m->st, m->part, nl, m->area, m->part + nl);
+  FMG_LAUNCH(k_fmg_submean, nl, WG, m->g, m->leafblk, which, m->part + nl);
   FMGCHK(hipGetLastError());
   return 0;
 }
@@ -877,7 +1028,9 @@ int amrv_fmg_create(const amrv_fmg_config* cfg, const int32_t* leaf_level, const
   m->red = reinterpret_cast<unsigned long long*>(base + m->L.off_red);
   for (int i = 0; i < 8; i++) m->tmp[i] = reinterpret_cast<double*>(base + m->L.off_tmp[i]);
   m->part = reinterpret_cast<double*>(base + m->L.off_part);
-  m->area = cfg->length * cfg->length;
+  m->nd = m->T.nd;
+  m->ncb = m->nd == 3 ? (long long)NB * NB * NB : (long long)NB * NB;
+  m->area = m->nd == 3 ? cfg->length * cfg->length * cfg->length : cfg->length * cfg->length;
   const amrv_mg_config mc = base_config(cfg);
   if (int rc = amrv_mg_create(&mc, base + m->L.off_mg, m->L.mg_bytes, stream, &m->base)) {
     (void)hipHostFree(m->hred);
@@ -885,7 +1038,7 @@ int amrv_fmg_create(const amrv_fmg_config* cfg, const int32_t* leaf_level, const
     return rc;
   }
   // parents start from zero (every parent is restricted before it is read)
-  e = hipMemsetAsync(g.u, 0, sizeof(double) * NC * (size_t)T.nblk, m->st);
+  e = hipMemsetAsync(g.u, 0, sizeof(double) * m->ncb * (size_t)T.nblk, m->st);
   if (e == hipSuccess) e = hipStreamSynchronize(m->st);
   if (e != hipSuccess) {
     amrv_mg_destroy(m->base);
@@ -917,7 +1070,7 @@ int amrv_fmg_solve(amrv_fmg* m, const double* f, double* phi, double lambda, dou
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) return set_error(AMRV_EINVAL, "lambda must be >= 0 and finite");
   if (!(tol > 0.0) || max_cycles < 0) return set_error(AMRV_EINVAL, "tol must be > 0 and max_cycles >= 0");
   m->g.lam = lambda;
-  hipLaunchKernelGGL(k_fmg_leaves, dim3(m->cfg.nleaves), dim3(NC), 0, m->st, m->g, m->leafblk, f, phi, 0);
+  FMG_LAUNCH(k_fmg_leaves, m->cfg.nleaves, WG, m->g, m->leafblk, f, phi, 0);
   FMGCHK(hipGetLastError());
   // Poisson: lap has the constants as null space and its area-weighted sums
   // vanish, so the problem solved is lap(phi) = f - mean(f), and phi is
@@ -947,7 +1100,7 @@ int amrv_fmg_solve(amrv_fmg* m, const double* f, double* phi, double lambda, dou
   m->last_cycles = c;
   if (poisson)
     if (int rc = remove_mean(m, 1)) return rc;
-  hipLaunchKernelGGL(k_fmg_leaves, dim3(m->cfg.nleaves), dim3(NC), 0, m->st, m->g, m->leafblk, f, phi, 1);
+  FMG_LAUNCH(k_fmg_leaves, m->cfg.nleaves, WG, m->g, m->leafblk, f, phi, 1);
   FMGCHK(hipGetLastError());
   FMGCHK(hipStreamSynchronize(m->st));
   if (cycles) *cycles = c;
@@ -970,7 +1123,7 @@ int amrv_fmg_rd_step(amrv_fmg* m, const amrv_rd_params* p, int32_t scheme, doubl
   const bool implicit = scheme == AMRV_RD_SPLIT || scheme == AMRV_RD_IMEX;
   if (implicit && (!(tol > 0.0) || max_cycles < 0)) return set_error(AMRV_EINVAL, "bad tol or max_cycles");
   const RdF k{p->model, p->Du, p->Dv, p->p1, p->p2, p->p3};
-  const long long n = (long long)m->cfg.nleaves * NC;
+  const long long n = (long long)m->cfg.nleaves * m->ncb;
   const int nb = (int)((n + 255) / 256);
   const int nl = (int)m->cfg.nleaves;
   FmgDev g0 = m->g;
@@ -978,8 +1131,8 @@ int amrv_fmg_rd_step(amrv_fmg* m, const amrv_rd_params* p, int32_t scheme, doubl
   double* const* T = m->tmp;
   // D lap of a leaf field into out
   auto lap = [&](const double* w, double D, double* out) {
-    hipLaunchKernelGGL(k_fmg_load, dim3(nl), dim3(NC), 0, m->st, g0, m->leafblk, w);
-    hipLaunchKernelGGL(k_fmg_lap, dim3(nl), dim3(NC), 0, m->st, g0, m->leafblk, D, out);
+    FMG_LAUNCH(k_fmg_load, nl, WG, g0, m->leafblk, w);
+    FMG_LAUNCH(k_fmg_lap, nl, WG, g0, m->leafblk, D, out);
   };
   int total = 0;
   double rmax = 0.0;
@@ -1040,20 +1193,21 @@ int amrv_fmg_divb_project(amrv_fmg* m, double* bx, double* by, double tol, int32
                           double* div_before, double* div_after) {
   if (!m || !bx || !by) return set_error(AMRV_EINVAL, "null argument");
   if (!(tol > 0.0) || max_cycles < 0) return set_error(AMRV_EINVAL, "bad tol or max_cycles");
-  const long long n = (long long)m->cfg.nleaves * NC;
+  if (m->nd != 2) return set_error(AMRV_ENOTSUP, "the forest divergence control is 2D");
+  const long long n = (long long)m->cfg.nleaves * m->ncb;
   const int nb = (int)((n + 255) / 256);
   const int nl = (int)m->cfg.nleaves;
   double* const* T = m->tmp;
   // the central divergence of (bx, by) into out
   auto div = [&](double* out) {
-    hipLaunchKernelGGL(k_fmg_load, dim3(nl), dim3(NC), 0, m->st, m->g, m->leafblk, bx);
-    hipLaunchKernelGGL(k_fmg_diff, dim3(nl), dim3(NC), 0, m->st, m->g, m->leafblk, 0, 0, out);
-    hipLaunchKernelGGL(k_fmg_load, dim3(nl), dim3(NC), 0, m->st, m->g, m->leafblk, by);
-    hipLaunchKernelGGL(k_fmg_diff, dim3(nl), dim3(NC), 0, m->st, m->g, m->leafblk, 1, 1, out);
+    FMG_LAUNCH(k_fmg_load, nl, WG, m->g, m->leafblk, bx);
+    FMG_LAUNCH(k_fmg_diff, nl, WG, m->g, m->leafblk, 0, 0, out);
+    FMG_LAUNCH(k_fmg_load, nl, WG, m->g, m->leafblk, by);
+    FMG_LAUNCH(k_fmg_diff, nl, WG, m->g, m->leafblk, 1, 1, out);
   };
   auto maxabs = [&](const double* v, double* out) -> int {
     hipLaunchKernelGGL(k_fmg_zero2, dim3(1), dim3(64), 0, m->st, m->red);
-    hipLaunchKernelGGL(k_fmg_maxabs, dim3(std::min(1024, nb)), dim3(NC), 0, m->st, v, n, m->red);
+    hipLaunchKernelGGL(k_fmg_maxabs, dim3(std::min(1024, nb)), dim3(WG), 0, m->st, v, n, m->red);
     FMGCHK(hipGetLastError());
     FMGCHK(hipMemcpyAsync(m->hred, m->red, sizeof(unsigned long long), hipMemcpyDeviceToHost, m->st));
     FMGCHK(hipStreamSynchronize(m->st));
@@ -1068,9 +1222,9 @@ int amrv_fmg_divb_project(amrv_fmg* m, double* bx, double* by, double tol, int32
   // phi: the zero-mean solution of lap(phi) = div B* - mean
   const int rc = amrv_fmg_solve(m, T[0], T[1], 0.0, tol, max_cycles, cycles, nullptr, nullptr);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_fmg_load, dim3(nl), dim3(NC), 0, m->st, m->g, m->leafblk, T[1]);
-  hipLaunchKernelGGL(k_fmg_diff, dim3(nl), dim3(NC), 0, m->st, m->g, m->leafblk, 0, 0, T[2]);
-  hipLaunchKernelGGL(k_fmg_diff, dim3(nl), dim3(NC), 0, m->st, m->g, m->leafblk, 1, 0, T[3]);
+  FMG_LAUNCH(k_fmg_load, nl, WG, m->g, m->leafblk, T[1]);
+  FMG_LAUNCH(k_fmg_diff, nl, WG, m->g, m->leafblk, 0, 0, T[2]);
+  FMG_LAUNCH(k_fmg_diff, nl, WG, m->g, m->leafblk, 1, 0, T[3]);
   hipLaunchKernelGGL(k_fmg_sub2, dim3(nb), dim3(256), 0, m->st, n, bx, T[2], by, T[3]);
   FMGCHK(hipGetLastError());
   if (div_after) {

@@ -139,13 +139,14 @@ class GpuMultigrid:
 
 
 def fmg_config(forest, length: float, bc: int, pre: int = 2, post: int = 2) -> N.FmgConfig:
-    """amrv_fmg_config of a 2D forest (workloads.Forest: square 16^2 blocks,
-    base x base blocks at level 1)."""
+    """amrv_fmg_config of a 2D or 3D forest (workloads.Forest: 16^d blocks,
+    base^d blocks at level 1)."""
     s = forest.scheme
-    if s.ndim != 2 or s.base_blocks[0] != s.base_blocks[1] or tuple(s.block_nx[:2]) != (16, 16):
-        raise ValueError("a 2D forest of 16 x 16 blocks on a square base grid")
+    nd = s.ndim
+    if nd not in (2, 3) or len(set(s.base_blocks[:nd])) != 1 or tuple(s.block_nx[:nd]) != (16,) * nd:
+        raise ValueError("a 2D or 3D forest of 16^d blocks on a square / cubic base grid")
     return N.FmgConfig(nleaves=forest.n, base=s.base_blocks[0], max_level=s.max_level, bc=bc, pre_sweeps=pre,
-                       post_sweeps=post, pad=0, length=length)
+                       post_sweeps=post, ndim=nd, length=length)
 
 
 def fmg_workspace_bytes(forest, length: float, bc: int) -> int:
@@ -164,9 +165,9 @@ def fmg_workspace_bytes(forest, length: float, bc: int) -> int:
 
 
 class GpuForestMultigrid:
-    """The Helmholtz solver on a 2D block-adaptive forest (amrv_fmg_*):
-    fields are float64 device tensors of shape [nleaves, 16, 16] (the
-    forest's layout of one variable)."""
+    """The Helmholtz solver on a 2D or 3D block-adaptive forest (amrv_fmg_*):
+    fields are float64 device tensors of nleaves * 16^d values ([nleaves,
+    (16,) 16, 16], the forest's layout of one variable)."""
 
     def __init__(self, forest, length: float, bc: int, pre: int = 2, post: int = 2,
                  device: str | torch.device = "cuda:0", stream: torch.cuda.Stream | None = None):
@@ -179,6 +180,7 @@ class GpuForestMultigrid:
         nbytes = fmg_workspace_bytes(forest, length, bc)
         self.device = torch.device(device)
         self.nleaves = forest.n
+        self.ncb = 16 ** forest.scheme.ndim
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -209,8 +211,8 @@ class GpuForestMultigrid:
         for t in (f, phi):
             if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
                 raise ValueError("expected contiguous float64 device tensors")
-            if t.numel() != self.nleaves * 256:
-                raise ValueError(f"expected {self.nleaves * 256} values, got {t.numel()}")
+            if t.numel() != self.nleaves * self.ncb:
+                raise ValueError(f"expected {self.nleaves * self.ncb} values, got {t.numel()}")
         cyc = ctypes.c_int32()
         res, fmax = ctypes.c_double(), ctypes.c_double()
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
@@ -228,8 +230,8 @@ class GpuForestMultigrid:
         for t in (u, v):
             if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
                 raise ValueError("expected contiguous float64 device tensors")
-            if t.numel() != self.nleaves * 256:
-                raise ValueError(f"expected {self.nleaves * 256} values, got {t.numel()}")
+            if t.numel() != self.nleaves * self.ncb:
+                raise ValueError(f"expected {self.nleaves * self.ncb} values, got {t.numel()}")
         p = rd_params(int(params["model"]), params["Du"], params["Dv"], params["p1"], params["p2"],
                       params.get("p3", 0.0))
         cyc = ctypes.c_int32()
@@ -247,8 +249,8 @@ class GpuForestMultigrid:
         for t in (bx, by):
             if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
                 raise ValueError("expected contiguous float64 device tensors")
-            if t.numel() != self.nleaves * 256:
-                raise ValueError(f"expected {self.nleaves * 256} values, got {t.numel()}")
+            if t.numel() != self.nleaves * self.ncb:
+                raise ValueError(f"expected {self.nleaves * self.ncb} values, got {t.numel()}")
         cyc = ctypes.c_int32()
         before, after = ctypes.c_double(), ctypes.c_double()
         self.stream.wait_stream(torch.cuda.current_stream(self.device))

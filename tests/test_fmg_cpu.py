@@ -70,3 +70,40 @@ def test_rejects_bad_configuration():
         lev = np.ascontiguousarray(f.level, dtype=np.int32)
         ijk = np.ascontiguousarray(f.ijk, dtype=np.int32)
         assert N.lib().amrv_fmg_workspace_bytes(cfg, lev.ctypes.data, ijk.ctypes.data) == 0, field
+
+
+def test_3d_octree_forests():
+    """Octree forests: the workspace covers every block of the tree; an
+    octree that breaks 2:1 balance and a 3D base grid above 512 cells per
+    side are rejected."""
+    f = W.fmg_forest(W.fmg_scheme(base=2, max_level=3, bc=MG.NEUMANN, ndim=3), centre=(0.3, 0.35, 0.4), radius=0.15)
+    nbytes = MG.fmg_workspace_bytes(f, 1.0, MG.NEUMANN)
+    anc = set()
+    for l, (i, j, k) in zip(f.level, f.ijk):
+        while l > 1:
+            l, i, j, k = l - 1, i >> 1, j >> 1, k >> 1
+            anc.add((int(l), int(i), int(j), int(k)))
+    assert nbytes >= (f.n + len(anc)) * 5 * 4096 * 8
+    s = W.fmg_scheme(base=2, max_level=3, ndim=3)
+    lev, ijk = [], []
+    for k in range(2):
+        for j in range(2):
+            for i in range(2):
+                if (i, j, k) != (0, 0, 0):
+                    lev.append(1)
+                    ijk.append([i, j, k])
+    for q in range(8):
+        a, b, c = q & 1, (q >> 1) & 1, q >> 2
+        if q == 7:
+            for r in range(8):
+                lev.append(3)
+                ijk.append([2 + (r & 1), 2 + ((r >> 1) & 1), 2 + (r >> 2)])
+        else:
+            lev.append(2)
+            ijk.append([a, b, c])
+    _expect_error(W.Forest(s, np.array(lev, dtype=np.int32), np.array(ijk, dtype=np.int32)))
+    cfg = MG.fmg_config(f, 1.0, MG.PERIODIC)
+    cfg.base = 64
+    lev_a = np.ascontiguousarray(f.level, dtype=np.int32)
+    ijk_a = np.ascontiguousarray(f.ijk, dtype=np.int32)
+    assert N.lib().amrv_fmg_workspace_bytes(cfg, lev_a.ctypes.data, ijk_a.ctypes.data) == 0
