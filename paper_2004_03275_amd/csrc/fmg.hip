@@ -347,11 +347,22 @@ __host__ __device__ inline void to_grid_cell(const FmgDev& g, int b, const int* 
   const int tx = threadIdx.x & (NB - 1), ty = threadIdx.x >> 4; \
   for (int tz = 0; tz < nplanes<ND>(); tz++)
 
+// a colour sweep over the blocks [b0, b0 + gridDim.x); in 3D the 256 threads
+// take the 128 cells of the colour in each of two planes at a time (x = 2 hx
+// + the parity that gives the colour), so no lane idles
 template <int ND>
 __global__ void __launch_bounds__(WG) k_fmg_smooth(FmgDev g, int b0, int colour) {
-  FMG_PLANES(ND) {
-    const int c[3] = {tx, ty, tz};
-    if (((tx + ty + tz) & 1) == colour) smooth_cell<ND>(g, b0 + blockIdx.x, c);
+  if constexpr (ND == 2) {
+    const int tx = threadIdx.x & (NB - 1), ty = threadIdx.x >> 4;
+    const int c[3] = {tx, ty, 0};
+    if (((tx + ty) & 1) == colour) smooth_cell<2>(g, b0 + blockIdx.x, c);
+  } else {
+    const int hx = threadIdx.x & 7, ty = (threadIdx.x >> 3) & (NB - 1), pz = threadIdx.x >> 7;
+    for (int z0 = 0; z0 < NB; z0 += 2) {
+      const int tz = z0 + pz;
+      const int c[3] = {2 * hx + ((ty + tz + colour) & 1), ty, tz};
+      smooth_cell<3>(g, b0 + blockIdx.x, c);
+    }
   }
 }
 
