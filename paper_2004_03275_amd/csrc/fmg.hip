@@ -282,11 +282,21 @@ __host__ __device__ inline void restrict_cell(const FmgDev& g, int b, int t) {
 template <int ND>
 __host__ __device__ inline void fas_cell(const FmgDev& g, int b, const int* c) {
   const size_t i = (size_t)b * ncb<ND>() + cidx(c);
-  const double lp = apply_cell<ND>(g, b, false, c);
   if (g.chi[CS * b] >= 0) {
-    g.f[i] = lp + g.r[i];
+    g.f[i] = apply_cell<ND>(g, b, false, c) + g.r[i];
     return;
   }
+  bool refined = false;  // a refined same-level neighbour (else both stencils agree)
+#pragma unroll
+  for (int face = 0; face < 2 * ND; face++) {
+    const int nb = g.nbr[FS * b + face];
+    refined = refined || (nb >= 0 && g.chi[CS * nb] >= 0);
+  }
+  if (!refined) {
+    g.f[i] = g.fu[i];
+    return;
+  }
+  const double lp = apply_cell<ND>(g, b, false, c);
   const double lc = apply_cell<ND>(g, b, true, c);
   g.f[i] = lp == lc ? g.fu[i] : lp + (g.fu[i] - lc);
 }
