@@ -326,6 +326,15 @@ def poisson(forest, f, length: float, bc: int) -> np.ndarray:
     return sol[:n].reshape(np.shape(f))
 
 
+def divb_project_nd(forest, B, length: float, bc: int):
+    """divb_project for a 2D or 3D forest: B a list of nd leaf fields.
+    Returns (list of projected fields, phi)."""
+    div = divergence(forest, B[0], B[1], length, bc, B[2] if len(B) > 2 else None)
+    phi = poisson(forest, div, length, bc)
+    G = gradient(forest, phi, length, bc)
+    return [B[d] - G[d] for d in range(len(B))], phi
+
+
 def divb_project(forest, bx, by, length: float, bc: int):
     """The divergence control of Sec. 2.4 on the leaf cells of a 2D forest:
     phi = the zero-mean solution of lap(phi) = div B*, B = B* - grad phi

@@ -325,3 +325,26 @@ def test_3d_symmetry_and_second_order():
         errs.append(np.max(np.abs(uu - ue)))
     order = np.log(errs[0] / errs[1]) / np.log(6 / 4)
     assert order >= 1.7, (errs, order)
+
+
+def test_3d_projection_on_a_uniform_forest_is_the_grid_projection():
+    """Every leaf at level 2 of an octree (4^3 cells per block, periodic 16^3
+    grid): divergence, zero-mean Poisson and projection equal oracle/rd.py's."""
+    s = W.fmg_scheme(base=2, max_level=2, bc=fmg.PERIODIC, ndim=3)
+    s.block_nx = (4, 4, 4)
+    f = W.uniform_forest(s, level=2)
+    x, y, z = fmg.cell_centres(f, 1.0)
+    B = [np.sin(2 * np.pi * x) * np.cos(2 * np.pi * z), np.cos(2 * np.pi * y + 0.3) * np.sin(2 * np.pi * x),
+         np.sin(4 * np.pi * z) + 0.2 * np.cos(2 * np.pi * y)]
+
+    def G(a):
+        out = np.zeros((16, 16, 16))
+        for k in range(f.n):
+            i, j, l = f.ijk[k]
+            out[4 * l:4 * l + 4, 4 * j:4 * j + 4, 4 * i:4 * i + 4] = a[k]
+        return out
+
+    P, _ = fmg.divb_project_nd(f, B, 1.0, fmg.PERIODIC)
+    R, _ = rd.divb_project([G(b) for b in B], 1.0, rd.PERIODIC)
+    for d in range(3):
+        assert np.max(np.abs(G(P[d]) - R[d])) <= 1e-11
