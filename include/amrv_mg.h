@@ -255,19 +255,19 @@ int amrv_fmg_solve(amrv_fmg* m, const double* f, double* phi, double lambda, dou
 int amrv_fmg_rd_step(amrv_fmg* m, const amrv_rd_params* p, int32_t scheme, double dt, int32_t nsteps, double* u,
                      double* v, double tol, int32_t max_cycles, int32_t* cycles_total, double* res_max);
 
-/* The divergence control of Sec. 2.4 on a 2D forest's leaf fields bx, by
- * (device, nleaves * 256 doubles each, updated in place): phi is the
+/* The divergence control of Sec. 2.4 on a forest's leaf fields bx, by, bz
+ * (device, nleaves * 16^ndim doubles each, updated in place; bz unused and
+ * may be NULL in 2D, required in 3D): phi is the
  * zero-mean solution of lap(phi) = div B* (amrv_fmg_solve with lambda = 0,
  * tol and max_cycles as there), then B = B* - grad phi; div and grad are
  * central differences (w(+1) - w(-1)) / (2 h_l) at each cell's level with
- * the neighbour values of the rules above (exact for linear data), added x
- * then y.  An approximate projection: it removes the divergence up to what
+ * the neighbour values of the rules above (exact for linear data), added x,
+ * y then z.  An approximate projection: it removes the divergence up to what
  * the compact lap and div(grad) disagree on (O(h^2) away from coarse-fine
  * faces, O(1) next to them).  div_before, div_after (host, may be NULL)
- * receive max |div B| before and after; cycles the V-cycle count.
- * AMRV_ENOTSUP on a 3D forest. */
-int amrv_fmg_divb_project(amrv_fmg* m, double* bx, double* by, double tol, int32_t max_cycles, int32_t* cycles,
-                          double* div_before, double* div_after);
+ * receive max |div B| before and after; cycles the V-cycle count. */
+int amrv_fmg_divb_project(amrv_fmg* m, double* bx, double* by, double* bz, double tol, int32_t max_cycles,
+                          int32_t* cycles, double* div_before, double* div_after);
 
 #ifdef __cplusplus
 }

@@ -169,7 +169,7 @@ SIGNATURES = {
     "amrv_fmg_rd_step": ([P, ctypes.POINTER(RdParams), ctypes.c_int32, ctypes.c_double, ctypes.c_int32, P, P,
                           ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                           ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
-    "amrv_fmg_divb_project": ([P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+    "amrv_fmg_divb_project": ([P, P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "amrv_last_error": ([], ctypes.c_char_p),
 }

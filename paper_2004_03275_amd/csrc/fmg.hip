@@ -565,11 +565,9 @@ __global__ void __launch_bounds__(WG) k_fmg_diff(FmgDev g, const int* leafblk, i
   }
 }
 
-__global__ void k_fmg_sub2(long long n, double* a, const double* da, double* b, const double* db) {
+__global__ void k_fmg_sub(long long n, double* a, const double* da) {
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  a[t] = a[t] - da[t];
-  b[t] = b[t] - db[t];
+  if (t < n) a[t] = a[t] - da[t];
 }
 
 __global__ void k_fmg_zero(long long n, double* a) {
@@ -1210,21 +1208,21 @@ int amrv_fmg_rd_step(amrv_fmg* m, const amrv_rd_params* p, int32_t scheme, doubl
   return 0;
 }
 
-int amrv_fmg_divb_project(amrv_fmg* m, double* bx, double* by, double tol, int32_t max_cycles, int32_t* cycles,
-                          double* div_before, double* div_after) {
-  if (!m || !bx || !by) return set_error(AMRV_EINVAL, "null argument");
+int amrv_fmg_divb_project(amrv_fmg* m, double* bx, double* by, double* bz, double tol, int32_t max_cycles,
+                          int32_t* cycles, double* div_before, double* div_after) {
+  if (!m || !bx || !by || (m->nd == 3 && !bz)) return set_error(AMRV_EINVAL, "null argument");
   if (!(tol > 0.0) || max_cycles < 0) return set_error(AMRV_EINVAL, "bad tol or max_cycles");
-  if (m->nd != 2) return set_error(AMRV_ENOTSUP, "the forest divergence control is 2D");
   const long long n = (long long)m->cfg.nleaves * m->ncb;
   const int nb = (int)((n + 255) / 256);
   const int nl = (int)m->cfg.nleaves;
   double* const* T = m->tmp;
-  // the central divergence of (bx, by) into out
+  double* const B[3] = {bx, by, bz};
+  // the central divergence of B into out, directions added x, y (, z)
   auto div = [&](double* out) {
-    FMG_LAUNCH(k_fmg_load, nl, WG, m->g, m->leafblk, bx);
-    FMG_LAUNCH(k_fmg_diff, nl, WG, m->g, m->leafblk, 0, 0, out);
-    FMG_LAUNCH(k_fmg_load, nl, WG, m->g, m->leafblk, by);
-    FMG_LAUNCH(k_fmg_diff, nl, WG, m->g, m->leafblk, 1, 1, out);
+    for (int d = 0; d < m->nd; d++) {
+      FMG_LAUNCH(k_fmg_load, nl, WG, m->g, m->leafblk, B[d]);
+      FMG_LAUNCH(k_fmg_diff, nl, WG, m->g, m->leafblk, d, d > 0 ? 1 : 0, out);
+    }
   };
   auto maxabs = [&](const double* v, double* out) -> int {
     hipLaunchKernelGGL(k_fmg_zero2, dim3(1), dim3(64), 0, m->st, m->red);
@@ -1244,9 +1242,8 @@ int amrv_fmg_divb_project(amrv_fmg* m, double* bx, double* by, double tol, int32
   const int rc = amrv_fmg_solve(m, T[0], T[1], 0.0, tol, max_cycles, cycles, nullptr, nullptr);
   if (rc) return rc;
   FMG_LAUNCH(k_fmg_load, nl, WG, m->g, m->leafblk, T[1]);
-  FMG_LAUNCH(k_fmg_diff, nl, WG, m->g, m->leafblk, 0, 0, T[2]);
-  FMG_LAUNCH(k_fmg_diff, nl, WG, m->g, m->leafblk, 1, 0, T[3]);
-  hipLaunchKernelGGL(k_fmg_sub2, dim3(nb), dim3(256), 0, m->st, n, bx, T[2], by, T[3]);
+  for (int d = 0; d < m->nd; d++) FMG_LAUNCH(k_fmg_diff, nl, WG, m->g, m->leafblk, d, 0, T[2 + d]);
+  for (int d = 0; d < m->nd; d++) hipLaunchKernelGGL(k_fmg_sub, dim3(nb), dim3(256), 0, m->st, n, B[d], T[2 + d]);
   FMGCHK(hipGetLastError());
   if (div_after) {
     div(T[0]);

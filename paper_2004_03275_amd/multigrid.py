@@ -180,7 +180,8 @@ class GpuForestMultigrid:
         nbytes = fmg_workspace_bytes(forest, length, bc)
         self.device = torch.device(device)
         self.nleaves = forest.n
-        self.ncb = 16 ** forest.scheme.ndim
+        self.ndim = forest.scheme.ndim
+        self.ncb = 16 ** self.ndim
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -243,10 +244,12 @@ class GpuForestMultigrid:
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
         return cyc.value, res.value
 
-    def divb_project(self, bx: torch.Tensor, by: torch.Tensor, tol: float = 1e-10, max_cycles: int = 50):
-        """The divergence control of Sec. 2.4 on the leaf fields bx, by
+    def divb_project(self, *B: torch.Tensor, tol: float = 1e-10, max_cycles: int = 50):
+        """The divergence control of Sec. 2.4 on the ndim leaf fields B
         (updated in place).  Returns (cycles, max |div B| before, after)."""
-        for t in (bx, by):
+        if len(B) != self.ndim:
+            raise ValueError(f"expected {self.ndim} field components, got {len(B)}")
+        for t in B:
             if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
                 raise ValueError("expected contiguous float64 device tensors")
             if t.numel() != self.nleaves * self.ncb:
@@ -254,7 +257,8 @@ class GpuForestMultigrid:
         cyc = ctypes.c_int32()
         before, after = ctypes.c_double(), ctypes.c_double()
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
-        N.check(N.lib().amrv_fmg_divb_project(self._h, ctypes.c_void_p(bx.data_ptr()), ctypes.c_void_p(by.data_ptr()),
+        ptr = [ctypes.c_void_p(t.data_ptr()) for t in B] + [None]
+        N.check(N.lib().amrv_fmg_divb_project(self._h, ptr[0], ptr[1], ptr[2],
                                               float(tol), int(max_cycles), ctypes.byref(cyc), ctypes.byref(before),
                                               ctypes.byref(after)))
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
@@ -262,12 +266,12 @@ class GpuForestMultigrid:
 
 
 def project_forest_b(g, fm: GpuForestMultigrid, ib: int, tol: float = 1e-10, max_cycles: int = 50):
-    """The divergence control of Sec. 2.4 on a 2D forest's state: B (state
-    variables ib, ib + 1, each a [leaf][16][16] field) projected in place by
+    """The divergence control of Sec. 2.4 on a forest's state: B (state
+    variables ib .. ib + ndim - 1, each a [leaf] + [16] * ndim field) projected in place by
     the forest solver fm built on the same leaves (g: forest.GpuForest).  The
     state moves device to device only.  Returns (cycles, max |div B| before,
     after)."""
     U = g.state_tensor()
-    out = fm.divb_project(U[ib], U[ib + 1], tol=tol, max_cycles=max_cycles)
+    out = fm.divb_project(*[U[ib + d] for d in range(fm.ndim)], tol=tol, max_cycles=max_cycles)
     g.set_state(U)
     return out
