@@ -204,6 +204,45 @@ __host__ __device__ inline void stencil(const FmgDev& g, int b, bool leaf, const
   }
 }
 
+// stencil for K cells of block b at once, the same sums in the same order:
+// every in-block neighbour load (the index clamped into the block; a lane
+// whose neighbour lies outside reads its own cell and discards it) is issued
+// before any face outside the block is resolved, so the K cells' loads are in
+// flight together instead of one cell's after another's
+template <int ND, int K>
+__host__ __device__ inline void stencil_k(const FmgDev& g, int b, bool leaf, const int (*c)[3], double* sc,
+                                          double* sw) {
+  const double* ub = g.u + (size_t)b * ncb<ND>();
+  double v[K][2 * ND];
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+#pragma unroll
+    for (int face = 0; face < 2 * ND; face++) {
+      int cn[3] = {c[k][0], c[k][1], c[k][2]};
+      const int x = cn[face >> 1] + ((face & 1) ? 1 : -1);
+      cn[face >> 1] = x < 0 ? 0 : (x > NB - 1 ? NB - 1 : x);
+      v[k][face] = ub[cidx(cn)];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    sc[k] = 0.0;
+    sw[k] = 0.0;
+#pragma unroll
+    for (int face = 0; face < 2 * ND; face++) {
+      const int x = c[k][face >> 1] + ((face & 1) ? 1 : -1);
+      if (x >= 0 && x < NB) {
+        sc[k] += v[k][face];
+      } else {
+        double cv, w;
+        across<ND>(g, b, leaf, c[k], face, cv, w);
+        sc[k] += cv;
+        sw[k] += w;
+      }
+    }
+  }
+}
+
 // Every kernel below applies one per-cell function (host-callable too, so a
 // host loop over the same functions checks a cycle on the CPU); a 256-thread
 // workgroup walks a block plane by plane, thread t at (t & 15, t >> 4).
@@ -306,7 +345,7 @@ __host__ __device__ inline void fas_cell(const FmgDev& g, int b, const int* c) {
 // from the parent cell and its neighbours toward the fine cell, the parent's
 // own cell where that neighbour lies outside the parent
 template <int ND>
-__host__ __device__ inline void prolong_cell(const FmgDev& g, int b, const int* c) {
+__host__ __device__ inline double prolong_delta(const FmgDev& g, int b, const int* c) {
   constexpr int NCB = ncb<ND>();
   const int p = g.par[b];
   int I[3] = {0, 0, 0}, I2[3] = {0, 0, 0};
@@ -331,7 +370,12 @@ __host__ __device__ inline void prolong_cell(const FmgDev& g, int b, const int* 
          3.0 * (e(1, 1, 0) + e(1, 0, 1) + e(0, 1, 1)) + e(1, 1, 1)) *
         (1.0 / 64.0);
   }
-  g.u[(size_t)b * NCB + cidx(c)] += d;
+  return d;
+}
+
+template <int ND>
+__host__ __device__ inline void prolong_cell(const FmgDev& g, int b, const int* c) {
+  g.u[(size_t)b * ncb<ND>() + cidx(c)] += prolong_delta<ND>(g, b, c);
 }
 
 // index of cell c of level-1 block b in the n^ND grid
@@ -367,20 +411,73 @@ __global__ void __launch_bounds__(WG) k_fmg_smooth(FmgDev g, int b0, int colour)
     const int c[3] = {tx, ty, 0};
     if (((tx + ty) & 1) == colour) smooth_cell<2>(g, b0 + blockIdx.x, c);
   } else {
+    // the cells of four plane pairs at a time (stencil_k): the same update
+    // as smooth_cell, its loads batched
+    constexpr int K = 4;
     const int hx = threadIdx.x & 7, ty = (threadIdx.x >> 3) & (NB - 1), pz = threadIdx.x >> 7;
-    for (int z0 = 0; z0 < NB; z0 += 2) {
-      const int tz = z0 + pz;
-      const int c[3] = {2 * hx + ((ty + tz + colour) & 1), ty, tz};
-      smooth_cell<3>(g, b0 + blockIdx.x, c);
+    const int b = b0 + blockIdx.x;
+    const double ih2 = g.ih2[g.lvl[b]];
+    for (int z0 = 0; z0 < NB; z0 += 2 * K) {
+      int c[K][3];
+      size_t i[K];
+      double fv[K], sc[K], sw[K];
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        const int tz = z0 + 2 * k + pz;
+        c[k][0] = 2 * hx + ((ty + tz + colour) & 1);
+        c[k][1] = ty;
+        c[k][2] = tz;
+        i[k] = (size_t)b * ncb<3>() + cidx(c[k]);
+        fv[k] = g.f[i[k]];
+      }
+      stencil_k<3, K>(g, b, false, c, sc, sw);
+#pragma unroll
+      for (int k = 0; k < K; k++) g.u[i[k]] = (fv[k] - ih2 * sc[k]) / (ih2 * (sw[k] - 2.0 * 3) - g.lam);
     }
   }
 }
 
+// lap(u) - lambda u at K cells of block b (u their values): apply_cell's
+// arithmetic with the loads batched as in stencil_k
+template <int ND, int K>
+__host__ __device__ inline void apply_k(const FmgDev& g, int b, bool leaf, const int (*c)[3], const double* u,
+                                        double* out) {
+  double sc[K], sw[K];
+  stencil_k<ND, K>(g, b, leaf, c, sc, sw);
+  const double ih2 = g.ih2[g.lvl[b]];
+#pragma unroll
+  for (int k = 0; k < K; k++) out[k] = ih2 * (sc[k] + sw[k] * u[k] - (2.0 * ND) * u[k]) - g.lam * u[k];
+}
+
 template <int ND>
 __global__ void __launch_bounds__(WG) k_fmg_resid(FmgDev g, int b0) {
-  FMG_PLANES(ND) {
-    const int c[3] = {tx, ty, tz};
-    resid_cell<ND>(g, b0 + blockIdx.x, c);
+  if constexpr (ND == 2) {
+    FMG_PLANES(ND) {
+      const int c[3] = {tx, ty, tz};
+      resid_cell<ND>(g, b0 + blockIdx.x, c);
+    }
+  } else {
+    // four planes at a time (apply_k)
+    constexpr int K = 4;
+    const int tx = threadIdx.x & (NB - 1), ty = threadIdx.x >> 4;
+    const int b = b0 + blockIdx.x;
+    for (int z0 = 0; z0 < NB; z0 += K) {
+      int c[K][3];
+      size_t i[K];
+      double fv[K], uv[K], a[K];
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        c[k][0] = tx;
+        c[k][1] = ty;
+        c[k][2] = z0 + k;
+        i[k] = (size_t)b * ncb<3>() + cidx(c[k]);
+        fv[k] = g.f[i[k]];
+        uv[k] = g.u[i[k]];
+      }
+      apply_k<3, K>(g, b, false, c, uv, a);
+#pragma unroll
+      for (int k = 0; k < K; k++) g.r[i[k]] = fv[k] - a[k];
+    }
   }
 }
 
@@ -389,8 +486,80 @@ __global__ void __launch_bounds__(WG) k_fmg_restrict(FmgDev g, int b0) {
   for (int t = threadIdx.x; t < (ND == 3 ? 512 : 64); t += blockDim.x) restrict_cell<ND>(g, b0 + blockIdx.x, t);
 }
 
+// a parent block in 3D: L(u) + r (fas_cell's first case) four planes at a
+// time (apply_k)
+__device__ inline void fas_parent_3d(const FmgDev& g, int b) {
+  constexpr int K = 4;
+  const int tx = threadIdx.x & (NB - 1), ty = threadIdx.x >> 4;
+  for (int z0 = 0; z0 < NB; z0 += K) {
+    int c[K][3];
+    size_t i[K];
+    double rv[K], uv[K], a[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      c[k][0] = tx;
+      c[k][1] = ty;
+      c[k][2] = z0 + k;
+      i[k] = (size_t)b * ncb<3>() + cidx(c[k]);
+      rv[k] = g.r[i[k]];
+      uv[k] = g.u[i[k]];
+    }
+    apply_k<3, K>(g, b, false, c, uv, a);
+#pragma unroll
+    for (int k = 0; k < K; k++) g.f[i[k]] = a[k] + rv[k];
+  }
+}
+
+// a leaf block below the finest level in 3D (fas_cell's other cases): f
+// copied from the problem's f where no same-level neighbour is refined, else
+// lp + (f - lc) with both stencils, four planes at a time
+__device__ inline void fas_leaf_3d(const FmgDev& g, int b) {
+  const int tx = threadIdx.x & (NB - 1), ty = threadIdx.x >> 4;
+  const size_t base = (size_t)b * ncb<3>() + tx + NB * ty;
+  bool refined = false;  // uniform per workgroup
+#pragma unroll
+  for (int face = 0; face < 6; face++) {
+    const int nb = g.nbr[FS * b + face];
+    refined = refined || (nb >= 0 && g.chi[CS * nb] >= 0);
+  }
+  if (!refined) {
+    double v[NB];
+#pragma unroll
+    for (int z = 0; z < NB; z++) v[z] = g.fu[base + (size_t)NB * NB * z];
+#pragma unroll
+    for (int z = 0; z < NB; z++) g.f[base + (size_t)NB * NB * z] = v[z];
+    return;
+  }
+  constexpr int K = 4;
+  for (int z0 = 0; z0 < NB; z0 += K) {
+    int c[K][3];
+    double fv[K], uv[K], lp[K], lc[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      c[k][0] = tx;
+      c[k][1] = ty;
+      c[k][2] = z0 + k;
+      fv[k] = g.fu[base + (size_t)NB * NB * (z0 + k)];
+      uv[k] = g.u[base + (size_t)NB * NB * (z0 + k)];
+    }
+    apply_k<3, K>(g, b, false, c, uv, lp);
+    apply_k<3, K>(g, b, true, c, uv, lc);
+#pragma unroll
+    for (int k = 0; k < K; k++)
+      g.f[base + (size_t)NB * NB * (z0 + k)] = lp[k] == lc[k] ? fv[k] : lp[k] + (fv[k] - lc[k]);
+  }
+}
+
 template <int ND>
 __global__ void __launch_bounds__(WG) k_fmg_fas(FmgDev g, int b0) {
+  if constexpr (ND == 3) {
+    const int b = b0 + blockIdx.x;
+    if (g.chi[CS * b] >= 0)
+      fas_parent_3d(g, b);
+    else
+      fas_leaf_3d(g, b);
+    return;
+  }
   FMG_PLANES(ND) {
     const int c[3] = {tx, ty, tz};
     fas_cell<ND>(g, b0 + blockIdx.x, c);
@@ -399,9 +568,30 @@ __global__ void __launch_bounds__(WG) k_fmg_fas(FmgDev g, int b0) {
 
 template <int ND>
 __global__ void __launch_bounds__(WG) k_fmg_prolong(FmgDev g, int b0) {
-  FMG_PLANES(ND) {
-    const int c[3] = {tx, ty, tz};
-    prolong_cell<ND>(g, b0 + blockIdx.x, c);
+  if constexpr (ND == 2) {
+    FMG_PLANES(ND) {
+      const int c[3] = {tx, ty, tz};
+      prolong_cell<ND>(g, b0 + blockIdx.x, c);
+    }
+  } else {
+    // four planes at a time: the parent's values (shared by neighbouring
+    // planes) and the cells' own values loaded before any store
+    constexpr int K = 4;
+    const int tx = threadIdx.x & (NB - 1), ty = threadIdx.x >> 4;
+    const int b = b0 + blockIdx.x;
+    for (int z0 = 0; z0 < NB; z0 += K) {
+      double d[K], uv[K];
+      size_t i[K];
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        const int c[3] = {tx, ty, z0 + k};
+        i[k] = (size_t)b * ncb<3>() + cidx(c);
+        uv[k] = g.u[i[k]];
+        d[k] = prolong_delta<3>(g, b, c);
+      }
+#pragma unroll
+      for (int k = 0; k < K; k++) g.u[i[k]] = uv[k] + d[k];
+    }
   }
 }
 
@@ -444,12 +634,39 @@ __global__ void __launch_bounds__(WG) k_fmg_resmax(FmgDev g, unsigned long long*
   const int b = blockIdx.x;
   if (g.chi[CS * b] >= 0) return;  // uniform per workgroup
   double mr = 0.0, mf = 0.0;
-  FMG_PLANES(ND) {
-    const int c[3] = {tx, ty, tz};
-    const double r = residual<ND>(g, b, c);
-    const double f = g.fu[(size_t)b * ncb<ND>() + cidx(c)];
-    mr = fmax(mr, isnan(r) ? INFINITY : fabs(r));
-    mf = fmax(mf, isnan(f) ? INFINITY : fabs(f));
+  if constexpr (ND == 2) {
+    FMG_PLANES(ND) {
+      const int c[3] = {tx, ty, tz};
+      const double r = residual<ND>(g, b, c);
+      const double f = g.fu[(size_t)b * ncb<ND>() + cidx(c)];
+      mr = fmax(mr, isnan(r) ? INFINITY : fabs(r));
+      mf = fmax(mf, isnan(f) ? INFINITY : fabs(f));
+    }
+  } else {
+    // residual() four planes at a time (stencil_k with the problem's rules)
+    constexpr int K = 4;
+    const int tx = threadIdx.x & (NB - 1), ty = threadIdx.x >> 4;
+    const double ih2 = g.ih2[g.lvl[b]];
+    for (int z0 = 0; z0 < NB; z0 += K) {
+      int c[K][3];
+      double fv[K], uv[K], sc[K], sw[K];
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        c[k][0] = tx;
+        c[k][1] = ty;
+        c[k][2] = z0 + k;
+        const size_t i = (size_t)b * ncb<3>() + cidx(c[k]);
+        fv[k] = g.fu[i];
+        uv[k] = g.u[i];
+      }
+      stencil_k<3, K>(g, b, true, c, sc, sw);
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        const double r = fv[k] - (ih2 * (sc[k] + sw[k] * uv[k] - (2.0 * 3) * uv[k]) - g.lam * uv[k]);
+        mr = fmax(mr, isnan(r) ? INFINITY : fabs(r));
+        mf = fmax(mf, isnan(fv[k]) ? INFINITY : fabs(fv[k]));
+      }
+    }
   }
   fold_max(mr, out);
   if (with_f) {
