@@ -205,23 +205,33 @@ __host__ __device__ inline void stencil(const FmgDev& g, int b, bool leaf, const
 }
 
 // stencil for K cells of block b at once, the same sums in the same order:
-// every in-block neighbour load (the index clamped into the block; a lane
-// whose neighbour lies outside reads its own cell and discards it) is issued
-// before any face outside the block is resolved, so the K cells' loads are in
-// flight together instead of one cell's after another's
+// every neighbour load that needs no rule (a cell of this block, or of a
+// same-level neighbour block whose own cell stands in: the face type is
+// uniform per block, so a lane on the face only changes the address) is
+// issued before any other face is resolved, so the K cells' loads are in
+// flight together; the lanes on a wall or coarse-fine face then take across()
 template <int ND, int K>
 __host__ __device__ inline void stencil_k(const FmgDev& g, int b, bool leaf, const int (*c)[3], double* sc,
                                           double* sw) {
-  const double* ub = g.u + (size_t)b * ncb<ND>();
+  constexpr int NCB = ncb<ND>();
   double v[K][2 * ND];
+  bool rule[2 * ND];  // the face needs across() for the lanes on it
 #pragma unroll
-  for (int k = 0; k < K; k++) {
+  for (int face = 0; face < 2 * ND; face++) {
+    const int d = face >> 1, s1 = (face & 1) ? 1 : -1;
+    const int nb = g.nbr[FS * b + face];
+    const bool plain = nb >= 0 && (!leaf || g.chi[CS * nb] < 0);
+    rule[face] = !plain;
 #pragma unroll
-    for (int face = 0; face < 2 * ND; face++) {
+    for (int k = 0; k < K; k++) {
       int cn[3] = {c[k][0], c[k][1], c[k][2]};
-      const int x = cn[face >> 1] + ((face & 1) ? 1 : -1);
-      cn[face >> 1] = x < 0 ? 0 : (x > NB - 1 ? NB - 1 : x);
-      v[k][face] = ub[cidx(cn)];
+      const int x = cn[d] + s1;
+      const bool out = x < 0 || x > NB - 1;
+      // in the block: the neighbour; out with a plain face: the neighbour
+      // block's cell; out otherwise: the cell itself (discarded)
+      cn[d] = out ? (plain ? (s1 > 0 ? 0 : NB - 1) : cn[d]) : x;
+      const int blk = out && plain ? nb : b;
+      v[k][face] = g.u[(size_t)blk * NCB + cidx(cn)];
     }
   }
 #pragma unroll
@@ -231,7 +241,7 @@ __host__ __device__ inline void stencil_k(const FmgDev& g, int b, bool leaf, con
 #pragma unroll
     for (int face = 0; face < 2 * ND; face++) {
       const int x = c[k][face >> 1] + ((face & 1) ? 1 : -1);
-      if (x >= 0 && x < NB) {
+      if ((x >= 0 && x < NB) || !rule[face]) {
         sc[k] += v[k][face];
       } else {
         double cv, w;
@@ -417,7 +427,8 @@ __global__ void __launch_bounds__(WG) k_fmg_smooth(FmgDev g, int b0, int colour)
     const int hx = threadIdx.x & 7, ty = (threadIdx.x >> 3) & (NB - 1), pz = threadIdx.x >> 7;
     const int b = b0 + blockIdx.x;
     const double ih2 = g.ih2[g.lvl[b]];
-    for (int z0 = 0; z0 < NB; z0 += 2 * K) {
+    const int span = NB / gridDim.y;  // the planes of this workgroup's part of the block
+    for (int z0 = blockIdx.y * span; z0 < (int)(blockIdx.y + 1) * span; z0 += 2 * K) {
       int c[K][3];
       size_t i[K];
       double fv[K], sc[K], sw[K];
@@ -461,7 +472,8 @@ __global__ void __launch_bounds__(WG) k_fmg_resid(FmgDev g, int b0) {
     constexpr int K = 4;
     const int tx = threadIdx.x & (NB - 1), ty = threadIdx.x >> 4;
     const int b = b0 + blockIdx.x;
-    for (int z0 = 0; z0 < NB; z0 += K) {
+    const int span = NB / gridDim.y;
+    for (int z0 = blockIdx.y * span; z0 < (int)(blockIdx.y + 1) * span; z0 += K) {
       int c[K][3];
       size_t i[K];
       double fv[K], uv[K], a[K];
@@ -491,7 +503,8 @@ __global__ void __launch_bounds__(WG) k_fmg_restrict(FmgDev g, int b0) {
 __device__ inline void fas_parent_3d(const FmgDev& g, int b) {
   constexpr int K = 4;
   const int tx = threadIdx.x & (NB - 1), ty = threadIdx.x >> 4;
-  for (int z0 = 0; z0 < NB; z0 += K) {
+  const int span = NB / gridDim.y;
+  for (int z0 = blockIdx.y * span; z0 < (int)(blockIdx.y + 1) * span; z0 += K) {
     int c[K][3];
     size_t i[K];
     double rv[K], uv[K], a[K];
@@ -522,16 +535,20 @@ __device__ inline void fas_leaf_3d(const FmgDev& g, int b) {
     const int nb = g.nbr[FS * b + face];
     refined = refined || (nb >= 0 && g.chi[CS * nb] >= 0);
   }
+  constexpr int K = 4;
+  const int span = NB / gridDim.y;
+  const int zlo = blockIdx.y * span, zhi = zlo + span;
   if (!refined) {
-    double v[NB];
+    for (int z0 = zlo; z0 < zhi; z0 += K) {
+      double v[K];
 #pragma unroll
-    for (int z = 0; z < NB; z++) v[z] = g.fu[base + (size_t)NB * NB * z];
+      for (int k = 0; k < K; k++) v[k] = g.fu[base + (size_t)NB * NB * (z0 + k)];
 #pragma unroll
-    for (int z = 0; z < NB; z++) g.f[base + (size_t)NB * NB * z] = v[z];
+      for (int k = 0; k < K; k++) g.f[base + (size_t)NB * NB * (z0 + k)] = v[k];
+    }
     return;
   }
-  constexpr int K = 4;
-  for (int z0 = 0; z0 < NB; z0 += K) {
+  for (int z0 = zlo; z0 < zhi; z0 += K) {
     int c[K][3];
     double fv[K], uv[K], lp[K], lc[K];
 #pragma unroll
@@ -1134,10 +1151,20 @@ int nblocks(const amrv_fmg* m, int l) { return m->T.lstart[l + 1] - m->T.lstart[
       hipLaunchKernelGGL((kern<3>), dim3(grid), dim3(block), 0, m->st, __VA_ARGS__); \
   } while (0)
 
+// the launch grid of a per-block kernel over level l: in 3D a level of few
+// blocks gives each block up to `parts` workgroups, each taking an equal
+// share of its planes, so that small levels still fill the chip
+dim3 level_grid(const amrv_fmg* m, int l, int parts) {
+  const int n = nblocks(m, l);
+  int s = 1;
+  while (m->nd == 3 && s < parts && (long long)n * s < 2048) s *= 2;
+  return dim3(n, s);
+}
+
 int sweeps(amrv_fmg* m, int l, int count) {
   for (int s = 0; s < count; s++)
     for (int c = 0; c < 2; c++)
-      FMG_LAUNCH(k_fmg_smooth, nblocks(m, l), WG, m->g, m->T.lstart[l], c);
+      FMG_LAUNCH(k_fmg_smooth, level_grid(m, l, 2), WG, m->g, m->T.lstart[l], c);
   FMGCHK(hipGetLastError());
   return 0;
 }
@@ -1148,14 +1175,14 @@ int vcycle(amrv_fmg* m) {
   const int pre = m->cfg.pre_sweeps, post = m->cfg.post_sweeps;
   for (int l = L; l >= 2; l--) {
     if (int rc = sweeps(m, l, pre)) return rc;
-    FMG_LAUNCH(k_fmg_resid, nblocks(m, l), WG, m->g, m->T.lstart[l]);
+    FMG_LAUNCH(k_fmg_resid, level_grid(m, l, 4), WG, m->g, m->T.lstart[l]);
     FMG_LAUNCH(k_fmg_restrict, nblocks(m, l), m->nd == 3 ? WG : 64, m->g, m->T.lstart[l]);
-    FMG_LAUNCH(k_fmg_fas, nblocks(m, l - 1), WG, m->g, m->T.lstart[l - 1]);
+    FMG_LAUNCH(k_fmg_fas, level_grid(m, l - 1, 4), WG, m->g, m->T.lstart[l - 1]);
     FMGCHK(hipGetLastError());
   }
   if (int rc = sweeps(m, 1, pre)) return rc;
   const int n = m->cfg.base * NB;
-  FMG_LAUNCH(k_fmg_resid, nblocks(m, 1), WG, m->g, m->T.lstart[1]);
+  FMG_LAUNCH(k_fmg_resid, level_grid(m, 1, 4), WG, m->g, m->T.lstart[1]);
   FMG_LAUNCH(k_fmg_to_grid, nblocks(m, 1), WG, m->g, m->T.lstart[1], n, m->fgrid, m->vgrid);
   FMGCHK(hipGetLastError());
   // the level-1 correction: one of the uniform solver's V-cycles from zero
