@@ -493,6 +493,44 @@ __global__ void __launch_bounds__(WG) k_fmg_resid(FmgDev g, int b0) {
   }
 }
 
+// 3D: a child block's residual restricted together with its state, so the
+// fine residual is never stored: parent cell t of the child's octant takes
+// the means of u and of f - L(u) (L the plain stencil) over its 8 cells,
+// restrict_cell's sums in its order, the residual as resid_cell's; on levels
+// of few blocks a block's 512 parent cells are split over gridDim.y
+// workgroups
+__global__ void __launch_bounds__(WG) k_fmg_resid_restrict3(FmgDev g, int b0) {
+  constexpr int NCB = ncb<3>();
+  const int b = b0 + blockIdx.x;
+  const int p = g.par[b];
+  const int q[3] = {g.ij[TS * b] & 1, g.ij[TS * b + 1] & 1, g.ij[TS * b + 2] & 1};
+  const int span = 512 / gridDim.y;
+  for (int t = blockIdx.y * span + threadIdx.x; t < (int)(blockIdx.y + 1) * span; t += WG) {
+    const int xx = t & 7, yy = (t >> 3) & 7, zz = t >> 6;
+    int c[8][3];
+    double uv[8], fv[8], a[8], r[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      c[k][0] = 2 * xx + (k & 1);
+      c[k][1] = 2 * yy + ((k >> 1) & 1);
+      c[k][2] = 2 * zz + (k >> 2);
+      const size_t i = (size_t)b * NCB + cidx(c[k]);
+      uv[k] = g.u[i];
+      fv[k] = g.f[i];
+    }
+    apply_k<3, 8>(g, b, false, c, uv, a);
+#pragma unroll
+    for (int k = 0; k < 8; k++) r[k] = fv[k] - a[k];
+    const double um = 0.125 * (((uv[0] + uv[1]) + (uv[2] + uv[3])) + ((uv[4] + uv[5]) + (uv[6] + uv[7])));
+    const double rm = 0.125 * (((r[0] + r[1]) + (r[2] + r[3])) + ((r[4] + r[5]) + (r[6] + r[7])));
+    const int pc[3] = {q[0] * 8 + xx, q[1] * 8 + yy, q[2] * 8 + zz};
+    const size_t ip = (size_t)p * NCB + cidx(pc);
+    g.u[ip] = um;
+    g.uo[ip] = um;
+    g.r[ip] = rm;
+  }
+}
+
 template <int ND>
 __global__ void __launch_bounds__(WG) k_fmg_restrict(FmgDev g, int b0) {
   for (int t = threadIdx.x; t < (ND == 3 ? 512 : 64); t += blockDim.x) restrict_cell<ND>(g, b0 + blockIdx.x, t);
@@ -1175,8 +1213,12 @@ int vcycle(amrv_fmg* m) {
   const int pre = m->cfg.pre_sweeps, post = m->cfg.post_sweeps;
   for (int l = L; l >= 2; l--) {
     if (int rc = sweeps(m, l, pre)) return rc;
-    FMG_LAUNCH(k_fmg_resid, level_grid(m, l, 4), WG, m->g, m->T.lstart[l]);
-    FMG_LAUNCH(k_fmg_restrict, nblocks(m, l), m->nd == 3 ? WG : 64, m->g, m->T.lstart[l]);
+    if (m->nd == 3) {
+      hipLaunchKernelGGL(k_fmg_resid_restrict3, level_grid(m, l, 2), dim3(WG), 0, m->st, m->g, m->T.lstart[l]);
+    } else {
+      FMG_LAUNCH(k_fmg_resid, nblocks(m, l), WG, m->g, m->T.lstart[l]);
+      FMG_LAUNCH(k_fmg_restrict, nblocks(m, l), 64, m->g, m->T.lstart[l]);
+    }
     FMG_LAUNCH(k_fmg_fas, level_grid(m, l - 1, 4), WG, m->g, m->T.lstart[l - 1]);
     FMGCHK(hipGetLastError());
   }

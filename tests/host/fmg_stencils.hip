@@ -1,6 +1,7 @@
 // Host check of the forest multigrid's batched stencils (csrc/fmg.hip): for
 // every block of a forest read from argv[1], stencil_k and apply_k (K = 4
-// cells, the batch layouts of the 3D sweep and of the residual kernels) give
+// cells, the batch layouts of the 3D sweep and of the residual kernels; K = 8,
+// the fused residual-restriction's 2x2x2 cube) give
 // the same sums, bit for bit, as stencil and apply_cell cell by cell, with
 // the plain stencil on every block and the problem's rules on the leaves.
 // Input: "nleaves base max_level bc ndim", then "level i j k" per leaf.
@@ -95,6 +96,22 @@ int main(int argc, char** argv) {
             bad += !same(apply_cell<3>(g, b, leaf != 0, cc[k]), a[k]);
           }
         }
+    // the fused residual-restriction's batch: the 8 cells of a parent cell
+    for (int t = 0; t < 512; t++) {
+      int cc[8][3];
+      double uv[8], a[8];
+      for (int k = 0; k < 8; k++) {
+        cc[k][0] = 2 * (t & 7) + (k & 1);
+        cc[k][1] = 2 * ((t >> 3) & 7) + ((k >> 1) & 1);
+        cc[k][2] = 2 * (t >> 6) + (k >> 2);
+        uv[k] = u[(size_t)b * NCB + cidx(cc[k])];
+      }
+      apply_k<3, 8>(g, b, false, cc, uv, a);
+      for (int k = 0; k < 8; k++) {
+        tot++;
+        bad += !same(apply_cell<3>(g, b, false, cc[k]), a[k]);
+      }
+    }
   }
   std::printf("blocks %d checked %lld mismatches %lld\n", T.nblk, tot, bad);
   return bad != 0;
