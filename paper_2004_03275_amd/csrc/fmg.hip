@@ -106,17 +106,21 @@ struct FmgDev {
 // a cell's index in its block, (x, y, z) with x fastest (z = 0 in 2D)
 __host__ __device__ inline int cidx(const int* c) { return c[0] + NB * (c[1] + NB * c[2]); }
 
+// a neighbour value in the form cv + w u(c)
+struct Across {
+  double cv, w;
+};
+
 // the value across face `face` (2d: -d, 2d + 1: +d) of cell c of block b, as
-// cv + w u(c) (host-callable too, for checks of the tables on the CPU)
+// cv + w u(c) (host-callable too, for checks of the tables on the CPU); the
+// pair is returned by value: written through references, the compiler kept
+// it in private memory, whose reload waits for every load in flight
 template <int ND>
-__host__ __device__ inline void across(const FmgDev& g, int b, bool leaf, const int* c, int face, double& cv,
-                                       double& w) {
+__host__ __device__ inline Across across(const FmgDev& g, int b, bool leaf, const int* c, int face) {
   constexpr int NCB = ncb<ND>();
   const int nb = g.nbr[FS * b + face];
   if (nb == NBR_WALL) {
-    cv = 0.0;
-    w = 1.0;
-    return;
+    return {0.0, 1.0};
   }
   const int d = face >> 1;
   const bool lo = (face & 1) == 0;
@@ -125,9 +129,7 @@ __host__ __device__ inline void across(const FmgDev& g, int b, bool leaf, const 
   if (nb >= 0) {
     const int* ch = g.chi + CS * nb;
     if (!leaf || ch[0] < 0) {
-      cv = g.u[(size_t)nb * NCB + cidx(C)];
-      w = 0.0;
-      return;
+      return {g.u[(size_t)nb * NCB + cidx(C)], 0.0};
     }
     // the coarse side: the 2^(ND-1) fine cells of the neighbour's children
     // that touch the face, in its grid of 32^ND child cells
@@ -149,9 +151,7 @@ __host__ __device__ inline void across(const FmgDev& g, int b, bool leaf, const 
       const int Fl[3] = {F[0] & (NB - 1), F[1] & (NB - 1), F[2] & (NB - 1)};
       s += g.u[(size_t)fb * NCB + cidx(Fl)];
     }
-    cv = ((4.0 / 3.0) / (1 << (ND - 1))) * s;
-    w = -1.0 / 3.0;
-    return;
+    return {((4.0 / 3.0) / (1 << (ND - 1))) * s, -1.0 / 3.0};
   }
   // the fine side: the coarser leaf across the face, its cell moved a quarter
   // cell toward this one along each tangential direction
@@ -179,29 +179,33 @@ __host__ __device__ inline void across(const FmgDev& g, int b, bool leaf, const 
       slope = 0.5 * p[st] - 0.5 * p[-st];
     val += ((gc[e] & 1) ? 0.25 : -0.25) * slope;
   }
-  cv = (2.0 / 3.0) * val;
-  w = 1.0 / 3.0;
+  return {(2.0 / 3.0) * val, 1.0 / 3.0};
 }
 
 // the neighbour sums of cell c of block b: sum of the 2 ND values as sc + sw u(c)
 template <int ND>
 __host__ __device__ inline void stencil(const FmgDev& g, int b, bool leaf, const int* c, double& sc, double& sw) {
   const double* ub = g.u + (size_t)b * ncb<ND>();
-  sc = 0.0;
-  sw = 0.0;
+  // local sums, each face's value selected (not the address it is added
+  // to), so both stay in registers
+  double s = 0.0, ws = 0.0;
 #pragma unroll
   for (int face = 0; face < 2 * ND; face++) {
     int cn[3] = {c[0], c[1], c[2]};
     cn[face >> 1] += (face & 1) ? 1 : -1;
+    double av, aw = 0.0;
     if (cn[face >> 1] >= 0 && cn[face >> 1] < NB) {
-      sc += ub[cidx(cn)];
+      av = ub[cidx(cn)];
     } else {
-      double cv, w;
-      across<ND>(g, b, leaf, c, face, cv, w);
-      sc += cv;
-      sw += w;
+      const Across a = across<ND>(g, b, leaf, c, face);
+      av = a.cv;
+      aw = a.w;
     }
+    s += av;
+    ws += aw;
   }
+  sc = s;
+  sw = ws;
 }
 
 // stencil for K cells of block b at once, the same sums in the same order:
@@ -236,20 +240,21 @@ __host__ __device__ inline void stencil_k(const FmgDev& g, int b, bool leaf, con
   }
 #pragma unroll
   for (int k = 0; k < K; k++) {
-    sc[k] = 0.0;
-    sw[k] = 0.0;
+    double s = 0.0, ws = 0.0;  // as in stencil
 #pragma unroll
     for (int face = 0; face < 2 * ND; face++) {
       const int x = c[k][face >> 1] + ((face & 1) ? 1 : -1);
-      if ((x >= 0 && x < NB) || !rule[face]) {
-        sc[k] += v[k][face];
-      } else {
-        double cv, w;
-        across<ND>(g, b, leaf, c[k], face, cv, w);
-        sc[k] += cv;
-        sw[k] += w;
+      double av = v[k][face], aw = 0.0;
+      if (!((x >= 0 && x < NB) || !rule[face])) {
+        const Across a = across<ND>(g, b, leaf, c[k], face);
+        av = a.cv;
+        aw = a.w;
       }
+      s += av;
+      ws += aw;
     }
+    sc[k] = s;
+    sw[k] = ws;
   }
 }
 
@@ -817,9 +822,8 @@ __host__ __device__ inline double face_value(const FmgDev& g, int b, const int* 
   int cn[3] = {c[0], c[1], c[2]};
   cn[face >> 1] += (face & 1) ? 1 : -1;
   if (cn[face >> 1] >= 0 && cn[face >> 1] < NB) return g.u[(size_t)b * NCB + cidx(cn)];
-  double cv, w;
-  across<ND>(g, b, true, c, face, cv, w);
-  return cv + w * g.u[(size_t)b * NCB + cidx(c)];
+  const Across a = across<ND>(g, b, true, c, face);
+  return a.cv + a.w * g.u[(size_t)b * NCB + cidx(c)];
 }
 
 // central difference along d of the loaded leaf field: (w(+1) - w(-1)) (n_l / 2L),
