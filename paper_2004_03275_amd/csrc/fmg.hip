@@ -412,6 +412,15 @@ __host__ __device__ inline void to_grid_cell(const FmgDev& g, int b, const int* 
   vgrid[gi] = 0.0;
 }
 
+// the block a workgroup of a 3D launch over n blocks takes: workgroups are
+// dealt to the 8 XCDs round robin (workgroup i to XCD i % 8), so each XCD is
+// given a contiguous range of the blocks instead, and blocks next to each
+// other in the tree's order read each other's faces through one L2
+__device__ inline int xcd_block(int i, int n) {
+  const int q = n >> 3, r = n & 7, x = i & 7;
+  return x * q + (x < r ? x : r) + (i >> 3);
+}
+
 #define FMG_PLANES(ND)                                        \
   const int tx = threadIdx.x & (NB - 1), ty = threadIdx.x >> 4; \
   for (int tz = 0; tz < nplanes<ND>(); tz++)
@@ -430,7 +439,7 @@ __global__ void __launch_bounds__(WG) k_fmg_smooth(FmgDev g, int b0, int colour)
     // as smooth_cell, its loads batched
     constexpr int K = 4;
     const int hx = threadIdx.x & 7, ty = (threadIdx.x >> 3) & (NB - 1), pz = threadIdx.x >> 7;
-    const int b = b0 + blockIdx.x;
+    const int b = b0 + xcd_block(blockIdx.x, gridDim.x);
     const double ih2 = g.ih2[g.lvl[b]];
     const int span = NB / gridDim.y;  // the planes of this workgroup's part of the block
     for (int z0 = blockIdx.y * span; z0 < (int)(blockIdx.y + 1) * span; z0 += 2 * K) {
@@ -476,7 +485,7 @@ __global__ void __launch_bounds__(WG) k_fmg_resid(FmgDev g, int b0) {
     // four planes at a time (apply_k)
     constexpr int K = 4;
     const int tx = threadIdx.x & (NB - 1), ty = threadIdx.x >> 4;
-    const int b = b0 + blockIdx.x;
+    const int b = b0 + xcd_block(blockIdx.x, gridDim.x);
     const int span = NB / gridDim.y;
     for (int z0 = blockIdx.y * span; z0 < (int)(blockIdx.y + 1) * span; z0 += K) {
       int c[K][3];
@@ -506,7 +515,7 @@ __global__ void __launch_bounds__(WG) k_fmg_resid(FmgDev g, int b0) {
 // workgroups
 __global__ void __launch_bounds__(WG) k_fmg_resid_restrict3(FmgDev g, int b0) {
   constexpr int NCB = ncb<3>();
-  const int b = b0 + blockIdx.x;
+  const int b = b0 + xcd_block(blockIdx.x, gridDim.x);
   const int p = g.par[b];
   const int q[3] = {g.ij[TS * b] & 1, g.ij[TS * b + 1] & 1, g.ij[TS * b + 2] & 1};
   const int span = 512 / gridDim.y;
@@ -613,7 +622,7 @@ __device__ inline void fas_leaf_3d(const FmgDev& g, int b) {
 template <int ND>
 __global__ void __launch_bounds__(WG) k_fmg_fas(FmgDev g, int b0) {
   if constexpr (ND == 3) {
-    const int b = b0 + blockIdx.x;
+    const int b = b0 + xcd_block(blockIdx.x, gridDim.x);
     if (g.chi[CS * b] >= 0)
       fas_parent_3d(g, b);
     else
@@ -638,7 +647,7 @@ __global__ void __launch_bounds__(WG) k_fmg_prolong(FmgDev g, int b0) {
     // planes) and the cells' own values loaded before any store
     constexpr int K = 4;
     const int tx = threadIdx.x & (NB - 1), ty = threadIdx.x >> 4;
-    const int b = b0 + blockIdx.x;
+    const int b = b0 + xcd_block(blockIdx.x, gridDim.x);
     for (int z0 = 0; z0 < NB; z0 += K) {
       double d[K], uv[K];
       size_t i[K];
@@ -691,7 +700,7 @@ __device__ __forceinline__ void fold_max(double v, unsigned long long* out) {
 // (the problem's f as solved) into out[1] (every block launched; parents skip)
 template <int ND>
 __global__ void __launch_bounds__(WG) k_fmg_resmax(FmgDev g, unsigned long long* out, int with_f) {
-  const int b = blockIdx.x;
+  const int b = ND == 3 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
   if (g.chi[CS * b] >= 0) return;  // uniform per workgroup
   double mr = 0.0, mf = 0.0;
   if constexpr (ND == 2) {
