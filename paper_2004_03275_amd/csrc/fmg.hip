@@ -46,8 +46,8 @@
 //   u, f, fu, r, uo  [block][16^d] doubles (state, relaxation right-hand
 //                 side, the problem's f, residual or restricted residual,
 //                 restricted state)
-//   fgrid, vgrid  the level-1 grid ((16 base)^d cells) for the uniform
-//                 solver, and that solver's own workspace
+//   the uniform solver's own workspace (its finest right-hand side and
+//                 solution arrays are the level-1 grid, fgrid and vgrid)
 //   red, tmp, part  two 64-bit maxima, eight leaf fields (reaction-diffusion
 //                 and projection temporaries), per-leaf sums
 #include <hip/hip_runtime.h>
@@ -1111,7 +1111,7 @@ amrv_mg_config base_config(const amrv_fmg_config* c) {
 }
 
 struct FmgLayout {
-  size_t off_tab[7], off_u, off_f, off_fu, off_r, off_uo, off_fg, off_vg, off_red, off_tmp[8], off_part, off_mg, total;
+  size_t off_tab[7], off_u, off_f, off_fu, off_r, off_uo, off_red, off_tmp[8], off_part, off_mg, total;
   size_t mg_bytes;
 };
 
@@ -1137,10 +1137,6 @@ FmgLayout layout(const amrv_fmg_config* c, const Tree& T) {
   L.off_fu = take(sizeof(double) * cb * nb);
   L.off_r = take(sizeof(double) * cb * nb);
   L.off_uo = take(sizeof(double) * cb * nb);
-  size_t gcells = 1;
-  for (int e = 0; e < nd; e++) gcells *= (size_t)c->base * NB;
-  L.off_fg = take(sizeof(double) * gcells);
-  L.off_vg = take(sizeof(double) * gcells);
   L.off_red = take(sizeof(unsigned long long) * 2);
   for (int i = 0; i < 8; i++) L.off_tmp[i] = take(sizeof(double) * cb * (size_t)c->nleaves);  // RD temporaries
   L.off_part = take(sizeof(double) * ((size_t)c->nleaves + 1));  // per-leaf sums and their mean
@@ -1244,7 +1240,7 @@ int vcycle(amrv_fmg* m) {
   // (it cuts the error by 20 or more; solved as a correction, what is left
   // shrinks with the residual from cycle to cycle), enqueued without a host
   // wait
-  if (int rc = amrv::mg_enqueue_correction(m->base, m->fgrid, m->vgrid, m->g.lam, 1)) return rc;
+  if (int rc = amrv::mg_enqueue_correction(m->base, m->fgrid, m->vgrid, m->g.lam, 1, true)) return rc;
   FMG_LAUNCH(k_fmg_from_grid, nblocks(m, 1), WG, m->g, m->T.lstart[1], n, m->vgrid);
   FMGCHK(hipGetLastError());
   if (int rc2 = sweeps(m, 1, post)) return rc2;
@@ -1341,8 +1337,6 @@ int amrv_fmg_create(const amrv_fmg_config* cfg, const int32_t* leaf_level, const
     g.ih2[l] = q * q;
     g.rh[l] = q;
   }
-  m->fgrid = reinterpret_cast<double*>(base + m->L.off_fg);
-  m->vgrid = reinterpret_cast<double*>(base + m->L.off_vg);
   m->red = reinterpret_cast<unsigned long long*>(base + m->L.off_red);
   for (int i = 0; i < 8; i++) m->tmp[i] = reinterpret_cast<double*>(base + m->L.off_tmp[i]);
   m->part = reinterpret_cast<double*>(base + m->L.off_part);
@@ -1355,6 +1349,9 @@ int amrv_fmg_create(const amrv_fmg_config* cfg, const int32_t* leaf_level, const
     delete m;
     return rc;
   }
+  // the level-1 grid is the uniform solver's own right-hand side and
+  // solution: k_fmg_to_grid fills the one and zeroes the other
+  amrv::mg_correction_grids(m->base, &m->fgrid, &m->vgrid);
   // parents start from zero (every parent is restricted before it is read)
   e = hipMemsetAsync(g.u, 0, sizeof(double) * m->ncb * (size_t)T.nblk, m->st);
   if (e == hipSuccess) e = hipStreamSynchronize(m->st);

@@ -950,6 +950,8 @@ struct amrv_mg {
   int last_cycles = 0;  // V-cycles of the last reaction-diffusion solve
   bool var = false;     // a cell coefficient is set (div(eps grad phi) - lambda phi)
   size_t tail_lds_var = 0;
+  int par_nf = 0;         // fields of the last parameter block set (0: none yet)
+  double par_lam0 = 0.0;  // its field-0 lambda
   double* eps[MG_MAXL] = {};
 };
 
@@ -1119,6 +1121,8 @@ int set_params(amrv_mg* m, const double* lam) {
   }
   hipLaunchKernelGGL(k_mg_set, dim3(1), dim3(64), 0, m->st, m->par, P);
   MGCHK(hipGetLastError());
+  m->par_nf = m->g.nf;
+  m->par_lam0 = lam[0];
   return 0;
 }
 
@@ -1222,17 +1226,25 @@ int run_cycles(amrv_mg* m, double tol, int max_cycles, int unchecked, int* cycle
 
 namespace amrv {
 
-int mg_enqueue_correction(amrv_mg* m, const double* f, double* out, double lambda, int cycles) {
+int mg_correction_grids(amrv_mg* m, double** f, double** e) {
+  if (!m || !f || !e) return set_error(AMRV_EINVAL, "null argument");
+  *f = m->g.f[0][0];
+  *e = m->g.phi[0][0];
+  return 0;
+}
+
+int mg_enqueue_correction(amrv_mg* m, const double* f, double* out, double lambda, int cycles, bool e_zeroed) {
   if (!m || !f || !out) return set_error(AMRV_EINVAL, "null argument");
   if (m->g.nf != 1 || m->var) return set_error(AMRV_EINVAL, "a correction solve needs one field and the constant coefficient");
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) return set_error(AMRV_EINVAL, "lambda must be non-negative and finite");
-  if (int rc = set_params(m, &lambda)) return rc;
+  if (m->par_nf != 1 || m->par_lam0 != lambda)
+    if (int rc = set_params(m, &lambda)) return rc;
   const size_t bytes = (size_t)m->g.cells[0] * sizeof(double);
-  MGCHK(hipMemcpyAsync(m->g.f[0][0], f, bytes, hipMemcpyDeviceToDevice, m->st));
-  MGCHK(hipMemsetAsync(m->g.phi[0][0], 0, bytes, m->st));
+  if (f != m->g.f[0][0]) MGCHK(hipMemcpyAsync(m->g.f[0][0], f, bytes, hipMemcpyDeviceToDevice, m->st));
+  if (!e_zeroed) MGCHK(hipMemsetAsync(m->g.phi[0][0], 0, bytes, m->st));
   for (int c = 0; c < cycles; c++)
     if (int rc = launch_cycle(m)) return rc;
-  MGCHK(hipMemcpyAsync(out, m->g.phi[0][0], bytes, hipMemcpyDeviceToDevice, m->st));
+  if (out != m->g.phi[0][0]) MGCHK(hipMemcpyAsync(out, m->g.phi[0][0], bytes, hipMemcpyDeviceToDevice, m->st));
   return 0;
 }
 
