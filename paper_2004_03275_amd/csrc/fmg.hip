@@ -300,39 +300,6 @@ __host__ __device__ inline double residual(const FmgDev& g, int b, const int* c)
   return g.fu[(size_t)b * ncb<ND>() + cidx(c)] - apply_cell<ND>(g, b, true, c);
 }
 
-// child b into its parent: parent cell t (0 .. 8^ND - 1) of the child's
-// quadrant / octant gets the mean of u and of r over its 2^ND cells (r into
-// the parent's r, u into its u and uo)
-template <int ND>
-__host__ __device__ inline void restrict_cell(const FmgDev& g, int b, int t) {
-  constexpr int NCB = ncb<ND>();
-  const int p = g.par[b];
-  const int q[3] = {g.ij[TS * b] & 1, g.ij[TS * b + 1] & 1, ND == 3 ? (g.ij[TS * b + 2] & 1) : 0};
-  const int xx = t & 7, yy = (t >> 3) & 7, zz = ND == 3 ? t >> 6 : 0;
-  const int c0[3] = {2 * xx, 2 * yy, 2 * zz};
-  const int pc[3] = {q[0] * 8 + xx, q[1] * 8 + yy, q[2] * 8 + zz};
-  const size_t i0 = (size_t)b * NCB + cidx(c0), ip = (size_t)p * NCB + cidx(pc);
-  double um, rm;
-  if constexpr (ND == 2) {
-    um = 0.25 * ((g.u[i0] + g.u[i0 + 1]) + (g.u[i0 + NB] + g.u[i0 + NB + 1]));
-    rm = 0.25 * ((g.r[i0] + g.r[i0 + 1]) + (g.r[i0 + NB] + g.r[i0 + NB + 1]));
-  } else {
-    constexpr int P = NB * NB;
-    um = 0.125 * (((g.u[i0] + g.u[i0 + 1]) + (g.u[i0 + NB] + g.u[i0 + NB + 1])) +
-                  ((g.u[i0 + P] + g.u[i0 + P + 1]) + (g.u[i0 + P + NB] + g.u[i0 + P + NB + 1])));
-    rm = 0.125 * (((g.r[i0] + g.r[i0 + 1]) + (g.r[i0 + NB] + g.r[i0 + NB + 1])) +
-                  ((g.r[i0 + P] + g.r[i0 + P + 1]) + (g.r[i0 + P + NB] + g.r[i0 + P + NB + 1])));
-  }
-  g.u[ip] = um;
-  g.uo[ip] = um;
-  g.r[ip] = rm;
-}
-
-// the right-hand side of a level below the finest: L(u) + r with L the plain
-// stencil, r the restricted residual (a parent) or the problem's residual (a
-// leaf; where the plain stencil is the problem's, exactly f).  A leaf next to
-// a refined block thereby relaxes with the same stencil as that block's
-// cells, and is left unchanged once the problem's residual vanishes.
 template <int ND>
 __host__ __device__ inline void fas_cell(const FmgDev& g, int b, const int* c) {
   const size_t i = (size_t)b * ncb<ND>() + cidx(c);
@@ -507,36 +474,43 @@ __global__ void __launch_bounds__(WG) k_fmg_resid(FmgDev g, int b0) {
   }
 }
 
-// 3D: a child block's residual restricted together with its state, so the
-// fine residual is never stored: parent cell t of the child's octant takes
-// the means of u and of f - L(u) (L the plain stencil) over its 8 cells,
-// restrict_cell's sums in its order, the residual as resid_cell's; on levels
-// of few blocks a block's 512 parent cells are split over gridDim.y
-// workgroups
-__global__ void __launch_bounds__(WG) k_fmg_resid_restrict3(FmgDev g, int b0) {
-  constexpr int NCB = ncb<3>();
-  const int b = b0 + xcd_block(blockIdx.x, gridDim.x);
+// a child block's residual restricted together with its state, so the fine
+// residual is never stored: parent cell t of the child's quadrant / octant
+// takes the means of u and of f - L(u) (L the plain stencil) over its 2^ND
+// cells (into the parent's u and uo, and r), the residual as resid_cell's; in
+// 3D 256 threads take the 512 parent cells (on levels of few blocks split
+// over gridDim.y workgroups), in 2D 64 threads the 64
+template <int ND>
+__global__ void __launch_bounds__(WG) k_fmg_resid_restrict(FmgDev g, int b0) {
+  constexpr int NCB = ncb<ND>(), NP = ND == 3 ? 512 : 64, NC = 1 << ND;
+  const int b = b0 + (ND == 3 ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x);
   const int p = g.par[b];
-  const int q[3] = {g.ij[TS * b] & 1, g.ij[TS * b + 1] & 1, g.ij[TS * b + 2] & 1};
-  const int span = 512 / gridDim.y;
-  for (int t = blockIdx.y * span + threadIdx.x; t < (int)(blockIdx.y + 1) * span; t += WG) {
-    const int xx = t & 7, yy = (t >> 3) & 7, zz = t >> 6;
-    int c[8][3];
-    double uv[8], fv[8], a[8], r[8];
+  const int q[3] = {g.ij[TS * b] & 1, g.ij[TS * b + 1] & 1, ND == 3 ? (g.ij[TS * b + 2] & 1) : 0};
+  const int span = NP / gridDim.y;
+  for (int t = blockIdx.y * span + threadIdx.x; t < (int)(blockIdx.y + 1) * span; t += blockDim.x) {
+    const int xx = t & 7, yy = (t >> 3) & 7, zz = ND == 3 ? t >> 6 : 0;
+    int c[NC][3];
+    double uv[NC], fv[NC], a[NC], r[NC];
 #pragma unroll
-    for (int k = 0; k < 8; k++) {
+    for (int k = 0; k < NC; k++) {
       c[k][0] = 2 * xx + (k & 1);
       c[k][1] = 2 * yy + ((k >> 1) & 1);
-      c[k][2] = 2 * zz + (k >> 2);
+      c[k][2] = ND == 3 ? 2 * zz + (k >> 2) : 0;
       const size_t i = (size_t)b * NCB + cidx(c[k]);
       uv[k] = g.u[i];
       fv[k] = g.f[i];
     }
-    apply_k<3, 8>(g, b, false, c, uv, a);
+    apply_k<ND, NC>(g, b, false, c, uv, a);
 #pragma unroll
-    for (int k = 0; k < 8; k++) r[k] = fv[k] - a[k];
-    const double um = 0.125 * (((uv[0] + uv[1]) + (uv[2] + uv[3])) + ((uv[4] + uv[5]) + (uv[6] + uv[7])));
-    const double rm = 0.125 * (((r[0] + r[1]) + (r[2] + r[3])) + ((r[4] + r[5]) + (r[6] + r[7])));
+    for (int k = 0; k < NC; k++) r[k] = fv[k] - a[k];
+    double um, rm;
+    if constexpr (ND == 2) {
+      um = 0.25 * ((uv[0] + uv[1]) + (uv[2] + uv[3]));
+      rm = 0.25 * ((r[0] + r[1]) + (r[2] + r[3]));
+    } else {
+      um = 0.125 * (((uv[0] + uv[1]) + (uv[2] + uv[3])) + ((uv[4] + uv[5]) + (uv[6] + uv[7])));
+      rm = 0.125 * (((r[0] + r[1]) + (r[2] + r[3])) + ((r[4] + r[5]) + (r[6] + r[7])));
+    }
     const int pc[3] = {q[0] * 8 + xx, q[1] * 8 + yy, q[2] * 8 + zz};
     const size_t ip = (size_t)p * NCB + cidx(pc);
     g.u[ip] = um;
@@ -545,10 +519,6 @@ __global__ void __launch_bounds__(WG) k_fmg_resid_restrict3(FmgDev g, int b0) {
   }
 }
 
-template <int ND>
-__global__ void __launch_bounds__(WG) k_fmg_restrict(FmgDev g, int b0) {
-  for (int t = threadIdx.x; t < (ND == 3 ? 512 : 64); t += blockDim.x) restrict_cell<ND>(g, b0 + blockIdx.x, t);
-}
 
 // a parent block in 3D: L(u) + r (fas_cell's first case) four planes at a
 // time (apply_k)
@@ -1222,12 +1192,7 @@ int vcycle(amrv_fmg* m) {
   const int pre = m->cfg.pre_sweeps, post = m->cfg.post_sweeps;
   for (int l = L; l >= 2; l--) {
     if (int rc = sweeps(m, l, pre)) return rc;
-    if (m->nd == 3) {
-      hipLaunchKernelGGL(k_fmg_resid_restrict3, level_grid(m, l, 2), dim3(WG), 0, m->st, m->g, m->T.lstart[l]);
-    } else {
-      FMG_LAUNCH(k_fmg_resid, nblocks(m, l), WG, m->g, m->T.lstart[l]);
-      FMG_LAUNCH(k_fmg_restrict, nblocks(m, l), 64, m->g, m->T.lstart[l]);
-    }
+    FMG_LAUNCH(k_fmg_resid_restrict, level_grid(m, l, 2), m->nd == 3 ? WG : 64, m->g, m->T.lstart[l]);
     FMG_LAUNCH(k_fmg_fas, level_grid(m, l - 1, 4), WG, m->g, m->T.lstart[l - 1]);
     FMGCHK(hipGetLastError());
   }
