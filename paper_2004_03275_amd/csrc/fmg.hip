@@ -300,6 +300,11 @@ __host__ __device__ inline double residual(const FmgDev& g, int b, const int* c)
   return g.fu[(size_t)b * ncb<ND>() + cidx(c)] - apply_cell<ND>(g, b, true, c);
 }
 
+// the right-hand side of a level below the finest: L(u) + r with L the plain
+// stencil, r the restricted residual (a parent) or the problem's residual (a
+// leaf; where the plain stencil is the problem's, exactly f).  A leaf next to
+// a refined block thereby relaxes with the same stencil as that block's
+// cells, and is left unchanged once the problem's residual vanishes.
 template <int ND>
 __host__ __device__ inline void fas_cell(const FmgDev& g, int b, const int* c) {
   const size_t i = (size_t)b * ncb<ND>() + cidx(c);
