@@ -36,15 +36,24 @@ def checker(tmp_path_factory):
     return exe
 
 
+CASES = [
+    # ndim, base, max_level, centre, radius
+    (3, 1, 3, (0.2, 0.2, 0.2), 0.1),
+    (3, 1, 3, (0.3, 0.35, 0.4), 0.2),
+    (2, 4, 3, (0.27, 0.3), 0.15),
+    (2, 2, 4, (0.5, 0.45), 0.2),
+]
+
+
 @pytest.mark.parametrize("bc", [0, 1])
-@pytest.mark.parametrize("centre,radius", [((0.2, 0.2, 0.2), 0.1), ((0.3, 0.35, 0.4), 0.2)])
-def test_batched_stencils_equal_the_per_cell_ones(checker, tmp_path, bc, centre, radius):
-    f = W.fmg_forest(W.fmg_scheme(base=1, max_level=3, bc=bc, ndim=3), centre=centre, radius=radius)
-    assert len(f.level_counts()) >= 1
+@pytest.mark.parametrize("nd,base,max_level,centre,radius", CASES)
+def test_batched_stencils_equal_the_per_cell_ones(checker, tmp_path, bc, nd, base, max_level, centre, radius):
+    f = W.fmg_forest(W.fmg_scheme(base=base, max_level=max_level, bc=bc, ndim=nd), centre=centre, radius=radius)
+    assert f.n >= 1
     s = f.scheme
     path = tmp_path / "forest.txt"
     with open(path, "w") as fh:
-        fh.write(f"{f.n} {s.base_blocks[0]} {s.max_level} {bc} 3\n")
+        fh.write(f"{f.n} {s.base_blocks[0]} {s.max_level} {bc} {nd}\n")
         for k in range(f.n):
             fh.write(f"{f.level[k]} {f.ijk[k, 0]} {f.ijk[k, 1]} {f.ijk[k, 2]}\n")
     out = subprocess.run([checker, str(path)], capture_output=True, text=True, timeout=300)
