@@ -1179,7 +1179,7 @@ int nblocks(const amrv_fmg* m, int l) { return m->T.lstart[l + 1] - m->T.lstart[
 dim3 level_grid(const amrv_fmg* m, int l, int parts) {
   const int n = nblocks(m, l);
   int s = 1;
-  while (m->nd == 3 && s < parts && (long long)n * s < 2048) s *= 2;
+  while (m->nd == 3 && s < parts && (long long)n * s < 4096) s *= 2;
   return dim3(n, s);
 }
 
